@@ -1,0 +1,158 @@
+"""Seeded, synthetic initial states shared by the tests, the benchmark and the
+oracle-side checks.
+
+This module holds no part of the discretisation: it only samples closed-form
+initial conditions at the interpolation nodes and draws seeded random numbers.
+It imports nothing else from the package, so the oracle side can use it
+without touching the GPU library.
+
+Layout of every state: float64, shape (nElems, 5, N+1, N+1, N+1), variables
+(rho, rho*u, rho*v, rho*w, E), x index fastest, elements e = ex + nx*(ey + ny*ez).
+Node positions inside an element are the Legendre-Gauss-Lobatto points
+(paper Sec. 2, split form on LGL nodes), computed here with numpy's Legendre
+polynomials.
+"""
+from __future__ import annotations
+
+import numpy as np
+from numpy.polynomial import legendre as _leg
+
+TWO_PI = 2.0 * np.pi
+
+
+def lgl_points(N: int) -> np.ndarray:
+    """Legendre-Gauss-Lobatto points on [-1, 1]: +-1 and the roots of L_N'."""
+    c = np.zeros(N + 1)
+    c[N] = 1.0
+    inner = np.sort(np.real(_leg.legroots(_leg.legder(c)))) if N > 1 else np.zeros(0)
+    return np.concatenate([[-1.0], inner, [1.0]])
+
+
+def node_coordinates(N: int, nelem, lo, hi):
+    """x, y, z arrays of shape (nElems, N+1, N+1, N+1) (index order k, j, i)."""
+    nx, ny, nz = nelem
+    xi = lgl_points(N)
+    dx = [(hi[d] - lo[d]) / nelem[d] for d in range(3)]
+    ex = np.arange(nx)
+    ey = np.arange(ny)
+    ez = np.arange(nz)
+    # element index e = ex + nx (ey + ny ez)
+    EZ, EY, EX = np.meshgrid(ez, ey, ex, indexing="ij")
+    EX, EY, EZ = EX.ravel(), EY.ravel(), EZ.ravel()
+    r = (xi + 1.0) / 2.0
+    x = lo[0] + (EX[:, None] + r[None, :]) * dx[0]  # (nE, n1) along i
+    y = lo[1] + (EY[:, None] + r[None, :]) * dx[1]
+    z = lo[2] + (EZ[:, None] + r[None, :]) * dx[2]
+    n1 = N + 1
+    X = np.broadcast_to(x[:, None, None, :], (len(EX), n1, n1, n1))
+    Y = np.broadcast_to(y[:, None, :, None], (len(EX), n1, n1, n1))
+    Z = np.broadcast_to(z[:, :, None, None], (len(EX), n1, n1, n1))
+    return X, Y, Z
+
+
+def element_centres(nelem, lo, hi):
+    nx, ny, nz = nelem
+    dx = [(hi[d] - lo[d]) / nelem[d] for d in range(3)]
+    EZ, EY, EX = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    return (lo[0] + (EX.ravel() + 0.5) * dx[0], lo[1] + (EY.ravel() + 0.5) * dx[1],
+            lo[2] + (EZ.ravel() + 0.5) * dx[2])
+
+
+def from_primitive(rho, u, v, w, p, gamma: float) -> np.ndarray:
+    rho, u, v, w, p = np.broadcast_arrays(rho, u, v, w, p)
+    E = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v + w * w)
+    return np.ascontiguousarray(np.stack([rho, rho * u, rho * v, rho * w, E], axis=1), dtype=np.float64)
+
+
+def density_wave(N: int, nelem=(4, 4, 4), lo=(0.0, 0.0, 0.0), hi=(TWO_PI,) * 3, gamma: float = 1.4,
+                 t: float = 0.0, amp: float = 0.2) -> np.ndarray:
+    """rho = 1 + amp sin(x + y + z - 3t), u = (1, 1, 1), p = 1 (exact Euler solution)."""
+    X, Y, Z = node_coordinates(N, nelem, lo, hi)
+    rho = 1.0 + amp * np.sin(X + Y + Z - 3.0 * t)
+    one = np.ones_like(rho)
+    return from_primitive(rho, one, one, one, one, gamma)
+
+
+def tgv(N: int, nelem=(32, 32, 32), Ma: float = 0.1, gamma: float = 1.4, symmetry_break: bool = False,
+        seed: int = 7, eps: float = 1e-3) -> np.ndarray:
+    """Taylor-Green vortex on [0, 2pi]^3 with rho0 = U0 = L = 1.
+
+    p0 = 1/(gamma Ma^2); u = sin x cos y cos z, v = -cos x sin y cos z, w = 0;
+    p = p0 + (cos 2x + cos 2y)(cos 2z + 2)/16; rho = p / p0 (isothermal start).
+    symmetry_break adds eps sin(x+f1) sin(2y+f2) cos(z+f3) to w, phases f ~ U(0, 2pi)
+    drawn from numpy's default_rng(seed).
+    """
+    X, Y, Z = node_coordinates(N, nelem, (0.0, 0.0, 0.0), (TWO_PI,) * 3)
+    p0 = 1.0 / (gamma * Ma * Ma)
+    u = np.sin(X) * np.cos(Y) * np.cos(Z)
+    v = -np.cos(X) * np.sin(Y) * np.cos(Z)
+    w = np.zeros_like(u)
+    if symmetry_break:
+        ph = np.random.default_rng(seed).uniform(0.0, TWO_PI, size=3)
+        w = w + eps * np.sin(X + ph[0]) * np.sin(2.0 * Y + ph[1]) * np.cos(Z + ph[2])
+    p = p0 + (np.cos(2.0 * X) + np.cos(2.0 * Y)) * (np.cos(2.0 * Z) + 2.0) / 16.0
+    rho = p / p0
+    return from_primitive(rho, u, v, w, p, gamma)
+
+
+def sod(N: int, nelem=(64, 8, 8), lo=(0.0, 0.0, 0.0), hi=(1.0, 0.125, 0.125), gamma: float = 1.4,
+        x0: float = 0.5) -> np.ndarray:
+    """Extruded Sod states chosen by element centre: (1, 0, 1) left of x0, (0.125, 0, 0.1) right."""
+    n1 = N + 1
+    xc, _, _ = element_centres(nelem, lo, hi)
+    left = (xc < x0)[:, None, None, None]
+    shape = (len(xc), n1, n1, n1)
+    rho = np.where(left, 1.0, 0.125) * np.ones(shape)
+    p = np.where(left, 1.0, 0.1) * np.ones(shape)
+    z = np.zeros(shape)
+    return from_primitive(rho, z, z, z, p, gamma)
+
+
+def freestream(N: int, nelem=(4, 4, 4), lo=(0.0, 0.0, 0.0), hi=(TWO_PI,) * 3, gamma: float = 1.4,
+               rho: float = 1.0, u=(0.5, 0.0, 0.0), p=None) -> np.ndarray:
+    """Constant state (default Ma 0.5: rho = 1, u = (0.5, 0, 0), p = 1/gamma)."""
+    n1 = N + 1
+    ne = int(np.prod(nelem))
+    if p is None:
+        p = 1.0 / gamma
+    one = np.ones((ne, n1, n1, n1))
+    return from_primitive(rho * one, u[0] * one, u[1] * one, u[2] * one, p * one, gamma)
+
+
+def random_smooth(N: int, nelem=(3, 2, 2), lo=(0.0, 0.0, 0.0), hi=(TWO_PI,) * 3, gamma: float = 1.4,
+                  seed: int = 0, amp: float = 0.1, modes: int = 3, mach: float = 0.5,
+                  noise: float = 0.0) -> np.ndarray:
+    """Seeded smooth positive state: sums of low Fourier modes with random phases.
+
+    noise > 0 adds i.i.d. node noise (relative) so that element interfaces are
+    discontinuous and every code path of the surface terms is exercised.
+    """
+    rng = np.random.default_rng(seed)
+    X, Y, Z = node_coordinates(N, nelem, lo, hi)
+    L = [hi[d] - lo[d] for d in range(3)]
+
+    def field():
+        f = np.zeros_like(X)
+        for _ in range(modes):
+            k = rng.integers(1, 3, size=3)
+            ph = rng.uniform(0, TWO_PI, size=3)
+            a = rng.uniform(-1.0, 1.0)
+            f = f + a * np.sin(TWO_PI * k[0] * X / L[0] + ph[0]) * np.cos(TWO_PI * k[1] * Y / L[1] + ph[1]) \
+                * np.sin(TWO_PI * k[2] * Z / L[2] + ph[2])
+        return f / modes
+
+    rho = 1.0 + amp * field()
+    p = 1.0 / gamma + amp * field() / gamma
+    u = mach * (0.5 + field())
+    v = mach * field()
+    w = mach * field()
+    if noise > 0:
+        rho = rho * (1.0 + noise * rng.standard_normal(rho.shape))
+        p = p * (1.0 + noise * rng.standard_normal(p.shape))
+        u = u + noise * rng.standard_normal(u.shape)
+    return from_primitive(rho, u, v, w, p, gamma)
+
+
+def random_directions(shape, k: int, base_seed: int = 1000) -> np.ndarray:
+    """Direction k of an i.i.d. N(0, 1) family, seed base_seed + k."""
+    return np.random.default_rng(base_seed + k).standard_normal(shape)

@@ -1,0 +1,211 @@
+"""Operator-level pins of the oracle: free-stream preservation, discrete
+conservation, kinetic-energy and entropy conservation of the split form with
+a central interface flux, equivalence with an independently written plain
+strong-form DGSEM for the arithmetic-mean flux, and a dense Kronecker
+brute-force evaluation."""
+import numpy as np
+import pytest
+
+from paper_2306_12891_amd import inputs as I
+
+G = 1.4
+
+
+def rel_integral(orc, s, Ut):
+    I_ = orc.integrals(s, Ut)
+    scale = orc.integrals(s, np.abs(Ut))
+    return np.abs(I_) / np.maximum(scale, 1e-300)
+
+
+CASES = [  # (equations, vol_flux, surf_flux)
+    (0, 0, 0), (0, 1, 1), (0, 2, 0), (0, 3, 2), (1, 1, 1), (1, 0, 0), (1, 2, 1),
+]
+
+
+@pytest.mark.parametrize("eq,vf,sf", CASES)
+def test_freestream(orc, eq, vf, sf):
+    for N in (2, 5):
+        s = orc.Setup(N=N, nelem=(2, 3, 2), equations=eq, vol_flux=vf, surf_flux=sf, mu=1e-2)
+        U = I.freestream(N, (2, 3, 2), u=(0.4, -0.3, 0.2))
+        Ut = orc.time_derivative(s, U)
+        scale = np.max(np.abs(U)) * (2.0 / (2 * np.pi / 3)) * N * (N + 1) / 2
+        assert np.max(np.abs(Ut)) <= 1e-13 * scale
+
+
+def test_freestream_blended(orc):
+    N = 4
+    s = orc.Setup(N=N, nelem=(2, 2, 2), blending=1)
+    U = I.freestream(N, (2, 2, 2), u=(0.4, -0.3, 0.2))
+    for alpha in (np.ones(8), np.linspace(0, 1, 8)):
+        Ut = orc.time_derivative(s, U, alpha=alpha)
+        assert np.max(np.abs(Ut)) <= 1e-13 * 10 * N * N
+
+
+@pytest.mark.parametrize("eq,vf,sf", CASES)
+def test_conservation(orc, eq, vf, sf):
+    N = 4
+    s = orc.Setup(N=N, nelem=(3, 2, 2), equations=eq, vol_flux=vf, surf_flux=sf, mu=2e-2)
+    U = I.random_smooth(N, (3, 2, 2), seed=11, noise=0.02)
+    Ut = orc.time_derivative(s, U)
+    assert np.all(rel_integral(orc, s, Ut) < 1e-13)
+
+
+def test_conservation_blended(orc):
+    N = 4
+    s = orc.Setup(N=N, nelem=(3, 2, 2), blending=1)
+    U = I.random_smooth(N, (3, 2, 2), seed=12, noise=0.05)
+    rng = np.random.default_rng(0)
+    Ut = orc.time_derivative(s, U, alpha=rng.uniform(0, 1, 12))
+    assert np.all(rel_integral(orc, s, Ut) < 1e-13)
+
+
+def kinetic_rate(orc, s, U, Ut):
+    rho, m = U[:, 0], U[:, 1:4]
+    u = m / rho[:, None]
+    integrand = np.einsum("evkji,evkji->ekji", u, Ut[:, 1:4]) - 0.5 * np.sum(u * u, axis=1) * Ut[:, 0]
+    X = np.zeros_like(U)
+    X[:, 0] = integrand
+    Xs = np.zeros_like(U)
+    Xs[:, 0] = np.abs(np.einsum("evkji,evkji->ekji", u, Ut[:, 1:4])) + np.abs(0.5 * np.sum(u * u, 1) * Ut[:, 0])
+    return orc.integrals(s, X)[0], orc.integrals(s, Xs)[0]
+
+
+@pytest.mark.parametrize("vf", [0, 1])
+def test_kinetic_energy_preservation(orc, vf):
+    """Constant pressure, arbitrary density and velocity, central interface
+    flux: the kinetic-energy production of the KG and PI split forms vanishes."""
+    N = 4
+    s = orc.Setup(N=N, nelem=(2, 2, 2), vol_flux=vf, surf_flux=2)
+    X, Y, Z = I.node_coordinates(N, (2, 2, 2), (0, 0, 0), (2 * np.pi,) * 3)
+    rng = np.random.default_rng(5)
+    rho = 1 + 0.3 * np.sin(X + 2 * Y) * np.cos(Z) + 0.05 * rng.standard_normal(X.shape)
+    u = np.sin(Y) + 0.1 * rng.standard_normal(X.shape)
+    v = np.cos(Z + X)
+    w = 0.5 * np.sin(X) * np.cos(Y)
+    U = I.from_primitive(rho, u, v, w, np.ones_like(X), G)
+    Ut = orc.time_derivative(s, U)
+    k, scale = kinetic_rate(orc, s, U, Ut)
+    assert abs(k) < 1e-13 * scale, (k, scale)
+
+
+def entropy_rate(orc, s, U, Ut):
+    rho, m, E = U[:, 0], U[:, 1:4], U[:, 4]
+    u = m / rho[:, None]
+    p = (G - 1) * (E - 0.5 * rho * np.sum(u * u, 1))
+    sent = np.log(p * rho ** (-G))
+    v0 = (G - sent) / (G - 1) - rho * np.sum(u * u, 1) / (2 * p)
+    vm = rho[:, None] * u / p[:, None]
+    v4 = -rho / p
+    dens = v0 * Ut[:, 0] + np.sum(vm * Ut[:, 1:4], 1) + v4 * Ut[:, 4]
+    mag = np.abs(v0 * Ut[:, 0]) + np.sum(np.abs(vm * Ut[:, 1:4]), 1) + np.abs(v4 * Ut[:, 4])
+    X = np.zeros_like(U)
+    X[:, 0] = dens
+    Xs = np.zeros_like(U)
+    Xs[:, 0] = mag
+    return orc.integrals(s, X)[0], orc.integrals(s, Xs)[0]
+
+
+def test_entropy_conservation(orc):
+    N = 4
+    s = orc.Setup(N=N, nelem=(2, 2, 2), vol_flux=2, surf_flux=2)
+    U = I.random_smooth(N, (2, 2, 2), seed=21, noise=0.02, amp=0.3)
+    Ut = orc.time_derivative(s, U)
+    r, scale = entropy_rate(orc, s, U, Ut)
+    assert abs(r) < 1e-14 * scale, (r, scale)
+
+
+@pytest.mark.parametrize("sf", [0, 1])
+def test_entropy_dissipation(orc, sf):
+    N = 4
+    s = orc.Setup(N=N, nelem=(2, 2, 2), vol_flux=2, surf_flux=sf)
+    U = I.random_smooth(N, (2, 2, 2), seed=22, noise=0.02, amp=0.3)
+    r, scale = entropy_rate(orc, s, U, orc.time_derivative(s, U))
+    # entropy s decreases in time for the mathematical entropy -rho s: rate <= 0 here
+    assert r < 1e-14 * scale
+
+
+# ---------------------------------------------------------------------------
+# Independent plain strong-form DGSEM (numpy) for the arithmetic-mean flux.
+# ---------------------------------------------------------------------------
+def lagrange_D(x):
+    n = len(x)
+    lam = np.array([1.0 / np.prod([x[j] - x[k] for k in range(n) if k != j]) for j in range(n)])
+    D = np.zeros((n, n))
+    for i in range(n):
+        for j in range(n):
+            if i != j:
+                D[i, j] = lam[j] / lam[i] / (x[i] - x[j])
+        D[i, i] = -np.sum(D[i])
+    return D
+
+
+def np_flux(U, d):
+    rho = U[:, 0]
+    u = U[:, 1:4] / rho[:, None]
+    p = (G - 1) * (U[:, 4] - 0.5 * rho * np.sum(u * u, 1))
+    F = np.empty_like(U)
+    F[:, 0] = U[:, 1 + d]
+    F[:, 1:4] = U[:, 1:4] * u[:, d:d + 1]
+    F[:, 1 + d] += p
+    F[:, 4] = (U[:, 4] + p) * u[:, d]
+    return F, np.abs(u[:, d]) + np.sqrt(G * p / rho)
+
+
+def strong_form(U, N, nelem, lo, hi):
+    x = I.lgl_points(N)
+    w = np.array([2.0 / (N * (N + 1) * np.polynomial.legendre.legval(xx, np.eye(N + 1)[N]) ** 2) for xx in x])
+    D = lagrange_D(x)
+    nx, ny, nz = nelem
+    ne = nx * ny * nz
+    idx = np.arange(ne)
+    ex, ey, ez = idx % nx, (idx // nx) % ny, idx // (nx * ny)
+    plus = [((ex + 1) % nx) + nx * (ey + ny * ez), ex + nx * (((ey + 1) % ny) + ny * ez),
+            ex + nx * (ey + ny * ((ez + 1) % nz))]
+    Ut = np.zeros_like(U)
+    for d in range(3):
+        ax = 4 - d  # axis of index i_d in (e, v, k, j, i)
+        invJ = 2.0 / ((hi[d] - lo[d]) / nelem[d])
+        F, lam = np_flux(U, d)
+        vol = np.moveaxis(np.tensordot(D, np.moveaxis(F, ax, 0), axes=([1], [0])), 0, ax)
+        # faces: minus side = element at index N, plus side = its + neighbour at index 0
+        UL = np.take(U, N, axis=ax)
+        UR = np.take(U[plus[d]], 0, axis=ax)
+        FL, lL = np_flux(UL, d)
+        FR, lR = np_flux(UR, d)
+        lmax = np.maximum(lL, lR)[:, None]
+        fs = 0.5 * (FL + FR) - 0.5 * lmax * (UR - UL)
+        minus_of = np.empty(ne, dtype=int)
+        minus_of[plus[d]] = idx
+        surf = np.zeros_like(U)
+        sl_N = [slice(None)] * 5
+        sl_N[ax] = N
+        sl_0 = [slice(None)] * 5
+        sl_0[ax] = 0
+        surf[tuple(sl_N)] += (fs - np.take(F, N, axis=ax)) / w[N]
+        surf[tuple(sl_0)] -= (fs[minus_of] - np.take(F, 0, axis=ax)) / w[0]
+        Ut -= invJ * (vol + surf)
+    return Ut
+
+
+@pytest.mark.parametrize("N", [1, 3, 5])
+def test_std_flux_equals_strong_form(orc, N):
+    nelem, lo, hi = (3, 2, 2), (0.0, -1.0, 0.5), (2.0, 1.0, 2.0)
+    s = orc.Setup(N=N, nelem=nelem, lo=lo, hi=hi, vol_flux=3, surf_flux=0)
+    U = I.random_smooth(N, nelem, lo, hi, seed=N, noise=0.02)
+    Ut = orc.time_derivative(s, U)
+    ref = strong_form(U, N, nelem, lo, hi)
+    scale = np.max(np.abs(ref), axis=(0, 2, 3, 4))
+    err = np.max(np.abs(Ut - ref), axis=(0, 2, 3, 4))
+    assert np.all(err <= 1e-13 * scale), (err, scale)
+
+
+@pytest.mark.parametrize("eq,vf,sf,nelem", [(0, 0, 0, (1, 1, 1)), (0, 1, 1, (2, 1, 1)), (0, 2, 1, (1, 2, 1)),
+                                            (1, 1, 1, (1, 1, 1)), (1, 0, 0, (2, 1, 1)), (1, 1, 1, (1, 1, 2))])
+def test_dense_brute_force(orc, eq, vf, sf, nelem):
+    N = 3
+    s = orc.Setup(N=N, nelem=nelem, equations=eq, vol_flux=vf, surf_flux=sf, mu=5e-2)
+    U = I.random_smooth(N, nelem, seed=4, noise=0.03)
+    Ut = orc.time_derivative(s, U)
+    ref = orc.dense_time_derivative(s, U)
+    scale = np.max(np.abs(ref), axis=(0, 2, 3, 4))
+    assert np.all(np.max(np.abs(Ut - ref), axis=(0, 2, 3, 4)) <= 1e-13 * scale)
