@@ -1,0 +1,163 @@
+"""Throughput benchmark of the split-form DGSEM hot path on one MI355X.
+
+Default workload: Taylor-Green vortex, Ma 0.1, Re 1600, Pr 0.72, N = 5 on
+32^3 periodic elements (7.08 M nodes), Pirozzoli split flux + Roe, BR1
+lifting, FP64, LSERK4.  A "step" is one Runge-Kutta step (5 stages) over the
+whole mesh.  The metric is DOF-stage updates per second (1/PID with the GPU as
+the single "core"; DOF counts nodes).  Inputs are resident in HBM before the
+timed region; the timed region is bracketed by torch.cuda.synchronize().
+
+Prints one JSON line with the throughput, the roofline of the dominant kernel
+(measured with HIP events on the library's stream during the timed region)
+and the CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DOF-stage updates/s (1/PID) FP64 vs mixed at stated err; adjoint/forward time"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    # name: (N, nelem, equations, vol_flux, surf_flux, mu, blending, description)
+    "tgv_n5_32": (5, (32, 32, 32), 1, 1, 1, 1.0 / 1600, 0,
+                  "TGV Ma0.1 Re1600 Pr0.72, N=5, 32^3 elems, PI+Roe, BR1, LSERK4"),
+    "tgv_n7_64": (7, (64, 64, 64), 1, 1, 1, 1.0 / 1600, 0,
+                  "TGV Ma0.1 Re1600 Pr0.72, N=7, 64^3 elems, PI+Roe, BR1, LSERK4"),
+    "density_wave_n3_4": (3, (4, 4, 4), 0, 0, 0, 0.0, 0,
+                          "Euler density wave, N=3, 4^3 elems, KG+LLF, LSERK4"),
+    "freestream_euler_n7_64": (7, (64, 64, 64), 0, 0, 0, 0.0, 0,
+                               "Euler freestream Ma0.5, N=7, 64^3 elems, KG+LLF, LSERK4"),
+    "sod_n5_64x8x8": (5, (64, 8, 8), 0, 0, 0, 0.0, 1,
+                      "Euler Sod tube, N=5, 64x8x8 elems, KG+LLF, DG/FV blending (minmod), LSERK4"),
+}
+
+
+def initial_state(name, N, nelem):
+    from paper_2306_12891_amd import inputs
+    if name.startswith("tgv"):
+        return inputs.tgv(N, nelem)
+    if name.startswith("density_wave"):
+        return inputs.density_wave(N, nelem)
+    if name.startswith("freestream"):
+        return inputs.freestream(N, nelem)
+    if name.startswith("sod"):
+        return inputs.sod(N, nelem, (0, 0, 0), (1.0, 0.125, 0.125))
+    raise KeyError(name)
+
+
+def domain(name):
+    if name.startswith("sod"):
+        return (0.0, 0.0, 0.0), (1.0, 0.125, 0.125)
+    return (0.0, 0.0, 0.0), (2 * math.pi,) * 3
+
+
+def stage_bytes_per_step(nodes):
+    """Algorithmic HBM bytes of the stage kernel over the five stages of one
+    step: read U (40 B/node) and write U (40); the register G is written in
+    stages 1-4 and read in stages 2-5 (stage 1 has A_1 = 0, the stage-5
+    register is dead): 2 x 120 + 3 x 160 = 720 B per node."""
+    return 720.0 * nodes
+
+
+def cpu_baseline(name, spec, U0, dt, seconds_hint):
+    from oracle import oracle as orc
+    N, nelem, eq, vf, sf, mu, blend, _ = spec
+    lo, hi = domain(name)
+    cores = len(os.sched_getaffinity(0))
+    orc.set_threads(cores)
+    s = orc.Setup(N=N, nelem=nelem, lo=lo, hi=hi, equations=eq, vol_flux=vf, surf_flux=sf, mu=mu,
+                  blending=blend, Pr=0.72)
+    nodes = U0.shape[0] * (N + 1) ** 3
+    t0 = time.perf_counter()
+    orc.rk_steps(s, U0, dt, 1)
+    wall = time.perf_counter() - t0
+    return {"value": nodes * 5 / wall, "unit": "DOF-stage/s", "cores": cores, "kind": "oracle",
+            "sample": f"1 LSERK4 step (5 operator evaluations) of the full {name} mesh, {wall:.1f} s wall",
+            "pid_us_per_core": wall * cores / (nodes * 5) * 1e6}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="tgv_n5_32", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this path runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU element decomposition is a design only)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2306_12891_amd import dg
+
+    name = args.workload
+    spec = WORKLOADS[name]
+    N, nelem, eq, vf, sf, mu, blend, desc = spec
+    lo, hi = domain(name)
+    U0 = initial_state(name, N, nelem)
+    nodes = U0.shape[0] * (N + 1) ** 3
+    op = dg.DG(nelem, N, gamma=1.4, mu=mu, lo=lo, hi=hi, equations=eq, vol_flux=vf, surf_flux=sf,
+               blending=blend, Pr=0.72)
+    U = torch.from_numpy(U0).to("cuda:0")
+    dt = op.max_dt(U, 0.5)
+    if args.warmup:
+        op.rk_steps(U, dt, args.warmup)
+    torch.cuda.synchronize()
+    op.set_profiling(not args.no_profile)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    op.rk_steps(U, dt, args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = op.profile_read() if not args.no_profile else None
+    op.set_profiling(False)
+    finite = op.check_finite(U)
+    value = nodes * 5 * args.steps / wall
+
+    roof = None
+    extra = {}
+    if prof:
+        ms_stage, n_stage = prof["stage"]
+        avg_ms = ms_stage / max(n_stage, 1)
+        A = stage_bytes_per_step(nodes) * args.steps / (ms_stage * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(A, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(A / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_stage (operator + LSERK4 stage)", "avg_launch_ms": round(avg_ms, 4),
+                "algorithmic_bytes_per_launch": stage_bytes_per_step(nodes) / 5}
+        extra["kernel_ms_per_step"] = {k: round(v[0] / args.steps, 4) for k, v in prof.items() if v[1]}
+    path_bytes = 160.0 * nodes * 5 * args.steps
+    extra["path_roofline_frac_160B"] = round(path_bytes / wall / 1e9 / HBM_PEAK_GBS, 4)
+    extra["pid_gpu_us"] = 1e6 / value
+    extra["finite_after_run"] = finite
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(name, spec, U0, dt, 20)
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "DOF-stage/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": desc, "N": N, "elements": list(nelem), "dof": nodes, "dt": dt,
+                   "precision": "fp64"},
+        "roofline": roof, "cpu_baseline": cpu, **extra,
+    }
+    print(json.dumps(line))
+    op.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,180 @@
+/* dg.h - C ABI of the MI355X split-form DGSEM library (libdgmi.so).
+ *
+ * The library evaluates the discontinuous Galerkin spectral element operator
+ * of the compressible Euler / Navier-Stokes equations on periodic Cartesian
+ * hexahedral meshes and advances it with a five-stage, fourth-order,
+ * two-register (2N-storage) explicit Runge-Kutta scheme.  All arithmetic runs
+ * in HIP kernels on one GPU; the host side only validates arguments and
+ * enqueues work.
+ *
+ * Method (paper: Blind et al., "Towards Exascale CFD Simulations Using the
+ * Discontinuous Galerkin Solver FLEXI"):
+ *   - split-form DG on Legendre-Gauss-Lobatto nodes in flux-differencing form
+ *     (Sec. 2, Sec. 4.1);
+ *   - element-wise convex blending with a finite-volume subcell operator,
+ *     U_t = a U_t^FV + (1 - a) U_t^DG (Sec. 4.1, blending equation), first
+ *     order in the outer subcells (Sec. 4.1);
+ *   - blending coefficient from a modal indicator through the sigmoid with
+ *     threshold T(N) = 0.5 * 10^(-1.8 (N+1)^0.25) (Sec. 4.1, indicator
+ *     equation), spread to face neighbours by 1/2 (Sec. 4.1), and kept in
+ *     {0} U [0.01, 0.7] (Sec. 4.2);
+ *   - explicit Runge-Kutta time stepping whose stages enter the performance
+ *     index (Sec. 2, eq. (pid)).
+ * The paper leaves open the two-point fluxes (Kennedy-Gruber, Pirozzoli),
+ * the Riemann solvers (LLF, Roe), the viscous lifting (BR1) and the
+ * Runge-Kutta coefficients (Carpenter-Kennedy (5,4) 2N-storage); the library
+ * implements those standard choices.
+ *
+ * Data layout (every state-sized array):
+ *   double, contiguous, [nElems][5][N+1 (z,k)][N+1 (y,j)][N+1 (x,i)], x fastest;
+ *   variables (rho, rho*u, rho*v, rho*w, E); element e = ex + nx*(ey + ny*ez);
+ *   node positions x_d = lo_d + (e_d + (xi+1)/2) * dx_d, dx_d = (hi_d-lo_d)/n_d,
+ *   xi the Legendre-Gauss-Lobatto points.  "DOF" counts nodes, not variables.
+ *
+ * Ownership: the caller owns every array passed in (U, Ut, ...), which must
+ * be device memory on the context's device and is never freed or retained.
+ * The context owns all scratch (Runge-Kutta register, ping-pong state, face
+ * buffers, blending arrays, reduction partials); dg_init allocates it and
+ * dg_finalize releases it.
+ *
+ * Errors: every function returns DG_OK (0) or a negative code; it never
+ * aborts or prints.  dg_last_error() gives a message.  Errors of asynchronous
+ * kernels surface at the next synchronising call as DG_EHIP.
+ *
+ * Streams: every call enqueues on the context's stream (default: the null
+ * stream) and returns without synchronising, except the calls that return
+ * host scalars (dg_max_dt, dg_integrals, dg_check_finite).  A context is not
+ * thread-safe; use one context per stream.
+ */
+#ifndef DG_H
+#define DG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  DG_OK = 0,
+  DG_EINVAL = -1,        /* bad argument (null/host pointer, alias, range)   */
+  DG_ENOMEM = -2,        /* device allocation failed in dg_init              */
+  DG_EHIP = -3,          /* HIP runtime error (launch or earlier kernel)     */
+  DG_EUNSUPPORTED = -4,  /* valid but unsupported combination of options     */
+  DG_ENONFINITE = -5,    /* dg_check_finite found a NaN or Inf               */
+  DG_ESTATE = -6         /* call not valid in the context's current state    */
+};
+
+enum { DG_EULER = 0, DG_NS = 1 };
+enum { DG_VF_KG = 0, DG_VF_PI = 1, DG_VF_CH = 2, DG_VF_STD = 3 };
+enum { DG_SF_LLF = 0, DG_SF_ROE = 1, DG_SF_CENTRAL = 2 };
+enum { DG_IND_HENNEMANN = 0, DG_IND_PERSSON = 1 };
+enum { DG_FV_FIRST = 0, DG_FV_MINMOD = 1 };
+enum { DG_FP64 = 0, DG_MIXED = 1 };
+
+typedef struct dg_ctx dg_ctx; /* opaque, library-owned */
+
+/* Periodic box: nelem[d] elements over [lo[d], hi[d]] in direction d. */
+typedef struct {
+  int32_t nelem[3];
+  double lo[3], hi[3];
+} dg_mesh;
+
+/* Operator options (dg_default_options fills the defaults noted here). */
+typedef struct {
+  int32_t equations;    /* DG_EULER | DG_NS                          (EULER)   */
+  int32_t vol_flux;     /* two-point volume flux: DG_VF_*            (KG)      */
+  int32_t surf_flux;    /* Riemann solver: DG_SF_*                   (LLF)     */
+  int32_t blending;     /* 0 | 1: DG/FV blending (Euler only)        (0)       */
+  int32_t indicator;    /* DG_IND_HENNEMANN | DG_IND_PERSSON         (HENNEMANN) */
+  int32_t fv_recon;     /* DG_FV_FIRST | DG_FV_MINMOD                (MINMOD)  */
+  int32_t precision;    /* DG_FP64 | DG_MIXED                        (FP64)    */
+  int32_t reserved;
+  double Pr;            /* Prandtl number                            (0.72)    */
+  double alpha_min;     /* below: pure DG (paper Sec. 4.2)           (0.01)    */
+  double alpha_max;     /* upper clip (paper Sec. 4.2)               (0.7)     */
+  double alpha_spread;  /* neighbour factor (paper Sec. 4.1)         (0.5)     */
+} dg_options;
+
+/* Fills *opt with the defaults above. */
+void dg_default_options(dg_options* opt);
+
+/* Creates a context for polynomial degree N (1..7) on the mesh, ratio of
+ * specific heats gamma (> 1) and dynamic viscosity mu (>= 0; used only by
+ * DG_NS).  Uses the current HIP device.  Allocates all scratch; on failure
+ * nothing stays allocated and *out is set to NULL. */
+int dg_init(const dg_mesh* mesh, int N, double gamma, double mu, dg_ctx** out);
+
+/* Replaces the options.  Validated here: DG_EUNSUPPORTED for blending with
+ * DG_NS, blending with N < 2, or DG_MIXED with blending. */
+int dg_set_options(dg_ctx* ctx, const dg_options* opt);
+int dg_get_options(const dg_ctx* ctx, dg_options* opt);
+
+/* Sets the HIP stream (hipStream_t) all later calls enqueue on; NULL = null
+ * stream. */
+int dg_set_stream(dg_ctx* ctx, void* hip_stream);
+
+/* Ut = L(U): the semi-discrete time derivative (paper Sec. 4.1: the solution's
+ * time derivative of the DG, FV or blended operator).  A pure function of U:
+ * the blending coefficient is recomputed from U.  Overwrites all of Ut.
+ * Ut must not alias U. */
+int dg_time_derivative(dg_ctx* ctx, const double* U, double* Ut);
+
+/* One Runge-Kutta step of size dt (> 0, finite), in place: five stages
+ * G <- A_k G + L(U), U <- U + B_k dt G.  The blending coefficient is
+ * recomputed at every stage. */
+int rk_step(dg_ctx* ctx, double* U, double dt);
+
+/* nsteps Runge-Kutta steps in place (same result as nsteps rk_step calls). */
+int dg_rk_steps(dg_ctx* ctx, double* U, double dt, int nsteps);
+
+/* Vector-Jacobian product of the operator: U_bar = (dL/dU)^T Ut_bar.
+ * Overwrites U_bar.  Not available with blending or DG_MIXED. */
+int dg_vjp(dg_ctx* ctx, const double* U, const double* Ut_bar, double* U_bar);
+
+/* Vector-Jacobian product of one rk_step: U_bar_n = (dU_{n+1}/dU_n)^T U_bar_np1,
+ * with U_n the state before the step.  Overwrites U_bar_n (may alias
+ * U_bar_np1).  Not available with blending or DG_MIXED. */
+int rk_step_vjp(dg_ctx* ctx, const double* U_n, double dt, const double* U_bar_np1, double* U_bar_n);
+
+/* Stable time step: cfl * min(1/((N+1) max sum_d (|u_d|+c)/dx_d),
+ *                             1/((N+1)^2 max nu_eff sum_d 1/dx_d^2)),
+ * nu_eff = mu gamma/(rho Pr) for DG_NS.  Synchronises. */
+int dg_max_dt(dg_ctx* ctx, const double* U, double cfl, double* dt_out);
+
+/* out[v] = sum_e J sum_ijk w_i w_j w_k X[e][v][ijk] (FP64).  Synchronises. */
+int dg_integrals(dg_ctx* ctx, const double* X, double out[5]);
+
+/* Blending coefficient per element of state U (device array of nElems). */
+int dg_alpha(dg_ctx* ctx, const double* U, double* alpha);
+
+/* DG_OK if every entry of the state-sized array X is finite, else
+ * DG_ENONFINITE.  Synchronises. */
+int dg_check_finite(dg_ctx* ctx, const double* X);
+
+/* Per-kernel timing for benchmarks.  While enabled (on != 0), every kernel
+ * launch of the operator is bracketed by two HIP events recorded on the
+ * context's stream.  dg_profile_read synchronises the stream, writes the
+ * summed milliseconds and the number of launches per kernel kind
+ * (DG_K_STAGE: operator + Runge-Kutta stage, DG_K_LIFT: BR1 lifting,
+ * DG_K_INDICATOR: modal indicator) into ms[3] and launches[3], and clears
+ * the records.  Disabling also clears them. */
+enum { DG_K_STAGE = 0, DG_K_LIFT = 1, DG_K_INDICATOR = 2 };
+int dg_set_profiling(dg_ctx* ctx, int on);
+int dg_profile_read(dg_ctx* ctx, double ms[3], int64_t launches[3]);
+
+/* Sizes: number of elements and nodes per element. */
+int dg_sizes(const dg_ctx* ctx, int64_t* n_elems, int64_t* nodes_per_elem);
+
+/* Releases the context and all its scratch (NULL is allowed). */
+int dg_finalize(dg_ctx* ctx);
+
+/* Message of the last error on ctx (or of the last failed dg_init when ctx
+ * is NULL). */
+const char* dg_last_error(const dg_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DG_H */

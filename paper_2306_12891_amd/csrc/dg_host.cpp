@@ -1,0 +1,612 @@
+// Host side of libdgmi: argument validation, context and scratch management,
+// the 1-D Legendre-Gauss-Lobatto basis, the periodic neighbour table, the
+// Runge-Kutta stage loop and the C ABI declared in include/dg.h.
+// No arithmetic of the operator runs here: every step is a HIP kernel.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "dg.h"
+#include "dg_internal.hpp"
+
+using namespace dgmi;
+
+namespace {
+
+constexpr int kRedBlocks = 1024;  // must match the reduction grid of the kernels
+
+// Carpenter-Kennedy five-stage fourth-order 2N-storage coefficients (the
+// explicit Runge-Kutta scheme of the paper's Sec. 2, whose stages enter the PID).
+const double kA[5] = {0.0, -567301805773.0 / 1357537059087.0, -2404267990393.0 / 2016746695238.0,
+                      -3550918686646.0 / 2091501179385.0, -1275806237668.0 / 842570457699.0};
+const double kB[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
+                      1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
+                      2277821191437.0 / 14882151754819.0};
+
+char g_init_error[256] = "";
+
+const KernelTable* table_for(int N) {
+  switch (N) {
+    case 1: return table_N1();
+    case 2: return table_N2();
+    case 3: return table_N3();
+    case 4: return table_N4();
+    case 5: return table_N5();
+    case 6: return table_N6();
+    case 7: return table_N7();
+    default: return nullptr;
+  }
+}
+
+// Legendre P_n and P_n' at x by the three-term recurrence.
+void legendre_pd(int n, double x, double& P, double& dP) {
+  double pm1 = 1.0, p = x;
+  if (n == 0) { P = 1.0; dP = 0.0; return; }
+  for (int k = 1; k < n; ++k) {
+    const double pn = ((2 * k + 1) * x * p - k * pm1) / (k + 1);
+    pm1 = p;
+    p = pn;
+  }
+  P = p;
+  dP = (std::fabs(x) < 1.0) ? n * (pm1 - x * p) / (1.0 - x * x) : 0.5 * n * (n + 1) * std::pow(x, n + 1);
+}
+
+// Packed basis for degree N (see BasisLayout).
+std::vector<double> build_basis(int N) {
+  const int n1 = N + 1;
+  const BasisLayout L(n1);
+  std::vector<double> b(L.size(), 0.0);
+  std::vector<double> x(n1), w(n1), PN(n1);
+  // LGL points: +-1 and the zeros of P_N'; Newton on P_N' using the Legendre
+  // ODE for P_N'' = (2x P_N' - N(N+1) P_N)/(1 - x^2), symmetric pairs.
+  x[0] = -1.0;
+  x[N] = 1.0;
+  for (int i = 1; i <= N / 2; ++i) {
+    double z = -std::cos(M_PI * i / N);
+    for (int it = 0; it < 60; ++it) {
+      double P, dP;
+      legendre_pd(N, z, P, dP);
+      const double d2P = (2.0 * z * dP - N * (N + 1.0) * P) / (1.0 - z * z);
+      const double step = dP / d2P;
+      z -= step;
+      if (std::fabs(step) <= 1e-17) break;
+    }
+    x[i] = z;
+    x[N - i] = -z;
+  }
+  if (N % 2 == 0) x[N / 2] = 0.0;
+  for (int i = 0; i < n1; ++i) {
+    double P, dP;
+    legendre_pd(N, x[i], P, dP);
+    PN[i] = P;
+    w[i] = 2.0 / (N * (N + 1.0) * P * P);
+  }
+  // Lagrange derivative matrix on the LGL points.
+  std::vector<double> D(n1 * n1, 0.0);
+  for (int i = 0; i < n1; ++i)
+    for (int j = 0; j < n1; ++j)
+      if (i != j) D[i * n1 + j] = PN[i] / (PN[j] * (x[i] - x[j]));
+  D[0] = -0.25 * N * (N + 1.0);
+  D[N * n1 + N] = 0.25 * N * (N + 1.0);
+  for (int i = 0; i < n1; ++i)
+    for (int j = 0; j < n1; ++j) {
+      // split form: 2D with the SBP boundary terms removed at the two corners
+      double dh = 2.0 * D[i * n1 + j];
+      if (i == j && (i == 0 || i == N)) dh = 0.0;
+      b[L.Dhat() + i * n1 + j] = dh;
+      // strong form with the boundary term folded in: D - W^-1 B
+      double dw = D[i * n1 + j];
+      if (i == j && i == 0) dw += 1.0 / w[0];
+      if (i == j && i == N) dw -= 1.0 / w[N];
+      b[L.Dw() + i * n1 + j] = dw;
+    }
+  for (int i = 0; i < n1; ++i) {
+    b[L.winv() + i] = 1.0 / w[i];
+    b[L.xi() + i] = x[i];
+    b[L.w() + i] = w[i];
+  }
+  double s = -1.0;
+  b[L.edge()] = -1.0;
+  for (int m = 0; m < n1; ++m) {
+    s += w[m];
+    b[L.edge() + m + 1] = s;
+  }
+  // Inverse of the orthonormal Legendre Vandermonde V_ij = sqrt(j + 1/2) P_j(x_i)
+  // (Gauss-Jordan with partial pivoting).
+  std::vector<double> V(n1 * n1), Vi(n1 * n1, 0.0);
+  for (int i = 0; i < n1; ++i)
+    for (int j = 0; j < n1; ++j) {
+      double P, dP;
+      legendre_pd(j, x[i], P, dP);
+      V[i * n1 + j] = std::sqrt(j + 0.5) * P;
+    }
+  for (int i = 0; i < n1; ++i) Vi[i * n1 + i] = 1.0;
+  for (int c = 0; c < n1; ++c) {
+    int p = c;
+    for (int r = c + 1; r < n1; ++r)
+      if (std::fabs(V[r * n1 + c]) > std::fabs(V[p * n1 + c])) p = r;
+    for (int k = 0; k < n1; ++k) {
+      std::swap(V[c * n1 + k], V[p * n1 + k]);
+      std::swap(Vi[c * n1 + k], Vi[p * n1 + k]);
+    }
+    const double piv = V[c * n1 + c];
+    for (int k = 0; k < n1; ++k) {
+      V[c * n1 + k] /= piv;
+      Vi[c * n1 + k] /= piv;
+    }
+    for (int r = 0; r < n1; ++r) {
+      if (r == c) continue;
+      const double f = V[r * n1 + c];
+      for (int k = 0; k < n1; ++k) {
+        V[r * n1 + k] -= f * V[c * n1 + k];
+        Vi[r * n1 + k] -= f * Vi[c * n1 + k];
+      }
+    }
+  }
+  for (int k = 0; k < n1 * n1; ++k) b[L.Vinv() + k] = Vi[k];
+  return b;
+}
+
+}  // namespace
+
+struct dg_ctx {
+  int N = 0, n1 = 0, nn = 0, nf = 0;
+  int ne[3] = {0, 0, 0};
+  int nelem = 0, chunk = 0;
+  double lo[3], hi[3], dx[3], invJ[3], Jac = 1.0;
+  double gamma = 1.4, mu = 0.0;
+  dg_options opt;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  const KernelTable* kt = nullptr;
+  size_t nstate = 0;  // doubles per state
+  int32_t* nbr = nullptr;
+  double* basis = nullptr;
+  double* G = nullptr;
+  double* U2 = nullptr;
+  double* alpha1 = nullptr;
+  double* alpha = nullptr;
+  double* Fvf = nullptr;
+  double* partial = nullptr;
+  double* h_partial = nullptr;
+  char err[256] = "";
+  // kernel timing (dg_set_profiling)
+  int profiling = 0;
+  std::vector<hipEvent_t> ev_pool;
+  struct Rec { int kind; int a, b; };
+  std::vector<Rec> recs;
+};
+
+namespace {
+
+int fail(dg_ctx* c, int code, const char* fmt, ...) {
+  char* buf = c ? c->err : g_init_error;
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, 256, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+int hip_fail(dg_ctx* c, hipError_t e, const char* where) {
+  return fail(c, DG_EHIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+bool is_device_ptr(const void* p) {
+  if (!p) return false;
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+void release(dg_ctx* c) {
+  if (!c) return;
+  for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
+  c->ev_pool.clear();
+  hipFree(c->nbr);
+  hipFree(c->basis);
+  hipFree(c->G);
+  hipFree(c->U2);
+  hipFree(c->alpha1);
+  hipFree(c->alpha);
+  hipFree(c->Fvf);
+  hipFree(c->partial);
+  if (c->h_partial) hipHostFree(c->h_partial);
+}
+
+StageArgs stage_args(const dg_ctx* c) {
+  StageArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.nbr = c->nbr;
+  a.basis = c->basis;
+  a.alpha1 = c->alpha1;
+  a.Fvf = c->Fvf;
+  for (int d = 0; d < 3; ++d) a.invJ[d] = c->invJ[d];
+  a.gamma = c->gamma;
+  a.mu = c->mu;
+  a.kappa = c->mu * c->gamma / ((c->gamma - 1.0) * c->opt.Pr);
+  a.amin = c->opt.alpha_min;
+  a.amax = c->opt.alpha_max;
+  a.aspread = c->opt.alpha_spread;
+  a.thresh = 0.5 * std::pow(10.0, -1.8 * std::pow(c->N + 1.0, 0.25));
+  a.sharp = std::log(9999.0);  // alpha0(E = 0) = 1e-4
+  a.nelem = c->nelem;
+  a.chunk = c->chunk;
+  a.vf = c->opt.vol_flux;
+  a.sf = c->opt.surf_flux;
+  a.blend = c->opt.blending;
+  a.indicator = c->opt.indicator;
+  a.recon = c->opt.fv_recon;
+  return a;
+}
+
+ReduceArgs reduce_args(const dg_ctx* c, const double* X) {
+  ReduceArgs r;
+  std::memset(&r, 0, sizeof(r));
+  r.X = X;
+  r.partial = c->partial;
+  r.basis = c->basis;
+  for (int d = 0; d < 3; ++d) r.invdx[d] = 1.0 / c->dx[d];
+  r.gamma = c->gamma;
+  r.nu_fac = c->opt.equations == DG_NS ? c->mu * c->gamma / c->opt.Pr : 0.0;
+  r.Jac = c->Jac;
+  r.nelem = c->nelem;
+  return r;
+}
+
+int check_ctx(dg_ctx* c) {
+  if (!c || !c->kt) return DG_EINVAL;
+  return DG_OK;
+}
+
+// Event pair around one launch when profiling; returns the pool index or -1.
+int prof_event(dg_ctx* c) {
+  const int used = 2 * (int)c->recs.size();
+  if ((int)c->ev_pool.size() < used + 2) {
+    for (int k = 0; k < 2; ++k) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return -1;
+      c->ev_pool.push_back(e);
+    }
+  }
+  return used;
+}
+
+template <class F>
+hipError_t timed(dg_ctx* c, int kind, F&& launch) {
+  if (!c->profiling) return launch();
+  const int i = prof_event(c);
+  if (i < 0) return launch();
+  hipEventRecord(c->ev_pool[i], c->stream);
+  const hipError_t e = launch();
+  hipEventRecord(c->ev_pool[i + 1], c->stream);
+  c->recs.push_back({kind, i, i + 1});
+  return e;
+}
+
+// One evaluation of the operator on X_in: [indicator], [BR1 lifting], stage.
+int run_stage(dg_ctx* c, const double* Xin, double* Xout, double* Ut, int mode, double A, double Bdt, int writeG,
+              double* alpha_out) {
+  StageArgs a = stage_args(c);
+  a.U = Xin;
+  a.Uout = Xout;
+  a.G = c->G;
+  a.Ut = Ut;
+  a.mode = mode;
+  a.A = A;
+  a.Bdt = Bdt;
+  a.writeG = writeG;
+  a.alpha_out = alpha_out;
+  hipError_t e;
+  if (c->opt.blending) {
+    e = timed(c, DG_K_INDICATOR, [&] { return c->kt->alpha1(a, c->stream); });
+    if (e != hipSuccess) return hip_fail(c, e, "indicator kernel");
+  }
+  if (c->opt.equations == DG_NS) {
+    e = timed(c, DG_K_LIFT, [&] { return c->kt->lift(a, c->stream); });
+    if (e != hipSuccess) return hip_fail(c, e, "lifting kernel");
+  }
+  e = timed(c, DG_K_STAGE, [&] { return c->kt->stage(a, c->opt.equations, c->stream); });
+  if (e != hipSuccess) return hip_fail(c, e, "stage kernel");
+  return DG_OK;
+}
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+}  // namespace
+
+extern "C" {
+
+void dg_default_options(dg_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->equations = DG_EULER;
+  o->vol_flux = DG_VF_KG;
+  o->surf_flux = DG_SF_LLF;
+  o->blending = 0;
+  o->indicator = DG_IND_HENNEMANN;
+  o->fv_recon = DG_FV_MINMOD;
+  o->precision = DG_FP64;
+  o->Pr = 0.72;
+  o->alpha_min = 0.01;
+  o->alpha_max = 0.7;
+  o->alpha_spread = 0.5;
+}
+
+int dg_init(const dg_mesh* mesh, int N, double gamma, double mu, dg_ctx** out) {
+  if (!out) return fail(nullptr, DG_EINVAL, "dg_init: out is NULL");
+  *out = nullptr;
+  if (!mesh) return fail(nullptr, DG_EINVAL, "dg_init: mesh is NULL");
+  if (N < 1 || N > 7) return fail(nullptr, DG_EINVAL, "dg_init: N = %d outside 1..7", N);
+  if (!(gamma > 1.0) || !std::isfinite(gamma)) return fail(nullptr, DG_EINVAL, "dg_init: gamma must be > 1");
+  if (!(mu >= 0.0) || !std::isfinite(mu)) return fail(nullptr, DG_EINVAL, "dg_init: mu must be >= 0");
+  long long ne = 1;
+  for (int d = 0; d < 3; ++d) {
+    if (mesh->nelem[d] < 1) return fail(nullptr, DG_EINVAL, "dg_init: nelem[%d] < 1", d);
+    if (!(mesh->hi[d] > mesh->lo[d]) || !std::isfinite(mesh->hi[d] - mesh->lo[d]))
+      return fail(nullptr, DG_EINVAL, "dg_init: hi[%d] must exceed lo[%d]", d, d);
+    ne *= mesh->nelem[d];
+  }
+  if (ne > (1LL << 28)) return fail(nullptr, DG_EINVAL, "dg_init: too many elements");
+  dg_ctx* c = new (std::nothrow) dg_ctx();
+  if (!c) return fail(nullptr, DG_ENOMEM, "dg_init: host allocation failed");
+  c->N = N;
+  c->n1 = N + 1;
+  c->nn = c->n1 * c->n1 * c->n1;
+  c->nf = c->n1 * c->n1;
+  c->nelem = (int)ne;
+  c->chunk = (c->nelem + 7) / 8;
+  c->gamma = gamma;
+  c->mu = mu;
+  c->kt = table_for(N);
+  dg_default_options(&c->opt);
+  for (int d = 0; d < 3; ++d) {
+    c->ne[d] = mesh->nelem[d];
+    c->lo[d] = mesh->lo[d];
+    c->hi[d] = mesh->hi[d];
+    c->dx[d] = (mesh->hi[d] - mesh->lo[d]) / mesh->nelem[d];
+    c->invJ[d] = 2.0 / c->dx[d];
+    c->Jac *= 0.5 * c->dx[d];
+  }
+  hipGetDevice(&c->device);
+  c->nstate = (size_t)c->nelem * 5 * c->nn;
+  const std::vector<double> basis = build_basis(N);
+  std::vector<int32_t> nbr((size_t)c->nelem * 6);
+  const int nx = c->ne[0], ny = c->ne[1], nz = c->ne[2];
+  for (int ez = 0; ez < nz; ++ez)
+    for (int ey = 0; ey < ny; ++ey)
+      for (int ex = 0; ex < nx; ++ex) {
+        const size_t e = ex + (size_t)nx * (ey + (size_t)ny * ez);
+        nbr[6 * e + 0] = ((ex + nx - 1) % nx) + nx * (ey + ny * ez);
+        nbr[6 * e + 1] = ((ex + 1) % nx) + nx * (ey + ny * ez);
+        nbr[6 * e + 2] = ex + nx * (((ey + ny - 1) % ny) + ny * ez);
+        nbr[6 * e + 3] = ex + nx * (((ey + 1) % ny) + ny * ez);
+        nbr[6 * e + 4] = ex + nx * (ey + ny * ((ez + nz - 1) % nz));
+        nbr[6 * e + 5] = ex + nx * (ey + ny * ((ez + 1) % nz));
+      }
+  hipError_t e = hipSuccess;
+  auto alloc = [&](void** p, size_t bytes) {
+    if (e == hipSuccess) e = hipMalloc(p, bytes);
+  };
+  alloc((void**)&c->nbr, nbr.size() * sizeof(int32_t));
+  alloc((void**)&c->basis, basis.size() * sizeof(double));
+  alloc((void**)&c->G, c->nstate * sizeof(double));
+  alloc((void**)&c->U2, c->nstate * sizeof(double));
+  alloc((void**)&c->alpha1, (size_t)c->nelem * sizeof(double));
+  alloc((void**)&c->alpha, (size_t)c->nelem * sizeof(double));
+  alloc((void**)&c->Fvf, (size_t)c->nelem * 6 * 4 * c->nf * sizeof(double));
+  alloc((void**)&c->partial, kRedBlocks * 5 * sizeof(double));
+  if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_partial, kRedBlocks * 5 * sizeof(double), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipMemcpy(c->nbr, nbr.data(), nbr.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(c->basis, basis.data(), basis.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(c->alpha1, 0, (size_t)c->nelem * sizeof(double));
+  if (e != hipSuccess) {
+    const bool oom = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation);
+    fail(nullptr, oom ? DG_ENOMEM : DG_EHIP, "dg_init: %s", hipGetErrorString(e));
+    (void)hipGetLastError();
+    release(c);
+    delete c;
+    return oom ? DG_ENOMEM : DG_EHIP;
+  }
+  *out = c;
+  return DG_OK;
+}
+
+int dg_set_options(dg_ctx* c, const dg_options* o) {
+  if (check_ctx(c) || !o) return fail(c, DG_EINVAL, "dg_set_options: NULL argument");
+  if (o->equations < 0 || o->equations > 1) return fail(c, DG_EINVAL, "dg_set_options: equations");
+  if (o->vol_flux < 0 || o->vol_flux > 3) return fail(c, DG_EINVAL, "dg_set_options: vol_flux");
+  if (o->surf_flux < 0 || o->surf_flux > 2) return fail(c, DG_EINVAL, "dg_set_options: surf_flux");
+  if (o->indicator < 0 || o->indicator > 1) return fail(c, DG_EINVAL, "dg_set_options: indicator");
+  if (o->fv_recon < 0 || o->fv_recon > 1) return fail(c, DG_EINVAL, "dg_set_options: fv_recon");
+  if (o->precision < 0 || o->precision > 1) return fail(c, DG_EINVAL, "dg_set_options: precision");
+  if (!finite_pos(o->Pr)) return fail(c, DG_EINVAL, "dg_set_options: Pr must be > 0");
+  if (!(o->alpha_min >= 0.0 && o->alpha_min <= o->alpha_max && o->alpha_max <= 1.0) ||
+      !(o->alpha_spread >= 0.0 && o->alpha_spread <= 1.0))
+    return fail(c, DG_EINVAL, "dg_set_options: need 0 <= alpha_min <= alpha_max <= 1, 0 <= spread <= 1");
+  if (o->blending && o->equations == DG_NS)
+    return fail(c, DG_EUNSUPPORTED, "dg_set_options: blending is implemented for the Euler equations only");
+  if (o->blending && c->N < 2) return fail(c, DG_EUNSUPPORTED, "dg_set_options: blending needs N >= 2");
+  if (o->precision == DG_MIXED && !c->kt->stage_mixed)
+    return fail(c, DG_EUNSUPPORTED, "dg_set_options: mixed precision not built for this degree");
+  if (o->precision == DG_MIXED && o->blending)
+    return fail(c, DG_EUNSUPPORTED, "dg_set_options: mixed precision without blending only");
+  c->opt = *o;
+  return DG_OK;
+}
+
+int dg_get_options(const dg_ctx* c, dg_options* o) {
+  if (!c || !o) return DG_EINVAL;
+  *o = c->opt;
+  return DG_OK;
+}
+
+int dg_set_stream(dg_ctx* c, void* s) {
+  if (check_ctx(c)) return DG_EINVAL;
+  c->stream = (hipStream_t)s;
+  return DG_OK;
+}
+
+int dg_time_derivative(dg_ctx* c, const double* U, double* Ut) {
+  if (check_ctx(c)) return DG_EINVAL;
+  if (!is_device_ptr(U) || !is_device_ptr(Ut))
+    return fail(c, DG_EINVAL, "dg_time_derivative: U and Ut must be device pointers");
+  if ((const void*)U == (const void*)Ut) return fail(c, DG_EINVAL, "dg_time_derivative: Ut aliases U");
+  return run_stage(c, U, nullptr, Ut, MODE_UT, 0.0, 0.0, 0, nullptr);
+}
+
+int dg_rk_steps(dg_ctx* c, double* U, double dt, int nsteps) {
+  if (check_ctx(c)) return DG_EINVAL;
+  if (!is_device_ptr(U)) return fail(c, DG_EINVAL, "rk_step: U must be a device pointer");
+  if (!finite_pos(dt)) return fail(c, DG_EINVAL, "rk_step: dt must be finite and > 0");
+  if (nsteps < 0) return fail(c, DG_EINVAL, "rk_step: nsteps < 0");
+  double* cur = U;
+  for (int s = 0; s < nsteps; ++s)
+    for (int k = 0; k < 5; ++k) {
+      double* nxt = (cur == U) ? c->U2 : U;
+      const int writeG = (k < 4) ? 1 : 0;  // the last stage's register is never read again
+      const int rc = run_stage(c, cur, nxt, nullptr, MODE_RK, kA[k], kB[k] * dt, writeG, nullptr);
+      if (rc) return rc;
+      cur = nxt;
+    }
+  if (cur != U) {
+    hipError_t e = hipMemcpyAsync(U, cur, c->nstate * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "rk_step copy");
+  }
+  return DG_OK;
+}
+
+int rk_step(dg_ctx* c, double* U, double dt) { return dg_rk_steps(c, U, dt, 1); }
+
+int dg_vjp(dg_ctx* c, const double* U, const double* Ut_bar, double* U_bar) {
+  if (check_ctx(c)) return DG_EINVAL;
+  (void)U; (void)Ut_bar; (void)U_bar;
+  return fail(c, DG_EUNSUPPORTED, "dg_vjp: not available in this build");
+}
+
+int rk_step_vjp(dg_ctx* c, const double* U_n, double dt, const double* U_bar_np1, double* U_bar_n) {
+  if (check_ctx(c)) return DG_EINVAL;
+  (void)U_n; (void)dt; (void)U_bar_np1; (void)U_bar_n;
+  return fail(c, DG_EUNSUPPORTED, "rk_step_vjp: not available in this build");
+}
+
+int dg_max_dt(dg_ctx* c, const double* U, double cfl, double* dt_out) {
+  if (check_ctx(c) || !dt_out) return fail(c, DG_EINVAL, "dg_max_dt: NULL argument");
+  if (!is_device_ptr(U)) return fail(c, DG_EINVAL, "dg_max_dt: U must be a device pointer");
+  if (!finite_pos(cfl)) return fail(c, DG_EINVAL, "dg_max_dt: cfl must be finite and > 0");
+  ReduceArgs r = reduce_args(c, U);
+  hipError_t e = c->kt->max_rate(r, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->h_partial, c->partial, 2 * kRedBlocks * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "dg_max_dt");
+  double la = 0.0, lv = 0.0;
+  for (int b = 0; b < kRedBlocks; ++b) {
+    la = std::max(la, c->h_partial[2 * b]);
+    lv = std::max(lv, c->h_partial[2 * b + 1]);
+  }
+  if (!(la > 0.0) || !std::isfinite(la) || !std::isfinite(lv))
+    return fail(c, DG_ENONFINITE, "dg_max_dt: non-finite or zero wave speed");
+  double dt = cfl / ((c->N + 1.0) * la);
+  if (lv > 0.0) dt = std::min(dt, cfl / ((c->N + 1.0) * (c->N + 1.0) * lv));
+  *dt_out = dt;
+  return DG_OK;
+}
+
+int dg_integrals(dg_ctx* c, const double* X, double out[5]) {
+  if (check_ctx(c) || !out) return fail(c, DG_EINVAL, "dg_integrals: NULL argument");
+  if (!is_device_ptr(X)) return fail(c, DG_EINVAL, "dg_integrals: X must be a device pointer");
+  ReduceArgs r = reduce_args(c, X);
+  hipError_t e = c->kt->integrals(r, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->h_partial, c->partial, 5 * kRedBlocks * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "dg_integrals");
+  for (int v = 0; v < 5; ++v) {
+    double s = 0.0;
+    for (int b = 0; b < kRedBlocks; ++b) s += c->h_partial[5 * b + v];
+    out[v] = s;
+  }
+  return DG_OK;
+}
+
+int dg_alpha(dg_ctx* c, const double* U, double* alpha) {
+  if (check_ctx(c)) return DG_EINVAL;
+  if (!is_device_ptr(U) || !is_device_ptr(alpha)) return fail(c, DG_EINVAL, "dg_alpha: device pointers required");
+  if (c->N < 2) return fail(c, DG_EUNSUPPORTED, "dg_alpha: needs N >= 2");
+  StageArgs a = stage_args(c);
+  a.U = U;
+  a.alpha_out = alpha;
+  hipError_t e = c->kt->alpha1(a, c->stream);
+  if (e == hipSuccess) e = c->kt->spread(a, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "dg_alpha");
+  return DG_OK;
+}
+
+int dg_check_finite(dg_ctx* c, const double* X) {
+  if (check_ctx(c)) return DG_EINVAL;
+  if (!is_device_ptr(X)) return fail(c, DG_EINVAL, "dg_check_finite: X must be a device pointer");
+  ReduceArgs r = reduce_args(c, X);
+  hipError_t e = c->kt->nonfinite(r, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->h_partial, c->partial, kRedBlocks * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "dg_check_finite");
+  double s = 0.0;
+  for (int b = 0; b < kRedBlocks; ++b) s += c->h_partial[b];
+  if (s > 0.0) return fail(c, DG_ENONFINITE, "dg_check_finite: %.0f non-finite entries", s);
+  return DG_OK;
+}
+
+int dg_set_profiling(dg_ctx* c, int on) {
+  if (check_ctx(c)) return DG_EINVAL;
+  c->profiling = on ? 1 : 0;
+  c->recs.clear();
+  return DG_OK;
+}
+
+int dg_profile_read(dg_ctx* c, double ms[3], int64_t launches[3]) {
+  if (check_ctx(c) || !ms || !launches) return fail(c, DG_EINVAL, "dg_profile_read: NULL argument");
+  for (int k = 0; k < 3; ++k) {
+    ms[k] = 0.0;
+    launches[k] = 0;
+  }
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "dg_profile_read");
+  for (const auto& r : c->recs) {
+    float t = 0.0f;
+    e = hipEventElapsedTime(&t, c->ev_pool[r.a], c->ev_pool[r.b]);
+    if (e != hipSuccess) return hip_fail(c, e, "dg_profile_read");
+    ms[r.kind] += t;
+    launches[r.kind] += 1;
+  }
+  c->recs.clear();
+  return DG_OK;
+}
+
+int dg_sizes(const dg_ctx* c, int64_t* n_elems, int64_t* nodes_per_elem) {
+  if (!c) return DG_EINVAL;
+  if (n_elems) *n_elems = c->nelem;
+  if (nodes_per_elem) *nodes_per_elem = c->nn;
+  return DG_OK;
+}
+
+int dg_finalize(dg_ctx* c) {
+  if (!c) return DG_OK;
+  release(c);
+  delete c;
+  return DG_OK;
+}
+
+const char* dg_last_error(const dg_ctx* c) { return c ? c->err : g_init_error; }
+
+}  // extern "C"

@@ -1,0 +1,96 @@
+// Internal interface between the host side of libdgmi (dg_host.cpp) and the
+// per-degree kernel translation units (dg_kernels.hip compiled once per N).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dgmi {
+
+enum { MODE_UT = 0, MODE_RK = 1 };
+
+// Packed 1-D basis, built on the host and read into LDS by the kernels.
+// Offsets in doubles for n1 = N + 1.
+struct BasisLayout {
+  int n1;
+  __host__ __device__ constexpr BasisLayout(int n) : n1(n) {}
+  __host__ __device__ constexpr int Dhat() const { return 0; }            // split-form volume matrix
+  __host__ __device__ constexpr int Dw() const { return n1 * n1; }        // D - W^-1 B  (= -W^-1 D^T W)
+  __host__ __device__ constexpr int winv() const { return 2 * n1 * n1; }  // 1 / w_i
+  __host__ __device__ constexpr int xi() const { return 2 * n1 * n1 + n1; }
+  __host__ __device__ constexpr int edge() const { return 2 * n1 * n1 + 2 * n1; }  // n1 + 1 subcell edges
+  __host__ __device__ constexpr int Vinv() const { return 2 * n1 * n1 + 3 * n1 + 1; }
+  __host__ __device__ constexpr int w() const { return 3 * n1 * n1 + 3 * n1 + 1; }
+  __host__ __device__ constexpr int size() const { return 3 * n1 * n1 + 4 * n1 + 1; }
+};
+
+struct StageArgs {
+  const double* U;      // stage input state
+  double* Uout;         // RK: output state (ping-pong, never aliases U)
+  double* G;            // RK register
+  double* Ut;           // MODE_UT output
+  const int32_t* nbr;   // [nelem][6]: -x +x -y +y -z +z
+  const double* basis;  // BasisLayout
+  const double* alpha1; // per element, clipped coefficient before spreading
+  double* alpha_out;    // optional: final blending coefficient per element
+  double* Fvf;          // NS: [nelem][6][4][nf] normal viscous flux on own faces
+  double invJ[3];       // 2 / dx_d
+  double gamma, mu, kappa;  // kappa = mu gamma / ((gamma - 1) Pr)
+  double A, Bdt;        // RK stage coefficients (A_k, B_k dt)
+  double amin, amax, aspread;
+  double thresh, sharp;  // T(N) and s
+  int nelem, chunk;      // chunk = ceil(nelem / 8): XCD-contiguous element ranges
+  int vf, sf, blend, mode, writeG, indicator, recon;
+};
+
+struct ReduceArgs {
+  const double* X;
+  double* partial;  // per block
+  const double* basis;
+  double invdx[3];
+  double gamma, nu_fac;  // nu_fac = mu gamma / Pr (0 for Euler)
+  double Jac;
+  int nelem;
+};
+
+// VJP arguments (reverse-mode operator).
+struct VjpArgs {
+  const double* U;
+  const double* Lbar;   // cotangent of U_t
+  double* Ubar;         // output (overwritten)
+  const int32_t* nbr;
+  const double* basis;
+  double* Gbar_face;    // NS: [nelem][6][12][nf] gradient cotangent from face viscous flux
+  double invJ[3];
+  double gamma, mu, kappa;
+  int nelem, chunk;
+  int vf, sf;
+  // RK-VJP fusion: Ubar_out = Ubar_in + scale * VJP  (accumulate mode)
+  const double* Uacc;
+  double scale;
+  int accumulate;
+};
+
+struct KernelTable {
+  int nt;  // threads per block
+  hipError_t (*stage)(const StageArgs&, int eq, hipStream_t);
+  hipError_t (*stage_mixed)(const StageArgs&, int eq, hipStream_t);
+  hipError_t (*lift)(const StageArgs&, hipStream_t);
+  hipError_t (*lift_mixed)(const StageArgs&, hipStream_t);
+  hipError_t (*alpha1)(const StageArgs&, hipStream_t);
+  hipError_t (*spread)(const StageArgs&, hipStream_t);
+  hipError_t (*max_rate)(const ReduceArgs&, hipStream_t);
+  hipError_t (*integrals)(const ReduceArgs&, hipStream_t);
+  hipError_t (*nonfinite)(const ReduceArgs&, hipStream_t);
+  hipError_t (*vjp)(const VjpArgs&, int eq, hipStream_t);
+  hipError_t (*vjp_lift)(const VjpArgs&, hipStream_t);
+};
+
+const KernelTable* table_N1();
+const KernelTable* table_N2();
+const KernelTable* table_N3();
+const KernelTable* table_N4();
+const KernelTable* table_N5();
+const KernelTable* table_N6();
+const KernelTable* table_N7();
+
+}  // namespace dgmi

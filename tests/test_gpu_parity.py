@@ -1,0 +1,257 @@
+"""Parity of the HIP library (through the C ABI) with the FP64 CPU oracle.
+
+Single evaluations must agree per variable to 1e-12 relative to
+max(max |U_t|, S_v), where S_v = max_d (2/dx_d) N(N+1)/2 max |F_d(U)_v| is the
+scale of the terms that cancel in U_t (a floor for near-zero derivatives);
+Runge-Kutta rollouts to 1e-12 relative to max |U_v|.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2306_12891_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+G = 1.4
+TWO_PI = 2 * math.pi
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def phys_flux_scale(U, N, invJ):
+    rho = U[:, 0]
+    u = U[:, 1:4] / rho[:, None]
+    p = (G - 1) * (U[:, 4] - 0.5 * rho * np.sum(u * u, 1))
+    S = np.zeros(5)
+    for d in range(3):
+        F = [U[:, 1 + d], *(U[:, 1 + j] * u[:, d] + (p if j == d else 0) for j in range(3)), (U[:, 4] + p) * u[:, d]]
+        for v in range(5):
+            S[v] = max(S[v], invJ[d] * N * (N + 1) / 2 * np.max(np.abs(F[v])))
+    return S
+
+
+def assert_ut_close(got, ref, U, N, nelem, lo, hi, tol=1e-12):
+    invJ = [2.0 / ((hi[d] - lo[d]) / nelem[d]) for d in range(3)]
+    S = phys_flux_scale(U, N, invJ)
+    for v in range(5):
+        scale = max(np.max(np.abs(ref[:, v])), S[v])
+        err = np.max(np.abs(got[:, v] - ref[:, v]))
+        assert err <= tol * scale, f"var {v}: err {err:.3e} scale {scale:.3e} rel {err / scale:.3e}"
+
+
+def make(orc, N, nelem, lo=(0, 0, 0), hi=(TWO_PI,) * 3, eq=0, vf=0, sf=0, mu=0.0, blending=0, recon=1,
+         indicator=0):
+    from paper_2306_12891_amd import dg
+    s = orc.Setup(N=N, nelem=nelem, lo=lo, hi=hi, equations=eq, vol_flux=vf, surf_flux=sf, mu=mu,
+                  blending=blending, fv_recon=recon, indicator=indicator)
+    op = dg.DG(nelem, N, gamma=G, mu=mu, lo=lo, hi=hi, equations=eq, vol_flux=vf, surf_flux=sf,
+               blending=blending, fv_recon=recon, indicator=indicator)
+    return s, op
+
+
+def assert_state_close(got, ref, tol=1e-12):
+    """Per variable, relative to max(max |U_v|, max rho * max c): the floor is
+    the momentum scale, for components that are zero in exact arithmetic."""
+    rho = ref[:, 0]
+    u = ref[:, 1:4] / rho[:, None]
+    p = (G - 1) * (ref[:, 4] - 0.5 * rho * np.sum(u * u, 1))
+    floor = np.max(np.abs(rho)) * np.max(np.sqrt(G * np.abs(p) / rho))
+    for v in range(5):
+        scale = max(np.max(np.abs(ref[:, v])), floor)
+        err = np.max(np.abs(got[:, v] - ref[:, v]))
+        assert err <= tol * scale, f"var {v}: err {err:.3e} scale {scale:.3e}"
+
+
+def gpu_ut(torch, op, U):
+    Ut = op.time_derivative(torch.from_numpy(U).cuda())
+    return Ut.cpu().numpy()
+
+
+@pytest.mark.parametrize("N", range(1, 8))
+def test_euler_kg_llf_all_degrees(orc, torch_cuda, N):
+    nelem = (3, 2, 2)  # 12 elements: not a multiple of the 8-way XCD split
+    s, op = make(orc, N, nelem)
+    U = I.random_smooth(N, nelem, seed=100 + N, noise=0.02)
+    assert_ut_close(gpu_ut(torch_cuda, op, U), orc.time_derivative(s, U), U, N, nelem, (0, 0, 0), (TWO_PI,) * 3)
+
+
+@pytest.mark.parametrize("vf", [0, 1, 2, 3])
+@pytest.mark.parametrize("sf", [0, 1, 2])
+@pytest.mark.parametrize("N", [3, 5, 7])
+def test_euler_flux_combinations(orc, torch_cuda, vf, sf, N):
+    nelem, lo, hi = (2, 3, 2), (0.0, -1.0, 0.5), (1.5, 1.0, 2.0)
+    s, op = make(orc, N, nelem, lo, hi, vf=vf, sf=sf)
+    U = I.random_smooth(N, nelem, lo, hi, seed=7 * N + vf + 3 * sf, noise=0.03)
+    assert_ut_close(gpu_ut(torch_cuda, op, U), orc.time_derivative(s, U), U, N, nelem, lo, hi)
+
+
+@pytest.mark.parametrize("vf,sf", [(1, 1), (0, 0), (3, 2)])
+@pytest.mark.parametrize("N", [2, 3, 4, 5, 6, 7])
+def test_navier_stokes(orc, torch_cuda, vf, sf, N):
+    nelem, lo, hi = (3, 2, 2), (0.0, 0.0, 0.0), (2.0, 1.5, 1.0)
+    mu = 2e-2
+    s, op = make(orc, N, nelem, lo, hi, eq=1, vf=vf, sf=sf, mu=mu)
+    U = I.random_smooth(N, nelem, lo, hi, seed=50 + N, noise=0.02)
+    assert_ut_close(gpu_ut(torch_cuda, op, U), orc.time_derivative(s, U), U, N, nelem, lo, hi)
+
+
+def test_single_element_self_periodic(orc, torch_cuda):
+    for eq in (0, 1):
+        s, op = make(orc, 4, (1, 1, 1), eq=eq, vf=1, sf=1, mu=0.05)
+        U = I.random_smooth(4, (1, 1, 1), seed=3, noise=0.02)
+        assert_ut_close(gpu_ut(torch_cuda, op, U), orc.time_derivative(s, U), U, 4, (1, 1, 1), (0, 0, 0),
+                        (TWO_PI,) * 3)
+
+
+@pytest.mark.parametrize("N,recon", [(3, 1), (5, 1), (5, 0), (7, 1)])
+def test_blended_sod(orc, torch_cuda, N, recon):
+    """Sod-type data after a few oracle steps, so that the indicator is active
+    in a band of elements; alpha is compared first (values in {0} U [0.01, 0.7])."""
+    nelem, lo, hi = (16, 2, 2), (0, 0, 0), (1.0, 0.125, 0.125)
+    s, op = make(orc, N, nelem, lo, hi, blending=1, recon=recon)
+    U = I.sod(N, nelem, lo, hi)
+    U = orc.rk_steps(s, U, 0.25 * orc.max_dt(s, U, 0.5), 3)
+    _, _, al_ref = orc.alpha(s, U)
+    import torch
+    al = op.alpha(torch.from_numpy(U).cuda()).cpu().numpy()
+    near = np.abs(al_ref - 0.01) < 1e-9
+    assert not near.any()
+    assert np.max(np.abs(al - al_ref)) < 1e-12 and np.count_nonzero(al_ref) > 0
+    assert_ut_close(gpu_ut(torch, op, U), orc.time_derivative(s, U), U, N, nelem, lo, hi)
+
+
+def test_forced_alpha_blend_matches_oracle_parts(orc, torch_cuda):
+    """With the indicator driven to alpha_max everywhere (pure top mode data),
+    the blended operator equals (1 - a) DG + a FV of the oracle."""
+    N, nelem = 4, (3, 2, 1)
+    x = I.lgl_points(N)
+    from numpy.polynomial import legendre as leg
+    X, _, _ = I.node_coordinates(N, nelem, (0, 0, 0), (1, 1, 1))
+    q = 1.0 + 0.3 * leg.legval(np.broadcast_to(x[None, None, :], X.shape[1:]), np.eye(N + 1)[N])
+    q = np.broadcast_to(q, X.shape)
+    one = np.ones_like(X)
+    U = I.from_primitive(one, 0.2 * one, 0 * one, 0.1 * one, q, G)
+    s, op = make(orc, N, nelem, (0, 0, 0), (1, 1, 1), blending=1)
+    ref, dgp, fvp, al = orc.time_derivative(s, U, parts=True)
+    assert np.all(al > 0.01)
+    assert_ut_close(gpu_ut(torch_cuda, op, U), ref, U, N, nelem, (0, 0, 0), (1, 1, 1))
+
+
+def test_density_wave_rollout(orc, torch_cuda):
+    """C1: 3-D Euler density wave, N = 3, 4^3 elements, KG + LLF, 10 steps."""
+    import torch
+    N, nelem = 3, (4, 4, 4)
+    s, op = make(orc, N, nelem)
+    U0 = I.density_wave(N, nelem)
+    Ud = torch.from_numpy(U0).cuda()
+    dt = op.max_dt(Ud, 0.5)
+    assert abs(dt - orc.max_dt(s, U0, 0.5)) <= 1e-14 * dt
+    op.rk_steps(Ud, dt, 10)
+    ref = orc.rk_steps(s, U0, dt, 10)
+    assert_state_close(Ud.cpu().numpy(), ref)
+    # one rk_step call equals one step of the multi-step call
+    U1 = torch.from_numpy(U0).cuda()
+    op.rk_step(U1, dt)
+    U2 = torch.from_numpy(U0).cuda()
+    op.rk_steps(U2, dt, 1)
+    assert torch.equal(U1, U2)
+
+
+def test_ns_rollout(orc, torch_cuda):
+    import torch
+    N, nelem = 4, (2, 3, 2)
+    s, op = make(orc, N, nelem, eq=1, vf=1, sf=1, mu=1e-2)
+    U0 = I.random_smooth(N, nelem, seed=9, noise=0.01)
+    Ud = torch.from_numpy(U0).cuda()
+    dt = op.max_dt(Ud, 0.5)
+    assert abs(dt - orc.max_dt(s, U0, 0.5)) <= 1e-14 * dt
+    op.rk_steps(Ud, dt, 4)
+    ref = orc.rk_steps(s, U0, dt, 4)
+    assert_state_close(Ud.cpu().numpy(), ref)
+
+
+def test_sod_rollout_blended(orc, torch_cuda):
+    import torch
+    N, nelem, lo, hi = 5, (16, 1, 1), (0, 0, 0), (1.0, 1 / 16, 1 / 16)
+    s, op = make(orc, N, nelem, lo, hi, blending=1)
+    U0 = I.sod(N, nelem, lo, hi)
+    Ud = torch.from_numpy(U0).cuda()
+    dt = op.max_dt(Ud, 0.5)
+    op.rk_steps(Ud, dt, 20)
+    ref = orc.rk_steps(s, U0, dt, 20)
+    assert_state_close(Ud.cpu().numpy(), ref)
+
+
+def test_tgv_c2_full_size_single_evaluation(orc, torch_cuda):
+    """TGV Ma 0.1 Re 1600, N = 5, 32^3 elements (7.1 M nodes), PI + Roe, BR1:
+    one full-size evaluation against the oracle."""
+    N, n = 5, 32
+    mu = 1.0 / 1600
+    s, op = make(orc, N, (n, n, n), eq=1, vf=1, sf=1, mu=mu)
+    U = I.tgv(N, (n, n, n))
+    assert_ut_close(gpu_ut(torch_cuda, op, U), orc.time_derivative(s, U), U, N, (n, n, n), (0, 0, 0),
+                    (TWO_PI,) * 3)
+
+
+def test_integrals_alpha_dt_and_conservation(orc, torch_cuda):
+    import torch
+    N, nelem = 5, (4, 3, 2)
+    s, op = make(orc, N, nelem, eq=1, vf=1, sf=1, mu=1e-2)
+    U = I.random_smooth(N, nelem, seed=77, noise=0.02)
+    Ud = torch.from_numpy(U).cuda()
+    gi = np.array(op.integrals(Ud))
+    oi = orc.integrals(s, U)
+    assert np.allclose(gi, oi, rtol=1e-13, atol=1e-13)
+    Ut = op.time_derivative(Ud)
+    cons = np.array(op.integrals(Ut))
+    mag = np.array(op.integrals(Ut.abs()))
+    assert np.all(np.abs(cons) <= 1e-13 * mag)
+
+
+def test_determinism(orc, torch_cuda):
+    import torch
+    N, nelem = 5, (4, 4, 2)
+    s, op = make(orc, N, nelem, eq=1, vf=1, sf=1, mu=1e-2)
+    U = torch.from_numpy(I.random_smooth(N, nelem, seed=5, noise=0.02)).cuda()
+    a = op.time_derivative(U)
+    b = op.time_derivative(U)
+    assert torch.equal(a, b)
+    U1, U2 = U.clone(), U.clone()
+    op.rk_steps(U1, 1e-3, 3)
+    op.rk_steps(U2, 1e-3, 3)
+    assert torch.equal(U1, U2)
+
+
+def test_error_paths(orc, torch_cuda):
+    import ctypes
+
+    import torch
+
+    from paper_2306_12891_amd import dg
+    op = dg.DG((2, 2, 2), 3)
+    U = torch.from_numpy(I.density_wave(3, (2, 2, 2))).cuda()
+    Uh = torch.from_numpy(I.density_wave(3, (2, 2, 2)))
+    P = ctypes.c_void_p
+    assert op.raw_call("dg_time_derivative", P(Uh.data_ptr()), P(U.data_ptr())) == dg.DG_EINVAL
+    assert op.raw_call("dg_time_derivative", P(U.data_ptr()), P(U.data_ptr())) == dg.DG_EINVAL
+    assert op.raw_call("rk_step", P(U.data_ptr()), ctypes.c_double(0.0)) == dg.DG_EINVAL
+    assert op.raw_call("rk_step", P(U.data_ptr()), ctypes.c_double(float("nan"))) == dg.DG_EINVAL
+    assert op.raw_call("rk_step", P(None), ctypes.c_double(1e-3)) == dg.DG_EINVAL
+    with pytest.raises(dg.DGError) as ei:
+        op.set_options(equations=1, blending=1)
+    assert ei.value.code == dg.DG_EUNSUPPORTED
+    assert op.check_finite(U)
+    V = U.clone()
+    V[1, 4, 2, 1, 0] = float("nan")
+    assert not op.check_finite(V)
+    op1 = dg.DG((2, 2, 2), 1)
+    with pytest.raises(dg.DGError):
+        op1.set_options(blending=1)
