@@ -92,8 +92,23 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="tgv_n5_32", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison run")
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-sized float64 device buffer 5 times (reference kernel for the "
+                         "FETCH_SIZE/WRITE_SIZE counters) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration * (1 << 20) // 8
+        x = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read_per_launch": n * 8, "bytes_written_per_launch": n * 8,
+                          "launches": 5}))
+        return
     if args.gpus != 1:
         print(f"bench.py: this path runs on one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU element decomposition is a design only)", file=sys.stderr)
@@ -142,6 +157,35 @@ def main():
     extra["path_roofline_frac_160B"] = round(path_bytes / wall / 1e9 / HBM_PEAK_GBS, 4)
     extra["pid_gpu_us"] = 1e6 / value
     extra["finite_after_run"] = finite
+
+    # Mixed-precision operator on the same workload: same initial state, same
+    # warm-up and timed steps; error of the final state against the FP64 run.
+    if not args.no_mixed and vf in (1, 3) and not blend:
+        opm = dg.DG(nelem, N, gamma=1.4, mu=mu, lo=lo, hi=hi, equations=eq, vol_flux=vf, surf_flux=sf,
+                    Pr=0.72, precision=dg.MIXED)
+        Um = torch.from_numpy(U0).to("cuda:0")
+        if args.warmup:
+            opm.rk_steps(Um, dt, args.warmup)
+        torch.cuda.synchronize()
+        opm.set_profiling(not args.no_profile)
+        t0 = time.perf_counter()
+        opm.rk_steps(Um, dt, args.steps)
+        torch.cuda.synchronize()
+        wall_m = time.perf_counter() - t0
+        profm = opm.profile_read() if not args.no_profile else None
+        diff = (Um - U).abs()
+        scale = torch.maximum(U.abs().amax(dim=(0, 2, 3, 4)), U[:, 0].abs().amax())
+        linf = (diff.amax(dim=(0, 2, 3, 4)) / scale).tolist()
+        l2 = (diff.pow(2).mean(dim=(0, 2, 3, 4)).sqrt() / scale).tolist()
+        extra["mixed"] = {"value": nodes * 5 * args.steps / wall_m, "unit": "DOF-stage/s",
+                          "ms_per_step": wall_m / args.steps * 1e3, "speedup_vs_fp64": wall / wall_m,
+                          "err_vs_fp64_linf_rel": linf, "err_vs_fp64_l2_rel": l2,
+                          "err_bound_stated": 1e-5, "within_bound": max(linf) <= 1e-5,
+                          "after_steps": args.warmup + args.steps}
+        if profm:
+            extra["mixed"]["kernel_ms_per_step"] = {k: round(v[0] / args.steps, 4) for k, v in profm.items() if v[1]}
+        opm.close()
+        del Um
 
     cpu = None
     if not args.no_cpu_baseline:

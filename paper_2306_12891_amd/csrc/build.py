@@ -31,22 +31,24 @@ def _run(cmd, verbose):
     return r.stdout
 
 
-def build(verbose: bool = False, jobs: int | None = None) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+def build(verbose: bool = False, jobs: int | None = None, out: str = OUT, defines=(), build_dir: str = BUILD) -> str:
+    """Compiles and links the library; defines are extra -D options (tuning)."""
+    os.makedirs(build_dir, exist_ok=True)
+    extra = [f"-D{d}" for d in defines]
     jobs = jobs or min(8, os.cpu_count() or 1)
     cmds = []
     for n in DEGREES:
-        obj = os.path.join(BUILD, f"dg_kernels_N{n}.o")
-        cmds.append([HIPCC, *FLAGS, f"-DDG_N={n}", "-c", os.path.join(HERE, "dg_kernels.hip"), "-o", obj])
-    host_obj = os.path.join(BUILD, "dg_host.o")
-    cmds.append([HIPCC, *FLAGS, "-x", "hip", "-c", os.path.join(HERE, "dg_host.cpp"), "-o", host_obj])
+        obj = os.path.join(build_dir, f"dg_kernels_N{n}.o")
+        cmds.append([HIPCC, *FLAGS, *extra, f"-DDG_N={n}", "-c", os.path.join(HERE, "dg_kernels.hip"), "-o", obj])
+    host_obj = os.path.join(build_dir, "dg_host.o")
+    cmds.append([HIPCC, *FLAGS, *extra, "-x", "hip", "-c", os.path.join(HERE, "dg_host.cpp"), "-o", host_obj])
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         list(ex.map(lambda c: _run(c, verbose), cmds))
     objs = [c[-1] for c in cmds]
-    tmp = OUT + ".tmp"
+    tmp = out + ".tmp"
     _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs], verbose)
-    os.replace(tmp, OUT)
-    return OUT
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

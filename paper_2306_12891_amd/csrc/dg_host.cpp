@@ -311,11 +311,14 @@ int run_stage(dg_ctx* c, const double* Xin, double* Xout, double* Ut, int mode, 
     e = timed(c, DG_K_INDICATOR, [&] { return c->kt->alpha1(a, c->stream); });
     if (e != hipSuccess) return hip_fail(c, e, "indicator kernel");
   }
+  const bool mixed = c->opt.precision == DG_MIXED;
   if (c->opt.equations == DG_NS) {
-    e = timed(c, DG_K_LIFT, [&] { return c->kt->lift(a, c->stream); });
+    e = timed(c, DG_K_LIFT, [&] { return mixed ? c->kt->lift_mixed(a, c->stream) : c->kt->lift(a, c->stream); });
     if (e != hipSuccess) return hip_fail(c, e, "lifting kernel");
   }
-  e = timed(c, DG_K_STAGE, [&] { return c->kt->stage(a, c->opt.equations, c->stream); });
+  e = timed(c, DG_K_STAGE, [&] {
+    return mixed ? c->kt->stage_mixed(a, c->opt.equations, c->stream) : c->kt->stage(a, c->opt.equations, c->stream);
+  });
   if (e != hipSuccess) return hip_fail(c, e, "stage kernel");
   return DG_OK;
 }
@@ -440,6 +443,8 @@ int dg_set_options(dg_ctx* c, const dg_options* o) {
     return fail(c, DG_EUNSUPPORTED, "dg_set_options: mixed precision not built for this degree");
   if (o->precision == DG_MIXED && o->blending)
     return fail(c, DG_EUNSUPPORTED, "dg_set_options: mixed precision without blending only");
+  if (o->precision == DG_MIXED && o->vol_flux != DG_VF_PI && o->vol_flux != DG_VF_STD)
+    return fail(c, DG_EUNSUPPORTED, "dg_set_options: mixed precision needs the PI or STD volume flux");
   c->opt = *o;
   return DG_OK;
 }

@@ -20,6 +20,16 @@
 //               U_t += sum_d (2/dx_d) [ sum_l Dw_{i_d l} Fv_{d,l} + (1/w)(delta_N Fv*_+ - delta_0 Fv*_-) ]
 //   with Dw = D - W^-1 B (strong form with the boundary term folded in).
 //   blend:      U_t = (1 - a) U_t^DG + a U_t^FV.
+//
+// Precision: every flux/derivative routine is templated on the arithmetic
+// type R.  R = double is the FP64 operator.  R = float is the mixed operator:
+// the state, the Runge-Kutta register and update stay FP64; node primitives,
+// interface values, fluxes, derivatives and U_t accumulate in FP32 after
+// subtracting a constant reference (p0, h0, theta0) from pressure, total
+// enthalpy and temperature.  For the Pirozzoli (or arithmetic-mean) flux the
+// shift is exact in real arithmetic: the momentum flux changes by the constant
+// p0 e_d, which the operator annihilates, and the energy flux by h0 times the
+// mass flux, which is added back as U_t,E += h0 U_t,rho in FP64.
 #include "dg_internal.hpp"
 
 #ifndef DG_N
@@ -39,6 +49,16 @@ constexpr int NTP2 = NT <= 64 ? 64 : (NT <= 128 ? 128 : (NT <= 256 ? 256 : 512))
 constexpr BasisLayout BL(n1);
 constexpr int NB_STAGE = 2 * n1 * n1 + 3 * n1 + 1;  // Dhat, Dw, winv, xi, edge
 
+// Tuning: minimum waves per SIMD requested from the register allocator for
+// the stage kernel (0 = compiler default), and whether the volume loop skips
+// the zero diagonal of Dhat.
+#ifndef DG_STAGE_MIN_WAVES
+#define DG_STAGE_MIN_WAVES 0
+#endif
+#ifndef DG_SKIP_DIAG
+#define DG_SKIP_DIAG 1
+#endif
+
 enum { VF_KG = 0, VF_PI = 1, VF_CH = 2, VF_STD = 3 };
 enum { SF_LLF = 0, SF_ROE = 1, SF_CENTRAL = 2 };
 
@@ -52,134 +72,298 @@ __device__ __forceinline__ int face_node(int d, int l, int a) {
 }
 
 // ---------------------------------------------------------------------------
+// Arithmetic helpers
+// ---------------------------------------------------------------------------
+// FP64 reciprocal and square root: hardware approximations refined by Newton
+// iterations, for positive normal arguments; within an ulp of the correctly
+// rounded result at a third of the instructions of the IEEE expansions.
+__device__ __forceinline__ double rcp64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+__device__ __forceinline__ double sqrt64(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double s = x * y, h = 0.5 * y;
+  const double r = fma(-h, s, 0.5);
+  s = fma(s, r, s);
+  h = fma(h, r, h);
+  double d = fma(-s, s, x);
+  s = fma(d, h, s);
+  d = fma(-s, s, x);
+  return fma(d, h, s);
+}
+
+__device__ __forceinline__ double rcpR(double x) { return rcp64(x); }
+__device__ __forceinline__ float rcpR(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double sqrtR(double x) { return sqrt64(x); }
+__device__ __forceinline__ float sqrtR(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double fmaR(double a, double b, double c) { return fma(a, b, c); }
+__device__ __forceinline__ float fmaR(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double absR(double a) { return fabs(a); }
+__device__ __forceinline__ float absR(float a) { return fabsf(a); }
+__device__ __forceinline__ double maxR(double a, double b) { return fmax(a, b); }
+__device__ __forceinline__ float maxR(float a, float b) { return fmaxf(a, b); }
+
+// Constant reference state subtracted in the mixed-precision operator
+// (all zero for FP64): pressure, total enthalpy h = (E + p)/rho, theta = p/rho.
+struct Ref {
+  double p, h, th;
+};
+
+// Reference of the mixed operator: the state at node 0 of element 0.  Any
+// constant is exact in real arithmetic; a state value keeps the shifted
+// quantities small for FP32.
+__device__ __forceinline__ Ref reference_state(const double* U, double gm1) {
+  const double r = U[0], ir = rcp64(r);
+  const double mx = U[nn], my = U[2 * nn], mz = U[3 * nn], E = U[4 * nn];
+  const double p = gm1 * (E - 0.5 * ir * (mx * mx + my * my + mz * mz));
+  Ref ref;
+  ref.p = p;
+  ref.h = (E + p) * ir;
+  ref.th = p * ir;
+  return ref;
+}
+
+// ---------------------------------------------------------------------------
 // Pointwise physics
 // ---------------------------------------------------------------------------
 // Primitive set kept per node: rho, u, v, w, p, x, theta with x = e (KG),
-// h (PI, STD) or beta = rho / (2p) (CH); theta = p / rho (Navier-Stokes).
-template <int VF>
-__device__ __forceinline__ void primitives(const double U[5], double gm1, double P[7]) {
+// h (PI, STD) or beta = rho / (2p) (CH); theta = p / rho.  Computed in FP64,
+// shifted by the reference (mixed) and rounded to R.
+template <int VF, class R, bool MX>
+__device__ __forceinline__ void primitives(const double U[5], double gm1, const Ref& ref, R P[7]) {
   const double rho = U[0];
-  const double ir = 1.0 / rho;
+  const double ir = rcp64(rho);
   const double vx = U[1] * ir, vy = U[2] * ir, vz = U[3] * ir;
   const double p = gm1 * (U[4] - 0.5 * (U[1] * vx + U[2] * vy + U[3] * vz));
-  P[0] = rho; P[1] = vx; P[2] = vy; P[3] = vz; P[4] = p;
-  if (VF == VF_KG) P[5] = U[4] * ir;
-  else if (VF == VF_CH) P[5] = 0.5 * rho / p;
-  else P[5] = (U[4] + p) * ir;
-  P[6] = p * ir;
+  double x;
+  if (VF == VF_KG) x = U[4] * ir;
+  else if (VF == VF_CH) x = 0.5 * rho * rcp64(p);
+  else x = (U[4] + p) * ir;
+  const double th = p * ir;
+  P[0] = (R)rho;
+  P[1] = (R)vx;
+  P[2] = (R)vy;
+  P[3] = (R)vz;
+  P[4] = (R)(MX ? p - ref.p : p);
+  P[5] = (R)(MX ? x - ref.h : x);
+  P[6] = (R)(MX ? th - ref.th : th);
 }
 
 __device__ __forceinline__ double logmean(double a, double b) {
-  const double zeta = a / b;
-  const double f = (zeta - 1.0) / (zeta + 1.0);
+  const double zeta = a * rcp64(b);
+  const double f = (zeta - 1.0) * rcp64(zeta + 1.0);
   const double u = f * f;
   const double F = (u < 1e-4) ? 1.0 + u * (1.0 / 3.0 + u * (1.0 / 5.0 + u * (1.0 / 7.0))) : log(zeta) / (2.0 * f);
-  return (a + b) / (2.0 * F);
+  return (a + b) * rcp64(2.0 * F);
 }
 
-// Two-point flux in a frame rotated so that the normal velocity is component 0.
-// Inputs: rho, (un, ut1, ut2), p, E of both states; output (f_rho, f_mn, f_mt1, f_mt2, f_E).
-template <int VF>
-__device__ __forceinline__ void twopoint_rot(const double ra, const double ua[3], const double pa, const double Ea,
-                                             const double rb, const double ub[3], const double pb, const double Eb,
-                                             double gm1, double f[5]) {
+template <int D>
+struct Axes {
+  static constexpr int kn = 1 + D, k1 = 1 + (D + 1) % 3, k2 = 1 + (D + 2) % 3;
+};
+
+// A state in the frame rotated to direction D: normal component first, then
+// the two tangential ones in cyclic order (D+1, D+2).  p and h are shifted by
+// the reference in the mixed operator; e = E/rho (KG only).
+template <class R>
+struct RotState {
+  R r, ir, un, u1, u2, p, h, e, mn;
+};
+
+// Jumps R - L of an interface (computed in FP64, then rounded), the LLF wave
+// speed and the reference enthalpy.
+template <class R>
+struct Jumps {
+  R dr, dmn, dm1, dm2, dE, dp, dun, du1, du2, lam, h0;
+};
+
+struct State64 {
+  double r, ir, un, u1, u2, p, h, e, mn, m1, m2, E;
+};
+
+template <int D>
+__device__ __forceinline__ State64 state64(const double U[5], double gm1) {
+  State64 s;
+  s.r = U[0];
+  s.ir = rcp64(U[0]);
+  s.mn = U[Axes<D>::kn];
+  s.m1 = U[Axes<D>::k1];
+  s.m2 = U[Axes<D>::k2];
+  s.E = U[4];
+  s.un = s.mn * s.ir;
+  s.u1 = s.m1 * s.ir;
+  s.u2 = s.m2 * s.ir;
+  s.p = gm1 * (s.E - 0.5 * (s.mn * s.un + s.m1 * s.u1 + s.m2 * s.u2));
+  s.h = (s.E + s.p) * s.ir;
+  s.e = s.E * s.ir;
+  return s;
+}
+
+template <class R, bool MX>
+__device__ __forceinline__ RotState<R> to_rot(const State64& s, const Ref& ref) {
+  RotState<R> o;
+  o.r = (R)s.r;
+  o.ir = (R)s.ir;
+  o.un = (R)s.un;
+  o.u1 = (R)s.u1;
+  o.u2 = (R)s.u2;
+  o.p = (R)(MX ? s.p - ref.p : s.p);
+  o.h = (R)(MX ? s.h - ref.h : s.h);
+  o.e = (R)s.e;
+  o.mn = (R)s.mn;
+  return o;
+}
+
+// Jumps of an interface; the energy jump of the mixed operator is
+// E_R - E_L - h0 (rho_R - rho_L), the jump of the shifted energy flux variable.
+template <class R, bool MX>
+__device__ __forceinline__ Jumps<R> jumps(const State64& L, const State64& Rt, double gamma, const Ref& ref,
+                                          int sf) {
+  Jumps<R> j;
+  const double dr = Rt.r - L.r;
+  j.dr = (R)dr;
+  j.dmn = (R)(Rt.mn - L.mn);
+  j.dm1 = (R)(Rt.m1 - L.m1);
+  j.dm2 = (R)(Rt.m2 - L.m2);
+  j.dE = (R)(MX ? (Rt.E - L.E) - ref.h * dr : Rt.E - L.E);
+  j.dp = (R)(Rt.p - L.p);
+  j.dun = (R)(Rt.un - L.un);
+  j.du1 = (R)(Rt.u1 - L.u1);
+  j.du2 = (R)(Rt.u2 - L.u2);
+  j.h0 = (R)(MX ? ref.h : 0.0);
+  j.lam = (R)0;
+  if (sf == SF_LLF) {
+    const double cL = sqrt64(gamma * L.p * L.ir), cR = sqrt64(gamma * Rt.p * Rt.ir);
+    j.lam = (R)fmax(fabs(L.un) + cL, fabs(Rt.un) + cR);
+  }
+  return j;
+}
+
+// Two-point flux in the rotated frame: (f_rho, f_mn, f_mt1, f_mt2, f_E).
+template <int VF, class R>
+__device__ __forceinline__ void twopoint_rot(const RotState<R>& a, const RotState<R>& b, R gm1, R f[5]) {
+  const R half = (R)0.5;
   if (VF == VF_STD) {
-    const double ha = (Ea + pa) / ra, hb = (Eb + pb) / rb;
-    const double ma = ra * ua[0], mb = rb * ub[0];
-    f[0] = 0.5 * (ma + mb);
-    f[1] = 0.5 * (ma * ua[0] + pa + mb * ub[0] + pb);
-    f[2] = 0.5 * (ma * ua[1] + mb * ub[1]);
-    f[3] = 0.5 * (ma * ua[2] + mb * ub[2]);
-    f[4] = 0.5 * (ma * ha + mb * hb);
+    f[0] = half * (a.mn + b.mn);
+    f[1] = half * (a.mn * a.un + a.p + b.mn * b.un + b.p);
+    f[2] = half * (a.mn * a.u1 + b.mn * b.u1);
+    f[3] = half * (a.mn * a.u2 + b.mn * b.u2);
+    f[4] = half * (a.mn * a.h + b.mn * b.h);
     return;
   }
-  const double um0 = 0.5 * (ua[0] + ub[0]), um1 = 0.5 * (ua[1] + ub[1]), um2 = 0.5 * (ua[2] + ub[2]);
+  const R um0 = half * (a.un + b.un), um1 = half * (a.u1 + b.u1), um2 = half * (a.u2 + b.u2);
   if (VF == VF_KG || VF == VF_PI) {
-    const double rm = 0.5 * (ra + rb), pm = 0.5 * (pa + pb);
-    const double fr = rm * um0;
+    const R rm = half * (a.r + b.r), pm = half * (a.p + b.p);
+    const R fr = rm * um0;
     f[0] = fr;
     f[1] = fr * um0 + pm;
     f[2] = fr * um1;
     f[3] = fr * um2;
-    if (VF == VF_KG) f[4] = fr * (0.5 * (Ea / ra + Eb / rb)) + pm * um0;
-    else f[4] = fr * (0.5 * ((Ea + pa) / ra + (Eb + pb) / rb));
+    if (VF == VF_KG) f[4] = fr * (half * (a.e + b.e)) + pm * um0;
+    else f[4] = fr * (half * (a.h + b.h));
     return;
   }
-  // Chandrashekar (entropy conservative)
-  const double ba = ra / (2.0 * pa), bb = rb / (2.0 * pb);
-  const double rln = logmean(ra, rb), bln = logmean(ba, bb);
-  const double rm = 0.5 * (ra + rb), bm = 0.5 * (ba + bb);
+  // Chandrashekar (entropy conservative; FP64 only)
+  const double ba = 0.5 * a.r * rcp64(a.p), bb = 0.5 * b.r * rcp64(b.p);
+  const double rln = logmean(a.r, b.r), bln = logmean(ba, bb);
+  const double rm = 0.5 * (a.r + b.r), bm = 0.5 * (ba + bb);
   const double fr = rln * um0;
   f[0] = fr;
-  f[1] = fr * um0 + rm / (2.0 * bm);
+  f[1] = fr * um0 + rm * rcp64(2.0 * bm);
   f[2] = fr * um1;
   f[3] = fr * um2;
-  const double usq = 0.5 * (ua[0] * ua[0] + ua[1] * ua[1] + ua[2] * ua[2] + ub[0] * ub[0] + ub[1] * ub[1] + ub[2] * ub[2]);
-  f[4] = fr * (1.0 / (2.0 * gm1 * bln) - 0.5 * usq) + um0 * f[1] + um1 * f[2] + um2 * f[3];
+  const double usq = 0.5 * (a.un * a.un + a.u1 * a.u1 + a.u2 * a.u2 + b.un * b.un + b.u1 * b.u1 + b.u2 * b.u2);
+  f[4] = fr * (rcp64(2.0 * gm1 * bln) - 0.5 * usq) + um0 * f[1] + um1 * f[2] + um2 * f[3];
 }
 
-// Surface flux f*_D(L, R) = F#_D(L, R) - Dis/2 of conservative states; the
-// Riemann solver is chosen at run time (uniform across the workgroup).
+// Interface flux f* = F#(L, R) - Dis/2 in the rotated frame; the Riemann
+// solver is chosen at run time (uniform across the workgroup).  In the mixed
+// operator the energy component is that of the shifted flux, f*_E - h0 f*_rho.
+template <int VF, class R>
+__device__ __forceinline__ void riemann_rot(int sf, const RotState<R>& L, const RotState<R>& Rs, const Jumps<R>& J,
+                                            R gamma, R g[5]) {
+  const R gm1 = gamma - (R)1;
+  const R half = (R)0.5;
+  twopoint_rot<VF, R>(L, Rs, gm1, g);
+  if (sf == SF_LLF) {
+    const R hl = half * J.lam;
+    g[0] -= hl * J.dr;
+    g[1] -= hl * J.dmn;
+    g[2] -= hl * J.dm1;
+    g[3] -= hl * J.dm2;
+    g[4] -= hl * J.dE;
+  } else if (sf == SF_ROE) {
+    const R sL = sqrtR(L.r), sR = sqrtR(Rs.r);
+    const R inv = rcpR(sL + sR);
+    const R ut0 = (sL * L.un + sR * Rs.un) * inv;
+    const R ut1 = (sL * L.u1 + sR * Rs.u1) * inv;
+    const R ut2 = (sL * L.u2 + sR * Rs.u2) * inv;
+    const R Hs = (sL * L.h + sR * Rs.h) * inv;  // Roe-averaged (shifted) total enthalpy
+    const R Ht = Hs + J.h0;
+    const R rt = sL * sR;
+    const R q2 = ut0 * ut0 + ut1 * ut1 + ut2 * ut2;
+    const R c2 = gm1 * (Ht - half * q2);
+    const R ct = sqrtR(c2);
+    const R ic2 = rcpR(c2);
+    const R a1 = half * (J.dp - rt * ct * J.dun) * ic2;
+    const R a5 = half * (J.dp + rt * ct * J.dun) * ic2;
+    const R a2 = J.dr - J.dp * ic2;
+    const R l1 = absR(ut0 - ct), l5 = absR(ut0 + ct), l2 = absR(ut0);
+    const R w1 = l1 * a1, w5 = l5 * a5;
+    const R D0 = w1 + w5 + l2 * a2;
+    const R Dn = w1 * (ut0 - ct) + w5 * (ut0 + ct) + l2 * (a2 * ut0);
+    const R D1 = w1 * ut1 + w5 * ut1 + l2 * (a2 * ut1 + rt * J.du1);
+    const R D2 = w1 * ut2 + w5 * ut2 + l2 * (a2 * ut2 + rt * J.du2);
+    const R D4 = w1 * (Hs - ct * ut0) + w5 * (Hs + ct * ut0) +
+                 l2 * (a2 * (half * q2 - J.h0) + rt * (ut1 * J.du1 + ut2 * J.du2));
+    g[0] -= half * D0;
+    g[1] -= half * Dn;
+    g[2] -= half * D1;
+    g[3] -= half * D2;
+    g[4] -= half * D4;
+  }
+}
+
+// Rotated-frame 5-vector back to (rho, x, y, z, E) order.
+template <int D, class R>
+__device__ __forceinline__ void unrotate(const R g[5], R f[5]) {
+  f[0] = g[0];
+  f[Axes<D>::kn] = g[1];
+  f[Axes<D>::k1] = g[2];
+  f[Axes<D>::k2] = g[3];
+  f[4] = g[4];
+}
+
+// Lifted interface value q* = (q- + q+)/2, q = (u, v, w, theta), from FP64
+// rotated states (theta shifted by the reference in the mixed operator).
+template <int D, class R, bool MX>
+__device__ __forceinline__ void interface_q(const State64& L, const State64& Rt, const Ref& ref, R q[4]) {
+  double a[4], b[4];
+  a[Axes<D>::kn - 1] = L.un; a[Axes<D>::k1 - 1] = L.u1; a[Axes<D>::k2 - 1] = L.u2; a[3] = L.p * L.ir;
+  b[Axes<D>::kn - 1] = Rt.un; b[Axes<D>::k1 - 1] = Rt.u1; b[Axes<D>::k2 - 1] = Rt.u2; b[3] = Rt.p * Rt.ir;
+  if (MX) {
+    a[3] -= ref.th;
+    b[3] -= ref.th;
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) q[c] = (R)(0.5 * (a[c] + b[c]));
+}
+
+// FP64 surface flux f*_D(L, R) of conservative states (minus side L).
 template <int VF, int D>
 __device__ __forceinline__ void surface_flux(int sf, const double L[5], const double R[5], double gamma,
                                              double f[5]) {
-  constexpr int kn = 1 + D, k1 = 1 + (D + 1) % 3, k2 = 1 + (D + 2) % 3;  // (n, t1, t2) cyclic
-  const double gm1 = gamma - 1.0;
-  const double mLn = L[kn], mL1 = L[k1], mL2 = L[k2];
-  const double mRn = R[kn], mR1 = R[k1], mR2 = R[k2];
-  const double rL = L[0], rR = R[0];
-  const double iL = 1.0 / rL, iR = 1.0 / rR;
-  const double uL[3] = {mLn * iL, mL1 * iL, mL2 * iL};
-  const double uR[3] = {mRn * iR, mR1 * iR, mR2 * iR};
-  const double pL = gm1 * (L[4] - 0.5 * (mLn * uL[0] + mL1 * uL[1] + mL2 * uL[2]));
-  const double pR = gm1 * (R[4] - 0.5 * (mRn * uR[0] + mR1 * uR[1] + mR2 * uR[2]));
+  const Ref ref{0.0, 0.0, 0.0};
+  const State64 a = state64<D>(L, gamma - 1.0), b = state64<D>(R, gamma - 1.0);
+  const Jumps<double> J = jumps<double, false>(a, b, gamma, ref, sf);
   double g[5];
-  twopoint_rot<VF>(rL, uL, pL, L[4], rR, uR, pR, R[4], gm1, g);
-  if (sf == SF_LLF) {
-    const double cL = sqrt(gamma * pL * iL), cR = sqrt(gamma * pR * iR);
-    const double lam = fmax(fabs(uL[0]) + cL, fabs(uR[0]) + cR);
-    const double hl = 0.5 * lam;
-    g[0] -= hl * (rR - rL);
-    g[1] -= hl * (mRn - mLn);
-    g[2] -= hl * (mR1 - mL1);
-    g[3] -= hl * (mR2 - mL2);
-    g[4] -= hl * (R[4] - L[4]);
-  } else if (sf == SF_ROE) {
-    const double sL = sqrt(rL), sR = sqrt(rR);
-    const double inv = 1.0 / (sL + sR);
-    const double ut0 = (sL * uL[0] + sR * uR[0]) * inv;
-    const double ut1 = (sL * uL[1] + sR * uR[1]) * inv;
-    const double ut2 = (sL * uL[2] + sR * uR[2]) * inv;
-    const double HL = (L[4] + pL) * iL, HR = (R[4] + pR) * iR;
-    const double Ht = (sL * HL + sR * HR) * inv;
-    const double rt = sL * sR;
-    const double q2 = ut0 * ut0 + ut1 * ut1 + ut2 * ut2;
-    const double c2 = gm1 * (Ht - 0.5 * q2);
-    const double ct = sqrt(c2);
-    const double drho = rR - rL, dp = pR - pL;
-    const double dun = uR[0] - uL[0], dt1 = uR[1] - uL[1], dt2 = uR[2] - uL[2];
-    const double i2c2 = 1.0 / (2.0 * c2);
-    const double a1 = (dp - rt * ct * dun) * i2c2;
-    const double a5 = (dp + rt * ct * dun) * i2c2;
-    const double a2 = drho - dp / c2;
-    const double l1 = fabs(ut0 - ct), l5 = fabs(ut0 + ct), l2 = fabs(ut0);
-    const double w1 = l1 * a1, w5 = l5 * a5;
-    const double D0 = w1 + w5 + l2 * a2;
-    const double Dn = w1 * (ut0 - ct) + w5 * (ut0 + ct) + l2 * (a2 * ut0);
-    const double D1 = w1 * ut1 + w5 * ut1 + l2 * (a2 * ut1 + rt * dt1);
-    const double D2 = w1 * ut2 + w5 * ut2 + l2 * (a2 * ut2 + rt * dt2);
-    const double D4 = w1 * (Ht - ct * ut0) + w5 * (Ht + ct * ut0) + l2 * (a2 * 0.5 * q2 + rt * (ut1 * dt1 + ut2 * dt2));
-    g[0] -= 0.5 * D0;
-    g[1] -= 0.5 * Dn;
-    g[2] -= 0.5 * D1;
-    g[3] -= 0.5 * D2;
-    g[4] -= 0.5 * D4;
-  }
-  f[0] = g[0];
-  f[kn] = g[1];
-  f[k1] = g[2];
-  f[k2] = g[3];
-  f[4] = g[4];
+  riemann_rot<VF, double>(sf, to_rot<double, false>(a, ref), to_rot<double, false>(b, ref), J, gamma, g);
+  unrotate<D, double>(g, f);
 }
 
 // Direction given as a (loop-unrolled) constant: dispatch to the specialised flux.
@@ -194,81 +378,98 @@ __device__ __forceinline__ void surface_flux_dir(int d, int sf, const double L[5
 // ---------------------------------------------------------------------------
 // Volume integral along direction D for node n (index id along D).
 // ---------------------------------------------------------------------------
-template <int VF, int D>
-__device__ __forceinline__ void volume_dir(const double (*sP)[nn], const double* sDhat, int n, int id,
-                                           const double me[7], double invJ, double gm1, double acc[5]) {
+// Dhat has a zero diagonal, so partner l = id is skipped: the loop visits
+// l = id + 1, ..., id + N (mod N + 1).
+__device__ __forceinline__ int partner(int id, int k) {
+  if (!DG_SKIP_DIAG) return k - 1;
+  const int l = id + k;
+  return l >= n1 ? l - n1 : l;
+}
+constexpr int kPartners = DG_SKIP_DIAG ? N : N + 1;
+
+template <int VF, int D, class R>
+__device__ __forceinline__ void volume_dir(const R (*sP)[nn], const R* sDhat, int n, int id, const R me[7], R invJ,
+                                           R gm1, R acc[5]) {
   constexpr int st = D == 0 ? 1 : (D == 1 ? n1 : nf);
   const int base = n - id * st;
-  const double* crow = sDhat + id * n1;
+  const R* crow = sDhat + id * n1;
   if (VF == VF_KG || VF == VF_PI) {
     // f_rho = fr4/4, f_m = fr4 us/8 + ps/2 e_D, f_E = fr4 xs/8 (+ ps und/4 for KG)
     // with sums s = a + b and fr4 = rho_s und_s.
-    double s_fr = 0.0, s_m0 = 0.0, s_m1 = 0.0, s_m2 = 0.0, s_p = 0.0, s_E1 = 0.0, s_E2 = 0.0;
+    R s_fr = 0, s_m0 = 0, s_m1 = 0, s_m2 = 0, s_p = 0, s_E1 = 0, s_E2 = 0;
 #pragma unroll
-    for (int l = 0; l < n1; ++l) {
+    for (int k = 1; k <= kPartners; ++k) {
+      const int l = partner(id, k);
       const int m = base + l * st;
-      const double c = crow[l];
-      const double rs = me[0] + sP[0][m];
-      const double us = me[1] + sP[1][m];
-      const double vs = me[2] + sP[2][m];
-      const double ws = me[3] + sP[3][m];
-      const double ps = me[4] + sP[4][m];
-      const double xs = me[5] + sP[5][m];
-      const double und = D == 0 ? us : (D == 1 ? vs : ws);
-      const double cf = c * (rs * und);
+      const R c = crow[l];
+      const R rs = me[0] + sP[0][m];
+      const R us = me[1] + sP[1][m];
+      const R vs = me[2] + sP[2][m];
+      const R ws = me[3] + sP[3][m];
+      const R ps = me[4] + sP[4][m];
+      const R xs = me[5] + sP[5][m];
+      const R und = D == 0 ? us : (D == 1 ? vs : ws);
+      const R cf = c * (rs * und);
       s_fr += cf;
-      s_m0 = fma(cf, us, s_m0);
-      s_m1 = fma(cf, vs, s_m1);
-      s_m2 = fma(cf, ws, s_m2);
-      const double cp = c * ps;
+      s_m0 = fmaR(cf, us, s_m0);
+      s_m1 = fmaR(cf, vs, s_m1);
+      s_m2 = fmaR(cf, ws, s_m2);
+      const R cp = c * ps;
       s_p += cp;
-      s_E1 = fma(cf, xs, s_E1);
-      if (VF == VF_KG) s_E2 = fma(cp, und, s_E2);
+      s_E1 = fmaR(cf, xs, s_E1);
+      if (VF == VF_KG) s_E2 = fmaR(cp, und, s_E2);
     }
-    acc[0] -= invJ * (0.25 * s_fr);
-    acc[1] -= invJ * (0.125 * s_m0 + (D == 0 ? 0.5 * s_p : 0.0));
-    acc[2] -= invJ * (0.125 * s_m1 + (D == 1 ? 0.5 * s_p : 0.0));
-    acc[3] -= invJ * (0.125 * s_m2 + (D == 2 ? 0.5 * s_p : 0.0));
-    acc[4] -= invJ * (0.125 * s_E1 + (VF == VF_KG ? 0.25 * s_E2 : 0.0));
+    const R q4 = (R)0.25, q8 = (R)0.125, h2 = (R)0.5;
+    acc[0] -= invJ * (q4 * s_fr);
+    acc[1] -= invJ * (q8 * s_m0 + (D == 0 ? h2 * s_p : (R)0));
+    acc[2] -= invJ * (q8 * s_m1 + (D == 1 ? h2 * s_p : (R)0));
+    acc[3] -= invJ * (q8 * s_m2 + (D == 2 ? h2 * s_p : (R)0));
+    acc[4] -= invJ * (q8 * s_E1 + (VF == VF_KG ? q4 * s_E2 : (R)0));
   } else if (VF == VF_STD) {
     // F# = (F(a) + F(b))/2 with F_rho = rho u_D, F_m = rho u_D u + p e_D, F_E = rho h u_D
-    const double mA = me[0] * me[1 + D];
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0, sp = 0.0;
+    const R mA = me[0] * me[1 + D];
+    R s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0, sp = 0;
 #pragma unroll
-    for (int l = 0; l < n1; ++l) {
+    for (int k = 1; k <= kPartners; ++k) {
+      const int l = partner(id, k);
       const int m = base + l * st;
-      const double c = crow[l];
-      const double mB = sP[0][m] * sP[1 + D][m];
-      s0 = fma(c, mA + mB, s0);
-      s1 = fma(c, mA * me[1] + mB * sP[1][m], s1);
-      s2 = fma(c, mA * me[2] + mB * sP[2][m], s2);
-      s3 = fma(c, mA * me[3] + mB * sP[3][m], s3);
-      sp = fma(c, me[4] + sP[4][m], sp);
-      s4 = fma(c, mA * me[5] + mB * sP[5][m], s4);
+      const R c = crow[l];
+      const R mB = sP[0][m] * sP[1 + D][m];
+      s0 = fmaR(c, mA + mB, s0);
+      s1 = fmaR(c, mA * me[1] + mB * sP[1][m], s1);
+      s2 = fmaR(c, mA * me[2] + mB * sP[2][m], s2);
+      s3 = fmaR(c, mA * me[3] + mB * sP[3][m], s3);
+      sp = fmaR(c, me[4] + sP[4][m], sp);
+      s4 = fmaR(c, mA * me[5] + mB * sP[5][m], s4);
     }
-    acc[0] -= invJ * (0.5 * s0);
-    acc[1] -= invJ * (0.5 * (s1 + (D == 0 ? sp : 0.0)));
-    acc[2] -= invJ * (0.5 * (s2 + (D == 1 ? sp : 0.0)));
-    acc[3] -= invJ * (0.5 * (s3 + (D == 2 ? sp : 0.0)));
-    acc[4] -= invJ * (0.5 * s4);
+    const R h2 = (R)0.5;
+    acc[0] -= invJ * (h2 * s0);
+    acc[1] -= invJ * (h2 * (s1 + (D == 0 ? sp : (R)0)));
+    acc[2] -= invJ * (h2 * (s2 + (D == 1 ? sp : (R)0)));
+    acc[3] -= invJ * (h2 * (s3 + (D == 2 ? sp : (R)0)));
+    acc[4] -= invJ * (h2 * s4);
   } else {
-    // Chandrashekar: general pairwise evaluation (test flux)
+    // Chandrashekar: general pairwise evaluation (FP64 test flux)
     double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    RotState<double> a;
+    a.r = me[0]; a.un = me[1 + D]; a.u1 = me[1 + (D + 1) % 3]; a.u2 = me[1 + (D + 2) % 3]; a.p = me[4];
 #pragma unroll
-    for (int l = 0; l < n1; ++l) {
+    for (int k = 1; k <= kPartners; ++k) {
+      const int l = partner(id, k);
       const int m = base + l * st;
       const double c = crow[l];
-      const double ua[3] = {me[1 + D], me[1 + (D + 1) % 3], me[1 + (D + 2) % 3]};
-      const double ub[3] = {sP[1 + D][m], sP[1 + (D + 1) % 3][m], sP[1 + (D + 2) % 3][m]};
+      RotState<double> b;
+      b.r = sP[0][m]; b.un = sP[1 + D][m]; b.u1 = sP[1 + (D + 1) % 3][m]; b.u2 = sP[1 + (D + 2) % 3][m];
+      b.p = sP[4][m];
       double f[5];
-      twopoint_rot<VF_CH>(me[0], ua, me[4], 0.0, sP[0][m], ub, sP[4][m], 0.0, gm1, f);
+      twopoint_rot<VF_CH, double>(a, b, gm1, f);
       s[0] = fma(c, f[0], s[0]);
       s[1 + D] = fma(c, f[1], s[1 + D]);
       s[1 + (D + 1) % 3] = fma(c, f[2], s[1 + (D + 1) % 3]);
       s[1 + (D + 2) % 3] = fma(c, f[3], s[1 + (D + 2) % 3]);
       s[4] = fma(c, f[4], s[4]);
     }
-    for (int v = 0; v < 5; ++v) acc[v] -= invJ * s[v];
+    for (int v = 0; v < 5; ++v) acc[v] -= invJ * (R)s[v];
   }
 }
 
@@ -276,39 +477,39 @@ __device__ __forceinline__ void volume_dir(const double (*sP)[nn], const double*
 // BR1 lifted gradient at node n: g[d][c] = d q_c / d x_d, q = (u, v, w, theta).
 // sQ holds the interface values q* on the six faces of the element.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void lifted_gradient(const double (*sP)[nn], const double (*sQ)[4][nf], const double* sDw,
-                                                const double* swinv, int n, const int ijk[3], const double invJ[3],
-                                                double g[3][4]) {
+template <class R>
+__device__ __forceinline__ void lifted_gradient(const R (*sP)[nn], const R (*sQ)[4][nf], const R* sDw, const R* swinv,
+                                                int n, const int ijk[3], const R invJ[3], R g[3][4]) {
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const int st = d == 0 ? 1 : (d == 1 ? n1 : nf);
     const int id = ijk[d];
     const int base = n - id * st;
     const int a = d == 0 ? ijk[1] + n1 * ijk[2] : (d == 1 ? ijk[0] + n1 * ijk[2] : ijk[0] + n1 * ijk[1]);
-    const double* crow = sDw + id * n1;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    const R* crow = sDw + id * n1;
+    R s0 = 0, s1 = 0, s2 = 0, s3 = 0;
 #pragma unroll
     for (int l = 0; l < n1; ++l) {
       const int m = base + l * st;
-      const double c = crow[l];
-      s0 = fma(c, sP[1][m], s0);
-      s1 = fma(c, sP[2][m], s1);
-      s2 = fma(c, sP[3][m], s2);
-      s3 = fma(c, sP[6][m], s3);
+      const R c = crow[l];
+      s0 = fmaR(c, sP[1][m], s0);
+      s1 = fmaR(c, sP[2][m], s1);
+      s2 = fmaR(c, sP[3][m], s2);
+      s3 = fmaR(c, sP[6][m], s3);
     }
     if (id == N) {
-      const double wN = swinv[N];
-      s0 = fma(wN, sQ[2 * d + 1][0][a], s0);
-      s1 = fma(wN, sQ[2 * d + 1][1][a], s1);
-      s2 = fma(wN, sQ[2 * d + 1][2][a], s2);
-      s3 = fma(wN, sQ[2 * d + 1][3][a], s3);
+      const R wN = swinv[N];
+      s0 = fmaR(wN, sQ[2 * d + 1][0][a], s0);
+      s1 = fmaR(wN, sQ[2 * d + 1][1][a], s1);
+      s2 = fmaR(wN, sQ[2 * d + 1][2][a], s2);
+      s3 = fmaR(wN, sQ[2 * d + 1][3][a], s3);
     }
     if (id == 0) {
-      const double w0 = swinv[0];
-      s0 = fma(-w0, sQ[2 * d][0][a], s0);
-      s1 = fma(-w0, sQ[2 * d][1][a], s1);
-      s2 = fma(-w0, sQ[2 * d][2][a], s2);
-      s3 = fma(-w0, sQ[2 * d][3][a], s3);
+      const R w0 = swinv[0];
+      s0 = fmaR(-w0, sQ[2 * d][0][a], s0);
+      s1 = fmaR(-w0, sQ[2 * d][1][a], s1);
+      s2 = fmaR(-w0, sQ[2 * d][2][a], s2);
+      s3 = fmaR(-w0, sQ[2 * d][3][a], s3);
     }
     g[d][0] = invJ[d] * s0;
     g[d][1] = invJ[d] * s1;
@@ -317,16 +518,15 @@ __device__ __forceinline__ void lifted_gradient(const double (*sP)[nn], const do
   }
 }
 
-// Viscous flux in direction d (momentum x, y, z and energy components):
-// tau = mu (grad u + grad u^T - 2/3 div u I), F_E = u . tau_d + kappa dtheta/dx_d.
-template <int D>
-__device__ __forceinline__ void viscous_flux(const double g[3][4], double vx, double vy, double vz, double mu,
-                                             double kappa, double F[4]) {
-  const double div = g[0][0] + g[1][1] + g[2][2];
-  const double dv = (2.0 / 3.0) * mu * div;
-  F[0] = mu * (g[D][0] + g[0][D]) - (D == 0 ? dv : 0.0);
-  F[1] = mu * (g[D][1] + g[1][D]) - (D == 1 ? dv : 0.0);
-  F[2] = mu * (g[D][2] + g[2][D]) - (D == 2 ? dv : 0.0);
+// Viscous flux in direction D (momentum x, y, z and energy components):
+// tau = mu (grad u + grad u^T - 2/3 div u I), F_E = u . tau_D + kappa dtheta/dx_D.
+template <int D, class R>
+__device__ __forceinline__ void viscous_flux(const R g[3][4], R vx, R vy, R vz, R mu, R kappa, R F[4]) {
+  const R div = g[0][0] + g[1][1] + g[2][2];
+  const R dv = (R)(2.0 / 3.0) * mu * div;
+  F[0] = mu * (g[D][0] + g[0][D]) - (D == 0 ? dv : (R)0);
+  F[1] = mu * (g[D][1] + g[1][D]) - (D == 1 ? dv : (R)0);
+  F[2] = mu * (g[D][2] + g[2][D]) - (D == 2 ? dv : (R)0);
   F[3] = vx * F[0] + vy * F[1] + vz * F[2] + kappa * g[D][3];
 }
 
@@ -343,9 +543,8 @@ __device__ __forceinline__ void subcell_face_state(const double (*sP)[nn], int b
                                                    int recon, const double* sxi, const double* sedge, double w[5]) {
   const int mm = base + m * st;
   double c[5];
-  const int pidx[5] = {0, 1, 2, 3, 4};
 #pragma unroll
-  for (int v = 0; v < 5; ++v) c[v] = sP[pidx[v]][mm];
+  for (int v = 0; v < 5; ++v) c[v] = sP[v][mm];
   if (recon == 1 && m >= 1 && m <= N - 1) {
     double sg[5];
     const double hl = 1.0 / (sxi[m] - sxi[m - 1]);
@@ -376,16 +575,15 @@ __device__ __forceinline__ void prim_to_cons(const double w[5], double gm1, doub
   U[4] = w[4] / gm1 + 0.5 * w[0] * (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]);
 }
 
-// Interface values of face item q (face f, face-local index a) into LDS:
-// advective f* and, for Navier-Stokes, q* = (q- + q+)/2.  D = f / 2.
-template <int VF, bool NS, int D>
-__device__ __forceinline__ void face_item(const StageArgs& A, int e, const double* Ue, int q, double (*sF)[5][nf],
-                                          double (*sQ)[4][nf]) {
-  const int f = q / nf;
-  const int a = q - f * nf;
+// Own and neighbour states of face item q (face f = q / nf, D = f / 2) in
+// canonical order: L = minus side, R = plus side.
+template <int D>
+__device__ __forceinline__ void face_states(const StageArgs& A, int e, const double* Ue, int q, double gm1,
+                                            State64& sL, State64& sR, int& f, int& a) {
+  f = q / nf;
+  a = q - f * nf;
   const int side = f & 1;
-  const int nb = A.nbr[6 * e + f];
-  const double* Un = A.U + (size_t)nb * 5 * nn;
+  const double* Un = A.U + (size_t)A.nbr[6 * e + f] * 5 * nn;
   const int nown = face_node(D, side ? N : 0, a);
   const int nnb = face_node(D, side ? 0 : N, a);
   double L[5], R[5];
@@ -396,66 +594,89 @@ __device__ __forceinline__ void face_item(const StageArgs& A, int e, const doubl
     L[v] = side ? xo : xn;
     R[v] = side ? xn : xo;
   }
-  double fs[5];
-  surface_flux<VF, D>(A.sf, L, R, A.gamma, fs);
+  sL = state64<D>(L, gm1);
+  sR = state64<D>(R, gm1);
+}
+
+// Interface values of face item q into LDS: advective f* and, for
+// Navier-Stokes, q* = (q- + q+)/2.
+template <int VF, bool NS, int D, class R, bool MX>
+__device__ __forceinline__ void face_item(const StageArgs& A, int e, const double* Ue, int q, const Ref& ref,
+                                          R (*sF)[5][nf], R (*sQ)[4][nf]) {
+  const double gm1 = A.gamma - 1.0;
+  State64 sL, sR;
+  int f, a;
+  face_states<D>(A, e, Ue, q, gm1, sL, sR, f, a);
+  const Jumps<R> J = jumps<R, MX>(sL, sR, A.gamma, ref, A.sf);
+  R g[5], fs[5];
+  riemann_rot<VF, R>(A.sf, to_rot<R, MX>(sL, ref), to_rot<R, MX>(sR, ref), J, (R)A.gamma, g);
+  unrotate<D, R>(g, fs);
 #pragma unroll
   for (int v = 0; v < 5; ++v) sF[f][v][a] = fs[v];
   if (NS) {
-    double PL[7], PR[7];
-    primitives<VF>(L, A.gamma - 1.0, PL);
-    primitives<VF>(R, A.gamma - 1.0, PR);
-    sQ[f][0][a] = 0.5 * (PL[1] + PR[1]);
-    sQ[f][1][a] = 0.5 * (PL[2] + PR[2]);
-    sQ[f][2][a] = 0.5 * (PL[3] + PR[3]);
-    sQ[f][3][a] = 0.5 * (PL[6] + PR[6]);
+    R qs[4];
+    interface_q<D, R, MX>(sL, sR, ref, qs);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) sQ[f][c][a] = qs[c];
   }
 }
 
 // Face items 0 .. 6 nf - 1 spread over the workgroup; items of one direction
 // run a direction-specialised code path.
-template <int VF, bool NS>
-__device__ __forceinline__ void all_face_items(const StageArgs& A, int e, const double* Ue, int t,
-                                               double (*sF)[5][nf], double (*sQ)[4][nf]) {
+template <int VF, bool NS, class R, bool MX>
+__device__ __forceinline__ void all_face_items(const StageArgs& A, int e, const double* Ue, int t, const Ref& ref,
+                                               R (*sF)[5][nf], R (*sQ)[4][nf]) {
   for (int q = t; q < 6 * nf; q += NT) {
-    if (q < 2 * nf) face_item<VF, NS, 0>(A, e, Ue, q, sF, sQ);
-    else if (q < 4 * nf) face_item<VF, NS, 1>(A, e, Ue, q, sF, sQ);
-    else face_item<VF, NS, 2>(A, e, Ue, q, sF, sQ);
+    if (q < 2 * nf) face_item<VF, NS, 0, R, MX>(A, e, Ue, q, ref, sF, sQ);
+    else if (q < 4 * nf) face_item<VF, NS, 1, R, MX>(A, e, Ue, q, ref, sF, sQ);
+    else face_item<VF, NS, 2, R, MX>(A, e, Ue, q, ref, sF, sQ);
   }
 }
 
 // ---------------------------------------------------------------------------
 // Stage kernel: operator (+ FV blend) and either U_t output or RK update.
-// EQ: 0 Euler, 1 Navier-Stokes.
+// EQ: 0 Euler, 1 Navier-Stokes.  R: arithmetic type (double, or float for
+// the mixed operator, MX).
 // ---------------------------------------------------------------------------
-template <int VF, int EQ, bool BLEND>
-__global__ __launch_bounds__(NT) void k_stage(StageArgs A) {
+#if DG_STAGE_MIN_WAVES > 0
+#define DG_STAGE_BOUNDS __launch_bounds__(NT, DG_STAGE_MIN_WAVES)
+#else
+#define DG_STAGE_BOUNDS __launch_bounds__(NT)
+#endif
+template <int VF, int EQ, bool BLEND, class R>
+__global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
   constexpr bool NS = (EQ == 1);
-  constexpr int NPV = NS ? 7 : 6;
-  __shared__ double sB[NB_STAGE];
-  __shared__ double sP[7][nn];
-  __shared__ double sF[6][5][nf];
-  __shared__ double sQ[NS ? 6 : 1][4][nf];
+  constexpr bool MX = sizeof(R) == 4;
+  static_assert(!(BLEND && MX), "the blended operator is FP64 only");
+  __shared__ R sB[NB_STAGE];
+  __shared__ R sP[7][nn];
+  __shared__ R sF[6][5][nf];
+  __shared__ R sQ[NS ? 6 : 1][4][nf];
   __shared__ double sX[BLEND ? 5 : 1][BLEND ? nn : 1];
-  (void)NPV;
+  __shared__ double sB64[BLEND ? NB_STAGE : 1];
 
   const int e = element_of_block(blockIdx.x, A.chunk);
   if (e >= A.nelem) return;
   const int t = threadIdx.x;
   const double gm1 = A.gamma - 1.0;
-  for (int q = t; q < NB_STAGE; q += NT) sB[q] = A.basis[q];
-  const double* sDhat = sB + BL.Dhat();
-  const double* sDw = sB + BL.Dw();
-  const double* swinv = sB + BL.winv();
-  const double* sxi = sB + BL.xi();
-  const double* sedge = sB + BL.edge();
+  for (int q = t; q < NB_STAGE; q += NT) {
+    sB[q] = (R)A.basis[q];
+    if (BLEND) sB64[q] = A.basis[q];
+  }
+  const R* sDhat = sB + BL.Dhat();
+  const R* sDw = sB + BL.Dw();
+  const R* swinv = sB + BL.winv();
+  const Ref ref = MX ? reference_state(A.U, gm1) : Ref{0.0, 0.0, 0.0};
+  const R invJ[3] = {(R)A.invJ[0], (R)A.invJ[1], (R)A.invJ[2]};
 
   const double* Ue = A.U + (size_t)e * 5 * nn;
-  double u[5], me[7];
+  double u[5];
+  R me[7];
   int ijk[3] = {0, 0, 0};
   if (t < nn) {
 #pragma unroll
     for (int v = 0; v < 5; ++v) u[v] = Ue[v * nn + t];
-    primitives<VF>(u, gm1, me);
+    primitives<VF, R, MX>(u, gm1, ref, me);
 #pragma unroll
     for (int k = 0; k < 7; ++k)
       if (k < 6 || NS) sP[k][t] = me[k];
@@ -463,41 +684,43 @@ __global__ __launch_bounds__(NT) void k_stage(StageArgs A) {
     ijk[1] = (t / n1) % n1;
     ijk[2] = t / nf;
   }
-  all_face_items<VF, NS>(A, e, Ue, t, sF, sQ);
+  all_face_items<VF, NS, R, MX>(A, e, Ue, t, ref, sF, sQ);
   __syncthreads();
 
-  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  double Fv[3][4];
+  R acc[5] = {0, 0, 0, 0, 0};
+  R Fv[3][4];
   if (t < nn) {
-    volume_dir<VF, 0>(sP, sDhat, t, ijk[0], me, A.invJ[0], gm1, acc);
-    volume_dir<VF, 1>(sP, sDhat, t, ijk[1], me, A.invJ[1], gm1, acc);
-    volume_dir<VF, 2>(sP, sDhat, t, ijk[2], me, A.invJ[2], gm1, acc);
+    volume_dir<VF, 0, R>(sP, sDhat, t, ijk[0], me, invJ[0], (R)gm1, acc);
+    volume_dir<VF, 1, R>(sP, sDhat, t, ijk[1], me, invJ[1], (R)gm1, acc);
+    volume_dir<VF, 2, R>(sP, sDhat, t, ijk[2], me, invJ[2], (R)gm1, acc);
     // advective surface terms
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const int id = ijk[d];
       const int a = d == 0 ? ijk[1] + n1 * ijk[2] : (d == 1 ? ijk[0] + n1 * ijk[2] : ijk[0] + n1 * ijk[1]);
       if (id == N) {
-        const double c = A.invJ[d] * swinv[N];
+        const R c = invJ[d] * swinv[N];
 #pragma unroll
         for (int v = 0; v < 5; ++v) acc[v] -= c * sF[2 * d + 1][v][a];
       }
       if (id == 0) {
-        const double c = A.invJ[d] * swinv[0];
+        const R c = invJ[d] * swinv[0];
 #pragma unroll
         for (int v = 0; v < 5; ++v) acc[v] += c * sF[2 * d][v][a];
       }
     }
     if (NS) {
-      double g[3][4];
-      lifted_gradient(sP, sQ, sDw, swinv, t, ijk, A.invJ, g);
-      viscous_flux<0>(g, me[1], me[2], me[3], A.mu, A.kappa, Fv[0]);
-      viscous_flux<1>(g, me[1], me[2], me[3], A.mu, A.kappa, Fv[1]);
-      viscous_flux<2>(g, me[1], me[2], me[3], A.mu, A.kappa, Fv[2]);
+      R g[3][4];
+      lifted_gradient<R>(sP, sQ, sDw, swinv, t, ijk, invJ, g);
+      const R mu = (R)A.mu, kap = (R)A.kappa;
+      viscous_flux<0, R>(g, me[1], me[2], me[3], mu, kap, Fv[0]);
+      viscous_flux<1, R>(g, me[1], me[2], me[3], mu, kap, Fv[1]);
+      viscous_flux<2, R>(g, me[1], me[2], me[3], mu, kap, Fv[2]);
     }
   }
 
   if (BLEND) {
+    // (FP64 only: R = double)
     double al = 0.0;
     {
       double m = 0.0;
@@ -508,6 +731,11 @@ __global__ __launch_bounds__(NT) void k_stage(StageArgs A) {
       if (t == 0 && A.alpha_out) A.alpha_out[e] = al;
     }
     if (al > 0.0) {  // uniform over the workgroup
+      const double* sxi = sB64 + BL.xi();
+      const double* sedge = sB64 + BL.edge();
+      const double* swinv64 = sB64 + BL.winv();
+      const double (*sP64)[nn] = reinterpret_cast<const double (*)[nn]>(sP);
+      const double (*sF64)[5][nf] = reinterpret_cast<const double (*)[5][nf]>(sF);
       double fv[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
@@ -516,8 +744,8 @@ __global__ __launch_bounds__(NT) void k_stage(StageArgs A) {
         if (t < nn && ijk[d] < N) {
           const int base = t - ijk[d] * st;
           double wl[5], wr[5], UL[5], UR[5], fs[5];
-          subcell_face_state(sP, base, st, ijk[d], true, A.recon, sxi, sedge, wl);
-          subcell_face_state(sP, base, st, ijk[d] + 1, false, A.recon, sxi, sedge, wr);
+          subcell_face_state(sP64, base, st, ijk[d], true, A.recon, sxi, sedge, wl);
+          subcell_face_state(sP64, base, st, ijk[d] + 1, false, A.recon, sxi, sedge, wr);
           prim_to_cons(wl, gm1, UL);
           prim_to_cons(wr, gm1, UR);
           surface_flux_dir<VF>(d, A.sf, UL, UR, A.gamma, fs);
@@ -528,22 +756,23 @@ __global__ __launch_bounds__(NT) void k_stage(StageArgs A) {
         if (t < nn) {
           const int id = ijk[d];
           const int a = d == 0 ? ijk[1] + n1 * ijk[2] : (d == 1 ? ijk[0] + n1 * ijk[2] : ijk[0] + n1 * ijk[1]);
-          const double c = A.invJ[d] * swinv[id];
+          const double c = A.invJ[d] * swinv64[id];
 #pragma unroll
           for (int v = 0; v < 5; ++v) {
-            const double Fr = (id == N) ? sF[2 * d + 1][v][a] : sX[v][t];
-            const double Fl = (id == 0) ? sF[2 * d][v][a] : sX[v][t - st];
+            const double Fr = (id == N) ? sF64[2 * d + 1][v][a] : sX[v][t];
+            const double Fl = (id == 0) ? sF64[2 * d][v][a] : sX[v][t - st];
             fv[v] -= c * (Fr - Fl);
           }
         }
       }
 #pragma unroll
-      for (int v = 0; v < 5; ++v) acc[v] = (1.0 - al) * acc[v] + al * fv[v];
+      for (int v = 0; v < 5; ++v) acc[v] = (R)((1.0 - al) * (double)acc[v] + al * fv[v]);
     }
   }
 
   if (NS) {
     // viscous divergence, one direction at a time through LDS (reuses sP)
+    const R* Fvf = reinterpret_cast<const R*>(A.Fvf);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       __syncthreads();
@@ -556,54 +785,59 @@ __global__ __launch_bounds__(NT) void k_stage(StageArgs A) {
         const int st = d == 0 ? 1 : (d == 1 ? n1 : nf);
         const int id = ijk[d];
         const int base = t - id * st;
-        const double* crow = sDw + id * n1;
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        const R* crow = sDw + id * n1;
+        R s0 = 0, s1 = 0, s2 = 0, s3 = 0;
 #pragma unroll
         for (int l = 0; l < n1; ++l) {
           const int m = base + l * st;
-          const double c = crow[l];
-          s0 = fma(c, sP[0][m], s0);
-          s1 = fma(c, sP[1][m], s1);
-          s2 = fma(c, sP[2][m], s2);
-          s3 = fma(c, sP[3][m], s3);
+          const R c = crow[l];
+          s0 = fmaR(c, sP[0][m], s0);
+          s1 = fmaR(c, sP[1][m], s1);
+          s2 = fmaR(c, sP[2][m], s2);
+          s3 = fmaR(c, sP[3][m], s3);
         }
         const int a = d == 0 ? ijk[1] + n1 * ijk[2] : (d == 1 ? ijk[0] + n1 * ijk[2] : ijk[0] + n1 * ijk[1]);
+        const R h2 = (R)0.5;
         if (id == N) {
           const int nb = A.nbr[6 * e + 2 * d + 1];
-          const double* Fn = A.Fvf + ((size_t)nb * 6 + 2 * d) * 4 * nf;
-          const double wN = swinv[N];
-          s0 = fma(wN, 0.5 * (Fv[d][0] + Fn[0 * nf + a]), s0);
-          s1 = fma(wN, 0.5 * (Fv[d][1] + Fn[1 * nf + a]), s1);
-          s2 = fma(wN, 0.5 * (Fv[d][2] + Fn[2 * nf + a]), s2);
-          s3 = fma(wN, 0.5 * (Fv[d][3] + Fn[3 * nf + a]), s3);
+          const R* Fn = Fvf + ((size_t)nb * 6 + 2 * d) * 4 * nf;
+          const R wN = swinv[N];
+          s0 = fmaR(wN, h2 * (Fv[d][0] + Fn[0 * nf + a]), s0);
+          s1 = fmaR(wN, h2 * (Fv[d][1] + Fn[1 * nf + a]), s1);
+          s2 = fmaR(wN, h2 * (Fv[d][2] + Fn[2 * nf + a]), s2);
+          s3 = fmaR(wN, h2 * (Fv[d][3] + Fn[3 * nf + a]), s3);
         }
         if (id == 0) {
           const int nb = A.nbr[6 * e + 2 * d];
-          const double* Fn = A.Fvf + ((size_t)nb * 6 + 2 * d + 1) * 4 * nf;
-          const double w0 = swinv[0];
-          s0 = fma(-w0, 0.5 * (Fv[d][0] + Fn[0 * nf + a]), s0);
-          s1 = fma(-w0, 0.5 * (Fv[d][1] + Fn[1 * nf + a]), s1);
-          s2 = fma(-w0, 0.5 * (Fv[d][2] + Fn[2 * nf + a]), s2);
-          s3 = fma(-w0, 0.5 * (Fv[d][3] + Fn[3 * nf + a]), s3);
+          const R* Fn = Fvf + ((size_t)nb * 6 + 2 * d + 1) * 4 * nf;
+          const R w0 = swinv[0];
+          s0 = fmaR(-w0, h2 * (Fv[d][0] + Fn[0 * nf + a]), s0);
+          s1 = fmaR(-w0, h2 * (Fv[d][1] + Fn[1 * nf + a]), s1);
+          s2 = fmaR(-w0, h2 * (Fv[d][2] + Fn[2 * nf + a]), s2);
+          s3 = fmaR(-w0, h2 * (Fv[d][3] + Fn[3 * nf + a]), s3);
         }
-        acc[1] = fma(A.invJ[d], s0, acc[1]);
-        acc[2] = fma(A.invJ[d], s1, acc[2]);
-        acc[3] = fma(A.invJ[d], s2, acc[3]);
-        acc[4] = fma(A.invJ[d], s3, acc[4]);
+        acc[1] = fmaR(invJ[d], s0, acc[1]);
+        acc[2] = fmaR(invJ[d], s1, acc[2]);
+        acc[3] = fmaR(invJ[d], s2, acc[3]);
+        acc[4] = fmaR(invJ[d], s3, acc[4]);
       }
     }
   }
 
   if (t < nn) {
+    double ut[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) ut[v] = (double)acc[v];
+    if (MX) ut[4] += ref.h * ut[0];  // undo the energy-flux shift h0 * (mass flux)
     const size_t o = (size_t)e * 5 * nn + t;
     if (A.mode == MODE_UT) {
 #pragma unroll
-      for (int v = 0; v < 5; ++v) A.Ut[o + v * nn] = acc[v];
+      for (int v = 0; v < 5; ++v) A.Ut[o + v * nn] = ut[v];
     } else {
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
-        double gv = acc[v];
-        if (A.A != 0.0) gv = A.A * A.G[o + v * nn] + acc[v];
+        double gv = ut[v];
+        if (A.A != 0.0) gv = A.A * A.G[o + v * nn] + ut[v];
         if (A.writeG) A.G[o + v * nn] = gv;
         A.Uout[o + v * nn] = u[v] + A.Bdt * gv;
       }
@@ -611,76 +845,71 @@ __global__ __launch_bounds__(NT) void k_stage(StageArgs A) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// BR1 lifting pass (Navier-Stokes): normal viscous flux at the element's own
+// face nodes -> Fvf[e][f][c][a] (type R), read by the neighbours' stage kernels.
+// ---------------------------------------------------------------------------
+template <int D, class R, bool MX>
+__device__ __forceinline__ void lift_face_q(const StageArgs& A, int e, const double* Ue, int q, const Ref& ref,
+                                            R (*sQ)[4][nf]) {
+  State64 sL, sR;
+  int f, a;
+  face_states<D>(A, e, Ue, q, A.gamma - 1.0, sL, sR, f, a);
+  R qs[4];
+  interface_q<D, R, MX>(sL, sR, ref, qs);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) sQ[f][c][a] = qs[c];
+}
+
 // Normal viscous flux at face node q of the element (face f = q / nf, D = f / 2).
-template <int D>
-__device__ __forceinline__ void lift_face_node(const StageArgs& A, int e, int q, const double (*sP)[nn],
-                                               const double (*sQ)[4][nf], const double* sB) {
+template <int D, class R>
+__device__ __forceinline__ void lift_face_node(const StageArgs& A, int e, int q, const R (*sP)[nn],
+                                               const R (*sQ)[4][nf], const R* sB, const R invJ[3]) {
   const int f = q / nf;
   const int a = q - f * nf;
   const int n = face_node(D, (f & 1) ? N : 0, a);
   const int ijk[3] = {n % n1, (n / n1) % n1, n / nf};
-  double g[3][4], F[4];
-  lifted_gradient(sP, sQ, sB + BL.Dw(), sB + BL.winv(), n, ijk, A.invJ, g);
-  viscous_flux<D>(g, sP[1][n], sP[2][n], sP[3][n], A.mu, A.kappa, F);
-  double* out = A.Fvf + ((size_t)e * 6 + f) * 4 * nf;
+  R g[3][4], F[4];
+  lifted_gradient<R>(sP, sQ, sB + BL.Dw(), sB + BL.winv(), n, ijk, invJ, g);
+  viscous_flux<D, R>(g, sP[1][n], sP[2][n], sP[3][n], (R)A.mu, (R)A.kappa, F);
+  R* out = reinterpret_cast<R*>(A.Fvf) + ((size_t)e * 6 + f) * 4 * nf;
 #pragma unroll
   for (int c = 0; c < 4; ++c) out[c * nf + a] = F[c];
 }
 
-// ---------------------------------------------------------------------------
-// BR1 lifting pass (Navier-Stokes): normal viscous flux at the element's own
-// face nodes -> Fvf[e][f][c][a], read by the neighbours' stage kernels.
-// ---------------------------------------------------------------------------
+template <class R>
 __global__ __launch_bounds__(NT) void k_lift(StageArgs A) {
-  __shared__ double sB[NB_STAGE];
-  __shared__ double sP[7][nn];
-  __shared__ double sF[1][5][nf];
-  __shared__ double sQ[6][4][nf];
+  constexpr bool MX = sizeof(R) == 4;
+  __shared__ R sB[NB_STAGE];
+  __shared__ R sP[7][nn];
+  __shared__ R sQ[6][4][nf];
   const int e = element_of_block(blockIdx.x, A.chunk);
   if (e >= A.nelem) return;
   const int t = threadIdx.x;
   const double gm1 = A.gamma - 1.0;
-  for (int q = t; q < NB_STAGE; q += NT) sB[q] = A.basis[q];
+  for (int q = t; q < NB_STAGE; q += NT) sB[q] = (R)A.basis[q];
+  const Ref ref = MX ? reference_state(A.U, gm1) : Ref{0.0, 0.0, 0.0};
+  const R invJ[3] = {(R)A.invJ[0], (R)A.invJ[1], (R)A.invJ[2]};
   const double* Ue = A.U + (size_t)e * 5 * nn;
   if (t < nn) {
-    double u[5], P[7];
+    double u[5];
+    R P[7];
 #pragma unroll
     for (int v = 0; v < 5; ++v) u[v] = Ue[v * nn + t];
-    primitives<VF_PI>(u, gm1, P);
+    primitives<VF_PI, R, MX>(u, gm1, ref, P);
 #pragma unroll
     for (int k = 0; k < 7; ++k) sP[k][t] = P[k];
   }
   for (int q = t; q < 6 * nf; q += NT) {
-    const int f = q / nf;
-    const int a = q - f * nf;
-    const int d = f >> 1;
-    const int side = f & 1;
-    const int nb = A.nbr[6 * e + f];
-    const double* Un = A.U + (size_t)nb * 5 * nn;
-    const int nown = face_node(d, side ? N : 0, a);
-    const int nnb = face_node(d, side ? 0 : N, a);
-    double L[5], R[5];
-#pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      const double xo = Ue[v * nn + nown];
-      const double xn = Un[v * nn + nnb];
-      L[v] = side ? xo : xn;
-      R[v] = side ? xn : xo;
-    }
-    double PL[7], PR[7];
-    primitives<VF_PI>(L, gm1, PL);
-    primitives<VF_PI>(R, gm1, PR);
-    sQ[f][0][a] = 0.5 * (PL[1] + PR[1]);
-    sQ[f][1][a] = 0.5 * (PL[2] + PR[2]);
-    sQ[f][2][a] = 0.5 * (PL[3] + PR[3]);
-    sQ[f][3][a] = 0.5 * (PL[6] + PR[6]);
+    if (q < 2 * nf) lift_face_q<0, R, MX>(A, e, Ue, q, ref, sQ);
+    else if (q < 4 * nf) lift_face_q<1, R, MX>(A, e, Ue, q, ref, sQ);
+    else lift_face_q<2, R, MX>(A, e, Ue, q, ref, sQ);
   }
   __syncthreads();
-  (void)sF;
   for (int q = t; q < 6 * nf; q += NT) {
-    if (q < 2 * nf) lift_face_node<0>(A, e, q, sP, sQ, sB);
-    else if (q < 4 * nf) lift_face_node<1>(A, e, q, sP, sQ, sB);
-    else lift_face_node<2>(A, e, q, sP, sQ, sB);
+    if (q < 2 * nf) lift_face_node<0, R>(A, e, q, sP, sQ, sB, invJ);
+    else if (q < 4 * nf) lift_face_node<1, R>(A, e, q, sP, sQ, sB, invJ);
+    else lift_face_node<2, R>(A, e, q, sP, sQ, sB, invJ);
   }
 }
 
@@ -868,26 +1097,45 @@ __global__ __launch_bounds__(NT) void k_nonfinite(ReduceArgs R) {
 // ---------------------------------------------------------------------------
 inline int blocks_for(const StageArgs& A) { return 8 * A.chunk; }
 
-template <int VF>
+template <int VF, class R>
 hipError_t launch_stage_vf(const StageArgs& A, int eq, hipStream_t s) {
   const dim3 grid(blocks_for(A)), block(NT);
-  if (eq == 1) hipLaunchKernelGGL((k_stage<VF, 1, false>), grid, block, 0, s, A);
-  else if (A.blend) hipLaunchKernelGGL((k_stage<VF, 0, true>), grid, block, 0, s, A);
-  else hipLaunchKernelGGL((k_stage<VF, 0, false>), grid, block, 0, s, A);
+  if (eq == 1) {
+    hipLaunchKernelGGL((k_stage<VF, 1, false, R>), grid, block, 0, s, A);
+  } else if (A.blend) {
+    if constexpr (sizeof(R) == 8) hipLaunchKernelGGL((k_stage<VF, 0, true, double>), grid, block, 0, s, A);
+    else return hipErrorInvalidValue;
+  } else {
+    hipLaunchKernelGGL((k_stage<VF, 0, false, R>), grid, block, 0, s, A);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_stage(const StageArgs& A, int eq, hipStream_t s) {
   switch (A.vf) {
-    case VF_KG: return launch_stage_vf<VF_KG>(A, eq, s);
-    case VF_PI: return launch_stage_vf<VF_PI>(A, eq, s);
-    case VF_CH: return launch_stage_vf<VF_CH>(A, eq, s);
-    default: return launch_stage_vf<VF_STD>(A, eq, s);
+    case VF_KG: return launch_stage_vf<VF_KG, double>(A, eq, s);
+    case VF_PI: return launch_stage_vf<VF_PI, double>(A, eq, s);
+    case VF_CH: return launch_stage_vf<VF_CH, double>(A, eq, s);
+    default: return launch_stage_vf<VF_STD, double>(A, eq, s);
+  }
+}
+
+// Mixed operator: flux forms whose reference shift is exact (PI, STD).
+hipError_t launch_stage_mixed(const StageArgs& A, int eq, hipStream_t s) {
+  switch (A.vf) {
+    case VF_PI: return launch_stage_vf<VF_PI, float>(A, eq, s);
+    case VF_STD: return launch_stage_vf<VF_STD, float>(A, eq, s);
+    default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_lift(const StageArgs& A, hipStream_t s) {
-  hipLaunchKernelGGL(k_lift, dim3(blocks_for(A)), dim3(NT), 0, s, A);
+  hipLaunchKernelGGL(k_lift<double>, dim3(blocks_for(A)), dim3(NT), 0, s, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_lift_mixed(const StageArgs& A, hipStream_t s) {
+  hipLaunchKernelGGL(k_lift<float>, dim3(blocks_for(A)), dim3(NT), 0, s, A);
   return hipGetLastError();
 }
 
@@ -917,7 +1165,7 @@ hipError_t launch_nonfinite(const ReduceArgs& R, hipStream_t s) {
 }
 
 const KernelTable kTable = {
-    NT, launch_stage, nullptr, launch_lift, nullptr, launch_alpha1, launch_spread,
+    NT, launch_stage, launch_stage_mixed, launch_lift, launch_lift_mixed, launch_alpha1, launch_spread,
     launch_max_rate, launch_integrals, launch_nonfinite, nullptr, nullptr,
 };
 

@@ -16,7 +16,8 @@ import os
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libdgmi.so")
+# DGMI_LIBRARY selects another build of the same library (e.g. a tuning variant).
+LIB_PATH = os.environ.get("DGMI_LIBRARY") or os.path.join(_HERE, "libdgmi.so")
 
 DG_OK, DG_EINVAL, DG_ENOMEM, DG_EHIP, DG_EUNSUPPORTED, DG_ENONFINITE, DG_ESTATE = 0, -1, -2, -3, -4, -5, -6
 EULER, NS = 0, 1
