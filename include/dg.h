@@ -128,13 +128,19 @@ int rk_step(dg_ctx* ctx, double* U, double dt);
 /* nsteps Runge-Kutta steps in place (same result as nsteps rk_step calls). */
 int dg_rk_steps(dg_ctx* ctx, double* U, double dt, int nsteps);
 
-/* Vector-Jacobian product of the operator: U_bar = (dL/dU)^T Ut_bar.
- * Overwrites U_bar.  Not available with blending or DG_MIXED. */
+/* Vector-Jacobian product of the operator: U_bar = (dL/dU)^T Ut_bar (the
+ * reverse mode of dg_time_derivative, for gradients of functionals of the
+ * solution).  Overwrites U_bar, which must not alias U or Ut_bar.  Not
+ * available with blending, DG_MIXED or the CH flux (DG_EUNSUPPORTED).
+ * Allocates the reverse-mode face buffer on first use. */
 int dg_vjp(dg_ctx* ctx, const double* U, const double* Ut_bar, double* U_bar);
 
 /* Vector-Jacobian product of one rk_step: U_bar_n = (dU_{n+1}/dU_n)^T U_bar_np1,
- * with U_n the state before the step.  Overwrites U_bar_n (may alias
- * U_bar_np1).  Not available with blending or DG_MIXED. */
+ * with U_n the state before the step.  Recomputes the five stage states from
+ * U_n and runs the reverse 2N-storage recurrence
+ *   Gbar <- A_{k+1} Gbar + B_k dt Ybar,  Ybar <- Ybar + VJP(Y_{k-1}, Gbar),
+ * k = 5..1.  Overwrites U_bar_n (may alias U_bar_np1, not U_n).  Same
+ * restrictions as dg_vjp; allocates seven state-sized buffers on first use. */
 int rk_step_vjp(dg_ctx* ctx, const double* U_n, double dt, const double* U_bar_np1, double* U_bar_n);
 
 /* Stable time step: cfl * min(1/((N+1) max sum_d (|u_d|+c)/dx_d),
@@ -157,11 +163,17 @@ int dg_check_finite(dg_ctx* ctx, const double* X);
  * context's stream.  dg_profile_read synchronises the stream, writes the
  * summed milliseconds and the number of launches per kernel kind
  * (DG_K_STAGE: operator + Runge-Kutta stage, DG_K_LIFT: BR1 lifting,
- * DG_K_INDICATOR: modal indicator) into ms[3] and launches[3], and clears
+ * DG_K_INDICATOR: modal indicator, DG_K_VJP: reverse operator,
+ * DG_K_VJP_LIFT: reverse BR1 lifting) into ms[5] and launches[5], and clears
  * the records.  Disabling also clears them. */
-enum { DG_K_STAGE = 0, DG_K_LIFT = 1, DG_K_INDICATOR = 2 };
+enum { DG_K_STAGE = 0, DG_K_LIFT = 1, DG_K_INDICATOR = 2, DG_K_VJP = 3, DG_K_VJP_LIFT = 4 };
 int dg_set_profiling(dg_ctx* ctx, int on);
-int dg_profile_read(dg_ctx* ctx, double ms[3], int64_t launches[3]);
+int dg_profile_read(dg_ctx* ctx, double ms[5], int64_t launches[5]);
+
+/* Quadrature weight of every node of an element, w_i w_j w_k J (host array
+ * of (N+1)^3 doubles, x index fastest), so that sum_e sum_n w_n X[e][v][n]
+ * is the integral of X_v (used to build functionals for the adjoint). */
+int dg_node_weights(const dg_ctx* ctx, double* w);
 
 /* Sizes: number of elements and nodes per element. */
 int dg_sizes(const dg_ctx* ctx, int64_t* n_elems, int64_t* nodes_per_elem);

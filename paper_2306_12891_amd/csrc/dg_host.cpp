@@ -175,6 +175,12 @@ struct dg_ctx {
   double* Fvf = nullptr;
   double* partial = nullptr;
   double* h_partial = nullptr;
+  // reverse mode (allocated on first use): stage states Y_0..Y_4, the
+  // register and state cotangents, and the face buffer of gradient cotangents
+  double* Y[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  double* Gbar = nullptr;
+  double* Ybar = nullptr;
+  double* Gbf = nullptr;
   char err[256] = "";
   // kernel timing (dg_set_profiling)
   int profiling = 0;
@@ -221,6 +227,10 @@ void release(dg_ctx* c) {
   hipFree(c->Fvf);
   hipFree(c->partial);
   if (c->h_partial) hipHostFree(c->h_partial);
+  for (double* y : c->Y) hipFree(y);
+  hipFree(c->Gbar);
+  hipFree(c->Ybar);
+  hipFree(c->Gbf);
 }
 
 StageArgs stage_args(const dg_ctx* c) {
@@ -324,6 +334,62 @@ int run_stage(dg_ctx* c, const double* Xin, double* Xout, double* Ut, int mode, 
 }
 
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+int vjp_supported(dg_ctx* c) {
+  if (c->opt.blending) return fail(c, DG_EUNSUPPORTED, "vjp: not available with blending");
+  if (c->opt.precision != DG_FP64) return fail(c, DG_EUNSUPPORTED, "vjp: FP64 operator only");
+  if (c->opt.vol_flux == DG_VF_CH) return fail(c, DG_EUNSUPPORTED, "vjp: not available for the CH flux");
+  return DG_OK;
+}
+
+// Reverse-mode scratch, allocated on first use.
+int ensure_reverse_buffers(dg_ctx* c, bool rk) {
+  hipError_t e = hipSuccess;
+  const size_t bytes = c->nstate * sizeof(double);
+  if (!c->Gbf) e = hipMalloc((void**)&c->Gbf, (size_t)c->nelem * 6 * 4 * c->nf * sizeof(double));
+  if (rk) {
+    for (int k = 0; k < 5 && e == hipSuccess; ++k)
+      if (!c->Y[k]) e = hipMalloc((void**)&c->Y[k], bytes);
+    if (e == hipSuccess && !c->Gbar) e = hipMalloc((void**)&c->Gbar, bytes);
+    if (e == hipSuccess && !c->Ybar) e = hipMalloc((void**)&c->Ybar, bytes);
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, (e == hipErrorOutOfMemory) ? DG_ENOMEM : DG_EHIP, "reverse-mode buffers: %s", hipGetErrorString(e));
+  }
+  return DG_OK;
+}
+
+// U_bar = [Uacc +] (dL/dU)^T lambda on the context's stream.
+int run_vjp(dg_ctx* c, const double* U, const double* lambda, double* U_bar, const double* Uacc) {
+  int rc = ensure_reverse_buffers(c, false);
+  if (rc) return rc;
+  VjpArgs v;
+  std::memset(&v, 0, sizeof(v));
+  v.U = U;
+  v.Lbar = lambda;
+  v.Ubar = U_bar;
+  v.Uacc = Uacc;
+  v.nbr = c->nbr;
+  v.basis = c->basis;
+  v.Gbf = c->Gbf;
+  for (int d = 0; d < 3; ++d) v.invJ[d] = c->invJ[d];
+  v.gamma = c->gamma;
+  v.mu = c->mu;
+  v.kappa = c->mu * c->gamma / ((c->gamma - 1.0) * c->opt.Pr);
+  v.nelem = c->nelem;
+  v.chunk = c->chunk;
+  v.vf = c->opt.vol_flux;
+  v.sf = c->opt.surf_flux;
+  hipError_t e;
+  if (c->opt.equations == DG_NS) {
+    e = timed(c, DG_K_VJP_LIFT, [&] { return c->kt->vjp_lift(v, c->stream); });
+    if (e != hipSuccess) return hip_fail(c, e, "vjp lifting kernel");
+  }
+  e = timed(c, DG_K_VJP, [&] { return c->kt->vjp(v, c->opt.equations, c->stream); });
+  if (e != hipSuccess) return hip_fail(c, e, "vjp kernel");
+  return DG_OK;
+}
 
 }  // namespace
 
@@ -494,14 +560,42 @@ int rk_step(dg_ctx* c, double* U, double dt) { return dg_rk_steps(c, U, dt, 1); 
 
 int dg_vjp(dg_ctx* c, const double* U, const double* Ut_bar, double* U_bar) {
   if (check_ctx(c)) return DG_EINVAL;
-  (void)U; (void)Ut_bar; (void)U_bar;
-  return fail(c, DG_EUNSUPPORTED, "dg_vjp: not available in this build");
+  if (!is_device_ptr(U) || !is_device_ptr(Ut_bar) || !is_device_ptr(U_bar))
+    return fail(c, DG_EINVAL, "dg_vjp: device pointers required");
+  if ((const void*)U_bar == (const void*)U || (const void*)U_bar == (const void*)Ut_bar)
+    return fail(c, DG_EINVAL, "dg_vjp: U_bar must not alias U or Ut_bar");
+  int rc = vjp_supported(c);
+  if (rc) return rc;
+  return run_vjp(c, U, Ut_bar, U_bar, nullptr);
 }
 
 int rk_step_vjp(dg_ctx* c, const double* U_n, double dt, const double* U_bar_np1, double* U_bar_n) {
   if (check_ctx(c)) return DG_EINVAL;
-  (void)U_n; (void)dt; (void)U_bar_np1; (void)U_bar_n;
-  return fail(c, DG_EUNSUPPORTED, "rk_step_vjp: not available in this build");
+  if (!is_device_ptr(U_n) || !is_device_ptr(U_bar_np1) || !is_device_ptr(U_bar_n))
+    return fail(c, DG_EINVAL, "rk_step_vjp: device pointers required");
+  if (!finite_pos(dt)) return fail(c, DG_EINVAL, "rk_step_vjp: dt must be finite and > 0");
+  if ((const void*)U_bar_n == (const void*)U_n) return fail(c, DG_EINVAL, "rk_step_vjp: U_bar_n aliases U_n");
+  int rc = vjp_supported(c);
+  if (rc) return rc;
+  if ((rc = ensure_reverse_buffers(c, true))) return rc;
+  const size_t bytes = c->nstate * sizeof(double);
+  hipError_t e = hipMemcpyAsync(c->Y[0], U_n, bytes, hipMemcpyDeviceToDevice, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "rk_step_vjp copy");
+  // forward: stage states Y_1..Y_4 (Y_5 = U_{n+1} is not needed)
+  for (int k = 0; k < 4; ++k)
+    if ((rc = run_stage(c, c->Y[k], c->Y[k + 1], nullptr, MODE_RK, kA[k], kB[k] * dt, 1, nullptr))) return rc;
+  // reverse: Gbar <- A_{k+1} Gbar + B_k dt Ybar;  Ybar += VJP(Y_k, Gbar)
+  e = hipMemcpyAsync(c->Ybar, U_bar_np1, bytes, hipMemcpyDeviceToDevice, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "rk_step_vjp copy");
+  for (int k = 4; k >= 0; --k) {
+    const double a = (k == 4) ? 0.0 : kA[k + 1];
+    e = c->kt->axpby(c->Gbar, a, c->Ybar, kB[k] * dt, c->nstate, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "rk_step_vjp axpby");
+    if ((rc = run_vjp(c, c->Y[k], c->Gbar, c->Ybar, c->Ybar))) return rc;
+  }
+  e = hipMemcpyAsync(U_bar_n, c->Ybar, bytes, hipMemcpyDeviceToDevice, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "rk_step_vjp copy");
+  return DG_OK;
 }
 
 int dg_max_dt(dg_ctx* c, const double* U, double cfl, double* dt_out) {
@@ -579,9 +673,9 @@ int dg_set_profiling(dg_ctx* c, int on) {
   return DG_OK;
 }
 
-int dg_profile_read(dg_ctx* c, double ms[3], int64_t launches[3]) {
+int dg_profile_read(dg_ctx* c, double ms[5], int64_t launches[5]) {
   if (check_ctx(c) || !ms || !launches) return fail(c, DG_EINVAL, "dg_profile_read: NULL argument");
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < 5; ++k) {
     ms[k] = 0.0;
     launches[k] = 0;
   }
@@ -595,6 +689,17 @@ int dg_profile_read(dg_ctx* c, double ms[3], int64_t launches[3]) {
     launches[r.kind] += 1;
   }
   c->recs.clear();
+  return DG_OK;
+}
+
+int dg_node_weights(const dg_ctx* c, double* w) {
+  if (!c || !w) return DG_EINVAL;
+  const std::vector<double> b = build_basis(c->N);
+  const BasisLayout L(c->n1);
+  for (int k = 0; k < c->n1; ++k)
+    for (int j = 0; j < c->n1; ++j)
+      for (int i = 0; i < c->n1; ++i)
+        w[i + c->n1 * (j + c->n1 * k)] = b[L.w() + i] * b[L.w() + j] * b[L.w() + k] * c->Jac;
   return DG_OK;
 }
 

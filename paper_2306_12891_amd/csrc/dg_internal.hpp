@@ -52,22 +52,19 @@ struct ReduceArgs {
   int nelem;
 };
 
-// VJP arguments (reverse-mode operator).
+// Vector-Jacobian product arguments (reverse mode of the FP64 operator).
 struct VjpArgs {
-  const double* U;
-  const double* Lbar;   // cotangent of U_t
-  double* Ubar;         // output (overwritten)
+  const double* U;      // state at which the operator is linearised
+  const double* Lbar;   // cotangent of U_t (lambda)
+  double* Ubar;         // output: (dL/dU)^T lambda, or Uacc + that
+  const double* Uacc;   // optional: accumulate into this array (may alias Ubar)
   const int32_t* nbr;
   const double* basis;
-  double* Gbar_face;    // NS: [nelem][6][12][nf] gradient cotangent from face viscous flux
+  double* Gbf;          // NS: [nelem][6][4][nf] cotangent of the normal lifted gradient at own face nodes
   double invJ[3];
   double gamma, mu, kappa;
   int nelem, chunk;
   int vf, sf;
-  // RK-VJP fusion: Ubar_out = Ubar_in + scale * VJP  (accumulate mode)
-  const double* Uacc;
-  double scale;
-  int accumulate;
 };
 
 struct KernelTable {
@@ -83,6 +80,8 @@ struct KernelTable {
   hipError_t (*nonfinite)(const ReduceArgs&, hipStream_t);
   hipError_t (*vjp)(const VjpArgs&, int eq, hipStream_t);
   hipError_t (*vjp_lift)(const VjpArgs&, hipStream_t);
+  // y <- a y + b x over n doubles
+  hipError_t (*axpby)(double* y, double a, const double* x, double b, size_t n, hipStream_t);
 };
 
 const KernelTable* table_N1();

@@ -30,6 +30,8 @@
 // shift is exact in real arithmetic: the momentum flux changes by the constant
 // p0 e_d, which the operator annihilates, and the energy flux by h0 times the
 // mass flux, which is added back as U_t,E += h0 U_t,rho in FP64.
+#include <algorithm>
+
 #include "dg_internal.hpp"
 
 #ifndef DG_N
@@ -913,6 +915,529 @@ __global__ __launch_bounds__(NT) void k_lift(StageArgs A) {
   }
 }
 
+// ===========================================================================
+// Reverse mode: vector-Jacobian product of the FP64 operator (no blending).
+//
+//   U_bar = (dL/dU)^T lambda,   lambda = cotangent of U_t.
+//
+// * Volume integral: F# is symmetric, so node n's cotangent is
+//     sum_d sum_l (d1 F#_d(U_n, U_l))^T w_nl,
+//     w_nl = -(2/dx_d)(Dhat_{i l} lambda_n + Dhat_{l i} lambda_l),
+//   evaluated by hand-derived reverse mode of the two-point flux in primitive
+//   variables, then pulled back to conservative variables once per node.
+// * Interface fluxes: each element differentiates f*(U-, U+) with respect to
+//   its own side with forward-mode dual numbers (five seeds), contracted with
+//   the flux cotangent that collects lambda of both elements.
+// * BR1 viscous terms: reverse of Fv(U, g), of g(q, q*) and of q(U).  The
+//   interface value q* couples the lifted gradients of both elements, so a
+//   first pass (k_vjp_lift) writes the cotangent of each element's normal
+//   gradient at its own face nodes, which the neighbours read.
+// Non-smooth points use the same conventions as the oracle's dual numbers:
+// d|x|/dx = 0 at 0 and max(a, b) takes the mean derivative at a tie.
+// ===========================================================================
+struct Dl {
+  double v, d;
+};
+__device__ __forceinline__ Dl operator+(Dl a, Dl b) { return {a.v + b.v, a.d + b.d}; }
+__device__ __forceinline__ Dl operator-(Dl a, Dl b) { return {a.v - b.v, a.d - b.d}; }
+__device__ __forceinline__ Dl operator-(Dl a) { return {-a.v, -a.d}; }
+__device__ __forceinline__ Dl operator*(Dl a, Dl b) { return {a.v * b.v, fma(a.d, b.v, a.v * b.d)}; }
+__device__ __forceinline__ Dl operator*(double a, Dl b) { return {a * b.v, a * b.d}; }
+__device__ __forceinline__ Dl operator*(Dl a, double b) { return {a.v * b, a.d * b}; }
+__device__ __forceinline__ Dl operator+(Dl a, double b) { return {a.v + b, a.d}; }
+__device__ __forceinline__ Dl operator-(double a, Dl b) { return {a - b.v, -b.d}; }
+__device__ __forceinline__ double val(double x) { return x; }
+__device__ __forceinline__ double val(Dl x) { return x.v; }
+__device__ __forceinline__ double s_rcp(double x) { return rcp64(x); }
+__device__ __forceinline__ Dl s_rcp(Dl x) {
+  const double r = rcp64(x.v);
+  return {r, -x.d * r * r};
+}
+__device__ __forceinline__ double s_sqrt(double x) { return sqrt64(x); }
+__device__ __forceinline__ Dl s_sqrt(Dl x) {
+  const double s = sqrt64(x.v);
+  return {s, x.d * 0.5 * rcp64(s)};
+}
+__device__ __forceinline__ double s_abs(double x) { return fabs(x); }
+__device__ __forceinline__ Dl s_abs(Dl x) {
+  if (x.v > 0.0) return x;
+  if (x.v < 0.0) return -x;
+  return {0.0, 0.0};
+}
+__device__ __forceinline__ double s_max(double a, double b) { return fmax(a, b); }
+__device__ __forceinline__ Dl s_max(Dl a, Dl b) {
+  if (a.v > b.v) return a;
+  if (b.v > a.v) return b;
+  return {a.v, 0.5 * (a.d + b.d)};
+}
+
+// Interface flux of conservative states (rotated by D) over a generic scalar;
+// the same arithmetic as state64 / jumps / riemann_rot of the forward operator.
+template <int VF, int D, class S>
+__device__ __forceinline__ void riemann_generic(int sf, const S L[5], const S R[5], double gamma, S f[5]) {
+  constexpr int kn = Axes<D>::kn, k1 = Axes<D>::k1, k2 = Axes<D>::k2;
+  const double gm1 = gamma - 1.0;
+  const S iL = s_rcp(L[0]), iR = s_rcp(R[0]);
+  const S unL = L[kn] * iL, u1L = L[k1] * iL, u2L = L[k2] * iL;
+  const S unR = R[kn] * iR, u1R = R[k1] * iR, u2R = R[k2] * iR;
+  const S pL = gm1 * (L[4] - 0.5 * (L[kn] * unL + L[k1] * u1L + L[k2] * u2L));
+  const S pR = gm1 * (R[4] - 0.5 * (R[kn] * unR + R[k1] * u1R + R[k2] * u2R));
+  const S hL = (L[4] + pL) * iL, hR = (R[4] + pR) * iR;
+  S g[5];
+  if (VF == VF_STD) {
+    g[0] = 0.5 * (L[kn] + R[kn]);
+    g[1] = 0.5 * (L[kn] * unL + pL + R[kn] * unR + pR);
+    g[2] = 0.5 * (L[kn] * u1L + R[kn] * u1R);
+    g[3] = 0.5 * (L[kn] * u2L + R[kn] * u2R);
+    g[4] = 0.5 * (L[kn] * hL + R[kn] * hR);
+  } else {
+    const S um0 = 0.5 * (unL + unR), um1 = 0.5 * (u1L + u1R), um2 = 0.5 * (u2L + u2R);
+    const S rm = 0.5 * (L[0] + R[0]), pm = 0.5 * (pL + pR);
+    const S fr = rm * um0;
+    g[0] = fr;
+    g[1] = fr * um0 + pm;
+    g[2] = fr * um1;
+    g[3] = fr * um2;
+    if (VF == VF_KG) g[4] = fr * (0.5 * (L[4] * iL + R[4] * iR)) + pm * um0;
+    else g[4] = fr * (0.5 * (hL + hR));
+  }
+  if (sf == SF_LLF) {
+    const S cL = s_sqrt(gamma * pL * iL), cR = s_sqrt(gamma * pR * iR);
+    const S hl = 0.5 * s_max(s_abs(unL) + cL, s_abs(unR) + cR);
+    g[0] = g[0] - hl * (R[0] - L[0]);
+    g[1] = g[1] - hl * (R[kn] - L[kn]);
+    g[2] = g[2] - hl * (R[k1] - L[k1]);
+    g[3] = g[3] - hl * (R[k2] - L[k2]);
+    g[4] = g[4] - hl * (R[4] - L[4]);
+  } else if (sf == SF_ROE) {
+    const S sL = s_sqrt(L[0]), sR = s_sqrt(R[0]);
+    const S inv = s_rcp(sL + sR);
+    const S ut0 = (sL * unL + sR * unR) * inv;
+    const S ut1 = (sL * u1L + sR * u1R) * inv;
+    const S ut2 = (sL * u2L + sR * u2R) * inv;
+    const S Ht = (sL * hL + sR * hR) * inv;
+    const S rt = sL * sR;
+    const S q2 = ut0 * ut0 + ut1 * ut1 + ut2 * ut2;
+    const S c2 = gm1 * (Ht - 0.5 * q2);
+    const S ct = s_sqrt(c2);
+    const S ic2 = s_rcp(c2);
+    const S dr = R[0] - L[0], dp = pR - pL;
+    const S dun = unR - unL, dt1 = u1R - u1L, dt2 = u2R - u2L;
+    const S a1 = 0.5 * (dp - rt * ct * dun) * ic2;
+    const S a5 = 0.5 * (dp + rt * ct * dun) * ic2;
+    const S a2 = dr - dp * ic2;
+    const S l1 = s_abs(ut0 - ct), l5 = s_abs(ut0 + ct), l2 = s_abs(ut0);
+    const S w1 = l1 * a1, w5 = l5 * a5;
+    const S D0 = w1 + w5 + l2 * a2;
+    const S Dn = w1 * (ut0 - ct) + w5 * (ut0 + ct) + l2 * (a2 * ut0);
+    const S D1 = w1 * ut1 + w5 * ut1 + l2 * (a2 * ut1 + rt * dt1);
+    const S D2 = w1 * ut2 + w5 * ut2 + l2 * (a2 * ut2 + rt * dt2);
+    const S D4 = w1 * (Ht - ct * ut0) + w5 * (Ht + ct * ut0) + l2 * (a2 * (0.5 * q2) + rt * (ut1 * dt1 + ut2 * dt2));
+    g[0] = g[0] - 0.5 * D0;
+    g[1] = g[1] - 0.5 * Dn;
+    g[2] = g[2] - 0.5 * D1;
+    g[3] = g[3] - 0.5 * D2;
+    g[4] = g[4] - 0.5 * D4;
+  }
+  f[0] = g[0];
+  f[kn] = g[1];
+  f[k1] = g[2];
+  f[k2] = g[3];
+  f[4] = g[4];
+}
+
+// Cotangent of the lifted viscous flux at node m in all three directions,
+// Fvb[d][c] (c = momentum x, y, z, energy), from lambda along the three lines
+// through m (sLam, components 1..4) and lambda of the neighbours on the faces
+// containing m (sLn[f][c][a], components 1..4):
+//   Fvb_d(m) = (2/dx_d) [ sum_n Dw_{i(n) i(m)} lambda_n
+//                         + 1/2 delta_{i N}(lambda_m / w_N - lambda_nb+ / w_0)
+//                         + 1/2 delta_{i 0}(lambda_nb- / w_N - lambda_m / w_0) ].
+__device__ __forceinline__ void viscous_flux_cotangent(const double (*sLam)[nn], const double (*sLn)[4][nf],
+                                                       const double* sDw, const double* swinv, int m,
+                                                       const int ijk[3], const double invJ[3], double Fvb[3][4]) {
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int st = d == 0 ? 1 : (d == 1 ? n1 : nf);
+    const int id = ijk[d];
+    const int base = m - id * st;
+    const int a = d == 0 ? ijk[1] + n1 * ijk[2] : (d == 1 ? ijk[0] + n1 * ijk[2] : ijk[0] + n1 * ijk[1]);
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int l = 0; l < n1; ++l) {
+      const double c = sDw[l * n1 + id];  // Dw transposed
+      const int k = base + l * st;
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc) s[cc] = fma(c, sLam[1 + cc][k], s[cc]);
+    }
+    if (id == N) {
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc)
+        s[cc] += 0.5 * (swinv[N] * sLam[1 + cc][m] - swinv[0] * sLn[2 * d + 1][cc][a]);
+    }
+    if (id == 0) {
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc)
+        s[cc] += 0.5 * (swinv[N] * sLn[2 * d][cc][a] - swinv[0] * sLam[1 + cc][m]);
+    }
+#pragma unroll
+    for (int cc = 0; cc < 4; ++cc) Fvb[d][cc] = invJ[d] * s[cc];
+  }
+}
+
+// Cotangent of the lifted gradient g[a][b] (b = u, v, w, theta) from the
+// viscous-flux cotangent: with taub_jd = Fvb_d[j] + u_j Fvb_d[E],
+//   gb[a][b] = mu (taub_ba + taub_ab) - 2/3 mu delta_ab sum_j taub_jj,  gb[a][3] = kappa Fvb_a[E].
+__device__ __forceinline__ void gradient_cotangent(const double Fvb[3][4], const double u[3], double mu,
+                                                   double kappa, double gb[3][4]) {
+  double tb[3][3];  // tb[j][d]
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) tb[j][d] = fma(u[j], Fvb[d][3], Fvb[d][j]);
+  const double tr = (2.0 / 3.0) * mu * (tb[0][0] + tb[1][1] + tb[2][2]);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+#pragma unroll
+    for (int b = 0; b < 3; ++b) gb[a][b] = mu * (tb[b][a] + tb[a][b]) - (a == b ? tr : 0.0);
+    gb[a][3] = kappa * Fvb[a][3];
+  }
+}
+
+// Neighbour lambda (components 1..4) on face item q into sLn.
+template <int D>
+__device__ __forceinline__ void neighbour_lambda(const VjpArgs& A, int e, int q, double (*sLn)[4][nf]) {
+  const int f = q / nf;
+  const int a = q - f * nf;
+  const int side = f & 1;
+  const double* Ln = A.Lbar + (size_t)A.nbr[6 * e + f] * 5 * nn;
+  const int nnb = face_node(D, side ? 0 : N, a);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) sLn[f][c][a] = Ln[(1 + c) * nn + nnb];
+}
+
+// Pass 1 of the viscous reverse: cotangent of each element's normal lifted
+// gradient at its own face nodes -> Gbf[e][f][c][a].
+template <int D>
+__device__ __forceinline__ void vjp_lift_face_node(const VjpArgs& A, int e, int q, const double (*sLam)[nn],
+                                                   const double (*sLn)[4][nf], const double (*sU)[nn],
+                                                   const double* sDw, const double* swinv) {
+  const int f = q / nf;
+  const int a = q - f * nf;
+  const int m = face_node(D, (f & 1) ? N : 0, a);
+  const int ijk[3] = {m % n1, (m / n1) % n1, m / nf};
+  double Fvb[3][4], gb[3][4];
+  viscous_flux_cotangent(sLam, sLn, sDw, swinv, m, ijk, A.invJ, Fvb);
+  const double u[3] = {sU[0][m], sU[1][m], sU[2][m]};
+  gradient_cotangent(Fvb, u, A.mu, A.kappa, gb);
+  double* out = A.Gbf + ((size_t)e * 6 + f) * 4 * nf;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) out[c * nf + a] = gb[D][c];
+}
+
+__global__ __launch_bounds__(NT) void k_vjp_lift(VjpArgs A) {
+  __shared__ double sB[NB_STAGE];
+  __shared__ double sLam[5][nn];
+  __shared__ double sU[3][nn];
+  __shared__ double sLn[6][4][nf];
+  const int e = element_of_block(blockIdx.x, A.chunk);
+  if (e >= A.nelem) return;
+  const int t = threadIdx.x;
+  for (int q = t; q < NB_STAGE; q += NT) sB[q] = A.basis[q];
+  if (t < nn) {
+    const double* Ue = A.U + (size_t)e * 5 * nn;
+    const double* Le = A.Lbar + (size_t)e * 5 * nn;
+    const double ir = rcp64(Ue[t]);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) sU[j][t] = Ue[(1 + j) * nn + t] * ir;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) sLam[v][t] = Le[v * nn + t];
+  }
+  for (int q = t; q < 6 * nf; q += NT) {
+    if (q < 2 * nf) neighbour_lambda<0>(A, e, q, sLn);
+    else if (q < 4 * nf) neighbour_lambda<1>(A, e, q, sLn);
+    else neighbour_lambda<2>(A, e, q, sLn);
+  }
+  __syncthreads();
+  for (int q = t; q < 6 * nf; q += NT) {
+    if (q < 2 * nf) vjp_lift_face_node<0>(A, e, q, sLam, sLn, sU, sB + BL.Dw(), sB + BL.winv());
+    else if (q < 4 * nf) vjp_lift_face_node<1>(A, e, q, sLam, sLn, sU, sB + BL.Dw(), sB + BL.winv());
+    else vjp_lift_face_node<2>(A, e, q, sLam, sLn, sU, sB + BL.Dw(), sB + BL.winv());
+  }
+}
+
+// Interface part of face item q: cotangent of the element's own face state,
+// (d f*/d U_own)^T fbar with fbar = -(2/dx_d)(lambda_- / w_N - lambda_+ / w_0),
+// by five dual-number evaluations; plus, for Navier-Stokes, q* (forward
+// gradient), the neighbour's lambda and its normal-gradient cotangent.
+template <int VF, bool NS, int D>
+__device__ __forceinline__ void vjp_face_item(const VjpArgs& A, int e, int q, const double* swinv,
+                                              double (*sSF)[5][nf], double (*sQ)[4][nf], double (*sLn)[4][nf],
+                                              double (*sGn)[4][nf]) {
+  const int f = q / nf;
+  const int a = q - f * nf;
+  const int side = f & 1;  // 1: own element is the minus side of this face
+  const int nb = A.nbr[6 * e + f];
+  const double* Ue = A.U + (size_t)e * 5 * nn;
+  const double* Un = A.U + (size_t)nb * 5 * nn;
+  const double* Le = A.Lbar + (size_t)e * 5 * nn;
+  const double* Ln = A.Lbar + (size_t)nb * 5 * nn;
+  const int nown = face_node(D, side ? N : 0, a);
+  const int nnb = face_node(D, side ? 0 : N, a);
+  double L[5], R[5], fb[5];
+  const double cm = -A.invJ[D] * swinv[N], cp = A.invJ[D] * swinv[0];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    const double xo = Ue[v * nn + nown], xn = Un[v * nn + nnb];
+    L[v] = side ? xo : xn;
+    R[v] = side ? xn : xo;
+    const double lo = Le[v * nn + nown], ln = Ln[v * nn + nnb];
+    fb[v] = side ? fma(cm, lo, cp * ln) : fma(cm, ln, cp * lo);
+  }
+#pragma unroll 1
+  for (int k = 0; k < 5; ++k) {
+    Dl Ld[5], Rd[5], fd[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      Ld[v] = {L[v], (side && v == k) ? 1.0 : 0.0};
+      Rd[v] = {R[v], (!side && v == k) ? 1.0 : 0.0};
+    }
+    riemann_generic<VF, D, Dl>(A.sf, Ld, Rd, A.gamma, fd);
+    double s = 0.0;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) s = fma(fb[v], fd[v].d, s);
+    sSF[f][k][a] = s;
+  }
+  if (NS) {
+    const double gm1 = A.gamma - 1.0;
+    const Ref ref{0.0, 0.0, 0.0};
+    double qs[4];
+    interface_q<D, double, false>(state64<D>(L, gm1), state64<D>(R, gm1), ref, qs);
+    const double* Gn = A.Gbf + ((size_t)nb * 6 + (f ^ 1)) * 4 * nf;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      sQ[f][c][a] = qs[c];
+      sLn[f][c][a] = Ln[(1 + c) * nn + nnb];
+      sGn[f][c][a] = Gn[c * nf + a];
+    }
+  }
+}
+
+// Hand-derived reverse mode of the two-point volume flux with respect to its
+// first argument, in primitive variables (rho, u, p, x), for the flux
+// cotangent w (unrotated components).  x = h (PI, STD) or e (KG).
+template <int VF, int D>
+__device__ __forceinline__ void twopoint_vjp(const double me[7], double rl, const double ul[3], double pl,
+                                             double xl, const double w[5], double pb[6]) {
+  if (VF == VF_STD) {
+    // d1 F# = (1/2) dF(a)/da; F = (rho u_D, rho u_D u + p e_D, rho h u_D)
+    const double r = me[0], uD = me[1 + D];
+    const double s = w[0] + w[1] * me[1] + w[2] * me[2] + w[3] * me[3] + w[4] * me[5];
+    pb[0] += 0.5 * uD * s;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) pb[1 + j] += 0.5 * w[1 + j] * r * uD;
+    pb[1 + D] += 0.5 * r * s;
+    pb[4] += 0.5 * w[1 + D];
+    pb[5] += 0.5 * w[4] * r * uD;
+    return;
+  }
+  const double rm = 0.5 * (me[0] + rl);
+  const double um[3] = {0.5 * (me[1] + ul[0]), 0.5 * (me[2] + ul[1]), 0.5 * (me[3] + ul[2])};
+  const double xm = 0.5 * (me[5] + xl);
+  const double fr = rm * um[D];
+  double wr = w[0] + w[1] * um[0] + w[2] * um[1] + w[3] * um[2] + w[4] * xm;  // total cotangent of f_rho
+  pb[0] += 0.5 * wr * um[D];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) pb[1 + j] += 0.5 * w[1 + j] * fr;
+  pb[1 + D] += 0.5 * wr * rm;
+  pb[4] += 0.5 * w[1 + D];
+  pb[5] += 0.5 * w[4] * fr;
+  if (VF == VF_KG) {  // + p_m u_m,D in the energy flux
+    const double pm = 0.5 * (me[4] + pl);
+    pb[4] += 0.5 * w[4] * um[D];
+    pb[1 + D] += 0.5 * w[4] * pm;
+  }
+}
+
+template <int VF, int D>
+__device__ __forceinline__ void volume_vjp_dir(const double (*sP)[nn], const double (*sLam)[nn], const double* sDhat,
+                                               int n, int id, const double me[7], const double lam[5], double invJ,
+                                               double pb[6]) {
+  constexpr int st = D == 0 ? 1 : (D == 1 ? n1 : nf);
+  const int base = n - id * st;
+#pragma unroll
+  for (int k = 1; k <= kPartners; ++k) {
+    const int l = partner(id, k);
+    const int m = base + l * st;
+    const double c1 = -invJ * sDhat[id * n1 + l], c2 = -invJ * sDhat[l * n1 + id];
+    double w[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) w[v] = fma(c1, lam[v], c2 * sLam[v][m]);
+    const double ul[3] = {sP[1][m], sP[2][m], sP[3][m]};
+    twopoint_vjp<VF, D>(me, sP[0][m], ul, sP[4][m], sP[5][m], w, pb);
+  }
+}
+
+// Main reverse kernel.  Writes U_bar (or U_acc + U_bar when A.Uacc is set).
+template <int VF, int EQ>
+__global__ __launch_bounds__(NT) void k_vjp(VjpArgs A) {
+  constexpr bool NS = (EQ == 1);
+  __shared__ double sB[NB_STAGE];
+  __shared__ double sP[7][nn];
+  __shared__ double sLam[5][nn];
+  __shared__ double sSF[6][5][nf];
+  __shared__ double sQ[NS ? 6 : 1][4][nf];
+  __shared__ double sLn[NS ? 6 : 1][4][nf];
+  __shared__ double sGn[NS ? 6 : 1][4][nf];
+  const int e = element_of_block(blockIdx.x, A.chunk);
+  if (e >= A.nelem) return;
+  const int t = threadIdx.x;
+  const double gm1 = A.gamma - 1.0;
+  for (int q = t; q < NB_STAGE; q += NT) sB[q] = A.basis[q];
+  const double* sDhat = sB + BL.Dhat();
+  const double* sDw = sB + BL.Dw();
+  const double* swinv = sB + BL.winv();
+  const Ref ref{0.0, 0.0, 0.0};
+  double u[5], me[7], lam[5];
+  int ijk[3] = {0, 0, 0};
+  if (t < nn) {
+    const double* Ue = A.U + (size_t)e * 5 * nn;
+    const double* Le = A.Lbar + (size_t)e * 5 * nn;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      u[v] = Ue[v * nn + t];
+      lam[v] = Le[v * nn + t];
+      sLam[v][t] = lam[v];
+    }
+    primitives<VF, double, false>(u, gm1, ref, me);
+#pragma unroll
+    for (int k = 0; k < 7; ++k) sP[k][t] = me[k];
+    ijk[0] = t % n1;
+    ijk[1] = (t / n1) % n1;
+    ijk[2] = t / nf;
+  }
+  for (int q = t; q < 6 * nf; q += NT) {
+    if (q < 2 * nf) vjp_face_item<VF, NS, 0>(A, e, q, swinv, sSF, sQ, sLn, sGn);
+    else if (q < 4 * nf) vjp_face_item<VF, NS, 1>(A, e, q, swinv, sSF, sQ, sLn, sGn);
+    else vjp_face_item<VF, NS, 2>(A, e, q, swinv, sSF, sQ, sLn, sGn);
+  }
+  __syncthreads();
+
+  // primitive cotangents: rho, u, v, w, p, x (= h or e); theta added below
+  double pb[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double thb = 0.0;
+  double gb[3][4];
+  if (t < nn) {
+    volume_vjp_dir<VF, 0>(sP, sLam, sDhat, t, ijk[0], me, lam, A.invJ[0], pb);
+    volume_vjp_dir<VF, 1>(sP, sLam, sDhat, t, ijk[1], me, lam, A.invJ[1], pb);
+    volume_vjp_dir<VF, 2>(sP, sLam, sDhat, t, ijk[2], me, lam, A.invJ[2], pb);
+    if (NS) {
+      double Fvb[3][4], g[3][4];
+      viscous_flux_cotangent(sLam, sLn, sDw, swinv, t, ijk, A.invJ, Fvb);
+      lifted_gradient<double>(sP, sQ, sDw, swinv, t, ijk, A.invJ, g);
+      // u enters the energy flux u . tau_d
+      const double div = g[0][0] + g[1][1] + g[2][2];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        double s = 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          const double tau = A.mu * (g[d][j] + g[j][d]) - (j == d ? (2.0 / 3.0) * A.mu * div : 0.0);
+          s = fma(tau, Fvb[d][3], s);
+        }
+        pb[1 + j] += s;
+      }
+      const double uu[3] = {me[1], me[2], me[3]};
+      gradient_cotangent(Fvb, uu, A.mu, A.kappa, gb);
+    }
+  }
+  if (NS) {
+    // q_bar = sum_d' (2/dx_d') [ Dw^T gb_d' along the d' line + interface terms ]
+    double (*sX)[nn] = sLam;  // lambda is no longer needed
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      __syncthreads();
+      if (t < nn) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sX[c][t] = gb[d][c];
+      }
+      __syncthreads();
+      if (t < nn) {
+        const int st = d == 0 ? 1 : (d == 1 ? n1 : nf);
+        const int id = ijk[d];
+        const int base = t - id * st;
+        const int a = d == 0 ? ijk[1] + n1 * ijk[2] : (d == 1 ? ijk[0] + n1 * ijk[2] : ijk[0] + n1 * ijk[1]);
+        double s[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int l = 0; l < n1; ++l) {
+          const double c = sDw[l * n1 + id];
+          const int k = base + l * st;
+#pragma unroll
+          for (int cc = 0; cc < 4; ++cc) s[cc] = fma(c, sX[cc][k], s[cc]);
+        }
+        if (id == N) {
+#pragma unroll
+          for (int cc = 0; cc < 4; ++cc) s[cc] += 0.5 * (swinv[N] * gb[d][cc] - swinv[0] * sGn[2 * d + 1][cc][a]);
+        }
+        if (id == 0) {
+#pragma unroll
+          for (int cc = 0; cc < 4; ++cc) s[cc] += 0.5 * (swinv[N] * sGn[2 * d][cc][a] - swinv[0] * gb[d][cc]);
+        }
+        pb[1] += A.invJ[d] * s[0];
+        pb[2] += A.invJ[d] * s[1];
+        pb[3] += A.invJ[d] * s[2];
+        thb += A.invJ[d] * s[3];
+      }
+    }
+  }
+  if (t < nn) {
+    // primitive cotangents -> conservative: u = m/rho, p = (g-1)(E - |m|^2/(2 rho)),
+    // x = h = (E + p)/rho (PI, STD) or e = E/rho (KG), theta = p/rho
+    const double ir = rcp64(u[0]);
+    double rb = pb[0], ub[3] = {pb[1], pb[2], pb[3]}, pbar = pb[4], Eb = 0.0;
+    if (VF == VF_KG) {
+      Eb += pb[5] * ir;
+      rb -= pb[5] * me[5] * ir;
+    } else {
+      Eb += pb[5] * ir;
+      pbar += pb[5] * ir;
+      rb -= pb[5] * me[5] * ir;
+    }
+    pbar += thb * ir;
+    rb -= thb * me[6] * ir;
+    const double q2 = me[1] * me[1] + me[2] * me[2] + me[3] * me[3];
+    Eb += gm1 * pbar;
+    rb += gm1 * pbar * 0.5 * q2;
+    double mb[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      mb[j] = -gm1 * pbar * me[1 + j] + ub[j] * ir;
+      rb -= ub[j] * me[1 + j] * ir;
+    }
+    double out[5] = {rb, mb[0], mb[1], mb[2], Eb};
+    // interface contributions of the faces containing this node
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int id = ijk[d];
+      const int a = d == 0 ? ijk[1] + n1 * ijk[2] : (d == 1 ? ijk[0] + n1 * ijk[2] : ijk[0] + n1 * ijk[1]);
+      if (id == N)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) out[v] += sSF[2 * d + 1][v][a];
+      if (id == 0)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) out[v] += sSF[2 * d][v][a];
+    }
+    const size_t o = (size_t)e * 5 * nn + t;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) A.Ubar[o + v * nn] = A.Uacc ? A.Uacc[o + v * nn] + out[v] : out[v];
+  }
+}
+
+__global__ void k_axpby(double* y, double a, const double* x, double b, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    y[i] = (a == 0.0 ? 0.0 : a * y[i]) + b * x[i];
+}
+
 // ---------------------------------------------------------------------------
 // Modal indicator -> clipped blending coefficient a1 per element (FP64).
 // q = rho p; qhat = (Vinv x Vinv x Vinv) q on orthonormal Legendre modes;
@@ -1159,6 +1684,34 @@ hipError_t launch_integrals(const ReduceArgs& R, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int VF>
+hipError_t launch_vjp_vf(const VjpArgs& A, int eq, hipStream_t s) {
+  const dim3 grid(8 * A.chunk), block(NT);
+  if (eq == 1) hipLaunchKernelGGL((k_vjp<VF, 1>), grid, block, 0, s, A);
+  else hipLaunchKernelGGL((k_vjp<VF, 0>), grid, block, 0, s, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_vjp(const VjpArgs& A, int eq, hipStream_t s) {
+  switch (A.vf) {
+    case VF_KG: return launch_vjp_vf<VF_KG>(A, eq, s);
+    case VF_PI: return launch_vjp_vf<VF_PI>(A, eq, s);
+    case VF_STD: return launch_vjp_vf<VF_STD>(A, eq, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_vjp_lift(const VjpArgs& A, hipStream_t s) {
+  hipLaunchKernelGGL(k_vjp_lift, dim3(8 * A.chunk), dim3(NT), 0, s, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpby(double* y, double a, const double* x, double b, size_t n, hipStream_t s) {
+  const size_t blocks = std::min<size_t>((n + 255) / 256, 16384);
+  hipLaunchKernelGGL(k_axpby, dim3((unsigned)blocks), dim3(256), 0, s, y, a, x, b, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_nonfinite(const ReduceArgs& R, hipStream_t s) {
   hipLaunchKernelGGL(k_nonfinite, dim3(RED_BLOCKS), dim3(NT), 0, s, R);
   return hipGetLastError();
@@ -1166,7 +1719,7 @@ hipError_t launch_nonfinite(const ReduceArgs& R, hipStream_t s) {
 
 const KernelTable kTable = {
     NT, launch_stage, launch_stage_mixed, launch_lift, launch_lift_mixed, launch_alpha1, launch_spread,
-    launch_max_rate, launch_integrals, launch_nonfinite, nullptr, nullptr,
+    launch_max_rate, launch_integrals, launch_nonfinite, launch_vjp, launch_vjp_lift, launch_axpby,
 };
 
 }  // namespace

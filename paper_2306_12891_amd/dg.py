@@ -29,8 +29,8 @@ FP64, MIXED = 0, 1
 
 EXPORTS = ["dg_default_options", "dg_init", "dg_set_options", "dg_get_options", "dg_set_stream",
            "dg_time_derivative", "rk_step", "dg_rk_steps", "dg_vjp", "rk_step_vjp", "dg_max_dt",
-           "dg_integrals", "dg_alpha", "dg_check_finite", "dg_set_profiling", "dg_profile_read", "dg_sizes",
-           "dg_finalize", "dg_last_error"]
+           "dg_integrals", "dg_alpha", "dg_check_finite", "dg_set_profiling", "dg_profile_read", "dg_node_weights",
+           "dg_sizes", "dg_finalize", "dg_last_error"]
 
 
 class DGError(RuntimeError):
@@ -79,6 +79,7 @@ def lib() -> ctypes.CDLL:
             "dg_check_finite": ([P, P], I),
             "dg_set_profiling": ([P, I], I),
             "dg_profile_read": ([P, P, P], I),
+            "dg_node_weights": ([P, P], I),
             "dg_sizes": ([P, P, P], I),
             "dg_finalize": ([P], I),
             "dg_last_error": ([P], ctypes.c_char_p),
@@ -233,12 +234,94 @@ class DG:
         self._check(lib().dg_set_profiling(self._ctx, 1 if on else 0))
 
     def profile_read(self):
-        """{kind: (total ms, launches)} for kinds 'stage', 'lift', 'indicator'."""
-        ms = (ctypes.c_double * 3)()
-        n = (ctypes.c_int64 * 3)()
+        """{kind: (total ms, launches)} for 'stage', 'lift', 'indicator', 'vjp', 'vjp_lift'."""
+        ms = (ctypes.c_double * 5)()
+        n = (ctypes.c_int64 * 5)()
         self._check(lib().dg_profile_read(self._ctx, ms, n))
-        return {k: (ms[i], n[i]) for i, k in enumerate(("stage", "lift", "indicator"))}
+        return {k: (ms[i], n[i]) for i, k in enumerate(("stage", "lift", "indicator", "vjp", "vjp_lift"))}
+
+    def node_weights(self, device=None) -> torch.Tensor:
+        """w_i w_j w_k J per node of an element, shape (N+1, N+1, N+1)."""
+        n1 = self.N + 1
+        w = (ctypes.c_double * (n1 ** 3))()
+        self._check(lib().dg_node_weights(self._ctx, w))
+        out = torch.tensor(list(w), dtype=torch.float64).reshape(n1, n1, n1)
+        return out.to(device) if device is not None else out
 
     def raw_call(self, name: str, *args) -> int:
         """Calls a C entry point with this context as first argument (error-path tests)."""
         return getattr(lib(), name)(self._ctx, *args)
+
+
+# ---------------------------------------------------------------------------
+# autograd: the operator and the Runge-Kutta step as differentiable functions
+# whose backward passes call the library's reverse-mode kernels.
+# ---------------------------------------------------------------------------
+class DGOperator(torch.autograd.Function):
+    """U_t = L(U); backward: U_bar = dg_vjp(U, U_t_bar)."""
+
+    @staticmethod
+    def forward(ctx, U, op):
+        ctx.op = op
+        ctx.save_for_backward(U)
+        return op.time_derivative(U.detach().contiguous())
+
+    @staticmethod
+    def backward(ctx, g):
+        (U,) = ctx.saved_tensors
+        return ctx.op.vjp(U.detach().contiguous(), g.contiguous()), None
+
+
+class RKStep(torch.autograd.Function):
+    """One LSERK4 step (out of place); backward: rk_step_vjp."""
+
+    @staticmethod
+    def forward(ctx, U, op, dt):
+        ctx.op, ctx.dt = op, float(dt)
+        ctx.save_for_backward(U)
+        V = U.detach().clone()
+        op.rk_step(V, dt)
+        return V
+
+    @staticmethod
+    def backward(ctx, g):
+        (U,) = ctx.saved_tensors
+        return ctx.op.rk_step_vjp(U.detach().contiguous(), ctx.dt, g.contiguous()), None, None
+
+
+class _Rollout(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, U0, op, dt, nsteps, every):
+        ctx.op, ctx.dt, ctx.nsteps, ctx.every = op, float(dt), int(nsteps), int(every)
+        U = U0.detach().clone()
+        ckpt = {0: U.clone()}
+        for s in range(nsteps):
+            op.rk_step(U, dt)
+            if (s + 1) % every == 0 and s + 1 < nsteps:
+                ckpt[s + 1] = U.clone()
+        ctx.ckpt = ckpt
+        return U
+
+    @staticmethod
+    def backward(ctx, g):
+        op, dt, every = ctx.op, ctx.dt, ctx.every
+        Ub = g.contiguous().clone()
+        for s0 in sorted(ctx.ckpt, reverse=True):
+            s1 = min(s0 + every, ctx.nsteps)
+            states = [ctx.ckpt[s0]]
+            U = ctx.ckpt[s0].clone()
+            for _ in range(s0, s1 - 1):
+                op.rk_step(U, dt)
+                states.append(U.clone())
+            for k in reversed(range(s1 - s0)):
+                op.rk_step_vjp(states[k], dt, Ub, out=Ub)
+        ctx.ckpt = None
+        return Ub, None, None, None, None
+
+
+def rollout(op: DG, U0: torch.Tensor, dt: float, nsteps: int, checkpoint_every: int = 20) -> torch.Tensor:
+    """nsteps LSERK4 steps from U0, differentiable with respect to U0: the
+    forward keeps the state every checkpoint_every steps and the backward
+    recomputes each segment from its checkpoint before running the reverse
+    steps (memory: checkpoints + one segment of states)."""
+    return _Rollout.apply(U0, op, dt, nsteps, checkpoint_every)
