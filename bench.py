@@ -68,6 +68,63 @@ def stage_bytes_per_step(nodes):
     return 720.0 * nodes
 
 
+def adjoint_leg(torch, dg, inputs, steps=200, every=20, n_dirs=8, eps=1e-6):
+    """Gradient of the volume-averaged kinetic energy after `steps` LSERK4
+    steps of the TGV (N = 5, 16^3 elements, symmetry-broken start) with respect
+    to the initial state, by the checkpointed reverse rollout; timed against
+    the forward rollout and checked against central differences."""
+    N, nelem, mu = 5, (16, 16, 16), 1.0 / 1600
+    op = dg.DG(nelem, N, gamma=1.4, mu=mu, equations=dg.NS, vol_flux=dg.PI, surf_flux=dg.ROE, Pr=0.72)
+    U0 = torch.from_numpy(inputs.tgv(N, nelem, symmetry_break=True)).to("cuda:0")
+    W = op.node_weights("cuda:0")
+    vol = (2 * math.pi) ** 3
+    dt = op.max_dt(U0, 0.5)
+
+    def ke(U):
+        m = U[:, 1:4]
+        return torch.sum(W * 0.5 * torch.sum(m * m, 1) / U[:, 0]) / vol
+
+    def forward(U):
+        V = U.clone()
+        op.rk_steps(V, dt, steps)
+        return ke(V).item()
+
+    forward(U0)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    forward(U0)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    x = U0.clone().requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ke(dg.rollout(op, x, dt, steps, checkpoint_every=every)).backward()
+    torch.cuda.synchronize()
+    t_grad = time.perf_counter() - t0
+    g = x.grad.detach()
+    errs = []
+    for k in range(n_dirs):
+        v = torch.from_numpy(inputs.random_directions(tuple(U0.shape), k)).to("cuda:0")
+        fd = (forward(U0 + eps * v) - forward(U0 - eps * v)) / (2 * eps)
+        ad = torch.sum(g * v).item()
+        errs.append(abs(fd - ad) / abs(ad))
+    # single-operator timing: dg_vjp against dg_time_derivative
+    lam = torch.from_numpy(inputs.random_directions(tuple(U0.shape), 99)).to("cuda:0")
+    op.set_profiling(True)
+    for _ in range(10):
+        op.time_derivative(U0)
+        op.vjp(U0, lam)
+    prof = op.profile_read()
+    op.set_profiling(False)
+    t_op = prof["stage"][0] + prof["lift"][0]
+    t_vjp = prof["vjp"][0] + prof["vjp_lift"][0]
+    op.close()
+    return {"workload": "TGV Ma0.1 Re1600, N=5, 16^3 elems, PI+Roe, BR1; d KE(t_200)/d U_0, checkpoints every 20",
+            "steps": steps, "forward_s": t_fwd, "gradient_s": t_grad, "gradient_over_forward": t_grad / t_fwd,
+            "vjp_over_operator_kernel_time": t_vjp / t_op,
+            "fd_check": {"eps": eps, "directions": n_dirs, "max_rel_err": max(errs), "rel_errs": errs}}
+
+
 def cpu_baseline(name, spec, U0, dt, seconds_hint):
     from oracle import oracle as orc
     N, nelem, eq, vf, sf, mu, blend, _ = spec
@@ -93,6 +150,7 @@ def main():
     ap.add_argument("--workload", default="tgv_n5_32", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison run")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint (gradient) leg")
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized float64 device buffer 5 times (reference kernel for the "
@@ -186,6 +244,10 @@ def main():
             extra["mixed"]["kernel_ms_per_step"] = {k: round(v[0] / args.steps, 4) for k, v in profm.items() if v[1]}
         opm.close()
         del Um
+
+    if not args.no_adjoint:
+        from paper_2306_12891_amd import inputs
+        extra["adjoint"] = adjoint_leg(torch, dg, inputs)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -31,7 +31,8 @@ def _run(cmd, verbose):
     return r.stdout
 
 
-def build(verbose: bool = False, jobs: int | None = None, out: str = OUT, defines=(), build_dir: str = BUILD) -> str:
+def build(verbose: bool = False, jobs: int | None = None, out: str = OUT, defines=(), build_dir: str = BUILD,
+          kernel_source: str = os.path.join(HERE, "dg_kernels.hip")) -> str:
     """Compiles and links the library; defines are extra -D options (tuning)."""
     os.makedirs(build_dir, exist_ok=True)
     extra = [f"-D{d}" for d in defines]
@@ -39,7 +40,7 @@ def build(verbose: bool = False, jobs: int | None = None, out: str = OUT, define
     cmds = []
     for n in DEGREES:
         obj = os.path.join(build_dir, f"dg_kernels_N{n}.o")
-        cmds.append([HIPCC, *FLAGS, *extra, f"-DDG_N={n}", "-c", os.path.join(HERE, "dg_kernels.hip"), "-o", obj])
+        cmds.append([HIPCC, *FLAGS, *extra, f"-DDG_N={n}", "-c", kernel_source, "-o", obj])
     host_obj = os.path.join(build_dir, "dg_host.o")
     cmds.append([HIPCC, *FLAGS, *extra, "-x", "hip", "-c", os.path.join(HERE, "dg_host.cpp"), "-o", host_obj])
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:

@@ -577,61 +577,90 @@ __device__ __forceinline__ void prim_to_cons(const double w[5], double gm1, doub
   U[4] = w[4] / gm1 + 0.5 * w[0] * (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]);
 }
 
-// Own and neighbour states of face item q (face f = q / nf, D = f / 2) in
-// canonical order: L = minus side, R = plus side.
-template <int D>
-__device__ __forceinline__ void face_states(const StageArgs& A, int e, const double* Ue, int q, double gm1,
-                                            State64& sL, State64& sR, int& f, int& a) {
-  f = q / nf;
-  a = q - f * nf;
-  const int side = f & 1;
-  const double* Un = A.U + (size_t)A.nbr[6 * e + f] * 5 * nn;
-  const int nown = face_node(D, side ? N : 0, a);
-  const int nnb = face_node(D, side ? 0 : N, a);
-  double L[5], R[5];
+// Geometry of face item q: face f (0:-x 1:+x 2:-y 3:+y 4:-z 5:+z), normal
+// direction d, face-local index a, the own and the neighbour's volume node on
+// the face.  One code path serves all directions (no branch divergence): the
+// direction only enters address arithmetic.
+struct FaceItem {
+  int f, a, d, side, nb, nown, nnb, k1, k2;  // k1, k2: tangential momentum components
+};
+
+__device__ __forceinline__ FaceItem face_item_geometry(const int32_t* nbr, int e, int q) {
+  FaceItem it;
+  it.f = q / nf;
+  it.a = q - it.f * nf;
+  it.d = it.f >> 1;
+  it.side = it.f & 1;
+  it.nb = nbr[6 * e + it.f];
+  const int t1 = it.a % n1, t2 = it.a / n1;
+  const int sn = it.d == 0 ? 1 : (it.d == 1 ? n1 : nf);
+  const int s1 = it.d == 0 ? n1 : 1;
+  const int s2 = it.d == 2 ? n1 : nf;
+  const int tang = t1 * s1 + t2 * s2;
+  it.nown = (it.side ? N : 0) * sn + tang;
+  it.nnb = (it.side ? 0 : N) * sn + tang;
+  it.k1 = it.d == 2 ? 1 : it.d + 2;  // 1 + (d+1) % 3
+  it.k2 = it.d == 0 ? 3 : it.d;      // 1 + (d+2) % 3
+  return it;
+}
+
+// Conservative state of node n with the momentum rotated to (normal, t1, t2).
+__device__ __forceinline__ void load_rotated(const double* Ux, int n, const FaceItem& it, double X[5]) {
+  X[0] = Ux[n];
+  X[1] = Ux[(1 + it.d) * nn + n];
+  X[2] = Ux[it.k1 * nn + n];
+  X[3] = Ux[it.k2 * nn + n];
+  X[4] = Ux[4 * nn + n];
+}
+
+// Minus (L) and plus (R) states of the face item, rotated.
+__device__ __forceinline__ void face_states(const double* U, int e, const FaceItem& it, double gm1, State64& sL,
+                                            State64& sR) {
+  double xo[5], xn[5], L[5], R[5];
+  load_rotated(U + (size_t)e * 5 * nn, it.nown, it, xo);
+  load_rotated(U + (size_t)it.nb * 5 * nn, it.nnb, it, xn);
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
-    const double xo = Ue[v * nn + nown];
-    const double xn = Un[v * nn + nnb];
-    L[v] = side ? xo : xn;
-    R[v] = side ? xn : xo;
+    L[v] = it.side ? xo[v] : xn[v];
+    R[v] = it.side ? xn[v] : xo[v];
   }
-  sL = state64<D>(L, gm1);
-  sR = state64<D>(R, gm1);
+  sL = state64<0>(L, gm1);
+  sR = state64<0>(R, gm1);
 }
 
-// Interface values of face item q into LDS: advective f* and, for
-// Navier-Stokes, q* = (q- + q+)/2.
-template <int VF, bool NS, int D, class R, bool MX>
-__device__ __forceinline__ void face_item(const StageArgs& A, int e, const double* Ue, int q, const Ref& ref,
-                                          R (*sF)[5][nf], R (*sQ)[4][nf]) {
-  const double gm1 = A.gamma - 1.0;
-  State64 sL, sR;
-  int f, a;
-  face_states<D>(A, e, Ue, q, gm1, sL, sR, f, a);
-  const Jumps<R> J = jumps<R, MX>(sL, sR, A.gamma, ref, A.sf);
-  R g[5], fs[5];
-  riemann_rot<VF, R>(A.sf, to_rot<R, MX>(sL, ref), to_rot<R, MX>(sR, ref), J, (R)A.gamma, g);
-  unrotate<D, R>(g, fs);
+template <class R>
+__device__ __forceinline__ void store_q(const FaceItem& it, const R qs[4], R (*sQ)[4][nf]) {
+  sQ[it.f][it.d][it.a] = qs[0];
+  sQ[it.f][it.k1 - 1][it.a] = qs[1];
+  sQ[it.f][it.k2 - 1][it.a] = qs[2];
+  sQ[it.f][3][it.a] = qs[3];
+}
+
+// Interface values of face item q into LDS: advective f*, and for
+// Navier-Stokes q* = (q- + q+)/2 and the neighbour's normal viscous flux.
+template <int VF, bool NS, class R, bool MX>
+__device__ __forceinline__ void face_item(const StageArgs& A, int e, int q, const Ref& ref, R (*sF)[5][nf],
+                                          R (*sQ)[4][nf], R (*sFn)[4][nf]) {
+  const FaceItem it = face_item_geometry(A.nbr, e, q);
+  if (NS) {  // issue the neighbour's viscous-flux loads first
+    const R* Fn = reinterpret_cast<const R*>(A.Fvf) + ((size_t)it.nb * 6 + (it.f ^ 1)) * 4 * nf;
 #pragma unroll
-  for (int v = 0; v < 5; ++v) sF[f][v][a] = fs[v];
+    for (int c = 0; c < 4; ++c) sFn[it.f][c][it.a] = Fn[c * nf + it.a];
+  }
+  State64 sL, sR;
+  face_states(A.U, e, it, A.gamma - 1.0, sL, sR);
+  const Jumps<R> J = jumps<R, MX>(sL, sR, A.gamma, ref, A.sf);
+  R g[5];
+  riemann_rot<VF, R>(A.sf, to_rot<R, MX>(sL, ref), to_rot<R, MX>(sR, ref), J, (R)A.gamma, g);
+  sF[it.f][0][it.a] = g[0];
+  sF[it.f][1 + it.d][it.a] = g[1];
+  sF[it.f][it.k1][it.a] = g[2];
+  sF[it.f][it.k2][it.a] = g[3];
+  sF[it.f][4][it.a] = g[4];
   if (NS) {
     R qs[4];
-    interface_q<D, R, MX>(sL, sR, ref, qs);
-#pragma unroll
-    for (int c = 0; c < 4; ++c) sQ[f][c][a] = qs[c];
-  }
-}
-
-// Face items 0 .. 6 nf - 1 spread over the workgroup; items of one direction
-// run a direction-specialised code path.
-template <int VF, bool NS, class R, bool MX>
-__device__ __forceinline__ void all_face_items(const StageArgs& A, int e, const double* Ue, int t, const Ref& ref,
-                                               R (*sF)[5][nf], R (*sQ)[4][nf]) {
-  for (int q = t; q < 6 * nf; q += NT) {
-    if (q < 2 * nf) face_item<VF, NS, 0, R, MX>(A, e, Ue, q, ref, sF, sQ);
-    else if (q < 4 * nf) face_item<VF, NS, 1, R, MX>(A, e, Ue, q, ref, sF, sQ);
-    else face_item<VF, NS, 2, R, MX>(A, e, Ue, q, ref, sF, sQ);
+    interface_q<0, R, MX>(sL, sR, ref, qs);
+    store_q(it, qs, sQ);
   }
 }
 
@@ -654,6 +683,7 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
   __shared__ R sP[7][nn];
   __shared__ R sF[6][5][nf];
   __shared__ R sQ[NS ? 6 : 1][4][nf];
+  __shared__ R sFn[NS ? 6 : 1][4][nf];
   __shared__ double sX[BLEND ? 5 : 1][BLEND ? nn : 1];
   __shared__ double sB64[BLEND ? NB_STAGE : 1];
 
@@ -686,7 +716,7 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
     ijk[1] = (t / n1) % n1;
     ijk[2] = t / nf;
   }
-  all_face_items<VF, NS, R, MX>(A, e, Ue, t, ref, sF, sQ);
+  for (int q = t; q < 6 * nf; q += NT) face_item<VF, NS, R, MX>(A, e, q, ref, sF, sQ, sFn);
   __syncthreads();
 
   R acc[5] = {0, 0, 0, 0, 0};
@@ -774,7 +804,6 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
 
   if (NS) {
     // viscous divergence, one direction at a time through LDS (reuses sP)
-    const R* Fvf = reinterpret_cast<const R*>(A.Fvf);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       __syncthreads();
@@ -800,23 +829,19 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
         }
         const int a = d == 0 ? ijk[1] + n1 * ijk[2] : (d == 1 ? ijk[0] + n1 * ijk[2] : ijk[0] + n1 * ijk[1]);
         const R h2 = (R)0.5;
-        if (id == N) {
-          const int nb = A.nbr[6 * e + 2 * d + 1];
-          const R* Fn = Fvf + ((size_t)nb * 6 + 2 * d) * 4 * nf;
+        if (id == N) {  // neighbour across the + face (its normal viscous flux in sFn)
           const R wN = swinv[N];
-          s0 = fmaR(wN, h2 * (Fv[d][0] + Fn[0 * nf + a]), s0);
-          s1 = fmaR(wN, h2 * (Fv[d][1] + Fn[1 * nf + a]), s1);
-          s2 = fmaR(wN, h2 * (Fv[d][2] + Fn[2 * nf + a]), s2);
-          s3 = fmaR(wN, h2 * (Fv[d][3] + Fn[3 * nf + a]), s3);
+          s0 = fmaR(wN, h2 * (Fv[d][0] + sFn[2 * d + 1][0][a]), s0);
+          s1 = fmaR(wN, h2 * (Fv[d][1] + sFn[2 * d + 1][1][a]), s1);
+          s2 = fmaR(wN, h2 * (Fv[d][2] + sFn[2 * d + 1][2][a]), s2);
+          s3 = fmaR(wN, h2 * (Fv[d][3] + sFn[2 * d + 1][3][a]), s3);
         }
         if (id == 0) {
-          const int nb = A.nbr[6 * e + 2 * d];
-          const R* Fn = Fvf + ((size_t)nb * 6 + 2 * d + 1) * 4 * nf;
           const R w0 = swinv[0];
-          s0 = fmaR(-w0, h2 * (Fv[d][0] + Fn[0 * nf + a]), s0);
-          s1 = fmaR(-w0, h2 * (Fv[d][1] + Fn[1 * nf + a]), s1);
-          s2 = fmaR(-w0, h2 * (Fv[d][2] + Fn[2 * nf + a]), s2);
-          s3 = fmaR(-w0, h2 * (Fv[d][3] + Fn[3 * nf + a]), s3);
+          s0 = fmaR(-w0, h2 * (Fv[d][0] + sFn[2 * d][0][a]), s0);
+          s1 = fmaR(-w0, h2 * (Fv[d][1] + sFn[2 * d][1][a]), s1);
+          s2 = fmaR(-w0, h2 * (Fv[d][2] + sFn[2 * d][2][a]), s2);
+          s3 = fmaR(-w0, h2 * (Fv[d][3] + sFn[2 * d][3][a]), s3);
         }
         acc[1] = fmaR(invJ[d], s0, acc[1]);
         acc[2] = fmaR(invJ[d], s1, acc[2]);
@@ -851,32 +876,32 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
 // BR1 lifting pass (Navier-Stokes): normal viscous flux at the element's own
 // face nodes -> Fvf[e][f][c][a] (type R), read by the neighbours' stage kernels.
 // ---------------------------------------------------------------------------
-template <int D, class R, bool MX>
-__device__ __forceinline__ void lift_face_q(const StageArgs& A, int e, const double* Ue, int q, const Ref& ref,
-                                            R (*sQ)[4][nf]) {
+template <class R, bool MX>
+__device__ __forceinline__ void lift_face_q(const StageArgs& A, int e, int q, const Ref& ref, R (*sQ)[4][nf]) {
+  const FaceItem it = face_item_geometry(A.nbr, e, q);
   State64 sL, sR;
-  int f, a;
-  face_states<D>(A, e, Ue, q, A.gamma - 1.0, sL, sR, f, a);
+  face_states(A.U, e, it, A.gamma - 1.0, sL, sR);
   R qs[4];
-  interface_q<D, R, MX>(sL, sR, ref, qs);
-#pragma unroll
-  for (int c = 0; c < 4; ++c) sQ[f][c][a] = qs[c];
+  interface_q<0, R, MX>(sL, sR, ref, qs);
+  store_q(it, qs, sQ);
 }
 
-// Normal viscous flux at face node q of the element (face f = q / nf, D = f / 2).
-template <int D, class R>
+// Normal viscous flux at face node q of the element (face f = q / nf).
+template <class R>
 __device__ __forceinline__ void lift_face_node(const StageArgs& A, int e, int q, const R (*sP)[nn],
                                                const R (*sQ)[4][nf], const R* sB, const R invJ[3]) {
-  const int f = q / nf;
-  const int a = q - f * nf;
-  const int n = face_node(D, (f & 1) ? N : 0, a);
+  const FaceItem it = face_item_geometry(A.nbr, e, q);
+  const int n = it.nown;
   const int ijk[3] = {n % n1, (n / n1) % n1, n / nf};
-  R g[3][4], F[4];
+  R g[3][4], F0[4], F1[4], F2[4];
   lifted_gradient<R>(sP, sQ, sB + BL.Dw(), sB + BL.winv(), n, ijk, invJ, g);
-  viscous_flux<D, R>(g, sP[1][n], sP[2][n], sP[3][n], (R)A.mu, (R)A.kappa, F);
-  R* out = reinterpret_cast<R*>(A.Fvf) + ((size_t)e * 6 + f) * 4 * nf;
+  const R mu = (R)A.mu, kap = (R)A.kappa;
+  viscous_flux<0, R>(g, sP[1][n], sP[2][n], sP[3][n], mu, kap, F0);
+  viscous_flux<1, R>(g, sP[1][n], sP[2][n], sP[3][n], mu, kap, F1);
+  viscous_flux<2, R>(g, sP[1][n], sP[2][n], sP[3][n], mu, kap, F2);
+  R* out = reinterpret_cast<R*>(A.Fvf) + ((size_t)e * 6 + it.f) * 4 * nf;
 #pragma unroll
-  for (int c = 0; c < 4; ++c) out[c * nf + a] = F[c];
+  for (int c = 0; c < 4; ++c) out[c * nf + it.a] = it.d == 0 ? F0[c] : (it.d == 1 ? F1[c] : F2[c]);
 }
 
 template <class R>
@@ -902,17 +927,9 @@ __global__ __launch_bounds__(NT) void k_lift(StageArgs A) {
 #pragma unroll
     for (int k = 0; k < 7; ++k) sP[k][t] = P[k];
   }
-  for (int q = t; q < 6 * nf; q += NT) {
-    if (q < 2 * nf) lift_face_q<0, R, MX>(A, e, Ue, q, ref, sQ);
-    else if (q < 4 * nf) lift_face_q<1, R, MX>(A, e, Ue, q, ref, sQ);
-    else lift_face_q<2, R, MX>(A, e, Ue, q, ref, sQ);
-  }
+  for (int q = t; q < 6 * nf; q += NT) lift_face_q<R, MX>(A, e, q, ref, sQ);
   __syncthreads();
-  for (int q = t; q < 6 * nf; q += NT) {
-    if (q < 2 * nf) lift_face_node<0, R>(A, e, q, sP, sQ, sB, invJ);
-    else if (q < 4 * nf) lift_face_node<1, R>(A, e, q, sP, sQ, sB, invJ);
-    else lift_face_node<2, R>(A, e, q, sP, sQ, sB, invJ);
-  }
+  for (int q = t; q < 6 * nf; q += NT) lift_face_node<R>(A, e, q, sP, sQ, sB, invJ);
 }
 
 // ===========================================================================
