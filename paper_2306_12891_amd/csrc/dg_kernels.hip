@@ -60,6 +60,11 @@ constexpr int NB_STAGE = 2 * n1 * n1 + 3 * n1 + 1;  // Dhat, Dw, winv, xi, edge
 #ifndef DG_SKIP_DIAG
 #define DG_SKIP_DIAG 1
 #endif
+// Accumulate the BR1 gradient inside the volume loop (1) or in a separate
+// pass over the element (0).
+#ifndef DG_FUSED_GRAD
+#define DG_FUSED_GRAD 0
+#endif
 
 enum { VF_KG = 0, VF_PI = 1, VF_CH = 2, VF_STD = 3 };
 enum { SF_LLF = 0, SF_ROE = 1, SF_CENTRAL = 2 };
@@ -389,12 +394,25 @@ __device__ __forceinline__ int partner(int id, int k) {
 }
 constexpr int kPartners = DG_SKIP_DIAG ? N : N + 1;
 
-template <int VF, int D, class R>
+// With GRAD, also returns gs[c] = sum_{l != id} Dw_{id l} q_c(l) along the line
+// (q = u, v, w, theta): the off-diagonal part of the BR1 gradient, which
+// reuses the partner values the flux loop reads anyway.
+template <int VF, int D, class R, bool GRAD = false>
 __device__ __forceinline__ void volume_dir(const R (*sP)[nn], const R* sDhat, int n, int id, const R me[7], R invJ,
-                                           R gm1, R acc[5]) {
+                                           R gm1, R acc[5], const R* sDw = nullptr, R* gs = nullptr) {
   constexpr int st = D == 0 ? 1 : (D == 1 ? n1 : nf);
   const int base = n - id * st;
   const R* crow = sDhat + id * n1;
+  R g0 = 0, g1 = 0, g2 = 0, g3 = 0;
+  auto grad_acc = [&](int l, int m) {
+    if (GRAD) {
+      const R cw = sDw[id * n1 + l];
+      g0 = fmaR(cw, sP[1][m], g0);
+      g1 = fmaR(cw, sP[2][m], g1);
+      g2 = fmaR(cw, sP[3][m], g2);
+      g3 = fmaR(cw, sP[6][m], g3);
+    }
+  };
   if (VF == VF_KG || VF == VF_PI) {
     // f_rho = fr4/4, f_m = fr4 us/8 + ps/2 e_D, f_E = fr4 xs/8 (+ ps und/4 for KG)
     // with sums s = a + b and fr4 = rho_s und_s.
@@ -404,6 +422,7 @@ __device__ __forceinline__ void volume_dir(const R (*sP)[nn], const R* sDhat, in
       const int l = partner(id, k);
       const int m = base + l * st;
       const R c = crow[l];
+      grad_acc(l, m);
       const R rs = me[0] + sP[0][m];
       const R us = me[1] + sP[1][m];
       const R vs = me[2] + sP[2][m];
@@ -436,6 +455,7 @@ __device__ __forceinline__ void volume_dir(const R (*sP)[nn], const R* sDhat, in
       const int l = partner(id, k);
       const int m = base + l * st;
       const R c = crow[l];
+      grad_acc(l, m);
       const R mB = sP[0][m] * sP[1 + D][m];
       s0 = fmaR(c, mA + mB, s0);
       s1 = fmaR(c, mA * me[1] + mB * sP[1][m], s1);
@@ -460,6 +480,7 @@ __device__ __forceinline__ void volume_dir(const R (*sP)[nn], const R* sDhat, in
       const int l = partner(id, k);
       const int m = base + l * st;
       const double c = crow[l];
+      grad_acc(l, m);
       RotState<double> b;
       b.r = sP[0][m]; b.un = sP[1 + D][m]; b.u1 = sP[1 + (D + 1) % 3][m]; b.u2 = sP[1 + (D + 2) % 3][m];
       b.p = sP[4][m];
@@ -472,6 +493,12 @@ __device__ __forceinline__ void volume_dir(const R (*sP)[nn], const R* sDhat, in
       s[4] = fma(c, f[4], s[4]);
     }
     for (int v = 0; v < 5; ++v) acc[v] -= invJ * (R)s[v];
+  }
+  if (GRAD) {
+    gs[0] = g0;
+    gs[1] = g1;
+    gs[2] = g2;
+    gs[3] = g3;
   }
 }
 
@@ -679,13 +706,23 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
   constexpr bool NS = (EQ == 1);
   constexpr bool MX = sizeof(R) == 4;
   static_assert(!(BLEND && MX), "the blended operator is FP64 only");
+  // LDS pool: primitives sP[7][nn], face fluxes sF[6][5][nf], and for
+  // Navier-Stokes the interface values sQ[6][4][nf] and the neighbours' normal
+  // viscous fluxes sFn[6][4][nf].  The twelve viscous-flux components of all
+  // nodes are later exchanged through sV[12][nn], which overlays sP, sF and sQ
+  // (all consumed by then) but not sFn.
+  constexpr int oF = 7 * nn, oQ = oF + 30 * nf, oFn = oQ + 24 * nf;
+  constexpr int POOL = NS ? oFn + 24 * nf : oQ;
+  static_assert(!NS || 12 * nn <= oFn, "viscous exchange must not overlay sFn");
+  __shared__ R sPool[POOL];
   __shared__ R sB[NB_STAGE];
-  __shared__ R sP[7][nn];
-  __shared__ R sF[6][5][nf];
-  __shared__ R sQ[NS ? 6 : 1][4][nf];
-  __shared__ R sFn[NS ? 6 : 1][4][nf];
   __shared__ double sX[BLEND ? 5 : 1][BLEND ? nn : 1];
   __shared__ double sB64[BLEND ? NB_STAGE : 1];
+  R (*sP)[nn] = reinterpret_cast<R (*)[nn]>(sPool);
+  R (*sF)[5][nf] = reinterpret_cast<R (*)[5][nf]>(sPool + oF);
+  R (*sQ)[4][nf] = reinterpret_cast<R (*)[4][nf]>(sPool + (NS ? oQ : 0));
+  R (*sFn)[4][nf] = reinterpret_cast<R (*)[4][nf]>(sPool + (NS ? oFn : 0));
+  R (*sV)[nn] = reinterpret_cast<R (*)[nn]>(sPool);
 
   const int e = element_of_block(blockIdx.x, A.chunk);
   if (e >= A.nelem) return;
@@ -722,9 +759,11 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
   R acc[5] = {0, 0, 0, 0, 0};
   R Fv[3][4];
   if (t < nn) {
-    volume_dir<VF, 0, R>(sP, sDhat, t, ijk[0], me, invJ[0], (R)gm1, acc);
-    volume_dir<VF, 1, R>(sP, sDhat, t, ijk[1], me, invJ[1], (R)gm1, acc);
-    volume_dir<VF, 2, R>(sP, sDhat, t, ijk[2], me, invJ[2], (R)gm1, acc);
+    constexpr bool FG = NS && DG_FUSED_GRAD;
+    R gs[3][4];
+    volume_dir<VF, 0, R, FG>(sP, sDhat, t, ijk[0], me, invJ[0], (R)gm1, acc, sDw, gs[0]);
+    volume_dir<VF, 1, R, FG>(sP, sDhat, t, ijk[1], me, invJ[1], (R)gm1, acc, sDw, gs[1]);
+    volume_dir<VF, 2, R, FG>(sP, sDhat, t, ijk[2], me, invJ[2], (R)gm1, acc, sDw, gs[2]);
     // advective surface terms
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -743,7 +782,25 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
     }
     if (NS) {
       R g[3][4];
-      lifted_gradient<R>(sP, sQ, sDw, swinv, t, ijk, invJ, g);
+      if (!FG) {
+        lifted_gradient<R>(sP, sQ, sDw, swinv, t, ijk, invJ, g);
+      } else {
+      // BR1 gradient: line sums from the volume loop + diagonal + interface values
+      const R qo[4] = {me[1], me[2], me[3], me[6]};
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int id = ijk[d];
+        const int a = d == 0 ? ijk[1] + n1 * ijk[2] : (d == 1 ? ijk[0] + n1 * ijk[2] : ijk[0] + n1 * ijk[1]);
+        const R cd = DG_SKIP_DIAG ? sDw[id * n1 + id] : (R)0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          R s = fmaR(cd, qo[c], gs[d][c]);
+          if (id == N) s = fmaR(swinv[N], sQ[2 * d + 1][c][a], s);
+          if (id == 0) s = fmaR(-swinv[0], sQ[2 * d][c][a], s);
+          g[d][c] = invJ[d] * s;
+        }
+      }
+      }
       const R mu = (R)A.mu, kap = (R)A.kappa;
       viscous_flux<0, R>(g, me[1], me[2], me[3], mu, kap, Fv[0]);
       viscous_flux<1, R>(g, me[1], me[2], me[3], mu, kap, Fv[1]);
@@ -803,16 +860,19 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
   }
 
   if (NS) {
-    // viscous divergence, one direction at a time through LDS (reuses sP)
+    // viscous divergence: all twelve flux components exchanged through LDS once
+    __syncthreads();
+    if (t < nn) {
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      __syncthreads();
-      if (t < nn) {
+      for (int d = 0; d < 3; ++d)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) sP[c][t] = Fv[d][c];
-      }
-      __syncthreads();
-      if (t < nn) {
+        for (int c = 0; c < 4; ++c) sV[4 * d + c][t] = Fv[d][c];
+    }
+    __syncthreads();
+    if (t < nn) {
+      const R h2 = (R)0.5;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
         const int st = d == 0 ? 1 : (d == 1 ? n1 : nf);
         const int id = ijk[d];
         const int base = t - id * st;
@@ -822,13 +882,12 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
         for (int l = 0; l < n1; ++l) {
           const int m = base + l * st;
           const R c = crow[l];
-          s0 = fmaR(c, sP[0][m], s0);
-          s1 = fmaR(c, sP[1][m], s1);
-          s2 = fmaR(c, sP[2][m], s2);
-          s3 = fmaR(c, sP[3][m], s3);
+          s0 = fmaR(c, sV[4 * d + 0][m], s0);
+          s1 = fmaR(c, sV[4 * d + 1][m], s1);
+          s2 = fmaR(c, sV[4 * d + 2][m], s2);
+          s3 = fmaR(c, sV[4 * d + 3][m], s3);
         }
         const int a = d == 0 ? ijk[1] + n1 * ijk[2] : (d == 1 ? ijk[0] + n1 * ijk[2] : ijk[0] + n1 * ijk[1]);
-        const R h2 = (R)0.5;
         if (id == N) {  // neighbour across the + face (its normal viscous flux in sFn)
           const R wN = swinv[N];
           s0 = fmaR(wN, h2 * (Fv[d][0] + sFn[2 * d + 1][0][a]), s0);
