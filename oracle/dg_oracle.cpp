@@ -971,6 +971,142 @@ static void dense_time_derivative(const Ctx& c, const double* U, double* Ut) {
       }
 }
 
+// ---------------------------------------------------------------------------
+// The same operator (no blending) evaluated only for a list of elements, for
+// spot checks of very large meshes.  Every quantity an output element needs is
+// recomputed locally (interface fluxes of its faces, the lifted gradients of
+// the element and of its six neighbours) with the same arithmetic, in the same
+// order, as the full-array passes above, so results are identical.
+// ---------------------------------------------------------------------------
+static void subset_time_derivative(const Ctx& c, const double* U, const int32_t* elems, int nsel, double* Ut_sel) {
+  const Basis& b = c.b;
+  const double g = c.s.gamma;
+  const int nn = c.nn, nf = c.nf, N = c.N;
+  // f* on the + face of element x in direction d at face index a
+  auto fplus = [&](int x, int d, int a, double f[5]) {
+    double L[5], R[5];
+    load_state(c, U, x, face_node(c, d, N, a), L);
+    load_state(c, U, c.nbr[6 * x + 2 * d + 1], face_node(c, d, 0, a), R);
+    surface_flux(c.s.surf_flux, c.s.vol_flux, d, g, L, R, f);
+  };
+  auto qnode = [&](int x, int n, double q[4]) {
+    double u[5];
+    load_state(c, U, x, n, u);
+    lifted(u, g, q);
+  };
+  // lifted gradient of element x: gr[(d*4 + k)*nn + n]
+  auto gradient = [&](int x, std::vector<double>& gr) {
+    gr.assign(12 * nn, 0.0);
+    std::vector<double> q(4 * nn);
+    for (int n = 0; n < nn; ++n) {
+      double qq[4];
+      qnode(x, n, qq);
+      for (int k = 0; k < 4; ++k) q[k * nn + n] = qq[k];
+    }
+    auto qstar_plus = [&](int y, int d, int k, int a) {
+      double qa[4], qb[4];
+      qnode(y, face_node(c, d, N, a), qa);
+      qnode(c.nbr[6 * y + 2 * d + 1], face_node(c, d, 0, a), qb);
+      return 0.5 * (qa[k] + qb[k]);
+    };
+    for (int n = 0; n < nn; ++n) {
+      int ijk[3];
+      coords(c, n, ijk);
+      for (int d = 0; d < 3; ++d) {
+        const int i = ijk[d];
+        const int a = face_index(c, ijk, d);
+        for (int k = 0; k < 4; ++k) {
+          double s = 0.0;
+          for (int l = 0; l <= N; ++l) s += b.D[i * c.n1 + l] * q[k * nn + node_along(c, ijk, d, l)];
+          if (i == N) s += (1.0 / b.w[N]) * (qstar_plus(x, d, k, a) - q[k * nn + n]);
+          if (i == 0) s -= (1.0 / b.w[0]) * (qstar_plus(c.nbr[6 * x + 2 * d], d, k, a) - q[k * nn + n]);
+          gr[(d * 4 + k) * nn + n] = c.invJ[d] * s;
+        }
+      }
+    }
+  };
+  auto fv_at = [&](int x, const std::vector<double>& gr, int n, int d, double F[5]) {
+    double u[5], G[3][4];
+    load_state(c, U, x, n, u);
+    for (int dd = 0; dd < 3; ++dd)
+      for (int k = 0; k < 4; ++k) G[dd][k] = gr[(dd * 4 + k) * nn + n];
+    viscous_flux(d, g, c.s.mu, c.s.Pr, u, G, F);
+  };
+#pragma omp parallel for schedule(dynamic)
+  for (int s = 0; s < nsel; ++s) {
+    const int e = elems[s];
+    double* Ut = Ut_sel + size_t(s) * 5 * nn;
+    // advective part
+    for (int n = 0; n < nn; ++n) {
+      int ijk[3];
+      coords(c, n, ijk);
+      double un[5];
+      load_state(c, U, e, n, un);
+      double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+      for (int d = 0; d < 3; ++d) {
+        const int i = ijk[d];
+        double sum[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int l = 0; l <= N; ++l) {
+          double ul[5], f[5];
+          load_state(c, U, e, node_along(c, ijk, d, l), ul);
+          two_point_flux(c.s.vol_flux, d, g, un, ul, f);
+          for (int v = 0; v < 5; ++v) sum[v] += b.Dhat[i * c.n1 + l] * f[v];
+        }
+        const int a = face_index(c, ijk, d);
+        if (i == N) {
+          double f[5];
+          fplus(e, d, a, f);
+          for (int v = 0; v < 5; ++v) sum[v] += (1.0 / b.w[N]) * f[v];
+        }
+        if (i == 0) {
+          double f[5];
+          fplus(c.nbr[6 * e + 2 * d], d, a, f);
+          for (int v = 0; v < 5; ++v) sum[v] -= (1.0 / b.w[0]) * f[v];
+        }
+        for (int v = 0; v < 5; ++v) acc[v] -= c.invJ[d] * sum[v];
+      }
+      for (int v = 0; v < 5; ++v) Ut[v * nn + n] = acc[v];
+    }
+    if (c.s.equations != EQ_NS) continue;
+    std::vector<double> gr_e, gr_nb[6];
+    gradient(e, gr_e);
+    for (int f = 0; f < 6; ++f) gradient(c.nbr[6 * e + f], gr_nb[f]);
+    for (int n = 0; n < nn; ++n) {
+      int ijk[3];
+      coords(c, n, ijk);
+      for (int d = 0; d < 3; ++d) {
+        const int i = ijk[d];
+        const int a = face_index(c, ijk, d);
+        double Fn[5];
+        fv_at(e, gr_e, n, d, Fn);
+        double Fl[5][16];  // Fv of the line along d (N + 1 <= 16)
+        for (int l = 0; l <= N; ++l) {
+          double F[5];
+          fv_at(e, gr_e, node_along(c, ijk, d, l), d, F);
+          for (int v = 0; v < 5; ++v) Fl[v][l] = F[v];
+        }
+        for (int v = 0; v < 5; ++v) {
+          double s2 = 0.0;
+          for (int l = 0; l <= N; ++l) s2 += b.D[i * c.n1 + l] * Fl[v][l];
+          if (i == N) {
+            double Fo[5];
+            fv_at(c.nbr[6 * e + 2 * d + 1], gr_nb[2 * d + 1], face_node(c, d, 0, a), d, Fo);
+            const double Fs = 0.5 * (Fn[v] + Fo[v]);
+            s2 += (1.0 / b.w[N]) * (Fs - Fn[v]);
+          }
+          if (i == 0) {
+            double Fo[5];
+            fv_at(c.nbr[6 * e + 2 * d], gr_nb[2 * d], face_node(c, d, N, a), d, Fo);
+            const double Fs = 0.5 * (Fo[v] + Fn[v]);
+            s2 -= (1.0 / b.w[0]) * (Fs - Fn[v]);
+          }
+          Ut[v * nn + n] += c.invJ[d] * s2;
+        }
+      }
+    }
+  }
+}
+
 static bool valid(const Setup* s) {
   if (!s) return false;
   if (s->N < 1 || s->N > 15) return false;
@@ -1041,6 +1177,16 @@ int or_time_derivative(const Setup* s, const double* U, double* Ut, const double
   if (!valid(s)) return -1;
   const Ctx c = make_ctx(*s);
   time_derivative(c, U, Ut, alpha_in, Ut_dg, Ut_fv, alpha_out);
+  return 0;
+}
+
+// Operator (no blending) for the elements elems[0..nsel-1] only: Ut_sel[s][5][nn].
+int or_time_derivative_elems(const Setup* s, const double* U, const int32_t* elems, int nsel, double* Ut_sel) {
+  if (!valid(s) || s->blending) return -1;
+  const Ctx c = make_ctx(*s);
+  for (int k = 0; k < nsel; ++k)
+    if (elems[k] < 0 || elems[k] >= c.nelem) return -1;
+  subset_time_derivative(c, U, elems, nsel, Ut_sel);
   return 0;
 }
 

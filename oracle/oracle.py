@@ -115,6 +115,7 @@ def lib() -> ctypes.CDLL:
             ("or_physical_flux", [P, ctypes.c_int, P, P], ctypes.c_int),
             ("or_time_derivative", [P, P, P, P, P, P, P], ctypes.c_int),
             ("or_dense_time_derivative", [P, P, P], ctypes.c_int),
+            ("or_time_derivative_elems", [P, P, P, ctypes.c_int, P], ctypes.c_int),
             ("or_alpha", [P, P, P, P, P], ctypes.c_int),
             ("or_threshold", [ctypes.c_int], ctypes.c_double),
             ("or_gradient", [P, P, P], ctypes.c_int),
@@ -200,6 +201,16 @@ def time_derivative(s: Setup, U, alpha=None, parts: bool = False):
         Udg = Ufv = al = None
     _check(lib().or_time_derivative(_ref(s), _p(U), _p(Ut), _p(a_in), _p(Udg), _p(Ufv), _p(al)))
     return (Ut, Udg, Ufv, al) if parts else Ut
+
+
+def time_derivative_elems(s: Setup, U, elems):
+    """U_t of the listed elements only (no blending): shape (len(elems), 5, n1, n1, n1)."""
+    U = _f64(U)
+    el = np.ascontiguousarray(elems, dtype=np.int32)
+    n1 = s.N + 1
+    out = np.zeros((len(el), 5, n1, n1, n1))
+    _check(lib().or_time_derivative_elems(_ref(s), _p(U), _p(el), len(el), _p(out)))
+    return out
 
 
 def dense_time_derivative(s: Setup, U):

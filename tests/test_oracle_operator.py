@@ -209,3 +209,16 @@ def test_dense_brute_force(orc, eq, vf, sf, nelem):
     ref = orc.dense_time_derivative(s, U)
     scale = np.max(np.abs(ref), axis=(0, 2, 3, 4))
     assert np.all(np.max(np.abs(Ut - ref), axis=(0, 2, 3, 4)) <= 1e-13 * scale)
+
+
+@pytest.mark.parametrize("eq,vf,sf", [(0, 0, 0), (1, 1, 1), (1, 0, 0)])
+def test_element_subset_equals_full_operator(orc, eq, vf, sf):
+    """The element-subset evaluation used for spot checks of large meshes gives
+    bitwise the same U_t as the full-array oracle."""
+    N, nelem = 3, (3, 3, 2)
+    s = orc.Setup(N=N, nelem=nelem, equations=eq, vol_flux=vf, surf_flux=sf, mu=3e-2)
+    U = I.random_smooth(N, nelem, seed=17, noise=0.02)
+    full = orc.time_derivative(s, U)
+    sel = [0, 4, 7, 17, 11]
+    part = orc.time_derivative_elems(s, U, sel)
+    assert np.array_equal(part, full[sel])
