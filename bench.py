@@ -62,6 +62,26 @@ def domain(name):
     return (0.0, 0.0, 0.0), (2 * math.pi,) * 3
 
 
+# HBM bytes per launch of the stage kernel measured with rocprofv3 --pmc
+# FETCH_SIZE and WRITE_SIZE (separate runs), each scaled by the plain-copy
+# calibration (FETCH x 2.000, WRITE x 1.000); see profiles/k_stage_*.md.  Valid
+# only for the kernel source they were taken on (sha256 prefix).
+MEASURED_TRAFFIC = {
+    "kernel_sha": "654c86e3c411f0dd",
+    "tgv_n5_32": {"bytes_per_launch": 1380.4e6, "fetch": 870.8e6, "write": 509.6e6},
+    "tgv_n7_64": {"bytes_per_launch": 26650.2e6, "fetch": 16986.5e6, "write": 9663.7e6},
+}
+
+
+def kernel_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("dg_kernels.hip", "dg_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_2306_12891_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def stage_bytes_per_step(nodes):
     """Algorithmic HBM bytes of the stage kernel over the five stages of one
     step: read U (40 B/node) and write U (40); the register G is written in
@@ -219,8 +239,11 @@ def main():
         ms_stage, n_stage = prof["stage"]
         avg_ms = ms_stage / max(n_stage, 1)
         A = stage_bytes_per_step(nodes) * args.steps / (ms_stage * 1e-3) / 1e9
+        traffic = None
+        if name in MEASURED_TRAFFIC and kernel_sha() == MEASURED_TRAFFIC["kernel_sha"]:
+            traffic = MEASURED_TRAFFIC[name]["bytes_per_launch"]
         roof = {"bound": "hbm", "achieved": round(A, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(A / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(A / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_unit": "bytes per launch",
                 "kernel": "k_stage (operator + LSERK4 stage)", "avg_launch_ms": round(avg_ms, 4),
                 "algorithmic_bytes_per_launch": stage_bytes_per_step(nodes) / 5}
         extra["kernel_ms_per_step"] = {k: round(v[0] / args.steps, 4) for k, v in prof.items() if v[1]}
