@@ -38,9 +38,17 @@ WORKLOADS = {
                           "Euler density wave, N=3, 4^3 elems, KG+LLF, LSERK4"),
     "freestream_euler_n7_64": (7, (64, 64, 64), 0, 0, 0, 0.0, 0,
                                "Euler freestream Ma0.5, N=7, 64^3 elems, KG+LLF, LSERK4"),
+    "freestream_ns_n7_64": (7, (64, 64, 64), 1, 1, 1, 1.0 / 1600, 0,
+                            "NS freestream Ma0.5, N=7, 64^3 elems, PI+Roe, BR1, LSERK4"),
     "sod_n5_64x8x8": (5, (64, 8, 8), 0, 0, 0, 0.0, 1,
                       "Euler Sod tube, N=5, 64x8x8 elems, KG+LLF, DG/FV blending (minmod), LSERK4"),
 }
+
+
+# Element counts of the freestream size sweep: 2^15 ... 2^21 elements, grown
+# one direction at a time (z, then y, then x) from 32^3.
+SWEEP_MESHES = [(32, 32, 32), (32, 32, 64), (32, 64, 64), (64, 64, 64), (64, 64, 128), (64, 128, 128),
+                (128, 128, 128)]
 
 
 def initial_state(name, N, nelem):
@@ -140,39 +148,149 @@ def adjoint_leg(torch, dg, inputs, steps=200, every=20, n_dirs=8, eps=1e-6):
     op.set_profiling(False)
     t_op = prof["stage"][0] + prof["lift"][0]
     t_vjp = prof["vjp"][0] + prof["vjp_lift"][0]
+    # one Runge-Kutta step against its reverse (which recomputes the stages)
+    V, Vb = U0.clone(), torch.empty_like(U0)
+
+    def wall_of(fn, reps=10):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    t_step = wall_of(lambda: op.rk_step(V, dt))
+    t_step_vjp = wall_of(lambda: op.rk_step_vjp(U0, dt, lam, out=Vb))
     op.close()
     return {"workload": "TGV Ma0.1 Re1600, N=5, 16^3 elems, PI+Roe, BR1; d KE(t_200)/d U_0, checkpoints every 20",
             "steps": steps, "forward_s": t_fwd, "gradient_s": t_grad, "gradient_over_forward": t_grad / t_fwd,
-            "vjp_over_operator_kernel_time": t_vjp / t_op,
+            "vjp_over_operator_kernel_time": t_vjp / t_op, "rk_step_vjp_over_rk_step": t_step_vjp / t_step,
             "fd_check": {"eps": eps, "directions": n_dirs, "max_rel_err": max(errs), "rel_errs": errs}}
 
 
 def cpu_baseline(name, spec, U0, dt, max_nodes=8_000_000):
     """The oracle timed on the host cores: one LSERK4 step of the workload; for
     meshes above max_nodes the same flow on a mesh with fewer elements per
-    direction (same N, same per-node work) so the sample stays near 10-30 s."""
+    direction (same N, same per-node work) so the sample stays near 10-30 s.
+    Also one core on an eighth of that sample (PID per core, for comparison
+    with the paper's per-core figures)."""
     from oracle import oracle as orc
-    from paper_2306_12891_amd import inputs
     N, nelem, eq, vf, sf, mu, blend, _ = spec
     lo, hi = domain(name)
     cores = len(os.sched_getaffinity(0))
-    orc.set_threads(cores)
     sample_elems = tuple(nelem)
     U = U0
     while int(np.prod(sample_elems)) * (N + 1) ** 3 > max_nodes:
         sample_elems = tuple(max(1, n // 2) for n in sample_elems)
-    if sample_elems != tuple(nelem):
+    if sample_elems != tuple(nelem) or U is None:
         U = initial_state(name, N, sample_elems)
-    s = orc.Setup(N=N, nelem=sample_elems, lo=lo, hi=hi, equations=eq, vol_flux=vf, surf_flux=sf, mu=mu,
-                  blending=blend, Pr=0.72)
+
+    def run(elems, U, threads):
+        orc.set_threads(threads)
+        s = orc.Setup(N=N, nelem=elems, lo=lo, hi=hi, equations=eq, vol_flux=vf, surf_flux=sf, mu=mu,
+                      blending=blend, Pr=0.72)
+        t0 = time.perf_counter()
+        orc.rk_steps(s, U, dt, 1)
+        return time.perf_counter() - t0
+
     nodes = U.shape[0] * (N + 1) ** 3
-    t0 = time.perf_counter()
-    orc.rk_steps(s, U, dt, 1)
-    wall = time.perf_counter() - t0
+    wall = run(sample_elems, U, cores)
+    one_elems = tuple(max(1, n // 2) for n in sample_elems)
+    U1 = initial_state(name, N, one_elems)
+    nodes1 = U1.shape[0] * (N + 1) ** 3
+    wall1 = run(one_elems, U1, 1)
+    orc.set_threads(cores)
     what = "full mesh" if sample_elems == tuple(nelem) else f"same flow on {sample_elems} elements"
     return {"value": nodes * 5 / wall, "unit": "DOF-stage/s", "cores": cores, "kind": "oracle",
             "sample": f"1 LSERK4 step (5 operator evaluations), {what}, {nodes} DOF, {wall:.1f} s wall",
-            "pid_us_per_core": wall * cores / (nodes * 5) * 1e6}
+            "pid_us_per_core": wall * cores / (nodes * 5) * 1e6,
+            "one_core": {"pid_us": wall1 / (nodes1 * 5) * 1e6,
+                         "sample": f"1 LSERK4 step on {one_elems} elements, {nodes1} DOF, {wall1:.1f} s wall"}}
+
+
+def device_freestream(torch, N, nelem, gamma=1.4, rho=1.0, u=0.5, p=None):
+    """Constant state rho = 1, u = (0.5, 0, 0), p = 1/gamma built directly in
+    device memory (the largest sweep meshes would need tens of GB of host RAM)."""
+    p = 1.0 / gamma if p is None else p
+    n1 = N + 1
+    U = torch.empty((int(np.prod(nelem)), 5, n1, n1, n1), dtype=torch.float64, device="cuda:0")
+    for v, val in enumerate((rho, rho * u, 0.0, 0.0, p / (gamma - 1.0) + 0.5 * rho * u * u)):
+        U[:, v].fill_(val)
+    return U
+
+
+def timed_rollouts(torch, op, U, dt, steps, warmup, repeats, profile):
+    """`warmup` untimed steps, then `repeats` blocks of exactly `steps` steps,
+    each bracketed by device synchronisation.  Per-kernel event times are
+    collected over the first block only."""
+    if warmup:
+        op.rk_steps(U, dt, warmup)
+    walls, prof = [], None
+    for r in range(repeats):
+        op.set_profiling(profile and r == 0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        op.rk_steps(U, dt, steps)
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
+        if profile and r == 0:
+            prof = op.profile_read()
+    op.set_profiling(False)
+    return walls, prof
+
+
+def repeat_stats(nodes, steps, walls):
+    vals = [nodes * 5 * steps / w for w in walls]
+    return {"n": len(vals), "mean": float(np.mean(vals)), "min": float(np.min(vals)), "max": float(np.max(vals))}
+
+
+def roofline(name, nodes, steps, prof):
+    ms_stage, n_stage = prof["stage"]
+    avg_ms = ms_stage / max(n_stage, 1)
+    A = stage_bytes_per_step(nodes) * steps / (ms_stage * 1e-3) / 1e9
+    traffic = None
+    if name in MEASURED_TRAFFIC and kernel_sha() == MEASURED_TRAFFIC["kernel_sha"]:
+        traffic = MEASURED_TRAFFIC[name]["bytes_per_launch"]
+    return {"bound": "hbm", "achieved": round(A, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(A / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_unit": "bytes per launch",
+            "kernel": "k_stage (operator + LSERK4 stage)", "avg_launch_ms": round(avg_ms, 4),
+            "algorithmic_bytes_per_launch": stage_bytes_per_step(nodes) / 5}
+
+
+def blended_fraction(torch, op, U0, dt, steps, every=50):
+    """Fraction of elements with alpha > 0, phi(t), along an untimed rollout."""
+    U = U0.clone()
+    out = []
+    for k in range(0, steps + 1, every):
+        if k:
+            op.rk_steps(U, dt, every)
+        a = op.alpha(U)
+        out.append({"step": k, "t": k * dt, "phi": float((a > 0).double().mean().item()),
+                    "alpha_max": float(a.max().item())})
+    return out
+
+
+def sweep(torch, dg, spec, steps, warmup, repeats):
+    """Freestream throughput over 2^15 ... 2^21 elements (N = 7)."""
+    N, _, eq, vf, sf, mu, blend, _ = spec
+    rows = []
+    for nelem in SWEEP_MESHES:
+        op = dg.DG(nelem, N, gamma=1.4, mu=mu, equations=eq, vol_flux=vf, surf_flux=sf, Pr=0.72)
+        U = device_freestream(torch, N, nelem)
+        nodes = U.shape[0] * (N + 1) ** 3
+        dt = op.max_dt(U, 0.5)
+        walls, prof = timed_rollouts(torch, op, U, dt, steps, warmup, repeats, True)
+        row = {"elements": list(nelem), "n_elems": int(np.prod(nelem)), "dof": nodes,
+               "value": nodes * 5 * steps / walls[0], "repeats": repeat_stats(nodes, steps, walls),
+               "stage_roofline_frac": roofline("", nodes, steps, prof)["frac"],
+               "finite_after_run": op.check_finite(U)}
+        rows.append(row)
+        print(json.dumps({"sweep_point": row}), file=sys.stderr, flush=True)
+        op.close()
+        del U
+        torch.cuda.empty_cache()
+    return rows
 
 
 def main():
@@ -180,7 +298,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="timed blocks of --steps steps; `value` is the first, the rest give mean/min/max")
     ap.add_argument("--workload", default="tgv_n5_32", choices=sorted(WORKLOADS))
+    ap.add_argument("--sweep", action="store_true",
+                    help="freestream workloads: also time 2^15 ... 2^21 elements")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison run")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint (gradient) leg")
@@ -204,6 +326,7 @@ def main():
         print(f"bench.py: this path runs on one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU element decomposition is a design only)", file=sys.stderr)
         sys.exit(2)
+    repeats = max(1, args.repeats)
 
     import torch
 
@@ -213,77 +336,65 @@ def main():
     spec = WORKLOADS[name]
     N, nelem, eq, vf, sf, mu, blend, desc = spec
     lo, hi = domain(name)
-    U0 = initial_state(name, N, nelem)
-    nodes = U0.shape[0] * (N + 1) ** 3
+    nodes = int(np.prod(nelem)) * (N + 1) ** 3
+    U0 = None if name.startswith("freestream") else initial_state(name, N, nelem)
     op = dg.DG(nelem, N, gamma=1.4, mu=mu, lo=lo, hi=hi, equations=eq, vol_flux=vf, surf_flux=sf,
                blending=blend, Pr=0.72)
-    U = torch.from_numpy(U0).to("cuda:0")
+    U_init = device_freestream(torch, N, nelem) if U0 is None else torch.from_numpy(U0).to("cuda:0")
+    U = U_init.clone()
     dt = op.max_dt(U, 0.5)
-    if args.warmup:
-        op.rk_steps(U, dt, args.warmup)
-    torch.cuda.synchronize()
-    op.set_profiling(not args.no_profile)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    op.rk_steps(U, dt, args.steps)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    prof = op.profile_read() if not args.no_profile else None
-    op.set_profiling(False)
+    walls, prof = timed_rollouts(torch, op, U, dt, args.steps, args.warmup, repeats, not args.no_profile)
+    wall = walls[0]
     finite = op.check_finite(U)
     value = nodes * 5 * args.steps / wall
 
     roof = None
-    extra = {}
+    extra = {"repeats": repeat_stats(nodes, args.steps, walls)}
     if prof:
-        ms_stage, n_stage = prof["stage"]
-        avg_ms = ms_stage / max(n_stage, 1)
-        A = stage_bytes_per_step(nodes) * args.steps / (ms_stage * 1e-3) / 1e9
-        traffic = None
-        if name in MEASURED_TRAFFIC and kernel_sha() == MEASURED_TRAFFIC["kernel_sha"]:
-            traffic = MEASURED_TRAFFIC[name]["bytes_per_launch"]
-        roof = {"bound": "hbm", "achieved": round(A, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(A / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_unit": "bytes per launch",
-                "kernel": "k_stage (operator + LSERK4 stage)", "avg_launch_ms": round(avg_ms, 4),
-                "algorithmic_bytes_per_launch": stage_bytes_per_step(nodes) / 5}
+        roof = roofline(name, nodes, args.steps, prof)
         extra["kernel_ms_per_step"] = {k: round(v[0] / args.steps, 4) for k, v in prof.items() if v[1]}
     path_bytes = 160.0 * nodes * 5 * args.steps
     extra["path_roofline_frac_160B"] = round(path_bytes / wall / 1e9 / HBM_PEAK_GBS, 4)
     extra["pid_gpu_us"] = 1e6 / value
     extra["finite_after_run"] = finite
+    if blend:
+        extra["blended_fraction"] = blended_fraction(torch, op, U_init, dt, args.warmup + args.steps * repeats)
 
     # Mixed-precision operator on the same workload: same initial state, same
     # warm-up and timed steps; error of the final state against the FP64 run.
     if not args.no_mixed and vf in (1, 3) and not blend:
         opm = dg.DG(nelem, N, gamma=1.4, mu=mu, lo=lo, hi=hi, equations=eq, vol_flux=vf, surf_flux=sf,
                     Pr=0.72, precision=dg.MIXED)
-        Um = torch.from_numpy(U0).to("cuda:0")
-        if args.warmup:
-            opm.rk_steps(Um, dt, args.warmup)
-        torch.cuda.synchronize()
-        opm.set_profiling(not args.no_profile)
-        t0 = time.perf_counter()
-        opm.rk_steps(Um, dt, args.steps)
-        torch.cuda.synchronize()
-        wall_m = time.perf_counter() - t0
-        profm = opm.profile_read() if not args.no_profile else None
+        Um = U_init.clone()
+        walls_m, profm = timed_rollouts(torch, opm, Um, dt, args.steps, args.warmup, repeats,
+                                        not args.no_profile)
+        wall_m = walls_m[0]
         diff = (Um - U).abs()
         scale = torch.maximum(U.abs().amax(dim=(0, 2, 3, 4)), U[:, 0].abs().amax())
         linf = (diff.amax(dim=(0, 2, 3, 4)) / scale).tolist()
         l2 = (diff.pow(2).mean(dim=(0, 2, 3, 4)).sqrt() / scale).tolist()
         extra["mixed"] = {"value": nodes * 5 * args.steps / wall_m, "unit": "DOF-stage/s",
+                          "repeats": repeat_stats(nodes, args.steps, walls_m),
                           "ms_per_step": wall_m / args.steps * 1e3, "speedup_vs_fp64": wall / wall_m,
                           "err_vs_fp64_linf_rel": linf, "err_vs_fp64_l2_rel": l2,
                           "err_bound_stated": 1e-5, "within_bound": max(linf) <= 1e-5,
-                          "after_steps": args.warmup + args.steps}
+                          "after_steps": args.warmup + args.steps * repeats}
         if profm:
             extra["mixed"]["kernel_ms_per_step"] = {k: round(v[0] / args.steps, 4) for k, v in profm.items() if v[1]}
+            extra["mixed"]["stage_roofline_frac"] = roofline("", nodes, args.steps, profm)["frac"]
         opm.close()
         del Um
 
     if not args.no_adjoint:
         from paper_2306_12891_amd import inputs
         extra["adjoint"] = adjoint_leg(torch, dg, inputs)
+
+    if args.sweep and name.startswith("freestream"):
+        op.close()
+        op = None
+        del U, U_init
+        torch.cuda.empty_cache()
+        extra["sweep"] = sweep(torch, dg, spec, args.steps, args.warmup, repeats)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -298,7 +409,8 @@ def main():
         "roofline": roof, "cpu_baseline": cpu, **extra,
     }
     print(json.dumps(line))
-    op.close()
+    if op is not None:
+        op.close()
 
 
 if __name__ == "__main__":
