@@ -12,6 +12,13 @@
 // order and the same code, which gives bitwise-identical interface fluxes and
 // hence discrete conservation to round-off.
 //
+// The Navier-Stokes stage kernel is bound by LDS traffic and issue rate, not
+// by HBM: the BR1 gradient is accumulated inside the split-form partner loop
+// (off the diagonal Dw = Dhat / 2, so partner values and coefficients are
+// shared), the twelve viscous-flux components are exchanged through LDS once,
+// and all global loads of a workgroup are issued in two rounds (indices,
+// state and basis; then the neighbours' face states) before any arithmetic.
+//
 // Equations (paper: Blind et al., FLEXI; Sec. 2 and Sec. 4.1 for the split
 // form on LGL nodes and the DG/FV blend, Sec. 4.2 for the alpha bounds):
 //   advective:  U_t = -sum_d (2/dx_d) [ sum_l Dhat_{i_d l} F#_d(U_n, U_l)
@@ -60,10 +67,12 @@ constexpr int NB_STAGE = 2 * n1 * n1 + 3 * n1 + 1;  // Dhat, Dw, winv, xi, edge
 #ifndef DG_SKIP_DIAG
 #define DG_SKIP_DIAG 1
 #endif
-// Accumulate the BR1 gradient inside the volume loop (1) or in a separate
-// pass over the element (0).
+// Accumulate the BR1 gradient inside the split-form volume loop, reusing its
+// partner values and coefficients (1), or in a separate pass (0).  The fused
+// loop is kept rolled: fully unrolled, the partner loads in flight need more
+// than 200 registers.
 #ifndef DG_FUSED_GRAD
-#define DG_FUSED_GRAD 0
+#define DG_FUSED_GRAD 1
 #endif
 
 enum { VF_KG = 0, VF_PI = 1, VF_CH = 2, VF_STD = 3 };
@@ -396,7 +405,8 @@ constexpr int kPartners = DG_SKIP_DIAG ? N : N + 1;
 
 // With GRAD, also returns gs[c] = sum_{l != id} Dw_{id l} q_c(l) along the line
 // (q = u, v, w, theta): the off-diagonal part of the BR1 gradient, which
-// reuses the partner values the flux loop reads anyway.
+// reuses the partner values and coefficients the flux loop reads anyway
+// (off the diagonal Dw = D = Dhat / 2 exactly).
 template <int VF, int D, class R, bool GRAD = false>
 __device__ __forceinline__ void volume_dir(const R (*sP)[nn], const R* sDhat, int n, int id, const R me[7], R invJ,
                                            R gm1, R acc[5], const R* sDw = nullptr, R* gs = nullptr) {
@@ -404,25 +414,23 @@ __device__ __forceinline__ void volume_dir(const R (*sP)[nn], const R* sDhat, in
   const int base = n - id * st;
   const R* crow = sDhat + id * n1;
   R g0 = 0, g1 = 0, g2 = 0, g3 = 0;
-  auto grad_acc = [&](int l, int m) {
+  auto grad_acc = [&](R c, int m) {
     if (GRAD) {
-      const R cw = sDw[id * n1 + l];
-      g0 = fmaR(cw, sP[1][m], g0);
-      g1 = fmaR(cw, sP[2][m], g1);
-      g2 = fmaR(cw, sP[3][m], g2);
-      g3 = fmaR(cw, sP[6][m], g3);
+      g0 = fmaR(c, sP[1][m], g0);
+      g1 = fmaR(c, sP[2][m], g1);
+      g2 = fmaR(c, sP[3][m], g2);
+      g3 = fmaR(c, sP[6][m], g3);
     }
   };
   if (VF == VF_KG || VF == VF_PI) {
     // f_rho = fr4/4, f_m = fr4 us/8 + ps/2 e_D, f_E = fr4 xs/8 (+ ps und/4 for KG)
     // with sums s = a + b and fr4 = rho_s und_s.
     R s_fr = 0, s_m0 = 0, s_m1 = 0, s_m2 = 0, s_p = 0, s_E1 = 0, s_E2 = 0;
-#pragma unroll
-    for (int k = 1; k <= kPartners; ++k) {
+    auto pair = [&](int k) {
       const int l = partner(id, k);
       const int m = base + l * st;
       const R c = crow[l];
-      grad_acc(l, m);
+      grad_acc(c, m);
       const R rs = me[0] + sP[0][m];
       const R us = me[1] + sP[1][m];
       const R vs = me[2] + sP[2][m];
@@ -439,6 +447,13 @@ __device__ __forceinline__ void volume_dir(const R (*sP)[nn], const R* sDhat, in
       s_p += cp;
       s_E1 = fmaR(cf, xs, s_E1);
       if (VF == VF_KG) s_E2 = fmaR(cp, und, s_E2);
+    };
+    if (GRAD) {
+#pragma unroll 1
+      for (int k = 1; k <= kPartners; ++k) pair(k);
+    } else {
+#pragma unroll
+      for (int k = 1; k <= kPartners; ++k) pair(k);
     }
     const R q4 = (R)0.25, q8 = (R)0.125, h2 = (R)0.5;
     acc[0] -= invJ * (q4 * s_fr);
@@ -450,12 +465,11 @@ __device__ __forceinline__ void volume_dir(const R (*sP)[nn], const R* sDhat, in
     // F# = (F(a) + F(b))/2 with F_rho = rho u_D, F_m = rho u_D u + p e_D, F_E = rho h u_D
     const R mA = me[0] * me[1 + D];
     R s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0, sp = 0;
-#pragma unroll
-    for (int k = 1; k <= kPartners; ++k) {
+    auto pair = [&](int k) {
       const int l = partner(id, k);
       const int m = base + l * st;
       const R c = crow[l];
-      grad_acc(l, m);
+      grad_acc(c, m);
       const R mB = sP[0][m] * sP[1 + D][m];
       s0 = fmaR(c, mA + mB, s0);
       s1 = fmaR(c, mA * me[1] + mB * sP[1][m], s1);
@@ -463,6 +477,13 @@ __device__ __forceinline__ void volume_dir(const R (*sP)[nn], const R* sDhat, in
       s3 = fmaR(c, mA * me[3] + mB * sP[3][m], s3);
       sp = fmaR(c, me[4] + sP[4][m], sp);
       s4 = fmaR(c, mA * me[5] + mB * sP[5][m], s4);
+    };
+    if (GRAD) {
+#pragma unroll 1
+      for (int k = 1; k <= kPartners; ++k) pair(k);
+    } else {
+#pragma unroll
+      for (int k = 1; k <= kPartners; ++k) pair(k);
     }
     const R h2 = (R)0.5;
     acc[0] -= invJ * (h2 * s0);
@@ -480,7 +501,7 @@ __device__ __forceinline__ void volume_dir(const R (*sP)[nn], const R* sDhat, in
       const int l = partner(id, k);
       const int m = base + l * st;
       const double c = crow[l];
-      grad_acc(l, m);
+      grad_acc((R)c, m);
       RotState<double> b;
       b.r = sP[0][m]; b.un = sP[1 + D][m]; b.u1 = sP[1 + (D + 1) % 3][m]; b.u2 = sP[1 + (D + 2) % 3][m];
       b.p = sP[4][m];
@@ -495,10 +516,11 @@ __device__ __forceinline__ void volume_dir(const R (*sP)[nn], const R* sDhat, in
     for (int v = 0; v < 5; ++v) acc[v] -= invJ * (R)s[v];
   }
   if (GRAD) {
-    gs[0] = g0;
-    gs[1] = g1;
-    gs[2] = g2;
-    gs[3] = g3;
+    const R h2 = (R)0.5;
+    gs[0] = h2 * g0;
+    gs[1] = h2 * g1;
+    gs[2] = h2 * g2;
+    gs[3] = h2 * g3;
   }
 }
 
@@ -526,19 +548,13 @@ __device__ __forceinline__ void lifted_gradient(const R (*sP)[nn], const R (*sQ)
       s2 = fmaR(c, sP[3][m], s2);
       s3 = fmaR(c, sP[6][m], s3);
     }
-    if (id == N) {
-      const R wN = swinv[N];
-      s0 = fmaR(wN, sQ[2 * d + 1][0][a], s0);
-      s1 = fmaR(wN, sQ[2 * d + 1][1][a], s1);
-      s2 = fmaR(wN, sQ[2 * d + 1][2][a], s2);
-      s3 = fmaR(wN, sQ[2 * d + 1][3][a], s3);
-    }
-    if (id == 0) {
-      const R w0 = swinv[0];
-      s0 = fmaR(-w0, sQ[2 * d][0][a], s0);
-      s1 = fmaR(-w0, sQ[2 * d][1][a], s1);
-      s2 = fmaR(-w0, sQ[2 * d][2][a], s2);
-      s3 = fmaR(-w0, sQ[2 * d][3][a], s3);
+    if (id == 0 || id == N) {  // one branch for both faces (N >= 1)
+      const int f = 2 * d + (id == N);
+      const R w = id == N ? swinv[N] : -swinv[0];
+      s0 = fmaR(w, sQ[f][0][a], s0);
+      s1 = fmaR(w, sQ[f][1][a], s1);
+      s2 = fmaR(w, sQ[f][2][a], s2);
+      s3 = fmaR(w, sQ[f][3][a], s3);
     }
     g[d][0] = invJ[d] * s0;
     g[d][1] = invJ[d] * s1;
@@ -640,19 +656,36 @@ __device__ __forceinline__ void load_rotated(const double* Ux, int n, const Face
   X[4] = Ux[4 * nn + n];
 }
 
-// Minus (L) and plus (R) states of the face item, rotated.
-__device__ __forceinline__ void face_states(const double* U, int e, const FaceItem& it, double gm1, State64& sL,
-                                            State64& sR) {
-  double xo[5], xn[5], L[5], R[5];
-  load_rotated(U + (size_t)e * 5 * nn, it.nown, it, xo);
-  load_rotated(U + (size_t)it.nb * 5 * nn, it.nnb, it, xn);
+// Conservative minus (L) and plus (R) states of the face item, rotated (the
+// side only selects the two addresses).
+__device__ __forceinline__ void face_loads(const double* U, int e, const FaceItem& it, double L[5], double R[5]) {
+  const int eL = it.side ? e : it.nb, eR = it.side ? it.nb : e;
+  const int nL = it.side ? it.nown : it.nnb, nR = it.side ? it.nnb : it.nown;
+  load_rotated(U + (size_t)eL * 5 * nn, nL, it, L);
+  load_rotated(U + (size_t)eR * 5 * nn, nR, it, R);
+}
+
+// Face items handled by one thread (item q = t + k NT, k < FI).
+constexpr int FI = (6 * nf + NT - 1) / NT;
+
+// Loads of one face item, issued together before any of them is used: both
+// rotated states and (Navier-Stokes) the neighbour's normal viscous flux.
+template <bool NS, class R>
+struct FaceData {
+  FaceItem it;
+  double L[5], R_[5];
+  R fn[4];
+};
+
+template <bool NS, class R>
+__device__ __forceinline__ void face_issue(const StageArgs& A, int e, FaceData<NS, R>& fd) {
+  const FaceItem& it = fd.it;
+  face_loads(A.U, e, it, fd.L, fd.R_);
+  if (NS) {
+    const R* Fn = reinterpret_cast<const R*>(A.Fvf) + ((size_t)it.nb * 6 + (it.f ^ 1)) * 4 * nf + it.a;
 #pragma unroll
-  for (int v = 0; v < 5; ++v) {
-    L[v] = it.side ? xo[v] : xn[v];
-    R[v] = it.side ? xn[v] : xo[v];
+    for (int c = 0; c < 4; ++c) fd.fn[c] = Fn[c * nf];
   }
-  sL = state64<0>(L, gm1);
-  sR = state64<0>(R, gm1);
 }
 
 template <class R>
@@ -663,19 +696,17 @@ __device__ __forceinline__ void store_q(const FaceItem& it, const R qs[4], R (*s
   sQ[it.f][3][it.a] = qs[3];
 }
 
-// Interface values of face item q into LDS: advective f*, and for
+// Interface values of a face item into LDS: advective f*, and for
 // Navier-Stokes q* = (q- + q+)/2 and the neighbour's normal viscous flux.
 template <int VF, bool NS, class R, bool MX>
-__device__ __forceinline__ void face_item(const StageArgs& A, int e, int q, const Ref& ref, R (*sF)[5][nf],
-                                          R (*sQ)[4][nf], R (*sFn)[4][nf]) {
-  const FaceItem it = face_item_geometry(A.nbr, e, q);
-  if (NS) {  // issue the neighbour's viscous-flux loads first
-    const R* Fn = reinterpret_cast<const R*>(A.Fvf) + ((size_t)it.nb * 6 + (it.f ^ 1)) * 4 * nf;
+__device__ __forceinline__ void face_item(const StageArgs& A, const FaceData<NS, R>& fd, const Ref& ref,
+                                          R (*sF)[5][nf], R (*sQ)[4][nf], R (*sFn)[4][nf]) {
+  const FaceItem& it = fd.it;
+  if (NS) {
 #pragma unroll
-    for (int c = 0; c < 4; ++c) sFn[it.f][c][it.a] = Fn[c * nf + it.a];
+    for (int c = 0; c < 4; ++c) sFn[it.f][c][it.a] = fd.fn[c];
   }
-  State64 sL, sR;
-  face_states(A.U, e, it, A.gamma - 1.0, sL, sR);
+  const State64 sL = state64<0>(fd.L, A.gamma - 1.0), sR = state64<0>(fd.R_, A.gamma - 1.0);
   const Jumps<R> J = jumps<R, MX>(sL, sR, A.gamma, ref, A.sf);
   R g[5];
   riemann_rot<VF, R>(A.sf, to_rot<R, MX>(sL, ref), to_rot<R, MX>(sR, ref), J, (R)A.gamma, g);
@@ -728,23 +759,37 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
   if (e >= A.nelem) return;
   const int t = threadIdx.x;
   const double gm1 = A.gamma - 1.0;
-  for (int q = t; q < NB_STAGE; q += NT) {
-    sB[q] = (R)A.basis[q];
-    if (BLEND) sB64[q] = A.basis[q];
+  // Memory round trip 1: neighbour indices of the thread's face items, the
+  // node state and the basis.
+  FaceData<NS, R> fd[FI];
+#pragma unroll
+  for (int k = 0; k < FI; ++k)
+    if (t + k * NT < 6 * nf) fd[k].it = face_item_geometry(A.nbr, e, t + k * NT);
+  const double* Ue = A.U + (size_t)e * 5 * nn;
+  double u[5], gprev[5];
+  if (t < nn) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) u[v] = Ue[v * nn + t];
+  }
+  static_assert(NB_STAGE <= NT, "one basis entry per thread");
+  const double bval = t < NB_STAGE ? A.basis[t] : 0.0;
+  const Ref ref = MX ? reference_state(A.U, gm1) : Ref{0.0, 0.0, 0.0};
+  // Round trip 2: the face states (needs the neighbour indices).
+#pragma unroll
+  for (int k = 0; k < FI; ++k)
+    if (t + k * NT < 6 * nf) face_issue<NS, R>(A, e, fd[k]);
+  if (t < NB_STAGE) {
+    sB[t] = (R)bval;
+    if (BLEND) sB64[t] = bval;
   }
   const R* sDhat = sB + BL.Dhat();
   const R* sDw = sB + BL.Dw();
   const R* swinv = sB + BL.winv();
-  const Ref ref = MX ? reference_state(A.U, gm1) : Ref{0.0, 0.0, 0.0};
   const R invJ[3] = {(R)A.invJ[0], (R)A.invJ[1], (R)A.invJ[2]};
 
-  const double* Ue = A.U + (size_t)e * 5 * nn;
-  double u[5];
   R me[7];
   int ijk[3] = {0, 0, 0};
   if (t < nn) {
-#pragma unroll
-    for (int v = 0; v < 5; ++v) u[v] = Ue[v * nn + t];
     primitives<VF, R, MX>(u, gm1, ref, me);
 #pragma unroll
     for (int k = 0; k < 7; ++k)
@@ -753,7 +798,9 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
     ijk[1] = (t / n1) % n1;
     ijk[2] = t / nf;
   }
-  for (int q = t; q < 6 * nf; q += NT) face_item<VF, NS, R, MX>(A, e, q, ref, sF, sQ, sFn);
+#pragma unroll
+  for (int k = 0; k < FI; ++k)
+    if (t + k * NT < 6 * nf) face_item<VF, NS, R, MX>(A, fd[k], ref, sF, sQ, sFn);
   __syncthreads();
 
   R acc[5] = {0, 0, 0, 0, 0};
@@ -769,15 +816,11 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
     for (int d = 0; d < 3; ++d) {
       const int id = ijk[d];
       const int a = d == 0 ? ijk[1] + n1 * ijk[2] : (d == 1 ? ijk[0] + n1 * ijk[2] : ijk[0] + n1 * ijk[1]);
-      if (id == N) {
-        const R c = invJ[d] * swinv[N];
+      if (id == 0 || id == N) {  // one branch for both faces (N >= 1)
+        const int f = 2 * d + (id == N);
+        const R c = invJ[d] * (id == N ? -swinv[N] : swinv[0]);
 #pragma unroll
-        for (int v = 0; v < 5; ++v) acc[v] -= c * sF[2 * d + 1][v][a];
-      }
-      if (id == 0) {
-        const R c = invJ[d] * swinv[0];
-#pragma unroll
-        for (int v = 0; v < 5; ++v) acc[v] += c * sF[2 * d][v][a];
+        for (int v = 0; v < 5; ++v) acc[v] = fmaR(c, sF[f][v][a], acc[v]);
       }
     }
     if (NS) {
@@ -791,14 +834,16 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
       for (int d = 0; d < 3; ++d) {
         const int id = ijk[d];
         const int a = d == 0 ? ijk[1] + n1 * ijk[2] : (d == 1 ? ijk[0] + n1 * ijk[2] : ijk[0] + n1 * ijk[1]);
-        const R cd = DG_SKIP_DIAG ? sDw[id * n1 + id] : (R)0;
+        R s[4] = {gs[d][0], gs[d][1], gs[d][2], gs[d][3]};
+        if (id == 0 || id == N) {  // diagonal of Dw (zero inside) and the lifting term
+          const int f = 2 * d + (id == N);
+          const R cd = sDw[id * n1 + id];
+          const R w = id == N ? swinv[N] : -swinv[0];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          R s = fmaR(cd, qo[c], gs[d][c]);
-          if (id == N) s = fmaR(swinv[N], sQ[2 * d + 1][c][a], s);
-          if (id == 0) s = fmaR(-swinv[0], sQ[2 * d][c][a], s);
-          g[d][c] = invJ[d] * s;
+          for (int c = 0; c < 4; ++c) s[c] = fmaR(w, sQ[f][c][a], fmaR(cd, qo[c], s[c]));
         }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) g[d][c] = invJ[d] * s[c];
       }
       }
       const R mu = (R)A.mu, kap = (R)A.kappa;
@@ -859,6 +904,13 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
     }
   }
 
+  // Runge-Kutta register (stages 2-5), loaded ahead of the viscous phase so
+  // that its latency is hidden (earlier, its registers would be live across
+  // the volume loop, the kernel's register peak).
+  if (t < nn && A.mode != MODE_UT && A.A != 0.0) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) gprev[v] = A.G[(size_t)e * 5 * nn + t + v * nn];
+  }
   if (NS) {
     // viscous divergence: all twelve flux components exchanged through LDS once
     __syncthreads();
@@ -888,19 +940,13 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
           s3 = fmaR(c, sV[4 * d + 3][m], s3);
         }
         const int a = d == 0 ? ijk[1] + n1 * ijk[2] : (d == 1 ? ijk[0] + n1 * ijk[2] : ijk[0] + n1 * ijk[1]);
-        if (id == N) {  // neighbour across the + face (its normal viscous flux in sFn)
-          const R wN = swinv[N];
-          s0 = fmaR(wN, h2 * (Fv[d][0] + sFn[2 * d + 1][0][a]), s0);
-          s1 = fmaR(wN, h2 * (Fv[d][1] + sFn[2 * d + 1][1][a]), s1);
-          s2 = fmaR(wN, h2 * (Fv[d][2] + sFn[2 * d + 1][2][a]), s2);
-          s3 = fmaR(wN, h2 * (Fv[d][3] + sFn[2 * d + 1][3][a]), s3);
-        }
-        if (id == 0) {
-          const R w0 = swinv[0];
-          s0 = fmaR(-w0, h2 * (Fv[d][0] + sFn[2 * d][0][a]), s0);
-          s1 = fmaR(-w0, h2 * (Fv[d][1] + sFn[2 * d][1][a]), s1);
-          s2 = fmaR(-w0, h2 * (Fv[d][2] + sFn[2 * d][2][a]), s2);
-          s3 = fmaR(-w0, h2 * (Fv[d][3] + sFn[2 * d][3][a]), s3);
+        if (id == 0 || id == N) {  // F*v = mean with the neighbour's normal viscous flux (sFn)
+          const int f = 2 * d + (id == N);
+          const R w = h2 * (id == N ? swinv[N] : -swinv[0]);
+          s0 = fmaR(w, Fv[d][0] + sFn[f][0][a], s0);
+          s1 = fmaR(w, Fv[d][1] + sFn[f][1][a], s1);
+          s2 = fmaR(w, Fv[d][2] + sFn[f][2][a], s2);
+          s3 = fmaR(w, Fv[d][3] + sFn[f][3][a], s3);
         }
         acc[1] = fmaR(invJ[d], s0, acc[1]);
         acc[2] = fmaR(invJ[d], s1, acc[2]);
@@ -923,7 +969,7 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
         double gv = ut[v];
-        if (A.A != 0.0) gv = A.A * A.G[o + v * nn] + ut[v];
+        if (A.A != 0.0) gv = A.A * gprev[v] + ut[v];
         if (A.writeG) A.G[o + v * nn] = gv;
         A.Uout[o + v * nn] = u[v] + A.Bdt * gv;
       }
@@ -936,59 +982,159 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
 // face nodes -> Fvf[e][f][c][a] (type R), read by the neighbours' stage kernels.
 // ---------------------------------------------------------------------------
 template <class R, bool MX>
-__device__ __forceinline__ void lift_face_q(const StageArgs& A, int e, int q, const Ref& ref, R (*sQ)[4][nf]) {
-  const FaceItem it = face_item_geometry(A.nbr, e, q);
-  State64 sL, sR;
-  face_states(A.U, e, it, A.gamma - 1.0, sL, sR);
+__device__ __forceinline__ void lift_face_q(const StageArgs& A, const FaceItem& it, const double L[5],
+                                            const double Rr[5], const Ref& ref, R (*sQ)[4][nf]) {
+  const State64 sL = state64<0>(L, A.gamma - 1.0), sR = state64<0>(Rr, A.gamma - 1.0);
   R qs[4];
   interface_q<0, R, MX>(sL, sR, ref, qs);
   store_q(it, qs, sQ);
 }
 
-// Normal viscous flux at face node q of the element (face f = q / nf).
-template <class R>
-__device__ __forceinline__ void lift_face_node(const StageArgs& A, int e, int q, const R (*sP)[nn],
-                                               const R (*sQ)[4][nf], const R* sB, const R invJ[3]) {
-  const FaceItem it = face_item_geometry(A.nbr, e, q);
-  const int n = it.nown;
-  const int ijk[3] = {n % n1, (n / n1) % n1, n / nf};
-  R g[3][4], F0[4], F1[4], F2[4];
-  lifted_gradient<R>(sP, sQ, sB + BL.Dw(), sB + BL.winv(), n, ijk, invJ, g);
-  const R mu = (R)A.mu, kap = (R)A.kappa;
-  viscous_flux<0, R>(g, sP[1][n], sP[2][n], sP[3][n], mu, kap, F0);
-  viscous_flux<1, R>(g, sP[1][n], sP[2][n], sP[3][n], mu, kap, F1);
-  viscous_flux<2, R>(g, sP[1][n], sP[2][n], sP[3][n], mu, kap, F2);
-  R* out = reinterpret_cast<R*>(A.Fvf) + ((size_t)e * 6 + it.f) * 4 * nf;
-#pragma unroll
-  for (int c = 0; c < 4; ++c) out[c * nf + it.a] = it.d == 0 ? F0[c] : (it.d == 1 ? F1[c] : F2[c]);
+__device__ __forceinline__ int axis_stride(int j) { return j == 0 ? 1 : (j == 1 ? n1 : nf); }
+
+// Index of volume node n on the face of axis j (lower remaining axis first).
+__device__ __forceinline__ int face_index(int j, int i0, int i1, int i2) {
+  return j == 0 ? i1 + n1 * i2 : (j == 1 ? i0 + n1 * i2 : i0 + n1 * i1);
 }
 
+// Derivative along tangential axis j of the normal velocity u_d and of u_j at
+// node n (BR1: line sum with Dw plus the lifting term of axis j's faces).
 template <class R>
-__global__ __launch_bounds__(NT) void k_lift(StageArgs A) {
+__device__ __forceinline__ void tangential_pair(const R (*sq)[nn], const R (*sQ)[4][nf], const R* sDw,
+                                                const R* swinv, int n, int d, int j, int i0, int i1, int i2,
+                                                R invJj, R& dud, R& duj) {
+  const int sj = axis_stride(j);
+  const int id = j == 0 ? i0 : (j == 1 ? i1 : i2);
+  const int base = n - id * sj;
+  const R* crow = sDw + id * n1;
+  const R* qd = sq[d];
+  const R* qj = sq[j];
+  R s0 = 0, s1 = 0;
+#pragma unroll 2
+  for (int l = 0; l < n1; ++l) {
+    const R c = crow[l];
+    s0 = fmaR(c, qd[base + l * sj], s0);
+    s1 = fmaR(c, qj[base + l * sj], s1);
+  }
+  if (id == 0 || id == N) {
+    const int f = 2 * j + (id == N);
+    const R w = id == N ? swinv[N] : -swinv[0];
+    const int a = face_index(j, i0, i1, i2);
+    s0 = fmaR(w, sQ[f][d][a], s0);
+    s1 = fmaR(w, sQ[f][j][a], s1);
+  }
+  dud = invJj * s0;
+  duj = invJj * s1;
+}
+
+// Normal viscous flux at face node q of the element (face f = q / nf, normal
+// axis d), from sq = (u, v, w, theta) at the nodes and the interface values
+// sQ.  Only the eight gradient components it needs are formed: the
+// derivatives along d of (u, v, w, theta) and, along each tangential axis j,
+// those of u_d and u_j.
+template <class R>
+__device__ __forceinline__ void lift_face_node(const StageArgs& A, int e, const FaceItem& it, const R (*sq)[nn],
+                                               const R (*sQ)[4][nf], const R* sB, const R invJ[3]) {
+  const int n = it.nown, d = it.d;
+  const int i0 = n % n1, i1 = (n / n1) % n1, i2 = n / nf;
+  const R* sDw = sB + BL.Dw();
+  const R* swinv = sB + BL.winv();
+  const int ja = d == 0 ? 1 : 0, jb = d == 2 ? 1 : 2;  // tangential axes
+  // normal line: derivatives of u, v, w, theta along d
+  const int sn = axis_stride(d);
+  const int id = it.side ? N : 0;
+  const int base = n - id * sn;
+  const R* crow = sDw + id * n1;
+  R g0 = 0, g1 = 0, g2 = 0, g3 = 0;
+#pragma unroll 2
+  for (int l = 0; l < n1; ++l) {
+    const int m = base + l * sn;
+    const R c = crow[l];
+    g0 = fmaR(c, sq[0][m], g0);
+    g1 = fmaR(c, sq[1][m], g1);
+    g2 = fmaR(c, sq[2][m], g2);
+    g3 = fmaR(c, sq[3][m], g3);
+  }
+  {
+    const R w = it.side ? swinv[N] : -swinv[0];
+    g0 = fmaR(w, sQ[it.f][0][it.a], g0);
+    g1 = fmaR(w, sQ[it.f][1][it.a], g1);
+    g2 = fmaR(w, sQ[it.f][2][it.a], g2);
+    g3 = fmaR(w, sQ[it.f][3][it.a], g3);
+  }
+  const R Jd = d == 0 ? invJ[0] : (d == 1 ? invJ[1] : invJ[2]);
+  g0 *= Jd;
+  g1 *= Jd;
+  g2 *= Jd;
+  g3 *= Jd;
+  R da_ud, da_ua, db_ud, db_ub;
+  tangential_pair<R>(sq, sQ, sDw, swinv, n, d, ja, i0, i1, i2, ja == 0 ? invJ[0] : invJ[1], da_ud, da_ua);
+  tangential_pair<R>(sq, sQ, sDw, swinv, n, d, jb, i0, i1, i2, jb == 1 ? invJ[1] : invJ[2], db_ud, db_ub);
+  const R dn_ud = d == 0 ? g0 : (d == 1 ? g1 : g2);
+  const R dn_ua = ja == 0 ? g0 : g1;
+  const R dn_ub = jb == 1 ? g1 : g2;
+  const R mu = (R)A.mu, kap = (R)A.kappa;
+  const R dv = (R)(2.0 / 3.0) * mu * (dn_ud + da_ua + db_ub);
+  const R Fd = mu * (dn_ud + dn_ud) - dv;
+  const R Fa = mu * (dn_ua + da_ud);
+  const R Fb = mu * (dn_ub + db_ud);
+  const R ud = sq[d][n], ua = sq[ja][n], ub = sq[jb][n];
+  const R FE = ud * Fd + ua * Fa + ub * Fb + kap * g3;
+  R* out = reinterpret_cast<R*>(A.Fvf) + ((size_t)e * 6 + it.f) * 4 * nf + it.a;
+  out[d * nf] = Fd;
+  out[ja * nf] = Fa;
+  out[jb * nf] = Fb;
+  out[3 * nf] = FE;
+}
+
+// Register budget of the lifting kernel: 8 waves per SIMD (64 VGPRs) with one
+// face item per thread, else 4; the
+// line sums with run-time strides are only partly unrolled so that the
+// partner loads in flight fit in it.
+template <class R>
+__global__ __launch_bounds__(NT, FI == 1 && N >= 2 ? 8 : 4) void k_lift(StageArgs A) {
   constexpr bool MX = sizeof(R) == 4;
   __shared__ R sB[NB_STAGE];
-  __shared__ R sP[7][nn];
+  __shared__ R sq[4][nn];  // u, v, w, theta
   __shared__ R sQ[6][4][nf];
   const int e = element_of_block(blockIdx.x, A.chunk);
   if (e >= A.nelem) return;
   const int t = threadIdx.x;
   const double gm1 = A.gamma - 1.0;
-  for (int q = t; q < NB_STAGE; q += NT) sB[q] = (R)A.basis[q];
-  const Ref ref = MX ? reference_state(A.U, gm1) : Ref{0.0, 0.0, 0.0};
-  const R invJ[3] = {(R)A.invJ[0], (R)A.invJ[1], (R)A.invJ[2]};
+  // Round trip 1: neighbour indices, node state, basis; round trip 2: face states.
+  FaceItem its[FI];
+#pragma unroll
+  for (int k = 0; k < FI; ++k)
+    if (t + k * NT < 6 * nf) its[k] = face_item_geometry(A.nbr, e, t + k * NT);
   const double* Ue = A.U + (size_t)e * 5 * nn;
+  double u[5];
   if (t < nn) {
-    double u[5];
-    R P[7];
 #pragma unroll
     for (int v = 0; v < 5; ++v) u[v] = Ue[v * nn + t];
-    primitives<VF_PI, R, MX>(u, gm1, ref, P);
-#pragma unroll
-    for (int k = 0; k < 7; ++k) sP[k][t] = P[k];
   }
-  for (int q = t; q < 6 * nf; q += NT) lift_face_q<R, MX>(A, e, q, ref, sQ);
+  const double bval = t < NB_STAGE ? A.basis[t] : 0.0;
+  const Ref ref = MX ? reference_state(A.U, gm1) : Ref{0.0, 0.0, 0.0};
+  double FL[FI][5], FR[FI][5];
+#pragma unroll
+  for (int k = 0; k < FI; ++k)
+    if (t + k * NT < 6 * nf) face_loads(A.U, e, its[k], FL[k], FR[k]);
+  if (t < NB_STAGE) sB[t] = (R)bval;
+  const R invJ[3] = {(R)A.invJ[0], (R)A.invJ[1], (R)A.invJ[2]};
+  if (t < nn) {
+    R P[7];
+    primitives<VF_PI, R, MX>(u, gm1, ref, P);
+    sq[0][t] = P[1];
+    sq[1][t] = P[2];
+    sq[2][t] = P[3];
+    sq[3][t] = P[6];
+  }
+#pragma unroll
+  for (int k = 0; k < FI; ++k)
+    if (t + k * NT < 6 * nf) lift_face_q<R, MX>(A, its[k], FL[k], FR[k], ref, sQ);
   __syncthreads();
-  for (int q = t; q < 6 * nf; q += NT) lift_face_node<R>(A, e, q, sP, sQ, sB, invJ);
+#pragma unroll
+  for (int k = 0; k < FI; ++k)
+    if (t + k * NT < 6 * nf) lift_face_node<R>(A, e, its[k], sq, sQ, sB, invJ);
 }
 
 // ===========================================================================
