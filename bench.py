@@ -75,9 +75,10 @@ def domain(name):
 # calibration (FETCH x 2.000, WRITE x 1.000); see profiles/k_stage_*.md.  Valid
 # only for the kernel source they were taken on (sha256 prefix).
 MEASURED_TRAFFIC = {
-    "kernel_sha": "654c86e3c411f0dd",
-    "tgv_n5_32": {"bytes_per_launch": 1380.4e6, "fetch": 870.8e6, "write": 509.6e6},
-    "tgv_n7_64": {"bytes_per_launch": 26650.2e6, "fetch": 16986.5e6, "write": 9663.7e6},
+    "kernel_sha": "3507ab3d785d1b90",
+    "tgv_n5_32": {"bytes_per_launch": 1380.3e6, "fetch": 870.7e6, "write": 509.6e6},
+    "tgv_n7_64": {"bytes_per_launch": 26682.5e6, "fetch": 17018.8e6, "write": 9663.7e6},
+    "freestream_euler_n7_64": {"bytes_per_launch": 22897.9e6, "fetch": 13234.2e6, "write": 9663.7e6},
 }
 
 
