@@ -23,7 +23,10 @@
 //   * blending sigmoid with threshold T(N) = 0.5*10^(-1.8 (N+1)^0.25): Sec. 4.1,
 //     indicator eq.; spread to neighbours by 1/2: Sec. 4.1;
 //   * a in [0.01, 0.7], pure DG below 0.01: Sec. 4.2 (Application);
-//   * explicit Runge-Kutta, stages counted in the PID: Sec. 2, eq. (pid).
+//   * explicit Runge-Kutta, stages counted in the PID: Sec. 2, eq. (pid);
+//   * Smagorinsky eddy viscosity with a constant or per-element coefficient
+//     C_s evaluated at every solution point: Sec. 5 (the standard model with
+//     constant C_s, and the learned model that sets C_s per element).
 // Everything the paper leaves open (BR1 lifting, the Kennedy-Gruber and
 // Pirozzoli two-point fluxes, LLF/Roe, the LSERK4 coefficients, the modal
 // energy definition, the sharpness s, the FV reconstruction) follows the
@@ -62,6 +65,10 @@ struct Setup {
   int32_t indicator, fv_recon, pad0, pad1;
   double lo[3], hi[3];
   double gamma, mu, Pr, alpha_min, alpha_max, alpha_spread;
+  // Smagorinsky model (Navier-Stokes): coefficient C_s (0: none), turbulent
+  // Prandtl number, optional per-element coefficients (overrides Cs).
+  double Cs, Prt;
+  const double* cs_elem;
 };
 
 // ---------------------------------------------------------------------------
@@ -185,7 +192,14 @@ struct Ctx {
   Basis b;
   int N, n1, nn, nf, nelem;
   double dx[3], invJ[3], Jac;
+  double delta2;         // squared filter width of the eddy viscosity
   std::vector<int> nbr;  // [e][6]
+  // (C_s Delta)^2 of element e; 0 without the Smagorinsky model
+  double csd2(int e) const {
+    const double cs = s.cs_elem ? s.cs_elem[e] : s.Cs;
+    return cs * cs * delta2;
+  }
+  bool les() const { return s.equations == 1 && (s.cs_elem != nullptr || s.Cs > 0.0); }
 };
 
 static Ctx make_ctx(const Setup& s) {
@@ -204,6 +218,10 @@ static Ctx make_ctx(const Setup& s) {
     c.invJ[d] = 2.0 / c.dx[d];  // J_d = dx_d / 2
     c.Jac *= 0.5 * c.dx[d];
   }
+  // reading: filter width = element size over the points per direction,
+  // Delta = (dx dy dz)^(1/3) / (N + 1)
+  const double delta = std::cbrt(c.dx[0] * c.dx[1] * c.dx[2]) / (s.N + 1.0);
+  c.delta2 = delta * delta;
   c.nbr.assign(6 * c.nelem, 0);
   for (int ez = 0; ez < s.nz; ++ez)
     for (int ey = 0; ey < s.ny; ++ey)
@@ -515,18 +533,35 @@ static void br1_gradient(const Ctx& c, const T* U, std::vector<T>& grad) {
 }
 
 // Viscous flux in direction d from the state and the lifted gradient
-// gr[d'][c] = d q_c / d x_{d'}.
+// gr[d'][c] = d q_c / d x_{d'}.  With csd2 = (C_s Delta)^2 > 0 the Smagorinsky
+// eddy viscosity is added at the node:
+//   mu_t = rho (C_s Delta)^2 |S|,  |S| = sqrt(2 S_ij S_ij),
+//   S_ij = (du_i/dx_j + du_j/dx_i) / 2,
+// and the heat flux coefficient by kappa'_t = mu_t gamma / ((gamma-1) Pr_t)
+// (reading: the standard model; the paper fixes C_s per element only).
 template <class T>
-static void viscous_flux(int d, double g, double mu, double Pr, const T U[5], const T gr[3][4], T F[5]) {
+static void viscous_flux(int d, double g, double mu, double Pr, double csd2, double Prt, const T U[5],
+                         const T gr[3][4], T F[5]) {
   const Prim<T> P = primitive(U, g);
+  T mu_e = T(mu), kap_e = T(mu * g / ((g - 1.0) * Pr));
+  if (csd2 > 0.0) {
+    T SS = T(0.0);
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        const T Sij = 0.5 * (gr[j][i] + gr[i][j]);  // du_i/dx_j = gr[j][i]
+        SS = SS + Sij * Sij;
+      }
+    const T mut = P.rho * csd2 * sqrt_(2.0 * SS);
+    mu_e = mu_e + mut;
+    kap_e = kap_e + mut * (g / ((g - 1.0) * Prt));
+  }
   const T div = gr[0][0] + gr[1][1] + gr[2][2];
   T tau[3];  // tau_{j d}, j = 0..2
   for (int j = 0; j < 3; ++j)
-    tau[j] = mu * (gr[d][j] + gr[j][d]) - (j == d ? (2.0 / 3.0) * mu * div : T(0.0));
-  const double kap = mu * g / ((g - 1.0) * Pr);
+    tau[j] = mu_e * (gr[d][j] + gr[j][d]) - (j == d ? (2.0 / 3.0) * mu_e * div : T(0.0));
   F[0] = T(0.0);
   for (int j = 0; j < 3; ++j) F[1 + j] = tau[j];
-  F[4] = P.u[0] * tau[0] + P.u[1] * tau[1] + P.u[2] * tau[2] + kap * gr[d][3];
+  F[4] = P.u[0] * tau[0] + P.u[1] * tau[1] + P.u[2] * tau[2] + kap_e * gr[d][3];
 }
 
 // Adds the viscous divergence (strong form, BR1) to Ut:
@@ -548,7 +583,7 @@ static void viscous_dg(const Ctx& c, const T* U, T* Ut) {
         for (int k = 0; k < 4; ++k) gr[dd][k] = grad[((size_t(e) * 3 + dd) * 4 + k) * c.nn + n];
       for (int d = 0; d < 3; ++d) {
         T F[5];
-        viscous_flux(d, g, mu, Pr, u, gr, F);
+        viscous_flux(d, g, mu, Pr, c.csd2(e), c.s.Prt, u, gr, F);
         for (int v = 0; v < 5; ++v) Fv[((size_t(e) * 3 + d) * 5 + v) * c.nn + n] = F[v];
       }
     }
@@ -943,7 +978,7 @@ static void dense_time_derivative(const Ctx& c, const double* U, double* Ut) {
     st(e, n, u);
     for (int dd = 0; dd < 3; ++dd)
       for (int k = 0; k < 4; ++k) gr[dd][k] = grad[(size_t(e) * nn + n) * 12 + dd * 4 + k];
-    viscous_flux(d, g, c.s.mu, c.s.Pr, u, gr, F);
+    viscous_flux(d, g, c.s.mu, c.s.Pr, c.csd2(e), c.s.Prt, u, gr, F);
   };
   for (int e = 0; e < c.nelem; ++e)
     for (int a = 0; a < nn; ++a)
@@ -1030,7 +1065,7 @@ static void subset_time_derivative(const Ctx& c, const double* U, const int32_t*
     load_state(c, U, x, n, u);
     for (int dd = 0; dd < 3; ++dd)
       for (int k = 0; k < 4; ++k) G[dd][k] = gr[(dd * 4 + k) * nn + n];
-    viscous_flux(d, g, c.s.mu, c.s.Pr, u, G, F);
+    viscous_flux(d, g, c.s.mu, c.s.Pr, c.csd2(x), c.s.Prt, u, G, F);
   };
 #pragma omp parallel for schedule(dynamic)
   for (int s = 0; s < nsel; ++s) {
@@ -1113,6 +1148,7 @@ static bool valid(const Setup* s) {
   if (s->nx < 1 || s->ny < 1 || s->nz < 1) return false;
   if (!(s->gamma > 1.0) || s->mu < 0.0) return false;
   if (s->blending && s->N < 2) return false;
+  if (s->Cs < 0.0 || ((s->Cs > 0.0 || s->cs_elem) && !(s->Prt > 0.0))) return false;
   return true;
 }
 
@@ -1250,6 +1286,7 @@ int or_lserk4_linear(int n, const double* A, double* u, double dt, int nsteps) {
 int or_jvp(const Setup* s, const double* U, const double* V, double* Ut, double* JV) {
   if (!valid(s)) return -1;
   const Ctx c = make_ctx(*s);
+  if (c.les()) return -1;
   const size_t n = size_t(c.nelem) * 5 * c.nn;
   std::vector<Dual> X(n), Y(n);
   for (size_t i = 0; i < n; ++i) X[i] = Dual(U[i], V[i]);
@@ -1262,6 +1299,7 @@ int or_jvp(const Setup* s, const double* U, const double* V, double* Ut, double*
 int or_rk_jvp(const Setup* s, double* U, double* V, double dt, int nsteps) {
   if (!valid(s)) return -1;
   const Ctx c = make_ctx(*s);
+  if (c.les()) return -1;
   const size_t n = size_t(c.nelem) * 5 * c.nn;
   std::vector<Dual> X(n);
   for (size_t i = 0; i < n; ++i) X[i] = Dual(U[i], V[i]);

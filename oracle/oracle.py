@@ -46,7 +46,8 @@ class _Setup(ctypes.Structure):
                 ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
                 ("gamma", ctypes.c_double), ("mu", ctypes.c_double), ("Pr", ctypes.c_double),
                 ("alpha_min", ctypes.c_double), ("alpha_max", ctypes.c_double),
-                ("alpha_spread", ctypes.c_double)]
+                ("alpha_spread", ctypes.c_double), ("Cs", ctypes.c_double), ("Prt", ctypes.c_double),
+                ("cs_elem", ctypes.c_void_p)]
 
 
 @dataclass
@@ -67,7 +68,11 @@ class Setup:
     alpha_min: float = 0.01
     alpha_max: float = 0.7
     alpha_spread: float = 0.5
+    Cs: float = 0.0          # Smagorinsky coefficient (0: no eddy viscosity)
+    Prt: float = 0.9         # turbulent Prandtl number
+    cs_elem: object = None   # optional per-element coefficients (numpy, n_elems)
     _c: object = field(default=None, repr=False, compare=False)
+    _keep: object = field(default=None, repr=False, compare=False)
 
     @property
     def n1(self) -> int:
@@ -93,6 +98,13 @@ class Setup:
             s.hi[d] = self.hi[d]
         s.gamma, s.mu, s.Pr = self.gamma, self.mu, self.Pr
         s.alpha_min, s.alpha_max, s.alpha_spread = self.alpha_min, self.alpha_max, self.alpha_spread
+        s.Cs, s.Prt = self.Cs, self.Prt
+        if self.cs_elem is not None:
+            self._keep = np.ascontiguousarray(self.cs_elem, dtype=np.float64)
+            assert self._keep.shape == (self.n_elems,)
+            s.cs_elem = self._keep.ctypes.data
+        else:
+            s.cs_elem = None
         return s
 
 
