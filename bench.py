@@ -42,7 +42,13 @@ WORKLOADS = {
                             "NS freestream Ma0.5, N=7, 64^3 elems, PI+Roe, BR1, LSERK4"),
     "sod_n5_64x8x8": (5, (64, 8, 8), 0, 0, 0, 0.0, 1,
                       "Euler Sod tube, N=5, 64x8x8 elems, KG+LLF, DG/FV blending (minmod), LSERK4"),
+    "tgv_les_n5_32": (5, (32, 32, 32), 1, 1, 1, 1.0 / 1600, 0,
+                      "TGV Ma0.1 Re1600 LES (Smagorinsky C_s=0.17, Pr_t=0.9), N=5, 32^3 elems, PI+Roe, BR1, "
+                      "LSERK4"),
 }
+
+# Smagorinsky coefficient of the LES workloads (standard model, constant C_s).
+MODEL_CS = {"tgv_les_n5_32": 0.17}
 
 
 # Element counts of the freestream size sweep: 2^15 ... 2^21 elements, grown
@@ -190,7 +196,7 @@ def cpu_baseline(name, spec, U0, dt, max_nodes=8_000_000):
     def run(elems, U, threads):
         orc.set_threads(threads)
         s = orc.Setup(N=N, nelem=elems, lo=lo, hi=hi, equations=eq, vol_flux=vf, surf_flux=sf, mu=mu,
-                      blending=blend, Pr=0.72)
+                      blending=blend, Pr=0.72, Cs=MODEL_CS.get(name, 0.0))
         t0 = time.perf_counter()
         orc.rk_steps(s, U, dt, 1)
         return time.perf_counter() - t0
@@ -339,8 +345,9 @@ def main():
     lo, hi = domain(name)
     nodes = int(np.prod(nelem)) * (N + 1) ** 3
     U0 = None if name.startswith("freestream") else initial_state(name, N, nelem)
+    cs = MODEL_CS.get(name, 0.0)
     op = dg.DG(nelem, N, gamma=1.4, mu=mu, lo=lo, hi=hi, equations=eq, vol_flux=vf, surf_flux=sf,
-               blending=blend, Pr=0.72)
+               blending=blend, Pr=0.72, Cs=cs)
     U_init = device_freestream(torch, N, nelem) if U0 is None else torch.from_numpy(U0).to("cuda:0")
     U = U_init.clone()
     dt = op.max_dt(U, 0.5)
@@ -365,7 +372,7 @@ def main():
     # warm-up and timed steps; error of the final state against the FP64 run.
     if not args.no_mixed and vf in (1, 3) and not blend:
         opm = dg.DG(nelem, N, gamma=1.4, mu=mu, lo=lo, hi=hi, equations=eq, vol_flux=vf, surf_flux=sf,
-                    Pr=0.72, precision=dg.MIXED)
+                    Pr=0.72, precision=dg.MIXED, Cs=cs)
         Um = U_init.clone()
         walls_m, profm = timed_rollouts(torch, opm, Um, dt, args.steps, args.warmup, repeats,
                                         not args.no_profile)

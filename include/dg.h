@@ -94,6 +94,9 @@ typedef struct {
   double alpha_min;     /* below: pure DG (paper Sec. 4.2)           (0.01)    */
   double alpha_max;     /* upper clip (paper Sec. 4.2)               (0.7)     */
   double alpha_spread;  /* neighbour factor (paper Sec. 4.1)         (0.5)     */
+  double Cs;            /* Smagorinsky coefficient, DG_NS only; 0 = no
+                           eddy viscosity (paper Sec. 5)             (0)       */
+  double Prt;           /* turbulent Prandtl number of the model     (0.9)     */
 } dg_options;
 
 /* Fills *opt with the defaults above. */
@@ -106,9 +109,27 @@ void dg_default_options(dg_options* opt);
 int dg_init(const dg_mesh* mesh, int N, double gamma, double mu, dg_ctx** out);
 
 /* Replaces the options.  Validated here: DG_EUNSUPPORTED for blending with
- * DG_NS, blending with N < 2, or DG_MIXED with blending. */
+ * DG_NS, blending with N < 2, DG_MIXED with blending, or the Smagorinsky
+ * model (Cs > 0) with the DG_VF_CH flux; DG_EINVAL for Cs < 0 or Prt <= 0. */
 int dg_set_options(dg_ctx* ctx, const dg_options* opt);
 int dg_get_options(const dg_ctx* ctx, dg_options* opt);
+
+/* Smagorinsky eddy viscosity with one coefficient per element (paper Sec. 5:
+ * the standard model uses a constant C_s; the learned model sets C_s per
+ * element and the eddy viscosity is evaluated at every solution point of the
+ * element).  With DG_NS, at every node of element e:
+ *   mu_t = rho (C_s(e) Delta)^2 |S|,  |S| = sqrt(2 S_ij S_ij) of the lifted
+ *   velocity gradient, Delta = (dx dy dz)^(1/3) / (N + 1),
+ * added to mu in the viscous stress, and mu_t gamma / ((gamma - 1) Prt) added
+ * to the heat-flux coefficient mu gamma / ((gamma - 1) Pr).
+ * cs: device pointer to nElems doubles (element order of the state), copied
+ * into the context on its stream (the caller may free it afterwards); it
+ * replaces opt.Cs until dg_set_cs_field(ctx, NULL) restores the constant.
+ * Errors: DG_EINVAL for a host pointer, DG_EUNSUPPORTED with DG_VF_CH,
+ * DG_ENOMEM.  The model has no adjoint: dg_vjp and rk_step_vjp return
+ * DG_EUNSUPPORTED while it is active.  The time-step estimate dg_max_dt uses
+ * the molecular viscosity only. */
+int dg_set_cs_field(dg_ctx* ctx, const double* cs);
 
 /* Sets the HIP stream (hipStream_t) all later calls enqueue on; NULL = null
  * stream. */

@@ -173,6 +173,8 @@ struct dg_ctx {
   double* alpha1 = nullptr;
   double* alpha = nullptr;
   double* Fvf = nullptr;
+  double* cs_field = nullptr;  // per-element Smagorinsky coefficients (dg_set_cs_field)
+  int has_cs_field = 0;
   double* partial = nullptr;
   double* h_partial = nullptr;
   // reverse mode (allocated on first use): stage states Y_0..Y_4, the
@@ -225,6 +227,7 @@ void release(dg_ctx* c) {
   hipFree(c->alpha1);
   hipFree(c->alpha);
   hipFree(c->Fvf);
+  hipFree(c->cs_field);
   hipFree(c->partial);
   if (c->h_partial) hipHostFree(c->h_partial);
   for (double* y : c->Y) hipFree(y);
@@ -256,7 +259,19 @@ StageArgs stage_args(const dg_ctx* c) {
   a.blend = c->opt.blending;
   a.indicator = c->opt.indicator;
   a.recon = c->opt.fv_recon;
+  a.cs_elem = c->has_cs_field ? c->cs_field : nullptr;
+  a.cs = c->opt.Cs;
+  const double delta = std::cbrt(c->dx[0] * c->dx[1] * c->dx[2]) / (c->N + 1.0);
+  a.delta2 = delta * delta;
+  a.ktf = c->gamma / ((c->gamma - 1.0) * c->opt.Prt);
   return a;
+}
+
+// Kernel variant of the equations: 0 Euler, 1 Navier-Stokes, 2 Navier-Stokes
+// with the Smagorinsky eddy viscosity (constant C_s > 0 or a per-element field).
+int eq_code(const dg_ctx* c) {
+  if (c->opt.equations != DG_NS) return 0;
+  return (c->has_cs_field || c->opt.Cs > 0.0) ? 2 : 1;
 }
 
 ReduceArgs reduce_args(const dg_ctx* c, const double* X) {
@@ -322,13 +337,14 @@ int run_stage(dg_ctx* c, const double* Xin, double* Xout, double* Ut, int mode, 
     if (e != hipSuccess) return hip_fail(c, e, "indicator kernel");
   }
   const bool mixed = c->opt.precision == DG_MIXED;
-  if (c->opt.equations == DG_NS) {
-    e = timed(c, DG_K_LIFT, [&] { return mixed ? c->kt->lift_mixed(a, c->stream) : c->kt->lift(a, c->stream); });
+  const int eq = eq_code(c);
+  if (eq >= 1) {
+    e = timed(c, DG_K_LIFT,
+              [&] { return mixed ? c->kt->lift_mixed(a, eq, c->stream) : c->kt->lift(a, eq, c->stream); });
     if (e != hipSuccess) return hip_fail(c, e, "lifting kernel");
   }
-  e = timed(c, DG_K_STAGE, [&] {
-    return mixed ? c->kt->stage_mixed(a, c->opt.equations, c->stream) : c->kt->stage(a, c->opt.equations, c->stream);
-  });
+  e = timed(c, DG_K_STAGE,
+            [&] { return mixed ? c->kt->stage_mixed(a, eq, c->stream) : c->kt->stage(a, eq, c->stream); });
   if (e != hipSuccess) return hip_fail(c, e, "stage kernel");
   return DG_OK;
 }
@@ -337,6 +353,7 @@ bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
 int vjp_supported(dg_ctx* c) {
   if (c->opt.blending) return fail(c, DG_EUNSUPPORTED, "vjp: not available with blending");
+  if (eq_code(c) == 2) return fail(c, DG_EUNSUPPORTED, "vjp: not available with the Smagorinsky model");
   if (c->opt.precision != DG_FP64) return fail(c, DG_EUNSUPPORTED, "vjp: FP64 operator only");
   if (c->opt.vol_flux == DG_VF_CH) return fail(c, DG_EUNSUPPORTED, "vjp: not available for the CH flux");
   return DG_OK;
@@ -409,6 +426,8 @@ void dg_default_options(dg_options* o) {
   o->alpha_min = 0.01;
   o->alpha_max = 0.7;
   o->alpha_spread = 0.5;
+  o->Cs = 0.0;
+  o->Prt = 0.9;
 }
 
 int dg_init(const dg_mesh* mesh, int N, double gamma, double mu, dg_ctx** out) {
@@ -511,7 +530,32 @@ int dg_set_options(dg_ctx* c, const dg_options* o) {
     return fail(c, DG_EUNSUPPORTED, "dg_set_options: mixed precision without blending only");
   if (o->precision == DG_MIXED && o->vol_flux != DG_VF_PI && o->vol_flux != DG_VF_STD)
     return fail(c, DG_EUNSUPPORTED, "dg_set_options: mixed precision needs the PI or STD volume flux");
+  if (!(o->Cs >= 0.0) || !std::isfinite(o->Cs) || !finite_pos(o->Prt))
+    return fail(c, DG_EINVAL, "dg_set_options: need Cs >= 0 and Prt > 0");
+  if ((o->Cs > 0.0 || c->has_cs_field) && o->equations == DG_NS && o->vol_flux == DG_VF_CH)
+    return fail(c, DG_EUNSUPPORTED, "dg_set_options: the Smagorinsky model is built for the KG, PI and STD fluxes");
   c->opt = *o;
+  return DG_OK;
+}
+
+int dg_set_cs_field(dg_ctx* c, const double* cs) {
+  if (check_ctx(c)) return DG_EINVAL;
+  if (!cs) {
+    c->has_cs_field = 0;
+    return DG_OK;
+  }
+  if (!is_device_ptr(cs)) return fail(c, DG_EINVAL, "dg_set_cs_field: cs must be a device pointer");
+  if (c->opt.vol_flux == DG_VF_CH)
+    return fail(c, DG_EUNSUPPORTED, "dg_set_cs_field: the Smagorinsky model is built for the KG, PI and STD fluxes");
+  hipError_t e = hipSuccess;
+  if (!c->cs_field) e = hipMalloc((void**)&c->cs_field, (size_t)c->nelem * sizeof(double));
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->cs_field, cs, (size_t)c->nelem * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, (e == hipErrorOutOfMemory) ? DG_ENOMEM : DG_EHIP, "dg_set_cs_field: %s", hipGetErrorString(e));
+  }
+  c->has_cs_field = 1;
   return DG_OK;
 }
 

@@ -38,6 +38,10 @@ struct StageArgs {
   double A, Bdt;        // RK stage coefficients (A_k, B_k dt)
   double amin, amax, aspread;
   double thresh, sharp;  // T(N) and s
+  // Smagorinsky model (stage/lift kernels with EQ 2): per-element C_s (or
+  // NULL: the constant cs), squared filter width, gamma / ((gamma - 1) Pr_t)
+  const double* cs_elem;
+  double cs, delta2, ktf;
   int nelem, chunk;      // chunk = ceil(nelem / 8): XCD-contiguous element ranges
   int vf, sf, blend, mode, writeG, indicator, recon;
 };
@@ -71,8 +75,8 @@ struct KernelTable {
   int nt;  // threads per block
   hipError_t (*stage)(const StageArgs&, int eq, hipStream_t);
   hipError_t (*stage_mixed)(const StageArgs&, int eq, hipStream_t);
-  hipError_t (*lift)(const StageArgs&, hipStream_t);
-  hipError_t (*lift_mixed)(const StageArgs&, hipStream_t);
+  hipError_t (*lift)(const StageArgs&, int eq, hipStream_t);
+  hipError_t (*lift_mixed)(const StageArgs&, int eq, hipStream_t);
   hipError_t (*alpha1)(const StageArgs&, hipStream_t);
   hipError_t (*spread)(const StageArgs&, hipStream_t);
   hipError_t (*max_rate)(const ReduceArgs&, hipStream_t);

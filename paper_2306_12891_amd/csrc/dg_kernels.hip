@@ -113,6 +113,10 @@ __device__ __forceinline__ double sqrt64(double x) {
   return fma(d, h, s);
 }
 
+// Square root of a non-negative argument (0 and tiny values give 0).
+__device__ __forceinline__ double sqrt_nonneg(double x) { return x > 1e-300 ? sqrt64(x) : 0.0; }
+__device__ __forceinline__ float sqrt_nonneg(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 __device__ __forceinline__ double rcpR(double x) { return rcp64(x); }
 __device__ __forceinline__ float rcpR(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double sqrtR(double x) { return sqrt64(x); }
@@ -575,6 +579,15 @@ __device__ __forceinline__ void viscous_flux(const R g[3][4], R vx, R vy, R vz, 
   F[3] = vx * F[0] + vy * F[1] + vz * F[2] + kappa * g[D][3];
 }
 
+// Smagorinsky eddy viscosity at a node from its lifted gradient g[d][c]
+// (c = u, v, w): mu_t = rho (C_s Delta)^2 |S|, |S|^2 = 2 S_ij S_ij.
+template <class R>
+__device__ __forceinline__ R eddy_viscosity(const R g[3][4], R rho, R csd2) {
+  const R a = g[0][1] + g[1][0], b = g[0][2] + g[2][0], c = g[1][2] + g[2][1];
+  const R S2 = (R)2 * (g[0][0] * g[0][0] + g[1][1] * g[1][1] + g[2][2] * g[2][2]) + a * a + b * b + c * c;
+  return rho * csd2 * sqrt_nonneg(S2);
+}
+
 __device__ __forceinline__ double minmod(double a, double b) {
   if (a * b <= 0.0) return 0.0;
   return a > 0.0 ? fmin(a, b) : fmax(a, b);
@@ -724,8 +737,8 @@ __device__ __forceinline__ void face_item(const StageArgs& A, const FaceData<NS,
 
 // ---------------------------------------------------------------------------
 // Stage kernel: operator (+ FV blend) and either U_t output or RK update.
-// EQ: 0 Euler, 1 Navier-Stokes.  R: arithmetic type (double, or float for
-// the mixed operator, MX).
+// EQ: 0 Euler, 1 Navier-Stokes, 2 Navier-Stokes with the Smagorinsky eddy
+// viscosity.  R: arithmetic type (double, or float for the mixed operator, MX).
 // ---------------------------------------------------------------------------
 #if DG_STAGE_MIN_WAVES > 0
 #define DG_STAGE_BOUNDS __launch_bounds__(NT, DG_STAGE_MIN_WAVES)
@@ -734,7 +747,8 @@ __device__ __forceinline__ void face_item(const StageArgs& A, const FaceData<NS,
 #endif
 template <int VF, int EQ, bool BLEND, class R>
 __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
-  constexpr bool NS = (EQ == 1);
+  constexpr bool NS = (EQ >= 1);
+  constexpr bool LES = (EQ == 2);
   constexpr bool MX = sizeof(R) == 4;
   static_assert(!(BLEND && MX), "the blended operator is FP64 only");
   // LDS pool: primitives sP[7][nn], face fluxes sF[6][5][nf], and for
@@ -846,7 +860,13 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
         for (int c = 0; c < 4; ++c) g[d][c] = invJ[d] * s[c];
       }
       }
-      const R mu = (R)A.mu, kap = (R)A.kappa;
+      R mu = (R)A.mu, kap = (R)A.kappa;
+      if (LES) {
+        const double cs = A.cs_elem ? A.cs_elem[e] : A.cs;
+        const R mut = eddy_viscosity<R>(g, me[0], (R)(cs * cs * A.delta2));
+        mu += mut;
+        kap = fmaR((R)A.ktf, mut, kap);
+      }
       viscous_flux<0, R>(g, me[1], me[2], me[3], mu, kap, Fv[0]);
       viscous_flux<1, R>(g, me[1], me[2], me[3], mu, kap, Fv[1]);
       viscous_flux<2, R>(g, me[1], me[2], me[3], mu, kap, Fv[2]);
@@ -998,23 +1018,26 @@ __device__ __forceinline__ int face_index(int j, int i0, int i1, int i2) {
 }
 
 // Derivative along tangential axis j of the normal velocity u_d and of u_j at
-// node n (BR1: line sum with Dw plus the lifting term of axis j's faces).
-template <class R>
+// node n (BR1: line sum with Dw plus the lifting term of axis j's faces); with
+// THIRD also that of u_o (o: the other tangential axis).
+template <class R, bool THIRD = false>
 __device__ __forceinline__ void tangential_pair(const R (*sq)[nn], const R (*sQ)[4][nf], const R* sDw,
                                                 const R* swinv, int n, int d, int j, int i0, int i1, int i2,
-                                                R invJj, R& dud, R& duj) {
+                                                R invJj, R& dud, R& duj, int o = 0, R* duo = nullptr) {
   const int sj = axis_stride(j);
   const int id = j == 0 ? i0 : (j == 1 ? i1 : i2);
   const int base = n - id * sj;
   const R* crow = sDw + id * n1;
   const R* qd = sq[d];
   const R* qj = sq[j];
-  R s0 = 0, s1 = 0;
+  const R* qo = sq[o];
+  R s0 = 0, s1 = 0, s2 = 0;
 #pragma unroll 2
   for (int l = 0; l < n1; ++l) {
     const R c = crow[l];
     s0 = fmaR(c, qd[base + l * sj], s0);
     s1 = fmaR(c, qj[base + l * sj], s1);
+    if (THIRD) s2 = fmaR(c, qo[base + l * sj], s2);
   }
   if (id == 0 || id == N) {
     const int f = 2 * j + (id == N);
@@ -1022,17 +1045,20 @@ __device__ __forceinline__ void tangential_pair(const R (*sq)[nn], const R (*sQ)
     const int a = face_index(j, i0, i1, i2);
     s0 = fmaR(w, sQ[f][d][a], s0);
     s1 = fmaR(w, sQ[f][j][a], s1);
+    if (THIRD) s2 = fmaR(w, sQ[f][o][a], s2);
   }
   dud = invJj * s0;
   duj = invJj * s1;
+  if (THIRD) *duo = invJj * s2;
 }
 
 // Normal viscous flux at face node q of the element (face f = q / nf, normal
-// axis d), from sq = (u, v, w, theta) at the nodes and the interface values
-// sQ.  Only the eight gradient components it needs are formed: the
+// axis d), from sq = (u, v, w, theta[, rho]) at the nodes and the interface
+// values sQ.  Only the gradient components it needs are formed: the
 // derivatives along d of (u, v, w, theta) and, along each tangential axis j,
-// those of u_d and u_j.
-template <class R>
+// those of u_d and u_j (with the eddy viscosity also the third velocity
+// component, for the full strain rate).
+template <class R, bool LES>
 __device__ __forceinline__ void lift_face_node(const StageArgs& A, int e, const FaceItem& it, const R (*sq)[nn],
                                                const R (*sQ)[4][nf], const R* sB, const R invJ[3]) {
   const int n = it.nown, d = it.d;
@@ -1067,13 +1093,23 @@ __device__ __forceinline__ void lift_face_node(const StageArgs& A, int e, const 
   g1 *= Jd;
   g2 *= Jd;
   g3 *= Jd;
-  R da_ud, da_ua, db_ud, db_ub;
-  tangential_pair<R>(sq, sQ, sDw, swinv, n, d, ja, i0, i1, i2, ja == 0 ? invJ[0] : invJ[1], da_ud, da_ua);
-  tangential_pair<R>(sq, sQ, sDw, swinv, n, d, jb, i0, i1, i2, jb == 1 ? invJ[1] : invJ[2], db_ud, db_ub);
+  R da_ud, da_ua, db_ud, db_ub, da_ub = 0, db_ua = 0;
+  tangential_pair<R, LES>(sq, sQ, sDw, swinv, n, d, ja, i0, i1, i2, ja == 0 ? invJ[0] : invJ[1], da_ud, da_ua, jb,
+                          &da_ub);
+  tangential_pair<R, LES>(sq, sQ, sDw, swinv, n, d, jb, i0, i1, i2, jb == 1 ? invJ[1] : invJ[2], db_ud, db_ub, ja,
+                          &db_ua);
   const R dn_ud = d == 0 ? g0 : (d == 1 ? g1 : g2);
   const R dn_ua = ja == 0 ? g0 : g1;
   const R dn_ub = jb == 1 ? g1 : g2;
-  const R mu = (R)A.mu, kap = (R)A.kappa;
+  R mu = (R)A.mu, kap = (R)A.kappa;
+  if (LES) {  // strain rate from the full velocity gradient in the face frame
+    const R sa = dn_ua + da_ud, sb = dn_ub + db_ud, sc = da_ub + db_ua;
+    const R S2 = (R)2 * (dn_ud * dn_ud + da_ua * da_ua + db_ub * db_ub) + sa * sa + sb * sb + sc * sc;
+    const double cs = A.cs_elem ? A.cs_elem[e] : A.cs;
+    const R mut = sq[LES ? 4 : 0][n] * (R)(cs * cs * A.delta2) * sqrt_nonneg(S2);
+    mu += mut;
+    kap = fmaR((R)A.ktf, mut, kap);
+  }
   const R dv = (R)(2.0 / 3.0) * mu * (dn_ud + da_ua + db_ub);
   const R Fd = mu * (dn_ud + dn_ud) - dv;
   const R Fa = mu * (dn_ua + da_ud);
@@ -1088,14 +1124,13 @@ __device__ __forceinline__ void lift_face_node(const StageArgs& A, int e, const 
 }
 
 // Register budget of the lifting kernel: 8 waves per SIMD (64 VGPRs) with one
-// face item per thread, else 4; the
-// line sums with run-time strides are only partly unrolled so that the
-// partner loads in flight fit in it.
-template <class R>
+// face item per thread, else 4; the line sums with run-time strides are only
+// partly unrolled so that the partner loads in flight fit in it.
+template <class R, bool LES>
 __global__ __launch_bounds__(NT, FI == 1 && N >= 2 ? 8 : 4) void k_lift(StageArgs A) {
   constexpr bool MX = sizeof(R) == 4;
   __shared__ R sB[NB_STAGE];
-  __shared__ R sq[4][nn];  // u, v, w, theta
+  __shared__ R sq[LES ? 5 : 4][nn];  // u, v, w, theta (, rho)
   __shared__ R sQ[6][4][nf];
   const int e = element_of_block(blockIdx.x, A.chunk);
   if (e >= A.nelem) return;
@@ -1127,6 +1162,7 @@ __global__ __launch_bounds__(NT, FI == 1 && N >= 2 ? 8 : 4) void k_lift(StageArg
     sq[1][t] = P[2];
     sq[2][t] = P[3];
     sq[3][t] = P[6];
+    if (LES) sq[LES ? 4 : 0][t] = P[0];
   }
 #pragma unroll
   for (int k = 0; k < FI; ++k)
@@ -1134,7 +1170,7 @@ __global__ __launch_bounds__(NT, FI == 1 && N >= 2 ? 8 : 4) void k_lift(StageArg
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < FI; ++k)
-    if (t + k * NT < 6 * nf) lift_face_node<R>(A, e, its[k], sq, sQ, sB, invJ);
+    if (t + k * NT < 6 * nf) lift_face_node<R, LES>(A, e, its[k], sq, sQ, sB, invJ);
 }
 
 // ===========================================================================
@@ -1847,7 +1883,10 @@ inline int blocks_for(const StageArgs& A) { return 8 * A.chunk; }
 template <int VF, class R>
 hipError_t launch_stage_vf(const StageArgs& A, int eq, hipStream_t s) {
   const dim3 grid(blocks_for(A)), block(NT);
-  if (eq == 1) {
+  if (eq == 2) {
+    if constexpr (VF != VF_CH) hipLaunchKernelGGL((k_stage<VF, 2, false, R>), grid, block, 0, s, A);
+    else return hipErrorInvalidValue;
+  } else if (eq == 1) {
     hipLaunchKernelGGL((k_stage<VF, 1, false, R>), grid, block, 0, s, A);
   } else if (A.blend) {
     if constexpr (sizeof(R) == 8) hipLaunchKernelGGL((k_stage<VF, 0, true, double>), grid, block, 0, s, A);
@@ -1876,13 +1915,15 @@ hipError_t launch_stage_mixed(const StageArgs& A, int eq, hipStream_t s) {
   }
 }
 
-hipError_t launch_lift(const StageArgs& A, hipStream_t s) {
-  hipLaunchKernelGGL(k_lift<double>, dim3(blocks_for(A)), dim3(NT), 0, s, A);
+hipError_t launch_lift(const StageArgs& A, int eq, hipStream_t s) {
+  if (eq == 2) hipLaunchKernelGGL((k_lift<double, true>), dim3(blocks_for(A)), dim3(NT), 0, s, A);
+  else hipLaunchKernelGGL((k_lift<double, false>), dim3(blocks_for(A)), dim3(NT), 0, s, A);
   return hipGetLastError();
 }
 
-hipError_t launch_lift_mixed(const StageArgs& A, hipStream_t s) {
-  hipLaunchKernelGGL(k_lift<float>, dim3(blocks_for(A)), dim3(NT), 0, s, A);
+hipError_t launch_lift_mixed(const StageArgs& A, int eq, hipStream_t s) {
+  if (eq == 2) hipLaunchKernelGGL((k_lift<float, true>), dim3(blocks_for(A)), dim3(NT), 0, s, A);
+  else hipLaunchKernelGGL((k_lift<float, false>), dim3(blocks_for(A)), dim3(NT), 0, s, A);
   return hipGetLastError();
 }
 

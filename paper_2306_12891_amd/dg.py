@@ -30,7 +30,7 @@ FP64, MIXED = 0, 1
 EXPORTS = ["dg_default_options", "dg_init", "dg_set_options", "dg_get_options", "dg_set_stream",
            "dg_time_derivative", "rk_step", "dg_rk_steps", "dg_vjp", "rk_step_vjp", "dg_max_dt",
            "dg_integrals", "dg_alpha", "dg_check_finite", "dg_set_profiling", "dg_profile_read", "dg_node_weights",
-           "dg_sizes", "dg_finalize", "dg_last_error"]
+           "dg_sizes", "dg_finalize", "dg_last_error", "dg_set_cs_field"]
 
 
 class DGError(RuntimeError):
@@ -47,7 +47,8 @@ class Options(ctypes.Structure):
     _fields_ = [("equations", ctypes.c_int32), ("vol_flux", ctypes.c_int32), ("surf_flux", ctypes.c_int32),
                 ("blending", ctypes.c_int32), ("indicator", ctypes.c_int32), ("fv_recon", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32), ("Pr", ctypes.c_double),
-                ("alpha_min", ctypes.c_double), ("alpha_max", ctypes.c_double), ("alpha_spread", ctypes.c_double)]
+                ("alpha_min", ctypes.c_double), ("alpha_max", ctypes.c_double), ("alpha_spread", ctypes.c_double),
+                ("Cs", ctypes.c_double), ("Prt", ctypes.c_double)]
 
 
 _lib = None
@@ -83,6 +84,7 @@ def lib() -> ctypes.CDLL:
             "dg_sizes": ([P, P, P], I),
             "dg_finalize": ([P], I),
             "dg_last_error": ([P], ctypes.c_char_p),
+            "dg_set_cs_field": ([P, P], I),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -145,6 +147,19 @@ class DG:
             setattr(o, k, v)
         self._check(lib().dg_set_options(self._ctx, ctypes.byref(o)))
         self.options = o
+
+    def set_cs_field(self, cs: torch.Tensor | None):
+        """Per-element Smagorinsky coefficients (float64 GPU tensor of n_elems
+        values, copied), or None for the constant options.Cs."""
+        if cs is None:
+            self._check(lib().dg_set_cs_field(self._ctx, None))
+            return
+        if not isinstance(cs, torch.Tensor) or not cs.is_cuda or cs.dtype != torch.float64:
+            raise TypeError("cs must be a float64 GPU tensor")
+        if cs.numel() != self.n_elems or not cs.is_contiguous():
+            raise ValueError(f"cs must be contiguous with {self.n_elems} values")
+        self._stream()
+        self._check(lib().dg_set_cs_field(self._ctx, ctypes.c_void_p(cs.data_ptr())))
 
     def close(self):
         if getattr(self, "_ctx", None) is not None and self._ctx.value:

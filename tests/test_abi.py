@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_options_struct_layout():
     from paper_2306_12891_amd import dg
-    assert ctypes.sizeof(dg.Options) == 8 * 4 + 4 * 8
+    assert ctypes.sizeof(dg.Options) == 8 * 4 + 6 * 8
     assert ctypes.sizeof(dg.Mesh) == 3 * 4 + 4 + 6 * 8  # 4 bytes of padding before lo
 
 
@@ -48,6 +48,7 @@ def test_default_options_and_init_rejects_bad_arguments():
     o = dg.default_options()
     assert (o.equations, o.vol_flux, o.surf_flux, o.blending) == (0, 0, 0, 0)
     assert (o.alpha_min, o.alpha_max, o.alpha_spread, o.Pr) == (0.01, 0.7, 0.5, 0.72)
+    assert (o.Cs, o.Prt) == (0.0, 0.9)
     L = dg.lib()
     m = dg.Mesh()
     for d in range(3):

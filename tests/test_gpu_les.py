@@ -1,0 +1,109 @@
+"""Smagorinsky eddy viscosity on the GPU (constant and per-element C_s) against
+the FP64 oracle, through the C ABI: single evaluations to 1e-12 of the term
+scale, the mixed operator within its stated bound, a rollout, and the error
+paths (no adjoint through the model, host pointers, the CH flux)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2306_12891_amd import inputs as I
+from test_gpu_parity import G, TWO_PI, assert_state_close, assert_ut_close, gpu_ut
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def make(orc, N, nelem, vf, sf, mu, Cs, lo=(0, 0, 0), hi=(TWO_PI,) * 3, cs_elem=None, **gpu_opts):
+    from paper_2306_12891_amd import dg
+    s = orc.Setup(N=N, nelem=nelem, lo=lo, hi=hi, equations=1, vol_flux=vf, surf_flux=sf, mu=mu, Cs=Cs,
+                  cs_elem=cs_elem)
+    op = dg.DG(nelem, N, gamma=G, mu=mu, lo=lo, hi=hi, equations=dg.NS, vol_flux=vf, surf_flux=sf, Cs=Cs,
+               **gpu_opts)
+    return s, op
+
+
+@pytest.mark.parametrize("vf,sf", [(1, 1), (0, 0), (3, 2)])
+@pytest.mark.parametrize("N", [2, 3, 5, 7])
+def test_constant_coefficient(orc, torch_cuda, vf, sf, N):
+    nelem, lo, hi = (3, 2, 2), (0.0, 0.0, 0.0), (2.0, 1.5, 1.0)
+    s, op = make(orc, N, nelem, vf, sf, 2e-2, 0.3, lo, hi)
+    U = I.random_smooth(N, nelem, lo, hi, seed=60 + N, noise=0.02)
+    ref = orc.time_derivative(s, U)
+    assert_ut_close(gpu_ut(torch_cuda, op, U), ref, U, N, nelem, lo, hi)
+    # the model changes the result well above the tolerance
+    plain = orc.time_derivative(orc.Setup(N=N, nelem=nelem, lo=lo, hi=hi, equations=1, vol_flux=vf, surf_flux=sf,
+                                          mu=2e-2), U)
+    assert np.max(np.abs(plain - ref)) > 1e-6 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("N", [3, 5])
+def test_per_element_field(orc, torch_cuda, N):
+    import torch
+    nelem = (4, 3, 2)
+    cs = np.random.default_rng(70 + N).uniform(0.05, 0.4, 24)
+    s, op = make(orc, N, nelem, 1, 1, 1e-2, 0.0, cs_elem=cs)
+    U = I.random_smooth(N, nelem, seed=71 + N, noise=0.02)
+    csd = torch.from_numpy(cs).cuda()
+    op.set_cs_field(csd)
+    del csd  # copied by the library
+    ref = orc.time_derivative(s, U)
+    assert_ut_close(gpu_ut(torch_cuda, op, U), ref, U, N, nelem, (0, 0, 0), (TWO_PI,) * 3)
+    # back to the constant coefficient (0: plain Navier-Stokes)
+    op.set_cs_field(None)
+    s0 = orc.Setup(N=N, nelem=nelem, equations=1, vol_flux=1, surf_flux=1, mu=1e-2)
+    assert_ut_close(gpu_ut(torch_cuda, op, U), orc.time_derivative(s0, U), U, N, nelem, (0, 0, 0), (TWO_PI,) * 3)
+
+
+@pytest.mark.parametrize("N", [3, 5])
+def test_mixed_precision(orc, torch_cuda, N):
+    """Mixed operator with the model: within 2e-5 of the term scale, as for
+    plain Navier-Stokes."""
+    from paper_2306_12891_amd import dg
+    nelem = (2, 2, 2)
+    s, op = make(orc, N, nelem, 1, 1, 1e-2, 0.25, precision=dg.MIXED)
+    U = I.tgv(N, nelem, symmetry_break=True)
+    assert_ut_close(gpu_ut(torch_cuda, op, U), orc.time_derivative(s, U), U, N, nelem, (0, 0, 0), (TWO_PI,) * 3,
+                    tol=2e-5)
+
+
+def test_tgv_les_rollout(orc, torch_cuda):
+    import torch
+    N, nelem = 3, (3, 3, 3)
+    s, op = make(orc, N, nelem, 1, 1, 1.0 / 1600, 0.17)
+    U0 = I.tgv(N, nelem, symmetry_break=True)
+    Ud = torch.from_numpy(U0).cuda()
+    dt = op.max_dt(Ud, 0.5)
+    op.rk_steps(Ud, dt, 6)
+    assert_state_close(Ud.cpu().numpy(), orc.rk_steps(s, U0, dt, 6))
+
+
+def test_error_paths(orc, torch_cuda):
+    import ctypes
+
+    import torch
+
+    from paper_2306_12891_amd import dg
+    N, nelem = 2, (2, 2, 2)
+    _, op = make(orc, N, nelem, 1, 1, 1e-2, 0.2)
+    U = torch.from_numpy(I.random_smooth(N, nelem, seed=5)).cuda()
+    with pytest.raises(dg.DGError) as ei:
+        op.vjp(U, U.clone())
+    assert ei.value.code == dg.DG_EUNSUPPORTED
+    host = np.full(8, 0.1)
+    assert op.raw_call("dg_set_cs_field", ctypes.c_void_p(host.ctypes.data)) == dg.DG_EINVAL
+    with pytest.raises(dg.DGError) as ei:
+        op.set_options(Cs=-0.1)
+    assert ei.value.code == dg.DG_EINVAL
+    with pytest.raises(dg.DGError) as ei:
+        op.set_options(vol_flux=dg.CH)
+    assert ei.value.code == dg.DG_EUNSUPPORTED
+    op.set_options(Cs=0.0)
+    op.vjp(U, U.clone())  # plain Navier-Stokes again: the adjoint is available
