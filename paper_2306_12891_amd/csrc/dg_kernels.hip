@@ -1424,60 +1424,68 @@ __global__ __launch_bounds__(NT) void k_vjp_lift(VjpArgs A) {
   }
 }
 
-// Interface part of face item q: cotangent of the element's own face state,
-// (d f*/d U_own)^T fbar with fbar = -(2/dx_d)(lambda_- / w_N - lambda_+ / w_0),
-// by five dual-number evaluations; plus, for Navier-Stokes, q* (forward
-// gradient), the neighbour's lambda and its normal-gradient cotangent.
-template <int VF, bool NS, int D>
-__device__ __forceinline__ void vjp_face_item(const VjpArgs& A, int e, int q, const double* swinv,
-                                              double (*sSF)[5][nf], double (*sQ)[4][nf], double (*sLn)[4][nf],
-                                              double (*sGn)[4][nf]) {
+// Interface part of face item q, seed k: component k of the cotangent of the
+// element's own face state, (d f*/d U_own,k) . fbar with
+// fbar = -(2/dx_d)(lambda_- / w_N - lambda_+ / w_0), by one dual-number
+// evaluation of the interface flux.  Each (item, seed) pair is a separate
+// work unit: the five seeds share no registers.
+template <int VF, int D>
+__device__ __forceinline__ void vjp_face_seed(const VjpArgs& A, int e, int q, int k, const double* swinv,
+                                              double (*sSF)[5][nf]) {
   const int f = q / nf;
   const int a = q - f * nf;
   const int side = f & 1;  // 1: own element is the minus side of this face
   const int nb = A.nbr[6 * e + f];
-  const double* Ue = A.U + (size_t)e * 5 * nn;
-  const double* Un = A.U + (size_t)nb * 5 * nn;
-  const double* Le = A.Lbar + (size_t)e * 5 * nn;
-  const double* Ln = A.Lbar + (size_t)nb * 5 * nn;
-  const int nown = face_node(D, side ? N : 0, a);
-  const int nnb = face_node(D, side ? 0 : N, a);
-  double L[5], R[5], fb[5];
+  const int eL = side ? e : nb, eR = side ? nb : e;
+  const int nL = face_node(D, N, a), nR = face_node(D, 0, a);
+  const double* UL = A.U + (size_t)eL * 5 * nn;
+  const double* UR = A.U + (size_t)eR * 5 * nn;
+  const double* LL = A.Lbar + (size_t)eL * 5 * nn;
+  const double* LR = A.Lbar + (size_t)eR * 5 * nn;
   const double cm = -A.invJ[D] * swinv[N], cp = A.invJ[D] * swinv[0];
+  Dl Ld[5], Rd[5], fd[5];
+  double fb[5];
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
-    const double xo = Ue[v * nn + nown], xn = Un[v * nn + nnb];
-    L[v] = side ? xo : xn;
-    R[v] = side ? xn : xo;
-    const double lo = Le[v * nn + nown], ln = Ln[v * nn + nnb];
-    fb[v] = side ? fma(cm, lo, cp * ln) : fma(cm, ln, cp * lo);
+    Ld[v] = {UL[v * nn + nL], (side && v == k) ? 1.0 : 0.0};
+    Rd[v] = {UR[v * nn + nR], (!side && v == k) ? 1.0 : 0.0};
+    fb[v] = fma(cm, LL[v * nn + nL], cp * LR[v * nn + nR]);
   }
-#pragma unroll 1
-  for (int k = 0; k < 5; ++k) {
-    Dl Ld[5], Rd[5], fd[5];
+  riemann_generic<VF, D, Dl>(A.sf, Ld, Rd, A.gamma, fd);
+  double s = 0.0;
 #pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      Ld[v] = {L[v], (side && v == k) ? 1.0 : 0.0};
-      Rd[v] = {R[v], (!side && v == k) ? 1.0 : 0.0};
-    }
-    riemann_generic<VF, D, Dl>(A.sf, Ld, Rd, A.gamma, fd);
-    double s = 0.0;
+  for (int v = 0; v < 5; ++v) s = fma(fb[v], fd[v].d, s);
+  sSF[f][k][a] = s;
+}
+
+// Navier-Stokes data of face item q: q* (forward gradient), the neighbour's
+// lambda and its normal-gradient cotangent.
+template <int D>
+__device__ __forceinline__ void vjp_face_ns(const VjpArgs& A, int e, int q, double (*sQ)[4][nf],
+                                            double (*sLn)[4][nf], double (*sGn)[4][nf]) {
+  const int f = q / nf;
+  const int a = q - f * nf;
+  const int side = f & 1;
+  const int nb = A.nbr[6 * e + f];
+  const int eL = side ? e : nb, eR = side ? nb : e;
+  const int nL = face_node(D, N, a), nR = face_node(D, 0, a), nnb = side ? nR : nL;
+  double L[5], R[5];
 #pragma unroll
-    for (int v = 0; v < 5; ++v) s = fma(fb[v], fd[v].d, s);
-    sSF[f][k][a] = s;
+  for (int v = 0; v < 5; ++v) {
+    L[v] = A.U[((size_t)eL * 5 + v) * nn + nL];
+    R[v] = A.U[((size_t)eR * 5 + v) * nn + nR];
   }
-  if (NS) {
-    const double gm1 = A.gamma - 1.0;
-    const Ref ref{0.0, 0.0, 0.0};
-    double qs[4];
-    interface_q<D, double, false>(state64<D>(L, gm1), state64<D>(R, gm1), ref, qs);
-    const double* Gn = A.Gbf + ((size_t)nb * 6 + (f ^ 1)) * 4 * nf;
+  const double gm1 = A.gamma - 1.0;
+  const Ref ref{0.0, 0.0, 0.0};
+  double qs[4];
+  interface_q<D, double, false>(state64<D>(L, gm1), state64<D>(R, gm1), ref, qs);
+  const double* Ln = A.Lbar + (size_t)nb * 5 * nn;
+  const double* Gn = A.Gbf + ((size_t)nb * 6 + (f ^ 1)) * 4 * nf;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      sQ[f][c][a] = qs[c];
-      sLn[f][c][a] = Ln[(1 + c) * nn + nnb];
-      sGn[f][c][a] = Gn[c * nf + a];
-    }
+  for (int c = 0; c < 4; ++c) {
+    sQ[f][c][a] = qs[c];
+    sLn[f][c][a] = Ln[(1 + c) * nn + nnb];
+    sGn[f][c][a] = Gn[c * nf + a];
   }
 }
 
@@ -1523,7 +1531,7 @@ __device__ __forceinline__ void volume_vjp_dir(const double (*sP)[nn], const dou
                                                double pb[6]) {
   constexpr int st = D == 0 ? 1 : (D == 1 ? n1 : nf);
   const int base = n - id * st;
-#pragma unroll
+#pragma unroll 1
   for (int k = 1; k <= kPartners; ++k) {
     const int l = partner(id, k);
     const int m = base + l * st;
@@ -1574,10 +1582,21 @@ __global__ __launch_bounds__(NT) void k_vjp(VjpArgs A) {
     ijk[1] = (t / n1) % n1;
     ijk[2] = t / nf;
   }
-  for (int q = t; q < 6 * nf; q += NT) {
-    if (q < 2 * nf) vjp_face_item<VF, NS, 0>(A, e, q, swinv, sSF, sQ, sLn, sGn);
-    else if (q < 4 * nf) vjp_face_item<VF, NS, 1>(A, e, q, swinv, sSF, sQ, sLn, sGn);
-    else vjp_face_item<VF, NS, 2>(A, e, q, swinv, sSF, sQ, sLn, sGn);
+  // (face item, seed) work units, seed-major so that neighbouring lanes take
+  // neighbouring face nodes
+#pragma unroll 1
+  for (int w = t; w < 5 * 6 * nf; w += NT) {
+    const int k = w / (6 * nf), q = w - k * (6 * nf);
+    if (q < 2 * nf) vjp_face_seed<VF, 0>(A, e, q, k, swinv, sSF);
+    else if (q < 4 * nf) vjp_face_seed<VF, 1>(A, e, q, k, swinv, sSF);
+    else vjp_face_seed<VF, 2>(A, e, q, k, swinv, sSF);
+  }
+  if (NS) {
+    for (int q = t; q < 6 * nf; q += NT) {
+      if (q < 2 * nf) vjp_face_ns<0>(A, e, q, sQ, sLn, sGn);
+      else if (q < 4 * nf) vjp_face_ns<1>(A, e, q, sQ, sLn, sGn);
+      else vjp_face_ns<2>(A, e, q, sQ, sLn, sGn);
+    }
   }
   __syncthreads();
 
