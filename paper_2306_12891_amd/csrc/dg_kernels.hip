@@ -1428,34 +1428,38 @@ __global__ __launch_bounds__(NT) void k_vjp_lift(VjpArgs A) {
 // element's own face state, (d f*/d U_own,k) . fbar with
 // fbar = -(2/dx_d)(lambda_- / w_N - lambda_+ / w_0), by one dual-number
 // evaluation of the interface flux.  Each (item, seed) pair is a separate
-// work unit: the five seeds share no registers.
-template <int VF, int D>
+// work unit: the five seeds share no registers.  One code path for all
+// directions: states, seed and cotangent are rotated by address (normal
+// component first), the flux is evaluated in the rotated frame.
+template <int VF>
 __device__ __forceinline__ void vjp_face_seed(const VjpArgs& A, int e, int q, int k, const double* swinv,
                                               double (*sSF)[5][nf]) {
-  const int f = q / nf;
-  const int a = q - f * nf;
-  const int side = f & 1;  // 1: own element is the minus side of this face
-  const int nb = A.nbr[6 * e + f];
-  const int eL = side ? e : nb, eR = side ? nb : e;
-  const int nL = face_node(D, N, a), nR = face_node(D, 0, a);
+  const FaceItem it = face_item_geometry(A.nbr, e, q);
+  const int eL = it.side ? e : it.nb, eR = it.side ? it.nb : e;
+  const int nL = it.side ? it.nown : it.nnb, nR = it.side ? it.nnb : it.nown;
+  const int row[5] = {0, 1 + it.d, it.k1, it.k2, 4};  // rotated position -> variable
+  const int own = it.side;  // 1: own element is the minus side
   const double* UL = A.U + (size_t)eL * 5 * nn;
   const double* UR = A.U + (size_t)eR * 5 * nn;
   const double* LL = A.Lbar + (size_t)eL * 5 * nn;
   const double* LR = A.Lbar + (size_t)eR * 5 * nn;
-  const double cm = -A.invJ[D] * swinv[N], cp = A.invJ[D] * swinv[0];
+  const double invJd = it.d == 0 ? A.invJ[0] : (it.d == 1 ? A.invJ[1] : A.invJ[2]);
+  const double cm = -invJd * swinv[N], cp = invJd * swinv[0];
   Dl Ld[5], Rd[5], fd[5];
   double fb[5];
 #pragma unroll
-  for (int v = 0; v < 5; ++v) {
-    Ld[v] = {UL[v * nn + nL], (side && v == k) ? 1.0 : 0.0};
-    Rd[v] = {UR[v * nn + nR], (!side && v == k) ? 1.0 : 0.0};
-    fb[v] = fma(cm, LL[v * nn + nL], cp * LR[v * nn + nR]);
+  for (int r = 0; r < 5; ++r) {
+    const int v = row[r];
+    const double seed = v == k ? 1.0 : 0.0;
+    Ld[r] = {UL[v * nn + nL], own ? seed : 0.0};
+    Rd[r] = {UR[v * nn + nR], own ? 0.0 : seed};
+    fb[r] = fma(cm, LL[v * nn + nL], cp * LR[v * nn + nR]);
   }
-  riemann_generic<VF, D, Dl>(A.sf, Ld, Rd, A.gamma, fd);
+  riemann_generic<VF, 0, Dl>(A.sf, Ld, Rd, A.gamma, fd);
   double s = 0.0;
 #pragma unroll
-  for (int v = 0; v < 5; ++v) s = fma(fb[v], fd[v].d, s);
-  sSF[f][k][a] = s;
+  for (int r = 0; r < 5; ++r) s = fma(fb[r], fd[r].d, s);
+  sSF[it.f][k][it.a] = s;
 }
 
 // Navier-Stokes data of face item q: q* (forward gradient), the neighbour's
@@ -1587,9 +1591,7 @@ __global__ __launch_bounds__(NT) void k_vjp(VjpArgs A) {
 #pragma unroll 1
   for (int w = t; w < 5 * 6 * nf; w += NT) {
     const int k = w / (6 * nf), q = w - k * (6 * nf);
-    if (q < 2 * nf) vjp_face_seed<VF, 0>(A, e, q, k, swinv, sSF);
-    else if (q < 4 * nf) vjp_face_seed<VF, 1>(A, e, q, k, swinv, sSF);
-    else vjp_face_seed<VF, 2>(A, e, q, k, swinv, sSF);
+    vjp_face_seed<VF>(A, e, q, k, swinv, sSF);
   }
   if (NS) {
     for (int q = t; q < 6 * nf; q += NT) {
