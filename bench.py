@@ -252,6 +252,26 @@ def repeat_stats(nodes, steps, walls):
     return {"n": len(vals), "mean": float(np.mean(vals)), "min": float(np.min(vals)), "max": float(np.max(vals))}
 
 
+def measured_copy_bandwidth(torch, mib=4096, reps=10):
+    """Achievable HBM bandwidth on this device: a plain device-to-device copy
+    of a float64 buffer (read + write bytes over the event-timed copies)."""
+    n = mib * (1 << 20) // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        y.copy_(x)
+    b.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * n * 8 * reps / (a.elapsed_time(b) * 1e-3) / 1e9
+    del x, y
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def roofline(name, nodes, steps, prof):
     ms_stage, n_stage = prof["stage"]
     avg_ms = ms_stage / max(n_stage, 1)
@@ -360,6 +380,9 @@ def main():
     extra = {"repeats": repeat_stats(nodes, args.steps, walls)}
     if prof:
         roof = roofline(name, nodes, args.steps, prof)
+        copy_gbs = measured_copy_bandwidth(torch)
+        roof["measured_copy_GBs"] = round(copy_gbs, 1)
+        roof["frac_of_measured_copy"] = round(roof["achieved"] / copy_gbs, 4)
         extra["kernel_ms_per_step"] = {k: round(v[0] / args.steps, 4) for k, v in prof.items() if v[1]}
     path_bytes = 160.0 * nodes * 5 * args.steps
     extra["path_roofline_frac_160B"] = round(path_bytes / wall / 1e9 / HBM_PEAK_GBS, 4)

@@ -53,6 +53,10 @@ constexpr int n1 = N + 1;
 constexpr int nn = n1 * n1 * n1;
 constexpr int nf = n1 * n1;
 constexpr int NT = ((nn + 63) / 64) * 64;
+// Row stride of the stage kernel's node arrays in LDS: a multiple of 64
+// doubles (N >= 3), so that one base address reaches every row through the
+// 512-byte offset units of paired LDS reads.
+constexpr int nnp = N <= 2 ? nn : ((nn + 63) / 64) * 64;
 // smallest power of two >= NT (tree reductions over NT threads)
 constexpr int NTP2 = NT <= 64 ? 64 : (NT <= 128 ? 128 : (NT <= 256 ? 256 : 512));
 constexpr BasisLayout BL(n1);
@@ -407,12 +411,39 @@ __device__ __forceinline__ int partner(int id, int k) {
 }
 constexpr int kPartners = DG_SKIP_DIAG ? N : N + 1;
 
+// Calls body(l, m) for the partners l of node n (index id along a line of
+// stride ST starting at node base) in the order above.  ROLLED: a rolled loop
+// with the partner index and node advanced incrementally (one wrap test per
+// partner instead of the modulo and two address products).
+template <bool ROLLED, int ST, class F>
+__device__ __forceinline__ void partner_loop(int id, int n, int base, F&& body) {
+  if (ROLLED) {
+    int l = DG_SKIP_DIAG ? id : -1, m = DG_SKIP_DIAG ? n : base - ST;
+#pragma unroll 1
+    for (int k = 1; k <= kPartners; ++k) {
+      ++l;
+      m += ST;
+      if (l == n1) {
+        l = 0;
+        m = base;
+      }
+      body(l, m);
+    }
+  } else {
+#pragma unroll
+    for (int k = 1; k <= kPartners; ++k) {
+      const int l = partner(id, k);
+      body(l, base + l * ST);
+    }
+  }
+}
+
 // With GRAD, also returns gs[c] = sum_{l != id} Dw_{id l} q_c(l) along the line
 // (q = u, v, w, theta): the off-diagonal part of the BR1 gradient, which
 // reuses the partner values and coefficients the flux loop reads anyway
 // (off the diagonal Dw = D = Dhat / 2 exactly).
 template <int VF, int D, class R, bool GRAD = false>
-__device__ __forceinline__ void volume_dir(const R (*sP)[nn], const R* sDhat, int n, int id, const R me[7], R invJ,
+__device__ __forceinline__ void volume_dir(const R (*sP)[nnp], const R* sDhat, int n, int id, const R me[7], R invJ,
                                            R gm1, R acc[5], const R* sDw = nullptr, R* gs = nullptr) {
   constexpr int st = D == 0 ? 1 : (D == 1 ? n1 : nf);
   const int base = n - id * st;
@@ -430,9 +461,7 @@ __device__ __forceinline__ void volume_dir(const R (*sP)[nn], const R* sDhat, in
     // f_rho = fr4/4, f_m = fr4 us/8 + ps/2 e_D, f_E = fr4 xs/8 (+ ps und/4 for KG)
     // with sums s = a + b and fr4 = rho_s und_s.
     R s_fr = 0, s_m0 = 0, s_m1 = 0, s_m2 = 0, s_p = 0, s_E1 = 0, s_E2 = 0;
-    auto pair = [&](int k) {
-      const int l = partner(id, k);
-      const int m = base + l * st;
+    auto pair = [&](int l, int m) {
       const R c = crow[l];
       grad_acc(c, m);
       const R rs = me[0] + sP[0][m];
@@ -452,13 +481,7 @@ __device__ __forceinline__ void volume_dir(const R (*sP)[nn], const R* sDhat, in
       s_E1 = fmaR(cf, xs, s_E1);
       if (VF == VF_KG) s_E2 = fmaR(cp, und, s_E2);
     };
-    if (GRAD) {
-#pragma unroll 1
-      for (int k = 1; k <= kPartners; ++k) pair(k);
-    } else {
-#pragma unroll
-      for (int k = 1; k <= kPartners; ++k) pair(k);
-    }
+    partner_loop<GRAD, st>(id, n, base, pair);
     const R q4 = (R)0.25, q8 = (R)0.125, h2 = (R)0.5;
     acc[0] -= invJ * (q4 * s_fr);
     acc[1] -= invJ * (q8 * s_m0 + (D == 0 ? h2 * s_p : (R)0));
@@ -469,9 +492,7 @@ __device__ __forceinline__ void volume_dir(const R (*sP)[nn], const R* sDhat, in
     // F# = (F(a) + F(b))/2 with F_rho = rho u_D, F_m = rho u_D u + p e_D, F_E = rho h u_D
     const R mA = me[0] * me[1 + D];
     R s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0, sp = 0;
-    auto pair = [&](int k) {
-      const int l = partner(id, k);
-      const int m = base + l * st;
+    auto pair = [&](int l, int m) {
       const R c = crow[l];
       grad_acc(c, m);
       const R mB = sP[0][m] * sP[1 + D][m];
@@ -482,13 +503,7 @@ __device__ __forceinline__ void volume_dir(const R (*sP)[nn], const R* sDhat, in
       sp = fmaR(c, me[4] + sP[4][m], sp);
       s4 = fmaR(c, mA * me[5] + mB * sP[5][m], s4);
     };
-    if (GRAD) {
-#pragma unroll 1
-      for (int k = 1; k <= kPartners; ++k) pair(k);
-    } else {
-#pragma unroll
-      for (int k = 1; k <= kPartners; ++k) pair(k);
-    }
+    partner_loop<GRAD, st>(id, n, base, pair);
     const R h2 = (R)0.5;
     acc[0] -= invJ * (h2 * s0);
     acc[1] -= invJ * (h2 * (s1 + (D == 0 ? sp : (R)0)));
@@ -532,8 +547,8 @@ __device__ __forceinline__ void volume_dir(const R (*sP)[nn], const R* sDhat, in
 // BR1 lifted gradient at node n: g[d][c] = d q_c / d x_d, q = (u, v, w, theta).
 // sQ holds the interface values q* on the six faces of the element.
 // ---------------------------------------------------------------------------
-template <class R>
-__device__ __forceinline__ void lifted_gradient(const R (*sP)[nn], const R (*sQ)[4][nf], const R* sDw, const R* swinv,
+template <class R, int ROW = nn>
+__device__ __forceinline__ void lifted_gradient(const R (*sP)[ROW], const R (*sQ)[4][nf], const R* sDw, const R* swinv,
                                                 int n, const int ijk[3], const R invJ[3], R g[3][4]) {
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
@@ -597,7 +612,7 @@ __device__ __forceinline__ double minmod(double a, double b) {
 // slopes by minmod of divided differences between node positions for interior
 // subcells (outer subcells first order), first-order fallback if a face state
 // has rho <= 0 or p <= 0.  Returns the state at the right (plus) or left face.
-__device__ __forceinline__ void subcell_face_state(const double (*sP)[nn], int base, int st, int m, bool right,
+__device__ __forceinline__ void subcell_face_state(const double (*sP)[nnp], int base, int st, int m, bool right,
                                                    int recon, const double* sxi, const double* sedge, double w[5]) {
   const int mm = base + m * st;
   double c[5];
@@ -751,23 +766,23 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
   constexpr bool LES = (EQ == 2);
   constexpr bool MX = sizeof(R) == 4;
   static_assert(!(BLEND && MX), "the blended operator is FP64 only");
-  // LDS pool: primitives sP[7][nn], face fluxes sF[6][5][nf], and for
+  // LDS pool: primitives sP[7][nnp], face fluxes sF[6][5][nf], and for
   // Navier-Stokes the interface values sQ[6][4][nf] and the neighbours' normal
   // viscous fluxes sFn[6][4][nf].  The twelve viscous-flux components of all
-  // nodes are later exchanged through sV[12][nn], which overlays sP, sF and sQ
+  // nodes are later exchanged through sV[12][nnp], which overlays sP, sF and sQ
   // (all consumed by then) but not sFn.
-  constexpr int oF = 7 * nn, oQ = oF + 30 * nf, oFn = oQ + 24 * nf;
+  constexpr int oF = 7 * nnp, oQ = oF + 30 * nf, oFn = std::max(oQ + 24 * nf, 12 * nnp);
   constexpr int POOL = NS ? oFn + 24 * nf : oQ;
-  static_assert(!NS || 12 * nn <= oFn, "viscous exchange must not overlay sFn");
+  static_assert(!NS || 12 * nnp <= oFn, "viscous exchange must not overlay sFn");
   __shared__ R sPool[POOL];
   __shared__ R sB[NB_STAGE];
   __shared__ double sX[BLEND ? 5 : 1][BLEND ? nn : 1];
   __shared__ double sB64[BLEND ? NB_STAGE : 1];
-  R (*sP)[nn] = reinterpret_cast<R (*)[nn]>(sPool);
+  R (*sP)[nnp] = reinterpret_cast<R (*)[nnp]>(sPool);
   R (*sF)[5][nf] = reinterpret_cast<R (*)[5][nf]>(sPool + oF);
   R (*sQ)[4][nf] = reinterpret_cast<R (*)[4][nf]>(sPool + (NS ? oQ : 0));
   R (*sFn)[4][nf] = reinterpret_cast<R (*)[4][nf]>(sPool + (NS ? oFn : 0));
-  R (*sV)[nn] = reinterpret_cast<R (*)[nn]>(sPool);
+  R (*sV)[nnp] = reinterpret_cast<R (*)[nnp]>(sPool);
 
   const int e = element_of_block(blockIdx.x, A.chunk);
   if (e >= A.nelem) return;
@@ -840,7 +855,7 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
     if (NS) {
       R g[3][4];
       if (!FG) {
-        lifted_gradient<R>(sP, sQ, sDw, swinv, t, ijk, invJ, g);
+        lifted_gradient<R, nnp>(sP, sQ, sDw, swinv, t, ijk, invJ, g);
       } else {
       // BR1 gradient: line sums from the volume loop + diagonal + interface values
       const R qo[4] = {me[1], me[2], me[3], me[6]};
@@ -888,7 +903,7 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
       const double* sxi = sB64 + BL.xi();
       const double* sedge = sB64 + BL.edge();
       const double* swinv64 = sB64 + BL.winv();
-      const double (*sP64)[nn] = reinterpret_cast<const double (*)[nn]>(sP);
+      const double (*sP64)[nnp] = reinterpret_cast<const double (*)[nnp]>(sP);
       const double (*sF64)[5][nf] = reinterpret_cast<const double (*)[5][nf]>(sF);
       double fv[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
