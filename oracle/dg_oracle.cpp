@@ -624,84 +624,87 @@ static void viscous_dg(const Ctx& c, const T* U, T* Ut) {
 
 // ---------------------------------------------------------------------------
 // Modal indicator and blending coefficient (paper Sec. 4.1 indicator eq.,
-// neighbour spread; Sec. 4.2 bounds).  Always FP64 on the state's values.
+// neighbour spread; Sec. 4.2 bounds), templated on the scalar so that dual
+// numbers differentiate through the coefficient.
 // reading: q = rho p; energies on orthonormal tensor Legendre modes;
 // E = max(E_N, E_{N-1}) (Hennemann) or E_N (Persson); s = ln(9999);
 // order clip -> zero -> spread over the 6 face neighbours -> zero.
+// Derivative conventions at the switches: the clip applies when a0 > alpha_max
+// and the cut-off when a < alpha_min (strict, derivative 0 there); maxima take
+// the mean derivative at ties (max_), evaluated in the order written.
 // ---------------------------------------------------------------------------
 static double threshold_T(int N) { return 0.5 * std::pow(10.0, -1.8 * std::pow(N + 1.0, 0.25)); }
 static const double kSharpness = 9.210240366975849;
 
 // Per-element indicator E and first-stage coefficient a1 (before spreading).
 template <class T>
-static void indicator_pass(const Ctx& c, const T* U, std::vector<double>& E, std::vector<double>& a1) {
+static void indicator_pass(const Ctx& c, const T* U, std::vector<T>& E, std::vector<T>& a1) {
   const Basis& b = c.b;
   const int n1 = c.n1, N = c.N;
-  E.assign(c.nelem, 0.0);
-  a1.assign(c.nelem, 0.0);
+  E.assign(c.nelem, T(0.0));
+  a1.assign(c.nelem, T(0.0));
   const double Tn = threshold_T(N);
 #pragma omp parallel for schedule(static)
   for (int e = 0; e < c.nelem; ++e) {
-    std::vector<double> q(c.nn), t1(c.nn), t2(c.nn), qh(c.nn);
+    std::vector<T> q(c.nn), t1(c.nn), t2(c.nn), qh(c.nn);
     for (int n = 0; n < c.nn; ++n) {
       T u[5];
       load_state(c, U, e, n, u);
-      double uv[5];
-      for (int v = 0; v < 5; ++v) uv[v] = value(u[v]);
-      const Prim<double> P = primitive(uv, c.s.gamma);
+      const Prim<T> P = primitive(u, c.s.gamma);
       q[n] = P.rho * P.p;
     }
     // qhat_{abc} = sum_{ijk} Vinv_{ai} Vinv_{bj} Vinv_{ck} q_{ijk}, one direction at a time
     for (int k = 0; k < n1; ++k)
       for (int j = 0; j < n1; ++j)
         for (int a = 0; a < n1; ++a) {
-          double s = 0.0;
+          T s = T(0.0);
           for (int i = 0; i < n1; ++i) s += b.Vinv[a * n1 + i] * q[node(c, i, j, k)];
           t1[node(c, a, j, k)] = s;
         }
     for (int k = 0; k < n1; ++k)
       for (int bb = 0; bb < n1; ++bb)
         for (int a = 0; a < n1; ++a) {
-          double s = 0.0;
+          T s = T(0.0);
           for (int j = 0; j < n1; ++j) s += b.Vinv[bb * n1 + j] * t1[node(c, a, j, k)];
           t2[node(c, a, bb, k)] = s;
         }
     for (int cc = 0; cc < n1; ++cc)
       for (int bb = 0; bb < n1; ++bb)
         for (int a = 0; a < n1; ++a) {
-          double s = 0.0;
+          T s = T(0.0);
           for (int k = 0; k < n1; ++k) s += b.Vinv[cc * n1 + k] * t2[node(c, a, bb, k)];
           qh[node(c, a, bb, cc)] = s;
         }
     // S_m = sum of qhat^2 over modes with max(a, b, c) <= m
-    double S[3] = {0.0, 0.0, 0.0};  // S_N, S_{N-1}, S_{N-2}
+    T S[3] = {T(0.0), T(0.0), T(0.0)};  // S_N, S_{N-1}, S_{N-2}
     for (int n = 0; n < c.nn; ++n) {
       int abc[3];
       coords(c, n, abc);
       const int m = std::max(abc[0], std::max(abc[1], abc[2]));
-      const double e2 = qh[n] * qh[n];
+      const T e2 = qh[n] * qh[n];
       S[0] += e2;
       if (m <= N - 1) S[1] += e2;
       if (m <= N - 2) S[2] += e2;
     }
-    const double EN = S[0] > 0.0 ? (S[0] - S[1]) / S[0] : 0.0;
-    const double EN1 = S[1] > 0.0 ? (S[1] - S[2]) / S[1] : 0.0;
-    const double Ee = (c.s.indicator == IND_PERSSON) ? EN : std::max(EN, EN1);
+    const T EN = value(S[0]) > 0.0 ? (S[0] - S[1]) / S[0] : T(0.0);
+    const T EN1 = value(S[1]) > 0.0 ? (S[1] - S[2]) / S[1] : T(0.0);
+    const T Ee = (c.s.indicator == IND_PERSSON) ? EN : max_(EN, EN1);
     E[e] = Ee;
-    const double a0 = 1.0 / (1.0 + std::exp(-(kSharpness / Tn) * (Ee - Tn)));
-    double a = std::min(a0, c.s.alpha_max);
-    if (a < c.s.alpha_min) a = 0.0;
+    const T a0 = 1.0 / (1.0 + exp_(-(kSharpness / Tn) * (Ee - Tn)));
+    T a = value(a0) > c.s.alpha_max ? T(c.s.alpha_max) : a0;
+    if (value(a) < c.s.alpha_min) a = T(0.0);
     a1[e] = a;
   }
 }
 
-static void spread_alpha(const Ctx& c, const std::vector<double>& a1, std::vector<double>& alpha) {
-  alpha.assign(c.nelem, 0.0);
+template <class T>
+static void spread_alpha(const Ctx& c, const std::vector<T>& a1, std::vector<T>& alpha) {
+  alpha.assign(c.nelem, T(0.0));
   for (int e = 0; e < c.nelem; ++e) {
-    double m = 0.0;
-    for (int f = 0; f < 6; ++f) m = std::max(m, a1[c.nbr[6 * e + f]]);
-    double a = std::max(a1[e], c.s.alpha_spread * m);
-    if (a < c.s.alpha_min) a = 0.0;
+    T m = T(0.0);
+    for (int f = 0; f < 6; ++f) m = max_(m, a1[c.nbr[6 * e + f]]);
+    T a = max_(a1[e], c.s.alpha_spread * m);
+    if (value(a) < c.s.alpha_min) a = T(0.0);
     alpha[e] = a;
   }
 }
@@ -792,12 +795,14 @@ static void time_derivative(const Ctx& c, const T* U, T* Ut, const double* alpha
   surface_pass(c, U, fstar);
   std::vector<T> Udg(tot), Ufv;
   advective_dg(c, U, fstar, Udg.data());
-  std::vector<double> alpha;
+  std::vector<T> alpha;
   const bool blend = c.s.blending != 0 || alpha_in != nullptr;
   if (blend) {
-    if (alpha_in) alpha.assign(alpha_in, alpha_in + c.nelem);
-    else {
-      std::vector<double> E, a1;
+    if (alpha_in) {
+      alpha.resize(c.nelem);
+      for (int e = 0; e < c.nelem; ++e) alpha[e] = T(alpha_in[e]);
+    } else {
+      std::vector<T> E, a1;
       indicator_pass(c, U, E, a1);
       spread_alpha(c, a1, alpha);
     }
@@ -805,13 +810,14 @@ static void time_derivative(const Ctx& c, const T* U, T* Ut, const double* alpha
     fv_subcell(c, U, fstar, Ufv.data());
   }
   for (int e = 0; e < c.nelem; ++e) {
-    const double a = blend ? alpha[e] : 0.0;
+    const T a = blend ? alpha[e] : T(0.0);
     for (size_t k = size_t(e) * 5 * c.nn; k < size_t(e + 1) * 5 * c.nn; ++k)
       Ut[k] = blend ? (1.0 - a) * Udg[k] + a * Ufv[k] : Udg[k];
   }
   if (Ut_dg_out) std::copy(Udg.begin(), Udg.end(), Ut_dg_out);
   if (Ut_fv_out && blend) std::copy(Ufv.begin(), Ufv.end(), Ut_fv_out);
-  if (alpha_out && blend) std::copy(alpha.begin(), alpha.end(), alpha_out);
+  if (alpha_out && blend)
+    for (int e = 0; e < c.nelem; ++e) alpha_out[e] = value(alpha[e]);
   if (c.s.equations == EQ_NS) viscous_dg(c, U, Ut);
 }
 
@@ -1282,7 +1288,8 @@ int or_lserk4_linear(int n, const double* A, double* u, double dt, int nsteps) {
 }
 
 // Jacobian-vector product of the operator: Ut = F(U), JV = F'(U) V.
-// With blending on, alpha is held at its value (no derivative through it).
+// With blending on, the derivative includes that of the blending coefficient
+// (see the conventions of the indicator above).
 int or_jvp(const Setup* s, const double* U, const double* V, double* Ut, double* JV) {
   if (!valid(s)) return -1;
   const Ctx c = make_ctx(*s);

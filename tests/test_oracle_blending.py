@@ -302,3 +302,35 @@ def test_sod_blended_converges(orc):
         errs.append(wq)
         assert rho.min() > 0.125 - 0.02 and rho.max() < 1.0 + 0.02
     assert errs[1] < 0.75 * errs[0], errs
+
+
+def blended_noisy_state(N=3, nelem=(3, 3, 2)):
+    """Smooth state with element-wise scaled node noise: blending coefficients
+    strictly inside (alpha_min, alpha_max), from the elements' own indicator
+    and from the neighbour spread, with no ties."""
+    base = I.random_smooth(N, nelem, seed=12, amp=0.1)
+    ne = int(np.prod(nelem))
+    fac = np.random.default_rng(5).uniform(0.2, 1.0, ne)[:, None, None, None, None]
+    return base * (1 + np.random.default_rng(99).standard_normal(base.shape) * 0.05 * fac)
+
+
+def test_jvp_through_blending_matches_central_differences(orc):
+    """The dual-number JVP of the blended operator includes the derivative of
+    the blending coefficient (indicator sigmoid, clip, spread) and of the
+    minmod reconstruction; central differences (eps = 1e-6) agree to 1e-7 of
+    max |J v|.  With alpha held fixed the result differs by the alpha part."""
+    N, nelem = 3, (3, 3, 2)
+    s = orc.Setup(N=N, nelem=nelem, blending=1, fv_recon=orc.FV_MINMOD, vol_flux=orc.KG, surf_flux=orc.LLF)
+    U = blended_noisy_state(N, nelem)
+    _, _, al = orc.alpha(s, U)
+    assert np.sum((al > 0.02) & (al < 0.69)) >= 6
+    eps = 1e-6
+    for k in range(2):
+        v = I.random_directions(U.shape, k)
+        _, Jv = orc.jvp(s, U, v)
+        fd = (orc.time_derivative(s, U + eps * v) - orc.time_derivative(s, U - eps * v)) / (2 * eps)
+        scale = np.max(np.abs(Jv))
+        assert np.max(np.abs(fd - Jv)) <= 1e-7 * scale
+        fixed = (orc.time_derivative(s, U + eps * v, alpha=al) - orc.time_derivative(s, U - eps * v, alpha=al)) / (
+            2 * eps)
+        assert np.max(np.abs(fixed - Jv)) > 1e-2 * scale
