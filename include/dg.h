@@ -151,9 +151,15 @@ int dg_rk_steps(dg_ctx* ctx, double* U, double dt, int nsteps);
 
 /* Vector-Jacobian product of the operator: U_bar = (dL/dU)^T Ut_bar (the
  * reverse mode of dg_time_derivative, for gradients of functionals of the
- * solution).  Overwrites U_bar, which must not alias U or Ut_bar.  Not
- * available with blending, DG_MIXED or the CH flux (DG_EUNSUPPORTED).
- * Allocates the reverse-mode face buffer on first use. */
+ * solution).  Overwrites U_bar, which must not alias U or Ut_bar.  With
+ * blending (Euler) the product includes the dependence of the blending
+ * coefficient on U (paper Sec. 4.1: indicator sigmoid, clip and neighbour
+ * spread) and of the FV subcell reconstruction; at their switches the
+ * one-sided rules are: derivative 0 where the coefficient is clipped or cut
+ * off, the mean derivative at ties of a maximum, the selected slope of the
+ * minmod limiter.  Not available with DG_MIXED, the CH flux or the
+ * Smagorinsky model (DG_EUNSUPPORTED).  Allocates the reverse-mode face
+ * buffer (and with blending two more buffers) on first use. */
 int dg_vjp(dg_ctx* ctx, const double* U, const double* Ut_bar, double* U_bar);
 
 /* Vector-Jacobian product of one rk_step: U_bar_n = (dU_{n+1}/dU_n)^T U_bar_np1,

@@ -183,6 +183,9 @@ struct dg_ctx {
   double* Gbar = nullptr;
   double* Ybar = nullptr;
   double* Gbf = nullptr;
+  // reverse mode through the blending: U_t^FV - U_t^DG and the cotangent of alpha
+  double* Dfd = nullptr;
+  double* abar = nullptr;
   char err[256] = "";
   // kernel timing (dg_set_profiling)
   int profiling = 0;
@@ -234,6 +237,8 @@ void release(dg_ctx* c) {
   hipFree(c->Gbar);
   hipFree(c->Ybar);
   hipFree(c->Gbf);
+  hipFree(c->Dfd);
+  hipFree(c->abar);
 }
 
 StageArgs stage_args(const dg_ctx* c) {
@@ -352,7 +357,6 @@ int run_stage(dg_ctx* c, const double* Xin, double* Xout, double* Ut, int mode, 
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
 int vjp_supported(dg_ctx* c) {
-  if (c->opt.blending) return fail(c, DG_EUNSUPPORTED, "vjp: not available with blending");
   if (eq_code(c) == 2) return fail(c, DG_EUNSUPPORTED, "vjp: not available with the Smagorinsky model");
   if (c->opt.precision != DG_FP64) return fail(c, DG_EUNSUPPORTED, "vjp: FP64 operator only");
   if (c->opt.vol_flux == DG_VF_CH) return fail(c, DG_EUNSUPPORTED, "vjp: not available for the CH flux");
@@ -364,6 +368,8 @@ int ensure_reverse_buffers(dg_ctx* c, bool rk) {
   hipError_t e = hipSuccess;
   const size_t bytes = c->nstate * sizeof(double);
   if (!c->Gbf) e = hipMalloc((void**)&c->Gbf, (size_t)c->nelem * 6 * 4 * c->nf * sizeof(double));
+  if (e == hipSuccess && c->opt.blending && !c->Dfd) e = hipMalloc((void**)&c->Dfd, bytes);
+  if (e == hipSuccess && c->opt.blending && !c->abar) e = hipMalloc((void**)&c->abar, (size_t)c->nelem * sizeof(double));
   if (rk) {
     for (int k = 0; k < 5 && e == hipSuccess; ++k)
       if (!c->Y[k]) e = hipMalloc((void**)&c->Y[k], bytes);
@@ -399,6 +405,29 @@ int run_vjp(dg_ctx* c, const double* U, const double* lambda, double* U_bar, con
   v.vf = c->opt.vol_flux;
   v.sf = c->opt.surf_flux;
   hipError_t e;
+  if (c->opt.blending) {
+    // forward at U: blending coefficients and U_t^FV - U_t^DG
+    if ((rc = run_stage(c, U, nullptr, c->Dfd, MODE_DIFF, 0.0, 0.0, 0, c->alpha))) return rc;
+    const StageArgs a = stage_args(c);
+    v.alpha = c->alpha;
+    v.alpha1 = c->alpha1;
+    v.Dfd = c->Dfd;
+    v.abar = c->abar;
+    v.amin = a.amin;
+    v.amax = a.amax;
+    v.aspread = a.aspread;
+    v.thresh = a.thresh;
+    v.sharp = a.sharp;
+    v.indicator = a.indicator;
+    v.recon = a.recon;
+    e = timed(c, DG_K_VJP, [&] { return c->kt->vjp_alpha_bar(v, c->stream); });
+    if (e != hipSuccess) return hip_fail(c, e, "vjp blending-coefficient kernel");
+    e = timed(c, DG_K_VJP, [&] { return c->kt->vjp_alpha(v, c->stream); });  // U_bar = [Uacc +] alpha part
+    if (e != hipSuccess) return hip_fail(c, e, "vjp blending-coefficient kernel");
+    e = timed(c, DG_K_VJP, [&] { return c->kt->vjp_fv(v, c->stream); });  // U_bar += FV part
+    if (e != hipSuccess) return hip_fail(c, e, "vjp FV subcell kernel");
+    v.Uacc = U_bar;  // the DG part accumulates on top
+  }
   if (c->opt.equations == DG_NS) {
     e = timed(c, DG_K_VJP_LIFT, [&] { return c->kt->vjp_lift(v, c->stream); });
     if (e != hipSuccess) return hip_fail(c, e, "vjp lifting kernel");

@@ -6,7 +6,9 @@
 
 namespace dgmi {
 
-enum { MODE_UT = 0, MODE_RK = 1 };
+// MODE_DIFF (blended Euler operator): U_t^FV - U_t^DG of blended elements
+// (zero elsewhere) into Ut, for the reverse mode through the blending.
+enum { MODE_UT = 0, MODE_RK = 1, MODE_DIFF = 2 };
 
 // Packed 1-D basis, built on the host and read into LDS by the kernels.
 // Offsets in doubles for n1 = N + 1.
@@ -69,6 +71,15 @@ struct VjpArgs {
   double gamma, mu, kappa;
   int nelem, chunk;
   int vf, sf;
+  // blending (Euler): final and first-stage coefficients of the linearisation
+  // state, the differences U_t^FV - U_t^DG (MODE_DIFF) and the per-element
+  // cotangent of alpha; all NULL without blending
+  const double* alpha;
+  const double* alpha1;
+  const double* Dfd;
+  double* abar;
+  double amin, amax, aspread, thresh, sharp;
+  int indicator, recon;
 };
 
 struct KernelTable {
@@ -84,6 +95,12 @@ struct KernelTable {
   hipError_t (*nonfinite)(const ReduceArgs&, hipStream_t);
   hipError_t (*vjp)(const VjpArgs&, int eq, hipStream_t);
   hipError_t (*vjp_lift)(const VjpArgs&, hipStream_t);
+  // reverse mode through the blending: per-element cotangent of alpha, its
+  // pullback to the state (writes Ubar = [Uacc +] ...), and the FV subcell
+  // part (adds to Ubar)
+  hipError_t (*vjp_alpha_bar)(const VjpArgs&, hipStream_t);
+  hipError_t (*vjp_alpha)(const VjpArgs&, hipStream_t);
+  hipError_t (*vjp_fv)(const VjpArgs&, hipStream_t);
   // y <- a y + b x over n doubles
   hipError_t (*axpby)(double* y, double a, const double* x, double b, size_t n, hipStream_t);
 };

@@ -934,8 +934,16 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
           }
         }
       }
+      if (A.mode == MODE_DIFF) {
 #pragma unroll
-      for (int v = 0; v < 5; ++v) acc[v] = (R)((1.0 - al) * (double)acc[v] + al * fv[v]);
+        for (int v = 0; v < 5; ++v) acc[v] = (R)(fv[v] - (double)acc[v]);
+      } else {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) acc[v] = (R)((1.0 - al) * (double)acc[v] + al * fv[v]);
+      }
+    } else if (A.mode == MODE_DIFF) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) acc[v] = (R)0;
     }
   }
 
@@ -997,7 +1005,7 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
     for (int v = 0; v < 5; ++v) ut[v] = (double)acc[v];
     if (MX) ut[4] += ref.h * ut[0];  // undo the energy-flux shift h0 * (mass flux)
     const size_t o = (size_t)e * 5 * nn + t;
-    if (A.mode == MODE_UT) {
+    if (A.mode != MODE_RK) {  // MODE_UT, MODE_DIFF
 #pragma unroll
       for (int v = 0; v < 5; ++v) A.Ut[o + v * nn] = ut[v];
     } else {
@@ -1625,6 +1633,11 @@ __global__ __launch_bounds__(NT) void k_vjp(VjpArgs A) {
     volume_vjp_dir<VF, 0>(sP, sLam, sDhat, t, ijk[0], me, lam, A.invJ[0], pb);
     volume_vjp_dir<VF, 1>(sP, sLam, sDhat, t, ijk[1], me, lam, A.invJ[1], pb);
     volume_vjp_dir<VF, 2>(sP, sLam, sDhat, t, ijk[2], me, lam, A.invJ[2], pb);
+    if (!NS && A.alpha) {  // blended: the DG volume term enters with weight 1 - alpha
+      const double wv = 1.0 - A.alpha[e];
+#pragma unroll
+      for (int i = 0; i < 6; ++i) pb[i] *= wv;
+    }
     if (NS) {
       double Fvb[3][4], g[3][4];
       viscous_flux_cotangent(sLam, sLn, sDw, swinv, t, ijk, A.invJ, Fvb);
@@ -1724,6 +1737,353 @@ __global__ __launch_bounds__(NT) void k_vjp(VjpArgs A) {
     const size_t o = (size_t)e * 5 * nn + t;
 #pragma unroll
     for (int v = 0; v < 5; ++v) A.Ubar[o + v * nn] = A.Uacc ? A.Uacc[o + v * nn] + out[v] : out[v];
+  }
+}
+
+// ===========================================================================
+// Reverse mode through the DG/FV blending (Euler).  The surface terms of the
+// DG and FV operators coincide (outer subcells first order), so
+//   U_t = (1 - a) V_DG + a V_FV + S(f*),
+//   U_bar = V_DG^T((1 - a) lambda) + V_FV^T(a lambda) + S^T lambda + (da/dU)^T abar,
+//   abar_e = sum over the nodes of e of lambda . (U_t^FV - U_t^DG).
+// k_vjp weights its volume part by 1 - a; the kernels below give the
+// coefficient and FV parts.  Conventions at switches as in the forward-mode
+// reference: clip when a0 > alpha_max, cut-off when a < alpha_min (derivative
+// 0), maxima with the mean derivative at ties in the order evaluated, minmod
+// through the selected slope (mean at ties), positivity fallback through the
+// selected branch.
+// ===========================================================================
+__global__ __launch_bounds__(NT) void k_vjp_alpha_bar(VjpArgs A) {
+  __shared__ double sred[NT];
+  const int e = element_of_block(blockIdx.x, A.chunk);
+  if (e >= A.nelem) return;
+  const int t = threadIdx.x;
+  if (A.alpha[e] == 0.0) {  // uniform over the workgroup
+    if (t == 0) A.abar[e] = 0.0;
+    return;
+  }
+  double s = 0.0;
+  if (t < nn) {
+    const size_t o = (size_t)e * 5 * nn + t;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) s = fma(A.Lbar[o + v * nn], A.Dfd[o + v * nn], s);
+  }
+  sred[t] = s;
+  __syncthreads();
+  for (int h = NTP2 / 2; h > 0; h >>= 1) {
+    if (t < h && t + h < NT) sred[t] += sred[t + h];
+    __syncthreads();
+  }
+  if (t == 0) A.abar[e] = sred[0];
+}
+
+// d alpha_j / d alpha1_e (j, e: elements; j is e or a face neighbour of e).
+__device__ double spread_weight(const VjpArgs& A, int j, int e) {
+  if (A.alpha[j] == 0.0) return 0.0;  // cut off: flat
+  double m = 0.0, w[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    const double x = A.alpha1[A.nbr[6 * j + f]];
+    if (x > m) {
+#pragma unroll
+      for (int g = 0; g < 6; ++g) w[g] = g == f ? 1.0 : 0.0;
+      m = x;
+    } else if (!(m > x)) {  // tie
+#pragma unroll
+      for (int g = 0; g < 6; ++g) w[g] = g == f ? 0.5 : 0.5 * w[g];
+    }
+  }
+  const double a1 = A.alpha1[j], sm = A.aspread * m;
+  const double ws = a1 > sm ? 1.0 : (sm > a1 ? 0.0 : 0.5);
+  double r = j == e ? ws : 0.0;
+#pragma unroll
+  for (int f = 0; f < 6; ++f)
+    if (A.nbr[6 * j + f] == e) r += (1.0 - ws) * A.aspread * w[f];
+  return r;
+}
+
+// U_bar = [Uacc +] (d alpha / d U)^T abar: pullback through the spread (a
+// gather over the element and its neighbours), the clip, the sigmoid, the
+// modal energies E_N, E_{N-1} of q = rho p and q(U).
+__global__ __launch_bounds__(NT) void k_vjp_alpha(VjpArgs A) {
+  __shared__ double sV[nf];
+  __shared__ double sq[nn];
+  __shared__ double st[nn];
+  __shared__ double sred[3][NT];
+  __shared__ double sa1b;
+  const int e = element_of_block(blockIdx.x, A.chunk);
+  if (e >= A.nelem) return;
+  const int t = threadIdx.x;
+  for (int q = t; q < nf; q += NT) sV[q] = A.basis[BL.Vinv() + q];
+  if (t == 0) {
+    int cand[7] = {e, A.nbr[6 * e], A.nbr[6 * e + 1], A.nbr[6 * e + 2], A.nbr[6 * e + 3], A.nbr[6 * e + 4],
+                   A.nbr[6 * e + 5]};
+    double r = 0.0;
+    for (int i = 0; i < 7; ++i) {
+      bool dup = false;
+      for (int k = 0; k < i; ++k) dup = dup || cand[k] == cand[i];
+      if (!dup) r += A.abar[cand[i]] * spread_weight(A, cand[i], e);
+    }
+    sa1b = r;
+  }
+  const double* Ue = A.U + (size_t)e * 5 * nn;
+  const double gm1 = A.gamma - 1.0;
+  int ijk[3] = {0, 0, 0};
+  double u[5], rho = 1.0, p = 0.0;
+  if (t < nn) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) u[v] = Ue[v * nn + t];
+    const double ir = 1.0 / u[0];
+    p = gm1 * (u[4] - 0.5 * ir * (u[1] * u[1] + u[2] * u[2] + u[3] * u[3]));
+    rho = u[0];
+    sq[t] = u[0] * p;
+    ijk[0] = t % n1;
+    ijk[1] = (t / n1) % n1;
+    ijk[2] = t / nf;
+  }
+  __syncthreads();
+  // forward modal transform (as k_alpha1), keeping the node's coefficient
+  if (t < nn) {
+    const int base = t - ijk[0];
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < n1; ++i) s = fma(sV[ijk[0] * n1 + i], sq[base + i], s);
+    st[t] = s;
+  }
+  __syncthreads();
+  if (t < nn) {
+    const int base = t - ijk[1] * n1;
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < n1; ++j) s = fma(sV[ijk[1] * n1 + j], st[base + j * n1], s);
+    sq[t] = s;
+  }
+  __syncthreads();
+  double qh = 0.0, e2 = 0.0;
+  int mx = 0;
+  if (t < nn) {
+    const int base = t - ijk[2] * nf;
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < n1; ++k) s = fma(sV[ijk[2] * n1 + k], sq[base + k * nf], s);
+    qh = s;
+    e2 = s * s;
+    mx = max(ijk[0], max(ijk[1], ijk[2]));
+  }
+  sred[0][t] = e2;
+  sred[1][t] = (mx == N) ? e2 : 0.0;
+  sred[2][t] = (mx == N - 1) ? e2 : 0.0;
+  __syncthreads();
+  for (int h = NTP2 / 2; h > 0; h >>= 1) {
+    if (t < h && t + h < NT) {
+      sred[0][t] += sred[0][t + h];
+      sred[1][t] += sred[1][t + h];
+      sred[2][t] += sred[2][t + h];
+    }
+    __syncthreads();
+  }
+  const double S = sred[0][0], SN = sred[1][0], SN1 = sred[2][0];
+  const double EN = S > 0.0 ? SN / S : 0.0;
+  const double Rr = S - SN;
+  const double EN1 = Rr > 0.0 ? SN1 / Rr : 0.0;
+  const double E = A.indicator == 1 ? EN : fmax(EN, EN1);
+  const double k = A.sharp / A.thresh;
+  const double a0 = 1.0 / (1.0 + exp(-k * (E - A.thresh)));
+  // uniform: no derivative when cut off or clipped
+  const bool live = sa1b != 0.0 && A.alpha1[e] != 0.0 && !(a0 > A.amax);
+  const double Eb = live ? sa1b * k * a0 * (1.0 - a0) : 0.0;
+  const double wN = A.indicator == 1 ? 1.0 : (EN > EN1 ? 1.0 : (EN1 > EN ? 0.0 : 0.5));
+  const double ENb = Eb * wN, EN1b = Eb * (1.0 - wN);
+  double e2b = 0.0;
+  if (S > 0.0) e2b += ENb * ((mx == N ? 1.0 : 0.0) - EN) / S;
+  if (Rr > 0.0) e2b += EN1b * ((mx == N - 1 ? 1.0 : 0.0) - (mx <= N - 1 ? EN1 : 0.0)) / Rr;
+  __syncthreads();
+  // transposed modal transform of qhat_bar = 2 qhat e2_bar: z, y, x
+  if (t < nn) sq[t] = 2.0 * qh * e2b;
+  __syncthreads();
+  if (t < nn) {
+    const int base = t - ijk[2] * nf;
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < n1; ++c) s = fma(sV[c * n1 + ijk[2]], sq[base + c * nf], s);
+    st[t] = s;
+  }
+  __syncthreads();
+  if (t < nn) {
+    const int base = t - ijk[1] * n1;
+    double s = 0.0;
+#pragma unroll
+    for (int b = 0; b < n1; ++b) s = fma(sV[b * n1 + ijk[1]], st[base + b * n1], s);
+    sq[t] = s;
+  }
+  __syncthreads();
+  if (t < nn) {
+    const int base = t - ijk[0];
+    double qb = 0.0;
+#pragma unroll
+    for (int a = 0; a < n1; ++a) qb = fma(sV[a * n1 + ijk[0]], sq[base + a], qb);
+    // q = rho p, p = (g-1)(E - |m|^2 / (2 rho))
+    const double rb = qb * p, pb = qb * rho;
+    const double ir = 1.0 / rho;
+    const double vx = u[1] * ir, vy = u[2] * ir, vz = u[3] * ir;
+    const double out[5] = {rb + gm1 * pb * 0.5 * (vx * vx + vy * vy + vz * vz), -gm1 * pb * vx, -gm1 * pb * vy,
+                           -gm1 * pb * vz, gm1 * pb};
+    const size_t o = (size_t)e * 5 * nn + t;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) A.Ubar[o + v * nn] = A.Uacc ? A.Uacc[o + v * nn] + out[v] : out[v];
+  }
+}
+
+// FV subcell part: U_bar += V_FV^T(a lambda) for blended elements.  Per
+// direction: the interior subcell fluxes F_{m+1/2} = f*(w+_m, w-_{m+1}) are
+// differentiated with respect to the ten primitive components of their two
+// reconstructed states by one dual-number evaluation per (interface, seed)
+// work unit (rotated frame, one code path for all directions); the
+// reconstruction (minmod, positivity fallback) is pulled back along each
+// line per variable.
+template <int VF>
+__global__ __launch_bounds__(NT) void k_vjp_fv(VjpArgs A) {
+  __shared__ double sB[NB_STAGE];
+  __shared__ double sW[5][nnp];  // primitives rho, u, v, w, p
+  __shared__ double sL[5][nn];   // lambda
+  __shared__ double sWb[5][nn];  // primitive cotangent
+  __shared__ double sG[N * nf][10];
+  const int e = element_of_block(blockIdx.x, A.chunk);
+  if (e >= A.nelem) return;
+  const double al = A.alpha[e];
+  if (al == 0.0) return;  // uniform: pure DG element
+  const int t = threadIdx.x;
+  const double gm1 = A.gamma - 1.0;
+  for (int q = t; q < NB_STAGE; q += NT) sB[q] = A.basis[q];
+  const double* sxi = sB + BL.xi();
+  const double* sedge = sB + BL.edge();
+  const double* swinv = sB + BL.winv();
+  const Ref ref{0.0, 0.0, 0.0};
+  double u[5], me[7];
+  if (t < nn) {
+    const size_t o = (size_t)e * 5 * nn + t;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      u[v] = A.U[o + v * nn];
+      sL[v][t] = A.Lbar[o + v * nn];
+      sWb[v][t] = 0.0;
+    }
+    primitives<VF, double, false>(u, gm1, ref, me);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) sW[v][t] = me[v];
+  }
+  for (int d = 0; d < 3; ++d) {
+    const int st = d == 0 ? 1 : (d == 1 ? n1 : nf);
+    const int c1 = d == 2 ? 0 : d + 1, c2 = d == 0 ? 2 : (d == 1 ? 0 : 1);  // tangential velocity (cyclic)
+    __syncthreads();
+#pragma unroll 1
+    for (int w = t; w < 10 * N * nf; w += NT) {
+      const int k = w / (N * nf), i = w - k * (N * nf);
+      const int m = i / nf, a = i - m * nf;
+      const int nm = face_node(d, m, a), base = nm - m * st;
+      double wp[5], wm[5];
+      subcell_face_state(sW, base, st, m, true, A.recon, sxi, sedge, wp);
+      subcell_face_state(sW, base, st, m + 1, false, A.recon, sxi, sedge, wm);
+      // flux cotangent (conservative, rotated): a (2/dx_d)(lambda_{m+1}/w_{m+1} - lambda_m/w_m)
+      const double invJd = d == 0 ? A.invJ[0] : (d == 1 ? A.invJ[1] : A.invJ[2]);
+      const int np = nm + st;
+      const int row[5] = {0, 1 + d, 1 + c1, 1 + c2, 4};
+      double fb[5];
+#pragma unroll
+      for (int r = 0; r < 5; ++r)
+        fb[r] = al * invJd * (sL[row[r]][np] * swinv[m + 1] - sL[row[r]][nm] * swinv[m]);
+      // dual primitive states, then conservative in the rotated frame
+      Dl W[2][5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        W[0][v] = {wp[v], k == v ? 1.0 : 0.0};
+        W[1][v] = {wm[v], k == 5 + v ? 1.0 : 0.0};
+      }
+      Dl C[2][5];
+#pragma unroll
+      for (int sd = 0; sd < 2; ++sd) {
+        const Dl r = W[sd][0];
+        const Dl un = d == 0 ? W[sd][1] : (d == 1 ? W[sd][2] : W[sd][3]);
+        const Dl u1 = c1 == 0 ? W[sd][1] : (c1 == 1 ? W[sd][2] : W[sd][3]);
+        const Dl u2 = c2 == 0 ? W[sd][1] : (c2 == 1 ? W[sd][2] : W[sd][3]);
+        C[sd][0] = r;
+        C[sd][1] = r * un;
+        C[sd][2] = r * u1;
+        C[sd][3] = r * u2;
+        C[sd][4] = W[sd][4] * (1.0 / gm1) + 0.5 * r * (W[sd][1] * W[sd][1] + W[sd][2] * W[sd][2] +
+                                                       W[sd][3] * W[sd][3]);
+      }
+      Dl fd[5];
+      riemann_generic<VF, 0, Dl>(A.sf, C[0], C[1], A.gamma, fd);
+      double s = 0.0;
+#pragma unroll
+      for (int r = 0; r < 5; ++r) s = fma(fb[r], fd[r].d, s);
+      sG[i][k] = s;
+    }
+    __syncthreads();
+    // pullback of the reconstruction, per (line, variable)
+    for (int w = t; w < 5 * nf; w += NT) {
+      const int v = w / nf, a = w - v * nf;
+      const int base = face_node(d, 0, a);
+      double wb[n1];
+#pragma unroll
+      for (int m = 0; m < n1; ++m) wb[m] = 0.0;
+#pragma unroll
+      for (int m = 0; m < n1; ++m) {
+        const double gp = m < N ? sG[m * nf + a][v] : 0.0;       // cotangent of w+_m
+        const double gmv = m > 0 ? sG[(m - 1) * nf + a][5 + v] : 0.0;  // of w-_m
+        wb[m] += gp + gmv;
+        if (A.recon == 1 && m >= 1 && m <= N - 1) {
+          const int mm = base + m * st;
+          const double hl = 1.0 / (sxi[m] - sxi[m - 1]);
+          const double hr = 1.0 / (sxi[m + 1] - sxi[m]);
+          const double dp = sedge[m + 1] - sxi[m], dm = sedge[m] - sxi[m];
+          // positivity flag of subcell m (as in subcell_face_state)
+          const double c0 = sW[0][mm], c4 = sW[4][mm];
+          const double s0 = minmod((c0 - sW[0][mm - st]) * hl, (sW[0][mm + st] - c0) * hr);
+          const double s4 = minmod((c4 - sW[4][mm - st]) * hl, (sW[4][mm + st] - c4) * hr);
+          const bool ok = (c0 + s0 * dp > 0.0) && (c4 + s4 * dp > 0.0) && (c0 + s0 * dm > 0.0) && (c4 + s4 * dm > 0.0);
+          if (ok) {
+            const double sb = gp * dp + gmv * dm;  // cotangent of the slope
+            const double cv = sW[v][mm];
+            const double sl = (cv - sW[v][mm - st]) * hl, sr = (sW[v][mm + st] - cv) * hr;
+            double bl = 0.0, br = 0.0;
+            if (sl * sr > 0.0) {
+              const bool pick_l = sl > 0.0 ? sl < sr : sl > sr;
+              const bool pick_r = sl > 0.0 ? sr < sl : sr > sl;
+              if (pick_l) bl = sb;
+              else if (pick_r) br = sb;
+              else {
+                bl = 0.5 * sb;
+                br = 0.5 * sb;
+              }
+            }
+            wb[m] += bl * hl - br * hr;
+            wb[m - 1] -= bl * hl;
+            wb[m + 1] += br * hr;
+          }
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < n1; ++m) sWb[v][base + m * st] += wb[m];
+    }
+  }
+  __syncthreads();
+  if (t < nn) {
+    // primitives (rho, u, v, w, p) -> conservative
+    const double ir = rcp64(u[0]);
+    const double vx = me[1], vy = me[2], vz = me[3];
+    const double pb = sWb[4][t];
+    const double ub[3] = {sWb[1][t], sWb[2][t], sWb[3][t]};
+    double out[5];
+    out[0] = sWb[0][t] - (ub[0] * vx + ub[1] * vy + ub[2] * vz) * ir + gm1 * pb * 0.5 * (vx * vx + vy * vy + vz * vz);
+    out[1] = ub[0] * ir - gm1 * pb * vx;
+    out[2] = ub[1] * ir - gm1 * pb * vy;
+    out[3] = ub[2] * ir - gm1 * pb * vz;
+    out[4] = gm1 * pb;
+    const size_t o = (size_t)e * 5 * nn + t;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) A.Ubar[o + v * nn] += out[v];
   }
 }
 
@@ -2000,6 +2360,27 @@ hipError_t launch_vjp(const VjpArgs& A, int eq, hipStream_t s) {
   }
 }
 
+hipError_t launch_vjp_alpha_bar(const VjpArgs& A, hipStream_t s) {
+  hipLaunchKernelGGL(k_vjp_alpha_bar, dim3(8 * A.chunk), dim3(NT), 0, s, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_vjp_alpha(const VjpArgs& A, hipStream_t s) {
+  hipLaunchKernelGGL(k_vjp_alpha, dim3(8 * A.chunk), dim3(NT), 0, s, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_vjp_fv(const VjpArgs& A, hipStream_t s) {
+  const dim3 grid(8 * A.chunk), block(NT);
+  switch (A.vf) {
+    case VF_KG: hipLaunchKernelGGL(k_vjp_fv<VF_KG>, grid, block, 0, s, A); break;
+    case VF_PI: hipLaunchKernelGGL(k_vjp_fv<VF_PI>, grid, block, 0, s, A); break;
+    case VF_STD: hipLaunchKernelGGL(k_vjp_fv<VF_STD>, grid, block, 0, s, A); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_vjp_lift(const VjpArgs& A, hipStream_t s) {
   hipLaunchKernelGGL(k_vjp_lift, dim3(8 * A.chunk), dim3(NT), 0, s, A);
   return hipGetLastError();
@@ -2018,7 +2399,8 @@ hipError_t launch_nonfinite(const ReduceArgs& R, hipStream_t s) {
 
 const KernelTable kTable = {
     NT, launch_stage, launch_stage_mixed, launch_lift, launch_lift_mixed, launch_alpha1, launch_spread,
-    launch_max_rate, launch_integrals, launch_nonfinite, launch_vjp, launch_vjp_lift, launch_axpby,
+    launch_max_rate, launch_integrals, launch_nonfinite, launch_vjp, launch_vjp_lift, launch_vjp_alpha_bar,
+    launch_vjp_alpha, launch_vjp_fv, launch_axpby,
 };
 
 }  // namespace
