@@ -81,10 +81,10 @@ def domain(name):
 # calibration (FETCH x 2.000, WRITE x 1.000); see profiles/k_stage_*.md.  Valid
 # only for the kernel source they were taken on (sha256 prefix).
 MEASURED_TRAFFIC = {
-    "kernel_sha": "3507ab3d785d1b90",
+    "kernel_sha": "5962c1ae78074f16",
     "tgv_n5_32": {"bytes_per_launch": 1380.3e6, "fetch": 870.7e6, "write": 509.6e6},
-    "tgv_n7_64": {"bytes_per_launch": 26682.5e6, "fetch": 17018.8e6, "write": 9663.7e6},
-    "freestream_euler_n7_64": {"bytes_per_launch": 22897.9e6, "fetch": 13234.2e6, "write": 9663.7e6},
+    "tgv_n7_64": {"bytes_per_launch": 26683.2e6, "fetch": 17019.5e6, "write": 9663.7e6},
+    "freestream_euler_n7_64": {"bytes_per_launch": 22908.9e6, "fetch": 13245.2e6, "write": 9663.7e6},
 }
 
 
@@ -298,6 +298,27 @@ def blended_fraction(torch, op, U0, dt, steps, every=50):
     return out
 
 
+def blended_adjoint_timing(torch, op, U, reps=20):
+    """One reverse-mode product through the blending (coefficient chain, FV
+    subcells, weighted DG) against one operator evaluation, wall time."""
+    lam = torch.ones_like(U)
+
+    def wall(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    t_op = wall(lambda: op.time_derivative(U))
+    t_vjp = wall(lambda: op.vjp(U, lam))
+    a = op.alpha(U)
+    return {"operator_ms": t_op * 1e3, "vjp_ms": t_vjp * 1e3, "vjp_over_operator": t_vjp / t_op,
+            "blended_fraction": float((a > 0).double().mean().item())}
+
+
 def sweep(torch, dg, spec, steps, warmup, repeats):
     """Freestream throughput over 2^15 ... 2^21 elements (N = 7)."""
     N, _, eq, vf, sf, mu, blend, _ = spec
@@ -390,6 +411,8 @@ def main():
     extra["finite_after_run"] = finite
     if blend:
         extra["blended_fraction"] = blended_fraction(torch, op, U_init, dt, args.warmup + args.steps * repeats)
+        if not args.no_adjoint:
+            extra["blended_adjoint"] = blended_adjoint_timing(torch, op, U)
 
     # Mixed-precision operator on the same workload: same initial state, same
     # warm-up and timed steps; error of the final state against the FP64 run.
