@@ -693,8 +693,52 @@ __device__ __forceinline__ void face_loads(const double* U, int e, const FaceIte
   load_rotated(U + (size_t)eR * 5 * nn, nR, it, R);
 }
 
-// Face items handled by one thread (item q = t + k NT, k < FI).
-constexpr int FI = (6 * nf + NT - 1) / NT;
+// Elements per workgroup (EPB) of the stage and lifting kernels.  With one
+// element per workgroup, N = 5 fills 216 of 256 lanes (the last wave is 3/8
+// full) and a wave instruction costs the same whatever its active lanes; two
+// elements fill 432 of 448.  Each element owns a slot of TPE consecutive
+// threads (node t and face item t of slot s is thread s TPE + t); the slots
+// share the basis in LDS and every barrier.  Measured at N = 5: the lifting
+// kernel gains 6 % with two elements; the stage kernel loses 17 % (its LDS then
+// admits two workgroups per CU instead of four), so it keeps one.
+#ifndef DG_EPB_STAGE
+#define DG_EPB_STAGE 1
+#endif
+#ifndef DG_EPB_LIFT
+#define DG_EPB_LIFT (DG_N == 5 ? 2 : 1)
+#endif
+template <int E>
+struct Pack {
+  static constexpr int EPB = E;
+  static constexpr int TPE = E == 1 ? NT : (nn > 6 * nf ? nn : 6 * nf);
+  static constexpr int NTB = ((E * TPE + 63) / 64) * 64;
+  // face items handled by one thread of a slot (item q = t + k TPE, k < FI)
+  static constexpr int FI = (6 * nf + TPE - 1) / TPE;
+  static_assert(E >= 1 && NTB <= 1024, "workgroup size");
+};
+using PS = Pack<DG_EPB_STAGE>;
+using PL = Pack<DG_EPB_LIFT>;
+
+// Slot of the calling thread: element e (clamped to a valid one), its thread
+// index t within the slot, and t = TPE (beyond every per-thread bound: nodes,
+// face items) for threads without an element: the padding of the last wave
+// and the second slot of a workgroup past the last element.
+struct Slot {
+  int s, e, t, traw;
+  bool live;
+};
+template <class P>
+__device__ __forceinline__ Slot slot_of_thread(int e0, int nelem) {
+  Slot r;
+  const int tid = threadIdx.x;
+  const int s0 = P::EPB == 1 ? 0 : tid / P::TPE;
+  r.s = s0 < P::EPB ? s0 : P::EPB - 1;
+  r.live = s0 < P::EPB && e0 + r.s < nelem;
+  r.e = r.live ? e0 + r.s : e0;
+  r.traw = tid - s0 * P::TPE;
+  r.t = r.live ? r.traw : P::TPE;
+  return r;
+}
 
 // Loads of one face item, issued together before any of them is used: both
 // rotated states and (Navier-Stokes) the neighbour's normal viscous flux.
@@ -755,10 +799,14 @@ __device__ __forceinline__ void face_item(const StageArgs& A, const FaceData<NS,
 // EQ: 0 Euler, 1 Navier-Stokes, 2 Navier-Stokes with the Smagorinsky eddy
 // viscosity.  R: arithmetic type (double, or float for the mixed operator, MX).
 // ---------------------------------------------------------------------------
+// Several elements per workgroup: two workgroups per CU need 4 waves per SIMD
+// (at most 128 registers); not imposed on the CH flux, which would spill.
 #if DG_STAGE_MIN_WAVES > 0
-#define DG_STAGE_BOUNDS __launch_bounds__(NT, DG_STAGE_MIN_WAVES)
+#define DG_STAGE_BOUNDS __launch_bounds__(PS::NTB, DG_STAGE_MIN_WAVES)
+#elif DG_EPB_STAGE > 1
+#define DG_STAGE_BOUNDS __launch_bounds__(PS::NTB, VF == VF_CH ? 1 : 4)
 #else
-#define DG_STAGE_BOUNDS __launch_bounds__(NT)
+#define DG_STAGE_BOUNDS __launch_bounds__(PS::NTB)
 #endif
 template <int VF, int EQ, bool BLEND, class R>
 __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
@@ -774,42 +822,46 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
   constexpr int oF = 7 * nnp, oQ = oF + 30 * nf, oFn = std::max(oQ + 24 * nf, 12 * nnp);
   constexpr int POOL = NS ? oFn + 24 * nf : oQ;
   static_assert(!NS || 12 * nnp <= oFn, "viscous exchange must not overlay sFn");
-  __shared__ R sPool[POOL];
+  constexpr int EPB = PS::EPB, TPE = PS::TPE, FI = PS::FI;
+  __shared__ R sPoolAll[EPB][POOL];
   __shared__ R sB[NB_STAGE];
-  __shared__ double sX[BLEND ? 5 : 1][BLEND ? nn : 1];
+  __shared__ double sXAll[EPB][BLEND ? 5 : 1][BLEND ? nn : 1];
   __shared__ double sB64[BLEND ? NB_STAGE : 1];
+
+  const int e0 = EPB * element_of_block(blockIdx.x, A.chunk);
+  if (e0 >= A.nelem) return;  // uniform over the workgroup
+  const Slot sl = slot_of_thread<PS>(e0, A.nelem);
+  const int e = sl.e, t = sl.t, tid = threadIdx.x;
+  R* sPool = sPoolAll[sl.s];
+  double (*sX)[BLEND ? nn : 1] = sXAll[sl.s];
   R (*sP)[nnp] = reinterpret_cast<R (*)[nnp]>(sPool);
   R (*sF)[5][nf] = reinterpret_cast<R (*)[5][nf]>(sPool + oF);
   R (*sQ)[4][nf] = reinterpret_cast<R (*)[4][nf]>(sPool + (NS ? oQ : 0));
   R (*sFn)[4][nf] = reinterpret_cast<R (*)[4][nf]>(sPool + (NS ? oFn : 0));
   R (*sV)[nnp] = reinterpret_cast<R (*)[nnp]>(sPool);
-
-  const int e = element_of_block(blockIdx.x, A.chunk);
-  if (e >= A.nelem) return;
-  const int t = threadIdx.x;
   const double gm1 = A.gamma - 1.0;
   // Memory round trip 1: neighbour indices of the thread's face items, the
   // node state and the basis.
   FaceData<NS, R> fd[FI];
 #pragma unroll
   for (int k = 0; k < FI; ++k)
-    if (t + k * NT < 6 * nf) fd[k].it = face_item_geometry(A.nbr, e, t + k * NT);
+    if (t + k * TPE < 6 * nf) fd[k].it = face_item_geometry(A.nbr, e, t + k * TPE);
   const double* Ue = A.U + (size_t)e * 5 * nn;
   double u[5], gprev[5];
   if (t < nn) {
 #pragma unroll
     for (int v = 0; v < 5; ++v) u[v] = Ue[v * nn + t];
   }
-  static_assert(NB_STAGE <= NT, "one basis entry per thread");
-  const double bval = t < NB_STAGE ? A.basis[t] : 0.0;
+  static_assert(NB_STAGE <= PS::NTB, "one basis entry per thread");
+  const double bval = tid < NB_STAGE ? A.basis[tid] : 0.0;
   const Ref ref = MX ? reference_state(A.U, gm1) : Ref{0.0, 0.0, 0.0};
   // Round trip 2: the face states (needs the neighbour indices).
 #pragma unroll
   for (int k = 0; k < FI; ++k)
-    if (t + k * NT < 6 * nf) face_issue<NS, R>(A, e, fd[k]);
-  if (t < NB_STAGE) {
-    sB[t] = (R)bval;
-    if (BLEND) sB64[t] = bval;
+    if (t + k * TPE < 6 * nf) face_issue<NS, R>(A, e, fd[k]);
+  if (tid < NB_STAGE) {
+    sB[tid] = (R)bval;
+    if (BLEND) sB64[tid] = bval;
   }
   const R* sDhat = sB + BL.Dhat();
   const R* sDw = sB + BL.Dw();
@@ -829,7 +881,7 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
   }
 #pragma unroll
   for (int k = 0; k < FI; ++k)
-    if (t + k * NT < 6 * nf) face_item<VF, NS, R, MX>(A, fd[k], ref, sF, sQ, sFn);
+    if (t + k * TPE < 6 * nf) face_item<VF, NS, R, MX>(A, fd[k], ref, sF, sQ, sFn);
   __syncthreads();
 
   R acc[5] = {0, 0, 0, 0, 0};
@@ -899,7 +951,18 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
       if (al < A.amin) al = 0.0;
       if (t == 0 && A.alpha_out) A.alpha_out[e] = al;
     }
-    if (al > 0.0) {  // uniform over the workgroup
+    // The subcell pass holds barriers: it runs when any element of the
+    // workgroup is blended, each slot doing its work only if its own is.
+    bool run = al > 0.0;
+    if (EPB > 1) {
+      __shared__ int sAny[EPB];
+      if (sl.traw == 0 && threadIdx.x < EPB * TPE) sAny[sl.s] = sl.live && al > 0.0;
+      __syncthreads();
+      run = false;
+#pragma unroll
+      for (int k = 0; k < EPB; ++k) run = run || sAny[k] != 0;
+    }
+    if (run) {  // uniform over the workgroup
       const double* sxi = sB64 + BL.xi();
       const double* sedge = sB64 + BL.edge();
       const double* swinv64 = sB64 + BL.winv();
@@ -910,7 +973,7 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
       for (int d = 0; d < 3; ++d) {
         const int st = d == 0 ? 1 : (d == 1 ? n1 : nf);
         __syncthreads();
-        if (t < nn && ijk[d] < N) {
+        if (t < nn && ijk[d] < N && al > 0.0) {
           const int base = t - ijk[d] * st;
           double wl[5], wr[5], UL[5], UR[5], fs[5];
           subcell_face_state(sP64, base, st, ijk[d], true, A.recon, sxi, sedge, wl);
@@ -922,7 +985,7 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
           for (int v = 0; v < 5; ++v) sX[v][t] = fs[v];
         }
         __syncthreads();
-        if (t < nn) {
+        if (t < nn && al > 0.0) {
           const int id = ijk[d];
           const int a = d == 0 ? ijk[1] + n1 * ijk[2] : (d == 1 ? ijk[0] + n1 * ijk[2] : ijk[0] + n1 * ijk[1]);
           const double c = A.invJ[d] * swinv64[id];
@@ -934,7 +997,12 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
           }
         }
       }
-      if (A.mode == MODE_DIFF) {
+      if (!(al > 0.0)) {
+        if (A.mode == MODE_DIFF) {
+#pragma unroll
+          for (int v = 0; v < 5; ++v) acc[v] = (R)0;
+        }
+      } else if (A.mode == MODE_DIFF) {
 #pragma unroll
         for (int v = 0; v < 5; ++v) acc[v] = (R)(fv[v] - (double)acc[v]);
       } else {
@@ -1150,33 +1218,37 @@ __device__ __forceinline__ void lift_face_node(const StageArgs& A, int e, const 
 // face item per thread, else 4; the line sums with run-time strides are only
 // partly unrolled so that the partner loads in flight fit in it.
 template <class R, bool LES>
-__global__ __launch_bounds__(NT, FI == 1 && N >= 2 ? 8 : 4) void k_lift(StageArgs A) {
+__global__ __launch_bounds__(PL::NTB, PL::FI == 1 && N >= 2 ? 8 : 4) void k_lift(StageArgs A) {
   constexpr bool MX = sizeof(R) == 4;
+  constexpr int EPB = PL::EPB, TPE = PL::TPE, FI = PL::FI;
   __shared__ R sB[NB_STAGE];
-  __shared__ R sq[LES ? 5 : 4][nn];  // u, v, w, theta (, rho)
-  __shared__ R sQ[6][4][nf];
-  const int e = element_of_block(blockIdx.x, A.chunk);
-  if (e >= A.nelem) return;
-  const int t = threadIdx.x;
+  __shared__ R sqAll[EPB][LES ? 5 : 4][nn];  // u, v, w, theta (, rho)
+  __shared__ R sQAll[EPB][6][4][nf];
+  const int e0 = EPB * element_of_block(blockIdx.x, A.chunk);
+  if (e0 >= A.nelem) return;  // uniform over the workgroup
+  const Slot sl = slot_of_thread<PL>(e0, A.nelem);
+  const int e = sl.e, t = sl.t, tid = threadIdx.x;
+  R (*sq)[nn] = sqAll[sl.s];
+  R (*sQ)[4][nf] = sQAll[sl.s];
   const double gm1 = A.gamma - 1.0;
   // Round trip 1: neighbour indices, node state, basis; round trip 2: face states.
   FaceItem its[FI];
 #pragma unroll
   for (int k = 0; k < FI; ++k)
-    if (t + k * NT < 6 * nf) its[k] = face_item_geometry(A.nbr, e, t + k * NT);
+    if (t + k * TPE < 6 * nf) its[k] = face_item_geometry(A.nbr, e, t + k * TPE);
   const double* Ue = A.U + (size_t)e * 5 * nn;
   double u[5];
   if (t < nn) {
 #pragma unroll
     for (int v = 0; v < 5; ++v) u[v] = Ue[v * nn + t];
   }
-  const double bval = t < NB_STAGE ? A.basis[t] : 0.0;
+  const double bval = tid < NB_STAGE ? A.basis[tid] : 0.0;
   const Ref ref = MX ? reference_state(A.U, gm1) : Ref{0.0, 0.0, 0.0};
   double FL[FI][5], FR[FI][5];
 #pragma unroll
   for (int k = 0; k < FI; ++k)
-    if (t + k * NT < 6 * nf) face_loads(A.U, e, its[k], FL[k], FR[k]);
-  if (t < NB_STAGE) sB[t] = (R)bval;
+    if (t + k * TPE < 6 * nf) face_loads(A.U, e, its[k], FL[k], FR[k]);
+  if (tid < NB_STAGE) sB[tid] = (R)bval;
   const R invJ[3] = {(R)A.invJ[0], (R)A.invJ[1], (R)A.invJ[2]};
   if (t < nn) {
     R P[7];
@@ -1189,11 +1261,11 @@ __global__ __launch_bounds__(NT, FI == 1 && N >= 2 ? 8 : 4) void k_lift(StageArg
   }
 #pragma unroll
   for (int k = 0; k < FI; ++k)
-    if (t + k * NT < 6 * nf) lift_face_q<R, MX>(A, its[k], FL[k], FR[k], ref, sQ);
+    if (t + k * TPE < 6 * nf) lift_face_q<R, MX>(A, its[k], FL[k], FR[k], ref, sQ);
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < FI; ++k)
-    if (t + k * NT < 6 * nf) lift_face_node<R, LES>(A, e, its[k], sq, sQ, sB, invJ);
+    if (t + k * TPE < 6 * nf) lift_face_node<R, LES>(A, e, its[k], sq, sQ, sB, invJ);
 }
 
 // ===========================================================================
@@ -2276,9 +2348,19 @@ __global__ __launch_bounds__(NT) void k_nonfinite(ReduceArgs R) {
 // ---------------------------------------------------------------------------
 inline int blocks_for(const StageArgs& A) { return 8 * A.chunk; }
 
+// Stage and lifting kernels: P::EPB elements per workgroup, the groups of
+// consecutive elements split into 8 XCD-contiguous ranges.
+template <class P>
+inline StageArgs grouped(const StageArgs& A) {
+  StageArgs B = A;
+  B.chunk = ((A.nelem + P::EPB - 1) / P::EPB + 7) / 8;
+  return B;
+}
+
 template <int VF, class R>
-hipError_t launch_stage_vf(const StageArgs& A, int eq, hipStream_t s) {
-  const dim3 grid(blocks_for(A)), block(NT);
+hipError_t launch_stage_vf(const StageArgs& A0, int eq, hipStream_t s) {
+  const StageArgs A = grouped<PS>(A0);
+  const dim3 grid(blocks_for(A)), block(PS::NTB);
   if (eq == 2) {
     if constexpr (VF != VF_CH) hipLaunchKernelGGL((k_stage<VF, 2, false, R>), grid, block, 0, s, A);
     else return hipErrorInvalidValue;
@@ -2311,15 +2393,17 @@ hipError_t launch_stage_mixed(const StageArgs& A, int eq, hipStream_t s) {
   }
 }
 
-hipError_t launch_lift(const StageArgs& A, int eq, hipStream_t s) {
-  if (eq == 2) hipLaunchKernelGGL((k_lift<double, true>), dim3(blocks_for(A)), dim3(NT), 0, s, A);
-  else hipLaunchKernelGGL((k_lift<double, false>), dim3(blocks_for(A)), dim3(NT), 0, s, A);
+hipError_t launch_lift(const StageArgs& A0, int eq, hipStream_t s) {
+  const StageArgs A = grouped<PL>(A0);
+  if (eq == 2) hipLaunchKernelGGL((k_lift<double, true>), dim3(blocks_for(A)), dim3(PL::NTB), 0, s, A);
+  else hipLaunchKernelGGL((k_lift<double, false>), dim3(blocks_for(A)), dim3(PL::NTB), 0, s, A);
   return hipGetLastError();
 }
 
-hipError_t launch_lift_mixed(const StageArgs& A, int eq, hipStream_t s) {
-  if (eq == 2) hipLaunchKernelGGL((k_lift<float, true>), dim3(blocks_for(A)), dim3(NT), 0, s, A);
-  else hipLaunchKernelGGL((k_lift<float, false>), dim3(blocks_for(A)), dim3(NT), 0, s, A);
+hipError_t launch_lift_mixed(const StageArgs& A0, int eq, hipStream_t s) {
+  const StageArgs A = grouped<PL>(A0);
+  if (eq == 2) hipLaunchKernelGGL((k_lift<float, true>), dim3(blocks_for(A)), dim3(PL::NTB), 0, s, A);
+  else hipLaunchKernelGGL((k_lift<float, false>), dim3(blocks_for(A)), dim3(PL::NTB), 0, s, A);
   return hipGetLastError();
 }
 
