@@ -26,7 +26,12 @@
 //   * explicit Runge-Kutta, stages counted in the PID: Sec. 2, eq. (pid);
 //   * Smagorinsky eddy viscosity with a constant or per-element coefficient
 //     C_s evaluated at every solution point: Sec. 5 (the standard model with
-//     constant C_s, and the learned model that sets C_s per element).
+//     constant C_s, and the learned model that sets C_s per element);
+//   * curved hexahedral elements (the meshes of Secs. 3-5 are unstructured
+//     and curvilinear): the split form with metric terms, where the paper
+//     names only the method and its properties; the metric terms, their
+//     averaging in the two-point flux and the BR1 gradient on curved
+//     elements are readings, marked below.
 // Everything the paper leaves open (BR1 lifting, the Kennedy-Gruber and
 // Pirozzoli two-point fluxes, LLF/Roe, the LSERK4 coefficients, the modal
 // energy definition, the sharpness s, the FV reconstruction) follows the
@@ -69,6 +74,10 @@ struct Setup {
   // Prandtl number, optional per-element coefficients (overrides Cs).
   double Cs, Prt;
   const double* cs_elem;
+  // Curved mesh: node coordinates X[e][3][(N+1)^3] of every element (the same
+  // structured periodic connectivity; lo/hi are then unused), or NULL for the
+  // Cartesian box.
+  const double* xnodes;
 };
 
 // ---------------------------------------------------------------------------
@@ -194,6 +203,13 @@ struct Ctx {
   double dx[3], invJ[3], Jac;
   double delta2;         // squared filter width of the eddy viscosity
   std::vector<int> nbr;  // [e][6]
+  // curved mesh: metric terms Ja^i_m (contravariant direction i, Cartesian
+  // component m) and Jacobian J at every node
+  bool curved = false;
+  std::vector<double> Ja;  // [e][i][m][n]
+  std::vector<double> Jn;  // [e][n]
+  double ja(int e, int i, int m, int n) const { return Ja[((size_t(e) * 3 + i) * 3 + m) * nn + n]; }
+  double jac(int e, int n) const { return Jn[size_t(e) * nn + n]; }
   // (C_s Delta)^2 of element e; 0 without the Smagorinsky model
   double csd2(int e) const {
     const double cs = s.cs_elem ? s.cs_elem[e] : s.Cs;
@@ -201,6 +217,8 @@ struct Ctx {
   }
   bool les() const { return s.equations == 1 && (s.cs_elem != nullptr || s.Cs > 0.0); }
 };
+
+static void curved_metrics(Ctx& c);
 
 static Ctx make_ctx(const Setup& s) {
   Ctx c;
@@ -238,6 +256,7 @@ static Ctx make_ctx(const Setup& s) {
         c.nbr[6 * e + 4] = id(ex, ey, ez - 1);
         c.nbr[6 * e + 5] = id(ex, ey, ez + 1);
       }
+  if (s.xnodes) curved_metrics(c);
   return c;
 }
 
@@ -269,6 +288,62 @@ static inline int face_node(const Ctx& c, int d, int l, int a) {
   else if (d == 1) { ijk[0] = t1; ijk[1] = l; ijk[2] = t2; }
   else { ijk[0] = t1; ijk[1] = t2; ijk[2] = l; }
   return node(c, ijk[0], ijk[1], ijk[2]);
+}
+
+// ---------------------------------------------------------------------------
+// Metric terms of a curved element (reading: the conservative curl form, which
+// makes the discrete metric identities sum_i d/dxi^i (J a^i) = 0 hold exactly,
+// so that a uniform state stays uniform):
+//   J a^i_m = -( d_j (X_l d_k X_n) - d_k (X_l d_j X_n) ),
+// (j, k) = (i+1, i+2) mod 3 the other two reference directions and
+// (m, n, l) = (m, m+1, m+2) mod 3, every d_j the LGL derivative matrix along
+// reference direction j applied to nodal values (products interpolated at the
+// nodes).  J is the determinant of the derivative matrix dX_m/dxi^j at the node.
+// ---------------------------------------------------------------------------
+static void deriv(const Ctx& c, const std::vector<double>& f, int j, std::vector<double>& out) {
+  out.assign(c.nn, 0.0);
+  for (int n = 0; n < c.nn; ++n) {
+    int ijk[3];
+    coords(c, n, ijk);
+    double s = 0.0;
+    for (int l = 0; l <= c.N; ++l) s += c.b.D[ijk[j] * c.n1 + l] * f[node_along(c, ijk, j, l)];
+    out[n] = s;
+  }
+}
+
+static void curved_metrics(Ctx& c) {
+  c.curved = true;
+  c.Ja.assign(size_t(c.nelem) * 9 * c.nn, 0.0);
+  c.Jn.assign(size_t(c.nelem) * c.nn, 0.0);
+  for (int e = 0; e < c.nelem; ++e) {
+    std::vector<double> X[3], dX[3][3];  // dX[m][j] = d X_m / d xi^j
+    for (int m = 0; m < 3; ++m) {
+      X[m].assign(c.s.xnodes + (size_t(e) * 3 + m) * c.nn, c.s.xnodes + (size_t(e) * 3 + m + 1) * c.nn);
+      for (int j = 0; j < 3; ++j) deriv(c, X[m], j, dX[m][j]);
+    }
+    for (int n = 0; n < c.nn; ++n) {
+      const double A[3][3] = {{dX[0][0][n], dX[0][1][n], dX[0][2][n]},
+                              {dX[1][0][n], dX[1][1][n], dX[1][2][n]},
+                              {dX[2][0][n], dX[2][1][n], dX[2][2][n]}};
+      c.Jn[size_t(e) * c.nn + n] = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) -
+                                   A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+                                   A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+    }
+    for (int i = 0; i < 3; ++i) {
+      const int j = (i + 1) % 3, k = (i + 2) % 3;
+      for (int m = 0; m < 3; ++m) {
+        const int mn = (m + 1) % 3, ml = (m + 2) % 3;
+        std::vector<double> p(c.nn), q(c.nn), dp, dq;
+        for (int n = 0; n < c.nn; ++n) {
+          p[n] = X[ml][n] * dX[mn][k][n];  // X_l d_k X_n
+          q[n] = X[ml][n] * dX[mn][j][n];  // X_l d_j X_n
+        }
+        deriv(c, p, j, dp);
+        deriv(c, q, k, dq);
+        for (int n = 0; n < c.nn; ++n) c.Ja[((size_t(e) * 3 + i) * 3 + m) * c.nn + n] = -(dp[n] - dq[n]);
+      }
+    }
+  }
 }
 
 template <class T>
@@ -406,6 +481,58 @@ static void surface_flux(int sf, int vf, int d, double g, const T L[5], const T 
     const T cj = (j == d) ? ct : T(0.0);
     Dis[1 + j] = l1 * a1 * (ut[j] - cj) + l5 * a5 * (ut[j] + cj) + l2 * (a2 * ut[j] + rt * dut[j]);
   }
+  Dis[4] = l1 * a1 * (Ht - ct * un) + l5 * a5 * (Ht + ct * un) +
+           l2 * (a2 * 0.5 * q2 + rt * (ut[0] * dut[0] + ut[1] * dut[1] + ut[2] * dut[2]));
+  for (int v = 0; v < 5; ++v) f[v] -= 0.5 * Dis[v];
+}
+
+// Surface numerical flux along a unit normal nv (curved faces): the central
+// part is sum_m nv_m F#_m(L, R); LLF and Roe as above with the normal velocity
+// u.nv and the tangential velocity jump du - (du.nv) nv in place of the
+// Cartesian components (the fluxes are rotationally invariant, so nv = e_d
+// gives surface_flux(d)).
+template <class T>
+static void surface_flux_n(int sf, int vf, double g, const double nv[3], const T L[5], const T R[5], T f[5]) {
+  for (int v = 0; v < 5; ++v) f[v] = T(0.0);
+  for (int m = 0; m < 3; ++m) {
+    T fm[5];
+    two_point_flux(vf, m, g, L, R, fm);
+    for (int v = 0; v < 5; ++v) f[v] += nv[m] * fm[v];
+  }
+  if (sf == SF_CENTRAL) return;
+  const Prim<T> A = primitive(L, g), B = primitive(R, g);
+  const T unA = nv[0] * A.u[0] + nv[1] * A.u[1] + nv[2] * A.u[2];
+  const T unB = nv[0] * B.u[0] + nv[1] * B.u[1] + nv[2] * B.u[2];
+  if (sf == SF_LLF) {
+    const T cA = sqrt_(g * A.p / A.rho), cB = sqrt_(g * B.p / B.rho);
+    const T lam = max_(abs_(unA) + cA, abs_(unB) + cB);
+    for (int v = 0; v < 5; ++v) f[v] -= 0.5 * lam * (R[v] - L[v]);
+    return;
+  }
+  const T sA = sqrt_(A.rho), sB = sqrt_(B.rho);
+  const T inv = 1.0 / (sA + sB);
+  T ut[3];
+  for (int j = 0; j < 3; ++j) ut[j] = (sA * A.u[j] + sB * B.u[j]) * inv;
+  const T HA = (L[4] + A.p) / A.rho, HB = (R[4] + B.p) / B.rho;
+  const T Ht = (sA * HA + sB * HB) * inv;
+  const T rt = sA * sB;
+  const T q2 = ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2];
+  const T c2 = (g - 1.0) * (Ht - 0.5 * q2);
+  const T ct = sqrt_(c2);
+  const T un = nv[0] * ut[0] + nv[1] * ut[1] + nv[2] * ut[2];
+  const T drho = B.rho - A.rho, dp = B.p - A.p;
+  T du[3], dut[3];
+  for (int j = 0; j < 3; ++j) du[j] = B.u[j] - A.u[j];
+  const T dun = nv[0] * du[0] + nv[1] * du[1] + nv[2] * du[2];
+  for (int j = 0; j < 3; ++j) dut[j] = du[j] - dun * nv[j];
+  const T a1 = (dp - rt * ct * dun) / (2.0 * c2);
+  const T a5 = (dp + rt * ct * dun) / (2.0 * c2);
+  const T a2 = drho - dp / c2;
+  const T l1 = abs_(un - ct), l5 = abs_(un + ct), l2 = abs_(un);
+  T Dis[5];
+  Dis[0] = l1 * a1 + l5 * a5 + l2 * a2;
+  for (int j = 0; j < 3; ++j)
+    Dis[1 + j] = l1 * a1 * (ut[j] - ct * nv[j]) + l5 * a5 * (ut[j] + ct * nv[j]) + l2 * (a2 * ut[j] + rt * dut[j]);
   Dis[4] = l1 * a1 * (Ht - ct * un) + l5 * a5 * (Ht + ct * un) +
            l2 * (a2 * 0.5 * q2 + rt * (ut[0] * dut[0] + ut[1] * dut[1] + ut[2] * dut[2]));
   for (int v = 0; v < 5; ++v) f[v] -= 0.5 * Dis[v];
@@ -623,6 +750,220 @@ static void viscous_dg(const Ctx& c, const T* U, T* Ut) {
 }
 
 // ---------------------------------------------------------------------------
+// Curved elements: the same split form with metric terms.
+//   J U_t = - sum_i [ sum_l Dhat_{i_i l} Ft#_i(U_n, U_{n: i_i -> l})
+//                     + (1/w_{i_i}) (delta_{i_i N} ft*_{i,+} - delta_{i_i 0} ft*_{i,-}) ]
+// reading: contravariant two-point flux with the metric of both nodes
+// averaged, Ft#_i(a, b) = sum_m (Ja^i_m(a) + Ja^i_m(b))/2 F#_m(a, b); at a face
+// node the metric is the mean of both elements' node metrics, Ja_f, and
+// ft* = |Ja_f| f*(U-, U+; Ja_f/|Ja_f|), so both elements see the same value.
+// ---------------------------------------------------------------------------
+// Face metric of the +i face of element e at face index a.
+static void face_metric(const Ctx& c, int e, int i, int a, double Jf[3]) {
+  const int nb = c.nbr[6 * e + 2 * i + 1];
+  const int nm = face_node(c, i, c.N, a), np = face_node(c, i, 0, a);
+  for (int m = 0; m < 3; ++m) Jf[m] = 0.5 * (c.ja(e, i, m, nm) + c.ja(nb, i, m, np));
+}
+
+template <class T>
+static void surface_pass_curved(const Ctx& c, const T* U, std::vector<T>& fstar) {
+  fstar.assign(size_t(c.nelem) * 3 * 5 * c.nf, T(0.0));
+#pragma omp parallel for schedule(static)
+  for (int e = 0; e < c.nelem; ++e)
+    for (int i = 0; i < 3; ++i) {
+      const int nb = c.nbr[6 * e + 2 * i + 1];
+      for (int a = 0; a < c.nf; ++a) {
+        double Jf[3], nv[3];
+        face_metric(c, e, i, a, Jf);
+        const double sh = std::sqrt(Jf[0] * Jf[0] + Jf[1] * Jf[1] + Jf[2] * Jf[2]);
+        for (int m = 0; m < 3; ++m) nv[m] = Jf[m] / sh;
+        T L[5], R[5], f[5];
+        load_state(c, U, e, face_node(c, i, c.N, a), L);
+        load_state(c, U, nb, face_node(c, i, 0, a), R);
+        surface_flux_n(c.s.surf_flux, c.s.vol_flux, c.s.gamma, nv, L, R, f);
+        for (int v = 0; v < 5; ++v) fstar[((size_t(e) * 3 + i) * 5 + v) * c.nf + a] = sh * f[v];
+      }
+    }
+}
+
+template <class T>
+static void advective_dg_curved(const Ctx& c, const T* U, const std::vector<T>& fstar, T* Ut) {
+  const Basis& b = c.b;
+#pragma omp parallel for schedule(static)
+  for (int e = 0; e < c.nelem; ++e)
+    for (int n = 0; n < c.nn; ++n) {
+      int ijk[3];
+      coords(c, n, ijk);
+      T un[5];
+      load_state(c, U, e, n, un);
+      T acc[5] = {T(0.0), T(0.0), T(0.0), T(0.0), T(0.0)};
+      for (int i = 0; i < 3; ++i) {
+        const int ii = ijk[i];
+        T sum[5] = {T(0.0), T(0.0), T(0.0), T(0.0), T(0.0)};
+        for (int l = 0; l <= c.N; ++l) {
+          const int p = node_along(c, ijk, i, l);
+          T ul[5];
+          load_state(c, U, e, p, ul);
+          for (int m = 0; m < 3; ++m) {
+            T f[5];
+            two_point_flux(c.s.vol_flux, m, c.s.gamma, un, ul, f);
+            const double jm = 0.5 * (c.ja(e, i, m, n) + c.ja(e, i, m, p));
+            for (int v = 0; v < 5; ++v) sum[v] += b.Dhat[ii * c.n1 + l] * (jm * f[v]);
+          }
+        }
+        const int a = face_index(c, ijk, i);
+        if (ii == c.N)
+          for (int v = 0; v < 5; ++v) sum[v] += (1.0 / b.w[c.N]) * fstar[((size_t(e) * 3 + i) * 5 + v) * c.nf + a];
+        if (ii == 0) {
+          const int em = c.nbr[6 * e + 2 * i];
+          for (int v = 0; v < 5; ++v) sum[v] -= (1.0 / b.w[0]) * fstar[((size_t(em) * 3 + i) * 5 + v) * c.nf + a];
+        }
+        for (int v = 0; v < 5; ++v) acc[v] -= sum[v];
+      }
+      for (int v = 0; v < 5; ++v) Ut[(size_t(e) * 5 + v) * c.nn + n] = acc[v] / c.jac(e, n);
+    }
+}
+
+// BR1 gradient on curved elements.  reading: chain rule in strong form,
+//   grad q = (1/J) sum_i Ja^i [ sum_l D_{i_i l} q_l
+//              + (1/w_{i_i}) (delta_{i_i N} (q*_+ - q) - delta_{i_i 0} (q*_- - q)) ],
+// with the node's own metric (a uniform q has zero gradient whatever the
+// metric); q* the arithmetic mean as on Cartesian meshes.
+template <class T>
+static void br1_gradient_curved(const Ctx& c, const T* U, std::vector<T>& grad) {
+  const Basis& b = c.b;
+  const double g = c.s.gamma;
+  std::vector<T> q(size_t(c.nelem) * 4 * c.nn);
+#pragma omp parallel for schedule(static)
+  for (int e = 0; e < c.nelem; ++e)
+    for (int n = 0; n < c.nn; ++n) {
+      T u[5], qq[4];
+      load_state(c, U, e, n, u);
+      lifted(u, g, qq);
+      for (int k = 0; k < 4; ++k) q[(size_t(e) * 4 + k) * c.nn + n] = qq[k];
+    }
+  std::vector<T> qs(size_t(c.nelem) * 3 * 4 * c.nf);
+#pragma omp parallel for schedule(static)
+  for (int e = 0; e < c.nelem; ++e)
+    for (int d = 0; d < 3; ++d) {
+      const int nb = c.nbr[6 * e + 2 * d + 1];
+      for (int k = 0; k < 4; ++k)
+        for (int a = 0; a < c.nf; ++a)
+          qs[((size_t(e) * 3 + d) * 4 + k) * c.nf + a] =
+              0.5 * (q[(size_t(e) * 4 + k) * c.nn + face_node(c, d, c.N, a)] +
+                     q[(size_t(nb) * 4 + k) * c.nn + face_node(c, d, 0, a)]);
+    }
+  grad.assign(size_t(c.nelem) * 3 * 4 * c.nn, T(0.0));
+#pragma omp parallel for schedule(static)
+  for (int e = 0; e < c.nelem; ++e)
+    for (int n = 0; n < c.nn; ++n) {
+      int ijk[3];
+      coords(c, n, ijk);
+      T s[3][4];  // reference-direction derivatives with lifting
+      for (int i = 0; i < 3; ++i) {
+        const int ii = ijk[i];
+        const int a = face_index(c, ijk, i);
+        for (int k = 0; k < 4; ++k) {
+          const T* qe = &q[(size_t(e) * 4 + k) * c.nn];
+          T acc = T(0.0);
+          for (int l = 0; l <= c.N; ++l) acc += b.D[ii * c.n1 + l] * qe[node_along(c, ijk, i, l)];
+          if (ii == c.N) acc += (1.0 / b.w[c.N]) * (qs[((size_t(e) * 3 + i) * 4 + k) * c.nf + a] - qe[n]);
+          if (ii == 0) {
+            const int em = c.nbr[6 * e + 2 * i];
+            acc -= (1.0 / b.w[0]) * (qs[((size_t(em) * 3 + i) * 4 + k) * c.nf + a] - qe[n]);
+          }
+          s[i][k] = acc;
+        }
+      }
+      const double iJ = 1.0 / c.jac(e, n);
+      for (int m = 0; m < 3; ++m)
+        for (int k = 0; k < 4; ++k) {
+          T gm = T(0.0);
+          for (int i = 0; i < 3; ++i) gm += c.ja(e, i, m, n) * s[i][k];
+          grad[((size_t(e) * 3 + m) * 4 + k) * c.nn + n] = iJ * gm;
+        }
+    }
+}
+
+// Viscous divergence on curved elements (strong form, BR1):
+//   U_t += (1/J) sum_i [ sum_l D_{i_i l} Gt_{i,l}
+//            + (1/w_{i_i}) (delta_{i_i N}(Gt*_{i,+} - Gt_{i,N}) - delta_{i_i 0}(Gt*_{i,-} - Gt_{i,0})) ],
+// Gt_i = sum_m Ja^i_m Fv_m the contravariant viscous flux at the node, and at
+// a face node Gt* = Ja_f . (Fv(-) + Fv(+))/2 with the face metric Ja_f.
+template <class T>
+static void viscous_dg_curved(const Ctx& c, const T* U, T* Ut) {
+  const Basis& b = c.b;
+  const double g = c.s.gamma, mu = c.s.mu, Pr = c.s.Pr;
+  std::vector<T> grad;
+  br1_gradient_curved(c, U, grad);
+  std::vector<T> Fv(size_t(c.nelem) * 3 * 5 * c.nn);  // Cartesian [e][m][v][n]
+#pragma omp parallel for schedule(static)
+  for (int e = 0; e < c.nelem; ++e)
+    for (int n = 0; n < c.nn; ++n) {
+      T u[5], gr[3][4];
+      load_state(c, U, e, n, u);
+      for (int dd = 0; dd < 3; ++dd)
+        for (int k = 0; k < 4; ++k) gr[dd][k] = grad[((size_t(e) * 3 + dd) * 4 + k) * c.nn + n];
+      for (int m = 0; m < 3; ++m) {
+        T F[5];
+        viscous_flux(m, g, mu, Pr, 0.0, c.s.Prt, u, gr, F);
+        for (int v = 0; v < 5; ++v) Fv[((size_t(e) * 3 + m) * 5 + v) * c.nn + n] = F[v];
+      }
+    }
+  std::vector<T> Gt(size_t(c.nelem) * 3 * 5 * c.nn);  // contravariant [e][i][v][n]
+#pragma omp parallel for schedule(static)
+  for (int e = 0; e < c.nelem; ++e)
+    for (int i = 0; i < 3; ++i)
+      for (int v = 0; v < 5; ++v)
+        for (int n = 0; n < c.nn; ++n) {
+          T s = T(0.0);
+          for (int m = 0; m < 3; ++m) s += c.ja(e, i, m, n) * Fv[((size_t(e) * 3 + m) * 5 + v) * c.nn + n];
+          Gt[((size_t(e) * 3 + i) * 5 + v) * c.nn + n] = s;
+        }
+  std::vector<T> Fs(size_t(c.nelem) * 3 * 5 * c.nf);
+#pragma omp parallel for schedule(static)
+  for (int e = 0; e < c.nelem; ++e)
+    for (int i = 0; i < 3; ++i) {
+      const int nb = c.nbr[6 * e + 2 * i + 1];
+      for (int a = 0; a < c.nf; ++a) {
+        double Jf[3];
+        face_metric(c, e, i, a, Jf);
+        const int nm = face_node(c, i, c.N, a), np = face_node(c, i, 0, a);
+        for (int v = 0; v < 5; ++v) {
+          T s = T(0.0);
+          for (int m = 0; m < 3; ++m)
+            s += Jf[m] * (0.5 * (Fv[((size_t(e) * 3 + m) * 5 + v) * c.nn + nm] +
+                                 Fv[((size_t(nb) * 3 + m) * 5 + v) * c.nn + np]));
+          Fs[((size_t(e) * 3 + i) * 5 + v) * c.nf + a] = s;
+        }
+      }
+    }
+#pragma omp parallel for schedule(static)
+  for (int e = 0; e < c.nelem; ++e)
+    for (int n = 0; n < c.nn; ++n) {
+      int ijk[3];
+      coords(c, n, ijk);
+      T tot[5] = {T(0.0), T(0.0), T(0.0), T(0.0), T(0.0)};
+      for (int i = 0; i < 3; ++i) {
+        const int ii = ijk[i];
+        const int a = face_index(c, ijk, i);
+        for (int v = 0; v < 5; ++v) {
+          const T* G = &Gt[((size_t(e) * 3 + i) * 5 + v) * c.nn];
+          T s = T(0.0);
+          for (int l = 0; l <= c.N; ++l) s += b.D[ii * c.n1 + l] * G[node_along(c, ijk, i, l)];
+          if (ii == c.N) s += (1.0 / b.w[c.N]) * (Fs[((size_t(e) * 3 + i) * 5 + v) * c.nf + a] - G[n]);
+          if (ii == 0) {
+            const int em = c.nbr[6 * e + 2 * i];
+            s -= (1.0 / b.w[0]) * (Fs[((size_t(em) * 3 + i) * 5 + v) * c.nf + a] - G[n]);
+          }
+          tot[v] += s;
+        }
+      }
+      for (int v = 0; v < 5; ++v) Ut[(size_t(e) * 5 + v) * c.nn + n] += tot[v] / c.jac(e, n);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Modal indicator and blending coefficient (paper Sec. 4.1 indicator eq.,
 // neighbour spread; Sec. 4.2 bounds), templated on the scalar so that dual
 // numbers differentiate through the coefficient.
@@ -791,6 +1132,14 @@ template <class T>
 static void time_derivative(const Ctx& c, const T* U, T* Ut, const double* alpha_in,
                             T* Ut_dg_out, T* Ut_fv_out, double* alpha_out) {
   const size_t tot = size_t(c.nelem) * 5 * c.nn;
+  if (c.curved) {  // no blending or eddy viscosity on curved meshes (refused by valid())
+    std::vector<T> fstar;
+    surface_pass_curved(c, U, fstar);
+    advective_dg_curved(c, U, fstar, Ut);
+    if (Ut_dg_out) std::copy(Ut, Ut + tot, Ut_dg_out);
+    if (c.s.equations == EQ_NS) viscous_dg_curved(c, U, Ut);
+    return;
+  }
   std::vector<T> fstar;
   surface_pass(c, U, fstar);
   std::vector<T> Udg(tot), Ufv;
@@ -855,14 +1204,16 @@ static void integrals(const Ctx& c, const double* X, double out[5]) {
     for (int n = 0; n < c.nn; ++n) {
       int ijk[3];
       coords(c, n, ijk);
-      const double wq = c.b.w[ijk[0]] * c.b.w[ijk[1]] * c.b.w[ijk[2]] * c.Jac;
+      const double wq = c.b.w[ijk[0]] * c.b.w[ijk[1]] * c.b.w[ijk[2]] * (c.curved ? c.jac(e, n) : c.Jac);
       for (int v = 0; v < 5; ++v) out[v] += wq * X[(size_t(e) * 5 + v) * c.nn + n];
     }
 }
 
 // Time step: dt = CFL * min( 1 / ((N+1) max sum_d (|u_d| + c)/dx_d),
 //                            1 / ((N+1)^2 max nu_eff sum_d 1/dx_d^2) ),
-// nu_eff = mu gamma / (rho Pr) (viscous part only for Navier-Stokes).
+// nu_eff = mu gamma / (rho Pr) (viscous part only for Navier-Stokes).  On
+// curved elements 1/dx_d becomes |Ja^d|/(2J) at the node and |u_d| the
+// contravariant |u.Ja^d|/|Ja^d| (both reduce to the Cartesian values).
 static double max_dt(const Ctx& c, const double* U, double cfl) {
   const double g = c.s.gamma;
   double lam_a = 0.0, lam_v = 0.0;
@@ -874,8 +1225,20 @@ static double max_dt(const Ctx& c, const double* U, double cfl) {
       const double cs = std::sqrt(g * P.p / P.rho);
       double s = 0.0, sv = 0.0;
       for (int d = 0; d < 3; ++d) {
-        s += (std::fabs(P.u[d]) + cs) / c.dx[d];
-        sv += 1.0 / (c.dx[d] * c.dx[d]);
+        if (c.curved) {
+          double un = 0.0, jn = 0.0;
+          for (int m = 0; m < 3; ++m) {
+            un += P.u[m] * c.ja(e, d, m, n);
+            jn += c.ja(e, d, m, n) * c.ja(e, d, m, n);
+          }
+          jn = std::sqrt(jn);
+          const double h = jn / (2.0 * c.jac(e, n));  // 1 / dx_d
+          s += (std::fabs(un) / jn + cs) * h;
+          sv += h * h;
+        } else {
+          s += (std::fabs(P.u[d]) + cs) / c.dx[d];
+          sv += 1.0 / (c.dx[d] * c.dx[d]);
+        }
       }
       lam_a = std::max(lam_a, s);
       if (c.s.equations == EQ_NS) lam_v = std::max(lam_v, c.s.mu * g / (P.rho * c.s.Pr) * sv);
@@ -1155,6 +1518,9 @@ static bool valid(const Setup* s) {
   if (!(s->gamma > 1.0) || s->mu < 0.0) return false;
   if (s->blending && s->N < 2) return false;
   if (s->Cs < 0.0 || ((s->Cs > 0.0 || s->cs_elem) && !(s->Prt > 0.0))) return false;
+  // curved meshes: split-form DG (Euler, Navier-Stokes) without blending or
+  // the eddy viscosity
+  if (s->xnodes && (s->blending || s->Cs > 0.0 || s->cs_elem)) return false;
   return true;
 }
 
@@ -1224,7 +1590,7 @@ int or_time_derivative(const Setup* s, const double* U, double* Ut, const double
 
 // Operator (no blending) for the elements elems[0..nsel-1] only: Ut_sel[s][5][nn].
 int or_time_derivative_elems(const Setup* s, const double* U, const int32_t* elems, int nsel, double* Ut_sel) {
-  if (!valid(s) || s->blending) return -1;
+  if (!valid(s) || s->blending || s->xnodes) return -1;
   const Ctx c = make_ctx(*s);
   for (int k = 0; k < nsel; ++k)
     if (elems[k] < 0 || elems[k] >= c.nelem) return -1;
@@ -1233,7 +1599,7 @@ int or_time_derivative_elems(const Setup* s, const double* U, const int32_t* ele
 }
 
 int or_dense_time_derivative(const Setup* s, const double* U, double* Ut) {
-  if (!valid(s) || s->blending) return -1;
+  if (!valid(s) || s->blending || s->xnodes) return -1;
   const Ctx c = make_ctx(*s);
   dense_time_derivative(c, U, Ut);
   return 0;
@@ -1259,7 +1625,8 @@ int or_gradient(const Setup* s, const double* U, double* grad) {
   if (!valid(s)) return -1;
   const Ctx c = make_ctx(*s);
   std::vector<double> g;
-  br1_gradient(c, U, g);
+  if (c.curved) br1_gradient_curved(c, U, g);
+  else br1_gradient(c, U, g);
   std::copy(g.begin(), g.end(), grad);
   return 0;
 }
@@ -1328,6 +1695,21 @@ double or_max_dt(const Setup* s, const double* U, double cfl) {
   if (!valid(s)) return -1.0;
   const Ctx c = make_ctx(*s);
   return max_dt(c, U, cfl);
+}
+
+// Metric terms of a curved mesh: Ja[e][i][m][n], J[e][n].
+int or_metrics(const Setup* s, double* Ja, double* J) {
+  if (!valid(s) || !s->xnodes) return -1;
+  const Ctx c = make_ctx(*s);
+  std::copy(c.Ja.begin(), c.Ja.end(), Ja);
+  std::copy(c.Jn.begin(), c.Jn.end(), J);
+  return 0;
+}
+
+// Surface flux along a unit normal (curved faces).
+int or_surface_flux_n(const Setup* s, const double* nv, const double* L, const double* R, double* f) {
+  surface_flux_n(s->surf_flux, s->vol_flux, s->gamma, nv, L, R, f);
+  return 0;
 }
 
 void or_rk_coefficients(double* A, double* B) {

@@ -47,7 +47,7 @@ class _Setup(ctypes.Structure):
                 ("gamma", ctypes.c_double), ("mu", ctypes.c_double), ("Pr", ctypes.c_double),
                 ("alpha_min", ctypes.c_double), ("alpha_max", ctypes.c_double),
                 ("alpha_spread", ctypes.c_double), ("Cs", ctypes.c_double), ("Prt", ctypes.c_double),
-                ("cs_elem", ctypes.c_void_p)]
+                ("cs_elem", ctypes.c_void_p), ("xnodes", ctypes.c_void_p)]
 
 
 @dataclass
@@ -71,8 +71,10 @@ class Setup:
     Cs: float = 0.0          # Smagorinsky coefficient (0: no eddy viscosity)
     Prt: float = 0.9         # turbulent Prandtl number
     cs_elem: object = None   # optional per-element coefficients (numpy, n_elems)
+    xnodes: object = None    # curved mesh: node coordinates (n_elems, 3, N+1, N+1, N+1), x index fastest
     _c: object = field(default=None, repr=False, compare=False)
     _keep: object = field(default=None, repr=False, compare=False)
+    _keepx: object = field(default=None, repr=False, compare=False)
 
     @property
     def n1(self) -> int:
@@ -105,6 +107,13 @@ class Setup:
             s.cs_elem = self._keep.ctypes.data
         else:
             s.cs_elem = None
+        if self.xnodes is not None:
+            self._keepx = np.ascontiguousarray(self.xnodes, dtype=np.float64)
+            n1 = self.N + 1
+            assert self._keepx.shape == (self.n_elems, 3, n1, n1, n1), self._keepx.shape
+            s.xnodes = self._keepx.ctypes.data
+        else:
+            s.xnodes = None
         return s
 
 
@@ -138,6 +147,8 @@ def lib() -> ctypes.CDLL:
             ("or_integrals", [P, P, P], ctypes.c_int),
             ("or_max_dt", [P, P, ctypes.c_double], ctypes.c_double),
             ("or_rk_coefficients", [P, P], None),
+            ("or_metrics", [P, P, P], ctypes.c_int),
+            ("or_surface_flux_n", [P, P, P, P, P], ctypes.c_int),
         ]:
             fn = getattr(L, name)
             fn.argtypes = args
@@ -296,3 +307,19 @@ def rk_coefficients():
     A, B = np.zeros(5), np.zeros(5)
     lib().or_rk_coefficients(_p(A), _p(B))
     return A, B
+
+
+def metrics(s: Setup):
+    """Curved mesh: metric terms Ja (n_elems, 3 [i], 3 [m], n1, n1, n1) and J (n_elems, n1, n1, n1)."""
+    n1 = s.N + 1
+    Ja = np.zeros((s.n_elems, 3, 3, n1, n1, n1))
+    J = np.zeros((s.n_elems, n1, n1, n1))
+    _check(lib().or_metrics(_ref(s), _p(Ja), _p(J)))
+    return Ja, J
+
+
+def surface_flux_n(s: Setup, nv, L, R):
+    """Surface flux along the unit normal nv."""
+    f = np.zeros(5)
+    lib().or_surface_flux_n(_ref(s), _p(_f64(nv)), _p(_f64(L)), _p(_f64(R)), _p(f))
+    return f

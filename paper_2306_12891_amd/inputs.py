@@ -50,6 +50,33 @@ def node_coordinates(N: int, nelem, lo, hi):
     return X, Y, Z
 
 
+def warped_coordinates(N: int, nelem, lo=(0.0, 0.0, 0.0), hi=(TWO_PI,) * 3, amp: float = 0.04) -> np.ndarray:
+    """Node coordinates of a curved periodic mesh, shape (nElems, 3, N+1, N+1, N+1).
+
+    Every Cartesian node (X, Y, Z) of the box is displaced by a smooth periodic
+    field, component d by amp * min(L) * sin(2pi(Xt + a_d)) sin(2pi(Yt + b_d))
+    sin(2pi(Zt + c_d)) with Xt = (X - lo_x)/L_x etc. and fixed phase offsets, so
+    all nine metric terms are non-zero; amp * 2pi < 1 keeps the mapping one to
+    one.  Faces shared by two elements get the same physical points.
+    """
+    X, Y, Z = node_coordinates(N, nelem, lo, hi)
+    L = [hi[d] - lo[d] for d in range(3)]
+    A = amp * min(L)
+    t = [(X - lo[0]) / L[0], (Y - lo[1]) / L[1], (Z - lo[2]) / L[2]]
+    ph = [(0.0, 0.1, 0.2), (0.3, 0.0, 0.4), (0.5, 0.6, 0.0)]
+    out = []
+    for d, base in enumerate((X, Y, Z)):
+        a, b, c = ph[d]
+        out.append(base + A * np.sin(TWO_PI * (t[0] + a)) * np.sin(TWO_PI * (t[1] + b)) * np.sin(TWO_PI * (t[2] + c)))
+    return np.ascontiguousarray(np.stack(out, axis=1), dtype=np.float64)
+
+
+def _xyz(N, nelem, lo, hi, xnodes):
+    if xnodes is None:
+        return node_coordinates(N, nelem, lo, hi)
+    return xnodes[:, 0], xnodes[:, 1], xnodes[:, 2]
+
+
 def element_centres(nelem, lo, hi):
     nx, ny, nz = nelem
     dx = [(hi[d] - lo[d]) / nelem[d] for d in range(3)]
@@ -65,24 +92,26 @@ def from_primitive(rho, u, v, w, p, gamma: float) -> np.ndarray:
 
 
 def density_wave(N: int, nelem=(4, 4, 4), lo=(0.0, 0.0, 0.0), hi=(TWO_PI,) * 3, gamma: float = 1.4,
-                 t: float = 0.0, amp: float = 0.2) -> np.ndarray:
-    """rho = 1 + amp sin(x + y + z - 3t), u = (1, 1, 1), p = 1 (exact Euler solution)."""
-    X, Y, Z = node_coordinates(N, nelem, lo, hi)
+                 t: float = 0.0, amp: float = 0.2, xnodes=None) -> np.ndarray:
+    """rho = 1 + amp sin(x + y + z - 3t), u = (1, 1, 1), p = 1 (exact Euler solution).
+    xnodes: sample at these node coordinates (curved mesh) instead of the box's."""
+    X, Y, Z = _xyz(N, nelem, lo, hi, xnodes)
     rho = 1.0 + amp * np.sin(X + Y + Z - 3.0 * t)
     one = np.ones_like(rho)
     return from_primitive(rho, one, one, one, one, gamma)
 
 
 def tgv(N: int, nelem=(32, 32, 32), Ma: float = 0.1, gamma: float = 1.4, symmetry_break: bool = False,
-        seed: int = 7, eps: float = 1e-3) -> np.ndarray:
+        seed: int = 7, eps: float = 1e-3, xnodes=None) -> np.ndarray:
     """Taylor-Green vortex on [0, 2pi]^3 with rho0 = U0 = L = 1.
 
     p0 = 1/(gamma Ma^2); u = sin x cos y cos z, v = -cos x sin y cos z, w = 0;
     p = p0 + (cos 2x + cos 2y)(cos 2z + 2)/16; rho = p / p0 (isothermal start).
     symmetry_break adds eps sin(x+f1) sin(2y+f2) cos(z+f3) to w, phases f ~ U(0, 2pi)
-    drawn from numpy's default_rng(seed).
+    drawn from numpy's default_rng(seed).  xnodes: sample at these node
+    coordinates (curved mesh of the same box).
     """
-    X, Y, Z = node_coordinates(N, nelem, (0.0, 0.0, 0.0), (TWO_PI,) * 3)
+    X, Y, Z = _xyz(N, nelem, (0.0, 0.0, 0.0), (TWO_PI,) * 3, xnodes)
     p0 = 1.0 / (gamma * Ma * Ma)
     u = np.sin(X) * np.cos(Y) * np.cos(Z)
     v = -np.cos(X) * np.sin(Y) * np.cos(Z)
@@ -121,14 +150,14 @@ def freestream(N: int, nelem=(4, 4, 4), lo=(0.0, 0.0, 0.0), hi=(TWO_PI,) * 3, ga
 
 def random_smooth(N: int, nelem=(3, 2, 2), lo=(0.0, 0.0, 0.0), hi=(TWO_PI,) * 3, gamma: float = 1.4,
                   seed: int = 0, amp: float = 0.1, modes: int = 3, mach: float = 0.5,
-                  noise: float = 0.0) -> np.ndarray:
+                  noise: float = 0.0, xnodes=None) -> np.ndarray:
     """Seeded smooth positive state: sums of low Fourier modes with random phases.
 
     noise > 0 adds i.i.d. node noise (relative) so that element interfaces are
     discontinuous and every code path of the surface terms is exercised.
     """
     rng = np.random.default_rng(seed)
-    X, Y, Z = node_coordinates(N, nelem, lo, hi)
+    X, Y, Z = _xyz(N, nelem, lo, hi, xnodes)
     L = [hi[d] - lo[d] for d in range(3)]
 
     def field():

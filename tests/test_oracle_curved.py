@@ -1,0 +1,292 @@
+"""Pins of the oracle's curved-element operator (split form with metric terms).
+
+* Metric terms: the discrete metric identities sum_i d_i(Ja^i_m) = 0 hold at
+  every node (checked with a derivative matrix built here from Lagrange
+  polynomials, not the oracle's); an affine sheared mapping gives the exact
+  constant metric (cofactors of the mapping's matrix) and J = its determinant.
+* A Cartesian mesh given as node coordinates reproduces the Cartesian
+  operator (Euler, Navier-Stokes, every flux family).
+* On a warped periodic mesh: a uniform state stays uniform (Euler and
+  Navier-Stokes), the integrals of U_t vanish (conservation), the kinetic
+  energy production of the KG/PI split forms and the entropy production of
+  the CH flux vanish with a central interface flux, and LLF/Roe dissipate
+  entropy.
+* Smooth exact solutions: the density wave's U_t and the viscous shear wave's
+  U_t converge to the closed-form values under refinement, as does the BR1
+  gradient of smooth data.
+* The surface flux along a general normal equals the Cartesian one for
+  n = e_d and is rotationally invariant.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2306_12891_amd import inputs as I
+
+G = 1.4
+TWO_PI = 2 * math.pi
+CASES = [(0, 0, 0), (0, 1, 1), (0, 2, 0), (0, 3, 2), (1, 1, 1), (1, 0, 0), (1, 3, 1)]
+
+
+def lagrange_D(x):
+    n = len(x)
+    lam = np.array([1.0 / np.prod([x[j] - x[k] for k in range(n) if k != j]) for j in range(n)])
+    D = np.zeros((n, n))
+    for i in range(n):
+        for j in range(n):
+            if i != j:
+                D[i, j] = lam[j] / lam[i] / (x[i] - x[j])
+        D[i, i] = -np.sum(D[i])
+    return D
+
+
+def dref(D, f, j):
+    """Derivative along reference direction j of nodal data f[..., k, j, i]."""
+    ax = f.ndim - 1 - j
+    return np.moveaxis(np.tensordot(D, np.moveaxis(f, ax, 0), axes=([1], [0])), 0, ax)
+
+
+def setup(orc, N, ne, xn, **kw):
+    return orc.Setup(N=N, nelem=ne, xnodes=xn, **kw)
+
+
+@pytest.mark.parametrize("N", [2, 4, 6])
+def test_metric_identities(orc, N):
+    ne = (2, 2, 3)
+    xn = I.warped_coordinates(N, ne, amp=0.06)
+    Ja, J = orc.metrics(setup(orc, N, ne, xn))
+    D = lagrange_D(I.lgl_points(N))
+    for m in range(3):
+        div = sum(dref(D, Ja[:, i, m], i) for i in range(3))
+        assert np.max(np.abs(div)) < 1e-12 * np.max(np.abs(Ja)), m
+    assert np.all(J > 0)
+
+
+def test_affine_mapping_metric(orc):
+    """x = A X (A sheared, constant): Ja^i = rows of cof(A) scaled to the element,
+    J = det of the element map."""
+    N, ne = 3, (2, 2, 2)
+    A = np.array([[1.0, 0.3, -0.2], [0.1, 0.9, 0.25], [-0.15, 0.2, 1.1]])
+    X, Y, Z = I.node_coordinates(N, ne, (0, 0, 0), (1.0, 1.0, 1.0))
+    P = np.stack([X, Y, Z], axis=1)  # (e, 3, k, j, i)
+    xn = np.ascontiguousarray(np.einsum("mn,enkji->emkji", A, P))
+    Ja, J = orc.metrics(setup(orc, N, ne, xn))
+    # element map: x = x0 + A diag(h/2) xi, h = 1/2
+    M = A * 0.25
+    detM = np.linalg.det(M)
+    cof = detM * np.linalg.inv(M)  # cof[i, m] = (J a^i)_m
+    assert np.max(np.abs(J - detM)) < 1e-14
+    for i in range(3):
+        for m in range(3):
+            assert np.max(np.abs(Ja[:, i, m] - cof[i, m])) < 1e-14, (i, m)
+
+
+@pytest.mark.parametrize("eq,vf,sf", CASES)
+def test_cartesian_coordinates_reproduce_box(orc, eq, vf, sf):
+    N, ne, lo, hi = 3, (3, 2, 2), (0.0, -1.0, 0.5), (2.0, 1.0, 2.0)
+    X, Y, Z = I.node_coordinates(N, ne, lo, hi)
+    xn = np.ascontiguousarray(np.stack([X, Y, Z], axis=1))
+    U = I.random_smooth(N, ne, lo, hi, seed=31, noise=0.02)
+    kw = dict(equations=eq, vol_flux=vf, surf_flux=sf, mu=2e-2)
+    a = orc.time_derivative(orc.Setup(N=N, nelem=ne, lo=lo, hi=hi, **kw), U)
+    b = orc.time_derivative(setup(orc, N, ne, xn, **kw), U)
+    assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(a))
+    s_box, s_cur = orc.Setup(N=N, nelem=ne, lo=lo, hi=hi, **kw), setup(orc, N, ne, xn, **kw)
+    assert abs(orc.max_dt(s_box, U) - orc.max_dt(s_cur, U)) <= 1e-12 * orc.max_dt(s_box, U)
+    assert np.allclose(orc.integrals(s_box, U), orc.integrals(s_cur, U), rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("eq,vf,sf", CASES)
+def test_freestream_preserved_on_warped_mesh(orc, eq, vf, sf):
+    for N in (2, 5):
+        ne = (2, 3, 2)
+        xn = I.warped_coordinates(N, ne, amp=0.06)
+        U = I.freestream(N, ne, u=(0.4, -0.3, 0.2))
+        Ut = orc.time_derivative(setup(orc, N, ne, xn, equations=eq, vol_flux=vf, surf_flux=sf, mu=1e-2), U)
+        # round-off of the metric identities, amplified by the sums over
+        # partners and metric components (a non-conservative metric, such as
+        # the cross-product form, leaves about 1e-5 here)
+        scale = np.max(np.abs(U)) * (2.0 / (TWO_PI / 3)) * N * (N + 1) / 2
+        assert np.max(np.abs(Ut)) <= 1e-12 * scale, (N, np.max(np.abs(Ut)))
+
+
+@pytest.mark.parametrize("eq,vf,sf", CASES)
+def test_conservation_on_warped_mesh(orc, eq, vf, sf):
+    N, ne = 4, (3, 2, 2)
+    xn = I.warped_coordinates(N, ne, amp=0.06)
+    s = setup(orc, N, ne, xn, equations=eq, vol_flux=vf, surf_flux=sf, mu=2e-2)
+    U = I.random_smooth(N, ne, seed=11, noise=0.02, xnodes=xn)
+    Ut = orc.time_derivative(s, U)
+    tot, mag = orc.integrals(s, Ut), orc.integrals(s, np.abs(Ut))
+    assert np.all(np.abs(tot) < 1e-13 * mag), (tot, mag)
+
+
+def kinetic_rate(orc, s, U, Ut):
+    rho, m = U[:, 0], U[:, 1:4]
+    u = m / rho[:, None]
+    a = np.einsum("evkji,evkji->ekji", u, Ut[:, 1:4])
+    b = 0.5 * np.sum(u * u, axis=1) * Ut[:, 0]
+    X, Xs = np.zeros_like(U), np.zeros_like(U)
+    X[:, 0] = a - b
+    Xs[:, 0] = np.abs(a) + np.abs(b)
+    return orc.integrals(s, X)[0], orc.integrals(s, Xs)[0]
+
+
+@pytest.mark.parametrize("vf", [0, 1])
+def test_kinetic_energy_preservation_on_warped_mesh(orc, vf):
+    N, ne = 4, (2, 2, 2)
+    xn = I.warped_coordinates(N, ne, amp=0.06)
+    X, Y, Z = xn[:, 0], xn[:, 1], xn[:, 2]
+    rng = np.random.default_rng(5)
+    rho = 1 + 0.3 * np.sin(X + 2 * Y) * np.cos(Z) + 0.05 * rng.standard_normal(X.shape)
+    u = np.sin(Y) + 0.1 * rng.standard_normal(X.shape)
+    U = I.from_primitive(rho, u, np.cos(Z + X), 0.5 * np.sin(X) * np.cos(Y), np.ones_like(X), G)
+    s = setup(orc, N, ne, xn, vol_flux=vf, surf_flux=2)
+    k, scale = kinetic_rate(orc, s, U, orc.time_derivative(s, U))
+    assert abs(k) < 1e-13 * scale, (k, scale)
+
+
+def entropy_rate(orc, s, U, Ut):
+    rho, m, E = U[:, 0], U[:, 1:4], U[:, 4]
+    u = m / rho[:, None]
+    p = (G - 1) * (E - 0.5 * rho * np.sum(u * u, 1))
+    sent = np.log(p * rho ** (-G))
+    v0 = (G - sent) / (G - 1) - rho * np.sum(u * u, 1) / (2 * p)
+    vm = rho[:, None] * u / p[:, None]
+    v4 = -rho / p
+    X, Xs = np.zeros_like(U), np.zeros_like(U)
+    X[:, 0] = v0 * Ut[:, 0] + np.sum(vm * Ut[:, 1:4], 1) + v4 * Ut[:, 4]
+    Xs[:, 0] = np.abs(v0 * Ut[:, 0]) + np.sum(np.abs(vm * Ut[:, 1:4]), 1) + np.abs(v4 * Ut[:, 4])
+    return orc.integrals(s, X)[0], orc.integrals(s, Xs)[0]
+
+
+def test_entropy_conservation_on_warped_mesh(orc):
+    """CH flux with a central interface flux: the metric average inside the
+    two-point flux keeps the scheme entropy conservative on curved elements."""
+    N, ne = 4, (2, 2, 2)
+    xn = I.warped_coordinates(N, ne, amp=0.06)
+    s = setup(orc, N, ne, xn, vol_flux=2, surf_flux=2)
+    U = I.random_smooth(N, ne, seed=21, noise=0.02, amp=0.3, xnodes=xn)
+    r, scale = entropy_rate(orc, s, U, orc.time_derivative(s, U))
+    assert abs(r) < 1e-14 * scale, (r, scale)
+
+
+@pytest.mark.parametrize("sf", [0, 1])
+def test_entropy_dissipation_on_warped_mesh(orc, sf):
+    N, ne = 4, (2, 2, 2)
+    xn = I.warped_coordinates(N, ne, amp=0.06)
+    s = setup(orc, N, ne, xn, vol_flux=2, surf_flux=sf)
+    U = I.random_smooth(N, ne, seed=22, noise=0.02, amp=0.3, xnodes=xn)
+    r, scale = entropy_rate(orc, s, U, orc.time_derivative(s, U))
+    assert r < -1e-6 * scale
+
+
+def density_wave_ut(xn):
+    """Exact U_t of the density wave at t = 0 (u = (1,1,1), p = 1)."""
+    rt = -3 * 0.2 * np.cos(xn[:, 0] + xn[:, 1] + xn[:, 2])
+    return np.stack([rt, rt, rt, rt, 1.5 * rt], axis=1)
+
+
+@pytest.mark.parametrize("vf,sf", [(0, 0), (1, 1)])
+def test_density_wave_converges_on_warped_mesh(orc, vf, sf):
+    """U_t of a smooth solution converges like the Cartesian operator, O(h^N)
+    (measured: 2.6e-2 -> 3.0e-3 from 8^3 to 16^3 elements at N = 3, against
+    8.8e-3 -> 1.1e-3 on the box)."""
+    N = 3
+    errs = []
+    for n in (8, 16):
+        ne = (n, n, n)
+        xn = I.warped_coordinates(N, ne, amp=0.04)
+        U = I.density_wave(N, ne, xnodes=xn)
+        Ut = orc.time_derivative(setup(orc, N, ne, xn, vol_flux=vf, surf_flux=sf), U)
+        errs.append(np.max(np.abs(Ut - density_wave_ut(xn))))
+    eoc = math.log2(errs[0] / errs[1])
+    assert errs[1] < 5e-3 and eoc > N - 0.5, (errs, eoc)
+
+
+def test_shear_wave_converges_on_warped_mesh(orc):
+    """u = A sin y, rho = 1, p = 2: U_t = (0, -mu A sin y, 0, 0, mu A^2 cos 2y).
+    On the warped mesh the advective terms leave a truncation error too (the
+    energy equation dominates); measured 0.11 -> 0.007 of mu A from 8^3 to
+    16^3 elements at N = 4."""
+    N, mu, A = 4, 0.05, 0.3
+    errs = []
+    for n in (8, 16):
+        ne = (n, n, n)
+        xn = I.warped_coordinates(N, ne, amp=0.04)
+        Y = xn[:, 1]
+        one = np.ones_like(Y)
+        U = I.from_primitive(one, A * np.sin(Y), 0 * Y, 0 * Y, 2.0 * one, G)
+        Ut = orc.time_derivative(setup(orc, N, ne, xn, equations=1, vol_flux=1, surf_flux=1, mu=mu), U)
+        ex = np.zeros_like(Ut)
+        ex[:, 1] = -mu * A * np.sin(Y)
+        ex[:, 4] = mu * A * A * np.cos(2 * Y)
+        errs.append(np.max(np.abs(Ut - ex)) / (mu * A))
+    eoc = math.log2(errs[0] / errs[1])
+    assert errs[1] < 2e-2 and eoc > N - 1.5, (errs, eoc)
+
+
+def test_gradient_converges_on_warped_mesh(orc):
+    N = 4
+    errs = []
+    for n in (3, 6):
+        ne = (n, n, n)
+        xn = I.warped_coordinates(N, ne, amp=0.04)
+        X, Y, Z = xn[:, 0], xn[:, 1], xn[:, 2]
+        rho = 1 + 0.2 * np.cos(Y)
+        u, v, w = np.sin(X), 0.5 * np.cos(Z), 0.3 * np.sin(Y) * np.cos(X)
+        p = 1.0 + 0.1 * np.sin(Z)
+        U = I.from_primitive(rho, u, v, w, p, G)
+        g = orc.gradient(setup(orc, N, ne, xn, equations=1, mu=1e-3), U)
+        ex_u = [np.cos(X), 0 * X, 0 * X]
+        ex_w = [-0.3 * np.sin(Y) * np.sin(X), 0.3 * np.cos(Y) * np.cos(X), 0 * X]
+        th = p / rho
+        ex_t = [0 * X, 0.2 * np.sin(Y) * p / rho ** 2, 0.1 * np.cos(Z) / rho]
+        e = 0.0
+        for d in range(3):
+            e = max(e, np.max(np.abs(g[:, d, 0] - ex_u[d])), np.max(np.abs(g[:, d, 2] - ex_w[d])),
+                    np.max(np.abs(g[:, d, 3] - ex_t[d])))
+        errs.append(e)
+        assert th.min() > 0
+    eoc = math.log2(errs[0] / errs[1])
+    assert eoc > N - 1.0, (errs, eoc)
+
+
+def test_surface_flux_along_axis_equals_cartesian(orc):
+    rng = np.random.default_rng(3)
+    for vf, sf in [(0, 0), (1, 1), (2, 0), (3, 2)]:
+        s = orc.Setup(N=2, vol_flux=vf, surf_flux=sf)
+        for d in range(3):
+            # rho = 1.1, u = (0.3, -0.2, 0.1), p = 0.9
+            L = np.array([1.1, 0.33, -0.22, 0.11, 0.9 / 0.4 + 0.5 * 1.1 * (0.09 + 0.04 + 0.01)])
+            R = L * (1 + 0.1 * rng.standard_normal(5))
+            R[4] = abs(R[4]) + 1.0
+            nv = np.zeros(3)
+            nv[d] = 1.0
+            a = orc.surface_flux(s, d, L, R)
+            b = orc.surface_flux_n(s, nv, L, R)
+            assert np.max(np.abs(a - b)) <= 1e-15 * np.max(np.abs(a)), (vf, sf, d)
+
+
+def test_surface_flux_rotational_invariance(orc):
+    """f*(n; L, R) = Q^T f*(e_x; Q L, Q R) with Q a rotation taking n to e_x
+    (momentum rotated, scalars unchanged)."""
+    rng = np.random.default_rng(4)
+    for vf, sf in [(0, 0), (1, 1), (2, 1), (3, 0)]:
+        s = orc.Setup(N=2, vol_flux=vf, surf_flux=sf)
+        for _ in range(5):
+            Q, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+            if np.linalg.det(Q) < 0:
+                Q[:, 0] = -Q[:, 0]
+            nv = Q[0]  # Q nv = e_x
+            def state():
+                rho, p = rng.uniform(0.5, 1.5), rng.uniform(0.5, 1.5)
+                u = rng.uniform(-0.5, 0.5, 3)
+                return np.array([rho, *(rho * u), p / 0.4 + 0.5 * rho * u @ u])
+            L, R = state(), state()
+            rot = lambda U: np.array([U[0], *(Q @ U[1:4]), U[4]])
+            f = orc.surface_flux_n(s, nv, L, R)
+            g = orc.surface_flux(s, 0, rot(L), rot(R))
+            back = np.array([g[0], *(Q.T @ g[1:4]), g[4]])
+            assert np.max(np.abs(f - back)) <= 1e-14 * np.max(np.abs(f)), (vf, sf)
