@@ -299,6 +299,10 @@ static inline int face_node(const Ctx& c, int d, int l, int a) {
 // (m, n, l) = (m, m+1, m+2) mod 3, every d_j the LGL derivative matrix along
 // reference direction j applied to nodal values (products interpolated at the
 // nodes).  J is the determinant of the derivative matrix dX_m/dxi^j at the node.
+// The coordinates are taken relative to the element's point c = (X_first +
+// X_last)/2 (first and last node): the curl form is unchanged by a
+// translation (the shift multiplies d_j d_k X_n - d_k d_j X_n = 0), and small
+// products X_l d X_n keep the round-off of the differences small.
 // ---------------------------------------------------------------------------
 static void deriv(const Ctx& c, const std::vector<double>& f, int j, std::vector<double>& out) {
   out.assign(c.nn, 0.0);
@@ -319,6 +323,8 @@ static void curved_metrics(Ctx& c) {
     std::vector<double> X[3], dX[3][3];  // dX[m][j] = d X_m / d xi^j
     for (int m = 0; m < 3; ++m) {
       X[m].assign(c.s.xnodes + (size_t(e) * 3 + m) * c.nn, c.s.xnodes + (size_t(e) * 3 + m + 1) * c.nn);
+      const double ctr = 0.5 * (X[m][0] + X[m][c.nn - 1]);
+      for (int n = 0; n < c.nn; ++n) X[m][n] = X[m][n] - ctr;
       for (int j = 0; j < 3; ++j) deriv(c, X[m], j, dX[m][j]);
     }
     for (int n = 0; n < c.nn; ++n) {
