@@ -45,7 +45,16 @@ WORKLOADS = {
     "tgv_les_n5_32": (5, (32, 32, 32), 1, 1, 1, 1.0 / 1600, 0,
                       "TGV Ma0.1 Re1600 LES (Smagorinsky C_s=0.17, Pr_t=0.9), N=5, 32^3 elems, PI+Roe, BR1, "
                       "LSERK4"),
+    "tgv_curved_n5_32": (5, (32, 32, 32), 1, 1, 1, 1.0 / 1600, 0,
+                         "TGV Ma0.1 Re1600 Pr0.72 on a warped periodic mesh (curved elements, curl-form metric "
+                         "terms, displacement amplitude 0.04 of the box), N=5, 32^3 elems, PI+Roe, BR1, LSERK4"),
 }
+
+# Curved workloads: amplitude of the smooth periodic node displacement
+# (inputs.warped_coordinates); the stage kernel then also reads the metric
+# terms, 10 doubles = 80 B per node and launch.
+CURVED = {"tgv_curved_n5_32": 0.04}
+METRIC_BYTES_PER_NODE = 80.0
 
 # Smagorinsky coefficient of the LES workloads (standard model, constant C_s).
 MODEL_CS = {"tgv_les_n5_32": 0.17}
@@ -57,10 +66,15 @@ SWEEP_MESHES = [(32, 32, 32), (32, 32, 64), (32, 64, 64), (64, 64, 64), (64, 64,
                 (128, 128, 128)]
 
 
+def curved_nodes(name, N, nelem):
+    from paper_2306_12891_amd import inputs
+    return inputs.warped_coordinates(N, nelem, amp=CURVED[name]) if name in CURVED else None
+
+
 def initial_state(name, N, nelem):
     from paper_2306_12891_amd import inputs
     if name.startswith("tgv"):
-        return inputs.tgv(N, nelem)
+        return inputs.tgv(N, nelem, xnodes=curved_nodes(name, N, nelem))
     if name.startswith("density_wave"):
         return inputs.density_wave(N, nelem)
     if name.startswith("freestream"):
@@ -196,7 +210,7 @@ def cpu_baseline(name, spec, U0, dt, max_nodes=8_000_000):
     def run(elems, U, threads):
         orc.set_threads(threads)
         s = orc.Setup(N=N, nelem=elems, lo=lo, hi=hi, equations=eq, vol_flux=vf, surf_flux=sf, mu=mu,
-                      blending=blend, Pr=0.72, Cs=MODEL_CS.get(name, 0.0))
+                      blending=blend, Pr=0.72, Cs=MODEL_CS.get(name, 0.0), xnodes=curved_nodes(name, N, elems))
         t0 = time.perf_counter()
         orc.rk_steps(s, U, dt, 1)
         return time.perf_counter() - t0
@@ -275,14 +289,15 @@ def measured_copy_bandwidth(torch, mib=4096, reps=10):
 def roofline(name, nodes, steps, prof):
     ms_stage, n_stage = prof["stage"]
     avg_ms = ms_stage / max(n_stage, 1)
-    A = stage_bytes_per_step(nodes) * steps / (ms_stage * 1e-3) / 1e9
+    step_bytes = stage_bytes_per_step(nodes) + (5 * METRIC_BYTES_PER_NODE * nodes if name in CURVED else 0.0)
+    A = step_bytes * steps / (ms_stage * 1e-3) / 1e9
     traffic = None
     if name in MEASURED_TRAFFIC and kernel_sha() == MEASURED_TRAFFIC["kernel_sha"]:
         traffic = MEASURED_TRAFFIC[name]["bytes_per_launch"]
     return {"bound": "hbm", "achieved": round(A, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(A / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_unit": "bytes per launch",
-            "kernel": "k_stage (operator + LSERK4 stage)", "avg_launch_ms": round(avg_ms, 4),
-            "algorithmic_bytes_per_launch": stage_bytes_per_step(nodes) / 5}
+            "kernel": ("k_stage_curved" if name in CURVED else "k_stage") + " (operator + LSERK4 stage)",
+            "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": step_bytes / 5}
 
 
 def blended_fraction(torch, op, U0, dt, steps, every=50):
@@ -389,6 +404,8 @@ def main():
     cs = MODEL_CS.get(name, 0.0)
     op = dg.DG(nelem, N, gamma=1.4, mu=mu, lo=lo, hi=hi, equations=eq, vol_flux=vf, surf_flux=sf,
                blending=blend, Pr=0.72, Cs=cs)
+    if name in CURVED:
+        op.set_geometry(torch.from_numpy(curved_nodes(name, N, nelem)).to("cuda:0"))
     U_init = device_freestream(torch, N, nelem) if U0 is None else torch.from_numpy(U0).to("cuda:0")
     U = U_init.clone()
     dt = op.max_dt(U, 0.5)
@@ -416,7 +433,7 @@ def main():
 
     # Mixed-precision operator on the same workload: same initial state, same
     # warm-up and timed steps; error of the final state against the FP64 run.
-    if not args.no_mixed and vf in (1, 3) and not blend:
+    if not args.no_mixed and vf in (1, 3) and not blend and name not in CURVED:
         opm = dg.DG(nelem, N, gamma=1.4, mu=mu, lo=lo, hi=hi, equations=eq, vol_flux=vf, surf_flux=sf,
                     Pr=0.72, precision=dg.MIXED, Cs=cs)
         Um = U_init.clone()

@@ -131,6 +131,31 @@ int dg_get_options(const dg_ctx* ctx, dg_options* opt);
  * the molecular viscosity only. */
 int dg_set_cs_field(dg_ctx* ctx, const double* cs);
 
+/* Curved hexahedral mesh (the paper's applications in Secs. 3-5 run on
+ * unstructured curvilinear meshes; the split form keeps its free-stream,
+ * conservation and kinetic-energy/entropy properties there when the metric
+ * terms satisfy the discrete metric identities).  X: device pointer to the
+ * node coordinates, X[e][m][k][j][i] (nElems x 3 x (N+1)^3 doubles, m = x, y,
+ * z; element order and face connectivity of the periodic structured mesh
+ * given to dg_init, each element a smooth image of the reference cube with
+ * faces shared by two elements holding the same points).  Read once: the
+ * library computes and keeps the metric terms (conservative curl form,
+ * 10 doubles per node: Ja^i_m and 1/J), after which every operator call
+ * (dg_time_derivative, dg_rk_steps, rk_step, dg_max_dt, dg_integrals) uses
+ * them:
+ *   J U_t = - sum_i [ sum_l Dhat_il F#(U_n, U_l).(Ja^i_n + Ja^i_l)/2 + lifted
+ *            face flux |Ja_f| f*(U-, U+; Ja_f/|Ja_f|) ],
+ * Ja_f the mean of both elements' metric at a face node; Navier-Stokes with
+ * the BR1 gradient (1/J) sum_i Ja^i (d_i q + lifting) and the contravariant
+ * viscous flux.  X = NULL returns to the Cartesian box of dg_init.
+ * Errors: DG_EINVAL for a host pointer or a non-positive / non-finite
+ * Jacobian at any node (the mesh stays Cartesian); DG_EUNSUPPORTED with
+ * blending, DG_MIXED, DG_VF_CH or the Smagorinsky model (and later
+ * dg_set_options / dg_set_cs_field calls that would enable them return it);
+ * DG_ENOMEM.  dg_vjp, rk_step_vjp and dg_node_weights return DG_EUNSUPPORTED
+ * on a curved mesh. */
+int dg_set_geometry(dg_ctx* ctx, const double* X);
+
 /* Sets the HIP stream (hipStream_t) all later calls enqueue on; NULL = null
  * stream. */
 int dg_set_stream(dg_ctx* ctx, void* hip_stream);

@@ -111,6 +111,7 @@ std::vector<double> build_basis(int N) {
     b[L.xi() + i] = x[i];
     b[L.w() + i] = w[i];
   }
+  for (int k = 0; k < n1 * n1; ++k) b[L.D() + k] = D[k];
   double s = -1.0;
   b[L.edge()] = -1.0;
   for (int m = 0; m < n1; ++m) {
@@ -175,6 +176,8 @@ struct dg_ctx {
   double* Fvf = nullptr;
   double* cs_field = nullptr;  // per-element Smagorinsky coefficients (dg_set_cs_field)
   int has_cs_field = 0;
+  double* M = nullptr;         // curved mesh metrics [nelem][10][nn] (dg_set_geometry), NULL: box
+  int* d_bad = nullptr;        // count of invalid Jacobians (dg_set_geometry)
   double* partial = nullptr;
   double* h_partial = nullptr;
   // reverse mode (allocated on first use): stage states Y_0..Y_4, the
@@ -231,6 +234,8 @@ void release(dg_ctx* c) {
   hipFree(c->alpha);
   hipFree(c->Fvf);
   hipFree(c->cs_field);
+  hipFree(c->M);
+  hipFree(c->d_bad);
   hipFree(c->partial);
   if (c->h_partial) hipHostFree(c->h_partial);
   for (double* y : c->Y) hipFree(y);
@@ -265,6 +270,7 @@ StageArgs stage_args(const dg_ctx* c) {
   a.indicator = c->opt.indicator;
   a.recon = c->opt.fv_recon;
   a.cs_elem = c->has_cs_field ? c->cs_field : nullptr;
+  a.M = c->M;
   a.cs = c->opt.Cs;
   const double delta = std::cbrt(c->dx[0] * c->dx[1] * c->dx[2]) / (c->N + 1.0);
   a.delta2 = delta * delta;
@@ -290,6 +296,7 @@ ReduceArgs reduce_args(const dg_ctx* c, const double* X) {
   r.nu_fac = c->opt.equations == DG_NS ? c->mu * c->gamma / c->opt.Pr : 0.0;
   r.Jac = c->Jac;
   r.nelem = c->nelem;
+  r.M = c->M;
   return r;
 }
 
@@ -341,8 +348,17 @@ int run_stage(dg_ctx* c, const double* Xin, double* Xout, double* Ut, int mode, 
     e = timed(c, DG_K_INDICATOR, [&] { return c->kt->alpha1(a, c->stream); });
     if (e != hipSuccess) return hip_fail(c, e, "indicator kernel");
   }
-  const bool mixed = c->opt.precision == DG_MIXED;
   const int eq = eq_code(c);
+  if (c->M) {  // curved mesh (FP64, no blending or eddy viscosity: checked when set)
+    if (eq >= 1) {
+      e = timed(c, DG_K_LIFT, [&] { return c->kt->lift_curved(a, c->stream); });
+      if (e != hipSuccess) return hip_fail(c, e, "lifting kernel (curved)");
+    }
+    e = timed(c, DG_K_STAGE, [&] { return c->kt->stage_curved(a, eq, c->stream); });
+    if (e != hipSuccess) return hip_fail(c, e, "stage kernel (curved)");
+    return DG_OK;
+  }
+  const bool mixed = c->opt.precision == DG_MIXED;
   if (eq >= 1) {
     e = timed(c, DG_K_LIFT,
               [&] { return mixed ? c->kt->lift_mixed(a, eq, c->stream) : c->kt->lift(a, eq, c->stream); });
@@ -356,7 +372,18 @@ int run_stage(dg_ctx* c, const double* Xin, double* Xout, double* Ut, int mode, 
 
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
+// Options a curved mesh supports: the FP64 operator with the KG, PI or STD
+// volume flux, Euler or Navier-Stokes, no blending, no eddy viscosity.
+int curved_compatible(dg_ctx* c, const dg_options* o, int cs_field, const char* where) {
+  if (o->blending) return fail(c, DG_EUNSUPPORTED, "%s: no blending on curved meshes", where);
+  if (o->precision != DG_FP64) return fail(c, DG_EUNSUPPORTED, "%s: curved meshes use the FP64 operator", where);
+  if (o->vol_flux == DG_VF_CH) return fail(c, DG_EUNSUPPORTED, "%s: curved meshes: KG, PI or STD flux", where);
+  if (o->Cs > 0.0 || cs_field) return fail(c, DG_EUNSUPPORTED, "%s: no Smagorinsky model on curved meshes", where);
+  return DG_OK;
+}
+
 int vjp_supported(dg_ctx* c) {
+  if (c->M) return fail(c, DG_EUNSUPPORTED, "vjp: not available on curved meshes");
   if (eq_code(c) == 2) return fail(c, DG_EUNSUPPORTED, "vjp: not available with the Smagorinsky model");
   if (c->opt.precision != DG_FP64) return fail(c, DG_EUNSUPPORTED, "vjp: FP64 operator only");
   if (c->opt.vol_flux == DG_VF_CH) return fail(c, DG_EUNSUPPORTED, "vjp: not available for the CH flux");
@@ -563,7 +590,44 @@ int dg_set_options(dg_ctx* c, const dg_options* o) {
     return fail(c, DG_EINVAL, "dg_set_options: need Cs >= 0 and Prt > 0");
   if ((o->Cs > 0.0 || c->has_cs_field) && o->equations == DG_NS && o->vol_flux == DG_VF_CH)
     return fail(c, DG_EUNSUPPORTED, "dg_set_options: the Smagorinsky model is built for the KG, PI and STD fluxes");
+  if (c->M) {
+    const int rc = curved_compatible(c, o, c->has_cs_field, "dg_set_options");
+    if (rc) return rc;
+  }
   c->opt = *o;
+  return DG_OK;
+}
+
+int dg_set_geometry(dg_ctx* c, const double* X) {
+  if (check_ctx(c)) return DG_EINVAL;
+  if (!X) {
+    hipFree(c->M);
+    c->M = nullptr;
+    return DG_OK;
+  }
+  if (!is_device_ptr(X)) return fail(c, DG_EINVAL, "dg_set_geometry: X must be a device pointer");
+  const int rc = curved_compatible(c, &c->opt, c->has_cs_field, "dg_set_geometry");
+  if (rc) return rc;
+  hipError_t e = hipSuccess;
+  double* M = c->M;
+  if (!M) e = hipMalloc((void**)&M, (size_t)c->nelem * 10 * c->nn * sizeof(double));
+  if (e == hipSuccess && !c->d_bad) e = hipMalloc((void**)&c->d_bad, sizeof(int));
+  int bad = 0;
+  if (e == hipSuccess) e = hipMemsetAsync(c->d_bad, 0, sizeof(int), c->stream);
+  if (e == hipSuccess) e = c->kt->metrics(X, c->basis, M, c->d_bad, c->nelem, c->chunk, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(&bad, c->d_bad, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    if (M != c->M) hipFree(M);
+    return fail(c, (e == hipErrorOutOfMemory) ? DG_ENOMEM : DG_EHIP, "dg_set_geometry: %s", hipGetErrorString(e));
+  }
+  c->M = M;
+  if (bad) {
+    hipFree(c->M);
+    c->M = nullptr;
+    return fail(c, DG_EINVAL, "dg_set_geometry: %d nodes with a non-positive or non-finite Jacobian", bad);
+  }
   return DG_OK;
 }
 
@@ -574,6 +638,7 @@ int dg_set_cs_field(dg_ctx* c, const double* cs) {
     return DG_OK;
   }
   if (!is_device_ptr(cs)) return fail(c, DG_EINVAL, "dg_set_cs_field: cs must be a device pointer");
+  if (c->M) return fail(c, DG_EUNSUPPORTED, "dg_set_cs_field: the Smagorinsky model is not built for curved meshes");
   if (c->opt.vol_flux == DG_VF_CH)
     return fail(c, DG_EUNSUPPORTED, "dg_set_cs_field: the Smagorinsky model is built for the KG, PI and STD fluxes");
   hipError_t e = hipSuccess;
@@ -767,6 +832,7 @@ int dg_profile_read(dg_ctx* c, double ms[5], int64_t launches[5]) {
 
 int dg_node_weights(const dg_ctx* c, double* w) {
   if (!c || !w) return DG_EINVAL;
+  if (c->M) return DG_EUNSUPPORTED;  // per-node Jacobians: use dg_integrals
   const std::vector<double> b = build_basis(c->N);
   const BasisLayout L(c->n1);
   for (int k = 0; k < c->n1; ++k)

@@ -22,7 +22,8 @@ struct BasisLayout {
   __host__ __device__ constexpr int edge() const { return 2 * n1 * n1 + 2 * n1; }  // n1 + 1 subcell edges
   __host__ __device__ constexpr int Vinv() const { return 2 * n1 * n1 + 3 * n1 + 1; }
   __host__ __device__ constexpr int w() const { return 3 * n1 * n1 + 3 * n1 + 1; }
-  __host__ __device__ constexpr int size() const { return 3 * n1 * n1 + 4 * n1 + 1; }
+  __host__ __device__ constexpr int D() const { return 3 * n1 * n1 + 4 * n1 + 1; }  // plain LGL derivative
+  __host__ __device__ constexpr int size() const { return 4 * n1 * n1 + 4 * n1 + 1; }
 };
 
 struct StageArgs {
@@ -46,6 +47,9 @@ struct StageArgs {
   double cs, delta2, ktf;
   int nelem, chunk;      // chunk = ceil(nelem / 8): XCD-contiguous element ranges
   int vf, sf, blend, mode, writeG, indicator, recon;
+  // curved mesh: M[e][10][nn], Ja^i_m at slot 3 i + m, 1/J at slot 9 (NULL:
+  // the Cartesian box)
+  const double* M;
 };
 
 struct ReduceArgs {
@@ -56,6 +60,7 @@ struct ReduceArgs {
   double gamma, nu_fac;  // nu_fac = mu gamma / Pr (0 for Euler)
   double Jac;
   int nelem;
+  const double* M;  // curved mesh metrics (see StageArgs), or NULL
 };
 
 // Vector-Jacobian product arguments (reverse mode of the FP64 operator).
@@ -103,6 +108,13 @@ struct KernelTable {
   hipError_t (*vjp_fv)(const VjpArgs&, hipStream_t);
   // y <- a y + b x over n doubles
   hipError_t (*axpby)(double* y, double a, const double* x, double b, size_t n, hipStream_t);
+  // curved mesh: metric terms from node coordinates X[e][3][nn] into M
+  // (counts non-positive or non-finite Jacobians into *bad), and the
+  // operator kernels with metric terms (FP64; eq 0 Euler, 1 Navier-Stokes)
+  hipError_t (*metrics)(const double* X, const double* basis, double* M, int* bad, int nelem, int chunk,
+                        hipStream_t);
+  hipError_t (*stage_curved)(const StageArgs&, int eq, hipStream_t);
+  hipError_t (*lift_curved)(const StageArgs&, hipStream_t);
 };
 
 const KernelTable* table_N1();

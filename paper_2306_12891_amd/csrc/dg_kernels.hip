@@ -2275,9 +2275,25 @@ __global__ __launch_bounds__(NT) void k_max_rate(ReduceArgs R) {
       const double vx = u[1] * ir, vy = u[2] * ir, vz = u[3] * ir;
       const double p = gm1 * (u[4] - 0.5 * (u[1] * vx + u[2] * vy + u[3] * vz));
       const double c = sqrt(R.gamma * p * ir);
-      const double ra = (fabs(vx) + c) * R.invdx[0] + (fabs(vy) + c) * R.invdx[1] + (fabs(vz) + c) * R.invdx[2];
-      const double rv = R.nu_fac * ir *
-                        (R.invdx[0] * R.invdx[0] + R.invdx[1] * R.invdx[1] + R.invdx[2] * R.invdx[2]);
+      double ra, rv;
+      if (R.M) {
+        // curved: 1/dx_d -> |Ja^d|/(2J), |u_d| -> |u.Ja^d|/|Ja^d| at the node
+        const double* Me = R.M + (size_t)e * 10 * nn + t;
+        const double iJ = Me[9 * nn];
+        ra = 0.0;
+        double h2 = 0.0;
+        for (int d = 0; d < 3; ++d) {
+          const double jx = Me[(3 * d) * nn], jy = Me[(3 * d + 1) * nn], jz = Me[(3 * d + 2) * nn];
+          const double jn = sqrt(jx * jx + jy * jy + jz * jz);
+          const double h = 0.5 * jn * iJ;
+          ra += (fabs(vx * jx + vy * jy + vz * jz) / jn + c) * h;
+          h2 += h * h;
+        }
+        rv = R.nu_fac * ir * h2;
+      } else {
+        ra = (fabs(vx) + c) * R.invdx[0] + (fabs(vy) + c) * R.invdx[1] + (fabs(vz) + c) * R.invdx[2];
+        rv = R.nu_fac * ir * (R.invdx[0] * R.invdx[0] + R.invdx[1] * R.invdx[1] + R.invdx[2] * R.invdx[2]);
+      }
       ma = fmax(ma, ra);
       mv = fmax(mv, rv);
     }
@@ -2310,7 +2326,9 @@ __global__ __launch_bounds__(NT) void k_integrals(ReduceArgs R) {
   for (int e = blockIdx.x; e < R.nelem; e += gridDim.x) {
     if (t < nn) {
       const double* Xe = R.X + (size_t)e * 5 * nn;
-      for (int v = 0; v < 5; ++v) acc[v] = fma(wq, Xe[v * nn + t], acc[v]);
+      // curved: the node's Jacobian in place of the constant one
+      const double wJ = R.M ? wq / (R.Jac * R.M[((size_t)e * 10 + 9) * nn + t]) : wq;
+      for (int v = 0; v < 5; ++v) acc[v] = fma(wJ, Xe[v * nn + t], acc[v]);
     }
   }
   for (int v = 0; v < 5; ++v) s[v][t] = acc[v];
@@ -2341,6 +2359,569 @@ __global__ __launch_bounds__(NT) void k_nonfinite(ReduceArgs R) {
     __syncthreads();
   }
   if (t == 0) R.partial[blockIdx.x] = s[0];
+}
+
+// ===========================================================================
+// Curved elements: the split form with metric terms (FP64).
+//
+// Metric array M[e][10][nn]: Ja^i_m (contravariant direction i, Cartesian
+// component m) at slot 3 i + m, 1/J at slot 9.  Computed once from the node
+// coordinates in the conservative curl form, which satisfies the discrete
+// metric identities (a uniform state stays uniform):
+//   Ja^i_m = -( d_j (X_l d_k X_n) - d_k (X_l d_j X_n) ),
+// (j, k) = (i+1, i+2) mod 3, (n, l) = (m+1, m+2) mod 3, d_j the LGL
+// derivative along reference direction j of nodal values.
+//   J U_t = - sum_i [ sum_l Dhat_il Ft#_i(U_n, U_l) + lifted surface flux ],
+//   Ft#_i(a, b) = F#(a, b) . (Ja^i(a) + Ja^i(b)) / 2,
+// with the interface flux ft* = |Ja_f| f*(U-, U+; Ja_f / |Ja_f|) and the face
+// metric Ja_f the mean of both elements' node metrics (both elements form the
+// same value, so conservation holds to round-off as on the box).  The
+// Navier-Stokes terms use the BR1 gradient by the chain rule,
+// grad q = (1/J) sum_i Ja^i (d_i q + lifting), and the contravariant viscous
+// flux sum_m Ja^i_m Fv_m, at faces Ja_f . (Fv- + Fv+)/2.
+// ===========================================================================
+constexpr int MS = 10;  // metric slots per node
+
+__device__ __forceinline__ int node_along(int n, int id, int st, int l) { return n + (l - id) * st; }
+
+// Metric terms of one element per workgroup; *bad counts nodes whose
+// Jacobian is not positive and finite.  Coordinates are taken relative to
+// c = (X_first + X_last)/2 of the element (the curl form is translation
+// invariant; small products keep the round-off of its differences small).
+__global__ __launch_bounds__(NT) void k_metrics(const double* X, const double* basis, double* M, int* bad,
+                                                 int nelem, int chunk) {
+  __shared__ double sD[nf];
+  __shared__ double sX[3][nn];
+  __shared__ double sG[2][nn];
+  const int e = element_of_block(blockIdx.x, chunk);
+  if (e >= nelem) return;
+  const int t = threadIdx.x;
+  for (int q = t; q < nf; q += NT) sD[q] = basis[BL.D() + q];
+  if (t < nn)
+    for (int m = 0; m < 3; ++m) {
+      const double* Xm = X + ((size_t)e * 3 + m) * nn;
+      sX[m][t] = Xm[t] - 0.5 * (Xm[0] + Xm[nn - 1]);
+    }
+  __syncthreads();
+  int ijk[3] = {0, 0, 0};
+  const int st[3] = {1, n1, nf};
+  double dX[3][3];
+  if (t < nn) {
+    ijk[0] = t % n1;
+    ijk[1] = (t / n1) % n1;
+    ijk[2] = t / nf;
+    for (int m = 0; m < 3; ++m)
+      for (int j = 0; j < 3; ++j) {
+        double s = 0.0;
+        for (int l = 0; l < n1; ++l) s = fma(sD[ijk[j] * n1 + l], sX[m][node_along(t, ijk[j], st[j], l)], s);
+        dX[m][j] = s;
+      }
+    const double J = dX[0][0] * (dX[1][1] * dX[2][2] - dX[1][2] * dX[2][1]) -
+                     dX[0][1] * (dX[1][0] * dX[2][2] - dX[1][2] * dX[2][0]) +
+                     dX[0][2] * (dX[1][0] * dX[2][1] - dX[1][1] * dX[2][0]);
+    if (!(J > 0.0) || !isfinite(J)) atomicAdd(bad, 1);
+    M[((size_t)e * MS + 9) * nn + t] = 1.0 / J;
+  }
+  for (int i = 0; i < 3; ++i) {
+    const int j = (i + 1) % 3, k = (i + 2) % 3;
+    for (int m = 0; m < 3; ++m) {
+      const int mn = (m + 1) % 3, ml = (m + 2) % 3;
+      __syncthreads();
+      if (t < nn) {
+        sG[0][t] = sX[ml][t] * dX[mn][k];
+        sG[1][t] = sX[ml][t] * dX[mn][j];
+      }
+      __syncthreads();
+      if (t < nn) {
+        double dp = 0.0, dq = 0.0;
+        for (int l = 0; l < n1; ++l) {
+          dp = fma(sD[ijk[j] * n1 + l], sG[0][node_along(t, ijk[j], st[j], l)], dp);
+          dq = fma(sD[ijk[k] * n1 + l], sG[1][node_along(t, ijk[k], st[k], l)], dq);
+        }
+        M[((size_t)e * MS + 3 * i + m) * nn + t] = -(dp - dq);
+      }
+    }
+  }
+}
+
+// Interface flux along the unit normal n: the momentum is rotated into an
+// orthonormal frame (n, t1, t2), the rotated-frame flux evaluated and rotated
+// back (the two-point fluxes and both dissipations are rotationally
+// invariant).  t1 is n crossed with the coordinate axis of its smallest
+// component.  L: minus side.
+template <int VF>
+__device__ __forceinline__ void surface_flux_normal(int sf, const double L[5], const double R[5], const double n[3],
+                                                    double gamma, double f[5]) {
+  const double ax = fabs(n[0]), ay = fabs(n[1]), az = fabs(n[2]);
+  double t1[3];
+  if (ax <= ay && ax <= az) {
+    t1[0] = 0.0; t1[1] = n[2]; t1[2] = -n[1];
+  } else if (ay <= az) {
+    t1[0] = -n[2]; t1[1] = 0.0; t1[2] = n[0];
+  } else {
+    t1[0] = n[1]; t1[1] = -n[0]; t1[2] = 0.0;
+  }
+  const double it = rcp64(sqrt64(t1[0] * t1[0] + t1[1] * t1[1] + t1[2] * t1[2]));
+  t1[0] *= it; t1[1] *= it; t1[2] *= it;
+  const double t2[3] = {n[1] * t1[2] - n[2] * t1[1], n[2] * t1[0] - n[0] * t1[2], n[0] * t1[1] - n[1] * t1[0]};
+  double a[5], b[5];
+  a[0] = L[0]; a[4] = L[4];
+  b[0] = R[0]; b[4] = R[4];
+  a[1] = n[0] * L[1] + n[1] * L[2] + n[2] * L[3];
+  a[2] = t1[0] * L[1] + t1[1] * L[2] + t1[2] * L[3];
+  a[3] = t2[0] * L[1] + t2[1] * L[2] + t2[2] * L[3];
+  b[1] = n[0] * R[1] + n[1] * R[2] + n[2] * R[3];
+  b[2] = t1[0] * R[1] + t1[1] * R[2] + t1[2] * R[3];
+  b[3] = t2[0] * R[1] + t2[1] * R[2] + t2[2] * R[3];
+  const Ref ref{0.0, 0.0, 0.0};
+  const State64 sa = state64<0>(a, gamma - 1.0), sb = state64<0>(b, gamma - 1.0);
+  const Jumps<double> J = jumps<double, false>(sa, sb, gamma, ref, sf);
+  double g[5];
+  riemann_rot<VF, double>(sf, to_rot<double, false>(sa, ref), to_rot<double, false>(sb, ref), J, gamma, g);
+  f[0] = g[0];
+  f[1] = g[1] * n[0] + g[2] * t1[0] + g[3] * t2[0];
+  f[2] = g[1] * n[1] + g[2] * t1[1] + g[3] * t2[1];
+  f[3] = g[1] * n[2] + g[2] * t1[2] + g[3] * t2[2];
+  f[4] = g[4];
+}
+
+// Geometry and loads of a curved face item: both conservative states in
+// Cartesian components, the metric row Ja^d of both elements at the face
+// node, and (Navier-Stokes) the neighbour's projected viscous flux.
+struct CurvedFace {
+  FaceItem it;
+  double L[5], R[5], jm[3], jp[3], fn[4];
+};
+
+template <bool NS>
+__device__ __forceinline__ void curved_face_issue(const StageArgs& A, int e, CurvedFace& cf) {
+  const FaceItem& it = cf.it;
+  const int eL = it.side ? e : it.nb, eR = it.side ? it.nb : e;
+  const int nL = it.side ? it.nown : it.nnb, nR = it.side ? it.nnb : it.nown;
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    cf.L[v] = A.U[((size_t)eL * 5 + v) * nn + nL];
+    cf.R[v] = A.U[((size_t)eR * 5 + v) * nn + nR];
+  }
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    cf.jm[m] = A.M[((size_t)eL * MS + 3 * it.d + m) * nn + nL];
+    cf.jp[m] = A.M[((size_t)eR * MS + 3 * it.d + m) * nn + nR];
+  }
+  if (NS) {
+    const double* Fn = A.Fvf + ((size_t)it.nb * 6 + (it.f ^ 1)) * 4 * nf + it.a;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) cf.fn[c] = Fn[c * nf];
+  }
+}
+
+// Face metric and lifted interface value q* = (q- + q+)/2, q = (u, v, w, theta).
+__device__ __forceinline__ void curved_face_q(const CurvedFace& cf, double gm1, double q[4]) {
+  const double iL = rcp64(cf.L[0]), iR = rcp64(cf.R[0]);
+  const double uL = cf.L[1] * iL, vL = cf.L[2] * iL, wL = cf.L[3] * iL;
+  const double uR = cf.R[1] * iR, vR = cf.R[2] * iR, wR = cf.R[3] * iR;
+  const double pL = gm1 * (cf.L[4] - 0.5 * (cf.L[1] * uL + cf.L[2] * vL + cf.L[3] * wL));
+  const double pR = gm1 * (cf.R[4] - 0.5 * (cf.R[1] * uR + cf.R[2] * vR + cf.R[3] * wR));
+  q[0] = 0.5 * (uL + uR);
+  q[1] = 0.5 * (vL + vR);
+  q[2] = 0.5 * (wL + wR);
+  q[3] = 0.5 * (pL * iL + pR * iR);
+}
+
+// Split-form volume sum along reference direction D with the averaged metric
+// (sums s = a + b of the node and partner values, js = Ja^D(a) + Ja^D(b)):
+//   KG/PI: f_rho = rs un/8, f_m = rs un us/16 + ps js/4, f_E = rs un xs/16
+//          (+ ps un/8 for KG), un = us.js;
+//   STD:   (F(a).js + F(b).js)/4.
+// Adds -(sum) to acc; with GRAD also returns the off-diagonal line sums of
+// the BR1 gradient (Dhat/2 = D off the diagonal).
+template <int VF, int D, bool GRAD>
+__device__ __forceinline__ void volume_dir_curved(const double (*sP)[nnp], const double (*sM)[nnp],
+                                                  const double* sDhat, int n, int id, const double me[7],
+                                                  const double jo[3], double acc[5], double* gs) {
+  constexpr int st = D == 0 ? 1 : (D == 1 ? n1 : nf);
+  const int base = n - id * st;
+  const double* crow = sDhat + id * n1;
+  double g0 = 0, g1 = 0, g2 = 0, g3 = 0;
+  double s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0, px = 0, py = 0, pz = 0, s5 = 0;
+  auto pair = [&](int l, int m) {
+    const double c = crow[l];
+    if (GRAD) {
+      g0 = fma(c, sP[1][m], g0);
+      g1 = fma(c, sP[2][m], g1);
+      g2 = fma(c, sP[3][m], g2);
+      g3 = fma(c, sP[6][m], g3);
+    }
+    const double jx = jo[0] + sM[3 * D + 0][m], jy = jo[1] + sM[3 * D + 1][m], jz = jo[2] + sM[3 * D + 2][m];
+    if (VF == VF_STD) {
+      const double ra = me[0], rb = sP[0][m];
+      const double ua = me[1] * jx + me[2] * jy + me[3] * jz;
+      const double ub = sP[1][m] * jx + sP[2][m] * jy + sP[3][m] * jz;
+      const double fa = c * (ra * ua), fb = c * (rb * ub);
+      s0 += fa + fb;
+      s1 = fma(fa, me[1], fma(fb, sP[1][m], s1));
+      s2 = fma(fa, me[2], fma(fb, sP[2][m], s2));
+      s3 = fma(fa, me[3], fma(fb, sP[3][m], s3));
+      s4 = fma(fa, me[5], fma(fb, sP[5][m], s4));
+      const double cp = c * (me[4] + sP[4][m]);
+      px = fma(cp, jx, px);
+      py = fma(cp, jy, py);
+      pz = fma(cp, jz, pz);
+    } else {
+      const double rs = me[0] + sP[0][m];
+      const double us = me[1] + sP[1][m], vs = me[2] + sP[2][m], ws = me[3] + sP[3][m];
+      const double ps = me[4] + sP[4][m], xs = me[5] + sP[5][m];
+      const double un = us * jx + vs * jy + ws * jz;
+      const double cf = c * (rs * un);
+      s0 += cf;
+      s1 = fma(cf, us, s1);
+      s2 = fma(cf, vs, s2);
+      s3 = fma(cf, ws, s3);
+      s4 = fma(cf, xs, s4);
+      const double cp = c * ps;
+      px = fma(cp, jx, px);
+      py = fma(cp, jy, py);
+      pz = fma(cp, jz, pz);
+      if (VF == VF_KG) s5 = fma(cp, un, s5);
+    }
+  };
+  partner_loop<true, st>(id, n, base, pair);
+  if (VF == VF_STD) {
+    acc[0] -= 0.25 * s0;
+    acc[1] -= 0.25 * (s1 + px);
+    acc[2] -= 0.25 * (s2 + py);
+    acc[3] -= 0.25 * (s3 + pz);
+    acc[4] -= 0.25 * s4;
+  } else {
+    acc[0] -= 0.125 * s0;
+    acc[1] -= 0.0625 * s1 + 0.25 * px;
+    acc[2] -= 0.0625 * s2 + 0.25 * py;
+    acc[3] -= 0.0625 * s3 + 0.25 * pz;
+    acc[4] -= 0.0625 * s4 + (VF == VF_KG ? 0.125 * s5 : 0.0);
+  }
+  if (GRAD) {
+    gs[0] = 0.5 * g0;
+    gs[1] = 0.5 * g1;
+    gs[2] = 0.5 * g2;
+    gs[3] = 0.5 * g3;
+  }
+}
+
+// Stage kernel on curved elements (one element per workgroup).  LDS:
+// primitives sP[7][nnp] and node metrics sM[9][nnp] (overlaid later by the
+// twelve contravariant viscous fluxes sV[12][nnp]), interface fluxes
+// sF[6][5][nf], and for Navier-Stokes q* sQ[6][4][nf], the neighbours'
+// projected viscous fluxes sFn[6][4][nf] and the face metrics sJf[6][3][nf].
+template <int VF, int EQ>
+__global__ __launch_bounds__(NT) void k_stage_curved(StageArgs A) {
+  constexpr bool NS = EQ >= 1;
+  constexpr int oM = 7 * nnp, oF = 16 * nnp, oQ = oF + 30 * nf, oFn = oQ + 24 * nf, oJf = oFn + 24 * nf;
+  constexpr int POOL = NS ? oJf + 18 * nf : oQ;
+  static_assert(12 * nnp <= oF, "viscous exchange overlays primitives and metrics only");
+  __shared__ double sPool[POOL];
+  __shared__ double sB[NB_STAGE];
+  double (*sP)[nnp] = reinterpret_cast<double (*)[nnp]>(sPool);
+  double (*sM)[nnp] = reinterpret_cast<double (*)[nnp]>(sPool + oM);
+  double (*sF)[5][nf] = reinterpret_cast<double (*)[5][nf]>(sPool + oF);
+  double (*sQ)[4][nf] = reinterpret_cast<double (*)[4][nf]>(sPool + (NS ? oQ : 0));
+  double (*sFn)[4][nf] = reinterpret_cast<double (*)[4][nf]>(sPool + (NS ? oFn : 0));
+  double (*sJf)[3][nf] = reinterpret_cast<double (*)[3][nf]>(sPool + (NS ? oJf : 0));
+  double (*sV)[nnp] = reinterpret_cast<double (*)[nnp]>(sPool);
+
+  const int e = element_of_block(blockIdx.x, A.chunk);
+  if (e >= A.nelem) return;
+  const int t = threadIdx.x;
+  const double gm1 = A.gamma - 1.0;
+  constexpr int FIC = (6 * nf + NT - 1) / NT;
+  CurvedFace cf[FIC];
+#pragma unroll
+  for (int k = 0; k < FIC; ++k)
+    if (t + k * NT < 6 * nf) cf[k].it = face_item_geometry(A.nbr, e, t + k * NT);
+  const double* Ue = A.U + (size_t)e * 5 * nn;
+  const double* Me = A.M + (size_t)e * MS * nn;
+  double u[5], gprev[5], mt[MS];
+  if (t < nn) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) u[v] = Ue[v * nn + t];
+#pragma unroll
+    for (int k = 0; k < MS; ++k) mt[k] = Me[k * nn + t];
+  }
+  const double bval = t < NB_STAGE ? A.basis[t] : 0.0;
+#pragma unroll
+  for (int k = 0; k < FIC; ++k)
+    if (t + k * NT < 6 * nf) curved_face_issue<NS>(A, e, cf[k]);
+  if (t < NB_STAGE) sB[t] = bval;
+  const double* sDhat = sB + BL.Dhat();
+  const double* sDw = sB + BL.Dw();
+  const double* swinv = sB + BL.winv();
+  const Ref ref0{0.0, 0.0, 0.0};
+
+  double me[7];
+  int ijk[3] = {0, 0, 0};
+  if (t < nn) {
+    primitives<VF, double, false>(u, gm1, ref0, me);
+#pragma unroll
+    for (int k = 0; k < 7; ++k)
+      if (k < 6 || NS) sP[k][t] = me[k];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) sM[k][t] = mt[k];
+    ijk[0] = t % n1;
+    ijk[1] = (t / n1) % n1;
+    ijk[2] = t / nf;
+  }
+#pragma unroll
+  for (int k = 0; k < FIC; ++k)
+    if (t + k * NT < 6 * nf) {
+      const CurvedFace& c = cf[k];
+      const FaceItem& it = c.it;
+      double Jf[3];
+#pragma unroll
+      for (int m = 0; m < 3; ++m) Jf[m] = 0.5 * (c.jm[m] + c.jp[m]);
+      const double sh = sqrt64(Jf[0] * Jf[0] + Jf[1] * Jf[1] + Jf[2] * Jf[2]);
+      const double ish = rcp64(sh);
+      const double nv[3] = {Jf[0] * ish, Jf[1] * ish, Jf[2] * ish};
+      double f[5];
+      surface_flux_normal<VF>(A.sf, c.L, c.R, nv, A.gamma, f);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) sF[it.f][v][it.a] = sh * f[v];
+      if (NS) {
+        double q[4];
+        curved_face_q(c, gm1, q);
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) {
+          sQ[it.f][cc][it.a] = q[cc];
+          sFn[it.f][cc][it.a] = c.fn[cc];
+        }
+#pragma unroll
+        for (int m = 0; m < 3; ++m) sJf[it.f][m][it.a] = Jf[m];
+      }
+    }
+  __syncthreads();
+
+  double acc[5] = {0, 0, 0, 0, 0};
+  double Fv[3][4];
+  if (t < nn) {
+    double gs[3][4];
+    volume_dir_curved<VF, 0, NS>(sP, sM, sDhat, t, ijk[0], me, mt + 0, acc, gs[0]);
+    volume_dir_curved<VF, 1, NS>(sP, sM, sDhat, t, ijk[1], me, mt + 3, acc, gs[1]);
+    volume_dir_curved<VF, 2, NS>(sP, sM, sDhat, t, ijk[2], me, mt + 6, acc, gs[2]);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int id = ijk[d];
+      const int a = d == 0 ? ijk[1] + n1 * ijk[2] : (d == 1 ? ijk[0] + n1 * ijk[2] : ijk[0] + n1 * ijk[1]);
+      if (id == 0 || id == N) {
+        const int f = 2 * d + (id == N);
+        const double c = id == N ? -swinv[N] : swinv[0];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) acc[v] = fma(c, sF[f][v][a], acc[v]);
+      }
+    }
+    if (NS) {
+      // reference-direction derivatives of q with the lifting, then the chain rule
+      const double qo[4] = {me[1], me[2], me[3], me[6]};
+      double s[3][4];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int id = ijk[d];
+        const int a = d == 0 ? ijk[1] + n1 * ijk[2] : (d == 1 ? ijk[0] + n1 * ijk[2] : ijk[0] + n1 * ijk[1]);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) s[d][c] = gs[d][c];
+        if (id == 0 || id == N) {
+          const int f = 2 * d + (id == N);
+          const double cd = sDw[id * n1 + id];
+          const double w = id == N ? swinv[N] : -swinv[0];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) s[d][c] = fma(w, sQ[f][c][a], fma(cd, qo[c], s[d][c]));
+        }
+      }
+      const double iJ = mt[9];
+      double g[3][4];
+#pragma unroll
+      for (int m = 0; m < 3; ++m)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          g[m][c] = iJ * (mt[m] * s[0][c] + mt[3 + m] * s[1][c] + mt[6 + m] * s[2][c]);
+      const double mu = A.mu, kap = A.kappa;
+      viscous_flux<0, double>(g, me[1], me[2], me[3], mu, kap, Fv[0]);
+      viscous_flux<1, double>(g, me[1], me[2], me[3], mu, kap, Fv[1]);
+      viscous_flux<2, double>(g, me[1], me[2], me[3], mu, kap, Fv[2]);
+    }
+  }
+
+  if (t < nn && A.mode != MODE_UT && A.A != 0.0) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) gprev[v] = A.G[(size_t)e * 5 * nn + t + v * nn];
+  }
+  if (NS) {
+    __syncthreads();  // sP, sM consumed
+    if (t < nn) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          sV[4 * d + c][t] = mt[3 * d] * Fv[0][c] + mt[3 * d + 1] * Fv[1][c] + mt[3 * d + 2] * Fv[2][c];
+    }
+    __syncthreads();
+    if (t < nn) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int st = d == 0 ? 1 : (d == 1 ? n1 : nf);
+        const int id = ijk[d];
+        const int base = t - id * st;
+        const double* crow = sDw + id * n1;
+        double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+#pragma unroll
+        for (int l = 0; l < n1; ++l) {
+          const int m = base + l * st;
+          const double c = crow[l];
+          s0 = fma(c, sV[4 * d + 0][m], s0);
+          s1 = fma(c, sV[4 * d + 1][m], s1);
+          s2 = fma(c, sV[4 * d + 2][m], s2);
+          s3 = fma(c, sV[4 * d + 3][m], s3);
+        }
+        const int a = d == 0 ? ijk[1] + n1 * ijk[2] : (d == 1 ? ijk[0] + n1 * ijk[2] : ijk[0] + n1 * ijk[1]);
+        if (id == 0 || id == N) {  // Gt* = Ja_f . (Fv(own) + Fv(nb)) / 2, the neighbour's part in sFn
+          const int f = 2 * d + (id == N);
+          const double w = 0.5 * (id == N ? swinv[N] : -swinv[0]);
+          const double jx = sJf[f][0][a], jy = sJf[f][1][a], jz = sJf[f][2][a];
+          s0 = fma(w, jx * Fv[0][0] + jy * Fv[1][0] + jz * Fv[2][0] + sFn[f][0][a], s0);
+          s1 = fma(w, jx * Fv[0][1] + jy * Fv[1][1] + jz * Fv[2][1] + sFn[f][1][a], s1);
+          s2 = fma(w, jx * Fv[0][2] + jy * Fv[1][2] + jz * Fv[2][2] + sFn[f][2][a], s2);
+          s3 = fma(w, jx * Fv[0][3] + jy * Fv[1][3] + jz * Fv[2][3] + sFn[f][3][a], s3);
+        }
+        acc[1] += s0;
+        acc[2] += s1;
+        acc[3] += s2;
+        acc[4] += s3;
+      }
+    }
+  }
+
+  if (t < nn) {
+    const double iJ = mt[9];
+    const size_t o = (size_t)e * 5 * nn + t;
+    if (A.mode != MODE_RK) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) A.Ut[o + v * nn] = acc[v] * iJ;
+    } else {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        const double ut = acc[v] * iJ;
+        double gv = ut;
+        if (A.A != 0.0) gv = A.A * gprev[v] + ut;
+        if (A.writeG) A.G[o + v * nn] = gv;
+        A.Uout[o + v * nn] = u[v] + A.Bdt * gv;
+      }
+    }
+  }
+}
+
+// BR1 lifting pass on curved elements: at each own face node the full
+// lifted gradient (reference derivatives of q along the three directions with
+// their lifting terms, chain rule with the node metric), the Cartesian viscous
+// fluxes and their projection on the face metric, Ja_f . Fv -> Fvf[e][f][c][a].
+__global__ __launch_bounds__(NT) void k_lift_curved(StageArgs A) {
+  __shared__ double sB[NB_STAGE];
+  __shared__ double sq[4][nn];
+  __shared__ double sQ[6][4][nf];
+  const int e = element_of_block(blockIdx.x, A.chunk);
+  if (e >= A.nelem) return;
+  const int t = threadIdx.x;
+  const double gm1 = A.gamma - 1.0;
+  constexpr int FIC = (6 * nf + NT - 1) / NT;
+  CurvedFace cf[FIC];
+#pragma unroll
+  for (int k = 0; k < FIC; ++k)
+    if (t + k * NT < 6 * nf) cf[k].it = face_item_geometry(A.nbr, e, t + k * NT);
+  const double* Ue = A.U + (size_t)e * 5 * nn;
+  double u[5];
+  if (t < nn) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) u[v] = Ue[v * nn + t];
+  }
+  const double bval = t < NB_STAGE ? A.basis[t] : 0.0;
+#pragma unroll
+  for (int k = 0; k < FIC; ++k)
+    if (t + k * NT < 6 * nf) curved_face_issue<false>(A, e, cf[k]);
+  if (t < NB_STAGE) sB[t] = bval;
+  if (t < nn) {
+    const double ir = rcp64(u[0]);
+    const double vx = u[1] * ir, vy = u[2] * ir, vz = u[3] * ir;
+    const double p = gm1 * (u[4] - 0.5 * (u[1] * vx + u[2] * vy + u[3] * vz));
+    sq[0][t] = vx;
+    sq[1][t] = vy;
+    sq[2][t] = vz;
+    sq[3][t] = p * ir;
+  }
+#pragma unroll
+  for (int k = 0; k < FIC; ++k)
+    if (t + k * NT < 6 * nf) {
+      double q[4];
+      curved_face_q(cf[k], gm1, q);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) sQ[cf[k].it.f][c][cf[k].it.a] = q[c];
+    }
+  __syncthreads();
+  const double* sDw = sB + BL.Dw();
+  const double* swinv = sB + BL.winv();
+#pragma unroll
+  for (int k = 0; k < FIC; ++k)
+    if (t + k * NT < 6 * nf) {
+      const FaceItem& it = cf[k].it;
+      const int n = it.nown;
+      const int ijk[3] = {n % n1, (n / n1) % n1, n / nf};
+      const double* Mn = A.M + (size_t)e * MS * nn + n;
+      double s[3][4];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int st = d == 0 ? 1 : (d == 1 ? n1 : nf);
+        const int id = ijk[d];
+        const int base = n - id * st;
+        const double* crow = sDw + id * n1;
+        double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+#pragma unroll 2
+        for (int l = 0; l < n1; ++l) {
+          const int m = base + l * st;
+          const double c = crow[l];
+          a0 = fma(c, sq[0][m], a0);
+          a1 = fma(c, sq[1][m], a1);
+          a2 = fma(c, sq[2][m], a2);
+          a3 = fma(c, sq[3][m], a3);
+        }
+        if (id == 0 || id == N) {
+          const int f = 2 * d + (id == N);
+          const int a = d == 0 ? ijk[1] + n1 * ijk[2] : (d == 1 ? ijk[0] + n1 * ijk[2] : ijk[0] + n1 * ijk[1]);
+          const double w = id == N ? swinv[N] : -swinv[0];
+          a0 = fma(w, sQ[f][0][a], a0);
+          a1 = fma(w, sQ[f][1][a], a1);
+          a2 = fma(w, sQ[f][2][a], a2);
+          a3 = fma(w, sQ[f][3][a], a3);
+        }
+        s[d][0] = a0;
+        s[d][1] = a1;
+        s[d][2] = a2;
+        s[d][3] = a3;
+      }
+      double mt[MS];
+#pragma unroll
+      for (int kk = 0; kk < MS; ++kk) mt[kk] = Mn[kk * nn];
+      double g[3][4];
+#pragma unroll
+      for (int m = 0; m < 3; ++m)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          g[m][c] = mt[9] * (mt[m] * s[0][c] + mt[3 + m] * s[1][c] + mt[6 + m] * s[2][c]);
+      double F[3][4];
+      viscous_flux<0, double>(g, sq[0][n], sq[1][n], sq[2][n], A.mu, A.kappa, F[0]);
+      viscous_flux<1, double>(g, sq[0][n], sq[1][n], sq[2][n], A.mu, A.kappa, F[1]);
+      viscous_flux<2, double>(g, sq[0][n], sq[1][n], sq[2][n], A.mu, A.kappa, F[2]);
+      double Jf[3];
+#pragma unroll
+      for (int m = 0; m < 3; ++m) Jf[m] = 0.5 * (cf[k].jm[m] + cf[k].jp[m]);
+      double* out = A.Fvf + ((size_t)e * 6 + it.f) * 4 * nf + it.a;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) out[c * nf] = Jf[0] * F[0][c] + Jf[1] * F[1][c] + Jf[2] * F[2][c];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -2476,6 +3057,35 @@ hipError_t launch_axpby(double* y, double a, const double* x, double b, size_t n
   return hipGetLastError();
 }
 
+template <int VF>
+hipError_t launch_stage_curved_vf(const StageArgs& A, int eq, hipStream_t s) {
+  const dim3 grid(blocks_for(A)), block(NT);
+  if (eq == 1) hipLaunchKernelGGL((k_stage_curved<VF, 1>), grid, block, 0, s, A);
+  else hipLaunchKernelGGL((k_stage_curved<VF, 0>), grid, block, 0, s, A);
+  return hipGetLastError();
+}
+
+// Curved elements: KG, PI and STD volume fluxes.
+hipError_t launch_stage_curved(const StageArgs& A, int eq, hipStream_t s) {
+  switch (A.vf) {
+    case VF_KG: return launch_stage_curved_vf<VF_KG>(A, eq, s);
+    case VF_PI: return launch_stage_curved_vf<VF_PI>(A, eq, s);
+    case VF_STD: return launch_stage_curved_vf<VF_STD>(A, eq, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_lift_curved(const StageArgs& A, hipStream_t s) {
+  hipLaunchKernelGGL(k_lift_curved, dim3(blocks_for(A)), dim3(NT), 0, s, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_metrics(const double* X, const double* basis, double* M, int* bad, int nelem, int chunk,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_metrics, dim3(8 * chunk), dim3(NT), 0, s, X, basis, M, bad, nelem, chunk);
+  return hipGetLastError();
+}
+
 hipError_t launch_nonfinite(const ReduceArgs& R, hipStream_t s) {
   hipLaunchKernelGGL(k_nonfinite, dim3(RED_BLOCKS), dim3(NT), 0, s, R);
   return hipGetLastError();
@@ -2484,7 +3094,7 @@ hipError_t launch_nonfinite(const ReduceArgs& R, hipStream_t s) {
 const KernelTable kTable = {
     NT, launch_stage, launch_stage_mixed, launch_lift, launch_lift_mixed, launch_alpha1, launch_spread,
     launch_max_rate, launch_integrals, launch_nonfinite, launch_vjp, launch_vjp_lift, launch_vjp_alpha_bar,
-    launch_vjp_alpha, launch_vjp_fv, launch_axpby,
+    launch_vjp_alpha, launch_vjp_fv, launch_axpby, launch_metrics, launch_stage_curved, launch_lift_curved,
 };
 
 }  // namespace

@@ -30,7 +30,7 @@ FP64, MIXED = 0, 1
 EXPORTS = ["dg_default_options", "dg_init", "dg_set_options", "dg_get_options", "dg_set_stream",
            "dg_time_derivative", "rk_step", "dg_rk_steps", "dg_vjp", "rk_step_vjp", "dg_max_dt",
            "dg_integrals", "dg_alpha", "dg_check_finite", "dg_set_profiling", "dg_profile_read", "dg_node_weights",
-           "dg_sizes", "dg_finalize", "dg_last_error", "dg_set_cs_field"]
+           "dg_sizes", "dg_finalize", "dg_last_error", "dg_set_cs_field", "dg_set_geometry"]
 
 
 class DGError(RuntimeError):
@@ -85,6 +85,7 @@ def lib() -> ctypes.CDLL:
             "dg_finalize": ([P], I),
             "dg_last_error": ([P], ctypes.c_char_p),
             "dg_set_cs_field": ([P, P], I),
+            "dg_set_geometry": ([P, P], I),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -160,6 +161,21 @@ class DG:
             raise ValueError(f"cs must be contiguous with {self.n_elems} values")
         self._stream()
         self._check(lib().dg_set_cs_field(self._ctx, ctypes.c_void_p(cs.data_ptr())))
+
+    def set_geometry(self, X: torch.Tensor | None):
+        """Curved mesh: node coordinates, float64 GPU tensor of shape
+        (n_elems, 3, N+1, N+1, N+1) (x index fastest; read once, the library
+        keeps the metric terms), or None for the Cartesian box."""
+        if X is None:
+            self._check(lib().dg_set_geometry(self._ctx, None))
+            return
+        n1 = self.N + 1
+        if not isinstance(X, torch.Tensor) or not X.is_cuda or X.dtype != torch.float64:
+            raise TypeError("X must be a float64 GPU tensor")
+        if tuple(X.shape) != (self.n_elems, 3, n1, n1, n1) or not X.is_contiguous():
+            raise ValueError(f"X must be contiguous of shape {(self.n_elems, 3, n1, n1, n1)}")
+        self._stream()
+        self._check(lib().dg_set_geometry(self._ctx, ctypes.c_void_p(X.data_ptr())))
 
     def close(self):
         if getattr(self, "_ctx", None) is not None and self._ctx.value:

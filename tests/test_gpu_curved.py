@@ -1,0 +1,188 @@
+"""Curved elements on the GPU (dg_set_geometry) against the FP64 oracle,
+through the C ABI: single evaluations on a warped periodic mesh for every
+degree and flux pair to 1e-12 of the term scale (Euler and Navier-Stokes),
+free-stream preservation, conservation, a Runge-Kutta rollout, the time step
+and integrals, the Cartesian box given as coordinates, a full-size TGV at
+N = 5 on 32^3 warped elements, and the error paths."""
+import ctypes
+import math
+
+import numpy as np
+import pytest
+
+from paper_2306_12891_amd import inputs as I
+from test_gpu_parity import G, TWO_PI, assert_state_close, assert_ut_close, phys_flux_scale
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def make(orc, torch, N, nelem, xn, eq=0, vf=0, sf=0, mu=0.0):
+    from paper_2306_12891_amd import dg
+    s = orc.Setup(N=N, nelem=nelem, equations=eq, vol_flux=vf, surf_flux=sf, mu=mu, xnodes=xn)
+    op = dg.DG(nelem, N, gamma=G, mu=mu, equations=eq, vol_flux=vf, surf_flux=sf)
+    op.set_geometry(torch.from_numpy(xn).cuda())
+    return s, op
+
+
+def gpu_ut(torch, op, U):
+    return op.time_derivative(torch.from_numpy(U).cuda()).cpu().numpy()
+
+
+def assert_curved_close(orc, s, got, ref, U, tol=1e-12):
+    """Per variable to tol of max(max |U_t|, S_v): S_v the scale of the terms
+    that cancel, N(N+1)/2 max |F| times the largest |Ja^i|/J of the mesh (the
+    curved counterpart of 2/dx)."""
+    Ja, J = orc.metrics(s)
+    h = max(np.max(np.sqrt(np.sum(Ja[:, i] ** 2, axis=1)) / J) for i in range(3))
+    S = phys_flux_scale(U, s.N, [h, h, h])
+    for v in range(5):
+        scale = max(np.max(np.abs(ref[:, v])), S[v])
+        err = np.max(np.abs(got[:, v] - ref[:, v]))
+        assert err <= tol * scale, f"var {v}: err {err:.3e} scale {scale:.3e} rel {err / scale:.3e}"
+
+
+BOX = ((0.0, 0.0, 0.0), (TWO_PI,) * 3)
+
+
+@pytest.mark.parametrize("N", range(1, 8))
+def test_euler_all_degrees(orc, torch_cuda, N):
+    ne = (3, 2, 2)
+    xn = I.warped_coordinates(N, ne, amp=0.05)
+    s, op = make(orc, torch_cuda, N, ne, xn, vf=0, sf=0)
+    U = I.random_smooth(N, ne, seed=80 + N, noise=0.02, xnodes=xn)
+    assert_curved_close(orc, s, gpu_ut(torch_cuda, op, U), orc.time_derivative(s, U), U)
+
+
+@pytest.mark.parametrize("vf,sf", [(1, 1), (3, 2), (0, 1), (1, 0), (3, 0)])
+@pytest.mark.parametrize("N", [3, 5])
+def test_euler_flux_pairs(orc, torch_cuda, N, vf, sf):
+    ne = (2, 3, 2)
+    xn = I.warped_coordinates(N, ne, amp=0.05)
+    s, op = make(orc, torch_cuda, N, ne, xn, vf=vf, sf=sf)
+    U = I.random_smooth(N, ne, seed=90 + N + 7 * vf, noise=0.02, xnodes=xn)
+    assert_curved_close(orc, s, gpu_ut(torch_cuda, op, U), orc.time_derivative(s, U), U)
+
+
+@pytest.mark.parametrize("vf,sf", [(1, 1), (0, 0), (3, 2)])
+@pytest.mark.parametrize("N", [2, 3, 4, 5, 6, 7])
+def test_navier_stokes(orc, torch_cuda, N, vf, sf):
+    ne = (2, 2, 3)
+    xn = I.warped_coordinates(N, ne, amp=0.05)
+    s, op = make(orc, torch_cuda, N, ne, xn, eq=1, vf=vf, sf=sf, mu=2e-2)
+    U = I.random_smooth(N, ne, seed=100 + N, noise=0.02, xnodes=xn)
+    ref = orc.time_derivative(s, U)
+    assert_curved_close(orc, s, gpu_ut(torch_cuda, op, U), ref, U)
+
+
+@pytest.mark.parametrize("eq", [0, 1])
+def test_freestream_and_conservation(orc, torch_cuda, eq):
+    import torch
+    N, ne = 4, (3, 3, 2)
+    xn = I.warped_coordinates(N, ne, amp=0.06)
+    s, op = make(orc, torch_cuda, N, ne, xn, eq=eq, vf=1, sf=1, mu=1e-2)
+    U = I.freestream(N, ne, u=(0.4, -0.3, 0.2))
+    Ut = gpu_ut(torch_cuda, op, U)
+    scale = np.max(np.abs(U)) * (2.0 / (TWO_PI / 3)) * N * (N + 1) / 2
+    assert np.max(np.abs(Ut)) <= 1e-12 * scale
+    U = I.random_smooth(N, ne, seed=7, noise=0.02, xnodes=xn)
+    Utd = op.time_derivative(torch.from_numpy(U).cuda())
+    tot = np.array(op.integrals(Utd))
+    mag = np.array(op.integrals(Utd.abs()))
+    assert np.all(np.abs(tot) <= 1e-13 * mag), (tot, mag)
+
+
+def test_rollout(orc, torch_cuda):
+    import torch
+    N, ne = 3, (3, 3, 3)
+    xn = I.warped_coordinates(N, ne, amp=0.04)
+    s, op = make(orc, torch_cuda, N, ne, xn, eq=1, vf=1, sf=1, mu=1.0 / 1600)
+    U0 = I.tgv(N, ne, symmetry_break=True, xnodes=xn)
+    Ud = torch.from_numpy(U0).cuda()
+    dt = op.max_dt(Ud, 0.5)
+    assert abs(dt - orc.max_dt(s, U0, 0.5)) <= 1e-12 * dt
+    op.rk_steps(Ud, dt, 5)
+    assert_state_close(Ud.cpu().numpy(), orc.rk_steps(s, U0, dt, 5))
+
+
+def test_integrals_and_dt(orc, torch_cuda):
+    import torch
+    N, ne = 5, (2, 3, 2)
+    xn = I.warped_coordinates(N, ne, amp=0.06)
+    s, op = make(orc, torch_cuda, N, ne, xn, eq=1, vf=1, sf=1, mu=3e-2)
+    U = I.random_smooth(N, ne, seed=12, xnodes=xn)
+    Ud = torch.from_numpy(U).cuda()
+    assert np.allclose(op.integrals(Ud), orc.integrals(s, U), rtol=1e-13, atol=0)
+    assert abs(op.max_dt(Ud, 0.5) - orc.max_dt(s, U, 0.5)) <= 1e-12 * orc.max_dt(s, U, 0.5)
+
+
+def test_box_coordinates_and_reset(orc, torch_cuda):
+    """The Cartesian box given as coordinates gives the Cartesian operator, and
+    set_geometry(None) returns to it."""
+    import torch
+
+    from paper_2306_12891_amd import dg
+    N, ne = 4, (3, 2, 2)
+    X, Y, Z = I.node_coordinates(N, ne, *BOX)
+    xc = np.ascontiguousarray(np.stack([X, Y, Z], axis=1))
+    U = I.random_smooth(N, ne, seed=13, noise=0.02)
+    Ud = torch.from_numpy(U).cuda()
+    op = dg.DG(ne, N, gamma=G, mu=2e-2, equations=dg.NS, vol_flux=dg.PI, surf_flux=dg.ROE)
+    box = op.time_derivative(Ud).cpu().numpy()
+    op.set_geometry(torch.from_numpy(xc).cuda())
+    cur = op.time_derivative(Ud).cpu().numpy()
+    assert_ut_close(cur, box, U, N, ne, *BOX)
+    op.set_geometry(None)
+    assert np.array_equal(op.time_derivative(Ud).cpu().numpy(), box)
+
+
+def test_full_size_tgv_n5_32(orc, torch_cuda):
+    """TGV at N = 5 on 32^3 warped elements (7 M DOF): whole-mesh U_t."""
+    N, ne = 5, (32, 32, 32)
+    xn = I.warped_coordinates(N, ne, amp=0.04)
+    s, op = make(orc, torch_cuda, N, ne, xn, eq=1, vf=1, sf=1, mu=1.0 / 1600)
+    U = I.tgv(N, ne, xnodes=xn)
+    assert_curved_close(orc, s, gpu_ut(torch_cuda, op, U), orc.time_derivative(s, U), U)
+
+
+def test_error_paths(orc, torch_cuda):
+    import torch
+
+    from paper_2306_12891_amd import dg
+    N, ne = 3, (2, 2, 2)
+    xn = I.warped_coordinates(N, ne, amp=0.05)
+    op = dg.DG(ne, N, gamma=G, mu=1e-2, equations=dg.NS, vol_flux=dg.PI, surf_flux=dg.ROE)
+    assert op.raw_call("dg_set_geometry", ctypes.c_void_p(xn.ctypes.data)) == dg.DG_EINVAL  # host pointer
+    # an inverted element: its x coordinates mirrored
+    bad = xn.copy()
+    bad[0, 0] = bad[0, 0, :, :, ::-1]
+    with pytest.raises(dg.DGError) as ei:
+        op.set_geometry(torch.from_numpy(np.ascontiguousarray(bad)).cuda())
+    assert ei.value.code == dg.DG_EINVAL
+    U = torch.from_numpy(I.random_smooth(N, ne, seed=3)).cuda()
+    box = op.time_derivative(U).cpu().numpy()  # still the box
+    s_box = orc.Setup(N=N, nelem=ne, equations=1, vol_flux=1, surf_flux=1, mu=1e-2)
+    assert_ut_close(box, orc.time_derivative(s_box, U.cpu().numpy()), U.cpu().numpy(), N, ne, *BOX)
+    op.set_geometry(torch.from_numpy(xn).cuda())
+    for kw in (dict(precision=dg.MIXED), dict(vol_flux=dg.CH), dict(Cs=0.1),
+               dict(equations=dg.EULER, blending=1)):
+        with pytest.raises(dg.DGError) as ei:
+            op.set_options(**kw)
+        assert ei.value.code == dg.DG_EUNSUPPORTED, kw
+    with pytest.raises(dg.DGError) as ei:
+        op.vjp(U, U.clone())
+    assert ei.value.code == dg.DG_EUNSUPPORTED
+    with pytest.raises(dg.DGError) as ei:
+        op.set_cs_field(torch.full((8,), 0.1, dtype=torch.float64, device="cuda"))
+    assert ei.value.code == dg.DG_EUNSUPPORTED
+    op2 = dg.DG(ne, N, gamma=G, mu=1e-2, equations=dg.NS, vol_flux=dg.PI, surf_flux=dg.ROE, precision=dg.MIXED)
+    with pytest.raises(dg.DGError) as ei:
+        op2.set_geometry(torch.from_numpy(xn).cuda())
+    assert ei.value.code == dg.DG_EUNSUPPORTED
