@@ -78,6 +78,10 @@ struct Setup {
   // structured periodic connectivity; lo/hi are then unused), or NULL for the
   // Cartesian box.
   const double* xnodes;
+  // Curved mesh with general connectivity (unstructured hexahedra): for every
+  // element e and local face f, conn[e][f] = (neighbour, neighbour's local
+  // face, orientation 0..7), or NULL for the structured periodic mesh.
+  const int32_t* conn;
 };
 
 // ---------------------------------------------------------------------------
@@ -208,6 +212,7 @@ struct Ctx {
   bool curved = false;
   std::vector<double> Ja;  // [e][i][m][n]
   std::vector<double> Jn;  // [e][n]
+  std::vector<int> conn;   // [e][f][3]: neighbour, its face, orientation (curved meshes)
   double ja(int e, int i, int m, int n) const { return Ja[((size_t(e) * 3 + i) * 3 + m) * nn + n]; }
   double jac(int e, int n) const { return Jn[size_t(e) * nn + n]; }
   // (C_s Delta)^2 of element e; 0 without the Smagorinsky model
@@ -256,7 +261,21 @@ static Ctx make_ctx(const Setup& s) {
         c.nbr[6 * e + 4] = id(ex, ey, ez - 1);
         c.nbr[6 * e + 5] = id(ex, ey, ez + 1);
       }
-  if (s.xnodes) curved_metrics(c);
+  if (s.xnodes) {
+    curved_metrics(c);
+    c.conn.assign(size_t(c.nelem) * 18, 0);
+    for (int e = 0; e < c.nelem; ++e)
+      for (int f = 0; f < 6; ++f) {
+        int* q = &c.conn[(size_t(e) * 6 + f) * 3];
+        if (s.conn) {
+          for (int k = 0; k < 3; ++k) q[k] = s.conn[(size_t(e) * 6 + f) * 3 + k];
+        } else {
+          q[0] = c.nbr[6 * e + f];
+          q[1] = f ^ 1;
+          q[2] = 0;
+        }
+      }
+  }
   return c;
 }
 
@@ -764,36 +783,85 @@ static void viscous_dg(const Ctx& c, const T* U, T* Ut) {
 // node the metric is the mean of both elements' node metrics, Ja_f, and
 // ft* = |Ja_f| f*(U-, U+; Ja_f/|Ja_f|), so both elements see the same value.
 // ---------------------------------------------------------------------------
-// Face metric of the +i face of element e at face index a.
-static void face_metric(const Ctx& c, int e, int i, int a, double Jf[3]) {
-  const int nb = c.nbr[6 * e + 2 * i + 1];
-  const int nm = face_node(c, i, c.N, a), np = face_node(c, i, 0, a);
-  for (int m = 0; m < 3; ++m) Jf[m] = 0.5 * (c.ja(e, i, m, nm) + c.ja(nb, i, m, np));
+// Face-local index a = t1 + (N+1) t2 of a face (t1 along the lower of the two
+// remaining reference axes) mapped to the neighbour's face-local index by the
+// orientation code o: bit 0 swaps (t1, t2), bit 1 reverses the first and bit 2
+// the second index of the result.
+static int orient_index(const Ctx& c, int o, int a) {
+  const int t1 = a % c.n1, t2 = a / c.n1;
+  int u = (o & 1) ? t2 : t1, v = (o & 1) ? t1 : t2;
+  if (o & 2) u = c.N - u;
+  if (o & 4) v = c.N - v;
+  return u + c.n1 * v;
 }
 
+// The two sides of face f of element e at face index a: own and neighbour
+// element, local face and volume node, and which side is the face's minus
+// side.  reading: every face is evaluated once, from its minus to its plus
+// side; the minus side is the one whose local face is a + face when the other
+// is a - face (so a structured mesh keeps "the element whose + face it is"),
+// else the smaller (element, face) pair.  The face normal from minus to plus,
+// N = (s_m Ja_m - s_p Ja_p)/2, s = +1 on + faces and -1 on - faces, Ja the
+// node metric row of the face's reference direction.
+struct FaceSides {
+  int e, f, n, nb, fb, nbn;
+  bool own_minus;
+};
+
+static FaceSides face_sides(const Ctx& c, int e, int f, int a) {
+  FaceSides r;
+  r.e = e;
+  r.f = f;
+  r.n = face_node(c, f >> 1, (f & 1) ? c.N : 0, a);
+  const int* q = &c.conn[(size_t(e) * 6 + f) * 3];
+  r.nb = q[0];
+  r.fb = q[1];
+  r.nbn = face_node(c, r.fb >> 1, (r.fb & 1) ? c.N : 0, orient_index(c, q[2], a));
+  const bool po = f & 1, pb = r.fb & 1;
+  r.own_minus = (po && !pb) || (po == pb && (e < r.nb || (e == r.nb && f < r.fb)));
+  return r;
+}
+
+// Face normal vector N (minus to plus) and the own face's metric along its
+// reference direction +xi, s * (outward normal) = s * (own_minus ? N : -N).
+static void face_vectors(const Ctx& c, const FaceSides& fs, double Nv[3], double Jown[3]) {
+  const double so = (fs.f & 1) ? 1.0 : -1.0, sb = (fs.fb & 1) ? 1.0 : -1.0;
+  const int io = fs.f >> 1, ib = fs.fb >> 1;
+  for (int m = 0; m < 3; ++m) {
+    const double ao = so * c.ja(fs.e, io, m, fs.n), ab = sb * c.ja(fs.nb, ib, m, fs.nbn);
+    Nv[m] = fs.own_minus ? 0.5 * (ao - ab) : 0.5 * (ab - ao);
+    Jown[m] = so * (fs.own_minus ? Nv[m] : -Nv[m]);
+  }
+}
+
+// Interface flux of every element face along the face's reference direction
+// +xi: fface[e][f][v][a] = s * (outward flux), the outward flux being
+// ft* = |N| f*(U_m, U_p; N/|N|) seen from the minus side and -ft* from the
+// plus side.
 template <class T>
-static void surface_pass_curved(const Ctx& c, const T* U, std::vector<T>& fstar) {
-  fstar.assign(size_t(c.nelem) * 3 * 5 * c.nf, T(0.0));
+static void surface_pass_curved(const Ctx& c, const T* U, std::vector<T>& fface) {
+  fface.assign(size_t(c.nelem) * 6 * 5 * c.nf, T(0.0));
 #pragma omp parallel for schedule(static)
   for (int e = 0; e < c.nelem; ++e)
-    for (int i = 0; i < 3; ++i) {
-      const int nb = c.nbr[6 * e + 2 * i + 1];
+    for (int f = 0; f < 6; ++f)
       for (int a = 0; a < c.nf; ++a) {
-        double Jf[3], nv[3];
-        face_metric(c, e, i, a, Jf);
-        const double sh = std::sqrt(Jf[0] * Jf[0] + Jf[1] * Jf[1] + Jf[2] * Jf[2]);
-        for (int m = 0; m < 3; ++m) nv[m] = Jf[m] / sh;
-        T L[5], R[5], f[5];
-        load_state(c, U, e, face_node(c, i, c.N, a), L);
-        load_state(c, U, nb, face_node(c, i, 0, a), R);
-        surface_flux_n(c.s.surf_flux, c.s.vol_flux, c.s.gamma, nv, L, R, f);
-        for (int v = 0; v < 5; ++v) fstar[((size_t(e) * 3 + i) * 5 + v) * c.nf + a] = sh * f[v];
+        const FaceSides fs = face_sides(c, e, f, a);
+        double Nv[3], Jo[3], nv[3];
+        face_vectors(c, fs, Nv, Jo);
+        const double sh = std::sqrt(Nv[0] * Nv[0] + Nv[1] * Nv[1] + Nv[2] * Nv[2]);
+        for (int m = 0; m < 3; ++m) nv[m] = Nv[m] / sh;
+        T Uo[5], Ub[5], fl[5];
+        load_state(c, U, e, fs.n, Uo);
+        load_state(c, U, fs.nb, fs.nbn, Ub);
+        if (fs.own_minus) surface_flux_n(c.s.surf_flux, c.s.vol_flux, c.s.gamma, nv, Uo, Ub, fl);
+        else surface_flux_n(c.s.surf_flux, c.s.vol_flux, c.s.gamma, nv, Ub, Uo, fl);
+        const double sgn = ((f & 1) ? 1.0 : -1.0) * (fs.own_minus ? 1.0 : -1.0);
+        for (int v = 0; v < 5; ++v) fface[((size_t(e) * 6 + f) * 5 + v) * c.nf + a] = (sgn * sh) * fl[v];
       }
-    }
 }
 
 template <class T>
-static void advective_dg_curved(const Ctx& c, const T* U, const std::vector<T>& fstar, T* Ut) {
+static void advective_dg_curved(const Ctx& c, const T* U, const std::vector<T>& fface, T* Ut) {
   const Basis& b = c.b;
 #pragma omp parallel for schedule(static)
   for (int e = 0; e < c.nelem; ++e)
@@ -819,11 +887,9 @@ static void advective_dg_curved(const Ctx& c, const T* U, const std::vector<T>& 
         }
         const int a = face_index(c, ijk, i);
         if (ii == c.N)
-          for (int v = 0; v < 5; ++v) sum[v] += (1.0 / b.w[c.N]) * fstar[((size_t(e) * 3 + i) * 5 + v) * c.nf + a];
-        if (ii == 0) {
-          const int em = c.nbr[6 * e + 2 * i];
-          for (int v = 0; v < 5; ++v) sum[v] -= (1.0 / b.w[0]) * fstar[((size_t(em) * 3 + i) * 5 + v) * c.nf + a];
-        }
+          for (int v = 0; v < 5; ++v) sum[v] += (1.0 / b.w[c.N]) * fface[((size_t(e) * 6 + 2 * i + 1) * 5 + v) * c.nf + a];
+        if (ii == 0)
+          for (int v = 0; v < 5; ++v) sum[v] -= (1.0 / b.w[0]) * fface[((size_t(e) * 6 + 2 * i) * 5 + v) * c.nf + a];
         for (int v = 0; v < 5; ++v) acc[v] -= sum[v];
       }
       for (int v = 0; v < 5; ++v) Ut[(size_t(e) * 5 + v) * c.nn + n] = acc[v] / c.jac(e, n);
@@ -834,7 +900,7 @@ static void advective_dg_curved(const Ctx& c, const T* U, const std::vector<T>& 
 //   grad q = (1/J) sum_i Ja^i [ sum_l D_{i_i l} q_l
 //              + (1/w_{i_i}) (delta_{i_i N} (q*_+ - q) - delta_{i_i 0} (q*_- - q)) ],
 // with the node's own metric (a uniform q has zero gradient whatever the
-// metric); q* the arithmetic mean as on Cartesian meshes.
+// metric); q* the arithmetic mean of both sides as on Cartesian meshes.
 template <class T>
 static void br1_gradient_curved(const Ctx& c, const T* U, std::vector<T>& grad) {
   const Basis& b = c.b;
@@ -848,17 +914,16 @@ static void br1_gradient_curved(const Ctx& c, const T* U, std::vector<T>& grad) 
       lifted(u, g, qq);
       for (int k = 0; k < 4; ++k) q[(size_t(e) * 4 + k) * c.nn + n] = qq[k];
     }
-  std::vector<T> qs(size_t(c.nelem) * 3 * 4 * c.nf);
+  std::vector<T> qs(size_t(c.nelem) * 6 * 4 * c.nf);  // [e][f][k][a]
 #pragma omp parallel for schedule(static)
   for (int e = 0; e < c.nelem; ++e)
-    for (int d = 0; d < 3; ++d) {
-      const int nb = c.nbr[6 * e + 2 * d + 1];
-      for (int k = 0; k < 4; ++k)
-        for (int a = 0; a < c.nf; ++a)
-          qs[((size_t(e) * 3 + d) * 4 + k) * c.nf + a] =
-              0.5 * (q[(size_t(e) * 4 + k) * c.nn + face_node(c, d, c.N, a)] +
-                     q[(size_t(nb) * 4 + k) * c.nn + face_node(c, d, 0, a)]);
-    }
+    for (int f = 0; f < 6; ++f)
+      for (int a = 0; a < c.nf; ++a) {
+        const FaceSides fs = face_sides(c, e, f, a);
+        for (int k = 0; k < 4; ++k)
+          qs[((size_t(e) * 6 + f) * 4 + k) * c.nf + a] =
+              0.5 * (q[(size_t(e) * 4 + k) * c.nn + fs.n] + q[(size_t(fs.nb) * 4 + k) * c.nn + fs.nbn]);
+      }
   grad.assign(size_t(c.nelem) * 3 * 4 * c.nn, T(0.0));
 #pragma omp parallel for schedule(static)
   for (int e = 0; e < c.nelem; ++e)
@@ -873,11 +938,8 @@ static void br1_gradient_curved(const Ctx& c, const T* U, std::vector<T>& grad) 
           const T* qe = &q[(size_t(e) * 4 + k) * c.nn];
           T acc = T(0.0);
           for (int l = 0; l <= c.N; ++l) acc += b.D[ii * c.n1 + l] * qe[node_along(c, ijk, i, l)];
-          if (ii == c.N) acc += (1.0 / b.w[c.N]) * (qs[((size_t(e) * 3 + i) * 4 + k) * c.nf + a] - qe[n]);
-          if (ii == 0) {
-            const int em = c.nbr[6 * e + 2 * i];
-            acc -= (1.0 / b.w[0]) * (qs[((size_t(em) * 3 + i) * 4 + k) * c.nf + a] - qe[n]);
-          }
+          if (ii == c.N) acc += (1.0 / b.w[c.N]) * (qs[((size_t(e) * 6 + 2 * i + 1) * 4 + k) * c.nf + a] - qe[n]);
+          if (ii == 0) acc -= (1.0 / b.w[0]) * (qs[((size_t(e) * 6 + 2 * i) * 4 + k) * c.nf + a] - qe[n]);
           s[i][k] = acc;
         }
       }
@@ -895,7 +957,8 @@ static void br1_gradient_curved(const Ctx& c, const T* U, std::vector<T>& grad) 
 //   U_t += (1/J) sum_i [ sum_l D_{i_i l} Gt_{i,l}
 //            + (1/w_{i_i}) (delta_{i_i N}(Gt*_{i,+} - Gt_{i,N}) - delta_{i_i 0}(Gt*_{i,-} - Gt_{i,0})) ],
 // Gt_i = sum_m Ja^i_m Fv_m the contravariant viscous flux at the node, and at
-// a face node Gt* = Ja_f . (Fv(-) + Fv(+))/2 with the face metric Ja_f.
+// a face node Gt* = Jf . (Fv(own) + Fv(neighbour))/2 with the face metric Jf
+// along the face's reference direction (from the face normal as above).
 template <class T>
 static void viscous_dg_curved(const Ctx& c, const T* U, T* Ut) {
   const Basis& b = c.b;
@@ -926,24 +989,22 @@ static void viscous_dg_curved(const Ctx& c, const T* U, T* Ut) {
           for (int m = 0; m < 3; ++m) s += c.ja(e, i, m, n) * Fv[((size_t(e) * 3 + m) * 5 + v) * c.nn + n];
           Gt[((size_t(e) * 3 + i) * 5 + v) * c.nn + n] = s;
         }
-  std::vector<T> Fs(size_t(c.nelem) * 3 * 5 * c.nf);
+  std::vector<T> Fs(size_t(c.nelem) * 6 * 5 * c.nf);  // [e][f][v][a]
 #pragma omp parallel for schedule(static)
   for (int e = 0; e < c.nelem; ++e)
-    for (int i = 0; i < 3; ++i) {
-      const int nb = c.nbr[6 * e + 2 * i + 1];
+    for (int f = 0; f < 6; ++f)
       for (int a = 0; a < c.nf; ++a) {
-        double Jf[3];
-        face_metric(c, e, i, a, Jf);
-        const int nm = face_node(c, i, c.N, a), np = face_node(c, i, 0, a);
+        const FaceSides fs = face_sides(c, e, f, a);
+        double Nv[3], Jo[3];
+        face_vectors(c, fs, Nv, Jo);
         for (int v = 0; v < 5; ++v) {
-          T s = T(0.0);
+          T sum = T(0.0);
           for (int m = 0; m < 3; ++m)
-            s += Jf[m] * (0.5 * (Fv[((size_t(e) * 3 + m) * 5 + v) * c.nn + nm] +
-                                 Fv[((size_t(nb) * 3 + m) * 5 + v) * c.nn + np]));
-          Fs[((size_t(e) * 3 + i) * 5 + v) * c.nf + a] = s;
+            sum += Jo[m] * (0.5 * (Fv[((size_t(e) * 3 + m) * 5 + v) * c.nn + fs.n] +
+                                   Fv[((size_t(fs.nb) * 3 + m) * 5 + v) * c.nn + fs.nbn]));
+          Fs[((size_t(e) * 6 + f) * 5 + v) * c.nf + a] = sum;
         }
       }
-    }
 #pragma omp parallel for schedule(static)
   for (int e = 0; e < c.nelem; ++e)
     for (int n = 0; n < c.nn; ++n) {
@@ -957,11 +1018,8 @@ static void viscous_dg_curved(const Ctx& c, const T* U, T* Ut) {
           const T* G = &Gt[((size_t(e) * 3 + i) * 5 + v) * c.nn];
           T s = T(0.0);
           for (int l = 0; l <= c.N; ++l) s += b.D[ii * c.n1 + l] * G[node_along(c, ijk, i, l)];
-          if (ii == c.N) s += (1.0 / b.w[c.N]) * (Fs[((size_t(e) * 3 + i) * 5 + v) * c.nf + a] - G[n]);
-          if (ii == 0) {
-            const int em = c.nbr[6 * e + 2 * i];
-            s -= (1.0 / b.w[0]) * (Fs[((size_t(em) * 3 + i) * 5 + v) * c.nf + a] - G[n]);
-          }
+          if (ii == c.N) s += (1.0 / b.w[c.N]) * (Fs[((size_t(e) * 6 + 2 * i + 1) * 5 + v) * c.nf + a] - G[n]);
+          if (ii == 0) s -= (1.0 / b.w[0]) * (Fs[((size_t(e) * 6 + 2 * i) * 5 + v) * c.nf + a] - G[n]);
           tot[v] += s;
         }
       }
@@ -1527,6 +1585,27 @@ static bool valid(const Setup* s) {
   // curved meshes: split-form DG (Euler, Navier-Stokes) without blending or
   // the eddy viscosity
   if (s->xnodes && (s->blending || s->Cs > 0.0 || s->cs_elem)) return false;
+  if (s->conn && !s->xnodes) return false;
+  if (s->conn) {  // every face pair must point back at itself with the inverse orientation
+    const int ne = s->nx * s->ny * s->nz, n1 = s->N + 1;
+    for (int e = 0; e < ne; ++e)
+      for (int f = 0; f < 6; ++f) {
+        const int32_t* q = s->conn + (size_t(e) * 6 + f) * 3;
+        if (q[0] < 0 || q[0] >= ne || q[1] < 0 || q[1] > 5 || q[2] < 0 || q[2] > 7) return false;
+        const int32_t* r = s->conn + (size_t(q[0]) * 6 + q[1]) * 3;
+        if (r[0] != e || r[1] != f) return false;
+        for (int a = 0; a < n1 * n1; ++a) {  // orientation r undoes q
+          auto map = [&](int o, int x) {
+            const int t1 = x % n1, t2 = x / n1;
+            int u = (o & 1) ? t2 : t1, v = (o & 1) ? t1 : t2;
+            if (o & 2) u = s->N - u;
+            if (o & 4) v = s->N - v;
+            return u + n1 * v;
+          };
+          if (map(r[2], map(q[2], a)) != a) return false;
+        }
+      }
+  }
   return true;
 }
 

@@ -47,7 +47,7 @@ class _Setup(ctypes.Structure):
                 ("gamma", ctypes.c_double), ("mu", ctypes.c_double), ("Pr", ctypes.c_double),
                 ("alpha_min", ctypes.c_double), ("alpha_max", ctypes.c_double),
                 ("alpha_spread", ctypes.c_double), ("Cs", ctypes.c_double), ("Prt", ctypes.c_double),
-                ("cs_elem", ctypes.c_void_p), ("xnodes", ctypes.c_void_p)]
+                ("cs_elem", ctypes.c_void_p), ("xnodes", ctypes.c_void_p), ("conn", ctypes.c_void_p)]
 
 
 @dataclass
@@ -72,9 +72,11 @@ class Setup:
     Prt: float = 0.9         # turbulent Prandtl number
     cs_elem: object = None   # optional per-element coefficients (numpy, n_elems)
     xnodes: object = None    # curved mesh: node coordinates (n_elems, 3, N+1, N+1, N+1), x index fastest
+    conn: object = None      # curved mesh, general connectivity: int32 (n_elems, 6, 3) (neighbour, face, orientation)
     _c: object = field(default=None, repr=False, compare=False)
     _keep: object = field(default=None, repr=False, compare=False)
     _keepx: object = field(default=None, repr=False, compare=False)
+    _keepc: object = field(default=None, repr=False, compare=False)
 
     @property
     def n1(self) -> int:
@@ -114,6 +116,12 @@ class Setup:
             s.xnodes = self._keepx.ctypes.data
         else:
             s.xnodes = None
+        if self.conn is not None:
+            self._keepc = np.ascontiguousarray(self.conn, dtype=np.int32)
+            assert self._keepc.shape == (self.n_elems, 6, 3), self._keepc.shape
+            s.conn = self._keepc.ctypes.data
+        else:
+            s.conn = None
         return s
 
 

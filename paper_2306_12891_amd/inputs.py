@@ -185,3 +185,131 @@ def random_smooth(N: int, nelem=(3, 2, 2), lo=(0.0, 0.0, 0.0), hi=(TWO_PI,) * 3,
 def random_directions(shape, k: int, base_seed: int = 1000) -> np.ndarray:
     """Direction k of an i.i.d. N(0, 1) family, seed base_seed + k."""
     return np.random.default_rng(base_seed + k).standard_normal(shape)
+
+
+def structured_neighbors(nelem) -> np.ndarray:
+    """Face neighbours (-x, +x, -y, +y, -z, +z) of the periodic structured mesh."""
+    nx, ny, nz = nelem
+    e = np.arange(nx * ny * nz)
+    ex, ey, ez = e % nx, (e // nx) % ny, e // (nx * ny)
+    idx = lambda x, y, z: (x % nx) + nx * ((y % ny) + ny * (z % nz))
+    return np.stack([idx(ex - 1, ey, ez), idx(ex + 1, ey, ez), idx(ex, ey - 1, ez), idx(ex, ey + 1, ez),
+                     idx(ex, ey, ez - 1), idx(ex, ey, ez + 1)], axis=1)
+
+
+def cube_rotations():
+    """The 24 rotations of the reference cube: signed permutation matrices P
+    with det P = +1 (new reference coordinates xi' = P xi)."""
+    import itertools
+    out = []
+    for perm in itertools.permutations(range(3)):
+        for signs in itertools.product((1, -1), repeat=3):
+            P = np.zeros((3, 3), dtype=int)
+            for a in range(3):
+                P[a, perm[a]] = signs[a]
+            if round(np.linalg.det(P)) == 1:
+                out.append(P)
+    return out
+
+
+def _face_local(N, d, i, j, k):
+    n1 = N + 1
+    return (j + n1 * k) if d == 0 else ((i + n1 * k) if d == 1 else (i + n1 * j))
+
+
+def _face_node_ijk(N, d, l, a):
+    n1 = N + 1
+    t1, t2 = a % n1, a // n1
+    return (l, t1, t2) if d == 0 else ((t1, l, t2) if d == 1 else (t1, t2, l))
+
+
+def _orient(N, o, a):
+    n1 = N + 1
+    t1, t2 = a % n1, a // n1
+    u, v = (t2, t1) if o & 1 else (t1, t2)
+    if o & 2:
+        u = N - u
+    if o & 4:
+        v = N - v
+    return u + n1 * v
+
+
+def rotated_elements(N: int, nelem, seed: int = 0):
+    """Unstructured-mesh test case from the periodic structured mesh: the
+    reference axes of every element are relabelled by a seeded cube rotation.
+
+    Returns (perm, conn): perm[e][n'] is the node of the structured labelling
+    that is node n' after the relabelling (apply as X_new[e][..., n'] =
+    X_old[e][..., perm[e][n']] on flattened nodes), and conn[e][f] = (neighbour,
+    neighbour's local face, orientation) in the new labelling, orientation o:
+    bit 0 swaps the face-local indices (t1, t2), bit 1 reverses the first and
+    bit 2 the second of the result (t1 along the lower remaining axis).
+    """
+    n1 = N + 1
+    nn = n1 ** 3
+    ne = int(np.prod(nelem))
+    rots = cube_rotations()
+    rng = np.random.default_rng(seed)
+    P = [rots[k] for k in rng.integers(0, len(rots), size=ne)]
+    perm = np.zeros((ne, nn), dtype=np.int64)
+    new_of_old = np.zeros((ne, nn), dtype=np.int64)
+    old_face = np.zeros((ne, 6), dtype=np.int64)  # new face -> old face
+    for e in range(ne):
+        Pe = P[e]
+        src = [int(np.nonzero(Pe[a])[0][0]) for a in range(3)]  # new axis a <- old axis src[a]
+        sg = [int(Pe[a, src[a]]) for a in range(3)]
+        for np_ in range(nn):
+            inew = (np_ % n1, (np_ // n1) % n1, np_ // (n1 * n1))
+            iold = [0, 0, 0]
+            for a in range(3):
+                iold[src[a]] = inew[a] if sg[a] > 0 else N - inew[a]
+            o = iold[0] + n1 * (iold[1] + n1 * iold[2])
+            perm[e, np_] = o
+            new_of_old[e, o] = np_
+        for a in range(3):
+            for side in range(2):
+                old_side = side if sg[a] > 0 else 1 - side
+                old_face[e, 2 * a + side] = 2 * src[a] + old_side
+    nbr = structured_neighbors(nelem)
+    conn = np.zeros((ne, 6, 3), dtype=np.int32)
+    for e in range(ne):
+        for f in range(6):
+            fo = int(old_face[e, f])
+            nb = int(nbr[e, fo])
+            fo_nb = fo ^ 1
+            fnew_nb = int(np.nonzero(old_face[nb] == fo_nb)[0][0])
+            # face-local indices: own new face -> old node -> matching node of nb -> nb's new face index
+            d, dn = f >> 1, fnew_nb >> 1
+            lo_, ln_ = (N if f & 1 else 0), (N if fnew_nb & 1 else 0)
+            target = []
+            for a in range(n1 * n1):
+                i, j, k = _face_node_ijk(N, d, lo_, a)
+                old = perm[e, i + n1 * (j + n1 * k)]
+                oi = [old % n1, (old // n1) % n1, old // (n1 * n1)]
+                ax = fo >> 1
+                oi[ax] = N - oi[ax]  # the matching node of the structured neighbour across that face
+                nbnew = new_of_old[nb, oi[0] + n1 * (oi[1] + n1 * oi[2])]
+                ii, jj, kk = nbnew % n1, (nbnew // n1) % n1, nbnew // (n1 * n1)
+                assert (ii, jj, kk)[dn] == ln_
+                target.append(_face_local(N, dn, ii, jj, kk))
+            o = [o for o in range(8) if all(_orient(N, o, a) == target[a] for a in range(n1 * n1))]
+            assert len(o) >= 1
+            conn[e, f] = (nb, fnew_nb, o[0])
+    return perm, conn
+
+
+def relabel(arr, perm) -> np.ndarray:
+    """Apply rotated_elements' node relabelling to nodal data (nElems, ..., N+1, N+1, N+1)."""
+    ne = arr.shape[0]
+    flat = arr.reshape(ne, -1, perm.shape[1])
+    out = np.take_along_axis(flat, perm[:, None, :], axis=2)
+    return np.ascontiguousarray(out.reshape(arr.shape))
+
+
+def unlabel(arr, perm) -> np.ndarray:
+    """Inverse of relabel."""
+    ne = arr.shape[0]
+    flat = arr.reshape(ne, -1, perm.shape[1])
+    out = np.empty_like(flat)
+    np.put_along_axis(out, np.broadcast_to(perm[:, None, :], flat.shape), flat, axis=2)
+    return np.ascontiguousarray(out.reshape(arr.shape))

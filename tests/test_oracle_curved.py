@@ -290,3 +290,57 @@ def test_surface_flux_rotational_invariance(orc):
             g = orc.surface_flux(s, 0, rot(L), rot(R))
             back = np.array([g[0], *(Q.T @ g[1:4]), g[4]])
             assert np.max(np.abs(f - back)) <= 1e-14 * np.max(np.abs(f)), (vf, sf)
+
+
+# ---------------------------------------------------------------------------
+# General connectivity (unstructured hexahedra): the warped periodic mesh with
+# the reference axes of every element relabelled by a seeded cube rotation.
+# The discrete operator does not depend on the labelling, so U_t of the
+# relabelled mesh is the relabelled U_t of the structured one.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("eq,vf,sf", CASES)
+@pytest.mark.parametrize("N", [2, 3, 4])
+def test_rotated_elements_match_structured(orc, N, eq, vf, sf):
+    ne = (3, 2, 2)
+    xn = I.warped_coordinates(N, ne, amp=0.05)
+    perm, conn = I.rotated_elements(N, ne, seed=N)
+    U = I.random_smooth(N, ne, seed=40 + N, noise=0.02, xnodes=xn)
+    kw = dict(equations=eq, vol_flux=vf, surf_flux=sf, mu=2e-2)
+    a = orc.time_derivative(setup(orc, N, ne, xn, **kw), U)
+    s1 = orc.Setup(N=N, nelem=ne, xnodes=I.relabel(xn, perm), conn=conn, **kw)
+    b = orc.time_derivative(s1, I.relabel(U, perm))
+    assert np.max(np.abs(I.unlabel(b, perm) - a)) <= 1e-12 * np.max(np.abs(a))
+
+
+def test_rotated_mesh_uses_every_orientation():
+    _, conn = I.rotated_elements(3, (3, 2, 2), seed=3)
+    assert set(conn[:, :, 2].ravel().tolist()) == set(range(8))
+
+
+@pytest.mark.parametrize("eq", [0, 1])
+def test_rotated_mesh_freestream_and_conservation(orc, eq):
+    N, ne = 4, (3, 2, 2)
+    xn = I.warped_coordinates(N, ne, amp=0.06)
+    perm, conn = I.rotated_elements(N, ne, seed=9)
+    s = orc.Setup(N=N, nelem=ne, xnodes=I.relabel(xn, perm), conn=conn, equations=eq, vol_flux=1, surf_flux=1,
+                  mu=1e-2)
+    U = I.freestream(N, ne, u=(0.4, -0.3, 0.2))
+    scale = np.max(np.abs(U)) * (2.0 / (TWO_PI / 3)) * N * (N + 1) / 2
+    assert np.max(np.abs(orc.time_derivative(s, U))) <= 1e-12 * scale
+    Ur = I.relabel(I.random_smooth(N, ne, seed=19, noise=0.02, xnodes=xn), perm)
+    Ut = orc.time_derivative(s, Ur)
+    tot, mag = orc.integrals(s, Ut), orc.integrals(s, np.abs(Ut))
+    assert np.all(np.abs(tot) < 1e-13 * mag), (tot, mag)
+
+
+def test_inconsistent_connectivity_rejected(orc):
+    N, ne = 2, (2, 2, 2)
+    xn = I.warped_coordinates(N, ne)
+    perm, conn = I.rotated_elements(N, ne, seed=1)
+    bad = conn.copy()
+    bad[0, 1, 2] = (bad[0, 1, 2] + 1) % 8  # orientation no longer undone by the neighbour's
+    with pytest.raises(ValueError):
+        orc.time_derivative(orc.Setup(N=N, nelem=ne, xnodes=I.relabel(xn, perm), conn=bad),
+                            I.freestream(N, ne))
+    with pytest.raises(ValueError):  # general connectivity needs the node coordinates
+        orc.time_derivative(orc.Setup(N=N, nelem=ne, conn=conn), I.freestream(N, ne))
