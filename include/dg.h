@@ -156,6 +156,24 @@ int dg_set_cs_field(dg_ctx* ctx, const double* cs);
  * on a curved mesh. */
 int dg_set_geometry(dg_ctx* ctx, const double* X);
 
+/* General connectivity of a curved mesh (unstructured hexahedra, as the
+ * paper's meshes in Secs. 3-5 are).  conn: host pointer to nElems x 6 x 3
+ * int32, for element e and local face f (0:-xi 1:+xi 2:-eta 3:+eta 4:-zeta
+ * 5:+zeta): the neighbour element, its local face that is shared, and the
+ * orientation o in 0..7 mapping the face-local node index a = t1 + (N+1) t2
+ * (t1 along the lower of the face's two reference axes) to the neighbour's:
+ * bit 0 swaps (t1, t2), then bit 1 reverses the first and bit 2 the second
+ * index.  Copied.  Every face is evaluated from a minus to a plus side (the
+ * + face of a (+,-) pair, else the smaller (element, face)), so both
+ * elements use the same interface values.  The node coordinates of
+ * dg_set_geometry must follow the same element-local labelling; the operator
+ * returns DG_ESTATE while general connectivity is set without curved
+ * geometry.  NULL restores the structured periodic mesh of dg_init.
+ * Errors: DG_EINVAL for an out-of-range entry, a face that is not named back
+ * by its neighbour, or orientations of a face pair that are not inverse to
+ * each other (nothing is changed then); DG_ENOMEM. */
+int dg_set_connectivity(dg_ctx* ctx, const int32_t* conn);
+
 /* Sets the HIP stream (hipStream_t) all later calls enqueue on; NULL = null
  * stream. */
 int dg_set_stream(dg_ctx* ctx, void* hip_stream);

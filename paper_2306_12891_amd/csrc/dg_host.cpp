@@ -178,6 +178,7 @@ struct dg_ctx {
   int has_cs_field = 0;
   double* M = nullptr;         // curved mesh metrics [nelem][10][nn] (dg_set_geometry), NULL: box
   int* d_bad = nullptr;        // count of invalid Jacobians (dg_set_geometry)
+  int32_t* conn = nullptr;     // general connectivity [nelem][6][3] (dg_set_connectivity), NULL: structured
   double* partial = nullptr;
   double* h_partial = nullptr;
   // reverse mode (allocated on first use): stage states Y_0..Y_4, the
@@ -236,6 +237,7 @@ void release(dg_ctx* c) {
   hipFree(c->cs_field);
   hipFree(c->M);
   hipFree(c->d_bad);
+  hipFree(c->conn);
   hipFree(c->partial);
   if (c->h_partial) hipHostFree(c->h_partial);
   for (double* y : c->Y) hipFree(y);
@@ -271,6 +273,7 @@ StageArgs stage_args(const dg_ctx* c) {
   a.recon = c->opt.fv_recon;
   a.cs_elem = c->has_cs_field ? c->cs_field : nullptr;
   a.M = c->M;
+  a.conn = c->conn;
   a.cs = c->opt.Cs;
   const double delta = std::cbrt(c->dx[0] * c->dx[1] * c->dx[2]) / (c->N + 1.0);
   a.delta2 = delta * delta;
@@ -349,6 +352,8 @@ int run_stage(dg_ctx* c, const double* Xin, double* Xout, double* Ut, int mode, 
     if (e != hipSuccess) return hip_fail(c, e, "indicator kernel");
   }
   const int eq = eq_code(c);
+  if (c->conn && !c->M)
+    return fail(c, DG_ESTATE, "general connectivity needs curved elements: call dg_set_geometry first");
   if (c->M) {  // curved mesh (FP64, no blending or eddy viscosity: checked when set)
     if (eq >= 1) {
       e = timed(c, DG_K_LIFT, [&] { return c->kt->lift_curved(a, c->stream); });
@@ -462,6 +467,34 @@ int run_vjp(dg_ctx* c, const double* U, const double* lambda, double* U_bar, con
   e = timed(c, DG_K_VJP, [&] { return c->kt->vjp(v, c->opt.equations, c->stream); });
   if (e != hipSuccess) return hip_fail(c, e, "vjp kernel");
   return DG_OK;
+}
+
+// Structured periodic neighbour table of the context's mesh.
+std::vector<int32_t> structured_nbr(const dg_ctx* c) {
+  std::vector<int32_t> nbr((size_t)c->nelem * 6);
+  const int nx = c->ne[0], ny = c->ne[1], nz = c->ne[2];
+  for (int ez = 0; ez < nz; ++ez)
+    for (int ey = 0; ey < ny; ++ey)
+      for (int ex = 0; ex < nx; ++ex) {
+        const size_t e = ex + (size_t)nx * (ey + (size_t)ny * ez);
+        nbr[6 * e + 0] = ((ex + nx - 1) % nx) + nx * (ey + ny * ez);
+        nbr[6 * e + 1] = ((ex + 1) % nx) + nx * (ey + ny * ez);
+        nbr[6 * e + 2] = ex + nx * (((ey + ny - 1) % ny) + ny * ez);
+        nbr[6 * e + 3] = ex + nx * (((ey + 1) % ny) + ny * ez);
+        nbr[6 * e + 4] = ex + nx * (ey + ny * ((ez + nz - 1) % nz));
+        nbr[6 * e + 5] = ex + nx * (ey + ny * ((ez + 1) % nz));
+      }
+  return nbr;
+}
+
+// Face-local index a mapped by orientation code o (bit 0 swap, bit 1 reverse
+// the first, bit 2 the second index).
+int orient_face_index(int N, int o, int a) {
+  const int n1 = N + 1, t1 = a % n1, t2 = a / n1;
+  int u = (o & 1) ? t2 : t1, v = (o & 1) ? t1 : t2;
+  if (o & 2) u = N - u;
+  if (o & 4) v = N - v;
+  return u + n1 * v;
 }
 
 }  // namespace
@@ -595,6 +628,47 @@ int dg_set_options(dg_ctx* c, const dg_options* o) {
     if (rc) return rc;
   }
   c->opt = *o;
+  return DG_OK;
+}
+
+int dg_set_connectivity(dg_ctx* c, const int32_t* conn) {
+  if (check_ctx(c)) return DG_EINVAL;
+  std::vector<int32_t> nbr;
+  if (!conn) {
+    hipFree(c->conn);
+    c->conn = nullptr;
+    nbr = structured_nbr(c);
+  } else {
+    // every face must name an existing neighbour face that names it back,
+    // with the inverse orientation
+    const int ne = c->nelem;
+    for (int e = 0; e < ne; ++e)
+      for (int f = 0; f < 6; ++f) {
+        const int32_t* q = conn + ((size_t)e * 6 + f) * 3;
+        if (q[0] < 0 || q[0] >= ne || q[1] < 0 || q[1] > 5 || q[2] < 0 || q[2] > 7)
+          return fail(c, DG_EINVAL, "dg_set_connectivity: element %d face %d out of range", e, f);
+        const int32_t* r = conn + ((size_t)q[0] * 6 + q[1]) * 3;
+        if (r[0] != e || r[1] != f)
+          return fail(c, DG_EINVAL, "dg_set_connectivity: element %d face %d is not named back", e, f);
+        for (int a = 0; a < c->nf; ++a)
+          if (orient_face_index(c->N, r[2], orient_face_index(c->N, q[2], a)) != a)
+            return fail(c, DG_EINVAL, "dg_set_connectivity: orientations of element %d face %d do not match", e,
+                        f);
+      }
+    nbr.resize((size_t)ne * 6);
+    for (size_t k = 0; k < nbr.size(); ++k) nbr[k] = conn[3 * k];
+    hipError_t e = hipSuccess;
+    if (!c->conn) e = hipMalloc((void**)&c->conn, (size_t)ne * 18 * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMemcpy(c->conn, conn, (size_t)ne * 18 * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(c, (e == hipErrorOutOfMemory) ? DG_ENOMEM : DG_EHIP, "dg_set_connectivity: %s",
+                  hipGetErrorString(e));
+    }
+  }
+  // the neighbour table (indicator spread, structured kernels) follows the connectivity
+  const hipError_t e = hipMemcpy(c->nbr, nbr.data(), nbr.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(c, e, "dg_set_connectivity");
   return DG_OK;
 }
 

@@ -50,6 +50,9 @@ struct StageArgs {
   // curved mesh: M[e][10][nn], Ja^i_m at slot 3 i + m, 1/J at slot 9 (NULL:
   // the Cartesian box)
   const double* M;
+  // curved mesh with general connectivity: conn[e][f] = (neighbour, its local
+  // face, orientation 0..7), validated on the host; NULL: structured (nbr)
+  const int32_t* conn;
 };
 
 struct ReduceArgs {

@@ -2485,34 +2485,96 @@ __device__ __forceinline__ void surface_flux_normal(int sf, const double L[5], c
   f[4] = g[4];
 }
 
-// Geometry and loads of a curved face item: both conservative states in
-// Cartesian components, the metric row Ja^d of both elements at the face
-// node, and (Navier-Stokes) the neighbour's projected viscous flux.
+// Face item q of element e on a curved mesh: own face f (normal reference
+// direction d), face index a and volume node; the neighbour, its local face
+// fb, face index ab (the orientation code maps a to ab: bit 0 swaps the two
+// face-local indices, bit 1 reverses the first, bit 2 the second) and volume
+// node.  Every face is evaluated from its minus to its plus side: the side
+// whose face is a + face when the other's is a - face (on a structured mesh
+// the element whose + face it is), else the smaller (element, face).
+struct CFaceItem {
+  int f, a, d, side, nown, nb, fb, ab, nnb;
+  bool own_minus;
+};
+
+__device__ __forceinline__ int face_vol_node(int f, int a) {
+  const int d = f >> 1;
+  const int t1 = a % n1, t2 = a / n1;
+  const int sn = d == 0 ? 1 : (d == 1 ? n1 : nf);
+  const int s1 = d == 0 ? n1 : 1;
+  const int s2 = d == 2 ? n1 : nf;
+  return ((f & 1) ? N : 0) * sn + t1 * s1 + t2 * s2;
+}
+
+__device__ __forceinline__ CFaceItem curved_face_item(const StageArgs& A, int e, int q) {
+  CFaceItem it;
+  it.f = q / nf;
+  it.a = q - it.f * nf;
+  it.d = it.f >> 1;
+  it.side = it.f & 1;
+  it.nown = face_vol_node(it.f, it.a);
+  int o = 0;
+  if (A.conn) {
+    const int32_t* c = A.conn + ((size_t)e * 6 + it.f) * 3;
+    it.nb = c[0];
+    it.fb = c[1];
+    o = c[2];
+  } else {
+    it.nb = A.nbr[6 * e + it.f];
+    it.fb = it.f ^ 1;
+  }
+  const int t1 = it.a % n1, t2 = it.a / n1;
+  int u = (o & 1) ? t2 : t1, v = (o & 1) ? t1 : t2;
+  if (o & 2) u = N - u;
+  if (o & 4) v = N - v;
+  it.ab = u + n1 * v;
+  it.nnb = face_vol_node(it.fb, it.ab);
+  const bool pb = it.fb & 1;
+  it.own_minus = (it.side && !pb) || ((it.side != 0) == pb && (e < it.nb || (e == it.nb && it.f < it.fb)));
+  return it;
+}
+
+// Loads of a curved face item: both conservative states in Cartesian
+// components (L the minus, R the plus side), the metric row of each side's
+// face direction at its node, signed by its face side (s Ja, s = +1 on +
+// faces), and (Navier-Stokes) the neighbour's projected viscous flux.
 struct CurvedFace {
-  FaceItem it;
+  CFaceItem it;
   double L[5], R[5], jm[3], jp[3], fn[4];
 };
 
 template <bool NS>
 __device__ __forceinline__ void curved_face_issue(const StageArgs& A, int e, CurvedFace& cf) {
-  const FaceItem& it = cf.it;
-  const int eL = it.side ? e : it.nb, eR = it.side ? it.nb : e;
-  const int nL = it.side ? it.nown : it.nnb, nR = it.side ? it.nnb : it.nown;
+  const CFaceItem& it = cf.it;
+  const int eL = it.own_minus ? e : it.nb, eR = it.own_minus ? it.nb : e;
+  const int nL = it.own_minus ? it.nown : it.nnb, nR = it.own_minus ? it.nnb : it.nown;
+  const int fL = it.own_minus ? it.f : it.fb, fR = it.own_minus ? it.fb : it.f;
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
     cf.L[v] = A.U[((size_t)eL * 5 + v) * nn + nL];
     cf.R[v] = A.U[((size_t)eR * 5 + v) * nn + nR];
   }
+  const double sL = (fL & 1) ? 1.0 : -1.0, sR = (fR & 1) ? 1.0 : -1.0;
 #pragma unroll
   for (int m = 0; m < 3; ++m) {
-    cf.jm[m] = A.M[((size_t)eL * MS + 3 * it.d + m) * nn + nL];
-    cf.jp[m] = A.M[((size_t)eR * MS + 3 * it.d + m) * nn + nR];
+    cf.jm[m] = sL * A.M[((size_t)eL * MS + 3 * (fL >> 1) + m) * nn + nL];
+    cf.jp[m] = sR * A.M[((size_t)eR * MS + 3 * (fR >> 1) + m) * nn + nR];
   }
   if (NS) {
-    const double* Fn = A.Fvf + ((size_t)it.nb * 6 + (it.f ^ 1)) * 4 * nf + it.a;
+    const double* Fn = A.Fvf + ((size_t)it.nb * 6 + it.fb) * 4 * nf + it.ab;
 #pragma unroll
     for (int c = 0; c < 4; ++c) cf.fn[c] = Fn[c * nf];
   }
+}
+
+// Face normal from the minus to the plus side, N = (s_m Ja_m - s_p Ja_p)/2
+// (both elements form it bitwise alike), and the sign that turns values
+// along N into values along the own face's reference direction +xi:
+// s_own (own_minus ? +1 : -1).
+__device__ __forceinline__ double curved_face_normal(const CurvedFace& cf, double Nv[3]) {
+#pragma unroll
+  for (int m = 0; m < 3; ++m) Nv[m] = 0.5 * (cf.jm[m] - cf.jp[m]);
+  return (cf.it.side ? 1.0 : -1.0) * (cf.it.own_minus ? 1.0 : -1.0);
 }
 
 // Face metric and lifted interface value q* = (q- + q+)/2, q = (u, v, w, theta).
@@ -2636,7 +2698,7 @@ __global__ __launch_bounds__(NT) void k_stage_curved(StageArgs A) {
   CurvedFace cf[FIC];
 #pragma unroll
   for (int k = 0; k < FIC; ++k)
-    if (t + k * NT < 6 * nf) cf[k].it = face_item_geometry(A.nbr, e, t + k * NT);
+    if (t + k * NT < 6 * nf) cf[k].it = curved_face_item(A, e, t + k * NT);
   const double* Ue = A.U + (size_t)e * 5 * nn;
   const double* Me = A.M + (size_t)e * MS * nn;
   double u[5], gprev[5], mt[MS];
@@ -2673,27 +2735,30 @@ __global__ __launch_bounds__(NT) void k_stage_curved(StageArgs A) {
   for (int k = 0; k < FIC; ++k)
     if (t + k * NT < 6 * nf) {
       const CurvedFace& c = cf[k];
-      const FaceItem& it = c.it;
-      double Jf[3];
-#pragma unroll
-      for (int m = 0; m < 3; ++m) Jf[m] = 0.5 * (c.jm[m] + c.jp[m]);
-      const double sh = sqrt64(Jf[0] * Jf[0] + Jf[1] * Jf[1] + Jf[2] * Jf[2]);
+      const CFaceItem& it = c.it;
+      double Nv[3];
+      const double so = curved_face_normal(c, Nv);
+      const double sh = sqrt64(Nv[0] * Nv[0] + Nv[1] * Nv[1] + Nv[2] * Nv[2]);
       const double ish = rcp64(sh);
-      const double nv[3] = {Jf[0] * ish, Jf[1] * ish, Jf[2] * ish};
+      const double nv[3] = {Nv[0] * ish, Nv[1] * ish, Nv[2] * ish};
       double f[5];
       surface_flux_normal<VF>(A.sf, c.L, c.R, nv, A.gamma, f);
+      const double sc = so * sh;  // flux along the own face's +xi
 #pragma unroll
-      for (int v = 0; v < 5; ++v) sF[it.f][v][it.a] = sh * f[v];
+      for (int v = 0; v < 5; ++v) sF[it.f][v][it.a] = sc * f[v];
       if (NS) {
         double q[4];
         curved_face_q(c, gm1, q);
+        // the neighbour projected its flux on its own face metric: along
+        // the own +xi that is -s_own s_nb times its value
+        const double sn = ((it.side != 0) == ((it.fb & 1) != 0)) ? -1.0 : 1.0;
 #pragma unroll
         for (int cc = 0; cc < 4; ++cc) {
           sQ[it.f][cc][it.a] = q[cc];
-          sFn[it.f][cc][it.a] = c.fn[cc];
+          sFn[it.f][cc][it.a] = sn * c.fn[cc];
         }
 #pragma unroll
-        for (int m = 0; m < 3; ++m) sJf[it.f][m][it.a] = Jf[m];
+        for (int m = 0; m < 3; ++m) sJf[it.f][m][it.a] = so * Nv[m];
       }
     }
   __syncthreads();
@@ -2832,7 +2897,7 @@ __global__ __launch_bounds__(NT) void k_lift_curved(StageArgs A) {
   CurvedFace cf[FIC];
 #pragma unroll
   for (int k = 0; k < FIC; ++k)
-    if (t + k * NT < 6 * nf) cf[k].it = face_item_geometry(A.nbr, e, t + k * NT);
+    if (t + k * NT < 6 * nf) cf[k].it = curved_face_item(A, e, t + k * NT);
   const double* Ue = A.U + (size_t)e * 5 * nn;
   double u[5];
   if (t < nn) {
@@ -2867,7 +2932,7 @@ __global__ __launch_bounds__(NT) void k_lift_curved(StageArgs A) {
 #pragma unroll
   for (int k = 0; k < FIC; ++k)
     if (t + k * NT < 6 * nf) {
-      const FaceItem& it = cf[k].it;
+      const CFaceItem& it = cf[k].it;
       const int n = it.nown;
       const int ijk[3] = {n % n1, (n / n1) % n1, n / nf};
       const double* Mn = A.M + (size_t)e * MS * nn + n;
@@ -2915,9 +2980,9 @@ __global__ __launch_bounds__(NT) void k_lift_curved(StageArgs A) {
       viscous_flux<0, double>(g, sq[0][n], sq[1][n], sq[2][n], A.mu, A.kappa, F[0]);
       viscous_flux<1, double>(g, sq[0][n], sq[1][n], sq[2][n], A.mu, A.kappa, F[1]);
       viscous_flux<2, double>(g, sq[0][n], sq[1][n], sq[2][n], A.mu, A.kappa, F[2]);
-      double Jf[3];
-#pragma unroll
-      for (int m = 0; m < 3; ++m) Jf[m] = 0.5 * (cf[k].jm[m] + cf[k].jp[m]);
+      double Nv[3];
+      const double so = curved_face_normal(cf[k], Nv);
+      const double Jf[3] = {so * Nv[0], so * Nv[1], so * Nv[2]};  // face metric along the own +xi
       double* out = A.Fvf + ((size_t)e * 6 + it.f) * 4 * nf + it.a;
 #pragma unroll
       for (int c = 0; c < 4; ++c) out[c * nf] = Jf[0] * F[0][c] + Jf[1] * F[1][c] + Jf[2] * F[2][c];

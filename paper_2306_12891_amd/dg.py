@@ -30,7 +30,8 @@ FP64, MIXED = 0, 1
 EXPORTS = ["dg_default_options", "dg_init", "dg_set_options", "dg_get_options", "dg_set_stream",
            "dg_time_derivative", "rk_step", "dg_rk_steps", "dg_vjp", "rk_step_vjp", "dg_max_dt",
            "dg_integrals", "dg_alpha", "dg_check_finite", "dg_set_profiling", "dg_profile_read", "dg_node_weights",
-           "dg_sizes", "dg_finalize", "dg_last_error", "dg_set_cs_field", "dg_set_geometry"]
+           "dg_sizes", "dg_finalize", "dg_last_error", "dg_set_cs_field", "dg_set_geometry",
+           "dg_set_connectivity"]
 
 
 class DGError(RuntimeError):
@@ -86,6 +87,7 @@ def lib() -> ctypes.CDLL:
             "dg_last_error": ([P], ctypes.c_char_p),
             "dg_set_cs_field": ([P, P], I),
             "dg_set_geometry": ([P, P], I),
+            "dg_set_connectivity": ([P, P], I),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -176,6 +178,19 @@ class DG:
             raise ValueError(f"X must be contiguous of shape {(self.n_elems, 3, n1, n1, n1)}")
         self._stream()
         self._check(lib().dg_set_geometry(self._ctx, ctypes.c_void_p(X.data_ptr())))
+
+    def set_connectivity(self, conn):
+        """General connectivity of a curved mesh: int32 array (n_elems, 6, 3) of
+        (neighbour, its local face, orientation) on the host (copied), or None
+        for the structured periodic mesh."""
+        import numpy as np
+        if conn is None:
+            self._check(lib().dg_set_connectivity(self._ctx, None))
+            return
+        c = np.ascontiguousarray(conn, dtype=np.int32)
+        if c.shape != (self.n_elems, 6, 3):
+            raise ValueError(f"conn must have shape {(self.n_elems, 6, 3)}")
+        self._check(lib().dg_set_connectivity(self._ctx, ctypes.c_void_p(c.ctypes.data)))
 
     def close(self):
         if getattr(self, "_ctx", None) is not None and self._ctx.value:

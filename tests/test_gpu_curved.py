@@ -186,3 +186,81 @@ def test_error_paths(orc, torch_cuda):
     with pytest.raises(dg.DGError) as ei:
         op2.set_geometry(torch.from_numpy(xn).cuda())
     assert ei.value.code == dg.DG_EUNSUPPORTED
+
+
+# ---------------------------------------------------------------------------
+# General connectivity (dg_set_connectivity): the warped periodic mesh with
+# every element's reference axes relabelled by a seeded cube rotation (all 8
+# face orientations occur).
+# ---------------------------------------------------------------------------
+def make_rotated(orc, torch, N, ne, seed, eq=0, vf=0, sf=0, mu=0.0, amp=0.05):
+    from paper_2306_12891_amd import dg
+    xn = I.warped_coordinates(N, ne, amp=amp)
+    perm, conn = I.rotated_elements(N, ne, seed=seed)
+    xr = I.relabel(xn, perm)
+    s = orc.Setup(N=N, nelem=ne, equations=eq, vol_flux=vf, surf_flux=sf, mu=mu, xnodes=xr, conn=conn)
+    op = dg.DG(ne, N, gamma=G, mu=mu, equations=eq, vol_flux=vf, surf_flux=sf)
+    op.set_connectivity(conn)
+    op.set_geometry(torch.from_numpy(xr).cuda())
+    return s, op, xn, perm
+
+
+@pytest.mark.parametrize("eq,vf,sf", [(0, 0, 0), (0, 1, 1), (1, 1, 1), (1, 3, 2), (1, 0, 0)])
+@pytest.mark.parametrize("N", [2, 3, 5])
+def test_rotated_elements(orc, torch_cuda, N, eq, vf, sf):
+    ne = (3, 2, 2)
+    s, op, xn, perm = make_rotated(orc, torch_cuda, N, ne, seed=N + 3, eq=eq, vf=vf, sf=sf, mu=2e-2)
+    U = I.relabel(I.random_smooth(N, ne, seed=110 + N, noise=0.02, xnodes=xn), perm)
+    assert_curved_close(orc, s, gpu_ut(torch_cuda, op, U), orc.time_derivative(s, U), U)
+
+
+def test_rotated_equals_structured_on_gpu(orc, torch_cuda):
+    """The relabelled mesh gives the relabelled U_t of the structured mesh."""
+    N, ne = 4, (2, 3, 2)
+    s, op, xn, perm = make_rotated(orc, torch_cuda, N, ne, seed=5, eq=1, vf=1, sf=1, mu=2e-2)
+    _, op0 = make(orc, torch_cuda, N, ne, xn, eq=1, vf=1, sf=1, mu=2e-2)
+    U = I.random_smooth(N, ne, seed=17, noise=0.02, xnodes=xn)
+    a = gpu_ut(torch_cuda, op0, U)
+    b = I.unlabel(gpu_ut(torch_cuda, op, I.relabel(U, perm)), perm)
+    assert_curved_close(orc, s, b, a, U)
+
+
+def test_rotated_rollout_and_conservation(orc, torch_cuda):
+    import torch
+    N, ne = 3, (3, 3, 2)
+    s, op, xn, perm = make_rotated(orc, torch_cuda, N, ne, seed=11, eq=1, vf=1, sf=1, mu=1.0 / 1600, amp=0.04)
+    U0 = I.relabel(I.random_smooth(N, ne, seed=23, xnodes=xn), perm)
+    Ud = torch.from_numpy(U0).cuda()
+    Utd = op.time_derivative(Ud)
+    tot, mag = np.array(op.integrals(Utd)), np.array(op.integrals(Utd.abs()))
+    assert np.all(np.abs(tot) <= 1e-13 * mag), (tot, mag)
+    dt = op.max_dt(Ud, 0.5)
+    op.rk_steps(Ud, dt, 4)
+    assert_state_close(Ud.cpu().numpy(), orc.rk_steps(s, U0, dt, 4))
+
+
+def test_connectivity_error_paths(orc, torch_cuda):
+    import torch
+
+    from paper_2306_12891_amd import dg
+    N, ne = 2, (2, 2, 2)
+    perm, conn = I.rotated_elements(N, ne, seed=2)
+    op = dg.DG(ne, N, gamma=G, equations=dg.EULER)
+    bad = conn.copy()
+    bad[3, 2, 2] = (bad[3, 2, 2] + 3) % 8
+    with pytest.raises(dg.DGError) as ei:
+        op.set_connectivity(bad)
+    assert ei.value.code == dg.DG_EINVAL
+    bad = conn.copy()
+    bad[1, 0, 0] = 99
+    with pytest.raises(dg.DGError) as ei:
+        op.set_connectivity(bad)
+    assert ei.value.code == dg.DG_EINVAL
+    U = torch.from_numpy(I.random_smooth(N, ne, seed=1)).cuda()
+    ref = op.time_derivative(U).cpu().numpy()  # rejected connectivity left the box unchanged
+    op.set_connectivity(conn)
+    with pytest.raises(dg.DGError) as ei:  # general connectivity without curved elements
+        op.time_derivative(U)
+    assert ei.value.code == dg.DG_ESTATE
+    op.set_connectivity(None)
+    assert np.array_equal(op.time_derivative(U).cpu().numpy(), ref)
