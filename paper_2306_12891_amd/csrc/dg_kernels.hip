@@ -2598,7 +2598,7 @@ __device__ __forceinline__ void curved_face_q(const CurvedFace& cf, double gm1, 
 // Adds -(sum) to acc; with GRAD also returns the off-diagonal line sums of
 // the BR1 gradient (Dhat/2 = D off the diagonal).
 template <int VF, int D, bool GRAD>
-__device__ __forceinline__ void volume_dir_curved(const double (*sP)[nnp], const double (*sM)[nnp],
+__device__ __forceinline__ void volume_dir_curved(const double (*sP)[nnp], const double (*sM)[nn],
                                                   const double* sDhat, int n, int id, const double me[7],
                                                   const double jo[3], double acc[5], double* gs) {
   constexpr int st = D == 0 ? 1 : (D == 1 ? n1 : nf);
@@ -2670,24 +2670,26 @@ __device__ __forceinline__ void volume_dir_curved(const double (*sP)[nnp], const
 }
 
 // Stage kernel on curved elements (one element per workgroup).  LDS:
-// primitives sP[7][nnp] and node metrics sM[9][nnp] (overlaid later by the
+// primitives sP[7][nnp] and node metrics sM[9][nn] (overlaid later by the
 // twelve contravariant viscous fluxes sV[12][nnp]), interface fluxes
-// sF[6][5][nf], and for Navier-Stokes q* sQ[6][4][nf], the neighbours'
-// projected viscous fluxes sFn[6][4][nf] and the face metrics sJf[6][3][nf].
+// sF[6][5][nf], and for Navier-Stokes q* sQ[6][4][nf], which the face metrics
+// sJf[6][3][nf] overlay once the gradient is formed, and the neighbours'
+// projected viscous fluxes sFn[6][4][nf].  At N = 5 this is 53 KB: three
+// workgroups per CU, with at most 168 registers (3 waves per SIMD).
 template <int VF, int EQ>
-__global__ __launch_bounds__(NT) void k_stage_curved(StageArgs A) {
+__global__ __launch_bounds__(NT, DG_N == 5 ? 3 : 1) void k_stage_curved(StageArgs A) {
   constexpr bool NS = EQ >= 1;
-  constexpr int oM = 7 * nnp, oF = 16 * nnp, oQ = oF + 30 * nf, oFn = oQ + 24 * nf, oJf = oFn + 24 * nf;
-  constexpr int POOL = NS ? oJf + 18 * nf : oQ;
+  constexpr int oM = 7 * nnp, oF = oM + 9 * nn, oQ = oF + 30 * nf, oFn = oQ + 24 * nf;
+  constexpr int POOL = NS ? oFn + 24 * nf : oQ;
   static_assert(12 * nnp <= oF, "viscous exchange overlays primitives and metrics only");
   __shared__ double sPool[POOL];
   __shared__ double sB[NB_STAGE];
   double (*sP)[nnp] = reinterpret_cast<double (*)[nnp]>(sPool);
-  double (*sM)[nnp] = reinterpret_cast<double (*)[nnp]>(sPool + oM);
+  double (*sM)[nn] = reinterpret_cast<double (*)[nn]>(sPool + oM);
   double (*sF)[5][nf] = reinterpret_cast<double (*)[5][nf]>(sPool + oF);
   double (*sQ)[4][nf] = reinterpret_cast<double (*)[4][nf]>(sPool + (NS ? oQ : 0));
   double (*sFn)[4][nf] = reinterpret_cast<double (*)[4][nf]>(sPool + (NS ? oFn : 0));
-  double (*sJf)[3][nf] = reinterpret_cast<double (*)[3][nf]>(sPool + (NS ? oJf : 0));
+  double (*sJf)[3][nf] = reinterpret_cast<double (*)[3][nf]>(sPool + (NS ? oQ : 0));
   double (*sV)[nnp] = reinterpret_cast<double (*)[nnp]>(sPool);
 
   const int e = element_of_block(blockIdx.x, A.chunk);
@@ -2719,6 +2721,7 @@ __global__ __launch_bounds__(NT) void k_stage_curved(StageArgs A) {
   const Ref ref0{0.0, 0.0, 0.0};
 
   double me[7];
+  double jfk[FIC][3];  // face metric along the own +xi, written to LDS after the gradient
   int ijk[3] = {0, 0, 0};
   if (t < nn) {
     primitives<VF, double, false>(u, gm1, ref0, me);
@@ -2758,7 +2761,7 @@ __global__ __launch_bounds__(NT) void k_stage_curved(StageArgs A) {
           sFn[it.f][cc][it.a] = sn * c.fn[cc];
         }
 #pragma unroll
-        for (int m = 0; m < 3; ++m) sJf[it.f][m][it.a] = so * Nv[m];
+        for (int m = 0; m < 3; ++m) jfk[k][m] = so * Nv[m];
       }
     }
   __syncthreads();
@@ -2818,7 +2821,7 @@ __global__ __launch_bounds__(NT) void k_stage_curved(StageArgs A) {
     for (int v = 0; v < 5; ++v) gprev[v] = A.G[(size_t)e * 5 * nn + t + v * nn];
   }
   if (NS) {
-    __syncthreads();  // sP, sM consumed
+    __syncthreads();  // sP, sM and sQ consumed
     if (t < nn) {
 #pragma unroll
       for (int d = 0; d < 3; ++d)
@@ -2826,6 +2829,11 @@ __global__ __launch_bounds__(NT) void k_stage_curved(StageArgs A) {
         for (int c = 0; c < 4; ++c)
           sV[4 * d + c][t] = mt[3 * d] * Fv[0][c] + mt[3 * d + 1] * Fv[1][c] + mt[3 * d + 2] * Fv[2][c];
     }
+#pragma unroll
+    for (int k = 0; k < FIC; ++k)
+      if (t + k * NT < 6 * nf)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) sJf[cf[k].it.f][m][cf[k].it.a] = jfk[k][m];
     __syncthreads();
     if (t < nn) {
 #pragma unroll
@@ -2885,30 +2893,36 @@ __global__ __launch_bounds__(NT) void k_stage_curved(StageArgs A) {
 // lifted gradient (reference derivatives of q along the three directions with
 // their lifting terms, chain rule with the node metric), the Cartesian viscous
 // fluxes and their projection on the face metric, Ja_f . Fv -> Fvf[e][f][c][a].
-__global__ __launch_bounds__(NT) void k_lift_curved(StageArgs A) {
+// One element per workgroup (measured at N = 5: two elements per workgroup,
+// which speeds up the Cartesian lifting kernel, make this one 9 % slower).
+using PLC = Pack<1>;
+__global__ __launch_bounds__(PLC::NTB) void k_lift_curved(StageArgs A) {
+  constexpr int EPB = PLC::EPB, TPE = PLC::TPE, FIC = PLC::FI;
   __shared__ double sB[NB_STAGE];
-  __shared__ double sq[4][nn];
-  __shared__ double sQ[6][4][nf];
-  const int e = element_of_block(blockIdx.x, A.chunk);
-  if (e >= A.nelem) return;
-  const int t = threadIdx.x;
+  __shared__ double sqAll[EPB][4][nn];
+  __shared__ double sQAll[EPB][6][4][nf];
+  const int e0 = EPB * element_of_block(blockIdx.x, A.chunk);
+  if (e0 >= A.nelem) return;  // uniform over the workgroup
+  const Slot sl = slot_of_thread<PLC>(e0, A.nelem);
+  const int e = sl.e, t = sl.t, tid = threadIdx.x;
+  double (*sq)[nn] = sqAll[sl.s];
+  double (*sQ)[4][nf] = sQAll[sl.s];
   const double gm1 = A.gamma - 1.0;
-  constexpr int FIC = (6 * nf + NT - 1) / NT;
   CurvedFace cf[FIC];
 #pragma unroll
   for (int k = 0; k < FIC; ++k)
-    if (t + k * NT < 6 * nf) cf[k].it = curved_face_item(A, e, t + k * NT);
+    if (t + k * TPE < 6 * nf) cf[k].it = curved_face_item(A, e, t + k * TPE);
   const double* Ue = A.U + (size_t)e * 5 * nn;
   double u[5];
   if (t < nn) {
 #pragma unroll
     for (int v = 0; v < 5; ++v) u[v] = Ue[v * nn + t];
   }
-  const double bval = t < NB_STAGE ? A.basis[t] : 0.0;
+  const double bval = tid < NB_STAGE ? A.basis[tid] : 0.0;
 #pragma unroll
   for (int k = 0; k < FIC; ++k)
-    if (t + k * NT < 6 * nf) curved_face_issue<false>(A, e, cf[k]);
-  if (t < NB_STAGE) sB[t] = bval;
+    if (t + k * TPE < 6 * nf) curved_face_issue<false>(A, e, cf[k]);
+  if (tid < NB_STAGE) sB[tid] = bval;
   if (t < nn) {
     const double ir = rcp64(u[0]);
     const double vx = u[1] * ir, vy = u[2] * ir, vz = u[3] * ir;
@@ -2920,7 +2934,7 @@ __global__ __launch_bounds__(NT) void k_lift_curved(StageArgs A) {
   }
 #pragma unroll
   for (int k = 0; k < FIC; ++k)
-    if (t + k * NT < 6 * nf) {
+    if (t + k * TPE < 6 * nf) {
       double q[4];
       curved_face_q(cf[k], gm1, q);
 #pragma unroll
@@ -2931,7 +2945,7 @@ __global__ __launch_bounds__(NT) void k_lift_curved(StageArgs A) {
   const double* swinv = sB + BL.winv();
 #pragma unroll
   for (int k = 0; k < FIC; ++k)
-    if (t + k * NT < 6 * nf) {
+    if (t + k * TPE < 6 * nf) {
       const CFaceItem& it = cf[k].it;
       const int n = it.nown;
       const int ijk[3] = {n % n1, (n / n1) % n1, n / nf};
@@ -3140,8 +3154,9 @@ hipError_t launch_stage_curved(const StageArgs& A, int eq, hipStream_t s) {
   }
 }
 
-hipError_t launch_lift_curved(const StageArgs& A, hipStream_t s) {
-  hipLaunchKernelGGL(k_lift_curved, dim3(blocks_for(A)), dim3(NT), 0, s, A);
+hipError_t launch_lift_curved(const StageArgs& A0, hipStream_t s) {
+  const StageArgs A = grouped<PLC>(A0);
+  hipLaunchKernelGGL(k_lift_curved, dim3(blocks_for(A)), dim3(PLC::NTB), 0, s, A);
   return hipGetLastError();
 }
 
