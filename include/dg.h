@@ -148,8 +148,8 @@ int dg_set_cs_field(dg_ctx* ctx, const double* cs);
  * Ja_f the mean of both elements' metric at a face node; Navier-Stokes with
  * the BR1 gradient (1/J) sum_i Ja^i (d_i q + lifting) and the contravariant
  * viscous flux.  X = NULL returns to the Cartesian box of dg_init.
- * Errors: DG_EINVAL for a host pointer or a non-positive / non-finite
- * Jacobian at any node (the mesh stays Cartesian); DG_EUNSUPPORTED with
+ * Errors (the context's geometry is then unchanged): DG_EINVAL for a host
+ * pointer or a non-positive / non-finite Jacobian at any node; DG_EUNSUPPORTED with
  * blending, DG_MIXED, DG_VF_CH or the Smagorinsky model (and later
  * dg_set_options / dg_set_cs_field calls that would enable them return it);
  * DG_ENOMEM.  dg_vjp, rk_step_vjp and dg_node_weights return DG_EUNSUPPORTED

@@ -657,18 +657,29 @@ int dg_set_connectivity(dg_ctx* c, const int32_t* conn) {
       }
     nbr.resize((size_t)ne * 6);
     for (size_t k = 0; k < nbr.size(); ++k) nbr[k] = conn[3 * k];
-    hipError_t e = hipSuccess;
-    if (!c->conn) e = hipMalloc((void**)&c->conn, (size_t)ne * 18 * sizeof(int32_t));
-    if (e == hipSuccess) e = hipMemcpy(c->conn, conn, (size_t)ne * 18 * sizeof(int32_t), hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(c, (e == hipErrorOutOfMemory) ? DG_ENOMEM : DG_EHIP, "dg_set_connectivity: %s",
-                  hipGetErrorString(e));
-    }
   }
-  // the neighbour table (indicator spread, structured kernels) follows the connectivity
-  const hipError_t e = hipMemcpy(c->nbr, nbr.data(), nbr.size() * sizeof(int32_t), hipMemcpyHostToDevice);
-  if (e != hipSuccess) return hip_fail(c, e, "dg_set_connectivity");
+  // New device tables (the neighbour table, used by the indicator spread and
+  // the structured kernels, follows the connectivity), filled on the
+  // context's stream behind its queued work and swapped in only when complete,
+  // so a failure leaves the context unchanged.
+  int32_t *dnbr = nullptr, *dconn = nullptr;
+  const size_t cbytes = (size_t)c->nelem * 18 * sizeof(int32_t);
+  hipError_t e = hipMalloc((void**)&dnbr, nbr.size() * sizeof(int32_t));
+  if (e == hipSuccess && conn) e = hipMalloc((void**)&dconn, cbytes);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dnbr, nbr.data(), nbr.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess && conn) e = hipMemcpyAsync(dconn, conn, cbytes, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);  // the host arrays are the caller's
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    hipFree(dnbr);
+    hipFree(dconn);
+    return fail(c, (e == hipErrorOutOfMemory) ? DG_ENOMEM : DG_EHIP, "dg_set_connectivity: %s", hipGetErrorString(e));
+  }
+  hipFree(c->nbr);
+  c->nbr = dnbr;
+  hipFree(c->conn);
+  c->conn = dconn;
   return DG_OK;
 }
 
@@ -682,9 +693,10 @@ int dg_set_geometry(dg_ctx* c, const double* X) {
   if (!is_device_ptr(X)) return fail(c, DG_EINVAL, "dg_set_geometry: X must be a device pointer");
   const int rc = curved_compatible(c, &c->opt, c->has_cs_field, "dg_set_geometry");
   if (rc) return rc;
-  hipError_t e = hipSuccess;
-  double* M = c->M;
-  if (!M) e = hipMalloc((void**)&M, (size_t)c->nelem * 10 * c->nn * sizeof(double));
+  // metric terms into a new array, swapped in only when complete and valid:
+  // a failure leaves the context's geometry unchanged
+  double* M = nullptr;
+  hipError_t e = hipMalloc((void**)&M, (size_t)c->nelem * 10 * c->nn * sizeof(double));
   if (e == hipSuccess && !c->d_bad) e = hipMalloc((void**)&c->d_bad, sizeof(int));
   int bad = 0;
   if (e == hipSuccess) e = hipMemsetAsync(c->d_bad, 0, sizeof(int), c->stream);
@@ -693,15 +705,15 @@ int dg_set_geometry(dg_ctx* c, const double* X) {
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
     (void)hipGetLastError();
-    if (M != c->M) hipFree(M);
+    hipFree(M);
     return fail(c, (e == hipErrorOutOfMemory) ? DG_ENOMEM : DG_EHIP, "dg_set_geometry: %s", hipGetErrorString(e));
   }
-  c->M = M;
   if (bad) {
-    hipFree(c->M);
-    c->M = nullptr;
+    hipFree(M);
     return fail(c, DG_EINVAL, "dg_set_geometry: %d nodes with a non-positive or non-finite Jacobian", bad);
   }
+  hipFree(c->M);
+  c->M = M;
   return DG_OK;
 }
 

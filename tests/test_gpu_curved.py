@@ -264,3 +264,23 @@ def test_connectivity_error_paths(orc, torch_cuda):
     assert ei.value.code == dg.DG_ESTATE
     op.set_connectivity(None)
     assert np.array_equal(op.time_derivative(U).cpu().numpy(), ref)
+
+
+def test_failed_calls_keep_the_previous_mesh(orc, torch_cuda):
+    """A rejected geometry or connectivity leaves the context as it was."""
+    import torch
+
+    from paper_2306_12891_amd import dg
+    N, ne = 3, (2, 2, 2)
+    s, op = make(orc, torch_cuda, N, ne, I.warped_coordinates(N, ne, amp=0.05), eq=1, vf=1, sf=1, mu=1e-2)
+    U = torch.from_numpy(I.random_smooth(N, ne, seed=4, xnodes=I.warped_coordinates(N, ne, amp=0.05))).cuda()
+    before = op.time_derivative(U).cpu().numpy()
+    bad = I.warped_coordinates(N, ne, amp=0.05)
+    bad[1, 1] = bad[1, 1, :, ::-1, :]  # element 1 inverted
+    with pytest.raises(dg.DGError):
+        op.set_geometry(torch.from_numpy(np.ascontiguousarray(bad)).cuda())
+    _, conn = I.rotated_elements(N, ne, seed=1)
+    conn[0, 0, 1] = (conn[0, 0, 1] + 1) % 6
+    with pytest.raises(dg.DGError):
+        op.set_connectivity(conn)
+    assert np.array_equal(op.time_derivative(U).cpu().numpy(), before)
