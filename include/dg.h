@@ -152,8 +152,9 @@ int dg_set_cs_field(dg_ctx* ctx, const double* cs);
  * pointer or a non-positive / non-finite Jacobian at any node; DG_EUNSUPPORTED with
  * blending, DG_MIXED, DG_VF_CH or the Smagorinsky model (and later
  * dg_set_options / dg_set_cs_field calls that would enable them return it);
- * DG_ENOMEM.  dg_vjp, rk_step_vjp and dg_node_weights return DG_EUNSUPPORTED
- * on a curved mesh. */
+ * DG_ENOMEM.  dg_vjp and rk_step_vjp work on curved meshes (also with general
+ * connectivity); dg_node_weights returns DG_EUNSUPPORTED there (per-node
+ * Jacobians: use dg_integrals). */
 int dg_set_geometry(dg_ctx* ctx, const double* X);
 
 /* General connectivity of a curved mesh (unstructured hexahedra, as the
@@ -200,9 +201,11 @@ int dg_rk_steps(dg_ctx* ctx, double* U, double dt, int nsteps);
  * spread) and of the FV subcell reconstruction; at their switches the
  * one-sided rules are: derivative 0 where the coefficient is clipped or cut
  * off, the mean derivative at ties of a maximum, the selected slope of the
- * minmod limiter.  Not available with DG_MIXED, the CH flux or the
- * Smagorinsky model (DG_EUNSUPPORTED).  Allocates the reverse-mode face
- * buffer (and with blending two more buffers) on first use. */
+ * minmod limiter.  On curved meshes (dg_set_geometry, also with general
+ * connectivity) the product is that of the curved operator.  Not available
+ * with DG_MIXED, the CH flux or the Smagorinsky model (DG_EUNSUPPORTED).
+ * Allocates the reverse-mode face buffer (and with blending two more buffers)
+ * on first use. */
 int dg_vjp(dg_ctx* ctx, const double* U, const double* Ut_bar, double* U_bar);
 
 /* Vector-Jacobian product of one rk_step: U_bar_n = (dU_{n+1}/dU_n)^T U_bar_np1,

@@ -388,7 +388,8 @@ int curved_compatible(dg_ctx* c, const dg_options* o, int cs_field, const char* 
 }
 
 int vjp_supported(dg_ctx* c) {
-  if (c->M) return fail(c, DG_EUNSUPPORTED, "vjp: not available on curved meshes");
+  if (c->conn && !c->M)
+    return fail(c, DG_ESTATE, "general connectivity needs curved elements: call dg_set_geometry first");
   if (eq_code(c) == 2) return fail(c, DG_EUNSUPPORTED, "vjp: not available with the Smagorinsky model");
   if (c->opt.precision != DG_FP64) return fail(c, DG_EUNSUPPORTED, "vjp: FP64 operator only");
   if (c->opt.vol_flux == DG_VF_CH) return fail(c, DG_EUNSUPPORTED, "vjp: not available for the CH flux");
@@ -436,7 +437,18 @@ int run_vjp(dg_ctx* c, const double* U, const double* lambda, double* U_bar, con
   v.chunk = c->chunk;
   v.vf = c->opt.vol_flux;
   v.sf = c->opt.surf_flux;
+  v.M = c->M;
+  v.conn = c->conn;
   hipError_t e;
+  if (c->M) {  // curved mesh (FP64, no blending: checked when set)
+    if (c->opt.equations == DG_NS) {
+      e = timed(c, DG_K_VJP_LIFT, [&] { return c->kt->vjp_lift_curved(v, c->stream); });
+      if (e != hipSuccess) return hip_fail(c, e, "vjp lifting kernel (curved)");
+    }
+    e = timed(c, DG_K_VJP, [&] { return c->kt->vjp_curved(v, c->opt.equations, c->stream); });
+    if (e != hipSuccess) return hip_fail(c, e, "vjp kernel (curved)");
+    return DG_OK;
+  }
   if (c->opt.blending) {
     // forward at U: blending coefficients and U_t^FV - U_t^DG
     if ((rc = run_stage(c, U, nullptr, c->Dfd, MODE_DIFF, 0.0, 0.0, 0, c->alpha))) return rc;

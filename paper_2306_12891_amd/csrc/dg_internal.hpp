@@ -88,6 +88,9 @@ struct VjpArgs {
   double* abar;
   double amin, amax, aspread, thresh, sharp;
   int indicator, recon;
+  // curved mesh: metric terms and general connectivity (see StageArgs), or NULL
+  const double* M;
+  const int32_t* conn;
 };
 
 struct KernelTable {
@@ -118,6 +121,9 @@ struct KernelTable {
                         hipStream_t);
   hipError_t (*stage_curved)(const StageArgs&, int eq, hipStream_t);
   hipError_t (*lift_curved)(const StageArgs&, hipStream_t);
+  // reverse mode on curved elements (FP64, no blending)
+  hipError_t (*vjp_curved)(const VjpArgs&, int eq, hipStream_t);
+  hipError_t (*vjp_lift_curved)(const VjpArgs&, hipStream_t);
 };
 
 const KernelTable* table_N1();

@@ -1681,6 +1681,7 @@ __global__ __launch_bounds__(NT) void k_vjp(VjpArgs A) {
     ijk[1] = (t / n1) % n1;
     ijk[2] = t / nf;
   }
+  __syncthreads();  // the face seeds read the basis (swinv)
   // (face item, seed) work units, seed-major so that neighbouring lanes take
   // neighbouring face nodes
 #pragma unroll 1
@@ -2506,7 +2507,7 @@ __device__ __forceinline__ int face_vol_node(int f, int a) {
   return ((f & 1) ? N : 0) * sn + t1 * s1 + t2 * s2;
 }
 
-__device__ __forceinline__ CFaceItem curved_face_item(const StageArgs& A, int e, int q) {
+__device__ __forceinline__ CFaceItem cface(const int32_t* conn, const int32_t* nbr, int e, int q) {
   CFaceItem it;
   it.f = q / nf;
   it.a = q - it.f * nf;
@@ -2514,13 +2515,13 @@ __device__ __forceinline__ CFaceItem curved_face_item(const StageArgs& A, int e,
   it.side = it.f & 1;
   it.nown = face_vol_node(it.f, it.a);
   int o = 0;
-  if (A.conn) {
-    const int32_t* c = A.conn + ((size_t)e * 6 + it.f) * 3;
+  if (conn) {
+    const int32_t* c = conn + ((size_t)e * 6 + it.f) * 3;
     it.nb = c[0];
     it.fb = c[1];
     o = c[2];
   } else {
-    it.nb = A.nbr[6 * e + it.f];
+    it.nb = nbr[6 * e + it.f];
     it.fb = it.f ^ 1;
   }
   const int t1 = it.a % n1, t2 = it.a / n1;
@@ -2532,6 +2533,10 @@ __device__ __forceinline__ CFaceItem curved_face_item(const StageArgs& A, int e,
   const bool pb = it.fb & 1;
   it.own_minus = (it.side && !pb) || ((it.side != 0) == pb && (e < it.nb || (e == it.nb && it.f < it.fb)));
   return it;
+}
+
+__device__ __forceinline__ CFaceItem curved_face_item(const StageArgs& A, int e, int q) {
+  return cface(A.conn, A.nbr, e, q);
 }
 
 // Loads of a curved face item: both conservative states in Cartesian
@@ -3003,6 +3008,502 @@ __global__ __launch_bounds__(PLC::NTB) void k_lift_curved(StageArgs A) {
     }
 }
 
+// ===========================================================================
+// Reverse mode on curved elements (FP64; Euler and Navier-Stokes; KG, PI and
+// STD fluxes).  U_t = (1/J)(...) at every node, so with lt = lambda / J the
+// Cartesian reverse formulas hold with the two-point flux along the averaged
+// metric vector (Ja^i(n) + Ja^i(l))/2, the interface flux along the face
+// normal N in its canonical orientation (its cotangent collects lt of both
+// elements), the chain-rule gradient and the contravariant viscous flux.
+// Pass 1 (k_vjp_lift_curved) writes, at each own face node, the cotangent of
+// the reference derivative along the face direction times its lifting weight,
+// which the neighbour's pass 2 (k_vjp_curved) reads.
+// ===========================================================================
+
+// Interface flux along the unit normal n over a generic scalar (dual numbers):
+// rotation into the frame (n, t1, t2) of surface_flux_normal, rotated-frame
+// flux, rotation back.
+template <int VF, class S>
+__device__ __forceinline__ void flux_normal_generic(int sf, const S L[5], const S R[5], const double n[3],
+                                                    double gamma, S f[5]) {
+  const double ax = fabs(n[0]), ay = fabs(n[1]), az = fabs(n[2]);
+  double t1[3];
+  if (ax <= ay && ax <= az) {
+    t1[0] = 0.0; t1[1] = n[2]; t1[2] = -n[1];
+  } else if (ay <= az) {
+    t1[0] = -n[2]; t1[1] = 0.0; t1[2] = n[0];
+  } else {
+    t1[0] = n[1]; t1[1] = -n[0]; t1[2] = 0.0;
+  }
+  const double it = rcp64(sqrt64(t1[0] * t1[0] + t1[1] * t1[1] + t1[2] * t1[2]));
+  t1[0] *= it; t1[1] *= it; t1[2] *= it;
+  const double t2[3] = {n[1] * t1[2] - n[2] * t1[1], n[2] * t1[0] - n[0] * t1[2], n[0] * t1[1] - n[1] * t1[0]};
+  S a[5], b[5], g[5];
+  a[0] = L[0]; a[4] = L[4];
+  b[0] = R[0]; b[4] = R[4];
+  a[1] = n[0] * L[1] + n[1] * L[2] + n[2] * L[3];
+  a[2] = t1[0] * L[1] + t1[1] * L[2] + t1[2] * L[3];
+  a[3] = t2[0] * L[1] + t2[1] * L[2] + t2[2] * L[3];
+  b[1] = n[0] * R[1] + n[1] * R[2] + n[2] * R[3];
+  b[2] = t1[0] * R[1] + t1[1] * R[2] + t1[2] * R[3];
+  b[3] = t2[0] * R[1] + t2[1] * R[2] + t2[2] * R[3];
+  riemann_generic<VF, 0, S>(sf, a, b, gamma, g);
+  f[0] = g[0];
+  f[1] = n[0] * g[1] + t1[0] * g[2] + t2[0] * g[3];
+  f[2] = n[1] * g[1] + t1[1] * g[2] + t2[1] * g[3];
+  f[3] = n[2] * g[1] + t1[2] * g[2] + t2[2] * g[3];
+  f[4] = g[4];
+}
+
+// The minus (L) and plus (R) side of a curved face item and its normal
+// N = (s_L Ja_L - s_R Ja_R)/2.
+struct CurvedSides {
+  int eL, eR, nL, nR, fL, fR;
+};
+__device__ __forceinline__ CurvedSides curved_sides(const CFaceItem& it, int e) {
+  CurvedSides c;
+  c.eL = it.own_minus ? e : it.nb;
+  c.eR = it.own_minus ? it.nb : e;
+  c.nL = it.own_minus ? it.nown : it.nnb;
+  c.nR = it.own_minus ? it.nnb : it.nown;
+  c.fL = it.own_minus ? it.f : it.fb;
+  c.fR = it.own_minus ? it.fb : it.f;
+  return c;
+}
+__device__ __forceinline__ void curved_normal(const double* M, const CurvedSides& c, double Nv[3]) {
+  const double sL = (c.fL & 1) ? 1.0 : -1.0, sR = (c.fR & 1) ? 1.0 : -1.0;
+#pragma unroll
+  for (int m = 0; m < 3; ++m)
+    Nv[m] = 0.5 * (sL * M[((size_t)c.eL * MS + 3 * (c.fL >> 1) + m) * nn + c.nL] -
+                   sR * M[((size_t)c.eR * MS + 3 * (c.fR >> 1) + m) * nn + c.nR]);
+}
+
+// Reverse of the two-point flux along the direction vector nv (not unit) with
+// respect to its first argument, in primitive variables (rho, u, p, x).
+template <int VF>
+__device__ __forceinline__ void twopoint_vjp_n(const double me[7], double rl, const double ul[3], double pl,
+                                               double xl, const double nv[3], const double w[5], double pb[6]) {
+  const double wn = w[1] * nv[0] + w[2] * nv[1] + w[3] * nv[2];
+  if (VF == VF_STD) {
+    const double r = me[0];
+    const double un = me[1] * nv[0] + me[2] * nv[1] + me[3] * nv[2];
+    const double s = w[0] + w[1] * me[1] + w[2] * me[2] + w[3] * me[3] + w[4] * me[5];
+    pb[0] += 0.5 * un * s;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) pb[1 + j] += 0.5 * (w[1 + j] * r * un + nv[j] * r * s);
+    pb[4] += 0.5 * wn;
+    pb[5] += 0.5 * w[4] * r * un;
+    return;
+  }
+  const double rm = 0.5 * (me[0] + rl);
+  const double um[3] = {0.5 * (me[1] + ul[0]), 0.5 * (me[2] + ul[1]), 0.5 * (me[3] + ul[2])};
+  const double xm = 0.5 * (me[5] + xl);
+  const double Un = um[0] * nv[0] + um[1] * nv[1] + um[2] * nv[2];
+  const double fr = rm * Un;
+  const double wr = w[0] + w[1] * um[0] + w[2] * um[1] + w[3] * um[2] + w[4] * xm;
+  pb[0] += 0.5 * wr * Un;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) pb[1 + j] += 0.5 * (w[1 + j] * fr + wr * rm * nv[j]);
+  pb[4] += 0.5 * wn;
+  pb[5] += 0.5 * w[4] * fr;
+  if (VF == VF_KG) {
+    const double pm = 0.5 * (me[4] + pl);
+    pb[4] += 0.5 * w[4] * Un;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) pb[1 + j] += 0.5 * w[4] * pm * nv[j];
+  }
+}
+
+template <int VF, int D>
+__device__ __forceinline__ void volume_vjp_dir_curved(const double (*sP)[nn], const double (*sM)[nn],
+                                                      const double (*sLt)[nn], const double* sDhat, int n, int id,
+                                                      const double me[7], const double jo[3], const double lt[5],
+                                                      double pb[6]) {
+  constexpr int st = D == 0 ? 1 : (D == 1 ? n1 : nf);
+  const int base = n - id * st;
+#pragma unroll 1
+  for (int k = 1; k <= kPartners; ++k) {
+    const int l = partner(id, k);
+    const int m = base + l * st;
+    const double c1 = -sDhat[id * n1 + l], c2 = -sDhat[l * n1 + id];
+    double w[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) w[v] = fma(c1, lt[v], c2 * sLt[v][m]);
+    const double nv[3] = {0.5 * (jo[0] + sM[3 * D][m]), 0.5 * (jo[1] + sM[3 * D + 1][m]),
+                          0.5 * (jo[2] + sM[3 * D + 2][m])};
+    const double ul[3] = {sP[1][m], sP[2][m], sP[3][m]};
+    twopoint_vjp_n<VF>(me, sP[0][m], ul, sP[4][m], sP[5][m], nv, w, pb);
+  }
+}
+
+// Interface part of face item q, seed k: (d ft*/d U_own,k) . fbar, ft* the
+// face flux |N| f*(U_L, U_R; N/|N|) in its canonical orientation and fbar its
+// cotangent, sum over both elements of (lifting coefficient) x (orientation
+// sign) x lt at their face node.
+template <int VF>
+__device__ __forceinline__ void vjp_face_seed_curved(const VjpArgs& A, int e, int q, int k, const double* swinv,
+                                                     double (*sSF)[5][nf]) {
+  const CFaceItem it = cface(A.conn, A.nbr, e, q);
+  const CurvedSides c = curved_sides(it, e);
+  double Nv[3];
+  curved_normal(A.M, c, Nv);
+  const double sh = sqrt64(Nv[0] * Nv[0] + Nv[1] * Nv[1] + Nv[2] * Nv[2]);
+  const double ish = rcp64(sh);
+  const double nv[3] = {Nv[0] * ish, Nv[1] * ish, Nv[2] * ish};
+  const double so = (it.side ? 1.0 : -1.0) * (it.own_minus ? 1.0 : -1.0);
+  const double sb = ((it.fb & 1) ? 1.0 : -1.0) * (it.own_minus ? -1.0 : 1.0);
+  const double co = so * (it.side ? -swinv[N] : swinv[0]) * A.M[((size_t)e * MS + 9) * nn + it.nown];
+  const double cb = sb * ((it.fb & 1) ? -swinv[N] : swinv[0]) * A.M[((size_t)it.nb * MS + 9) * nn + it.nnb];
+  const double* UL = A.U + (size_t)c.eL * 5 * nn;
+  const double* UR = A.U + (size_t)c.eR * 5 * nn;
+  const double* Lo = A.Lbar + (size_t)e * 5 * nn;
+  const double* Lb = A.Lbar + (size_t)it.nb * 5 * nn;
+  Dl Ld[5], Rd[5], fd[5];
+  double fb[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    const double seed = v == k ? 1.0 : 0.0;
+    Ld[v] = {UL[v * nn + c.nL], it.own_minus ? seed : 0.0};
+    Rd[v] = {UR[v * nn + c.nR], it.own_minus ? 0.0 : seed};
+    fb[v] = fma(co, Lo[v * nn + it.nown], cb * Lb[v * nn + it.nnb]);
+  }
+  flux_normal_generic<VF, Dl>(A.sf, Ld, Rd, nv, A.gamma, fd);
+  double s = 0.0;
+#pragma unroll
+  for (int v = 0; v < 5; ++v) s = fma(fb[v], fd[v].d, s);
+  sSF[it.f][k][it.a] = sh * s;
+}
+
+// Navier-Stokes face data of face item q: the face metric along the own +xi
+// (sJo), the neighbour's lt at its node scaled by -s_own s_nb w_nb (sLn; w the
+// lifting weight of the neighbour's face), and, with Q, q* (forward gradient)
+// and the neighbour's pass-1 output (sGn).
+template <bool Q>
+__device__ __forceinline__ void vjp_face_ns_curved(const VjpArgs& A, int e, int q, const double* swinv,
+                                                   double (*sJo)[3][nf], double (*sLn)[4][nf], double (*sQ)[4][nf],
+                                                   double (*sGn)[4][nf]) {
+  const CFaceItem it = cface(A.conn, A.nbr, e, q);
+  const CurvedSides c = curved_sides(it, e);
+  double Nv[3];
+  curved_normal(A.M, c, Nv);
+  const double so = (it.side ? 1.0 : -1.0) * (it.own_minus ? 1.0 : -1.0);
+#pragma unroll
+  for (int m = 0; m < 3; ++m) sJo[it.f][m][it.a] = so * Nv[m];
+  const double sameside = ((it.side != 0) == ((it.fb & 1) != 0)) ? -1.0 : 1.0;  // -s_own s_nb
+  const double wb = (it.fb & 1) ? swinv[N] : -swinv[0];
+  const double lb = sameside * wb * A.M[((size_t)it.nb * MS + 9) * nn + it.nnb];
+  const double* Lb = A.Lbar + (size_t)it.nb * 5 * nn;
+#pragma unroll
+  for (int cc = 0; cc < 4; ++cc) sLn[it.f][cc][it.a] = lb * Lb[(1 + cc) * nn + it.nnb];
+  if (Q) {
+    double L[5], R[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      L[v] = A.U[((size_t)c.eL * 5 + v) * nn + c.nL];
+      R[v] = A.U[((size_t)c.eR * 5 + v) * nn + c.nR];
+    }
+    const double gm1 = A.gamma - 1.0;
+    const double iL = rcp64(L[0]), iR = rcp64(R[0]);
+    const double uL = L[1] * iL, vL = L[2] * iL, wL = L[3] * iL, uR = R[1] * iR, vR = R[2] * iR, wR = R[3] * iR;
+    const double pL = gm1 * (L[4] - 0.5 * (L[1] * uL + L[2] * vL + L[3] * wL));
+    const double pR = gm1 * (R[4] - 0.5 * (R[1] * uR + R[2] * vR + R[3] * wR));
+    sQ[it.f][0][it.a] = 0.5 * (uL + uR);
+    sQ[it.f][1][it.a] = 0.5 * (vL + vR);
+    sQ[it.f][2][it.a] = 0.5 * (wL + wR);
+    sQ[it.f][3][it.a] = 0.5 * (pL * iL + pR * iR);
+    const double* Gn = A.Gbf + ((size_t)it.nb * 6 + it.fb) * 4 * nf;
+#pragma unroll
+    for (int cc = 0; cc < 4; ++cc) sGn[it.f][cc][it.a] = Gn[cc * nf + it.ab];
+  }
+}
+
+// Cotangent of the Cartesian viscous fluxes Fvb[m][c] at node p: the
+// contravariant cotangents from lt along the three lines (Dw transposed),
+// mapped by the node metric, plus the face terms Jo (w_own lt_own + sLn)/2 of
+// the faces containing p.
+__device__ __forceinline__ void viscous_flux_cotangent_curved(const double (*sLt)[nn], const double (*sLn)[4][nf],
+                                                              const double (*sJo)[3][nf], const double* sDw,
+                                                              const double* swinv, int p, const int ijk[3],
+                                                              const double mt[MS], double Fvb[3][4]) {
+#pragma unroll
+  for (int m = 0; m < 3; ++m)
+#pragma unroll
+    for (int cc = 0; cc < 4; ++cc) Fvb[m][cc] = 0.0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int st = d == 0 ? 1 : (d == 1 ? n1 : nf);
+    const int id = ijk[d];
+    const int base = p - id * st;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int l = 0; l < n1; ++l) {
+      const double c = sDw[l * n1 + id];
+      const int k = base + l * st;
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc) s[cc] = fma(c, sLt[1 + cc][k], s[cc]);
+    }
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc) Fvb[m][cc] = fma(mt[3 * d + m], s[cc], Fvb[m][cc]);
+    if (id == 0 || id == N) {
+      const int f = 2 * d + (id == N);
+      const int a = d == 0 ? ijk[1] + n1 * ijk[2] : (d == 1 ? ijk[0] + n1 * ijk[2] : ijk[0] + n1 * ijk[1]);
+      const double wo = id == N ? swinv[N] : -swinv[0];
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc) {
+        const double tt = 0.5 * fma(wo, sLt[1 + cc][p], sLn[f][cc][a]);
+#pragma unroll
+        for (int m = 0; m < 3; ++m) Fvb[m][cc] = fma(sJo[f][m][a], tt, Fvb[m][cc]);
+      }
+    }
+  }
+}
+
+// Pass 1: at each own face node, the cotangent of the reference derivative of
+// q along the face direction times the face's lifting weight -> Gbf[e][f][c][a].
+__global__ __launch_bounds__(NT) void k_vjp_lift_curved(VjpArgs A) {
+  __shared__ double sB[NB_STAGE];
+  __shared__ double sLt[5][nn];
+  __shared__ double sU[3][nn];
+  __shared__ double sLn[6][4][nf];
+  __shared__ double sJo[6][3][nf];
+  const int e = element_of_block(blockIdx.x, A.chunk);
+  if (e >= A.nelem) return;
+  const int t = threadIdx.x;
+  for (int q = t; q < NB_STAGE; q += NT) sB[q] = A.basis[q];
+  const double* swinv = sB + BL.winv();
+  if (t < nn) {
+    const double* Ue = A.U + (size_t)e * 5 * nn;
+    const double* Le = A.Lbar + (size_t)e * 5 * nn;
+    const double ir = rcp64(Ue[t]);
+    const double iJ = A.M[((size_t)e * MS + 9) * nn + t];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) sU[j][t] = Ue[(1 + j) * nn + t] * ir;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) sLt[v][t] = Le[v * nn + t] * iJ;
+  }
+  __syncthreads();  // swinv
+  for (int q = t; q < 6 * nf; q += NT) vjp_face_ns_curved<false>(A, e, q, swinv, sJo, sLn, nullptr, nullptr);
+  __syncthreads();
+  for (int q = t; q < 6 * nf; q += NT) {
+    const int f = q / nf, a = q - f * nf, d = f >> 1;
+    const int p = face_vol_node(f, a);
+    const int ijk[3] = {p % n1, (p / n1) % n1, p / nf};
+    double mt[MS];
+#pragma unroll
+    for (int k = 0; k < MS; ++k) mt[k] = A.M[((size_t)e * MS + k) * nn + p];
+    double Fvb[3][4], gb[3][4];
+    viscous_flux_cotangent_curved(sLt, sLn, sJo, sB + BL.Dw(), swinv, p, ijk, mt, Fvb);
+    const double u[3] = {sU[0][p], sU[1][p], sU[2][p]};
+    gradient_cotangent(Fvb, u, A.mu, A.kappa, gb);
+    const double w = (f & 1) ? swinv[N] : -swinv[0];
+    double* out = A.Gbf + ((size_t)e * 6 + f) * 4 * nf;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      out[c * nf + a] = w * mt[9] * (mt[3 * d] * gb[0][c] + mt[3 * d + 1] * gb[1][c] + mt[3 * d + 2] * gb[2][c]);
+  }
+}
+
+// Pass 2: U_bar (or U_acc + U_bar) on curved elements.
+template <int VF, int EQ>
+__global__ __launch_bounds__(NT) void k_vjp_curved(VjpArgs A) {
+  constexpr bool NS = (EQ == 1);
+  __shared__ double sB[NB_STAGE];
+  __shared__ double sP[7][nn];
+  __shared__ double sM[9][nn];
+  __shared__ double sLt[5][nn];
+  __shared__ double sSF[6][5][nf];
+  __shared__ double sQ[NS ? 6 : 1][4][nf];
+  __shared__ double sLn[NS ? 6 : 1][4][nf];
+  __shared__ double sGn[NS ? 6 : 1][4][nf];
+  __shared__ double sJo[NS ? 6 : 1][3][nf];
+  const int e = element_of_block(blockIdx.x, A.chunk);
+  if (e >= A.nelem) return;
+  const int t = threadIdx.x;
+  const double gm1 = A.gamma - 1.0;
+  for (int q = t; q < NB_STAGE; q += NT) sB[q] = A.basis[q];
+  const double* sDhat = sB + BL.Dhat();
+  const double* sDw = sB + BL.Dw();
+  const double* swinv = sB + BL.winv();
+  const Ref ref{0.0, 0.0, 0.0};
+  double u[5], me[7], lt[5], mt[MS];
+  int ijk[3] = {0, 0, 0};
+  if (t < nn) {
+    const double* Ue = A.U + (size_t)e * 5 * nn;
+    const double* Le = A.Lbar + (size_t)e * 5 * nn;
+#pragma unroll
+    for (int k = 0; k < MS; ++k) mt[k] = A.M[((size_t)e * MS + k) * nn + t];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      u[v] = Ue[v * nn + t];
+      lt[v] = Le[v * nn + t] * mt[9];
+      sLt[v][t] = lt[v];
+    }
+    primitives<VF, double, false>(u, gm1, ref, me);
+#pragma unroll
+    for (int k = 0; k < 7; ++k) sP[k][t] = me[k];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) sM[k][t] = mt[k];
+    ijk[0] = t % n1;
+    ijk[1] = (t / n1) % n1;
+    ijk[2] = t / nf;
+  }
+  __syncthreads();  // swinv
+#pragma unroll 1
+  for (int w = t; w < 5 * 6 * nf; w += NT) {
+    const int k = w / (6 * nf), q = w - k * (6 * nf);
+    vjp_face_seed_curved<VF>(A, e, q, k, swinv, sSF);
+  }
+  if (NS)
+    for (int q = t; q < 6 * nf; q += NT) vjp_face_ns_curved<true>(A, e, q, swinv, sJo, sLn, sQ, sGn);
+  __syncthreads();
+
+  double pb[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double thb = 0.0;
+  double sb[3][4];  // cotangents of the reference derivatives of q
+  if (t < nn) {
+    volume_vjp_dir_curved<VF, 0>(sP, sM, sLt, sDhat, t, ijk[0], me, mt + 0, lt, pb);
+    volume_vjp_dir_curved<VF, 1>(sP, sM, sLt, sDhat, t, ijk[1], me, mt + 3, lt, pb);
+    volume_vjp_dir_curved<VF, 2>(sP, sM, sLt, sDhat, t, ijk[2], me, mt + 6, lt, pb);
+    if (NS) {
+      double Fvb[3][4];
+      viscous_flux_cotangent_curved(sLt, sLn, sJo, sDw, swinv, t, ijk, mt, Fvb);
+      // forward gradient: reference derivatives with lifting, chain rule
+      double s[3][4];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int st = d == 0 ? 1 : (d == 1 ? n1 : nf);
+        const int id = ijk[d];
+        const int base = t - id * st;
+        const double* crow = sDw + id * n1;
+        double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+#pragma unroll
+        for (int l = 0; l < n1; ++l) {
+          const int m = base + l * st;
+          const double c = crow[l];
+          a0 = fma(c, sP[1][m], a0);
+          a1 = fma(c, sP[2][m], a1);
+          a2 = fma(c, sP[3][m], a2);
+          a3 = fma(c, sP[6][m], a3);
+        }
+        if (id == 0 || id == N) {
+          const int f = 2 * d + (id == N);
+          const int a = d == 0 ? ijk[1] + n1 * ijk[2] : (d == 1 ? ijk[0] + n1 * ijk[2] : ijk[0] + n1 * ijk[1]);
+          const double w = id == N ? swinv[N] : -swinv[0];
+          a0 = fma(w, sQ[f][0][a], a0);
+          a1 = fma(w, sQ[f][1][a], a1);
+          a2 = fma(w, sQ[f][2][a], a2);
+          a3 = fma(w, sQ[f][3][a], a3);
+        }
+        s[d][0] = a0;
+        s[d][1] = a1;
+        s[d][2] = a2;
+        s[d][3] = a3;
+      }
+      double g[3][4];
+#pragma unroll
+      for (int m = 0; m < 3; ++m)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) g[m][c] = mt[9] * (mt[m] * s[0][c] + mt[3 + m] * s[1][c] + mt[6 + m] * s[2][c]);
+      const double div = g[0][0] + g[1][1] + g[2][2];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        double acc = 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          const double tau = A.mu * (g[d][j] + g[j][d]) - (j == d ? (2.0 / 3.0) * A.mu * div : 0.0);
+          acc = fma(tau, Fvb[d][3], acc);
+        }
+        pb[1 + j] += acc;
+      }
+      double gb[3][4];
+      const double uu[3] = {me[1], me[2], me[3]};
+      gradient_cotangent(Fvb, uu, A.mu, A.kappa, gb);
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          sb[d][c] = mt[9] * (mt[3 * d] * gb[0][c] + mt[3 * d + 1] * gb[1][c] + mt[3 * d + 2] * gb[2][c]);
+    }
+  }
+  if (NS) {
+    // q_bar = sum_d [ Dw^T sb_d along the d line + (w_own sb_d + neighbour's) / 2 at faces ]
+    double (*sX)[nn] = sLt;  // lt is no longer needed
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      __syncthreads();
+      if (t < nn) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sX[c][t] = sb[d][c];
+      }
+      __syncthreads();
+      if (t < nn) {
+        const int st = d == 0 ? 1 : (d == 1 ? n1 : nf);
+        const int id = ijk[d];
+        const int base = t - id * st;
+        double s[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int l = 0; l < n1; ++l) {
+          const double c = sDw[l * n1 + id];
+          const int k = base + l * st;
+#pragma unroll
+          for (int cc = 0; cc < 4; ++cc) s[cc] = fma(c, sX[cc][k], s[cc]);
+        }
+        if (id == 0 || id == N) {
+          const int f = 2 * d + (id == N);
+          const int a = d == 0 ? ijk[1] + n1 * ijk[2] : (d == 1 ? ijk[0] + n1 * ijk[2] : ijk[0] + n1 * ijk[1]);
+          const double wo = id == N ? swinv[N] : -swinv[0];
+#pragma unroll
+          for (int cc = 0; cc < 4; ++cc) s[cc] += 0.5 * fma(wo, sb[d][cc], sGn[f][cc][a]);
+        }
+        pb[1] += s[0];
+        pb[2] += s[1];
+        pb[3] += s[2];
+        thb += s[3];
+      }
+    }
+  }
+  if (t < nn) {
+    const double ir = rcp64(u[0]);
+    double rb = pb[0], ub[3] = {pb[1], pb[2], pb[3]}, pbar = pb[4], Eb = 0.0;
+    if (VF == VF_KG) {
+      Eb += pb[5] * ir;
+      rb -= pb[5] * me[5] * ir;
+    } else {
+      Eb += pb[5] * ir;
+      pbar += pb[5] * ir;
+      rb -= pb[5] * me[5] * ir;
+    }
+    pbar += thb * ir;
+    rb -= thb * me[6] * ir;
+    const double q2 = me[1] * me[1] + me[2] * me[2] + me[3] * me[3];
+    Eb += gm1 * pbar;
+    rb += gm1 * pbar * 0.5 * q2;
+    double mb[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      mb[j] = -gm1 * pbar * me[1 + j] + ub[j] * ir;
+      rb -= ub[j] * me[1 + j] * ir;
+    }
+    double out[5] = {rb, mb[0], mb[1], mb[2], Eb};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int id = ijk[d];
+      const int a = d == 0 ? ijk[1] + n1 * ijk[2] : (d == 1 ? ijk[0] + n1 * ijk[2] : ijk[0] + n1 * ijk[1]);
+      if (id == N)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) out[v] += sSF[2 * d + 1][v][a];
+      if (id == 0)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) out[v] += sSF[2 * d][v][a];
+    }
+    const size_t o = (size_t)e * 5 * nn + t;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) A.Ubar[o + v * nn] = A.Uacc ? A.Uacc[o + v * nn] + out[v] : out[v];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
@@ -3160,6 +3661,28 @@ hipError_t launch_lift_curved(const StageArgs& A0, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int VF>
+hipError_t launch_vjp_curved_vf(const VjpArgs& A, int eq, hipStream_t s) {
+  const dim3 grid(8 * A.chunk), block(NT);
+  if (eq == 1) hipLaunchKernelGGL((k_vjp_curved<VF, 1>), grid, block, 0, s, A);
+  else hipLaunchKernelGGL((k_vjp_curved<VF, 0>), grid, block, 0, s, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_vjp_curved(const VjpArgs& A, int eq, hipStream_t s) {
+  switch (A.vf) {
+    case VF_KG: return launch_vjp_curved_vf<VF_KG>(A, eq, s);
+    case VF_PI: return launch_vjp_curved_vf<VF_PI>(A, eq, s);
+    case VF_STD: return launch_vjp_curved_vf<VF_STD>(A, eq, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_vjp_lift_curved(const VjpArgs& A, hipStream_t s) {
+  hipLaunchKernelGGL(k_vjp_lift_curved, dim3(8 * A.chunk), dim3(NT), 0, s, A);
+  return hipGetLastError();
+}
+
 hipError_t launch_metrics(const double* X, const double* basis, double* M, int* bad, int nelem, int chunk,
                           hipStream_t s) {
   hipLaunchKernelGGL(k_metrics, dim3(8 * chunk), dim3(NT), 0, s, X, basis, M, bad, nelem, chunk);
@@ -3175,6 +3698,7 @@ const KernelTable kTable = {
     NT, launch_stage, launch_stage_mixed, launch_lift, launch_lift_mixed, launch_alpha1, launch_spread,
     launch_max_rate, launch_integrals, launch_nonfinite, launch_vjp, launch_vjp_lift, launch_vjp_alpha_bar,
     launch_vjp_alpha, launch_vjp_fv, launch_axpby, launch_metrics, launch_stage_curved, launch_lift_curved,
+    launch_vjp_curved, launch_vjp_lift_curved,
 };
 
 }  // namespace

@@ -176,9 +176,7 @@ def test_error_paths(orc, torch_cuda):
         with pytest.raises(dg.DGError) as ei:
             op.set_options(**kw)
         assert ei.value.code == dg.DG_EUNSUPPORTED, kw
-    with pytest.raises(dg.DGError) as ei:
-        op.vjp(U, U.clone())
-    assert ei.value.code == dg.DG_EUNSUPPORTED
+    op.vjp(U, U.clone())  # the reverse mode covers curved meshes
     with pytest.raises(dg.DGError) as ei:
         op.set_cs_field(torch.full((8,), 0.1, dtype=torch.float64, device="cuda"))
     assert ei.value.code == dg.DG_EUNSUPPORTED

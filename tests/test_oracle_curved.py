@@ -344,3 +344,22 @@ def test_inconsistent_connectivity_rejected(orc):
                             I.freestream(N, ne))
     with pytest.raises(ValueError):  # general connectivity needs the node coordinates
         orc.time_derivative(orc.Setup(N=N, nelem=ne, conn=conn), I.freestream(N, ne))
+
+
+@pytest.mark.parametrize("eq,rot", [(0, False), (1, False), (1, True)])
+def test_jvp_on_curved_mesh_matches_central_differences(orc, eq, rot):
+    """The dual-number JVP of the curved operator (the reference of the GPU
+    reverse mode) against central differences."""
+    N, ne = 3, (2, 2, 2)
+    xn = I.warped_coordinates(N, ne, amp=0.05)
+    conn = None
+    if rot:
+        perm, conn = I.rotated_elements(N, ne, seed=4)
+        xn = I.relabel(xn, perm)
+    s = orc.Setup(N=N, nelem=ne, equations=eq, vol_flux=1, surf_flux=1, mu=2e-2, xnodes=xn, conn=conn)
+    U = I.random_smooth(N, ne, seed=8, noise=0.02, xnodes=xn)
+    V = I.random_directions(U.shape, 9)
+    _, JV = orc.jvp(s, U, V)
+    eps = 1e-6
+    fd = (orc.time_derivative(s, U + eps * V) - orc.time_derivative(s, U - eps * V)) / (2 * eps)
+    assert np.max(np.abs(JV - fd)) <= 1e-7 * np.max(np.abs(JV))
