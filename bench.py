@@ -314,9 +314,9 @@ def blended_fraction(torch, op, U0, dt, steps, every=50):
     return out
 
 
-def blended_adjoint_timing(torch, op, U, reps=20):
-    """One reverse-mode product through the blending (coefficient chain, FV
-    subcells, weighted DG) against one operator evaluation, wall time."""
+def adjoint_timing(torch, op, U, reps=20):
+    """One reverse-mode product (through the blending, or on the curved mesh)
+    against one operator evaluation, wall time."""
     lam = torch.ones_like(U)
 
     def wall(fn):
@@ -330,9 +330,10 @@ def blended_adjoint_timing(torch, op, U, reps=20):
 
     t_op = wall(lambda: op.time_derivative(U))
     t_vjp = wall(lambda: op.vjp(U, lam))
-    a = op.alpha(U)
-    return {"operator_ms": t_op * 1e3, "vjp_ms": t_vjp * 1e3, "vjp_over_operator": t_vjp / t_op,
-            "blended_fraction": float((a > 0).double().mean().item())}
+    out = {"operator_ms": t_op * 1e3, "vjp_ms": t_vjp * 1e3, "vjp_over_operator": t_vjp / t_op}
+    if op.options.blending:
+        out["blended_fraction"] = float((op.alpha(U) > 0).double().mean().item())
+    return out
 
 
 def sweep(torch, dg, spec, steps, warmup, repeats):
@@ -430,7 +431,7 @@ def main():
     if blend:
         extra["blended_fraction"] = blended_fraction(torch, op, U_init, dt, args.warmup + args.steps * repeats)
         if not args.no_adjoint:
-            extra["blended_adjoint"] = blended_adjoint_timing(torch, op, U)
+            extra["blended_adjoint"] = adjoint_timing(torch, op, U)
 
     # Mixed-precision operator on the same workload: same initial state, same
     # warm-up and timed steps; error of the final state against the FP64 run.
@@ -457,7 +458,9 @@ def main():
         opm.close()
         del Um
 
-    if not args.no_adjoint:
+    if not args.no_adjoint and name in CURVED:
+        extra["curved_adjoint"] = adjoint_timing(torch, op, U)
+    elif not args.no_adjoint:
         from paper_2306_12891_amd import inputs
         extra["adjoint"] = adjoint_leg(torch, dg, inputs)
 
