@@ -31,7 +31,11 @@
 //     and curvilinear): the split form with metric terms, where the paper
 //     names only the method and its properties; the metric terms, their
 //     averaging in the two-point flux and the BR1 gradient on curved
-//     elements are readings, marked below.
+//     elements are readings, marked below;
+//   * wall-modelled boundaries: Spalding's law of the wall with the van
+//     Driest transformation of the input velocity (Sec. 3, Spalding and van
+//     Driest eqs.); how the model enters the DG boundary (slip-wall
+//     interface states, exchange location, tangential stress) is a reading.
 // Everything the paper leaves open (BR1 lifting, the Kennedy-Gruber and
 // Pirozzoli two-point fluxes, LLF/Roe, the LSERK4 coefficients, the modal
 // energy definition, the sharpness s, the FV reconstruction) follows the
@@ -82,6 +86,12 @@ struct Setup {
   // element e and local face f, conn[e][f] = (neighbour, neighbour's local
   // face, orientation 0..7), or NULL for the structured periodic mesh.
   const int32_t* conn;
+  // Wall-modelled boundaries (Navier-Stokes on the box): the two faces of the
+  // box normal to direction wall_dir are walls (-1: periodic everywhere);
+  // van Driest transformation with freestream velocity wm_uinf and Mach number
+  // wm_mainf (0: Spalding's law on the untransformed velocity).
+  int32_t wall_dir, pad2;
+  double wm_uinf, wm_mainf;
 };
 
 // ---------------------------------------------------------------------------
@@ -260,6 +270,13 @@ static Ctx make_ctx(const Setup& s) {
         c.nbr[6 * e + 3] = id(ex, ey + 1, ez);
         c.nbr[6 * e + 4] = id(ex, ey, ez - 1);
         c.nbr[6 * e + 5] = id(ex, ey, ez + 1);
+        // wall faces have no neighbour
+        const int w = s.wall_dir;
+        const int ew[3] = {ex, ey, ez}, nw[3] = {s.nx, s.ny, s.nz};
+        if (w >= 0 && w < 3) {
+          if (ew[w] == 0) c.nbr[6 * e + 2 * w] = -1;
+          if (ew[w] == nw[w] - 1) c.nbr[6 * e + 2 * w + 1] = -1;
+        }
       }
   if (s.xnodes) {
     curved_metrics(c);
@@ -564,6 +581,117 @@ static void surface_flux_n(int sf, int vf, double g, const double nv[3], const T
 }
 
 // ---------------------------------------------------------------------------
+// Wall-modelled boundaries (paper Sec. 3).
+// Spalding's law of the wall, y+ = g(u+) with
+//   g(u+) = u+ + 0.1108 [e^(0.4 u+) - 1 - 0.4 u+ - (0.4 u+)^2/2! - (0.4 u+)^3/3! - (0.4 u+)^4/4!],
+// solved for the friction velocity u_tau given the velocity u at the exchange
+// distance h.  With x = u+ = u/u_tau and Re_h = h u / nu the law reads
+// x g(x) = Re_h.  Newton's method runs on K(s) = ln x + ln g(x) - ln Re_h in
+// s = ln x: K is increasing and convex (x g'(x)/g(x) grows with x), so from a
+// start right of the root the iterates decrease monotonically to it.  The
+// laminar bound x g(x) >= x^2 puts sqrt(Re_h) right of the root; the start is
+// capped at x = 1700, right of the root for Re_h up to about 1e297, where
+// e^(0.4 x) is still finite.
+// The input velocity is first mapped by the van Driest transformation
+//   u_eq = (u_inf/b) asin(b u / u_inf),  b = sqrt(r / (1 + r)),
+//   r = (gamma-1)/2 Ma_inf^2 Pr^(1/3).
+// reading: the argument of asin is capped at 1.
+// ---------------------------------------------------------------------------
+template <class T>
+static T spalding_g(T up) {
+  const T k = 0.4 * up;
+  return up + 0.1108 * (exp_(k) - 1.0 - k - k * k / 2.0 - k * k * k / 6.0 - k * k * k * k / 24.0);
+}
+template <class T>
+static T spalding_dg(T up) {
+  const T k = 0.4 * up;
+  return 1.0 + 0.1108 * 0.4 * (exp_(k) - 1.0 - k - k * k / 2.0 - k * k * k / 6.0);
+}
+
+// u_tau for velocity u (> 0) at distance h, kinematic viscosity nu.  The root
+// is found in double; one further Newton step on F(u_tau) = g(u/u_tau) -
+// h u_tau / nu, taken in T at the root, carries the derivative of a
+// dual-number input (implicit function theorem).
+template <class T>
+static T friction_velocity(T u, T nu, double h) {
+  const double a = value(u), n = value(nu);
+  const double lre = std::log(h * a / n);
+  double x = std::min(std::exp(0.5 * lre), 1700.0);
+  double sl = std::log(x);
+  for (int it = 0; it < 100; ++it) {
+    const double K = sl + std::log(spalding_g(x)) - lre;
+    const double dK = 1.0 + x * spalding_dg(x) / spalding_g(x);
+    const double step = K / dK;
+    sl -= step;
+    x = std::exp(sl);
+    if (std::fabs(step) <= 1e-15) break;
+  }
+  const double ut = a / x;
+  const double up = x;
+  const double dF = -spalding_dg(up) * up / ut - h / n;
+  const T F = spalding_g(u / T(ut)) - T(h * ut) / nu;
+  return T(ut) - F / dF;
+}
+
+template <class T>
+static T van_driest(T u, double uinf, double mainf, double g, double Pr) {
+  if (!(mainf > 0.0)) return u;
+  const double r = 0.5 * (g - 1.0) * mainf * mainf * std::cbrt(Pr);
+  const double b = std::sqrt(r / (1.0 + r));
+  T arg = (b / uinf) * u;
+  if (value(arg) > 1.0) arg = T(1.0);
+  return (uinf / b) * asin_(arg);
+}
+
+// Mirror state across a wall normal to axis d (normal momentum reversed).
+template <class T>
+static void mirror(int d, const T U[5], T M[5]) {
+  for (int v = 0; v < 5; ++v) M[v] = U[v];
+  M[1 + d] = -U[1 + d];
+}
+
+// Inviscid flux along +d at the wall face node a of element e (plus: the
+// element's + face).  reading: the interface flux with the mirror state (a
+// slip wall), minus side first.
+template <class T>
+static void wall_inviscid_flux(const Ctx& c, const T* U, int e, int d, int a, bool plus, T f[5]) {
+  T u[5], m[5];
+  load_state(c, U, e, face_node(c, d, plus ? c.N : 0, a), u);
+  mirror(d, u, m);
+  if (plus) surface_flux(c.s.surf_flux, c.s.vol_flux, d, c.s.gamma, u, m, f);
+  else surface_flux(c.s.surf_flux, c.s.vol_flux, d, c.s.gamma, m, u, f);
+}
+
+// Viscous flux along +d at the wall face node a of element e.  reading: the
+// exchange location is the element's node at the same tangential position
+// on the opposite face (h_wm = the element size dx_d); the wall-parallel
+// velocity there gives u_tau by Spalding's law (van Driest transformed),
+// tau_w = rho_w u_tau^2 with rho_w and nu = mu / rho_w at the wall node; the
+// flux carries -s tau_w t in the tangential momentum (t the direction of the
+// exchange velocity, s = +1 on the + face) and nothing in mass, normal
+// momentum and energy (adiabatic wall at rest).
+template <class T>
+static void wall_viscous_flux(const Ctx& c, const T* U, int e, int d, int a, bool plus, T F[5]) {
+  for (int v = 0; v < 5; ++v) F[v] = T(0.0);
+  T uw[5], ux[5];
+  load_state(c, U, e, face_node(c, d, plus ? c.N : 0, a), uw);
+  load_state(c, U, e, face_node(c, d, plus ? 0 : c.N, a), ux);
+  const Prim<T> Pw = primitive(uw, c.s.gamma), Px = primitive(ux, c.s.gamma);
+  T up[3];
+  for (int j = 0; j < 3; ++j) up[j] = (j == d) ? T(0.0) : Px.u[j];
+  const T s2 = up[0] * up[0] + up[1] * up[1] + up[2] * up[2];
+  if (!(value(s2) > 0.0)) return;
+  const T sp = sqrt_(s2);
+  const T ueq = van_driest(sp, c.s.wm_uinf, c.s.wm_mainf, c.s.gamma, c.s.Pr);
+  const T nu = c.s.mu / Pw.rho;
+  const T ut = friction_velocity(ueq, nu, c.dx[d]);
+  const T tw = Pw.rho * ut * ut;
+  const double sg = plus ? -1.0 : 1.0;
+  for (int j = 0; j < 3; ++j)
+    if (j != d) F[1 + j] = sg * tw * (up[j] / sp);
+}
+
+// ---------------------------------------------------------------------------
 // Pass 1: surface fluxes on every element's + faces: fstar[e][d][v][a].
 // The minus side is element e at normal index N, the plus side nbr[e][+d]
 // at normal index 0 (identity orientation, periodic wrap).
@@ -577,9 +705,13 @@ static void surface_pass(const Ctx& c, const T* U, std::vector<T>& fstar) {
       const int nb = c.nbr[6 * e + 2 * d + 1];
       for (int a = 0; a < c.nf; ++a) {
         T L[5], R[5], f[5];
-        load_state(c, U, e, face_node(c, d, c.N, a), L);
-        load_state(c, U, nb, face_node(c, d, 0, a), R);
-        surface_flux(c.s.surf_flux, c.s.vol_flux, d, c.s.gamma, L, R, f);
+        if (nb < 0) {
+          wall_inviscid_flux(c, U, e, d, a, true, f);
+        } else {
+          load_state(c, U, e, face_node(c, d, c.N, a), L);
+          load_state(c, U, nb, face_node(c, d, 0, a), R);
+          surface_flux(c.s.surf_flux, c.s.vol_flux, d, c.s.gamma, L, R, f);
+        }
         for (int v = 0; v < 5; ++v) fstar[((size_t(e) * 3 + d) * 5 + v) * c.nf + a] = f[v];
       }
     }
@@ -613,7 +745,10 @@ static void advective_dg(const Ctx& c, const T* U, const std::vector<T>& fstar, 
           for (int v = 0; v < 5; ++v) sum[v] += (1.0 / b.w[c.N]) * fstar[((size_t(e) * 3 + d) * 5 + v) * c.nf + a];
         if (i == 0) {
           const int em = c.nbr[6 * e + 2 * d];
-          for (int v = 0; v < 5; ++v) sum[v] -= (1.0 / b.w[0]) * fstar[((size_t(em) * 3 + d) * 5 + v) * c.nf + a];
+          T fw[5];
+          if (em < 0) wall_inviscid_flux(c, U, e, d, a, false, fw);
+          for (int v = 0; v < 5; ++v)
+            sum[v] -= (1.0 / b.w[0]) * (em < 0 ? fw[v] : fstar[((size_t(em) * 3 + d) * 5 + v) * c.nf + a]);
         }
         for (int v = 0; v < 5; ++v) acc[v] -= c.invJ[d] * sum[v];
       }
@@ -648,17 +783,25 @@ static void br1_gradient(const Ctx& c, const T* U, std::vector<T>& grad) {
       lifted(u, g, qq);
       for (int k = 0; k < 4; ++k) q[(size_t(e) * 4 + k) * c.nn + n] = qq[k];
     }
-  // interface values on + faces: qs[e][d][k][a] = (q_e(i_d = N) + q_nbr(i_d = 0)) / 2
-  std::vector<T> qs(size_t(c.nelem) * 3 * 4 * c.nf);
+  // interface values on + faces: qs[e][d][k][a] = (q_e(i_d = N) + q_nbr(i_d = 0)) / 2;
+  // at a wall the other side is the mirror state (normal velocity reversed).
+  // qw[e][d][k][a]: the same at - faces that are walls.
+  std::vector<T> qs(size_t(c.nelem) * 3 * 4 * c.nf), qw(size_t(c.nelem) * 3 * 4 * c.nf);
 #pragma omp parallel for schedule(static)
   for (int e = 0; e < c.nelem; ++e)
     for (int d = 0; d < 3; ++d) {
-      const int nb = c.nbr[6 * e + 2 * d + 1];
+      const int nb = c.nbr[6 * e + 2 * d + 1], em = c.nbr[6 * e + 2 * d];
       for (int k = 0; k < 4; ++k)
-        for (int a = 0; a < c.nf; ++a)
+        for (int a = 0; a < c.nf; ++a) {
+          const T qo = q[(size_t(e) * 4 + k) * c.nn + face_node(c, d, c.N, a)];
+          const T qm = (k == d) ? -qo : qo;
           qs[((size_t(e) * 3 + d) * 4 + k) * c.nf + a] =
-              0.5 * (q[(size_t(e) * 4 + k) * c.nn + face_node(c, d, c.N, a)] +
-                     q[(size_t(nb) * 4 + k) * c.nn + face_node(c, d, 0, a)]);
+              nb < 0 ? 0.5 * (qo + qm) : 0.5 * (qo + q[(size_t(nb) * 4 + k) * c.nn + face_node(c, d, 0, a)]);
+          if (em < 0) {
+            const T q0 = q[(size_t(e) * 4 + k) * c.nn + face_node(c, d, 0, a)];
+            qw[((size_t(e) * 3 + d) * 4 + k) * c.nf + a] = 0.5 * (((k == d) ? -q0 : q0) + q0);
+          }
+        }
     }
   grad.assign(size_t(c.nelem) * 3 * 4 * c.nn, T(0.0));
 #pragma omp parallel for schedule(static)
@@ -676,7 +819,9 @@ static void br1_gradient(const Ctx& c, const T* U, std::vector<T>& grad) {
           if (i == c.N) s += (1.0 / b.w[c.N]) * (qs[((size_t(e) * 3 + d) * 4 + k) * c.nf + a] - qe[n]);
           if (i == 0) {
             const int em = c.nbr[6 * e + 2 * d];
-            s -= (1.0 / b.w[0]) * (qs[((size_t(em) * 3 + d) * 4 + k) * c.nf + a] - qe[n]);
+            const T qstar = em < 0 ? qw[((size_t(e) * 3 + d) * 4 + k) * c.nf + a]
+                                   : qs[((size_t(em) * 3 + d) * 4 + k) * c.nf + a];
+            s -= (1.0 / b.w[0]) * (qstar - qe[n]);
           }
           grad[((size_t(e) * 3 + d) * 4 + k) * c.nn + n] = c.invJ[d] * s;
         }
@@ -739,17 +884,25 @@ static void viscous_dg(const Ctx& c, const T* U, T* Ut) {
         for (int v = 0; v < 5; ++v) Fv[((size_t(e) * 3 + d) * 5 + v) * c.nn + n] = F[v];
       }
     }
-  // interface viscous flux on + faces: mean of both sides
-  std::vector<T> Fs(size_t(c.nelem) * 3 * 5 * c.nf);
+  // interface viscous flux on + faces: mean of both sides; at walls the wall
+  // model's flux (Fw: the same at - faces that are walls)
+  std::vector<T> Fs(size_t(c.nelem) * 3 * 5 * c.nf), Fw(size_t(c.nelem) * 3 * 5 * c.nf);
 #pragma omp parallel for schedule(static)
   for (int e = 0; e < c.nelem; ++e)
     for (int d = 0; d < 3; ++d) {
-      const int nb = c.nbr[6 * e + 2 * d + 1];
-      for (int v = 0; v < 5; ++v)
-        for (int a = 0; a < c.nf; ++a)
+      const int nb = c.nbr[6 * e + 2 * d + 1], em = c.nbr[6 * e + 2 * d];
+      for (int a = 0; a < c.nf; ++a) {
+        T fp[5], fm[5];
+        if (nb < 0) wall_viscous_flux(c, U, e, d, a, true, fp);
+        if (em < 0) wall_viscous_flux(c, U, e, d, a, false, fm);
+        for (int v = 0; v < 5; ++v) {
           Fs[((size_t(e) * 3 + d) * 5 + v) * c.nf + a] =
-              0.5 * (Fv[((size_t(e) * 3 + d) * 5 + v) * c.nn + face_node(c, d, c.N, a)] +
-                     Fv[((size_t(nb) * 3 + d) * 5 + v) * c.nn + face_node(c, d, 0, a)]);
+              nb < 0 ? fp[v]
+                     : 0.5 * (Fv[((size_t(e) * 3 + d) * 5 + v) * c.nn + face_node(c, d, c.N, a)] +
+                              Fv[((size_t(nb) * 3 + d) * 5 + v) * c.nn + face_node(c, d, 0, a)]);
+          if (em < 0) Fw[((size_t(e) * 3 + d) * 5 + v) * c.nf + a] = fm[v];
+        }
+      }
     }
 #pragma omp parallel for schedule(static)
   for (int e = 0; e < c.nelem; ++e)
@@ -766,7 +919,9 @@ static void viscous_dg(const Ctx& c, const T* U, T* Ut) {
           if (i == c.N) s += (1.0 / b.w[c.N]) * (Fs[((size_t(e) * 3 + d) * 5 + v) * c.nf + a] - F[n]);
           if (i == 0) {
             const int em = c.nbr[6 * e + 2 * d];
-            s -= (1.0 / b.w[0]) * (Fs[((size_t(em) * 3 + d) * 5 + v) * c.nf + a] - F[n]);
+            const T fs = em < 0 ? Fw[((size_t(e) * 3 + d) * 5 + v) * c.nf + a]
+                                : Fs[((size_t(em) * 3 + d) * 5 + v) * c.nf + a];
+            s -= (1.0 / b.w[0]) * (fs - F[n]);
           }
           Ut[(size_t(e) * 5 + v) * c.nn + n] += c.invJ[d] * s;
         }
@@ -1586,6 +1741,9 @@ static bool valid(const Setup* s) {
   // the eddy viscosity
   if (s->xnodes && (s->blending || s->Cs > 0.0 || s->cs_elem)) return false;
   if (s->conn && !s->xnodes) return false;
+  // walls: Navier-Stokes on the box, no blending (the spread needs neighbours)
+  if (s->wall_dir >= 0 && (s->wall_dir > 2 || s->equations != EQ_NS || s->blending || s->xnodes)) return false;
+  if (s->wall_dir >= 0 && s->wm_mainf > 0.0 && !(s->wm_uinf > 0.0)) return false;
   if (s->conn) {  // every face pair must point back at itself with the inverse orientation
     const int ne = s->nx * s->ny * s->nz, n1 = s->N + 1;
     for (int e = 0; e < ne; ++e)
@@ -1675,7 +1833,7 @@ int or_time_derivative(const Setup* s, const double* U, double* Ut, const double
 
 // Operator (no blending) for the elements elems[0..nsel-1] only: Ut_sel[s][5][nn].
 int or_time_derivative_elems(const Setup* s, const double* U, const int32_t* elems, int nsel, double* Ut_sel) {
-  if (!valid(s) || s->blending || s->xnodes) return -1;
+  if (!valid(s) || s->blending || s->xnodes || s->wall_dir >= 0) return -1;
   const Ctx c = make_ctx(*s);
   for (int k = 0; k < nsel; ++k)
     if (elems[k] < 0 || elems[k] >= c.nelem) return -1;
@@ -1684,7 +1842,7 @@ int or_time_derivative_elems(const Setup* s, const double* U, const int32_t* ele
 }
 
 int or_dense_time_derivative(const Setup* s, const double* U, double* Ut) {
-  if (!valid(s) || s->blending || s->xnodes) return -1;
+  if (!valid(s) || s->blending || s->xnodes || s->wall_dir >= 0) return -1;
   const Ctx c = make_ctx(*s);
   dense_time_derivative(c, U, Ut);
   return 0;
@@ -1692,7 +1850,7 @@ int or_dense_time_derivative(const Setup* s, const double* U, double* Ut) {
 
 // Indicator E, clipped a1 (before spread) and final alpha, per element.
 int or_alpha(const Setup* s, const double* U, double* E, double* a1, double* alpha) {
-  if (!valid(s) || s->N < 2) return -1;
+  if (!valid(s) || s->N < 2 || s->wall_dir >= 0) return -1;
   const Ctx c = make_ctx(*s);
   std::vector<double> Ev, a1v, al;
   indicator_pass(c, U, Ev, a1v);
@@ -1796,6 +1954,15 @@ int or_surface_flux_n(const Setup* s, const double* nv, const double* L, const d
   surface_flux_n(s->surf_flux, s->vol_flux, s->gamma, nv, L, R, f);
   return 0;
 }
+
+// Friction velocity of the wall model for velocity u at distance h
+// (kinematic viscosity nu), with the van Driest transformation of the setup.
+double or_wall_friction_velocity(const Setup* s, double u, double nu, double h) {
+  const double ueq = van_driest(u, s->wm_uinf, s->wm_mainf, s->gamma, s->Pr);
+  return friction_velocity(ueq, nu, h);
+}
+
+double or_spalding(double up) { return spalding_g(up); }
 
 void or_rk_coefficients(double* A, double* B) {
   for (int k = 0; k < 5; ++k) { A[k] = kRK_A[k]; B[k] = kRK_B[k]; }

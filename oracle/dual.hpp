@@ -59,6 +59,9 @@ inline Dual exp_(Dual x) {
 inline double log_(double x) { return std::log(x); }
 inline Dual log_(Dual x) { return Dual(std::log(x.v), x.d / x.v); }
 
+inline double asin_(double x) { return std::asin(x); }
+inline Dual asin_(Dual x) { return Dual(std::asin(x.v), x.d / std::sqrt(1.0 - x.v * x.v)); }
+
 inline double abs_(double x) { return std::fabs(x); }
 inline Dual abs_(Dual x) {
   if (x.v > 0.0) return x;

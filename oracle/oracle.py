@@ -47,7 +47,9 @@ class _Setup(ctypes.Structure):
                 ("gamma", ctypes.c_double), ("mu", ctypes.c_double), ("Pr", ctypes.c_double),
                 ("alpha_min", ctypes.c_double), ("alpha_max", ctypes.c_double),
                 ("alpha_spread", ctypes.c_double), ("Cs", ctypes.c_double), ("Prt", ctypes.c_double),
-                ("cs_elem", ctypes.c_void_p), ("xnodes", ctypes.c_void_p), ("conn", ctypes.c_void_p)]
+                ("cs_elem", ctypes.c_void_p), ("xnodes", ctypes.c_void_p), ("conn", ctypes.c_void_p),
+                ("wall_dir", ctypes.c_int32), ("pad2", ctypes.c_int32), ("wm_uinf", ctypes.c_double),
+                ("wm_mainf", ctypes.c_double)]
 
 
 @dataclass
@@ -73,6 +75,9 @@ class Setup:
     cs_elem: object = None   # optional per-element coefficients (numpy, n_elems)
     xnodes: object = None    # curved mesh: node coordinates (n_elems, 3, N+1, N+1, N+1), x index fastest
     conn: object = None      # curved mesh, general connectivity: int32 (n_elems, 6, 3) (neighbour, face, orientation)
+    wall_dir: int = -1       # wall-modelled boundaries normal to this direction (-1: periodic)
+    wm_uinf: float = 1.0     # van Driest freestream velocity
+    wm_mainf: float = 0.0    # van Driest freestream Mach number (0: untransformed Spalding)
     _c: object = field(default=None, repr=False, compare=False)
     _keep: object = field(default=None, repr=False, compare=False)
     _keepx: object = field(default=None, repr=False, compare=False)
@@ -103,6 +108,7 @@ class Setup:
         s.gamma, s.mu, s.Pr = self.gamma, self.mu, self.Pr
         s.alpha_min, s.alpha_max, s.alpha_spread = self.alpha_min, self.alpha_max, self.alpha_spread
         s.Cs, s.Prt = self.Cs, self.Prt
+        s.wall_dir, s.wm_uinf, s.wm_mainf = self.wall_dir, self.wm_uinf, self.wm_mainf
         if self.cs_elem is not None:
             self._keep = np.ascontiguousarray(self.cs_elem, dtype=np.float64)
             assert self._keep.shape == (self.n_elems,)
@@ -157,6 +163,8 @@ def lib() -> ctypes.CDLL:
             ("or_rk_coefficients", [P, P], None),
             ("or_metrics", [P, P, P], ctypes.c_int),
             ("or_surface_flux_n", [P, P, P, P, P], ctypes.c_int),
+            ("or_wall_friction_velocity", [P, ctypes.c_double, ctypes.c_double, ctypes.c_double], ctypes.c_double),
+            ("or_spalding", [ctypes.c_double], ctypes.c_double),
         ]:
             fn = getattr(L, name)
             fn.argtypes = args
@@ -331,3 +339,13 @@ def surface_flux_n(s: Setup, nv, L, R):
     f = np.zeros(5)
     lib().or_surface_flux_n(_ref(s), _p(_f64(nv)), _p(_f64(L)), _p(_f64(R)), _p(f))
     return f
+
+
+def wall_friction_velocity(s: Setup, u: float, nu: float, h: float) -> float:
+    """Friction velocity of the wall model (Spalding, van Driest per the setup)."""
+    return lib().or_wall_friction_velocity(_ref(s), float(u), float(nu), float(h))
+
+
+def spalding(up: float) -> float:
+    """y+ of Spalding's law at u+."""
+    return lib().or_spalding(float(up))
