@@ -175,6 +175,32 @@ int dg_set_geometry(dg_ctx* ctx, const double* X);
  * each other (nothing is changed then); DG_ENOMEM. */
 int dg_set_connectivity(dg_ctx* ctx, const int32_t* conn);
 
+/* Wall-modelled boundaries (paper Sec. 3): the two faces of the box normal to
+ * direction wall_dir (0 x, 1 y, 2 z) become walls, the other directions stay
+ * periodic; wall_dir = -1 restores the periodic box.  At a wall the advective
+ * flux and the BR1 interface value take the mirror image of the own face state
+ * (normal momentum reversed) as the other side.  The viscous flux through the
+ * wall is the wall model's: the wall-parallel velocity u of the element's node
+ * on the opposite face (the exchange location, h = the element size along
+ * wall_dir) gives the friction velocity u_tau by Spalding's law of the wall
+ *   y+ = u+ + 0.1108 [e^(0.4 u+) - 1 - 0.4 u+ - (0.4 u+)^2/2 - (0.4 u+)^3/6
+ *        - (0.4 u+)^4/24],  y+ = h u_tau / nu,  u+ = u / u_tau,
+ * nu = mu / rho at the wall node, solved by Newton's method to full precision;
+ * with ma_inf > 0 u is first van Driest transformed,
+ *   u_eq = (u_inf / b) asin(min(b u / u_inf, 1)),  b = sqrt(r / (1 + r)),
+ *   r = (gamma - 1)/2 ma_inf^2 Pr^(1/3).
+ * The wall shear stress rho u_tau^2 acts against that velocity in the
+ * tangential momentum; mass, normal momentum and energy see no flux through
+ * the wall (adiabatic wall at rest).  Needs the FP64 Navier-Stokes operator
+ * (also with the Smagorinsky model), mu > 0, no blending, the Cartesian box;
+ * while walls are set, dg_set_options, dg_set_geometry and dg_set_connectivity
+ * calls that would break this return DG_EUNSUPPORTED, and dg_vjp /
+ * rk_step_vjp return DG_EUNSUPPORTED.
+ * Errors (nothing is changed then): DG_EINVAL for wall_dir outside -1..2,
+ * ma_inf < 0 or non-finite, or ma_inf > 0 with u_inf <= 0; DG_EUNSUPPORTED as
+ * above; DG_ENOMEM. */
+int dg_set_wall_model(dg_ctx* ctx, int wall_dir, double u_inf, double ma_inf);
+
 /* Sets the HIP stream (hipStream_t) all later calls enqueue on; NULL = null
  * stream. */
 int dg_set_stream(dg_ctx* ctx, void* hip_stream);

@@ -179,6 +179,8 @@ struct dg_ctx {
   double* M = nullptr;         // curved mesh metrics [nelem][10][nn] (dg_set_geometry), NULL: box
   int* d_bad = nullptr;        // count of invalid Jacobians (dg_set_geometry)
   int32_t* conn = nullptr;     // general connectivity [nelem][6][3] (dg_set_connectivity), NULL: structured
+  int wall_dir = -1;           // wall-modelled faces normal to this direction (dg_set_wall_model), -1: none
+  double wm_uinf = 1.0, wm_mainf = 0.0;
   double* partial = nullptr;
   double* h_partial = nullptr;
   // reverse mode (allocated on first use): stage states Y_0..Y_4, the
@@ -275,6 +277,14 @@ StageArgs stage_args(const dg_ctx* c) {
   a.M = c->M;
   a.conn = c->conn;
   a.cs = c->opt.Cs;
+  a.wall_dir = c->wall_dir;
+  if (c->wall_dir >= 0) {
+    a.wm_h = c->dx[c->wall_dir];
+    a.wm_uinf = c->wm_uinf;
+    // van Driest: b = sqrt(r / (1 + r)), r = (gamma - 1)/2 Ma^2 Pr^(1/3)
+    const double r = 0.5 * (c->gamma - 1.0) * c->wm_mainf * c->wm_mainf * std::cbrt(c->opt.Pr);
+    a.wm_b = c->wm_mainf > 0.0 ? std::sqrt(r / (1.0 + r)) : 0.0;
+  }
   const double delta = std::cbrt(c->dx[0] * c->dx[1] * c->dx[2]) / (c->N + 1.0);
   a.delta2 = delta * delta;
   a.ktf = c->gamma / ((c->gamma - 1.0) * c->opt.Prt);
@@ -354,6 +364,8 @@ int run_stage(dg_ctx* c, const double* Xin, double* Xout, double* Ut, int mode, 
   const int eq = eq_code(c);
   if (c->conn && !c->M)
     return fail(c, DG_ESTATE, "general connectivity needs curved elements: call dg_set_geometry first");
+  if (c->wall_dir >= 0 && (eq == 0 || c->opt.blending || c->opt.precision != DG_FP64 || c->M))
+    return fail(c, DG_ESTATE, "wall-modelled boundaries need the FP64 Navier-Stokes operator on the box");
   if (c->M) {  // curved mesh (FP64, no blending or eddy viscosity: checked when set)
     if (eq >= 1) {
       e = timed(c, DG_K_LIFT, [&] { return c->kt->lift_curved(a, c->stream); });
@@ -387,9 +399,20 @@ int curved_compatible(dg_ctx* c, const dg_options* o, int cs_field, const char* 
   return DG_OK;
 }
 
+// Options wall-modelled boundaries support: the FP64 Navier-Stokes operator
+// (with or without eddy viscosity), no blending, on the Cartesian box.
+int wall_compatible(dg_ctx* c, const dg_options* o, const char* where) {
+  if (o->equations != DG_NS) return fail(c, DG_EUNSUPPORTED, "%s: walls need the Navier-Stokes equations", where);
+  if (o->blending) return fail(c, DG_EUNSUPPORTED, "%s: no blending with walls", where);
+  if (o->precision != DG_FP64) return fail(c, DG_EUNSUPPORTED, "%s: walls use the FP64 operator", where);
+  if (c->M || c->conn) return fail(c, DG_EUNSUPPORTED, "%s: walls are built for the Cartesian box", where);
+  return DG_OK;
+}
+
 int vjp_supported(dg_ctx* c) {
   if (c->conn && !c->M)
     return fail(c, DG_ESTATE, "general connectivity needs curved elements: call dg_set_geometry first");
+  if (c->wall_dir >= 0) return fail(c, DG_EUNSUPPORTED, "vjp: not available with wall-modelled boundaries");
   if (eq_code(c) == 2) return fail(c, DG_EUNSUPPORTED, "vjp: not available with the Smagorinsky model");
   if (c->opt.precision != DG_FP64) return fail(c, DG_EUNSUPPORTED, "vjp: FP64 operator only");
   if (c->opt.vol_flux == DG_VF_CH) return fail(c, DG_EUNSUPPORTED, "vjp: not available for the CH flux");
@@ -497,6 +520,45 @@ std::vector<int32_t> structured_nbr(const dg_ctx* c) {
         nbr[6 * e + 5] = ex + nx * (ey + ny * ((ez + 1) % nz));
       }
   return nbr;
+}
+
+// Neighbour table of the box: periodic, with -1 on the wall faces normal to
+// the context's wall direction.
+std::vector<int32_t> box_nbr(const dg_ctx* c, int wall_dir) {
+  std::vector<int32_t> nbr = structured_nbr(c);
+  if (wall_dir < 0) return nbr;
+  const int nx = c->ne[0], ny = c->ne[1];
+  for (size_t e = 0; e < (size_t)c->nelem; ++e) {
+    const int ix[3] = {(int)(e % nx), (int)((e / nx) % ny), (int)(e / ((size_t)nx * ny))};
+    if (ix[wall_dir] == 0) nbr[6 * e + 2 * wall_dir] = -1;
+    if (ix[wall_dir] == c->ne[wall_dir] - 1) nbr[6 * e + 2 * wall_dir + 1] = -1;
+  }
+  return nbr;
+}
+
+// New device neighbour table (and connectivity) filled on the context's
+// stream behind its queued work, swapped in only when complete, so that a
+// failure leaves the context unchanged.
+int swap_tables(dg_ctx* c, const std::vector<int32_t>& nbr, const int32_t* conn, const char* where) {
+  int32_t *dnbr = nullptr, *dconn = nullptr;
+  const size_t cbytes = (size_t)c->nelem * 18 * sizeof(int32_t);
+  hipError_t e = hipMalloc((void**)&dnbr, nbr.size() * sizeof(int32_t));
+  if (e == hipSuccess && conn) e = hipMalloc((void**)&dconn, cbytes);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dnbr, nbr.data(), nbr.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess && conn) e = hipMemcpyAsync(dconn, conn, cbytes, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);  // the host arrays are the caller's
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    hipFree(dnbr);
+    hipFree(dconn);
+    return fail(c, (e == hipErrorOutOfMemory) ? DG_ENOMEM : DG_EHIP, "%s: %s", where, hipGetErrorString(e));
+  }
+  hipFree(c->nbr);
+  c->nbr = dnbr;
+  hipFree(c->conn);
+  c->conn = dconn;
+  return DG_OK;
 }
 
 // Face-local index a mapped by orientation code o (bit 0 swap, bit 1 reverse
@@ -639,6 +701,10 @@ int dg_set_options(dg_ctx* c, const dg_options* o) {
     const int rc = curved_compatible(c, o, c->has_cs_field, "dg_set_options");
     if (rc) return rc;
   }
+  if (c->wall_dir >= 0) {
+    const int rc = wall_compatible(c, o, "dg_set_options");
+    if (rc) return rc;
+  }
   c->opt = *o;
   return DG_OK;
 }
@@ -647,10 +713,10 @@ int dg_set_connectivity(dg_ctx* c, const int32_t* conn) {
   if (check_ctx(c)) return DG_EINVAL;
   std::vector<int32_t> nbr;
   if (!conn) {
-    hipFree(c->conn);
-    c->conn = nullptr;
-    nbr = structured_nbr(c);
+    nbr = box_nbr(c, c->wall_dir);
   } else {
+    if (c->wall_dir >= 0)
+      return fail(c, DG_EUNSUPPORTED, "dg_set_connectivity: walls are built for the Cartesian box");
     // every face must name an existing neighbour face that names it back,
     // with the inverse orientation
     const int ne = c->nelem;
@@ -670,28 +736,30 @@ int dg_set_connectivity(dg_ctx* c, const int32_t* conn) {
     nbr.resize((size_t)ne * 6);
     for (size_t k = 0; k < nbr.size(); ++k) nbr[k] = conn[3 * k];
   }
-  // New device tables (the neighbour table, used by the indicator spread and
-  // the structured kernels, follows the connectivity), filled on the
-  // context's stream behind its queued work and swapped in only when complete,
-  // so a failure leaves the context unchanged.
-  int32_t *dnbr = nullptr, *dconn = nullptr;
-  const size_t cbytes = (size_t)c->nelem * 18 * sizeof(int32_t);
-  hipError_t e = hipMalloc((void**)&dnbr, nbr.size() * sizeof(int32_t));
-  if (e == hipSuccess && conn) e = hipMalloc((void**)&dconn, cbytes);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(dnbr, nbr.data(), nbr.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream);
-  if (e == hipSuccess && conn) e = hipMemcpyAsync(dconn, conn, cbytes, hipMemcpyHostToDevice, c->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);  // the host arrays are the caller's
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    hipFree(dnbr);
-    hipFree(dconn);
-    return fail(c, (e == hipErrorOutOfMemory) ? DG_ENOMEM : DG_EHIP, "dg_set_connectivity: %s", hipGetErrorString(e));
+  // the neighbour table (used by the indicator spread and the structured
+  // kernels) follows the connectivity
+  return swap_tables(c, nbr, conn, "dg_set_connectivity");
+}
+
+int dg_set_wall_model(dg_ctx* c, int wall_dir, double u_inf, double ma_inf) {
+  if (check_ctx(c)) return DG_EINVAL;
+  if (wall_dir < -1 || wall_dir > 2) return fail(c, DG_EINVAL, "dg_set_wall_model: wall_dir must be -1, 0, 1 or 2");
+  if (wall_dir >= 0) {
+    if (!(ma_inf >= 0.0) || !std::isfinite(ma_inf))
+      return fail(c, DG_EINVAL, "dg_set_wall_model: need a finite ma_inf >= 0");
+    if (ma_inf > 0.0 && !finite_pos(u_inf))
+      return fail(c, DG_EINVAL, "dg_set_wall_model: the van Driest transformation needs u_inf > 0");
+    if (!(c->mu > 0.0)) return fail(c, DG_EUNSUPPORTED, "dg_set_wall_model: the wall model needs mu > 0");
+    const int rc = wall_compatible(c, &c->opt, "dg_set_wall_model");
+    if (rc) return rc;
+  } else if (c->wall_dir < 0) {
+    return DG_OK;  // no walls to remove (and any general connectivity stays)
   }
-  hipFree(c->nbr);
-  c->nbr = dnbr;
-  hipFree(c->conn);
-  c->conn = dconn;
+  const int rc = swap_tables(c, box_nbr(c, wall_dir), nullptr, "dg_set_wall_model");
+  if (rc) return rc;
+  c->wall_dir = wall_dir;
+  c->wm_uinf = wall_dir >= 0 && ma_inf > 0.0 ? u_inf : 1.0;
+  c->wm_mainf = wall_dir >= 0 ? ma_inf : 0.0;
   return DG_OK;
 }
 
@@ -703,6 +771,7 @@ int dg_set_geometry(dg_ctx* c, const double* X) {
     return DG_OK;
   }
   if (!is_device_ptr(X)) return fail(c, DG_EINVAL, "dg_set_geometry: X must be a device pointer");
+  if (c->wall_dir >= 0) return fail(c, DG_EUNSUPPORTED, "dg_set_geometry: walls are built for the Cartesian box");
   const int rc = curved_compatible(c, &c->opt, c->has_cs_field, "dg_set_geometry");
   if (rc) return rc;
   // metric terms into a new array, swapped in only when complete and valid:

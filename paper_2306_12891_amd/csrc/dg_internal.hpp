@@ -53,6 +53,12 @@ struct StageArgs {
   // curved mesh with general connectivity: conn[e][f] = (neighbour, its local
   // face, orientation 0..7), validated on the host; NULL: structured (nbr)
   const int32_t* conn;
+  // wall-modelled boundaries on the two box faces normal to wall_dir (-1:
+  // none; those faces have neighbour -1 in nbr): exchange distance wm_h (the
+  // element size along wall_dir), van Driest freestream velocity wm_uinf and
+  // factor wm_b (0: the untransformed law)
+  int wall_dir;
+  double wm_h, wm_uinf, wm_b;
 };
 
 struct ReduceArgs {

@@ -693,6 +693,89 @@ __device__ __forceinline__ void face_loads(const double* U, int e, const FaceIte
   load_rotated(U + (size_t)eR * 5 * nn, nR, it, R);
 }
 
+// ---------------------------------------------------------------------------
+// Wall-modelled boundaries (paper Sec. 3).  A face without neighbour (nbr -1)
+// is a wall.  Its advective flux and its BR1 interface value take the mirror
+// image of the own face state (normal momentum reversed) as the other side; its
+// viscous flux comes from the wall model: Spalding's law of the wall
+//   y+ = u+ + c [e^(k u+) - 1 - (k u+) - (k u+)^2/2 - (k u+)^3/6 - (k u+)^4/24],
+//   k = 0.4, c = 0.1108,
+// solved for the friction velocity with the wall-parallel velocity of the
+// element's node on the opposite face (distance h = the element size) as input,
+// optionally van Driest transformed first.  The shear stress rho_w u_tau^2
+// acts against that velocity; mass, normal momentum and energy see no flux.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wm_bracket(double k, double ek) {
+  // e^k minus its Taylor polynomial of degree four
+  return ek - (1.0 + k * (1.0 + k * (0.5 + k * (1.0 / 6.0 + k * (1.0 / 24.0)))));
+}
+
+// u_tau for wall-parallel speed u > 0 at distance h, kinematic viscosity nu.
+// With x = u / u_tau the law reads x y+(x) = Re_h = h u / nu.  Newton's method
+// in s = ln x on ln(x y+(x)) - ln(Re_h), which is increasing and convex in s,
+// converges monotonically from any start right of the root; x = sqrt(Re_h)
+// is one (y+(x) >= x), capped at 1700 where e^(0.4 x) is still finite.  A
+// final Newton step on y+(u/u_tau) - h u_tau / nu polishes the root.
+__device__ double wm_friction_velocity(double u, double nu, double h) {
+  const double lre = log(h * u / nu);
+  double s = fmin(0.5 * lre, log(1700.0));
+  double x = exp(s);
+  for (int it = 0; it < 100; ++it) {
+    const double k = 0.4 * x, ek = exp(k);
+    const double y = x + 0.1108 * wm_bracket(k, ek);
+    const double dy = 1.0 + 0.1108 * 0.4 * (ek - (1.0 + k * (1.0 + k * (0.5 + k * (1.0 / 6.0)))));
+    const double step = (s + log(y) - lre) / (1.0 + x * dy / y);
+    s -= step;
+    x = exp(s);
+    if (fabs(step) <= 1e-15) break;
+  }
+  const double ut = u / x;
+  const double k = 0.4 * x, ek = exp(k);
+  const double y = x + 0.1108 * wm_bracket(k, ek);
+  const double dy = 1.0 + 0.1108 * 0.4 * (ek - (1.0 + k * (1.0 + k * (0.5 + k * (1.0 / 6.0)))));
+  const double F = y - h * ut / nu;
+  const double dF = -dy * x / ut - h / nu;
+  return ut - F / dF;
+}
+
+// Wall-model viscous flux of a wall face item along +d in the rotated frame
+// (normal, t1, t2, energy): rhow = density at the wall node, (rx, mt1, mt2) =
+// density and tangential momenta of the exchange node, sg = -1 on the
+// element's + face.
+__device__ __forceinline__ void wall_model_flux(const StageArgs& A, double rhow, double rx, double mt1, double mt2,
+                                                double sg, double g[4]) {
+  g[0] = g[1] = g[2] = g[3] = 0.0;
+  const double ir = 1.0 / rx;
+  const double v1 = mt1 * ir, v2 = mt2 * ir;
+  const double sp2 = v1 * v1 + v2 * v2;
+  if (!(sp2 > 0.0)) return;
+  const double sp = sqrt(sp2);
+  double ueq = sp;
+  if (A.wm_b > 0.0) ueq = (A.wm_uinf / A.wm_b) * asin(fmin(A.wm_b * sp / A.wm_uinf, 1.0));
+  const double ut = wm_friction_velocity(ueq, A.mu / rhow, A.wm_h);
+  const double c = sg * rhow * ut * ut / sp;
+  g[1] = c * v1;
+  g[2] = c * v2;
+}
+
+// Face item without neighbour: the own face node (minus side if it lies on the
+// element's + face) and its mirror image.
+__device__ __forceinline__ void wall_face_loads(const double* U, int e, const FaceItem& it, double L[5],
+                                                double R[5]) {
+  double X[5];
+  load_rotated(U + (size_t)e * 5 * nn, it.nown, it, X);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) L[v] = R[v] = X[v];
+  if (it.side) R[1] = -X[1];
+  else L[1] = -X[1];
+}
+
+template <bool WALL>
+__device__ __forceinline__ void face_loads_w(const double* U, int e, const FaceItem& it, double L[5], double R[5]) {
+  if (WALL && it.nb < 0) wall_face_loads(U, e, it, L, R);
+  else face_loads(U, e, it, L, R);
+}
+
 // Elements per workgroup (EPB) of the stage and lifting kernels.  With one
 // element per workgroup, N = 5 fills 216 of 256 lanes (the last wave is 3/8
 // full) and a wave instruction costs the same whatever its active lanes; two
@@ -742,16 +825,27 @@ __device__ __forceinline__ Slot slot_of_thread(int e0, int nelem) {
 
 // Loads of one face item, issued together before any of them is used: both
 // rotated states and (Navier-Stokes) the neighbour's normal viscous flux.
-template <bool NS, class R>
+// At a wall (WALL variant, neighbour -1) fn holds the exchange node's density
+// and tangential momenta instead.
+template <bool NS, class R, bool WALL = false>
 struct FaceData {
   FaceItem it;
   double L[5], R_[5];
   R fn[4];
 };
 
-template <bool NS, class R>
-__device__ __forceinline__ void face_issue(const StageArgs& A, int e, FaceData<NS, R>& fd) {
+template <bool NS, class R, bool WALL = false>
+__device__ __forceinline__ void face_issue(const StageArgs& A, int e, FaceData<NS, R, WALL>& fd) {
   const FaceItem& it = fd.it;
+  if (WALL && it.nb < 0) {
+    wall_face_loads(A.U, e, it, fd.L, fd.R_);
+    const double* Ue = A.U + (size_t)e * 5 * nn;
+    fd.fn[0] = Ue[it.nnb];
+    fd.fn[1] = Ue[it.k1 * nn + it.nnb];
+    fd.fn[2] = Ue[it.k2 * nn + it.nnb];
+    fd.fn[3] = 0.0;
+    return;
+  }
   face_loads(A.U, e, it, fd.L, fd.R_);
   if (NS) {
     const R* Fn = reinterpret_cast<const R*>(A.Fvf) + ((size_t)it.nb * 6 + (it.f ^ 1)) * 4 * nf + it.a;
@@ -770,11 +864,19 @@ __device__ __forceinline__ void store_q(const FaceItem& it, const R qs[4], R (*s
 
 // Interface values of a face item into LDS: advective f*, and for
 // Navier-Stokes q* = (q- + q+)/2 and the neighbour's normal viscous flux.
-template <int VF, bool NS, class R, bool MX>
-__device__ __forceinline__ void face_item(const StageArgs& A, const FaceData<NS, R>& fd, const Ref& ref,
+template <int VF, bool NS, class R, bool MX, bool WALL = false>
+__device__ __forceinline__ void face_item(const StageArgs& A, const FaceData<NS, R, WALL>& fd, const Ref& ref,
                                           R (*sF)[5][nf], R (*sQ)[4][nf], R (*sFn)[4][nf]) {
   const FaceItem& it = fd.it;
-  if (NS) {
+  if (WALL && it.nb < 0) {
+    // the wall-model flux replaces the interface mean (used without the own term)
+    double g[4];
+    wall_model_flux(A, it.side ? fd.L[0] : fd.R_[0], fd.fn[0], fd.fn[1], fd.fn[2], it.side ? -1.0 : 1.0, g);
+    sFn[it.f][it.d][it.a] = g[0];
+    sFn[it.f][it.k1 - 1][it.a] = g[1];
+    sFn[it.f][it.k2 - 1][it.a] = g[2];
+    sFn[it.f][3][it.a] = g[3];
+  } else if (NS) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) sFn[it.f][c][it.a] = fd.fn[c];
   }
@@ -808,12 +910,13 @@ __device__ __forceinline__ void face_item(const StageArgs& A, const FaceData<NS,
 #else
 #define DG_STAGE_BOUNDS __launch_bounds__(PS::NTB)
 #endif
-template <int VF, int EQ, bool BLEND, class R>
+template <int VF, int EQ, bool BLEND, class R, bool WALL = false>
 __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
   constexpr bool NS = (EQ >= 1);
   constexpr bool LES = (EQ == 2);
   constexpr bool MX = sizeof(R) == 4;
   static_assert(!(BLEND && MX), "the blended operator is FP64 only");
+  static_assert(!WALL || (NS && !BLEND && !MX), "walls: FP64 Navier-Stokes without blending");
   // LDS pool: primitives sP[7][nnp], face fluxes sF[6][5][nf], and for
   // Navier-Stokes the interface values sQ[6][4][nf] and the neighbours' normal
   // viscous fluxes sFn[6][4][nf].  The twelve viscous-flux components of all
@@ -842,10 +945,16 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
   const double gm1 = A.gamma - 1.0;
   // Memory round trip 1: neighbour indices of the thread's face items, the
   // node state and the basis.
-  FaceData<NS, R> fd[FI];
+  FaceData<NS, R, WALL> fd[FI];
 #pragma unroll
   for (int k = 0; k < FI; ++k)
     if (t + k * TPE < 6 * nf) fd[k].it = face_item_geometry(A.nbr, e, t + k * TPE);
+  // wall faces of the element (bit f): at most the two normal to wall_dir
+  int wmask = 0;
+  if (WALL) {
+    const int f0 = 2 * A.wall_dir;
+    wmask = (A.nbr[6 * e + f0] < 0 ? 1 << f0 : 0) | (A.nbr[6 * e + f0 + 1] < 0 ? 2 << f0 : 0);
+  }
   const double* Ue = A.U + (size_t)e * 5 * nn;
   double u[5], gprev[5];
   if (t < nn) {
@@ -858,7 +967,7 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
   // Round trip 2: the face states (needs the neighbour indices).
 #pragma unroll
   for (int k = 0; k < FI; ++k)
-    if (t + k * TPE < 6 * nf) face_issue<NS, R>(A, e, fd[k]);
+    if (t + k * TPE < 6 * nf) face_issue<NS, R, WALL>(A, e, fd[k]);
   if (tid < NB_STAGE) {
     sB[tid] = (R)bval;
     if (BLEND) sB64[tid] = bval;
@@ -881,7 +990,7 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
   }
 #pragma unroll
   for (int k = 0; k < FI; ++k)
-    if (t + k * TPE < 6 * nf) face_item<VF, NS, R, MX>(A, fd[k], ref, sF, sQ, sFn);
+    if (t + k * TPE < 6 * nf) face_item<VF, NS, R, MX, WALL>(A, fd[k], ref, sF, sQ, sFn);
   __syncthreads();
 
   R acc[5] = {0, 0, 0, 0, 0};
@@ -1053,11 +1162,13 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
         const int a = d == 0 ? ijk[1] + n1 * ijk[2] : (d == 1 ? ijk[0] + n1 * ijk[2] : ijk[0] + n1 * ijk[1]);
         if (id == 0 || id == N) {  // F*v = mean with the neighbour's normal viscous flux (sFn)
           const int f = 2 * d + (id == N);
-          const R w = h2 * (id == N ? swinv[N] : -swinv[0]);
-          s0 = fmaR(w, Fv[d][0] + sFn[f][0][a], s0);
-          s1 = fmaR(w, Fv[d][1] + sFn[f][1][a], s1);
-          s2 = fmaR(w, Fv[d][2] + sFn[f][2][a], s2);
-          s3 = fmaR(w, Fv[d][3] + sFn[f][3][a], s3);
+          const bool wf = WALL && ((wmask >> f) & 1);  // wall: sFn is F*v itself
+          const R w = (wf ? (R)1 : h2) * (id == N ? swinv[N] : -swinv[0]);
+          const R o = wf ? (R)0 : (R)1;
+          s0 = fmaR(w, fmaR(o, Fv[d][0], sFn[f][0][a]), s0);
+          s1 = fmaR(w, fmaR(o, Fv[d][1], sFn[f][1][a]), s1);
+          s2 = fmaR(w, fmaR(o, Fv[d][2], sFn[f][2][a]), s2);
+          s3 = fmaR(w, fmaR(o, Fv[d][3], sFn[f][3][a]), s3);
         }
         acc[1] = fmaR(invJ[d], s0, acc[1]);
         acc[2] = fmaR(invJ[d], s1, acc[2]);
@@ -1217,7 +1328,7 @@ __device__ __forceinline__ void lift_face_node(const StageArgs& A, int e, const 
 // Register budget of the lifting kernel: 8 waves per SIMD (64 VGPRs) with one
 // face item per thread, else 4; the line sums with run-time strides are only
 // partly unrolled so that the partner loads in flight fit in it.
-template <class R, bool LES>
+template <class R, bool LES, bool WALL = false>
 __global__ __launch_bounds__(PL::NTB, PL::FI == 1 && N >= 2 ? 8 : 4) void k_lift(StageArgs A) {
   constexpr bool MX = sizeof(R) == 4;
   constexpr int EPB = PL::EPB, TPE = PL::TPE, FI = PL::FI;
@@ -1247,7 +1358,7 @@ __global__ __launch_bounds__(PL::NTB, PL::FI == 1 && N >= 2 ? 8 : 4) void k_lift
   double FL[FI][5], FR[FI][5];
 #pragma unroll
   for (int k = 0; k < FI; ++k)
-    if (t + k * TPE < 6 * nf) face_loads(A.U, e, its[k], FL[k], FR[k]);
+    if (t + k * TPE < 6 * nf) face_loads_w<WALL>(A.U, e, its[k], FL[k], FR[k]);
   if (tid < NB_STAGE) sB[tid] = (R)bval;
   const R invJ[3] = {(R)A.invJ[0], (R)A.invJ[1], (R)A.invJ[2]};
   if (t < nn) {
@@ -3522,6 +3633,21 @@ template <int VF, class R>
 hipError_t launch_stage_vf(const StageArgs& A0, int eq, hipStream_t s) {
   const StageArgs A = grouped<PS>(A0);
   const dim3 grid(blocks_for(A)), block(PS::NTB);
+  if (A.wall_dir >= 0) {  // walls: FP64 Navier-Stokes (checked on the host)
+    if constexpr (sizeof(R) == 8) {
+      if (eq == 2) {
+        if constexpr (VF != VF_CH) hipLaunchKernelGGL((k_stage<VF, 2, false, double, true>), grid, block, 0, s, A);
+        else return hipErrorInvalidValue;
+      } else if (eq == 1) {
+        hipLaunchKernelGGL((k_stage<VF, 1, false, double, true>), grid, block, 0, s, A);
+      } else {
+        return hipErrorInvalidValue;
+      }
+      return hipGetLastError();
+    } else {
+      return hipErrorInvalidValue;
+    }
+  }
   if (eq == 2) {
     if constexpr (VF != VF_CH) hipLaunchKernelGGL((k_stage<VF, 2, false, R>), grid, block, 0, s, A);
     else return hipErrorInvalidValue;
@@ -3556,6 +3682,11 @@ hipError_t launch_stage_mixed(const StageArgs& A, int eq, hipStream_t s) {
 
 hipError_t launch_lift(const StageArgs& A0, int eq, hipStream_t s) {
   const StageArgs A = grouped<PL>(A0);
+  if (A.wall_dir >= 0) {
+    if (eq == 2) hipLaunchKernelGGL((k_lift<double, true, true>), dim3(blocks_for(A)), dim3(PL::NTB), 0, s, A);
+    else hipLaunchKernelGGL((k_lift<double, false, true>), dim3(blocks_for(A)), dim3(PL::NTB), 0, s, A);
+    return hipGetLastError();
+  }
   if (eq == 2) hipLaunchKernelGGL((k_lift<double, true>), dim3(blocks_for(A)), dim3(PL::NTB), 0, s, A);
   else hipLaunchKernelGGL((k_lift<double, false>), dim3(blocks_for(A)), dim3(PL::NTB), 0, s, A);
   return hipGetLastError();
@@ -3563,6 +3694,7 @@ hipError_t launch_lift(const StageArgs& A0, int eq, hipStream_t s) {
 
 hipError_t launch_lift_mixed(const StageArgs& A0, int eq, hipStream_t s) {
   const StageArgs A = grouped<PL>(A0);
+  if (A.wall_dir >= 0) return hipErrorInvalidValue;
   if (eq == 2) hipLaunchKernelGGL((k_lift<float, true>), dim3(blocks_for(A)), dim3(PL::NTB), 0, s, A);
   else hipLaunchKernelGGL((k_lift<float, false>), dim3(blocks_for(A)), dim3(PL::NTB), 0, s, A);
   return hipGetLastError();

@@ -31,7 +31,7 @@ EXPORTS = ["dg_default_options", "dg_init", "dg_set_options", "dg_get_options", 
            "dg_time_derivative", "rk_step", "dg_rk_steps", "dg_vjp", "rk_step_vjp", "dg_max_dt",
            "dg_integrals", "dg_alpha", "dg_check_finite", "dg_set_profiling", "dg_profile_read", "dg_node_weights",
            "dg_sizes", "dg_finalize", "dg_last_error", "dg_set_cs_field", "dg_set_geometry",
-           "dg_set_connectivity"]
+           "dg_set_connectivity", "dg_set_wall_model"]
 
 
 class DGError(RuntimeError):
@@ -88,6 +88,7 @@ def lib() -> ctypes.CDLL:
             "dg_set_cs_field": ([P, P], I),
             "dg_set_geometry": ([P, P], I),
             "dg_set_connectivity": ([P, P], I),
+            "dg_set_wall_model": ([P, I, ctypes.c_double, ctypes.c_double], I),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -191,6 +192,13 @@ class DG:
         if c.shape != (self.n_elems, 6, 3):
             raise ValueError(f"conn must have shape {(self.n_elems, 6, 3)}")
         self._check(lib().dg_set_connectivity(self._ctx, ctypes.c_void_p(c.ctypes.data)))
+
+    def set_wall_model(self, wall_dir: int, u_inf: float = 1.0, ma_inf: float = 0.0):
+        """Wall-modelled boundaries on the two box faces normal to wall_dir
+        (0, 1, 2; -1: periodic again): Spalding's law of the wall, van Driest
+        transformed with freestream velocity u_inf and Mach number ma_inf > 0."""
+        self._stream()
+        self._check(lib().dg_set_wall_model(self._ctx, int(wall_dir), float(u_inf), float(ma_inf)))
 
     def close(self):
         if getattr(self, "_ctx", None) is not None and self._ctx.value:

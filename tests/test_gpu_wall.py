@@ -1,0 +1,156 @@
+"""Wall-modelled boundaries on the GPU (dg_set_wall_model: Spalding's law of
+the wall, optionally van Driest transformed, paper Sec. 3) against the FP64
+oracle through the C ABI: single evaluations to 1e-12 of the term scale for
+all degrees, wall directions, flux pairs, with the Smagorinsky model and in
+the log region of the law, a Runge-Kutta rollout, removal of the walls, and the
+error paths."""
+import numpy as np
+import pytest
+
+from paper_2306_12891_amd import inputs as I
+from test_gpu_parity import G, TWO_PI, assert_state_close, assert_ut_close, gpu_ut
+
+pytestmark = pytest.mark.gpu
+
+LO, HI = (0.0, 0.0, 0.0), (2.0, 1.5, 1.0)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def make(orc, N, nelem, wall_dir, vf=1, sf=1, mu=2e-3, Cs=0.0, uinf=1.0, mainf=0.0, lo=LO, hi=HI):
+    from paper_2306_12891_amd import dg
+    s = orc.Setup(N=N, nelem=nelem, lo=lo, hi=hi, equations=orc.NS, vol_flux=vf, surf_flux=sf, mu=mu, Cs=Cs,
+                  wall_dir=wall_dir, wm_uinf=uinf, wm_mainf=mainf)
+    op = dg.DG(nelem, N, gamma=G, mu=mu, lo=lo, hi=hi, equations=dg.NS, vol_flux=vf, surf_flux=sf, Cs=Cs)
+    op.set_wall_model(wall_dir, uinf, mainf)
+    return s, op
+
+
+def channel_state(N, nelem, seed, lo=LO, hi=HI, noise=0.02):
+    return I.random_smooth(N, nelem, lo, hi, seed=seed, noise=noise)
+
+
+@pytest.mark.parametrize("wall_dir", [0, 1, 2])
+@pytest.mark.parametrize("N", [1, 2, 3, 5, 7])
+def test_parity_all_degrees_and_directions(orc, torch_cuda, N, wall_dir):
+    nelem = (3, 4, 2)
+    s, op = make(orc, N, nelem, wall_dir)
+    U = channel_state(N, nelem, 300 + N)
+    ref = orc.time_derivative(s, U)
+    assert_ut_close(gpu_ut(torch_cuda, op, U), ref, U, N, nelem, LO, HI)
+    # the walls change the result well above the tolerance
+    per = orc.time_derivative(orc.Setup(N=N, nelem=nelem, lo=LO, hi=HI, equations=orc.NS, vol_flux=1, surf_flux=1,
+                                        mu=2e-3), U)
+    assert np.max(np.abs(per - ref)) > 1e-4 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("vf,sf,Cs,mainf", [(0, 0, 0.0, 0.0), (1, 1, 0.0, 0.6), (2, 2, 0.0, 0.0), (3, 1, 0.0, 1.5),
+                                            (1, 2, 0.2, 0.0), (0, 1, 0.15, 0.8), (3, 0, 0.3, 0.0)])
+@pytest.mark.parametrize("N", [3, 5])
+def test_parity_fluxes_les_van_driest(orc, torch_cuda, N, vf, sf, Cs, mainf):
+    nelem = (2, 3, 3)
+    s, op = make(orc, N, nelem, 1, vf=vf, sf=sf, Cs=Cs, uinf=0.8, mainf=mainf)
+    U = channel_state(N, nelem, 310 + N + vf)
+    assert_ut_close(gpu_ut(torch_cuda, op, U), orc.time_derivative(s, U), U, N, nelem, LO, HI)
+
+
+@pytest.mark.parametrize("mu", [1e-5, 1e-7])
+def test_parity_log_region(orc, torch_cuda, mu):
+    """Exchange Reynolds numbers 1e4..1e6 (y+ in the log layer)."""
+    N, nelem = 4, (2, 3, 2)
+    s, op = make(orc, N, nelem, 2, mu=mu, mainf=0.7, uinf=0.9)
+    U = channel_state(N, nelem, 320)
+    assert_ut_close(gpu_ut(torch_cuda, op, U), orc.time_derivative(s, U), U, N, nelem, LO, HI)
+
+
+def test_one_element_between_the_walls(orc, torch_cuda):
+    """Both wall faces on the same element (one element across the channel)."""
+    N, nelem = 3, (3, 1, 2)
+    s, op = make(orc, N, nelem, 1, Cs=0.1)
+    U = channel_state(N, nelem, 330)
+    assert_ut_close(gpu_ut(torch_cuda, op, U), orc.time_derivative(s, U), U, N, nelem, LO, HI)
+
+
+def test_uniform_flow_with_zero_velocity_component(orc, torch_cuda):
+    """Wall-parallel uniform flow, and a state at rest (zero shear branch)."""
+    N, nelem = 3, (2, 3, 2)
+    s, op = make(orc, N, nelem, 1)
+    for u in [(0.4, 0.0, 0.1), (0.0, 0.0, 0.0)]:
+        U = I.freestream(N, nelem, LO, HI, u=u)
+        ref = orc.time_derivative(s, U)
+        got = gpu_ut(torch_cuda, op, U)
+        assert np.max(np.abs(got - ref)) <= 1e-12 * max(np.max(np.abs(ref)), 1.0)
+
+
+def test_rollout(orc, torch_cuda):
+    import torch
+    N, nelem = 3, (3, 4, 2)
+    s, op = make(orc, N, nelem, 1, sf=1, vf=1, Cs=0.1, mu=1e-3)
+    U0 = channel_state(N, nelem, 340, noise=0.0)
+    dt = 0.5 * orc.max_dt(s, U0, 0.5)
+    U = torch.from_numpy(U0).cuda()
+    op.rk_steps(U, dt, 4)
+    assert_state_close(U.cpu().numpy(), orc.rk_steps(s, U0, dt, 4))
+
+
+def test_walls_removed_and_moved(orc, torch_cuda):
+    N, nelem = 3, (2, 3, 2)
+    s, op = make(orc, N, nelem, 1)
+    U = channel_state(N, nelem, 350)
+    assert_ut_close(gpu_ut(torch_cuda, op, U), orc.time_derivative(s, U), U, N, nelem, LO, HI)
+    op.set_wall_model(2)
+    s2 = orc.Setup(N=N, nelem=nelem, lo=LO, hi=HI, equations=orc.NS, vol_flux=1, surf_flux=1, mu=2e-3, wall_dir=2)
+    assert_ut_close(gpu_ut(torch_cuda, op, U), orc.time_derivative(s2, U), U, N, nelem, LO, HI)
+    op.set_wall_model(-1)
+    s0 = orc.Setup(N=N, nelem=nelem, lo=LO, hi=HI, equations=orc.NS, vol_flux=1, surf_flux=1, mu=2e-3)
+    assert_ut_close(gpu_ut(torch_cuda, op, U), orc.time_derivative(s0, U), U, N, nelem, LO, HI)
+
+
+def test_error_paths(orc, torch_cuda):
+    import torch
+
+    from paper_2306_12891_amd import dg
+    N, nelem = 3, (2, 2, 2)
+    op = dg.DG(nelem, N, gamma=G, mu=1e-3, equations=dg.EULER)
+    with pytest.raises(dg.DGError) as ei:
+        op.set_wall_model(1)
+    assert ei.value.code == dg.DG_EUNSUPPORTED
+    op = dg.DG(nelem, N, gamma=G, mu=1e-3, equations=dg.NS, vol_flux=dg.PI, surf_flux=dg.ROE)
+    for args in [(3,), (-2,), (1, 1.0, -0.5), (1, 0.0, 0.5), (1, 1.0, float("nan"))]:
+        with pytest.raises(dg.DGError) as ei:
+            op.set_wall_model(*args)
+        assert ei.value.code == dg.DG_EINVAL, args
+    op.set_wall_model(1, 1.0, 0.5)
+    for kw in (dict(precision=dg.MIXED), dict(equations=dg.EULER), dict(equations=dg.EULER, blending=1)):
+        with pytest.raises(dg.DGError) as ei:
+            op.set_options(**kw)
+        assert ei.value.code == dg.DG_EUNSUPPORTED, kw
+    U = torch.from_numpy(channel_state(N, nelem, 360, lo=(0, 0, 0), hi=(TWO_PI,) * 3)).cuda()
+    with pytest.raises(dg.DGError) as ei:
+        op.vjp(U, U.clone())
+    assert ei.value.code == dg.DG_EUNSUPPORTED
+    with pytest.raises(dg.DGError) as ei:
+        op.set_geometry(torch.from_numpy(I.warped_coordinates(N, nelem)).cuda())
+    assert ei.value.code == dg.DG_EUNSUPPORTED
+    _, conn = I.rotated_elements(N, nelem, seed=1)
+    with pytest.raises(dg.DGError) as ei:
+        op.set_connectivity(conn)
+    assert ei.value.code == dg.DG_EUNSUPPORTED
+    # the walls are still in place after the refused calls
+    s = orc.Setup(N=N, nelem=nelem, equations=orc.NS, vol_flux=1, surf_flux=1, mu=1e-3, wall_dir=1, wm_uinf=1.0,
+                  wm_mainf=0.5)
+    Un = U.cpu().numpy()
+    assert_ut_close(gpu_ut(torch_cuda, op, Un), orc.time_derivative(s, Un), Un, N, nelem, (0, 0, 0), (TWO_PI,) * 3)
+    # a curved mesh refuses walls
+    op2 = dg.DG(nelem, N, gamma=G, mu=1e-3, equations=dg.NS, vol_flux=dg.PI, surf_flux=dg.ROE)
+    op2.set_geometry(torch.from_numpy(I.warped_coordinates(N, nelem)).cuda())
+    with pytest.raises(dg.DGError) as ei:
+        op2.set_wall_model(0)
+    assert ei.value.code == dg.DG_EUNSUPPORTED
+    op2.set_wall_model(-1)  # nothing to remove: the curved mesh stays
