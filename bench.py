@@ -48,7 +48,15 @@ WORKLOADS = {
     "tgv_curved_n5_32": (5, (32, 32, 32), 1, 1, 1, 1.0 / 1600, 0,
                          "TGV Ma0.1 Re1600 Pr0.72 on a warped periodic mesh (curved elements, curl-form metric "
                          "terms, displacement amplitude 0.04 of the box), N=5, 32^3 elems, PI+Roe, BR1, LSERK4"),
+    "channel_wm_n5_32": (5, (32, 32, 32), 1, 1, 1, 2e-5, 0,
+                         "Wall-modelled channel LES, 2pi x 2 x pi, walls normal to y (Spalding's law with van Driest "
+                         "transformation, u_inf 1, Ma_inf 0.7), Smagorinsky C_s=0.17, centre-line Ma 0.7, "
+                         "mu 2e-5, N=5, 32^3 elems, PI+Roe, BR1, LSERK4"),
 }
+
+# Wall-modelled workloads: (wall direction, u_inf, Ma_inf of the van Driest
+# transformation).
+WALLS = {"channel_wm_n5_32": (1, 1.0, 0.7)}
 
 # Curved workloads: amplitude of the smooth periodic node displacement
 # (inputs.warped_coordinates); the stage kernel then also reads the metric
@@ -57,7 +65,7 @@ CURVED = {"tgv_curved_n5_32": 0.04}
 METRIC_BYTES_PER_NODE = 80.0
 
 # Smagorinsky coefficient of the LES workloads (standard model, constant C_s).
-MODEL_CS = {"tgv_les_n5_32": 0.17}
+MODEL_CS = {"tgv_les_n5_32": 0.17, "channel_wm_n5_32": 0.17}
 
 
 # Element counts of the freestream size sweep: 2^15 ... 2^21 elements, grown
@@ -81,12 +89,16 @@ def initial_state(name, N, nelem):
         return inputs.freestream(N, nelem)
     if name.startswith("sod"):
         return inputs.sod(N, nelem, (0, 0, 0), (1.0, 0.125, 0.125))
+    if name.startswith("channel"):
+        return inputs.channel(N, nelem, *domain(name))
     raise KeyError(name)
 
 
 def domain(name):
     if name.startswith("sod"):
         return (0.0, 0.0, 0.0), (1.0, 0.125, 0.125)
+    if name.startswith("channel"):
+        return (0.0, 0.0, 0.0), (2 * math.pi, 2.0, math.pi)
     return (0.0, 0.0, 0.0), (2 * math.pi,) * 3
 
 
@@ -210,8 +222,10 @@ def cpu_baseline(name, spec, U0, dt, max_nodes=8_000_000):
 
     def run(elems, U, threads):
         orc.set_threads(threads)
+        wd, ui, mi = WALLS.get(name, (-1, 1.0, 0.0))
         s = orc.Setup(N=N, nelem=elems, lo=lo, hi=hi, equations=eq, vol_flux=vf, surf_flux=sf, mu=mu,
-                      blending=blend, Pr=0.72, Cs=MODEL_CS.get(name, 0.0), xnodes=curved_nodes(name, N, elems))
+                      blending=blend, Pr=0.72, Cs=MODEL_CS.get(name, 0.0), xnodes=curved_nodes(name, N, elems),
+                      wall_dir=wd, wm_uinf=ui, wm_mainf=mi)
         t0 = time.perf_counter()
         orc.rk_steps(s, U, dt, 1)
         return time.perf_counter() - t0
@@ -336,6 +350,23 @@ def adjoint_timing(torch, op, U, reps=20):
     return out
 
 
+def wall_model_cost(torch, op, U_init, dt, steps, warmup, wall):
+    """Rollouts of the same start with the wall model without the van Driest
+    transformation and without walls (periodic), against the wall-modelled
+    run: per-step wall time and stage/lifting kernel time."""
+    out = {}
+    wd, ui, _ = wall
+    for label, args in (("spalding_only", (wd, ui, 0.0)), ("periodic", (-1,))):
+        op.set_wall_model(*args)
+        U = U_init.clone()
+        w, prof = timed_rollouts(torch, op, U, dt, steps, warmup, 1, True)
+        out[label] = {"ms_per_step": w[0] / steps * 1e3,
+                      "kernel_ms_per_step": {k: round(v[0] / steps, 4) for k, v in prof.items() if v[1]}}
+        del U
+    op.set_wall_model(*wall)
+    return out
+
+
 def sweep(torch, dg, spec, steps, warmup, repeats):
     """Freestream throughput over 2^15 ... 2^21 elements (N = 7)."""
     N, _, eq, vf, sf, mu, blend, _ = spec
@@ -408,6 +439,8 @@ def main():
                blending=blend, Pr=0.72, Cs=cs)
     if name in CURVED:
         op.set_geometry(torch.from_numpy(curved_nodes(name, N, nelem)).to("cuda:0"))
+    if name in WALLS:
+        op.set_wall_model(*WALLS[name])
     U_init = device_freestream(torch, N, nelem) if U0 is None else torch.from_numpy(U0).to("cuda:0")
     U = U_init.clone()
     dt = op.max_dt(U, 0.5)
@@ -435,7 +468,7 @@ def main():
 
     # Mixed-precision operator on the same workload: same initial state, same
     # warm-up and timed steps; error of the final state against the FP64 run.
-    if not args.no_mixed and vf in (1, 3) and not blend and name not in CURVED:
+    if not args.no_mixed and vf in (1, 3) and not blend and name not in CURVED and name not in WALLS:
         opm = dg.DG(nelem, N, gamma=1.4, mu=mu, lo=lo, hi=hi, equations=eq, vol_flux=vf, surf_flux=sf,
                     Pr=0.72, precision=dg.MIXED, Cs=cs)
         Um = U_init.clone()
@@ -458,7 +491,10 @@ def main():
         opm.close()
         del Um
 
-    if not args.no_adjoint and name in CURVED:
+    if name in WALLS:
+        if prof:
+            extra["wall_model_cost"] = wall_model_cost(torch, op, U_init, dt, args.steps, args.warmup, WALLS[name])
+    elif not args.no_adjoint and name in CURVED:
         extra["curved_adjoint"] = adjoint_timing(torch, op, U)
     elif not args.no_adjoint:
         from paper_2306_12891_amd import inputs

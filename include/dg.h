@@ -261,7 +261,8 @@ int dg_check_finite(dg_ctx* ctx, const double* X);
  * launch of the operator is bracketed by two HIP events recorded on the
  * context's stream.  dg_profile_read synchronises the stream, writes the
  * summed milliseconds and the number of launches per kernel kind
- * (DG_K_STAGE: operator + Runge-Kutta stage, DG_K_LIFT: BR1 lifting,
+ * (DG_K_STAGE: operator + Runge-Kutta stage, DG_K_LIFT: BR1 lifting and
+ * the wall-model pass of dg_set_wall_model,
  * DG_K_INDICATOR: modal indicator, DG_K_VJP: reverse operator,
  * DG_K_VJP_LIFT: reverse BR1 lifting) into ms[5] and launches[5], and clears
  * the records.  Disabling also clears them. */

@@ -1605,8 +1605,13 @@ static void subset_time_derivative(const Ctx& c, const double* U, const int32_t*
   const Basis& b = c.b;
   const double g = c.s.gamma;
   const int nn = c.nn, nf = c.nf, N = c.N;
-  // f* on the + face of element x in direction d at face index a
+  // f* on the + face of element x in direction d at face index a (walls: the
+  // wall flux of that face)
   auto fplus = [&](int x, int d, int a, double f[5]) {
+    if (c.nbr[6 * x + 2 * d + 1] < 0) {
+      wall_inviscid_flux(c, U, x, d, a, true, f);
+      return;
+    }
     double L[5], R[5];
     load_state(c, U, x, face_node(c, d, N, a), L);
     load_state(c, U, c.nbr[6 * x + 2 * d + 1], face_node(c, d, 0, a), R);
@@ -1626,11 +1631,20 @@ static void subset_time_derivative(const Ctx& c, const double* U, const int32_t*
       qnode(x, n, qq);
       for (int k = 0; k < 4; ++k) q[k * nn + n] = qq[k];
     }
+    // q* on the + face of y; at a wall the mirror state (normal velocity reversed)
     auto qstar_plus = [&](int y, int d, int k, int a) {
       double qa[4], qb[4];
       qnode(y, face_node(c, d, N, a), qa);
+      if (c.nbr[6 * y + 2 * d + 1] < 0) return 0.5 * (qa[k] + (k == d ? -qa[k] : qa[k]));
       qnode(c.nbr[6 * y + 2 * d + 1], face_node(c, d, 0, a), qb);
       return 0.5 * (qa[k] + qb[k]);
+    };
+    // q* on the - face of x
+    auto qstar_minus = [&](int d, int k, int a) {
+      if (c.nbr[6 * x + 2 * d] >= 0) return qstar_plus(c.nbr[6 * x + 2 * d], d, k, a);
+      double qa[4];
+      qnode(x, face_node(c, d, 0, a), qa);
+      return 0.5 * (qa[k] + (k == d ? -qa[k] : qa[k]));
     };
     for (int n = 0; n < nn; ++n) {
       int ijk[3];
@@ -1642,7 +1656,7 @@ static void subset_time_derivative(const Ctx& c, const double* U, const int32_t*
           double s = 0.0;
           for (int l = 0; l <= N; ++l) s += b.D[i * c.n1 + l] * q[k * nn + node_along(c, ijk, d, l)];
           if (i == N) s += (1.0 / b.w[N]) * (qstar_plus(x, d, k, a) - q[k * nn + n]);
-          if (i == 0) s -= (1.0 / b.w[0]) * (qstar_plus(c.nbr[6 * x + 2 * d], d, k, a) - q[k * nn + n]);
+          if (i == 0) s -= (1.0 / b.w[0]) * (qstar_minus(d, k, a) - q[k * nn + n]);
           gr[(d * 4 + k) * nn + n] = c.invJ[d] * s;
         }
       }
@@ -1683,7 +1697,8 @@ static void subset_time_derivative(const Ctx& c, const double* U, const int32_t*
         }
         if (i == 0) {
           double f[5];
-          fplus(c.nbr[6 * e + 2 * d], d, a, f);
+          if (c.nbr[6 * e + 2 * d] < 0) wall_inviscid_flux(c, U, e, d, a, false, f);
+          else fplus(c.nbr[6 * e + 2 * d], d, a, f);
           for (int v = 0; v < 5; ++v) sum[v] -= (1.0 / b.w[0]) * f[v];
         }
         for (int v = 0; v < 5; ++v) acc[v] -= c.invJ[d] * sum[v];
@@ -1693,7 +1708,8 @@ static void subset_time_derivative(const Ctx& c, const double* U, const int32_t*
     if (c.s.equations != EQ_NS) continue;
     std::vector<double> gr_e, gr_nb[6];
     gradient(e, gr_e);
-    for (int f = 0; f < 6; ++f) gradient(c.nbr[6 * e + f], gr_nb[f]);
+    for (int f = 0; f < 6; ++f)
+      if (c.nbr[6 * e + f] >= 0) gradient(c.nbr[6 * e + f], gr_nb[f]);
     for (int n = 0; n < nn; ++n) {
       int ijk[3];
       coords(c, n, ijk);
@@ -1712,15 +1728,25 @@ static void subset_time_derivative(const Ctx& c, const double* U, const int32_t*
           double s2 = 0.0;
           for (int l = 0; l <= N; ++l) s2 += b.D[i * c.n1 + l] * Fl[v][l];
           if (i == N) {
-            double Fo[5];
-            fv_at(c.nbr[6 * e + 2 * d + 1], gr_nb[2 * d + 1], face_node(c, d, 0, a), d, Fo);
-            const double Fs = 0.5 * (Fn[v] + Fo[v]);
+            double Fo[5], Fs;
+            if (c.nbr[6 * e + 2 * d + 1] < 0) {
+              wall_viscous_flux(c, U, e, d, a, true, Fo);
+              Fs = Fo[v];
+            } else {
+              fv_at(c.nbr[6 * e + 2 * d + 1], gr_nb[2 * d + 1], face_node(c, d, 0, a), d, Fo);
+              Fs = 0.5 * (Fn[v] + Fo[v]);
+            }
             s2 += (1.0 / b.w[N]) * (Fs - Fn[v]);
           }
           if (i == 0) {
-            double Fo[5];
-            fv_at(c.nbr[6 * e + 2 * d], gr_nb[2 * d], face_node(c, d, N, a), d, Fo);
-            const double Fs = 0.5 * (Fo[v] + Fn[v]);
+            double Fo[5], Fs;
+            if (c.nbr[6 * e + 2 * d] < 0) {
+              wall_viscous_flux(c, U, e, d, a, false, Fo);
+              Fs = Fo[v];
+            } else {
+              fv_at(c.nbr[6 * e + 2 * d], gr_nb[2 * d], face_node(c, d, N, a), d, Fo);
+              Fs = 0.5 * (Fo[v] + Fn[v]);
+            }
             s2 -= (1.0 / b.w[0]) * (Fs - Fn[v]);
           }
           Ut[v * nn + n] += c.invJ[d] * s2;
@@ -1833,7 +1859,7 @@ int or_time_derivative(const Setup* s, const double* U, double* Ut, const double
 
 // Operator (no blending) for the elements elems[0..nsel-1] only: Ut_sel[s][5][nn].
 int or_time_derivative_elems(const Setup* s, const double* U, const int32_t* elems, int nsel, double* Ut_sel) {
-  if (!valid(s) || s->blending || s->xnodes || s->wall_dir >= 0) return -1;
+  if (!valid(s) || s->blending || s->xnodes) return -1;
   const Ctx c = make_ctx(*s);
   for (int k = 0; k < nsel; ++k)
     if (elems[k] < 0 || elems[k] >= c.nelem) return -1;

@@ -278,6 +278,7 @@ StageArgs stage_args(const dg_ctx* c) {
   a.conn = c->conn;
   a.cs = c->opt.Cs;
   a.wall_dir = c->wall_dir;
+  for (int d = 0; d < 3; ++d) a.ne[d] = c->ne[d];
   if (c->wall_dir >= 0) {
     a.wm_h = c->dx[c->wall_dir];
     a.wm_uinf = c->wm_uinf;
@@ -380,6 +381,10 @@ int run_stage(dg_ctx* c, const double* Xin, double* Xout, double* Ut, int mode, 
     e = timed(c, DG_K_LIFT,
               [&] { return mixed ? c->kt->lift_mixed(a, eq, c->stream) : c->kt->lift(a, eq, c->stream); });
     if (e != hipSuccess) return hip_fail(c, e, "lifting kernel");
+  }
+  if (c->wall_dir >= 0) {  // FP64 Navier-Stokes (checked above)
+    e = timed(c, DG_K_LIFT, [&] { return c->kt->wall_flux(a, c->stream); });
+    if (e != hipSuccess) return hip_fail(c, e, "wall-model kernel");
   }
   e = timed(c, DG_K_STAGE,
             [&] { return mixed ? c->kt->stage_mixed(a, eq, c->stream) : c->kt->stage(a, eq, c->stream); });

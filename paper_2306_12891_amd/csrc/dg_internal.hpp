@@ -59,6 +59,7 @@ struct StageArgs {
   // factor wm_b (0: the untransformed law)
   int wall_dir;
   double wm_h, wm_uinf, wm_b;
+  int ne[3];  // elements per direction of the box
 };
 
 struct ReduceArgs {
@@ -130,6 +131,8 @@ struct KernelTable {
   // reverse mode on curved elements (FP64, no blending)
   hipError_t (*vjp_curved)(const VjpArgs&, int eq, hipStream_t);
   hipError_t (*vjp_lift_curved)(const VjpArgs&, hipStream_t);
+  // wall-model flux at the wall face nodes into Fvf (FP64, after the lift)
+  hipError_t (*wall_flux)(const StageArgs&, hipStream_t);
 };
 
 const KernelTable* table_N1();

@@ -704,6 +704,10 @@ __device__ __forceinline__ void face_loads(const double* U, int e, const FaceIte
 // element's node on the opposite face (distance h = the element size) as input,
 // optionally van Driest transformed first.  The shear stress rho_w u_tau^2
 // acts against that velocity; mass, normal momentum and energy see no flux.
+// The solve runs in its own kernel over the wall face nodes (k_wall_flux),
+// which writes the flux into the wall face's own slot of Fvf; the stage
+// kernel reads it there, so that the Newton iteration (transcendental
+// functions in FP64) does not raise the register count of the stage kernel.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double wm_bracket(double k, double ek) {
   // e^k minus its Taylor polynomial of degree four
@@ -825,8 +829,8 @@ __device__ __forceinline__ Slot slot_of_thread(int e0, int nelem) {
 
 // Loads of one face item, issued together before any of them is used: both
 // rotated states and (Navier-Stokes) the neighbour's normal viscous flux.
-// At a wall (WALL variant, neighbour -1) fn holds the exchange node's density
-// and tangential momenta instead.
+// At a wall (WALL variant, neighbour -1) fn is the wall-model flux, read from
+// the element's own slot of the wall face.
 template <bool NS, class R, bool WALL = false>
 struct FaceData {
   FaceItem it;
@@ -839,11 +843,9 @@ __device__ __forceinline__ void face_issue(const StageArgs& A, int e, FaceData<N
   const FaceItem& it = fd.it;
   if (WALL && it.nb < 0) {
     wall_face_loads(A.U, e, it, fd.L, fd.R_);
-    const double* Ue = A.U + (size_t)e * 5 * nn;
-    fd.fn[0] = Ue[it.nnb];
-    fd.fn[1] = Ue[it.k1 * nn + it.nnb];
-    fd.fn[2] = Ue[it.k2 * nn + it.nnb];
-    fd.fn[3] = 0.0;
+    const R* Fn = reinterpret_cast<const R*>(A.Fvf) + ((size_t)e * 6 + it.f) * 4 * nf + it.a;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) fd.fn[c] = Fn[c * nf];
     return;
   }
   face_loads(A.U, e, it, fd.L, fd.R_);
@@ -868,15 +870,7 @@ template <int VF, bool NS, class R, bool MX, bool WALL = false>
 __device__ __forceinline__ void face_item(const StageArgs& A, const FaceData<NS, R, WALL>& fd, const Ref& ref,
                                           R (*sF)[5][nf], R (*sQ)[4][nf], R (*sFn)[4][nf]) {
   const FaceItem& it = fd.it;
-  if (WALL && it.nb < 0) {
-    // the wall-model flux replaces the interface mean (used without the own term)
-    double g[4];
-    wall_model_flux(A, it.side ? fd.L[0] : fd.R_[0], fd.fn[0], fd.fn[1], fd.fn[2], it.side ? -1.0 : 1.0, g);
-    sFn[it.f][it.d][it.a] = g[0];
-    sFn[it.f][it.k1 - 1][it.a] = g[1];
-    sFn[it.f][it.k2 - 1][it.a] = g[2];
-    sFn[it.f][3][it.a] = g[3];
-  } else if (NS) {
+  if (NS) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) sFn[it.f][c][it.a] = fd.fn[c];
   }
@@ -1376,7 +1370,38 @@ __global__ __launch_bounds__(PL::NTB, PL::FI == 1 && N >= 2 ? 8 : 4) void k_lift
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < FI; ++k)
-    if (t + k * TPE < 6 * nf) lift_face_node<R, LES>(A, e, its[k], sq, sQ, sB, invJ);
+    if (t + k * TPE < 6 * nf && !(WALL && its[k].nb < 0)) lift_face_node<R, LES>(A, e, its[k], sq, sQ, sB, invJ);
+}
+
+// Wall-model flux at every wall face node (FP64): thread -> (side p, element
+// of the wall plane, face node a); the flux goes into Fvf[e][f][c][a] of the
+// wall face f = 2 wall_dir + p, in the global components (x, y, z momentum,
+// energy), read by the stage kernel of the same element.
+__global__ __launch_bounds__(256) void k_wall_flux(StageArgs A) {
+  const int wd = A.wall_dir;
+  const int da = wd == 0 ? 1 : 0, db = wd == 2 ? 1 : 2;  // the plane's directions
+  const int na = A.ne[da], nb = A.ne[db];
+  const long long total = 2LL * na * nb * nf;
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= total) return;
+  const int a = (int)(id % nf);
+  const long long r = id / nf;
+  const int ia = (int)(r % na), ib = (int)((r / na) % nb), p = (int)(r / ((long long)na * nb));
+  int ix[3];
+  ix[wd] = p ? A.ne[wd] - 1 : 0;
+  ix[da] = ia;
+  ix[db] = ib;
+  const int e = ix[0] + A.ne[0] * (ix[1] + A.ne[1] * ix[2]);
+  const int f = 2 * wd + p;
+  const FaceItem it = face_item_geometry(A.nbr, e, f * nf + a);
+  const double* Ue = A.U + (size_t)e * 5 * nn;
+  double g[4];
+  wall_model_flux(A, Ue[it.nown], Ue[it.nnb], Ue[it.k1 * nn + it.nnb], Ue[it.k2 * nn + it.nnb], p ? -1.0 : 1.0, g);
+  double* out = A.Fvf + ((size_t)e * 6 + f) * 4 * nf + a;
+  out[it.d * nf] = g[0];
+  out[(it.k1 - 1) * nf] = g[1];
+  out[(it.k2 - 1) * nf] = g[2];
+  out[3 * nf] = g[3];
 }
 
 // ===========================================================================
@@ -3692,6 +3717,14 @@ hipError_t launch_lift(const StageArgs& A0, int eq, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_wall_flux(const StageArgs& A, hipStream_t s) {
+  const int wd = A.wall_dir;
+  if (wd < 0 || wd > 2) return hipErrorInvalidValue;
+  const long long total = 2LL * A.ne[wd == 0 ? 1 : 0] * A.ne[wd == 2 ? 1 : 2] * nf;
+  hipLaunchKernelGGL(k_wall_flux, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, A);
+  return hipGetLastError();
+}
+
 hipError_t launch_lift_mixed(const StageArgs& A0, int eq, hipStream_t s) {
   const StageArgs A = grouped<PL>(A0);
   if (A.wall_dir >= 0) return hipErrorInvalidValue;
@@ -3830,7 +3863,7 @@ const KernelTable kTable = {
     NT, launch_stage, launch_stage_mixed, launch_lift, launch_lift_mixed, launch_alpha1, launch_spread,
     launch_max_rate, launch_integrals, launch_nonfinite, launch_vjp, launch_vjp_lift, launch_vjp_alpha_bar,
     launch_vjp_alpha, launch_vjp_fv, launch_axpby, launch_metrics, launch_stage_curved, launch_lift_curved,
-    launch_vjp_curved, launch_vjp_lift_curved,
+    launch_vjp_curved, launch_vjp_lift_curved, launch_wall_flux,
 };
 
 }  // namespace

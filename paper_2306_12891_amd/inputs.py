@@ -124,6 +124,39 @@ def tgv(N: int, nelem=(32, 32, 32), Ma: float = 0.1, gamma: float = 1.4, symmetr
     return from_primitive(rho, u, v, w, p, gamma)
 
 
+def channel(N: int, nelem=(32, 32, 32), lo=(0.0, 0.0, 0.0), hi=(TWO_PI, 2.0, np.pi), Ma: float = 0.7,
+            gamma: float = 1.4, seed: int = 11, amp: float = 0.1, modes: int = 4) -> np.ndarray:
+    """Channel between walls normal to y (half height h = (hi_y - lo_y)/2,
+    centre-line velocity 1, density 1, centre-line Mach number Ma):
+    u = 1 - eta^8 (eta = (y - y_c)/h, a flat turbulent-like profile) plus seeded
+    smooth perturbations of all three velocity components, amp (1 - eta^2)
+    times a sum of periodic Fourier modes in x and z with random phases;
+    p = 1/(gamma Ma^2), rho = 1."""
+    rng = np.random.default_rng(seed)
+    X, Y, Z = _xyz(N, nelem, lo, hi, None)
+    Lx, Lz = hi[0] - lo[0], hi[2] - lo[2]
+    yc, h = 0.5 * (lo[1] + hi[1]), 0.5 * (hi[1] - lo[1])
+    eta = (Y - yc) / h
+    env = amp * (1.0 - eta * eta)
+
+    def pert():
+        f = np.zeros_like(X)
+        for _ in range(modes):
+            kx, kz = rng.integers(1, 4, size=2)
+            ky = rng.uniform(0.5, 2.0)
+            ph = rng.uniform(0, TWO_PI, size=3)
+            f = f + np.sin(TWO_PI * kx * (X - lo[0]) / Lx + ph[0]) * np.cos(np.pi * ky * eta + ph[1]) \
+                * np.sin(TWO_PI * kz * (Z - lo[2]) / Lz + ph[2])
+        return env * f / modes
+
+    u = 1.0 - eta ** 8 + pert()
+    v = pert()
+    w = pert()
+    rho = np.ones_like(u)
+    p = np.full_like(u, 1.0 / (gamma * Ma * Ma))
+    return from_primitive(rho, u, v, w, p, gamma)
+
+
 def sod(N: int, nelem=(64, 8, 8), lo=(0.0, 0.0, 0.0), hi=(1.0, 0.125, 0.125), gamma: float = 1.4,
         x0: float = 0.5) -> np.ndarray:
     """Extruded Sod states chosen by element centre: (1, 0, 1) left of x0, (0.125, 0, 0.1) right."""

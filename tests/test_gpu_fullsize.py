@@ -106,3 +106,37 @@ def test_sod_64x8x8_500_steps(orc, torch_cuda):
                 assert err <= 1e-8 * np.max(np.abs(ref[:, 0])), (ez, ey, v, err)
     rho = got[:, 0]
     assert rho.min() > 0.1 and rho.max() < 1.05
+
+
+def test_channel_wm_n5_32_sampled(orc, torch_cuda):
+    """Wall-modelled channel LES at the benchmark's size (N = 5, 32^3
+    elements, walls normal to y with the van Driest transformed law,
+    Smagorinsky C_s = 0.17): one FP64 evaluation against the oracle on
+    elements of both wall rows, the rows next to them and seeded random
+    elements."""
+    import torch
+
+    from paper_2306_12891_amd import dg
+    N, n = 5, 32
+    lo, hi = (0.0, 0.0, 0.0), (TWO_PI, 2.0, math.pi)
+    mu, Cs = 2e-5, 0.17
+    U = I.channel(N, (n, n, n), lo, hi)
+    rng = np.random.default_rng(77)
+    ex, ez = rng.integers(0, n, 24), rng.integers(0, n, 24)
+    ey = np.tile([0, 1, n - 2, n - 1, 7, 19], 4)
+    sel = np.unique(np.concatenate([ex + n * (ey + n * ez), rng.integers(0, n ** 3, 16)])).astype(np.int32)
+    s = orc.Setup(N=N, nelem=(n, n, n), lo=lo, hi=hi, equations=1, vol_flux=1, surf_flux=1, mu=mu, Cs=Cs,
+                  wall_dir=1, wm_uinf=1.0, wm_mainf=0.7)
+    ref = orc.time_derivative_elems(s, U, sel)
+    op = dg.DG((n, n, n), N, gamma=G, mu=mu, lo=lo, hi=hi, equations=dg.NS, vol_flux=dg.PI, surf_flux=dg.ROE,
+               Cs=Cs)
+    op.set_wall_model(1, 1.0, 0.7)
+    Ud = torch.from_numpy(U).cuda()
+    got = op.time_derivative(Ud)[torch.from_numpy(sel).long().cuda()].cpu().numpy()
+    del Ud
+    op.close()
+    S = term_scale(U[sel], N, [2.0 / ((hi[d] - lo[d]) / n) for d in range(3)])
+    for v in range(5):
+        scale = max(S[v], np.max(np.abs(ref[:, v])))
+        err = np.max(np.abs(got[:, v] - ref[:, v]))
+        assert err <= 1e-12 * scale, (v, err, scale)

@@ -260,3 +260,26 @@ def test_unsupported_wall_setups_are_rejected(orc):
         orc.time_derivative(wall_setup(orc, N, nelem, wall_dir=3), U)
     with pytest.raises(ValueError):
         orc.time_derivative(wall_setup(orc, N, nelem, xnodes=I.warped_coordinates(N, nelem)), U)
+
+
+@pytest.mark.parametrize("Cs,mainf", [(0.0, 0.0), (0.2, 0.7)])
+def test_element_subset_equals_full_operator(orc, Cs, mainf):
+    """The element-subset evaluation (spot checks of large meshes) with walls:
+    bitwise the full operator's rows, for wall elements and interior ones."""
+    N, nelem = 3, (2, 4, 2)
+    s = wall_setup(orc, N, nelem, mu=3e-3, surf_flux=1, vol_flux=1, Cs=Cs, wm_uinf=0.9, wm_mainf=mainf)
+    U = I.random_smooth(N, nelem, seed=43, noise=0.02)
+    full = orc.time_derivative(s, U)
+    sel = [0, 3, 5, 9, 14, 15]
+    assert np.array_equal(orc.time_derivative_elems(s, U, sel), full[sel])
+
+
+def test_channel_state_is_a_wall_flow(orc):
+    """The channel workload's start: zero velocity on the walls, centre-line
+    velocity 1, walls normal to y."""
+    N, nelem = 3, (4, 4, 2)
+    U = I.channel(N, nelem, (0.0, 0.0, 0.0), (TWO_PI, 2.0, math.pi))
+    V = U.reshape(nelem[2], nelem[1], nelem[0], 5, N + 1, N + 1, N + 1)
+    assert np.max(np.abs(V[:, 0, :, 1:4, :, 0, :])) < 1e-14
+    assert np.max(np.abs(V[:, -1, :, 1:4, :, N, :])) < 1e-14
+    assert abs(np.max(U[:, 1]) - 1.0) < 0.15
