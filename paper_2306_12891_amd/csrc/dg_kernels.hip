@@ -1414,9 +1414,9 @@ __global__ __launch_bounds__(256) void k_wall_flux(StageArgs A) {
 //     w_nl = -(2/dx_d)(Dhat_{i l} lambda_n + Dhat_{l i} lambda_l),
 //   evaluated by hand-derived reverse mode of the two-point flux in primitive
 //   variables, then pulled back to conservative variables once per node.
-// * Interface fluxes: each element differentiates f*(U-, U+) with respect to
-//   its own side with forward-mode dual numbers (five seeds), contracted with
-//   the flux cotangent that collects lambda of both elements.
+// * Interface fluxes: each element pulls the flux cotangent (which collects
+//   lambda of both elements) back to its own face state by a hand-derived
+//   reverse sweep of f*(U-, U+) (riemann_vjp), one per face node.
 // * BR1 viscous terms: reverse of Fv(U, g), of g(q, q*) and of q(U).  The
 //   interface value q* couples the lifted gradients of both elements, so a
 //   first pass (k_vjp_lift) writes the cotangent of each element's normal
@@ -1424,115 +1424,223 @@ __global__ __launch_bounds__(256) void k_wall_flux(StageArgs A) {
 // Non-smooth points use the same conventions as the oracle's dual numbers:
 // d|x|/dx = 0 at 0 and max(a, b) takes the mean derivative at a tie.
 // ===========================================================================
-struct Dl {
-  double v, d;
-};
-__device__ __forceinline__ Dl operator+(Dl a, Dl b) { return {a.v + b.v, a.d + b.d}; }
-__device__ __forceinline__ Dl operator-(Dl a, Dl b) { return {a.v - b.v, a.d - b.d}; }
-__device__ __forceinline__ Dl operator-(Dl a) { return {-a.v, -a.d}; }
-__device__ __forceinline__ Dl operator*(Dl a, Dl b) { return {a.v * b.v, fma(a.d, b.v, a.v * b.d)}; }
-__device__ __forceinline__ Dl operator*(double a, Dl b) { return {a * b.v, a * b.d}; }
-__device__ __forceinline__ Dl operator*(Dl a, double b) { return {a.v * b, a.d * b}; }
-__device__ __forceinline__ Dl operator+(Dl a, double b) { return {a.v + b, a.d}; }
-__device__ __forceinline__ Dl operator-(double a, Dl b) { return {a - b.v, -b.d}; }
-__device__ __forceinline__ double val(double x) { return x; }
-__device__ __forceinline__ double val(Dl x) { return x.v; }
-__device__ __forceinline__ double s_rcp(double x) { return rcp64(x); }
-__device__ __forceinline__ Dl s_rcp(Dl x) {
-  const double r = rcp64(x.v);
-  return {r, -x.d * r * r};
-}
-__device__ __forceinline__ double s_sqrt(double x) { return sqrt64(x); }
-__device__ __forceinline__ Dl s_sqrt(Dl x) {
-  const double s = sqrt64(x.v);
-  return {s, x.d * 0.5 * rcp64(s)};
-}
-__device__ __forceinline__ double s_abs(double x) { return fabs(x); }
-__device__ __forceinline__ Dl s_abs(Dl x) {
-  if (x.v > 0.0) return x;
-  if (x.v < 0.0) return -x;
-  return {0.0, 0.0};
-}
-__device__ __forceinline__ double s_max(double a, double b) { return fmax(a, b); }
-__device__ __forceinline__ Dl s_max(Dl a, Dl b) {
-  if (a.v > b.v) return a;
-  if (b.v > a.v) return b;
-  return {a.v, 0.5 * (a.d + b.d)};
-}
+// sign(x) with 0 at 0: the derivative of |x| under the adjoint's convention.
+__device__ __forceinline__ double sgn0(double x) { return x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0); }
 
-// Interface flux of conservative states (rotated by D) over a generic scalar;
-// the same arithmetic as state64 / jumps / riemann_rot of the forward operator.
-template <int VF, int D, class S>
-__device__ __forceinline__ void riemann_generic(int sf, const S L[5], const S R[5], double gamma, S f[5]) {
-  constexpr int kn = Axes<D>::kn, k1 = Axes<D>::k1, k2 = Axes<D>::k2;
+// Reverse mode of the interface flux f* = F#(L, R) - Dis/2 of riemann_rot
+// (FP64, rotated frame: normal momentum in slot 1), from conservative states:
+// for the flux cotangent gb, the cotangents Lb and Rb of both states, in one
+// hand-derived sweep.  Non-smooth points as in the oracle's dual numbers:
+// |x|' = 0 at 0, max(a, b) takes half of each derivative at a tie.
+template <int VF>
+__device__ __forceinline__ void riemann_vjp(int sf, const double L[5], const double R[5], double gamma,
+                                            const double gb[5], double Lb[5], double Rb[5]) {
   const double gm1 = gamma - 1.0;
-  const S iL = s_rcp(L[0]), iR = s_rcp(R[0]);
-  const S unL = L[kn] * iL, u1L = L[k1] * iL, u2L = L[k2] * iL;
-  const S unR = R[kn] * iR, u1R = R[k1] * iR, u2R = R[k2] * iR;
-  const S pL = gm1 * (L[4] - 0.5 * (L[kn] * unL + L[k1] * u1L + L[k2] * u2L));
-  const S pR = gm1 * (R[4] - 0.5 * (R[kn] * unR + R[k1] * u1R + R[k2] * u2R));
-  const S hL = (L[4] + pL) * iL, hR = (R[4] + pR) * iR;
-  S g[5];
+  const double iL = rcp64(L[0]), iR = rcp64(R[0]);
+  const double unL = L[1] * iL, u1L = L[2] * iL, u2L = L[3] * iL;
+  const double unR = R[1] * iR, u1R = R[2] * iR, u2R = R[3] * iR;
+  const double pL = gm1 * (L[4] - 0.5 * (L[1] * unL + L[2] * u1L + L[3] * u2L));
+  const double pR = gm1 * (R[4] - 0.5 * (R[1] * unR + R[2] * u1R + R[3] * u2R));
+  const double hL = (L[4] + pL) * iL, hR = (R[4] + pR) * iR;
+  // cotangents of the primitive intermediates of each side (normal and
+  // tangential velocities, pressure, enthalpy, 1/rho)
+  double bunL = 0.0, bu1L = 0.0, bu2L = 0.0, bpL = 0.0, bhL = 0.0, biL = 0.0;
+  double bunR = 0.0, bu1R = 0.0, bu2R = 0.0, bpR = 0.0, bhR = 0.0, biR = 0.0;
+#pragma unroll
+  for (int v = 0; v < 5; ++v) Lb[v] = Rb[v] = 0.0;
+  // central part
   if (VF == VF_STD) {
-    g[0] = 0.5 * (L[kn] + R[kn]);
-    g[1] = 0.5 * (L[kn] * unL + pL + R[kn] * unR + pR);
-    g[2] = 0.5 * (L[kn] * u1L + R[kn] * u1R);
-    g[3] = 0.5 * (L[kn] * u2L + R[kn] * u2R);
-    g[4] = 0.5 * (L[kn] * hL + R[kn] * hR);
+    Lb[1] += 0.5 * (gb[0] + gb[1] * unL + gb[2] * u1L + gb[3] * u2L + gb[4] * hL);
+    Rb[1] += 0.5 * (gb[0] + gb[1] * unR + gb[2] * u1R + gb[3] * u2R + gb[4] * hR);
+    bunL += 0.5 * gb[1] * L[1];
+    bunR += 0.5 * gb[1] * R[1];
+    bpL += 0.5 * gb[1];
+    bpR += 0.5 * gb[1];
+    bu1L += 0.5 * gb[2] * L[1];
+    bu1R += 0.5 * gb[2] * R[1];
+    bu2L += 0.5 * gb[3] * L[1];
+    bu2R += 0.5 * gb[3] * R[1];
+    bhL += 0.5 * gb[4] * L[1];
+    bhR += 0.5 * gb[4] * R[1];
   } else {
-    const S um0 = 0.5 * (unL + unR), um1 = 0.5 * (u1L + u1R), um2 = 0.5 * (u2L + u2R);
-    const S rm = 0.5 * (L[0] + R[0]), pm = 0.5 * (pL + pR);
-    const S fr = rm * um0;
-    g[0] = fr;
-    g[1] = fr * um0 + pm;
-    g[2] = fr * um1;
-    g[3] = fr * um2;
-    if (VF == VF_KG) g[4] = fr * (0.5 * (L[4] * iL + R[4] * iR)) + pm * um0;
-    else g[4] = fr * (0.5 * (hL + hR));
+    const double um0 = 0.5 * (unL + unR), um1 = 0.5 * (u1L + u1R), um2 = 0.5 * (u2L + u2R);
+    const double rm = 0.5 * (L[0] + R[0]), pm = 0.5 * (pL + pR);
+    const double fr = rm * um0;
+    double bfr = gb[0] + gb[1] * um0 + gb[2] * um1 + gb[3] * um2;
+    double bum0 = gb[1] * fr, bpm = gb[1];
+    const double bum1 = gb[2] * fr, bum2 = gb[3] * fr;
+    if (VF == VF_KG) {
+      const double xm = 0.5 * (L[4] * iL + R[4] * iR);
+      bfr += gb[4] * xm;
+      bpm += gb[4] * um0;
+      bum0 += gb[4] * pm;
+      const double bxm = 0.5 * gb[4] * fr;
+      Lb[4] += bxm * iL;
+      Rb[4] += bxm * iR;
+      biL += bxm * L[4];
+      biR += bxm * R[4];
+    } else {
+      bfr += gb[4] * 0.5 * (hL + hR);
+      bhL += 0.5 * gb[4] * fr;
+      bhR += 0.5 * gb[4] * fr;
+    }
+    bum0 += bfr * rm;
+    const double brm = bfr * um0;
+    Lb[0] += 0.5 * brm;
+    Rb[0] += 0.5 * brm;
+    bpL += 0.5 * bpm;
+    bpR += 0.5 * bpm;
+    bunL += 0.5 * bum0;
+    bunR += 0.5 * bum0;
+    bu1L += 0.5 * bum1;
+    bu1R += 0.5 * bum1;
+    bu2L += 0.5 * bum2;
+    bu2R += 0.5 * bum2;
   }
   if (sf == SF_LLF) {
-    const S cL = s_sqrt(gamma * pL * iL), cR = s_sqrt(gamma * pR * iR);
-    const S hl = 0.5 * s_max(s_abs(unL) + cL, s_abs(unR) + cR);
-    g[0] = g[0] - hl * (R[0] - L[0]);
-    g[1] = g[1] - hl * (R[kn] - L[kn]);
-    g[2] = g[2] - hl * (R[k1] - L[k1]);
-    g[3] = g[3] - hl * (R[k2] - L[k2]);
-    g[4] = g[4] - hl * (R[4] - L[4]);
+    const double cL = sqrt64(gamma * pL * iL), cR = sqrt64(gamma * pR * iR);
+    const double aL = fabs(unL) + cL, aR = fabs(unR) + cR;
+    const double hl = 0.5 * fmax(aL, aR);
+    double bhl = 0.0;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      bhl -= gb[v] * (R[v] - L[v]);
+      Lb[v] += hl * gb[v];
+      Rb[v] -= hl * gb[v];
+    }
+    const double baL = aL > aR ? 0.5 * bhl : (aR > aL ? 0.0 : 0.25 * bhl);
+    const double baR = aR > aL ? 0.5 * bhl : (aL > aR ? 0.0 : 0.25 * bhl);
+    bunL += baL * sgn0(unL);
+    bunR += baR * sgn0(unR);
+    const double kL = 0.5 * gamma * baL * rcp64(cL), kR = 0.5 * gamma * baR * rcp64(cR);
+    bpL += kL * iL;
+    biL += kL * pL;
+    bpR += kR * iR;
+    biR += kR * pR;
   } else if (sf == SF_ROE) {
-    const S sL = s_sqrt(L[0]), sR = s_sqrt(R[0]);
-    const S inv = s_rcp(sL + sR);
-    const S ut0 = (sL * unL + sR * unR) * inv;
-    const S ut1 = (sL * u1L + sR * u1R) * inv;
-    const S ut2 = (sL * u2L + sR * u2R) * inv;
-    const S Ht = (sL * hL + sR * hR) * inv;
-    const S rt = sL * sR;
-    const S q2 = ut0 * ut0 + ut1 * ut1 + ut2 * ut2;
-    const S c2 = gm1 * (Ht - 0.5 * q2);
-    const S ct = s_sqrt(c2);
-    const S ic2 = s_rcp(c2);
-    const S dr = R[0] - L[0], dp = pR - pL;
-    const S dun = unR - unL, dt1 = u1R - u1L, dt2 = u2R - u2L;
-    const S a1 = 0.5 * (dp - rt * ct * dun) * ic2;
-    const S a5 = 0.5 * (dp + rt * ct * dun) * ic2;
-    const S a2 = dr - dp * ic2;
-    const S l1 = s_abs(ut0 - ct), l5 = s_abs(ut0 + ct), l2 = s_abs(ut0);
-    const S w1 = l1 * a1, w5 = l5 * a5;
-    const S D0 = w1 + w5 + l2 * a2;
-    const S Dn = w1 * (ut0 - ct) + w5 * (ut0 + ct) + l2 * (a2 * ut0);
-    const S D1 = w1 * ut1 + w5 * ut1 + l2 * (a2 * ut1 + rt * dt1);
-    const S D2 = w1 * ut2 + w5 * ut2 + l2 * (a2 * ut2 + rt * dt2);
-    const S D4 = w1 * (Ht - ct * ut0) + w5 * (Ht + ct * ut0) + l2 * (a2 * (0.5 * q2) + rt * (ut1 * dt1 + ut2 * dt2));
-    g[0] = g[0] - 0.5 * D0;
-    g[1] = g[1] - 0.5 * Dn;
-    g[2] = g[2] - 0.5 * D1;
-    g[3] = g[3] - 0.5 * D2;
-    g[4] = g[4] - 0.5 * D4;
+    const double sL = sqrt64(L[0]), sR = sqrt64(R[0]);
+    const double inv = rcp64(sL + sR);
+    const double ut0 = (sL * unL + sR * unR) * inv;
+    const double ut1 = (sL * u1L + sR * u1R) * inv;
+    const double ut2 = (sL * u2L + sR * u2R) * inv;
+    const double Ht = (sL * hL + sR * hR) * inv;
+    const double rt = sL * sR;
+    const double q2 = ut0 * ut0 + ut1 * ut1 + ut2 * ut2;
+    const double c2 = gm1 * (Ht - 0.5 * q2);
+    const double ct = sqrt64(c2);
+    const double ic2 = rcp64(c2);
+    const double dp = pR - pL;
+    const double dun = unR - unL, dt1 = u1R - u1L, dt2 = u2R - u2L;
+    const double a1 = 0.5 * (dp - rt * ct * dun) * ic2;
+    const double a5 = 0.5 * (dp + rt * ct * dun) * ic2;
+    const double a2 = (R[0] - L[0]) - dp * ic2;
+    const double l1 = fabs(ut0 - ct), l5 = fabs(ut0 + ct), l2 = fabs(ut0);
+    const double w1 = l1 * a1, w5 = l5 * a5;
+    // cotangents of the dissipation terms (f = g - D/2)
+    const double bD0 = -0.5 * gb[0], bDn = -0.5 * gb[1], bD1 = -0.5 * gb[2], bD2 = -0.5 * gb[3],
+                 bD4 = -0.5 * gb[4];
+    const double tt = ut1 * dt1 + ut2 * dt2;
+    double bw1 = bD0 + bDn * (ut0 - ct) + (bD1 * ut1 + bD2 * ut2) + bD4 * (Ht - ct * ut0);
+    double bw5 = bD0 + bDn * (ut0 + ct) + (bD1 * ut1 + bD2 * ut2) + bD4 * (Ht + ct * ut0);
+    double bl2 = bD0 * a2 + bDn * a2 * ut0 + bD1 * (a2 * ut1 + rt * dt1) + bD2 * (a2 * ut2 + rt * dt2) +
+                 bD4 * (a2 * 0.5 * q2 + rt * tt);
+    double ba2 = l2 * (bD0 + bDn * ut0 + bD1 * ut1 + bD2 * ut2 + bD4 * 0.5 * q2);
+    const double wsum = w1 + w5 + l2 * a2;
+    double but0 = bDn * wsum + bD4 * ct * (w5 - w1);
+    double but1 = bD1 * wsum + bD4 * l2 * rt * dt1;
+    double but2 = bD2 * wsum + bD4 * l2 * rt * dt2;
+    double bct = bDn * (w5 - w1) + bD4 * ut0 * (w5 - w1);
+    double bHt = bD4 * (w1 + w5);
+    double bq2 = bD4 * l2 * a2 * 0.5;
+    double brt = l2 * (bD1 * dt1 + bD2 * dt2 + bD4 * tt);
+    const double bdt1 = l2 * rt * (bD1 + bD4 * ut1);
+    const double bdt2 = l2 * rt * (bD2 + bD4 * ut2);
+    // w1 = l1 a1, w5 = l5 a5; the absolute values
+    const double bl1 = bw1 * a1, ba1 = bw1 * l1;
+    const double bl5 = bw5 * a5, ba5 = bw5 * l5;
+    const double s1 = sgn0(ut0 - ct), s5 = sgn0(ut0 + ct);
+    but0 += bl1 * s1 + bl5 * s5 + bl2 * sgn0(ut0);
+    bct += -bl1 * s1 + bl5 * s5;
+    // wave strengths
+    const double bdr = ba2;
+    double bdp = -ba2 * ic2 + 0.5 * (ba1 + ba5) * ic2;
+    double bic2 = -ba2 * dp + ba1 * 0.5 * (dp - rt * ct * dun) + ba5 * 0.5 * (dp + rt * ct * dun);
+    const double kd = 0.5 * (ba5 - ba1) * ic2;
+    brt += kd * ct * dun;
+    bct += kd * rt * dun;
+    const double bdun = kd * rt * ct;
+    // sound speed and Roe averages
+    double bc2 = -bic2 * ic2 * ic2 + bct * 0.5 * rcp64(ct);
+    bHt += gm1 * bc2;
+    bq2 -= 0.5 * gm1 * bc2;
+    but0 += 2.0 * ut0 * bq2;
+    but1 += 2.0 * ut1 * bq2;
+    but2 += 2.0 * ut2 * bq2;
+    double bsL = brt * sR, bsR = brt * sL;
+    const double binv = but0 * (sL * unL + sR * unR) + but1 * (sL * u1L + sR * u1R) + but2 * (sL * u2L + sR * u2R) +
+                        bHt * (sL * hL + sR * hR);
+    bsL += inv * (but0 * unL + but1 * u1L + but2 * u2L + bHt * hL);
+    bsR += inv * (but0 * unR + but1 * u1R + but2 * u2R + bHt * hR);
+    bunL += but0 * sL * inv;
+    bunR += but0 * sR * inv;
+    bu1L += but1 * sL * inv;
+    bu1R += but1 * sR * inv;
+    bu2L += but2 * sL * inv;
+    bu2R += but2 * sR * inv;
+    bhL += bHt * sL * inv;
+    bhR += bHt * sR * inv;
+    const double bS = -binv * inv * inv;
+    bsL += bS;
+    bsR += bS;
+    Lb[0] += bsL * 0.5 * rcp64(sL) - bdr;
+    Rb[0] += bsR * 0.5 * rcp64(sR) + bdr;
+    bpL -= bdp;
+    bpR += bdp;
+    bunL -= bdun;
+    bunR += bdun;
+    bu1L -= bdt1;
+    bu1R += bdt1;
+    bu2L -= bdt2;
+    bu2R += bdt2;
   }
-  f[0] = g[0];
-  f[kn] = g[1];
-  f[k1] = g[2];
-  f[k2] = g[3];
-  f[4] = g[4];
+  // primitives -> conservative state, each side: h = (E + p)/rho,
+  // p = (g-1)(E - (m . u)/2), u = m/rho
+  {
+    Lb[4] += bhL * iL;
+    bpL += bhL * iL;
+    biL += bhL * (L[4] + pL);
+    Lb[4] += gm1 * bpL;
+    const double kp = -0.5 * gm1 * bpL;
+    Lb[1] += kp * unL;
+    Lb[2] += kp * u1L;
+    Lb[3] += kp * u2L;
+    bunL += kp * L[1];
+    bu1L += kp * L[2];
+    bu2L += kp * L[3];
+    Lb[1] += bunL * iL;
+    Lb[2] += bu1L * iL;
+    Lb[3] += bu2L * iL;
+    biL += bunL * L[1] + bu1L * L[2] + bu2L * L[3];
+    Lb[0] -= biL * iL * iL;
+  }
+  {
+    Rb[4] += bhR * iR;
+    bpR += bhR * iR;
+    biR += bhR * (R[4] + pR);
+    Rb[4] += gm1 * bpR;
+    const double kp = -0.5 * gm1 * bpR;
+    Rb[1] += kp * unR;
+    Rb[2] += kp * u1R;
+    Rb[3] += kp * u2R;
+    bunR += kp * R[1];
+    bu1R += kp * R[2];
+    bu2R += kp * R[3];
+    Rb[1] += bunR * iR;
+    Rb[2] += bu1R * iR;
+    Rb[3] += bu2R * iR;
+    biR += bunR * R[1] + bu1R * R[2] + bu2R * R[3];
+    Rb[0] -= biR * iR * iR;
+  }
 }
 
 // Cotangent of the lifted viscous flux at node m in all three directions,
@@ -1655,42 +1763,35 @@ __global__ __launch_bounds__(NT) void k_vjp_lift(VjpArgs A) {
   }
 }
 
-// Interface part of face item q, seed k: component k of the cotangent of the
-// element's own face state, (d f*/d U_own,k) . fbar with
-// fbar = -(2/dx_d)(lambda_- / w_N - lambda_+ / w_0), by one dual-number
-// evaluation of the interface flux.  Each (item, seed) pair is a separate
-// work unit: the five seeds share no registers.  One code path for all
-// directions: states, seed and cotangent are rotated by address (normal
-// component first), the flux is evaluated in the rotated frame.
+// Interface part of face item q: the cotangent of the element's own face
+// state, (d f*/d U_own)^T fbar with fbar = -(2/dx_d)(lambda_- / w_N -
+// lambda_+ / w_0), by the reverse sweep of the interface flux (riemann_vjp).
+// One code path for all directions: states and cotangent are rotated by
+// address (normal component first).
 template <int VF>
-__device__ __forceinline__ void vjp_face_seed(const VjpArgs& A, int e, int q, int k, const double* swinv,
+__device__ __forceinline__ void vjp_face_item(const VjpArgs& A, int e, int q, const double* swinv,
                                               double (*sSF)[5][nf]) {
   const FaceItem it = face_item_geometry(A.nbr, e, q);
   const int eL = it.side ? e : it.nb, eR = it.side ? it.nb : e;
   const int nL = it.side ? it.nown : it.nnb, nR = it.side ? it.nnb : it.nown;
   const int row[5] = {0, 1 + it.d, it.k1, it.k2, 4};  // rotated position -> variable
-  const int own = it.side;  // 1: own element is the minus side
   const double* UL = A.U + (size_t)eL * 5 * nn;
   const double* UR = A.U + (size_t)eR * 5 * nn;
   const double* LL = A.Lbar + (size_t)eL * 5 * nn;
   const double* LR = A.Lbar + (size_t)eR * 5 * nn;
   const double invJd = it.d == 0 ? A.invJ[0] : (it.d == 1 ? A.invJ[1] : A.invJ[2]);
   const double cm = -invJd * swinv[N], cp = invJd * swinv[0];
-  Dl Ld[5], Rd[5], fd[5];
-  double fb[5];
+  double L[5], R[5], fb[5], Lb[5], Rb[5];
 #pragma unroll
   for (int r = 0; r < 5; ++r) {
     const int v = row[r];
-    const double seed = v == k ? 1.0 : 0.0;
-    Ld[r] = {UL[v * nn + nL], own ? seed : 0.0};
-    Rd[r] = {UR[v * nn + nR], own ? 0.0 : seed};
+    L[r] = UL[v * nn + nL];
+    R[r] = UR[v * nn + nR];
     fb[r] = fma(cm, LL[v * nn + nL], cp * LR[v * nn + nR]);
   }
-  riemann_generic<VF, 0, Dl>(A.sf, Ld, Rd, A.gamma, fd);
-  double s = 0.0;
+  riemann_vjp<VF>(A.sf, L, R, A.gamma, fb, Lb, Rb);
 #pragma unroll
-  for (int r = 0; r < 5; ++r) s = fma(fb[r], fd[r].d, s);
-  sSF[it.f][k][it.a] = s;
+  for (int r = 0; r < 5; ++r) sSF[it.f][row[r]][it.a] = it.side ? Lb[r] : Rb[r];
 }
 
 // Navier-Stokes data of face item q: q* (forward gradient), the neighbour's
@@ -1817,14 +1918,9 @@ __global__ __launch_bounds__(NT) void k_vjp(VjpArgs A) {
     ijk[1] = (t / n1) % n1;
     ijk[2] = t / nf;
   }
-  __syncthreads();  // the face seeds read the basis (swinv)
-  // (face item, seed) work units, seed-major so that neighbouring lanes take
-  // neighbouring face nodes
+  __syncthreads();  // the face items read the basis (swinv)
 #pragma unroll 1
-  for (int w = t; w < 5 * 6 * nf; w += NT) {
-    const int k = w / (6 * nf), q = w - k * (6 * nf);
-    vjp_face_seed<VF>(A, e, q, k, swinv, sSF);
-  }
+  for (int q = t; q < 6 * nf; q += NT) vjp_face_item<VF>(A, e, q, swinv, sSF);
   if (NS) {
     for (int q = t; q < 6 * nf; q += NT) {
       if (q < 2 * nf) vjp_face_ns<0>(A, e, q, sQ, sLn, sGn);
@@ -2186,13 +2282,12 @@ __global__ __launch_bounds__(NT) void k_vjp_fv(VjpArgs A) {
     const int c1 = d == 2 ? 0 : d + 1, c2 = d == 0 ? 2 : (d == 1 ? 0 : 1);  // tangential velocity (cyclic)
     __syncthreads();
 #pragma unroll 1
-    for (int w = t; w < 10 * N * nf; w += NT) {
-      const int k = w / (N * nf), i = w - k * (N * nf);
+    for (int i = t; i < N * nf; i += NT) {
       const int m = i / nf, a = i - m * nf;
       const int nm = face_node(d, m, a), base = nm - m * st;
-      double wp[5], wm[5];
-      subcell_face_state(sW, base, st, m, true, A.recon, sxi, sedge, wp);
-      subcell_face_state(sW, base, st, m + 1, false, A.recon, sxi, sedge, wm);
+      double W[2][5];
+      subcell_face_state(sW, base, st, m, true, A.recon, sxi, sedge, W[0]);
+      subcell_face_state(sW, base, st, m + 1, false, A.recon, sxi, sedge, W[1]);
       // flux cotangent (conservative, rotated): a (2/dx_d)(lambda_{m+1}/w_{m+1} - lambda_m/w_m)
       const double invJd = d == 0 ? A.invJ[0] : (d == 1 ? A.invJ[1] : A.invJ[2]);
       const int np = nm + st;
@@ -2201,20 +2296,15 @@ __global__ __launch_bounds__(NT) void k_vjp_fv(VjpArgs A) {
 #pragma unroll
       for (int r = 0; r < 5; ++r)
         fb[r] = al * invJd * (sL[row[r]][np] * swinv[m + 1] - sL[row[r]][nm] * swinv[m]);
-      // dual primitive states, then conservative in the rotated frame
-      Dl W[2][5];
-#pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        W[0][v] = {wp[v], k == v ? 1.0 : 0.0};
-        W[1][v] = {wm[v], k == 5 + v ? 1.0 : 0.0};
-      }
-      Dl C[2][5];
+      // conservative states in the rotated frame, the reverse sweep of the
+      // interface flux, and the pullback to both primitive face states
+      double C[2][5], Cb[2][5];
 #pragma unroll
       for (int sd = 0; sd < 2; ++sd) {
-        const Dl r = W[sd][0];
-        const Dl un = d == 0 ? W[sd][1] : (d == 1 ? W[sd][2] : W[sd][3]);
-        const Dl u1 = c1 == 0 ? W[sd][1] : (c1 == 1 ? W[sd][2] : W[sd][3]);
-        const Dl u2 = c2 == 0 ? W[sd][1] : (c2 == 1 ? W[sd][2] : W[sd][3]);
+        const double r = W[sd][0];
+        const double un = d == 0 ? W[sd][1] : (d == 1 ? W[sd][2] : W[sd][3]);
+        const double u1 = c1 == 0 ? W[sd][1] : (c1 == 1 ? W[sd][2] : W[sd][3]);
+        const double u2 = c2 == 0 ? W[sd][1] : (c2 == 1 ? W[sd][2] : W[sd][3]);
         C[sd][0] = r;
         C[sd][1] = r * un;
         C[sd][2] = r * u1;
@@ -2222,12 +2312,21 @@ __global__ __launch_bounds__(NT) void k_vjp_fv(VjpArgs A) {
         C[sd][4] = W[sd][4] * (1.0 / gm1) + 0.5 * r * (W[sd][1] * W[sd][1] + W[sd][2] * W[sd][2] +
                                                        W[sd][3] * W[sd][3]);
       }
-      Dl fd[5];
-      riemann_generic<VF, 0, Dl>(A.sf, C[0], C[1], A.gamma, fd);
-      double s = 0.0;
+      riemann_vjp<VF>(A.sf, C[0], C[1], A.gamma, fb, Cb[0], Cb[1]);
 #pragma unroll
-      for (int r = 0; r < 5; ++r) s = fma(fb[r], fd[r].d, s);
-      sG[i][k] = s;
+      for (int sd = 0; sd < 2; ++sd) {
+        const double r = W[sd][0];
+        const double un = d == 0 ? W[sd][1] : (d == 1 ? W[sd][2] : W[sd][3]);
+        const double u1 = c1 == 0 ? W[sd][1] : (c1 == 1 ? W[sd][2] : W[sd][3]);
+        const double u2 = c2 == 0 ? W[sd][1] : (c2 == 1 ? W[sd][2] : W[sd][3]);
+        const double* B = Cb[sd];
+        const double q2h = 0.5 * (W[sd][1] * W[sd][1] + W[sd][2] * W[sd][2] + W[sd][3] * W[sd][3]);
+        sG[i][5 * sd + 0] = B[0] + B[1] * un + B[2] * u1 + B[3] * u2 + B[4] * q2h;
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+          sG[i][5 * sd + 1 + j] = (j == d ? B[1] : (j == c1 ? B[2] : B[3])) * r + B[4] * r * W[sd][1 + j];
+        sG[i][5 * sd + 4] = B[4] * (1.0 / gm1);
+      }
     }
     __syncthreads();
     // pullback of the reconstruction, per (line, variable)
@@ -3156,12 +3255,12 @@ __global__ __launch_bounds__(PLC::NTB) void k_lift_curved(StageArgs A) {
 // which the neighbour's pass 2 (k_vjp_curved) reads.
 // ===========================================================================
 
-// Interface flux along the unit normal n over a generic scalar (dual numbers):
-// rotation into the frame (n, t1, t2) of surface_flux_normal, rotated-frame
-// flux, rotation back.
-template <int VF, class S>
-__device__ __forceinline__ void flux_normal_generic(int sf, const S L[5], const S R[5], const double n[3],
-                                                    double gamma, S f[5]) {
+// Reverse mode of the interface flux along the unit normal n: the cotangent
+// rotated into the frame (n, t1, t2), the rotated-frame reverse sweep
+// (riemann_vjp), the state cotangents rotated back.
+template <int VF>
+__device__ __forceinline__ void flux_normal_vjp(int sf, const double L[5], const double R[5], const double n[3],
+                                                double gamma, const double fb[5], double Lb[5], double Rb[5]) {
   const double ax = fabs(n[0]), ay = fabs(n[1]), az = fabs(n[2]);
   double t1[3];
   if (ax <= ay && ax <= az) {
@@ -3174,7 +3273,7 @@ __device__ __forceinline__ void flux_normal_generic(int sf, const S L[5], const 
   const double it = rcp64(sqrt64(t1[0] * t1[0] + t1[1] * t1[1] + t1[2] * t1[2]));
   t1[0] *= it; t1[1] *= it; t1[2] *= it;
   const double t2[3] = {n[1] * t1[2] - n[2] * t1[1], n[2] * t1[0] - n[0] * t1[2], n[0] * t1[1] - n[1] * t1[0]};
-  S a[5], b[5], g[5];
+  double a[5], b[5], gb[5], ab[5], bb[5];
   a[0] = L[0]; a[4] = L[4];
   b[0] = R[0]; b[4] = R[4];
   a[1] = n[0] * L[1] + n[1] * L[2] + n[2] * L[3];
@@ -3183,12 +3282,19 @@ __device__ __forceinline__ void flux_normal_generic(int sf, const S L[5], const 
   b[1] = n[0] * R[1] + n[1] * R[2] + n[2] * R[3];
   b[2] = t1[0] * R[1] + t1[1] * R[2] + t1[2] * R[3];
   b[3] = t2[0] * R[1] + t2[1] * R[2] + t2[2] * R[3];
-  riemann_generic<VF, 0, S>(sf, a, b, gamma, g);
-  f[0] = g[0];
-  f[1] = n[0] * g[1] + t1[0] * g[2] + t2[0] * g[3];
-  f[2] = n[1] * g[1] + t1[1] * g[2] + t2[1] * g[3];
-  f[3] = n[2] * g[1] + t1[2] * g[2] + t2[2] * g[3];
-  f[4] = g[4];
+  gb[0] = fb[0];
+  gb[1] = n[0] * fb[1] + n[1] * fb[2] + n[2] * fb[3];
+  gb[2] = t1[0] * fb[1] + t1[1] * fb[2] + t1[2] * fb[3];
+  gb[3] = t2[0] * fb[1] + t2[1] * fb[2] + t2[2] * fb[3];
+  gb[4] = fb[4];
+  riemann_vjp<VF>(sf, a, b, gamma, gb, ab, bb);
+  Lb[0] = ab[0]; Lb[4] = ab[4];
+  Rb[0] = bb[0]; Rb[4] = bb[4];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    Lb[1 + j] = n[j] * ab[1] + t1[j] * ab[2] + t2[j] * ab[3];
+    Rb[1 + j] = n[j] * bb[1] + t1[j] * bb[2] + t2[j] * bb[3];
+  }
 }
 
 // The minus (L) and plus (R) side of a curved face item and its normal
@@ -3272,12 +3378,12 @@ __device__ __forceinline__ void volume_vjp_dir_curved(const double (*sP)[nn], co
   }
 }
 
-// Interface part of face item q, seed k: (d ft*/d U_own,k) . fbar, ft* the
-// face flux |N| f*(U_L, U_R; N/|N|) in its canonical orientation and fbar its
+// Interface part of curved face item q: (d ft*/d U_own)^T fbar, ft* the face
+// flux |N| f*(U_L, U_R; N/|N|) in its canonical orientation and fbar its
 // cotangent, sum over both elements of (lifting coefficient) x (orientation
-// sign) x lt at their face node.
+// sign) x lt at their face node (flux_normal_vjp).
 template <int VF>
-__device__ __forceinline__ void vjp_face_seed_curved(const VjpArgs& A, int e, int q, int k, const double* swinv,
+__device__ __forceinline__ void vjp_face_item_curved(const VjpArgs& A, int e, int q, const double* swinv,
                                                      double (*sSF)[5][nf]) {
   const CFaceItem it = cface(A.conn, A.nbr, e, q);
   const CurvedSides c = curved_sides(it, e);
@@ -3294,20 +3400,16 @@ __device__ __forceinline__ void vjp_face_seed_curved(const VjpArgs& A, int e, in
   const double* UR = A.U + (size_t)c.eR * 5 * nn;
   const double* Lo = A.Lbar + (size_t)e * 5 * nn;
   const double* Lb = A.Lbar + (size_t)it.nb * 5 * nn;
-  Dl Ld[5], Rd[5], fd[5];
-  double fb[5];
+  double L[5], R[5], fb[5], Lc[5], Rc[5];
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
-    const double seed = v == k ? 1.0 : 0.0;
-    Ld[v] = {UL[v * nn + c.nL], it.own_minus ? seed : 0.0};
-    Rd[v] = {UR[v * nn + c.nR], it.own_minus ? 0.0 : seed};
+    L[v] = UL[v * nn + c.nL];
+    R[v] = UR[v * nn + c.nR];
     fb[v] = fma(co, Lo[v * nn + it.nown], cb * Lb[v * nn + it.nnb]);
   }
-  flux_normal_generic<VF, Dl>(A.sf, Ld, Rd, nv, A.gamma, fd);
-  double s = 0.0;
+  flux_normal_vjp<VF>(A.sf, L, R, nv, A.gamma, fb, Lc, Rc);
 #pragma unroll
-  for (int v = 0; v < 5; ++v) s = fma(fb[v], fd[v].d, s);
-  sSF[it.f][k][it.a] = sh * s;
+  for (int v = 0; v < 5; ++v) sSF[it.f][v][it.a] = sh * (it.own_minus ? Lc[v] : Rc[v]);
 }
 
 // Navier-Stokes face data of face item q: the face metric along the own +xi
@@ -3487,10 +3589,7 @@ __global__ __launch_bounds__(NT) void k_vjp_curved(VjpArgs A) {
   }
   __syncthreads();  // swinv
 #pragma unroll 1
-  for (int w = t; w < 5 * 6 * nf; w += NT) {
-    const int k = w / (6 * nf), q = w - k * (6 * nf);
-    vjp_face_seed_curved<VF>(A, e, q, k, swinv, sSF);
-  }
+  for (int q = t; q < 6 * nf; q += NT) vjp_face_item_curved<VF>(A, e, q, swinv, sSF);
   if (NS)
     for (int q = t; q < 6 * nf; q += NT) vjp_face_ns_curved<true>(A, e, q, swinv, sJo, sLn, sQ, sGn);
   __syncthreads();
