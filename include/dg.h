@@ -242,6 +242,22 @@ int dg_vjp(dg_ctx* ctx, const double* U, const double* Ut_bar, double* U_bar);
  * restrictions as dg_vjp; allocates seven state-sized buffers on first use. */
 int rk_step_vjp(dg_ctx* ctx, const double* U_n, double dt, const double* U_bar_np1, double* U_bar_n);
 
+/* One rk_step in place on U that also records its five stage states: Y is a
+ * device pointer to 5 x (nElems x 5 x (N+1)^3) doubles owned by the caller,
+ * filled with Y_0 = U_n, Y_1, ..., Y_4 (the inputs of the five stages; paper
+ * Sec. 4: the explicit Runge-Kutta scheme).  U ends as U_{n+1}, bitwise the
+ * same as rk_step.  For checkpointed reverse sweeps that keep the stage states
+ * of a segment instead of recomputing them in rk_step_vjp.  Errors: DG_EINVAL
+ * for host pointers, dt not finite and > 0, or Y overlapping U. */
+int rk_step_record(dg_ctx* ctx, double* U, double dt, double* Y);
+
+/* rk_step_vjp from the stage states recorded by rk_step_record (Y, read
+ * only): the same reverse recurrence without recomputing the stages, so the
+ * same result bitwise.  U_bar_n may alias U_bar_np1; neither may overlap Y.
+ * Same restrictions as dg_vjp; allocates two state-sized buffers on first
+ * use. */
+int rk_step_vjp_recorded(dg_ctx* ctx, const double* Y, double dt, const double* U_bar_np1, double* U_bar_n);
+
 /* Stable time step: cfl * min(1/((N+1) max sum_d (|u_d|+c)/dx_d),
  *                             1/((N+1)^2 max nu_eff sum_d 1/dx_d^2)),
  * nu_eff = mu gamma/(rho Pr) for DG_NS.  Synchronises. */

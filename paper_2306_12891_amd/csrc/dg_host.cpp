@@ -424,15 +424,16 @@ int vjp_supported(dg_ctx* c) {
   return DG_OK;
 }
 
-// Reverse-mode scratch, allocated on first use.
-int ensure_reverse_buffers(dg_ctx* c, bool rk) {
+// Reverse-mode scratch, allocated on first use (stages: the five stage states
+// that rk_step_vjp recomputes).
+int ensure_reverse_buffers(dg_ctx* c, bool rk, bool stages = true) {
   hipError_t e = hipSuccess;
   const size_t bytes = c->nstate * sizeof(double);
   if (!c->Gbf) e = hipMalloc((void**)&c->Gbf, (size_t)c->nelem * 6 * 4 * c->nf * sizeof(double));
   if (e == hipSuccess && c->opt.blending && !c->Dfd) e = hipMalloc((void**)&c->Dfd, bytes);
   if (e == hipSuccess && c->opt.blending && !c->abar) e = hipMalloc((void**)&c->abar, (size_t)c->nelem * sizeof(double));
   if (rk) {
-    for (int k = 0; k < 5 && e == hipSuccess; ++k)
+    for (int k = 0; k < 5 && e == hipSuccess && stages; ++k)
       if (!c->Y[k]) e = hipMalloc((void**)&c->Y[k], bytes);
     if (e == hipSuccess && !c->Gbar) e = hipMalloc((void**)&c->Gbar, bytes);
     if (e == hipSuccess && !c->Ybar) e = hipMalloc((void**)&c->Ybar, bytes);
@@ -879,6 +880,65 @@ int dg_vjp(dg_ctx* c, const double* U, const double* Ut_bar, double* U_bar) {
   return run_vjp(c, U, Ut_bar, U_bar, nullptr);
 }
 
+}  // extern "C"
+
+namespace {
+
+bool overlaps(const double* a, size_t na, const double* b, size_t nb) { return a < b + nb && b < a + na; }
+
+// Reverse 2N-storage recurrence over the stage states Ys[0..4] of one step:
+//   Gbar <- A_{k+1} Gbar + B_k dt Ybar,  Ybar <- Ybar + VJP(Y_k, Gbar), k = 4..0.
+int rk_reverse(dg_ctx* c, const double* const Ys[5], double dt, const double* U_bar_np1, double* U_bar_n,
+               const char* where) {
+  const size_t bytes = c->nstate * sizeof(double);
+  hipError_t e = hipMemcpyAsync(c->Ybar, U_bar_np1, bytes, hipMemcpyDeviceToDevice, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, where);
+  for (int k = 4; k >= 0; --k) {
+    const double a = (k == 4) ? 0.0 : kA[k + 1];
+    e = c->kt->axpby(c->Gbar, a, c->Ybar, kB[k] * dt, c->nstate, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, where);
+    const int rc = run_vjp(c, Ys[k], c->Gbar, c->Ybar, c->Ybar);
+    if (rc) return rc;
+  }
+  e = hipMemcpyAsync(U_bar_n, c->Ybar, bytes, hipMemcpyDeviceToDevice, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, where);
+  return DG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rk_step_record(dg_ctx* c, double* U, double dt, double* Y) {
+  if (check_ctx(c)) return DG_EINVAL;
+  if (!is_device_ptr(U) || !is_device_ptr(Y)) return fail(c, DG_EINVAL, "rk_step_record: device pointers required");
+  if (!finite_pos(dt)) return fail(c, DG_EINVAL, "rk_step_record: dt must be finite and > 0");
+  const size_t n = c->nstate;
+  if (overlaps(U, n, Y, 5 * n)) return fail(c, DG_EINVAL, "rk_step_record: Y overlaps U");
+  hipError_t e = hipMemcpyAsync(Y, U, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "rk_step_record copy");
+  for (int k = 0; k < 4; ++k) {
+    const int rc = run_stage(c, Y + k * n, Y + (k + 1) * n, nullptr, MODE_RK, kA[k], kB[k] * dt, 1, nullptr);
+    if (rc) return rc;
+  }
+  return run_stage(c, Y + 4 * n, U, nullptr, MODE_RK, kA[4], kB[4] * dt, 0, nullptr);
+}
+
+int rk_step_vjp_recorded(dg_ctx* c, const double* Y, double dt, const double* U_bar_np1, double* U_bar_n) {
+  if (check_ctx(c)) return DG_EINVAL;
+  if (!is_device_ptr(Y) || !is_device_ptr(U_bar_np1) || !is_device_ptr(U_bar_n))
+    return fail(c, DG_EINVAL, "rk_step_vjp_recorded: device pointers required");
+  if (!finite_pos(dt)) return fail(c, DG_EINVAL, "rk_step_vjp_recorded: dt must be finite and > 0");
+  const size_t n = c->nstate;
+  if (overlaps(U_bar_n, n, Y, 5 * n) || overlaps(U_bar_np1, n, Y, 5 * n))
+    return fail(c, DG_EINVAL, "rk_step_vjp_recorded: a cotangent overlaps Y");
+  int rc = vjp_supported(c);
+  if (rc) return rc;
+  if ((rc = ensure_reverse_buffers(c, true, false))) return rc;
+  const double* Ys[5] = {Y, Y + n, Y + 2 * n, Y + 3 * n, Y + 4 * n};
+  return rk_reverse(c, Ys, dt, U_bar_np1, U_bar_n, "rk_step_vjp_recorded");
+}
+
 int rk_step_vjp(dg_ctx* c, const double* U_n, double dt, const double* U_bar_np1, double* U_bar_n) {
   if (check_ctx(c)) return DG_EINVAL;
   if (!is_device_ptr(U_n) || !is_device_ptr(U_bar_np1) || !is_device_ptr(U_bar_n))
@@ -894,18 +954,8 @@ int rk_step_vjp(dg_ctx* c, const double* U_n, double dt, const double* U_bar_np1
   // forward: stage states Y_1..Y_4 (Y_5 = U_{n+1} is not needed)
   for (int k = 0; k < 4; ++k)
     if ((rc = run_stage(c, c->Y[k], c->Y[k + 1], nullptr, MODE_RK, kA[k], kB[k] * dt, 1, nullptr))) return rc;
-  // reverse: Gbar <- A_{k+1} Gbar + B_k dt Ybar;  Ybar += VJP(Y_k, Gbar)
-  e = hipMemcpyAsync(c->Ybar, U_bar_np1, bytes, hipMemcpyDeviceToDevice, c->stream);
-  if (e != hipSuccess) return hip_fail(c, e, "rk_step_vjp copy");
-  for (int k = 4; k >= 0; --k) {
-    const double a = (k == 4) ? 0.0 : kA[k + 1];
-    e = c->kt->axpby(c->Gbar, a, c->Ybar, kB[k] * dt, c->nstate, c->stream);
-    if (e != hipSuccess) return hip_fail(c, e, "rk_step_vjp axpby");
-    if ((rc = run_vjp(c, c->Y[k], c->Gbar, c->Ybar, c->Ybar))) return rc;
-  }
-  e = hipMemcpyAsync(U_bar_n, c->Ybar, bytes, hipMemcpyDeviceToDevice, c->stream);
-  if (e != hipSuccess) return hip_fail(c, e, "rk_step_vjp copy");
-  return DG_OK;
+  const double* Ys[5] = {c->Y[0], c->Y[1], c->Y[2], c->Y[3], c->Y[4]};
+  return rk_reverse(c, Ys, dt, U_bar_np1, U_bar_n, "rk_step_vjp");
 }
 
 int dg_max_dt(dg_ctx* c, const double* U, double cfl, double* dt_out) {

@@ -31,7 +31,7 @@ EXPORTS = ["dg_default_options", "dg_init", "dg_set_options", "dg_get_options", 
            "dg_time_derivative", "rk_step", "dg_rk_steps", "dg_vjp", "rk_step_vjp", "dg_max_dt",
            "dg_integrals", "dg_alpha", "dg_check_finite", "dg_set_profiling", "dg_profile_read", "dg_node_weights",
            "dg_sizes", "dg_finalize", "dg_last_error", "dg_set_cs_field", "dg_set_geometry",
-           "dg_set_connectivity", "dg_set_wall_model"]
+           "dg_set_connectivity", "dg_set_wall_model", "rk_step_record", "rk_step_vjp_recorded"]
 
 
 class DGError(RuntimeError):
@@ -89,6 +89,8 @@ def lib() -> ctypes.CDLL:
             "dg_set_geometry": ([P, P], I),
             "dg_set_connectivity": ([P, P], I),
             "dg_set_wall_model": ([P, I, ctypes.c_double, ctypes.c_double], I),
+            "rk_step_record": ([P, P, ctypes.c_double, P], I),
+            "rk_step_vjp_recorded": ([P, P, ctypes.c_double, P, P], I),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -253,6 +255,33 @@ class DG:
                                       ctypes.c_void_p(po)))
         return out
 
+    def _stages(self, Y: torch.Tensor) -> int:
+        if not isinstance(Y, torch.Tensor) or not Y.is_cuda or Y.dtype != torch.float64:
+            raise TypeError("Y must be a float64 GPU tensor")
+        if tuple(Y.shape) != (5,) + self.shape or not Y.is_contiguous():
+            raise ValueError(f"Y must be contiguous of shape {(5,) + self.shape}")
+        return Y.data_ptr()
+
+    def rk_step_record(self, U: torch.Tensor, dt: float, Y: torch.Tensor) -> torch.Tensor:
+        """rk_step in place on U that also writes its five stage states into Y
+        (shape (5,) + U.shape)."""
+        pu, py = self._state(U, "U"), self._stages(Y)
+        self._stream()
+        self._check(lib().rk_step_record(self._ctx, ctypes.c_void_p(pu), float(dt), ctypes.c_void_p(py)))
+        return U
+
+    def rk_step_vjp_recorded(self, Y: torch.Tensor, dt: float, U_bar_np1: torch.Tensor,
+                             out: torch.Tensor | None = None) -> torch.Tensor:
+        """rk_step_vjp from the stage states recorded by rk_step_record."""
+        py, pb = self._stages(Y), self._state(U_bar_np1, "U_bar_np1")
+        if out is None:
+            out = torch.empty_like(U_bar_np1)
+        po = self._state(out, "U_bar_n")
+        self._stream()
+        self._check(lib().rk_step_vjp_recorded(self._ctx, ctypes.c_void_p(py), float(dt), ctypes.c_void_p(pb),
+                                               ctypes.c_void_p(po)))
+        return out
+
     # -- diagnostics ------------------------------------------------------
     def max_dt(self, U: torch.Tensor, cfl: float = 0.5) -> float:
         pu = self._state(U, "U")
@@ -360,15 +389,17 @@ class _Rollout(torch.autograd.Function):
     def backward(ctx, g):
         op, dt, every = ctx.op, ctx.dt, ctx.every
         Ub = g.contiguous().clone()
+        Y = None
         for s0 in sorted(ctx.ckpt, reverse=True):
             s1 = min(s0 + every, ctx.nsteps)
-            states = [ctx.ckpt[s0]]
+            # recompute the segment once, keeping every step's stage states
+            if Y is None or Y.shape[0] < s1 - s0:
+                Y = torch.empty((s1 - s0, 5) + tuple(Ub.shape), dtype=Ub.dtype, device=Ub.device)
             U = ctx.ckpt[s0].clone()
-            for _ in range(s0, s1 - 1):
-                op.rk_step(U, dt)
-                states.append(U.clone())
+            for k in range(s1 - s0):
+                op.rk_step_record(U, dt, Y[k])
             for k in reversed(range(s1 - s0)):
-                op.rk_step_vjp(states[k], dt, Ub, out=Ub)
+                op.rk_step_vjp_recorded(Y[k], dt, Ub, out=Ub)
         ctx.ckpt = None
         return Ub, None, None, None, None
 
@@ -376,6 +407,7 @@ class _Rollout(torch.autograd.Function):
 def rollout(op: DG, U0: torch.Tensor, dt: float, nsteps: int, checkpoint_every: int = 20) -> torch.Tensor:
     """nsteps LSERK4 steps from U0, differentiable with respect to U0: the
     forward keeps the state every checkpoint_every steps and the backward
-    recomputes each segment from its checkpoint before running the reverse
-    steps (memory: checkpoints + one segment of states)."""
+    recomputes each segment from its checkpoint once, keeping the five stage
+    states of every step, before running the reverse steps on them (memory:
+    checkpoints + 5 x checkpoint_every states)."""
     return _Rollout.apply(U0, op, dt, nsteps, checkpoint_every)

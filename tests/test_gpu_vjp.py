@@ -3,6 +3,7 @@ functions and the checkpointed rollout) against the oracle's forward-mode
 dual numbers (the oracle has no transpose: the identity <w, J v> = <J^T w, v>
 checks one against the other), a full Jacobian on a one-element mesh, and
 central finite differences of a rollout functional."""
+import ctypes
 import math
 
 import numpy as np
@@ -88,6 +89,37 @@ def test_rk_step_vjp_dot_product(orc, torch_cuda, eq, vf, sf):
     # in-place form (U_bar_n aliasing U_bar_np1) gives the same result
     op.rk_step_vjp(Ud, dt, wd, out=wd)
     assert np.array_equal(wd.cpu().numpy(), JTw)
+
+
+@pytest.mark.parametrize("eq,vf,sf", [(0, 0, 0), (1, 1, 1)])
+def test_recorded_stages(orc, torch_cuda, eq, vf, sf):
+    """rk_step_record advances U bitwise as rk_step, starts its stage record
+    with U_n, and rk_step_vjp_recorded on that record equals rk_step_vjp
+    bitwise (the same stage states, not recomputed)."""
+    import torch
+
+    from paper_2306_12891_amd import dg
+    N, nelem = 3, (2, 3, 2)
+    s, op = make(orc, N, nelem, eq, vf, sf)
+    U0 = torch.from_numpy(I.random_smooth(N, nelem, seed=23, noise=0.01)).cuda()
+    w = torch.from_numpy(I.random_directions(U0.shape, 6)).cuda()
+    dt = 0.5 * orc.max_dt(s, U0.cpu().numpy(), 0.5)
+    Y = torch.empty((5,) + tuple(U0.shape), dtype=torch.float64, device="cuda")
+    Ua, Ub = U0.clone(), U0.clone()
+    op.rk_step(Ua, dt)
+    op.rk_step_record(Ub, dt, Y)
+    assert torch.equal(Ua, Ub)
+    assert torch.equal(Y[0], U0)
+    assert not torch.equal(Y[1], Y[0]) and not torch.equal(Y[4], Ua)
+    ref = op.rk_step_vjp(U0, dt, w)
+    got = op.rk_step_vjp_recorded(Y, dt, w)
+    assert torch.equal(ref, got)
+    # errors: Y overlapping U or the output
+    Yb = torch.empty((5,) + tuple(U0.shape), dtype=torch.float64, device="cuda")
+    assert op.raw_call("rk_step_record", ctypes.c_void_p(Yb[2].data_ptr()), ctypes.c_double(dt),
+                       ctypes.c_void_p(Yb.data_ptr())) == dg.DG_EINVAL
+    assert op.raw_call("rk_step_vjp_recorded", ctypes.c_void_p(Y.data_ptr()), ctypes.c_double(dt),
+                       ctypes.c_void_p(w.data_ptr()), ctypes.c_void_p(Y[3].data_ptr())) == dg.DG_EINVAL
 
 
 def test_autograd_functions(orc, torch_cuda):
