@@ -848,7 +848,8 @@ static void viscous_flux(int d, double g, double mu, double Pr, double csd2, dou
         const T Sij = 0.5 * (gr[j][i] + gr[i][j]);  // du_i/dx_j = gr[j][i]
         SS = SS + Sij * Sij;
       }
-    const T mut = P.rho * csd2 * sqrt_(2.0 * SS);
+    // |S| = sqrt(2 S_ij S_ij); derivative 0 where |S| = 0 (as |x|' = 0 at 0)
+    const T mut = P.rho * csd2 * (value(SS) > 0.0 ? sqrt_(2.0 * SS) : T(0.0));
     mu_e = mu_e + mut;
     kap_e = kap_e + mut * (g / ((g - 1.0) * Prt));
   }
@@ -1929,7 +1930,6 @@ int or_lserk4_linear(int n, const double* A, double* u, double dt, int nsteps) {
 int or_jvp(const Setup* s, const double* U, const double* V, double* Ut, double* JV) {
   if (!valid(s)) return -1;
   const Ctx c = make_ctx(*s);
-  if (c.les()) return -1;
   const size_t n = size_t(c.nelem) * 5 * c.nn;
   std::vector<Dual> X(n), Y(n);
   for (size_t i = 0; i < n; ++i) X[i] = Dual(U[i], V[i]);
@@ -1942,7 +1942,6 @@ int or_jvp(const Setup* s, const double* U, const double* V, double* Ut, double*
 int or_rk_jvp(const Setup* s, double* U, double* V, double dt, int nsteps) {
   if (!valid(s)) return -1;
   const Ctx c = make_ctx(*s);
-  if (c.les()) return -1;
   const size_t n = size_t(c.nelem) * 5 * c.nn;
   std::vector<Dual> X(n);
   for (size_t i = 0; i < n; ++i) X[i] = Dual(U[i], V[i]);

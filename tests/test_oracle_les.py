@@ -14,6 +14,9 @@ kappa'_t = mu_t gamma / ((gamma - 1) Pr_t), Delta = (dx dy dz)^(1/3) / (N + 1).
   the nodes on them (where the exact energy U_t jumps) are left out.
 * A per-element coefficient acts locally: changing C_s in one element leaves
   U_t bitwise unchanged outside that element and its six face neighbours.
+* Forward-mode derivatives through the model (|S| and the density factor;
+  reading: |S|' = 0 where |S| = 0, as |x|' = 0 at 0) agree with central
+  differences of the operator and of a two-step rollout.
 """
 import math
 
@@ -135,8 +138,35 @@ def test_per_element_coefficient_is_local(orc):
         assert same == (k not in touched), k
 
 
-def test_jvp_rejects_the_model(orc):
-    s = orc.Setup(N=2, nelem=(2, 2, 2), equations=orc.NS, mu=0.01, Cs=0.1)
-    U = I.random_smooth(2, (2, 2, 2), seed=1)
-    with pytest.raises(ValueError):
-        orc.jvp(s, U, U)
+@pytest.mark.parametrize("vf,sf,field", [(1, 1, False), (0, 0, True), (3, 2, False)])
+def test_jvp_through_the_model_matches_central_differences(orc, vf, sf, field):
+    """Dual numbers through the eddy viscosity (|S| and the density factor)
+    against central differences of the operator, constant and per-element
+    C_s; a state with |S| > 0 at every node (away from the convention at
+    |S| = 0)."""
+    N, nelem = 3, (2, 3, 2)
+    cs = np.random.default_rng(3).uniform(0.1, 0.4, 12) if field else None
+    s = orc.Setup(N=N, nelem=nelem, equations=orc.NS, vol_flux=vf, surf_flux=sf, mu=5e-3, Cs=0.0 if field else 0.3,
+                  cs_elem=cs)
+    U = I.random_smooth(N, nelem, seed=51, noise=0.02)
+    V = I.random_directions(U.shape, 8)
+    Ut, JV = orc.jvp(s, U, V)
+    assert np.array_equal(Ut, orc.time_derivative(s, U))
+    h = 1e-6
+    fd = (orc.time_derivative(s, U + h * V) - orc.time_derivative(s, U - h * V)) / (2 * h)
+    assert np.max(np.abs(JV - fd)) <= 1e-6 * np.max(np.abs(JV))
+    # the model's share of the derivative is well above that tolerance
+    s0 = orc.Setup(N=N, nelem=nelem, equations=orc.NS, vol_flux=vf, surf_flux=sf, mu=5e-3)
+    assert np.max(np.abs(orc.jvp(s0, U, V)[1] - JV)) > 1e-3 * np.max(np.abs(JV))
+
+
+def test_rollout_jvp_through_the_model(orc):
+    N, nelem = 2, (2, 2, 2)
+    s = orc.Setup(N=N, nelem=nelem, equations=orc.NS, vol_flux=1, surf_flux=1, mu=5e-3, Cs=0.2)
+    U = I.random_smooth(N, nelem, seed=52, noise=0.02)
+    V = I.random_directions(U.shape, 9)
+    dt = 0.5 * orc.max_dt(s, U, 0.5)
+    _, JV = orc.rk_jvp(s, U, V, dt, 2)
+    h = 1e-6
+    fd = (orc.rk_steps(s, U + h * V, dt, 2) - orc.rk_steps(s, U - h * V, dt, 2)) / (2 * h)
+    assert np.max(np.abs(JV - fd)) <= 1e-6 * np.max(np.abs(JV))
