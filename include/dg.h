@@ -126,9 +126,9 @@ int dg_get_options(const dg_ctx* ctx, dg_options* opt);
  * into the context on its stream (the caller may free it afterwards); it
  * replaces opt.Cs until dg_set_cs_field(ctx, NULL) restores the constant.
  * Errors: DG_EINVAL for a host pointer, DG_EUNSUPPORTED with DG_VF_CH,
- * DG_ENOMEM.  The model has no adjoint: dg_vjp and rk_step_vjp return
- * DG_EUNSUPPORTED while it is active.  The time-step estimate dg_max_dt uses
- * the molecular viscosity only. */
+ * DG_ENOMEM.  dg_vjp and rk_step_vjp differentiate through the model (mu_t
+ * through |S|, with derivative 0 where |S| = 0, and through rho).  The
+ * time-step estimate dg_max_dt uses the molecular viscosity only. */
 int dg_set_cs_field(dg_ctx* ctx, const double* cs);
 
 /* Curved hexahedral mesh (the paper's applications in Secs. 3-5 run on
@@ -228,8 +228,11 @@ int dg_rk_steps(dg_ctx* ctx, double* U, double dt, int nsteps);
  * one-sided rules are: derivative 0 where the coefficient is clipped or cut
  * off, the mean derivative at ties of a maximum, the selected slope of the
  * minmod limiter.  On curved meshes (dg_set_geometry, also with general
- * connectivity) the product is that of the curved operator.  Not available
- * with DG_MIXED, the CH flux or the Smagorinsky model (DG_EUNSUPPORTED).
+ * connectivity) the product is that of the curved operator; with the
+ * Smagorinsky model it includes the eddy viscosity's dependence on the
+ * lifted gradient and the density (derivative of |S| taken as 0 where
+ * |S| = 0).  Not available with DG_MIXED, the CH flux or wall-modelled
+ * boundaries (DG_EUNSUPPORTED).
  * Allocates the reverse-mode face buffer (and with blending two more buffers)
  * on first use. */
 int dg_vjp(dg_ctx* ctx, const double* U, const double* Ut_bar, double* U_bar);

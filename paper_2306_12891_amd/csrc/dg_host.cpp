@@ -418,7 +418,6 @@ int vjp_supported(dg_ctx* c) {
   if (c->conn && !c->M)
     return fail(c, DG_ESTATE, "general connectivity needs curved elements: call dg_set_geometry first");
   if (c->wall_dir >= 0) return fail(c, DG_EUNSUPPORTED, "vjp: not available with wall-modelled boundaries");
-  if (eq_code(c) == 2) return fail(c, DG_EUNSUPPORTED, "vjp: not available with the Smagorinsky model");
   if (c->opt.precision != DG_FP64) return fail(c, DG_EUNSUPPORTED, "vjp: FP64 operator only");
   if (c->opt.vol_flux == DG_VF_CH) return fail(c, DG_EUNSUPPORTED, "vjp: not available for the CH flux");
   return DG_OK;
@@ -468,6 +467,14 @@ int run_vjp(dg_ctx* c, const double* U, const double* lambda, double* U_bar, con
   v.sf = c->opt.surf_flux;
   v.M = c->M;
   v.conn = c->conn;
+  {
+    const StageArgs a = stage_args(c);
+    v.les = eq_code(c) == 2;
+    v.cs_elem = a.cs_elem;
+    v.cs = a.cs;
+    v.delta2 = a.delta2;
+    v.ktf = a.ktf;
+  }
   hipError_t e;
   if (c->M) {  // curved mesh (FP64, no blending: checked when set)
     if (c->opt.equations == DG_NS) {
@@ -505,7 +512,7 @@ int run_vjp(dg_ctx* c, const double* U, const double* lambda, double* U_bar, con
     e = timed(c, DG_K_VJP_LIFT, [&] { return c->kt->vjp_lift(v, c->stream); });
     if (e != hipSuccess) return hip_fail(c, e, "vjp lifting kernel");
   }
-  e = timed(c, DG_K_VJP, [&] { return c->kt->vjp(v, c->opt.equations, c->stream); });
+  e = timed(c, DG_K_VJP, [&] { return c->kt->vjp(v, eq_code(c), c->stream); });
   if (e != hipSuccess) return hip_fail(c, e, "vjp kernel");
   return DG_OK;
 }

@@ -82,6 +82,11 @@ struct VjpArgs {
   const int32_t* nbr;
   const double* basis;
   double* Gbf;          // NS: [nelem][6][4][nf] cotangent of the normal lifted gradient at own face nodes
+  // Smagorinsky model (les != 0): per-element C_s (or NULL: the constant cs),
+  // squared filter width, gamma / ((gamma - 1) Pr_t), as in StageArgs
+  int les;
+  const double* cs_elem;
+  double cs, delta2, ktf;
   double invJ[3];
   double gamma, mu, kappa;
   int nelem, chunk;

@@ -1701,6 +1701,51 @@ __device__ __forceinline__ void gradient_cotangent(const double Fvb[3][4], const
   }
 }
 
+// With the Smagorinsky model: the cotangent of the lifted gradient with the
+// effective coefficients mu + mu_t, kappa + ktf mu_t (mu_t = rho csd2 |S|,
+// |S|^2 = 2 S_ij S_ij), plus the pullback of mu_t through |S| (derivative 0
+// where |S| = 0) into gb and through rho into rhob:
+//   mub = sum_d [ sum_j taub_jd tauhat_dj + ktf Fvb_d[E] g[d][3] ],
+//   tauhat_dj = g[d][j] + g[j][d] - 2/3 delta_dj div.
+__device__ __forceinline__ void les_gradient_cotangent(const double Fvb[3][4], const double u[3],
+                                                       const double g[3][4], double rho, double mu, double kappa,
+                                                       double csd2, double ktf, double gb[3][4], double& rhob) {
+  const double a = g[0][1] + g[1][0], b = g[0][2] + g[2][0], c = g[1][2] + g[2][1];
+  const double S2 = 2.0 * (g[0][0] * g[0][0] + g[1][1] * g[1][1] + g[2][2] * g[2][2]) + a * a + b * b + c * c;
+  const double Sm = sqrt_nonneg(S2);
+  const double mut = rho * csd2 * Sm;
+  gradient_cotangent(Fvb, u, mu + mut, fma(ktf, mut, kappa), gb);
+  const double tr = (2.0 / 3.0) * (g[0][0] + g[1][1] + g[2][2]);
+  double mub = 0.0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const double th = g[d][j] + g[j][d] - (j == d ? tr : 0.0);
+      mub = fma(fma(u[j], Fvb[d][3], Fvb[d][j]), th, mub);
+    }
+    mub = fma(ktf * Fvb[d][3], g[d][3], mub);
+  }
+  rhob = fma(mub * csd2, Sm, rhob);
+  if (Sm > 0.0) {
+    const double k = mub * rho * csd2 * rcp64(Sm);  // d|S| = dS2 / (2|S|)
+    gb[0][0] = fma(2.0 * k, g[0][0], gb[0][0]);
+    gb[1][1] = fma(2.0 * k, g[1][1], gb[1][1]);
+    gb[2][2] = fma(2.0 * k, g[2][2], gb[2][2]);
+    gb[0][1] = fma(k, a, gb[0][1]);
+    gb[1][0] = fma(k, a, gb[1][0]);
+    gb[0][2] = fma(k, b, gb[0][2]);
+    gb[2][0] = fma(k, b, gb[2][0]);
+    gb[1][2] = fma(k, c, gb[1][2]);
+    gb[2][1] = fma(k, c, gb[2][1]);
+  }
+}
+
+__device__ __forceinline__ double vjp_csd2(const VjpArgs& A, int e) {
+  const double cs = A.cs_elem ? A.cs_elem[e] : A.cs;
+  return cs * cs * A.delta2;
+}
+
 // Neighbour lambda (components 1..4) on face item q into sLn.
 template <int D>
 __device__ __forceinline__ void neighbour_lambda(const VjpArgs& A, int e, int q, double (*sLn)[4][nf]) {
@@ -1796,7 +1841,7 @@ __device__ __forceinline__ void vjp_face_item(const VjpArgs& A, int e, int q, co
 
 // Navier-Stokes data of face item q: q* (forward gradient), the neighbour's
 // lambda and its normal-gradient cotangent.
-template <int D>
+template <int D, bool GN = true>
 __device__ __forceinline__ void vjp_face_ns(const VjpArgs& A, int e, int q, double (*sQ)[4][nf],
                                             double (*sLn)[4][nf], double (*sGn)[4][nf]) {
   const int f = q / nf;
@@ -1821,7 +1866,59 @@ __device__ __forceinline__ void vjp_face_ns(const VjpArgs& A, int e, int q, doub
   for (int c = 0; c < 4; ++c) {
     sQ[f][c][a] = qs[c];
     sLn[f][c][a] = Ln[(1 + c) * nn + nnb];
-    sGn[f][c][a] = Gn[c * nf + a];
+    if (GN) sGn[f][c][a] = Gn[c * nf + a];
+  }
+}
+
+// Pass 1 with the Smagorinsky model: the gradient cotangent at a face node
+// depends on the eddy viscosity there, so the kernel forms the forward lifted
+// gradient (interface values q* of all six faces) and the density at its own
+// face nodes first.
+__global__ __launch_bounds__(NT) void k_vjp_lift_les(VjpArgs A) {
+  __shared__ double sB[NB_STAGE];
+  __shared__ double sP[7][nn];
+  __shared__ double sLam[5][nn];
+  __shared__ double sQ[6][4][nf];
+  __shared__ double sLn[6][4][nf];
+  const int e = element_of_block(blockIdx.x, A.chunk);
+  if (e >= A.nelem) return;
+  const int t = threadIdx.x;
+  const double gm1 = A.gamma - 1.0;
+  for (int q = t; q < NB_STAGE; q += NT) sB[q] = A.basis[q];
+  if (t < nn) {
+    const double* Ue = A.U + (size_t)e * 5 * nn;
+    const double* Le = A.Lbar + (size_t)e * 5 * nn;
+    double u[5], me[7];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      u[v] = Ue[v * nn + t];
+      sLam[v][t] = Le[v * nn + t];
+    }
+    primitives<VF_PI, double, false>(u, gm1, Ref{0.0, 0.0, 0.0}, me);
+#pragma unroll
+    for (int k = 0; k < 7; ++k) sP[k][t] = me[k];
+  }
+  for (int q = t; q < 6 * nf; q += NT) {
+    if (q < 2 * nf) vjp_face_ns<0, false>(A, e, q, sQ, sLn, nullptr);
+    else if (q < 4 * nf) vjp_face_ns<1, false>(A, e, q, sQ, sLn, nullptr);
+    else vjp_face_ns<2, false>(A, e, q, sQ, sLn, nullptr);
+  }
+  __syncthreads();
+  const double* sDw = sB + BL.Dw();
+  const double* swinv = sB + BL.winv();
+  const double csd2 = vjp_csd2(A, e);
+  for (int q = t; q < 6 * nf; q += NT) {
+    const int f = q / nf, a = q - f * nf, d = f >> 1;
+    const int m = face_node(d, (f & 1) ? N : 0, a);
+    const int ijk[3] = {m % n1, (m / n1) % n1, m / nf};
+    double g[3][4], Fvb[3][4], gb[3][4], rhob = 0.0;
+    lifted_gradient<double>(sP, sQ, sDw, swinv, m, ijk, A.invJ, g);
+    viscous_flux_cotangent(sLam, sLn, sDw, swinv, m, ijk, A.invJ, Fvb);
+    const double u[3] = {sP[1][m], sP[2][m], sP[3][m]};
+    les_gradient_cotangent(Fvb, u, g, sP[0][m], A.mu, A.kappa, csd2, A.ktf, gb, rhob);
+    double* out = A.Gbf + ((size_t)e * 6 + f) * 4 * nf;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) out[c * nf + a] = d == 0 ? gb[0][c] : (d == 1 ? gb[1][c] : gb[2][c]);
   }
 }
 
@@ -1883,7 +1980,8 @@ __device__ __forceinline__ void volume_vjp_dir(const double (*sP)[nn], const dou
 // Main reverse kernel.  Writes U_bar (or U_acc + U_bar when A.Uacc is set).
 template <int VF, int EQ>
 __global__ __launch_bounds__(NT) void k_vjp(VjpArgs A) {
-  constexpr bool NS = (EQ == 1);
+  constexpr bool NS = (EQ >= 1);
+  constexpr bool LES = (EQ == 2);
   __shared__ double sB[NB_STAGE];
   __shared__ double sP[7][nn];
   __shared__ double sLam[5][nn];
@@ -1947,6 +2045,8 @@ __global__ __launch_bounds__(NT) void k_vjp(VjpArgs A) {
       double Fvb[3][4], g[3][4];
       viscous_flux_cotangent(sLam, sLn, sDw, swinv, t, ijk, A.invJ, Fvb);
       lifted_gradient<double>(sP, sQ, sDw, swinv, t, ijk, A.invJ, g);
+      const double csd2 = LES ? vjp_csd2(A, e) : 0.0;
+      const double mue = LES ? A.mu + eddy_viscosity<double>(g, me[0], csd2) : A.mu;
       // u enters the energy flux u . tau_d
       const double div = g[0][0] + g[1][1] + g[2][2];
 #pragma unroll
@@ -1954,13 +2054,14 @@ __global__ __launch_bounds__(NT) void k_vjp(VjpArgs A) {
         double s = 0.0;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-          const double tau = A.mu * (g[d][j] + g[j][d]) - (j == d ? (2.0 / 3.0) * A.mu * div : 0.0);
+          const double tau = mue * (g[d][j] + g[j][d]) - (j == d ? (2.0 / 3.0) * mue * div : 0.0);
           s = fma(tau, Fvb[d][3], s);
         }
         pb[1 + j] += s;
       }
       const double uu[3] = {me[1], me[2], me[3]};
-      gradient_cotangent(Fvb, uu, A.mu, A.kappa, gb);
+      if (LES) les_gradient_cotangent(Fvb, uu, g, me[0], A.mu, A.kappa, csd2, A.ktf, gb, pb[0]);
+      else gradient_cotangent(Fvb, uu, A.mu, A.kappa, gb);
     }
   }
   if (NS) {
@@ -3855,7 +3956,8 @@ hipError_t launch_integrals(const ReduceArgs& R, hipStream_t s) {
 template <int VF>
 hipError_t launch_vjp_vf(const VjpArgs& A, int eq, hipStream_t s) {
   const dim3 grid(8 * A.chunk), block(NT);
-  if (eq == 1) hipLaunchKernelGGL((k_vjp<VF, 1>), grid, block, 0, s, A);
+  if (eq == 2) hipLaunchKernelGGL((k_vjp<VF, 2>), grid, block, 0, s, A);
+  else if (eq == 1) hipLaunchKernelGGL((k_vjp<VF, 1>), grid, block, 0, s, A);
   else hipLaunchKernelGGL((k_vjp<VF, 0>), grid, block, 0, s, A);
   return hipGetLastError();
 }
@@ -3891,7 +3993,8 @@ hipError_t launch_vjp_fv(const VjpArgs& A, hipStream_t s) {
 }
 
 hipError_t launch_vjp_lift(const VjpArgs& A, hipStream_t s) {
-  hipLaunchKernelGGL(k_vjp_lift, dim3(8 * A.chunk), dim3(NT), 0, s, A);
+  if (A.les) hipLaunchKernelGGL(k_vjp_lift_les, dim3(8 * A.chunk), dim3(NT), 0, s, A);
+  else hipLaunchKernelGGL(k_vjp_lift, dim3(8 * A.chunk), dim3(NT), 0, s, A);
   return hipGetLastError();
 }
 

@@ -1,7 +1,9 @@
 """Smagorinsky eddy viscosity on the GPU (constant and per-element C_s) against
 the FP64 oracle, through the C ABI: single evaluations to 1e-12 of the term
-scale, the mixed operator within its stated bound, a rollout, and the error
-paths (no adjoint through the model, host pointers, the CH flux)."""
+scale, the mixed operator within its stated bound, a rollout, the reverse
+mode through the model (dot products against the oracle's dual numbers, a
+full Jacobian, the Runge-Kutta step), and the error paths (host pointers,
+the CH flux)."""
 import math
 
 import numpy as np
@@ -94,9 +96,6 @@ def test_error_paths(orc, torch_cuda):
     N, nelem = 2, (2, 2, 2)
     _, op = make(orc, N, nelem, 1, 1, 1e-2, 0.2)
     U = torch.from_numpy(I.random_smooth(N, nelem, seed=5)).cuda()
-    with pytest.raises(dg.DGError) as ei:
-        op.vjp(U, U.clone())
-    assert ei.value.code == dg.DG_EUNSUPPORTED
     host = np.full(8, 0.1)
     assert op.raw_call("dg_set_cs_field", ctypes.c_void_p(host.ctypes.data)) == dg.DG_EINVAL
     with pytest.raises(dg.DGError) as ei:
@@ -106,4 +105,60 @@ def test_error_paths(orc, torch_cuda):
         op.set_options(vol_flux=dg.CH)
     assert ei.value.code == dg.DG_EUNSUPPORTED
     op.set_options(Cs=0.0)
-    op.vjp(U, U.clone())  # plain Navier-Stokes again: the adjoint is available
+    op.vjp(U, U.clone())
+
+
+@pytest.mark.parametrize("vf,sf,field", [(1, 1, False), (0, 0, True), (3, 2, False), (1, 1, True)])
+@pytest.mark.parametrize("N", [2, 3, 5])
+def test_vjp_dot_product(orc, torch_cuda, vf, sf, field, N):
+    """Reverse mode through the model: <w, J v> from the oracle's dual numbers
+    equals <J^T w, v> from the GPU to 1e-12 of the product scale (constant and
+    per-element C_s)."""
+    nelem = (3, 2, 2)
+    cs = np.random.default_rng(80 + N).uniform(0.1, 0.4, 12) if field else None
+    s, op = make(orc, N, nelem, vf, sf, 5e-3, 0.0 if field else 0.3, cs_elem=cs)
+    if field:
+        op.set_cs_field(torch_cuda.from_numpy(cs).cuda())
+    U = I.random_smooth(N, nelem, seed=90 + N, noise=0.02)
+    v = I.random_directions(U.shape, 10)
+    w = I.random_directions(U.shape, 11)
+    _, Jv = orc.jvp(s, U, v)
+    JTw = op.vjp(torch_cuda.from_numpy(U).cuda(), torch_cuda.from_numpy(w).cuda()).cpu().numpy()
+    a, b = np.sum(w * Jv), np.sum(JTw * v)
+    assert abs(a - b) <= 1e-12 * np.sum(np.abs(w * Jv)), (a, b)
+
+
+def test_vjp_full_jacobian_one_element(orc, torch_cuda):
+    """N = 2 on one self-periodic element with the model: the 135 rows J^T e_k
+    against the columns J e_k of the oracle's dual numbers."""
+    import torch
+    N, nelem = 2, (1, 1, 1)
+    s, op = make(orc, N, nelem, 1, 1, 2e-2, 0.3)
+    U = I.random_smooth(N, nelem, seed=33, noise=0.05)
+    n = U.size
+    J = np.zeros((n, n))
+    for k in range(n):
+        e = np.zeros(n)
+        e[k] = 1.0
+        J[:, k] = orc.jvp(s, U, e.reshape(U.shape))[1].ravel()
+    Ud = torch.from_numpy(U).cuda()
+    JT = np.zeros((n, n))
+    for k in range(n):
+        e = torch.zeros(U.shape, dtype=torch.float64, device="cuda")
+        e.view(-1)[k] = 1.0
+        JT[k] = op.vjp(Ud, e).cpu().numpy().ravel()
+    assert np.max(np.abs(JT - J)) <= 1e-12 * np.max(np.abs(J))
+
+
+def test_rk_step_vjp_dot_product(orc, torch_cuda):
+    import torch
+    N, nelem = 3, (2, 3, 2)
+    s, op = make(orc, N, nelem, 1, 1, 5e-3, 0.25)
+    U = I.random_smooth(N, nelem, seed=95, noise=0.01)
+    v = I.random_directions(U.shape, 12)
+    w = I.random_directions(U.shape, 13)
+    dt = 0.5 * orc.max_dt(s, U, 0.5)
+    _, Jv = orc.rk_jvp(s, U, v, dt, 1)
+    JTw = op.rk_step_vjp(torch.from_numpy(U).cuda(), dt, torch.from_numpy(w).cuda()).cpu().numpy()
+    a, b = np.sum(w * Jv), np.sum(JTw * v)
+    assert abs(a - b) <= 1e-12 * np.sum(np.abs(w * Jv)), (a, b)
