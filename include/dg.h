@@ -194,8 +194,11 @@ int dg_set_connectivity(dg_ctx* ctx, const int32_t* conn);
  * the wall (adiabatic wall at rest).  Needs the FP64 Navier-Stokes operator
  * (also with the Smagorinsky model), mu > 0, no blending, the Cartesian box;
  * while walls are set, dg_set_options, dg_set_geometry and dg_set_connectivity
- * calls that would break this return DG_EUNSUPPORTED, and dg_vjp /
- * rk_step_vjp return DG_EUNSUPPORTED.
+ * calls that would break this return DG_EUNSUPPORTED.  dg_vjp and rk_step_vjp
+ * differentiate through the walls (mirror states, and the wall shear through
+ * the Newton solution by the implicit function theorem and through the van
+ * Driest transformation, derivative 0 where its argument is capped); not
+ * together with the Smagorinsky model (DG_EUNSUPPORTED).
  * Errors (nothing is changed then): DG_EINVAL for wall_dir outside -1..2,
  * ma_inf < 0 or non-finite, or ma_inf > 0 with u_inf <= 0; DG_EUNSUPPORTED as
  * above; DG_ENOMEM. */
@@ -231,8 +234,9 @@ int dg_rk_steps(dg_ctx* ctx, double* U, double dt, int nsteps);
  * connectivity) the product is that of the curved operator; with the
  * Smagorinsky model it includes the eddy viscosity's dependence on the
  * lifted gradient and the density (derivative of |S| taken as 0 where
- * |S| = 0).  Not available with DG_MIXED, the CH flux or wall-modelled
- * boundaries (DG_EUNSUPPORTED).
+ * |S| = 0); with wall-modelled boundaries it includes the wall model.  Not
+ * available with DG_MIXED, the CH flux, or walls together with the
+ * Smagorinsky model (DG_EUNSUPPORTED).
  * Allocates the reverse-mode face buffer (and with blending two more buffers)
  * on first use. */
 int dg_vjp(dg_ctx* ctx, const double* U, const double* Ut_bar, double* U_bar);

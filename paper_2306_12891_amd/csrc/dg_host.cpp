@@ -417,7 +417,8 @@ int wall_compatible(dg_ctx* c, const dg_options* o, const char* where) {
 int vjp_supported(dg_ctx* c) {
   if (c->conn && !c->M)
     return fail(c, DG_ESTATE, "general connectivity needs curved elements: call dg_set_geometry first");
-  if (c->wall_dir >= 0) return fail(c, DG_EUNSUPPORTED, "vjp: not available with wall-modelled boundaries");
+  if (c->wall_dir >= 0 && eq_code(c) == 2)
+    return fail(c, DG_EUNSUPPORTED, "vjp: not available with wall-modelled boundaries and the Smagorinsky model");
   if (c->opt.precision != DG_FP64) return fail(c, DG_EUNSUPPORTED, "vjp: FP64 operator only");
   if (c->opt.vol_flux == DG_VF_CH) return fail(c, DG_EUNSUPPORTED, "vjp: not available for the CH flux");
   return DG_OK;
@@ -474,6 +475,10 @@ int run_vjp(dg_ctx* c, const double* U, const double* lambda, double* U_bar, con
     v.cs = a.cs;
     v.delta2 = a.delta2;
     v.ktf = a.ktf;
+    v.wall_dir = a.wall_dir;
+    v.wm_h = a.wm_h;
+    v.wm_uinf = a.wm_uinf;
+    v.wm_b = a.wm_b;
   }
   hipError_t e;
   if (c->M) {  // curved mesh (FP64, no blending: checked when set)

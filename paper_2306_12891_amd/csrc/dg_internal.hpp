@@ -87,6 +87,9 @@ struct VjpArgs {
   int les;
   const double* cs_elem;
   double cs, delta2, ktf;
+  // wall-modelled boundaries (see StageArgs); wall_dir -1: none
+  int wall_dir;
+  double wm_h, wm_uinf, wm_b;
   double invJ[3];
   double gamma, mu, kappa;
   int nelem, chunk;

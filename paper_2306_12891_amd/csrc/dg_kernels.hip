@@ -1650,9 +1650,12 @@ __device__ __forceinline__ void riemann_vjp(int sf, const double L[5], const dou
 //   Fvb_d(m) = (2/dx_d) [ sum_n Dw_{i(n) i(m)} lambda_n
 //                         + 1/2 delta_{i N}(lambda_m / w_N - lambda_nb+ / w_0)
 //                         + 1/2 delta_{i 0}(lambda_nb- / w_N - lambda_m / w_0) ].
+// wmask: bit f set for wall faces, whose surface term is the wall model's
+// flux (no own or neighbour share of the lifted viscous flux).
 __device__ __forceinline__ void viscous_flux_cotangent(const double (*sLam)[nn], const double (*sLn)[4][nf],
                                                        const double* sDw, const double* swinv, int m,
-                                                       const int ijk[3], const double invJ[3], double Fvb[3][4]) {
+                                                       const int ijk[3], const double invJ[3], double Fvb[3][4],
+                                                       int wmask = 0) {
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const int st = d == 0 ? 1 : (d == 1 ? n1 : nf);
@@ -1667,12 +1670,12 @@ __device__ __forceinline__ void viscous_flux_cotangent(const double (*sLam)[nn],
 #pragma unroll
       for (int cc = 0; cc < 4; ++cc) s[cc] = fma(c, sLam[1 + cc][k], s[cc]);
     }
-    if (id == N) {
+    if (id == N && !((wmask >> (2 * d + 1)) & 1)) {
 #pragma unroll
       for (int cc = 0; cc < 4; ++cc)
         s[cc] += 0.5 * (swinv[N] * sLam[1 + cc][m] - swinv[0] * sLn[2 * d + 1][cc][a]);
     }
-    if (id == 0) {
+    if (id == 0 && !((wmask >> (2 * d)) & 1)) {
 #pragma unroll
       for (int cc = 0; cc < 4; ++cc)
         s[cc] += 0.5 * (swinv[N] * sLn[2 * d][cc][a] - swinv[0] * sLam[1 + cc][m]);
@@ -1746,12 +1749,70 @@ __device__ __forceinline__ double vjp_csd2(const VjpArgs& A, int e) {
   return cs * cs * A.delta2;
 }
 
-// Neighbour lambda (components 1..4) on face item q into sLn.
+// Wall faces of element e (bit f), at most the two normal to wall_dir.
+__device__ __forceinline__ int vjp_wall_mask(const VjpArgs& A, int e) {
+  if (A.wall_dir < 0) return 0;
+  const int f0 = 2 * A.wall_dir;
+  return (A.nbr[6 * e + f0] < 0 ? 1 << f0 : 0) | (A.nbr[6 * e + f0 + 1] < 0 ? 2 << f0 : 0);
+}
+
+// Reverse of wall_model_flux: the cotangents gb1, gb2 of its two tangential
+// components pulled back to the wall node's density and the exchange node's
+// density and tangential momenta (added).  u_tau depends on the (van Driest
+// transformed) speed and on nu = mu / rho_w through Spalding's law
+// F(u_tau) = y+(u/u_tau) - h u_tau / nu = 0: du_tau = -(F_u du + F_nu dnu) / F_utau.
+__device__ void wall_model_flux_vjp(const VjpArgs& A, double rhow, double rx, double mt1, double mt2, double sg,
+                                    double gb1, double gb2, double& rhowb, double& rxb, double& mt1b,
+                                    double& mt2b) {
+  const double ir = 1.0 / rx;
+  const double v1 = mt1 * ir, v2 = mt2 * ir;
+  const double sp2 = v1 * v1 + v2 * v2;
+  if (!(sp2 > 0.0)) return;  // zero flux
+  const double sp = sqrt(sp2);
+  double ueq = sp, dueq = 1.0;
+  if (A.wm_b > 0.0) {
+    const double arg = A.wm_b * sp / A.wm_uinf;
+    if (arg > 1.0) {  // capped: constant
+      ueq = (A.wm_uinf / A.wm_b) * asin(1.0);
+      dueq = 0.0;
+    } else {
+      ueq = (A.wm_uinf / A.wm_b) * asin(arg);
+      dueq = 1.0 / sqrt(1.0 - arg * arg);
+    }
+  }
+  const double nu = A.mu / rhow, h = A.wm_h;
+  const double ut = wm_friction_velocity(ueq, nu, h);
+  const double x = ueq / ut;
+  const double k = 0.4 * x, ek = exp(k);
+  const double dy = 1.0 + 0.1108 * 0.4 * (ek - (1.0 + k * (1.0 + k * (0.5 + k * (1.0 / 6.0)))));
+  const double Fut = -dy * x / ut - h / nu, Fu = dy / ut, Fnu = h * ut / (nu * nu);
+  const double c = sg * rhow * ut * ut / sp;
+  const double cb = gb1 * v1 + gb2 * v2;
+  double v1b = gb1 * c, v2b = gb2 * c;
+  rhowb += cb * sg * ut * ut / sp;
+  const double utb = cb * sg * rhow * 2.0 * ut / sp;
+  double spb = -cb * c / sp;
+  const double nub = -utb * Fnu / Fut;
+  spb += -utb * Fu / Fut * dueq;
+  rhowb -= nub * A.mu / (rhow * rhow);
+  v1b += spb * v1 / sp;
+  v2b += spb * v2 / sp;
+  mt1b += v1b * ir;
+  mt2b += v2b * ir;
+  rxb -= (v1b * v1 + v2b * v2) * ir;
+}
+
+// Neighbour lambda (components 1..4) on face item q into sLn (zero at walls).
 template <int D>
 __device__ __forceinline__ void neighbour_lambda(const VjpArgs& A, int e, int q, double (*sLn)[4][nf]) {
   const int f = q / nf;
   const int a = q - f * nf;
   const int side = f & 1;
+  if (A.nbr[6 * e + f] < 0) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) sLn[f][c][a] = 0.0;
+    return;
+  }
   const double* Ln = A.Lbar + (size_t)A.nbr[6 * e + f] * 5 * nn;
   const int nnb = face_node(D, side ? 0 : N, a);
 #pragma unroll
@@ -1763,13 +1824,13 @@ __device__ __forceinline__ void neighbour_lambda(const VjpArgs& A, int e, int q,
 template <int D>
 __device__ __forceinline__ void vjp_lift_face_node(const VjpArgs& A, int e, int q, const double (*sLam)[nn],
                                                    const double (*sLn)[4][nf], const double (*sU)[nn],
-                                                   const double* sDw, const double* swinv) {
+                                                   const double* sDw, const double* swinv, int wmask) {
   const int f = q / nf;
   const int a = q - f * nf;
   const int m = face_node(D, (f & 1) ? N : 0, a);
   const int ijk[3] = {m % n1, (m / n1) % n1, m / nf};
   double Fvb[3][4], gb[3][4];
-  viscous_flux_cotangent(sLam, sLn, sDw, swinv, m, ijk, A.invJ, Fvb);
+  viscous_flux_cotangent(sLam, sLn, sDw, swinv, m, ijk, A.invJ, Fvb, wmask);
   const double u[3] = {sU[0][m], sU[1][m], sU[2][m]};
   gradient_cotangent(Fvb, u, A.mu, A.kappa, gb);
   double* out = A.Gbf + ((size_t)e * 6 + f) * 4 * nf;
@@ -1801,10 +1862,11 @@ __global__ __launch_bounds__(NT) void k_vjp_lift(VjpArgs A) {
     else neighbour_lambda<2>(A, e, q, sLn);
   }
   __syncthreads();
+  const int wmask = vjp_wall_mask(A, e);
   for (int q = t; q < 6 * nf; q += NT) {
-    if (q < 2 * nf) vjp_lift_face_node<0>(A, e, q, sLam, sLn, sU, sB + BL.Dw(), sB + BL.winv());
-    else if (q < 4 * nf) vjp_lift_face_node<1>(A, e, q, sLam, sLn, sU, sB + BL.Dw(), sB + BL.winv());
-    else vjp_lift_face_node<2>(A, e, q, sLam, sLn, sU, sB + BL.Dw(), sB + BL.winv());
+    if (q < 2 * nf) vjp_lift_face_node<0>(A, e, q, sLam, sLn, sU, sB + BL.Dw(), sB + BL.winv(), wmask);
+    else if (q < 4 * nf) vjp_lift_face_node<1>(A, e, q, sLam, sLn, sU, sB + BL.Dw(), sB + BL.winv(), wmask);
+    else vjp_lift_face_node<2>(A, e, q, sLam, sLn, sU, sB + BL.Dw(), sB + BL.winv(), wmask);
   }
 }
 
@@ -1813,10 +1875,47 @@ __global__ __launch_bounds__(NT) void k_vjp_lift(VjpArgs A) {
 // lambda_+ / w_0), by the reverse sweep of the interface flux (riemann_vjp).
 // One code path for all directions: states and cotangent are rotated by
 // address (normal component first).
-template <int VF>
+// At a wall face (WALL, neighbour -1): the interface flux with the mirror
+// state (normal momentum reversed) as the other side, so its cotangent reaches
+// the own state through both arguments; plus the reverse of the wall model's
+// viscous flux, whose exchange-node part goes to sWx[side][variable][a]
+// (density and momenta).
+template <int VF, bool WALL = false>
 __device__ __forceinline__ void vjp_face_item(const VjpArgs& A, int e, int q, const double* swinv,
-                                              double (*sSF)[5][nf]) {
+                                              double (*sSF)[5][nf], double (*sWx)[4][nf] = nullptr) {
   const FaceItem it = face_item_geometry(A.nbr, e, q);
+  if (WALL && it.nb < 0) {
+    const int row[5] = {0, 1 + it.d, it.k1, it.k2, 4};
+    const double* Ue = A.U + (size_t)e * 5 * nn;
+    const double* Le = A.Lbar + (size_t)e * 5 * nn;
+    const double invJd = it.d == 0 ? A.invJ[0] : (it.d == 1 ? A.invJ[1] : A.invJ[2]);
+    const double cw = it.side ? -invJd * swinv[N] : invJd * swinv[0];
+    double L[5], R[5], fb[5], Lb[5], Rb[5];
+#pragma unroll
+    for (int r = 0; r < 5; ++r) {
+      const double X = Ue[row[r] * nn + it.nown];
+      L[r] = (r == 1 && !it.side) ? -X : X;
+      R[r] = (r == 1 && it.side) ? -X : X;
+      fb[r] = cw * Le[row[r] * nn + it.nown];
+    }
+    riemann_vjp<VF>(A.sf, L, R, A.gamma, fb, Lb, Rb);
+    double ob[5];
+#pragma unroll
+    for (int r = 0; r < 5; ++r) ob[r] = (it.side ? Lb[r] : Rb[r]) + (r == 1 ? -1.0 : 1.0) * (it.side ? Rb[r] : Lb[r]);
+    const double cv = invJd * (it.side ? swinv[N] : -swinv[0]);
+    double rhowb = 0.0, rxb = 0.0, m1b = 0.0, m2b = 0.0;
+    wall_model_flux_vjp(A, L[0], Ue[it.nnb], Ue[it.k1 * nn + it.nnb], Ue[it.k2 * nn + it.nnb],
+                        it.side ? -1.0 : 1.0, cv * Le[it.k1 * nn + it.nown], cv * Le[it.k2 * nn + it.nown], rhowb,
+                        rxb, m1b, m2b);
+    ob[0] += rhowb;
+#pragma unroll
+    for (int r = 0; r < 5; ++r) sSF[it.f][row[r]][it.a] = ob[r];
+    sWx[it.side][0][it.a] = rxb;
+    sWx[it.side][1 + it.d][it.a] = 0.0;
+    sWx[it.side][it.k1][it.a] = m1b;
+    sWx[it.side][it.k2][it.a] = m2b;
+    return;
+  }
   const int eL = it.side ? e : it.nb, eR = it.side ? it.nb : e;
   const int nL = it.side ? it.nown : it.nnb, nR = it.side ? it.nnb : it.nown;
   const int row[5] = {0, 1 + it.d, it.k1, it.k2, 4};  // rotated position -> variable
@@ -1851,6 +1950,23 @@ __device__ __forceinline__ void vjp_face_ns(const VjpArgs& A, int e, int q, doub
   const int eL = side ? e : nb, eR = side ? nb : e;
   const int nL = face_node(D, N, a), nR = face_node(D, 0, a), nnb = side ? nR : nL;
   double L[5], R[5];
+  if (nb < 0) {  // wall: the own face state and its mirror image
+    const int no = side ? nL : nR;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) L[v] = R[v] = A.U[((size_t)e * 5 + v) * nn + no];
+    if (side) R[1 + D] = -R[1 + D];
+    else L[1 + D] = -L[1 + D];
+    const double gm1 = A.gamma - 1.0;
+    double qs[4];
+    interface_q<D, double, false>(state64<D>(L, gm1), state64<D>(R, gm1), Ref{0.0, 0.0, 0.0}, qs);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      sQ[f][c][a] = qs[c];
+      sLn[f][c][a] = 0.0;
+      if (GN) sGn[f][c][a] = 0.0;
+    }
+    return;
+  }
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
     L[v] = A.U[((size_t)eL * 5 + v) * nn + nL];
@@ -1978,10 +2094,12 @@ __device__ __forceinline__ void volume_vjp_dir(const double (*sP)[nn], const dou
 }
 
 // Main reverse kernel.  Writes U_bar (or U_acc + U_bar when A.Uacc is set).
-template <int VF, int EQ>
+template <int VF, int EQ, bool WALL = false>
 __global__ __launch_bounds__(NT) void k_vjp(VjpArgs A) {
   constexpr bool NS = (EQ >= 1);
   constexpr bool LES = (EQ == 2);
+  static_assert(!WALL || EQ == 1, "walls: Navier-Stokes without the eddy viscosity");
+  __shared__ double sWx[WALL ? 2 : 1][4][nf];
   __shared__ double sB[NB_STAGE];
   __shared__ double sP[7][nn];
   __shared__ double sLam[5][nn];
@@ -2017,8 +2135,9 @@ __global__ __launch_bounds__(NT) void k_vjp(VjpArgs A) {
     ijk[2] = t / nf;
   }
   __syncthreads();  // the face items read the basis (swinv)
+  const int wmask = WALL ? vjp_wall_mask(A, e) : 0;
 #pragma unroll 1
-  for (int q = t; q < 6 * nf; q += NT) vjp_face_item<VF>(A, e, q, swinv, sSF);
+  for (int q = t; q < 6 * nf; q += NT) vjp_face_item<VF, WALL>(A, e, q, swinv, sSF, sWx);
   if (NS) {
     for (int q = t; q < 6 * nf; q += NT) {
       if (q < 2 * nf) vjp_face_ns<0>(A, e, q, sQ, sLn, sGn);
@@ -2043,7 +2162,7 @@ __global__ __launch_bounds__(NT) void k_vjp(VjpArgs A) {
     }
     if (NS) {
       double Fvb[3][4], g[3][4];
-      viscous_flux_cotangent(sLam, sLn, sDw, swinv, t, ijk, A.invJ, Fvb);
+      viscous_flux_cotangent(sLam, sLn, sDw, swinv, t, ijk, A.invJ, Fvb, wmask);
       lifted_gradient<double>(sP, sQ, sDw, swinv, t, ijk, A.invJ, g);
       const double csd2 = LES ? vjp_csd2(A, e) : 0.0;
       const double mue = LES ? A.mu + eddy_viscosity<double>(g, me[0], csd2) : A.mu;
@@ -2088,13 +2207,25 @@ __global__ __launch_bounds__(NT) void k_vjp(VjpArgs A) {
 #pragma unroll
           for (int cc = 0; cc < 4; ++cc) s[cc] = fma(c, sX[cc][k], s[cc]);
         }
+        // interface value q* = (q + q_nb)/2; at a wall (q + M q)/2, M the
+        // mirror (normal velocity reversed)
         if (id == N) {
+          if (WALL && ((wmask >> (2 * d + 1)) & 1)) {
 #pragma unroll
-          for (int cc = 0; cc < 4; ++cc) s[cc] += 0.5 * (swinv[N] * gb[d][cc] - swinv[0] * sGn[2 * d + 1][cc][a]);
+            for (int cc = 0; cc < 4; ++cc) s[cc] += cc == d ? 0.0 : swinv[N] * gb[d][cc];
+          } else {
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc) s[cc] += 0.5 * (swinv[N] * gb[d][cc] - swinv[0] * sGn[2 * d + 1][cc][a]);
+          }
         }
         if (id == 0) {
+          if (WALL && ((wmask >> (2 * d)) & 1)) {
 #pragma unroll
-          for (int cc = 0; cc < 4; ++cc) s[cc] += 0.5 * (swinv[N] * sGn[2 * d][cc][a] - swinv[0] * gb[d][cc]);
+            for (int cc = 0; cc < 4; ++cc) s[cc] -= cc == d ? 0.0 : swinv[0] * gb[d][cc];
+          } else {
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc) s[cc] += 0.5 * (swinv[N] * sGn[2 * d][cc][a] - swinv[0] * gb[d][cc]);
+          }
         }
         pb[1] += A.invJ[d] * s[0];
         pb[2] += A.invJ[d] * s[1];
@@ -2139,6 +2270,20 @@ __global__ __launch_bounds__(NT) void k_vjp(VjpArgs A) {
       if (id == 0)
 #pragma unroll
         for (int v = 0; v < 5; ++v) out[v] += sSF[2 * d][v][a];
+    }
+    if (WALL) {  // exchange nodes of the wall faces: the wall model's pullback
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        if (d != A.wall_dir) continue;
+        const int id = ijk[d];
+        const int a = d == 0 ? ijk[1] + n1 * ijk[2] : (d == 1 ? ijk[0] + n1 * ijk[2] : ijk[0] + n1 * ijk[1]);
+        if (id == 0 && ((wmask >> (2 * d + 1)) & 1))
+#pragma unroll
+          for (int v = 0; v < 4; ++v) out[v] += sWx[1][v][a];
+        if (id == N && ((wmask >> (2 * d)) & 1))
+#pragma unroll
+          for (int v = 0; v < 4; ++v) out[v] += sWx[0][v][a];
+      }
     }
     const size_t o = (size_t)e * 5 * nn + t;
 #pragma unroll
@@ -3956,7 +4101,10 @@ hipError_t launch_integrals(const ReduceArgs& R, hipStream_t s) {
 template <int VF>
 hipError_t launch_vjp_vf(const VjpArgs& A, int eq, hipStream_t s) {
   const dim3 grid(8 * A.chunk), block(NT);
-  if (eq == 2) hipLaunchKernelGGL((k_vjp<VF, 2>), grid, block, 0, s, A);
+  if (A.wall_dir >= 0) {  // walls: Navier-Stokes without the eddy viscosity (checked on the host)
+    if (eq != 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_vjp<VF, 1, true>), grid, block, 0, s, A);
+  } else if (eq == 2) hipLaunchKernelGGL((k_vjp<VF, 2>), grid, block, 0, s, A);
   else if (eq == 1) hipLaunchKernelGGL((k_vjp<VF, 1>), grid, block, 0, s, A);
   else hipLaunchKernelGGL((k_vjp<VF, 0>), grid, block, 0, s, A);
   return hipGetLastError();

@@ -2,8 +2,9 @@
 the wall, optionally van Driest transformed, paper Sec. 3) against the FP64
 oracle through the C ABI: single evaluations to 1e-12 of the term scale for
 all degrees, wall directions, flux pairs, with the Smagorinsky model and in
-the log region of the law, a Runge-Kutta rollout, removal of the walls, and the
-error paths."""
+the log region of the law, a Runge-Kutta rollout, removal of the walls, the error
+paths, and the reverse mode through the wall model (dot products against the
+oracle's dual numbers, a full Jacobian, rk_step_vjp)."""
 import numpy as np
 import pytest
 
@@ -132,9 +133,12 @@ def test_error_paths(orc, torch_cuda):
             op.set_options(**kw)
         assert ei.value.code == dg.DG_EUNSUPPORTED, kw
     U = torch.from_numpy(channel_state(N, nelem, 360, lo=(0, 0, 0), hi=(TWO_PI,) * 3)).cuda()
-    with pytest.raises(dg.DGError) as ei:
+    op.vjp(U, U.clone())  # the adjoint covers the wall model
+    op.set_options(Cs=0.1)
+    with pytest.raises(dg.DGError) as ei:  # but not with the eddy viscosity as well
         op.vjp(U, U.clone())
     assert ei.value.code == dg.DG_EUNSUPPORTED
+    op.set_options(Cs=0.0)
     with pytest.raises(dg.DGError) as ei:
         op.set_geometry(torch.from_numpy(I.warped_coordinates(N, nelem)).cuda())
     assert ei.value.code == dg.DG_EUNSUPPORTED
@@ -154,3 +158,63 @@ def test_error_paths(orc, torch_cuda):
         op2.set_wall_model(0)
     assert ei.value.code == dg.DG_EUNSUPPORTED
     op2.set_wall_model(-1)  # nothing to remove: the curved mesh stays
+
+
+def dot_check(orc, torch, s, op, U, seed):
+    v = I.random_directions(U.shape, seed)
+    w = I.random_directions(U.shape, seed + 1)
+    _, Jv = orc.jvp(s, U, v)
+    JTw = op.vjp(torch.from_numpy(U).cuda(), torch.from_numpy(w).cuda()).cpu().numpy()
+    a, b = np.sum(w * Jv), np.sum(JTw * v)
+    assert abs(a - b) <= 1e-12 * np.sum(np.abs(w * Jv)), (a, b, abs(a - b) / np.sum(np.abs(w * Jv)))
+
+
+@pytest.mark.parametrize("wall_dir", [0, 1, 2])
+@pytest.mark.parametrize("N", [1, 2, 3, 5])
+def test_vjp_dot_product(orc, torch_cuda, N, wall_dir):
+    nelem = (2, 3, 2)
+    s, op = make(orc, N, nelem, wall_dir, mu=2e-3)
+    dot_check(orc, torch_cuda, s, op, channel_state(N, nelem, 370 + N), 20)
+
+
+@pytest.mark.parametrize("vf,sf,mainf,mu", [(0, 0, 0.0, 2e-3), (1, 1, 0.7, 1e-5), (3, 2, 1.5, 2e-3), (1, 2, 0.0, 1e-7)])
+def test_vjp_dot_product_fluxes_van_driest(orc, torch_cuda, vf, sf, mainf, mu):
+    N, nelem = 3, (2, 3, 2)
+    s, op = make(orc, N, nelem, 1, vf=vf, sf=sf, mu=mu, uinf=0.8, mainf=mainf)
+    dot_check(orc, torch_cuda, s, op, channel_state(N, nelem, 380 + vf), 22)
+
+
+def test_vjp_full_jacobian_one_element_between_walls(orc, torch_cuda):
+    """N = 2, one element, both y faces walls (x, z self-periodic): the 135
+    rows J^T e_k against the columns J e_k of the oracle's dual numbers."""
+    import torch
+    N, nelem = 2, (1, 1, 1)
+    s, op = make(orc, N, nelem, 1, mu=1e-3, uinf=0.9, mainf=0.6)
+    U = channel_state(N, nelem, 390, noise=0.05)
+    n = U.size
+    J = np.zeros((n, n))
+    for k in range(n):
+        e = np.zeros(n)
+        e[k] = 1.0
+        J[:, k] = orc.jvp(s, U, e.reshape(U.shape))[1].ravel()
+    Ud = torch.from_numpy(U).cuda()
+    JT = np.zeros((n, n))
+    for k in range(n):
+        e = torch.zeros(U.shape, dtype=torch.float64, device="cuda")
+        e.view(-1)[k] = 1.0
+        JT[k] = op.vjp(Ud, e).cpu().numpy().ravel()
+    assert np.max(np.abs(JT - J)) <= 1e-12 * np.max(np.abs(J))
+
+
+def test_rk_step_vjp_dot_product(orc, torch_cuda):
+    import torch
+    N, nelem = 3, (2, 4, 2)
+    s, op = make(orc, N, nelem, 1, mu=1e-4, uinf=1.0, mainf=0.7)
+    U = channel_state(N, nelem, 395, noise=0.01)
+    v = I.random_directions(U.shape, 24)
+    w = I.random_directions(U.shape, 25)
+    dt = 0.5 * orc.max_dt(s, U, 0.5)
+    _, Jv = orc.rk_jvp(s, U, v, dt, 1)
+    JTw = op.rk_step_vjp(torch.from_numpy(U).cuda(), dt, torch.from_numpy(w).cuda()).cpu().numpy()
+    a, b = np.sum(w * Jv), np.sum(JTw * v)
+    assert abs(a - b) <= 1e-12 * np.sum(np.abs(w * Jv)), (a, b)
