@@ -197,8 +197,8 @@ int dg_set_connectivity(dg_ctx* ctx, const int32_t* conn);
  * calls that would break this return DG_EUNSUPPORTED.  dg_vjp and rk_step_vjp
  * differentiate through the walls (mirror states, and the wall shear through
  * the Newton solution by the implicit function theorem and through the van
- * Driest transformation, derivative 0 where its argument is capped); not
- * together with the Smagorinsky model (DG_EUNSUPPORTED).
+ * Driest transformation, derivative 0 where its argument is capped), also
+ * together with the Smagorinsky model.
  * Errors (nothing is changed then): DG_EINVAL for wall_dir outside -1..2,
  * ma_inf < 0 or non-finite, or ma_inf > 0 with u_inf <= 0; DG_EUNSUPPORTED as
  * above; DG_ENOMEM. */
@@ -235,8 +235,7 @@ int dg_rk_steps(dg_ctx* ctx, double* U, double dt, int nsteps);
  * Smagorinsky model it includes the eddy viscosity's dependence on the
  * lifted gradient and the density (derivative of |S| taken as 0 where
  * |S| = 0); with wall-modelled boundaries it includes the wall model.  Not
- * available with DG_MIXED, the CH flux, or walls together with the
- * Smagorinsky model (DG_EUNSUPPORTED).
+ * available with DG_MIXED or the CH flux (DG_EUNSUPPORTED).
  * Allocates the reverse-mode face buffer (and with blending two more buffers)
  * on first use. */
 int dg_vjp(dg_ctx* ctx, const double* U, const double* Ut_bar, double* U_bar);

@@ -417,8 +417,6 @@ int wall_compatible(dg_ctx* c, const dg_options* o, const char* where) {
 int vjp_supported(dg_ctx* c) {
   if (c->conn && !c->M)
     return fail(c, DG_ESTATE, "general connectivity needs curved elements: call dg_set_geometry first");
-  if (c->wall_dir >= 0 && eq_code(c) == 2)
-    return fail(c, DG_EUNSUPPORTED, "vjp: not available with wall-modelled boundaries and the Smagorinsky model");
   if (c->opt.precision != DG_FP64) return fail(c, DG_EUNSUPPORTED, "vjp: FP64 operator only");
   if (c->opt.vol_flux == DG_VF_CH) return fail(c, DG_EUNSUPPORTED, "vjp: not available for the CH flux");
   return DG_OK;

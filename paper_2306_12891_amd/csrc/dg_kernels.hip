@@ -2023,13 +2023,14 @@ __global__ __launch_bounds__(NT) void k_vjp_lift_les(VjpArgs A) {
   const double* sDw = sB + BL.Dw();
   const double* swinv = sB + BL.winv();
   const double csd2 = vjp_csd2(A, e);
+  const int wmask = vjp_wall_mask(A, e);
   for (int q = t; q < 6 * nf; q += NT) {
     const int f = q / nf, a = q - f * nf, d = f >> 1;
     const int m = face_node(d, (f & 1) ? N : 0, a);
     const int ijk[3] = {m % n1, (m / n1) % n1, m / nf};
     double g[3][4], Fvb[3][4], gb[3][4], rhob = 0.0;
     lifted_gradient<double>(sP, sQ, sDw, swinv, m, ijk, A.invJ, g);
-    viscous_flux_cotangent(sLam, sLn, sDw, swinv, m, ijk, A.invJ, Fvb);
+    viscous_flux_cotangent(sLam, sLn, sDw, swinv, m, ijk, A.invJ, Fvb, wmask);
     const double u[3] = {sP[1][m], sP[2][m], sP[3][m]};
     les_gradient_cotangent(Fvb, u, g, sP[0][m], A.mu, A.kappa, csd2, A.ktf, gb, rhob);
     double* out = A.Gbf + ((size_t)e * 6 + f) * 4 * nf;
@@ -2098,7 +2099,7 @@ template <int VF, int EQ, bool WALL = false>
 __global__ __launch_bounds__(NT) void k_vjp(VjpArgs A) {
   constexpr bool NS = (EQ >= 1);
   constexpr bool LES = (EQ == 2);
-  static_assert(!WALL || EQ == 1, "walls: Navier-Stokes without the eddy viscosity");
+  static_assert(!WALL || EQ >= 1, "walls: Navier-Stokes");
   __shared__ double sWx[WALL ? 2 : 1][4][nf];
   __shared__ double sB[NB_STAGE];
   __shared__ double sP[7][nn];
@@ -4101,9 +4102,10 @@ hipError_t launch_integrals(const ReduceArgs& R, hipStream_t s) {
 template <int VF>
 hipError_t launch_vjp_vf(const VjpArgs& A, int eq, hipStream_t s) {
   const dim3 grid(8 * A.chunk), block(NT);
-  if (A.wall_dir >= 0) {  // walls: Navier-Stokes without the eddy viscosity (checked on the host)
-    if (eq != 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_vjp<VF, 1, true>), grid, block, 0, s, A);
+  if (A.wall_dir >= 0) {  // walls: Navier-Stokes (checked on the host)
+    if (eq == 2) hipLaunchKernelGGL((k_vjp<VF, 2, true>), grid, block, 0, s, A);
+    else if (eq == 1) hipLaunchKernelGGL((k_vjp<VF, 1, true>), grid, block, 0, s, A);
+    else return hipErrorInvalidValue;
   } else if (eq == 2) hipLaunchKernelGGL((k_vjp<VF, 2>), grid, block, 0, s, A);
   else if (eq == 1) hipLaunchKernelGGL((k_vjp<VF, 1>), grid, block, 0, s, A);
   else hipLaunchKernelGGL((k_vjp<VF, 0>), grid, block, 0, s, A);

@@ -134,11 +134,6 @@ def test_error_paths(orc, torch_cuda):
         assert ei.value.code == dg.DG_EUNSUPPORTED, kw
     U = torch.from_numpy(channel_state(N, nelem, 360, lo=(0, 0, 0), hi=(TWO_PI,) * 3)).cuda()
     op.vjp(U, U.clone())  # the adjoint covers the wall model
-    op.set_options(Cs=0.1)
-    with pytest.raises(dg.DGError) as ei:  # but not with the eddy viscosity as well
-        op.vjp(U, U.clone())
-    assert ei.value.code == dg.DG_EUNSUPPORTED
-    op.set_options(Cs=0.0)
     with pytest.raises(dg.DGError) as ei:
         op.set_geometry(torch.from_numpy(I.warped_coordinates(N, nelem)).cuda())
     assert ei.value.code == dg.DG_EUNSUPPORTED
@@ -177,10 +172,12 @@ def test_vjp_dot_product(orc, torch_cuda, N, wall_dir):
     dot_check(orc, torch_cuda, s, op, channel_state(N, nelem, 370 + N), 20)
 
 
-@pytest.mark.parametrize("vf,sf,mainf,mu", [(0, 0, 0.0, 2e-3), (1, 1, 0.7, 1e-5), (3, 2, 1.5, 2e-3), (1, 2, 0.0, 1e-7)])
-def test_vjp_dot_product_fluxes_van_driest(orc, torch_cuda, vf, sf, mainf, mu):
+@pytest.mark.parametrize("vf,sf,mainf,mu,Cs", [(0, 0, 0.0, 2e-3, 0.0), (1, 1, 0.7, 1e-5, 0.0), (3, 2, 1.5, 2e-3, 0.0),
+                                             (1, 2, 0.0, 1e-7, 0.0), (1, 1, 0.7, 2e-3, 0.2), (0, 0, 0.0, 1e-5, 0.3)])
+def test_vjp_dot_product_fluxes_van_driest(orc, torch_cuda, vf, sf, mainf, mu, Cs):
+    """Also with the Smagorinsky model (Cs > 0)."""
     N, nelem = 3, (2, 3, 2)
-    s, op = make(orc, N, nelem, 1, vf=vf, sf=sf, mu=mu, uinf=0.8, mainf=mainf)
+    s, op = make(orc, N, nelem, 1, vf=vf, sf=sf, mu=mu, Cs=Cs, uinf=0.8, mainf=mainf)
     dot_check(orc, torch_cuda, s, op, channel_state(N, nelem, 380 + vf), 22)
 
 
