@@ -107,11 +107,12 @@ def domain(name):
 # calibration (FETCH x 2.000, WRITE x 1.000); see profiles/k_stage_*.md.  Valid
 # only for the kernel source they were taken on (sha256 prefix).
 MEASURED_TRAFFIC = {
-    "kernel_sha": "9e5f8f8bb9fc32d2",
+    "kernel_sha": "4d3edc3e3c9dbf3d",
     "tgv_n5_32": {"bytes_per_launch": 1380.3e6, "fetch": 870.7e6, "write": 509.6e6},
-    "tgv_n7_64": {"bytes_per_launch": 26683.5e6, "fetch": 17019.8e6, "write": 9663.7e6},
-    "freestream_euler_n7_64": {"bytes_per_launch": 22932.5e6, "fetch": 13268.8e6, "write": 9663.7e6},
-    "tgv_curved_n5_32": {"bytes_per_launch": 2029.6e6, "fetch": 1520.0e6, "write": 509.6e6},
+    "tgv_n7_64": {"bytes_per_launch": 26683.9e6, "fetch": 17020.3e6, "write": 9663.7e6},
+    "freestream_euler_n7_64": {"bytes_per_launch": 22929.5e6, "fetch": 13265.8e6, "write": 9663.7e6},
+    "tgv_curved_n5_32": {"bytes_per_launch": 2029.4e6, "fetch": 1519.8e6, "write": 509.6e6},
+    "channel_wm_n5_32": {"bytes_per_launch": 1372.5e6, "fetch": 862.9e6, "write": 509.6e6},
 }
 
 
