@@ -2096,9 +2096,10 @@ __device__ __forceinline__ void volume_vjp_dir(const double (*sP)[nn], const dou
 
 // Main reverse kernel.  Writes U_bar (or U_acc + U_bar when A.Uacc is set).
 // Three waves per SIMD (at most 168 registers; a few spill) run the reverse
-// kernel faster than two without spills; the wall variants keep their registers.
+// kernel faster than two without spills; the wall variants keep their
+// registers, and so does N = 7, where the LDS admits one workgroup per CU.
 template <int VF, int EQ, bool WALL = false>
-__global__ __launch_bounds__(NT, WALL ? 1 : 3) void k_vjp(VjpArgs A) {
+__global__ __launch_bounds__(NT, WALL || N > 6 ? 1 : 3) void k_vjp(VjpArgs A) {
   constexpr bool NS = (EQ >= 1);
   constexpr bool LES = (EQ == 2);
   static_assert(!WALL || EQ >= 1, "walls: Navier-Stokes");

@@ -378,10 +378,13 @@ class _Rollout(torch.autograd.Function):
         ctx.op, ctx.dt, ctx.nsteps, ctx.every = op, float(dt), int(nsteps), int(every)
         U = U0.detach().clone()
         ckpt = {0: U.clone()}
-        for s in range(nsteps):
-            op.rk_step(U, dt)
-            if (s + 1) % every == 0 and s + 1 < nsteps:
-                ckpt[s + 1] = U.clone()
+        s = 0
+        while s < nsteps:  # one library call per segment (the same steps as rk_step, bitwise)
+            k = min(every, nsteps - s)
+            op.rk_steps(U, dt, k)
+            s += k
+            if s < nsteps:
+                ckpt[s] = U.clone()
         ctx.ckpt = ckpt
         return U
 

@@ -122,6 +122,26 @@ def test_recorded_stages(orc, torch_cuda, eq, vf, sf):
                        ctypes.c_void_p(w.data_ptr()), ctypes.c_void_p(Y[3].data_ptr())) == dg.DG_EINVAL
 
 
+def test_rollout_forward_is_rk_steps(orc, torch_cuda):
+    """The checkpointed rollout's forward (one library call per segment, with
+    checkpoints) gives bitwise the state of plain rk_steps and of rk_step
+    called step by step."""
+    import torch
+
+    from paper_2306_12891_amd import dg
+    N, nelem = 3, (2, 2, 2)
+    s, op = make(orc, N, nelem, 1, 1, 1)
+    U0 = torch.from_numpy(I.random_smooth(N, nelem, seed=27, noise=0.01)).cuda()
+    dt = 0.5 * orc.max_dt(s, U0.cpu().numpy(), 0.5)
+    a = dg.rollout(op, U0, dt, 7, checkpoint_every=3)
+    b = U0.clone()
+    op.rk_steps(b, dt, 7)
+    c = U0.clone()
+    for _ in range(7):
+        op.rk_step(c, dt)
+    assert torch.equal(a, b) and torch.equal(b, c)
+
+
 def test_autograd_functions(orc, torch_cuda):
     import torch
 
