@@ -119,6 +119,9 @@ struct KernelTable {
   hipError_t (*max_rate)(const ReduceArgs&, hipStream_t);
   hipError_t (*integrals)(const ReduceArgs&, hipStream_t);
   hipError_t (*nonfinite)(const ReduceArgs&, hipStream_t);
+  // reverse operator (eq 0 Euler, 1 Navier-Stokes, 2 with the eddy viscosity;
+  // walls per VjpArgs.wall_dir) and its BR1 pass 1 (the eddy-viscosity
+  // variant per VjpArgs.les)
   hipError_t (*vjp)(const VjpArgs&, int eq, hipStream_t);
   hipError_t (*vjp_lift)(const VjpArgs&, hipStream_t);
   // reverse mode through the blending: per-element cotangent of alpha, its
@@ -136,7 +139,7 @@ struct KernelTable {
                         hipStream_t);
   hipError_t (*stage_curved)(const StageArgs&, int eq, hipStream_t);
   hipError_t (*lift_curved)(const StageArgs&, hipStream_t);
-  // reverse mode on curved elements (FP64, no blending)
+  // reverse mode on curved elements (FP64; no blending or eddy viscosity there)
   hipError_t (*vjp_curved)(const VjpArgs&, int eq, hipStream_t);
   hipError_t (*vjp_lift_curved)(const VjpArgs&, hipStream_t);
   // wall-model flux at the wall face nodes into Fvf (FP64, after the lift)

@@ -1405,7 +1405,9 @@ __global__ __launch_bounds__(256) void k_wall_flux(StageArgs A) {
 }
 
 // ===========================================================================
-// Reverse mode: vector-Jacobian product of the FP64 operator (no blending).
+// Reverse mode: vector-Jacobian product of the FP64 operator (the blending,
+// curved meshes, the eddy viscosity and the wall model further below or as
+// variants of these kernels).
 //
 //   U_bar = (dL/dU)^T lambda,   lambda = cotangent of U_t.
 //
@@ -2095,6 +2097,8 @@ __device__ __forceinline__ void volume_vjp_dir(const double (*sP)[nn], const dou
 }
 
 // Main reverse kernel.  Writes U_bar (or U_acc + U_bar when A.Uacc is set).
+// EQ: 0 Euler, 1 Navier-Stokes, 2 with the Smagorinsky eddy viscosity; WALL:
+// wall-modelled faces (neighbour -1).
 // Three waves per SIMD (at most 168 registers; a few spill) run the reverse
 // kernel faster than two without spills; the wall variants keep their
 // registers, and so does N = 7, where the LDS admits one workgroup per CU.
@@ -2491,10 +2495,10 @@ __global__ __launch_bounds__(NT) void k_vjp_alpha(VjpArgs A) {
 
 // FV subcell part: U_bar += V_FV^T(a lambda) for blended elements.  Per
 // direction: the interior subcell fluxes F_{m+1/2} = f*(w+_m, w-_{m+1}) are
-// differentiated with respect to the ten primitive components of their two
-// reconstructed states by one dual-number evaluation per (interface, seed)
-// work unit (rotated frame, one code path for all directions); the
-// reconstruction (minmod, positivity fallback) is pulled back along each
+// pulled back to the ten primitive components of their two reconstructed
+// states by one reverse sweep of the interface flux (riemann_vjp) per
+// subcell interface node (rotated frame, one code path for all directions);
+// the reconstruction (minmod, positivity fallback) is pulled back along each
 // line per variable.
 template <int VF>
 __global__ __launch_bounds__(NT) void k_vjp_fv(VjpArgs A) {
