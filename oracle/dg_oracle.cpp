@@ -223,12 +223,13 @@ struct Ctx {
   std::vector<double> Ja;  // [e][i][m][n]
   std::vector<double> Jn;  // [e][n]
   std::vector<int> conn;   // [e][f][3]: neighbour, its face, orientation (curved meshes)
+  std::vector<double> d2e; // curved meshes: squared filter width per element
   double ja(int e, int i, int m, int n) const { return Ja[((size_t(e) * 3 + i) * 3 + m) * nn + n]; }
   double jac(int e, int n) const { return Jn[size_t(e) * nn + n]; }
   // (C_s Delta)^2 of element e; 0 without the Smagorinsky model
   double csd2(int e) const {
     const double cs = s.cs_elem ? s.cs_elem[e] : s.Cs;
-    return cs * cs * delta2;
+    return cs * cs * (curved ? d2e[e] : delta2);
   }
   bool les() const { return s.equations == 1 && (s.cs_elem != nullptr || s.Cs > 0.0); }
 };
@@ -280,6 +281,16 @@ static Ctx make_ctx(const Setup& s) {
       }
   if (s.xnodes) {
     curved_metrics(c);
+    // reading (curved elements): filter width = (element volume)^(1/3) / (N + 1),
+    // the volume sum_n w_i w_j w_k J_n (the box's (dx dy dz)^(1/3) / (N + 1))
+    c.d2e.assign(c.nelem, 0.0);
+    for (int e = 0; e < c.nelem; ++e) {
+      double vol = 0.0;
+      for (int n = 0; n < c.nn; ++n)
+        vol += c.b.w[n % c.n1] * c.b.w[(n / c.n1) % c.n1] * c.b.w[n / c.nf] * c.jac(e, n);
+      const double delta = std::cbrt(vol) / (c.N + 1.0);
+      c.d2e[e] = delta * delta;
+    }
     c.conn.assign(size_t(c.nelem) * 18, 0);
     for (int e = 0; e < c.nelem; ++e)
       for (int f = 0; f < 6; ++f) {
@@ -1131,7 +1142,7 @@ static void viscous_dg_curved(const Ctx& c, const T* U, T* Ut) {
         for (int k = 0; k < 4; ++k) gr[dd][k] = grad[((size_t(e) * 3 + dd) * 4 + k) * c.nn + n];
       for (int m = 0; m < 3; ++m) {
         T F[5];
-        viscous_flux(m, g, mu, Pr, 0.0, c.s.Prt, u, gr, F);
+        viscous_flux(m, g, mu, Pr, c.csd2(e), c.s.Prt, u, gr, F);
         for (int v = 0; v < 5; ++v) Fv[((size_t(e) * 3 + m) * 5 + v) * c.nn + n] = F[v];
       }
     }
@@ -1352,7 +1363,7 @@ template <class T>
 static void time_derivative(const Ctx& c, const T* U, T* Ut, const double* alpha_in,
                             T* Ut_dg_out, T* Ut_fv_out, double* alpha_out) {
   const size_t tot = size_t(c.nelem) * 5 * c.nn;
-  if (c.curved) {  // no blending or eddy viscosity on curved meshes (refused by valid())
+  if (c.curved) {  // no blending on curved meshes (refused by valid())
     std::vector<T> fstar;
     surface_pass_curved(c, U, fstar);
     advective_dg_curved(c, U, fstar, Ut);
@@ -1764,9 +1775,9 @@ static bool valid(const Setup* s) {
   if (!(s->gamma > 1.0) || s->mu < 0.0) return false;
   if (s->blending && s->N < 2) return false;
   if (s->Cs < 0.0 || ((s->Cs > 0.0 || s->cs_elem) && !(s->Prt > 0.0))) return false;
-  // curved meshes: split-form DG (Euler, Navier-Stokes) without blending or
-  // the eddy viscosity
-  if (s->xnodes && (s->blending || s->Cs > 0.0 || s->cs_elem)) return false;
+  // curved meshes: split-form DG (Euler, Navier-Stokes, also with the eddy
+  // viscosity) without blending
+  if (s->xnodes && s->blending) return false;
   if (s->conn && !s->xnodes) return false;
   // walls: Navier-Stokes on the box, no blending (the spread needs neighbours)
   if (s->wall_dir >= 0 && (s->wall_dir > 2 || s->equations != EQ_NS || s->blending || s->xnodes)) return false;

@@ -363,3 +363,47 @@ def test_jvp_on_curved_mesh_matches_central_differences(orc, eq, rot):
     eps = 1e-6
     fd = (orc.time_derivative(s, U + eps * V) - orc.time_derivative(s, U - eps * V)) / (2 * eps)
     assert np.max(np.abs(JV - fd)) <= 1e-7 * np.max(np.abs(JV))
+
+
+# ---------------------------------------------------------------------------
+# Smagorinsky eddy viscosity on curved elements.  Reading: the filter width
+# of an element is (element volume)^(1/3) / (N + 1), the volume the quadrature
+# sum of J, which is the box's (dx dy dz)^(1/3) / (N + 1): the box given as
+# coordinates (also with elements of aspect ratio 2) reproduces the Cartesian
+# model; conservation and forward-mode derivatives on warped meshes.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("vf,sf,field", [(1, 1, False), (0, 0, True), (3, 2, False)])
+def test_les_cartesian_coordinates_reproduce_box(orc, vf, sf, field):
+    N, ne, lo, hi = 3, (3, 2, 2), (0.0, -1.0, 0.5), (6.0, 1.0, 2.0)
+    X, Y, Z = I.node_coordinates(N, ne, lo, hi)
+    xn = np.ascontiguousarray(np.stack([X, Y, Z], axis=1))
+    U = I.random_smooth(N, ne, lo, hi, seed=61, noise=0.02)
+    cs = np.random.default_rng(5).uniform(0.1, 0.4, 12) if field else None
+    kw = dict(equations=1, vol_flux=vf, surf_flux=sf, mu=2e-3, Cs=0.0 if field else 0.3, cs_elem=cs)
+    a = orc.time_derivative(orc.Setup(N=N, nelem=ne, lo=lo, hi=hi, **kw), U)
+    b = orc.time_derivative(setup(orc, N, ne, xn, **kw), U)
+    assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(a))
+    # the model is active well above that tolerance
+    plain = orc.time_derivative(orc.Setup(N=N, nelem=ne, lo=lo, hi=hi, equations=1, vol_flux=vf, surf_flux=sf,
+                                          mu=2e-3), U)
+    assert np.max(np.abs(plain - a)) > 1e-4 * np.max(np.abs(a))
+
+
+@pytest.mark.parametrize("rot", [False, True])
+def test_les_conservation_and_jvp_on_warped_mesh(orc, rot):
+    N, ne = 3, (3, 2, 2)
+    xn = I.warped_coordinates(N, ne, amp=0.05)
+    conn = None
+    if rot:
+        perm, conn = I.rotated_elements(N, ne, seed=6)
+        xn = I.relabel(xn, perm)
+    s = orc.Setup(N=N, nelem=ne, equations=1, vol_flux=1, surf_flux=1, mu=2e-3, Cs=0.25, xnodes=xn, conn=conn)
+    U = I.random_smooth(N, ne, seed=63, noise=0.02, xnodes=xn)
+    Ut = orc.time_derivative(s, U)
+    tot, mag = orc.integrals(s, Ut), orc.integrals(s, np.abs(Ut))
+    assert np.all(np.abs(tot) < 1e-13 * mag), (tot, mag)
+    V = I.random_directions(U.shape, 12)
+    _, JV = orc.jvp(s, U, V)
+    eps = 1e-6
+    fd = (orc.time_derivative(s, U + eps * V) - orc.time_derivative(s, U - eps * V)) / (2 * eps)
+    assert np.max(np.abs(JV - fd)) <= 1e-6 * np.max(np.abs(JV))
