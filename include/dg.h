@@ -119,7 +119,8 @@ int dg_get_options(const dg_ctx* ctx, dg_options* opt);
  * element and the eddy viscosity is evaluated at every solution point of the
  * element).  With DG_NS, at every node of element e:
  *   mu_t = rho (C_s(e) Delta)^2 |S|,  |S| = sqrt(2 S_ij S_ij) of the lifted
- *   velocity gradient, Delta = (dx dy dz)^(1/3) / (N + 1),
+ *   velocity gradient, Delta = (dx dy dz)^(1/3) / (N + 1) (on curved meshes
+ *   (element volume)^(1/3) / (N + 1), see dg_set_geometry),
  * added to mu in the viscous stress, and mu_t gamma / ((gamma - 1) Prt) added
  * to the heat-flux coefficient mu gamma / ((gamma - 1) Pr).
  * cs: device pointer to nElems doubles (element order of the state), copied
@@ -127,7 +128,8 @@ int dg_get_options(const dg_ctx* ctx, dg_options* opt);
  * replaces opt.Cs until dg_set_cs_field(ctx, NULL) restores the constant.
  * Errors: DG_EINVAL for a host pointer, DG_EUNSUPPORTED with DG_VF_CH,
  * DG_ENOMEM.  dg_vjp and rk_step_vjp differentiate through the model (mu_t
- * through |S|, with derivative 0 where |S| = 0, and through rho).  The
+ * through |S|, with derivative 0 where |S| = 0, and through rho), on the
+ * Cartesian box.  The
  * time-step estimate dg_max_dt uses the molecular viscosity only. */
 int dg_set_cs_field(dg_ctx* ctx, const double* cs);
 
@@ -147,14 +149,17 @@ int dg_set_cs_field(dg_ctx* ctx, const double* cs);
  *            face flux |Ja_f| f*(U-, U+; Ja_f/|Ja_f|) ],
  * Ja_f the mean of both elements' metric at a face node; Navier-Stokes with
  * the BR1 gradient (1/J) sum_i Ja^i (d_i q + lifting) and the contravariant
- * viscous flux.  X = NULL returns to the Cartesian box of dg_init.
+ * viscous flux; with the Smagorinsky model the filter width of an element is
+ * (element volume)^(1/3) / (N + 1), the volume the quadrature sum of J (on
+ * the box the Cartesian (dx dy dz)^(1/3) / (N + 1)).  X = NULL returns to the
+ * Cartesian box of dg_init.
  * Errors (the context's geometry is then unchanged): DG_EINVAL for a host
  * pointer or a non-positive / non-finite Jacobian at any node; DG_EUNSUPPORTED with
- * blending, DG_MIXED, DG_VF_CH or the Smagorinsky model (and later
- * dg_set_options / dg_set_cs_field calls that would enable them return it);
- * DG_ENOMEM.  dg_vjp and rk_step_vjp work on curved meshes (also with general
- * connectivity); dg_node_weights returns DG_EUNSUPPORTED there (per-node
- * Jacobians: use dg_integrals). */
+ * blending, DG_MIXED or DG_VF_CH (and later dg_set_options calls that would
+ * enable them return it); DG_ENOMEM.  dg_vjp and rk_step_vjp work on curved
+ * meshes (also with general connectivity), except with the Smagorinsky model
+ * there (DG_EUNSUPPORTED); dg_node_weights returns DG_EUNSUPPORTED there
+ * (per-node Jacobians: use dg_integrals). */
 int dg_set_geometry(dg_ctx* ctx, const double* X);
 
 /* General connectivity of a curved mesh (unstructured hexahedra, as the
@@ -235,7 +240,8 @@ int dg_rk_steps(dg_ctx* ctx, double* U, double dt, int nsteps);
  * Smagorinsky model it includes the eddy viscosity's dependence on the
  * lifted gradient and the density (derivative of |S| taken as 0 where
  * |S| = 0); with wall-modelled boundaries it includes the wall model.  Not
- * available with DG_MIXED or the CH flux (DG_EUNSUPPORTED).
+ * available with DG_MIXED, the CH flux, or the Smagorinsky model on curved
+ * meshes (DG_EUNSUPPORTED).
  * Allocates the reverse-mode face buffer (and with blending two more buffers)
  * on first use. */
 int dg_vjp(dg_ctx* ctx, const double* U, const double* Ut_bar, double* U_bar);

@@ -177,6 +177,7 @@ struct dg_ctx {
   double* cs_field = nullptr;  // per-element Smagorinsky coefficients (dg_set_cs_field)
   int has_cs_field = 0;
   double* M = nullptr;         // curved mesh metrics [nelem][10][nn] (dg_set_geometry), NULL: box
+  double* d2e = nullptr;       // curved mesh: squared filter width of the eddy viscosity per element
   int* d_bad = nullptr;        // count of invalid Jacobians (dg_set_geometry)
   int32_t* conn = nullptr;     // general connectivity [nelem][6][3] (dg_set_connectivity), NULL: structured
   int wall_dir = -1;           // wall-modelled faces normal to this direction (dg_set_wall_model), -1: none
@@ -238,6 +239,7 @@ void release(dg_ctx* c) {
   hipFree(c->Fvf);
   hipFree(c->cs_field);
   hipFree(c->M);
+  hipFree(c->d2e);
   hipFree(c->d_bad);
   hipFree(c->conn);
   hipFree(c->partial);
@@ -276,6 +278,7 @@ StageArgs stage_args(const dg_ctx* c) {
   a.cs_elem = c->has_cs_field ? c->cs_field : nullptr;
   a.M = c->M;
   a.conn = c->conn;
+  a.delta2_elem = c->d2e;
   a.cs = c->opt.Cs;
   a.wall_dir = c->wall_dir;
   for (int d = 0; d < 3; ++d) a.ne[d] = c->ne[d];
@@ -367,9 +370,9 @@ int run_stage(dg_ctx* c, const double* Xin, double* Xout, double* Ut, int mode, 
     return fail(c, DG_ESTATE, "general connectivity needs curved elements: call dg_set_geometry first");
   if (c->wall_dir >= 0 && (eq == 0 || c->opt.blending || c->opt.precision != DG_FP64 || c->M))
     return fail(c, DG_ESTATE, "wall-modelled boundaries need the FP64 Navier-Stokes operator on the box");
-  if (c->M) {  // curved mesh (FP64, no blending or eddy viscosity: checked when set)
+  if (c->M) {  // curved mesh (FP64, no blending: checked when set)
     if (eq >= 1) {
-      e = timed(c, DG_K_LIFT, [&] { return c->kt->lift_curved(a, c->stream); });
+      e = timed(c, DG_K_LIFT, [&] { return c->kt->lift_curved(a, eq, c->stream); });
       if (e != hipSuccess) return hip_fail(c, e, "lifting kernel (curved)");
     }
     e = timed(c, DG_K_STAGE, [&] { return c->kt->stage_curved(a, eq, c->stream); });
@@ -395,12 +398,13 @@ int run_stage(dg_ctx* c, const double* Xin, double* Xout, double* Ut, int mode, 
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
 // Options a curved mesh supports: the FP64 operator with the KG, PI or STD
-// volume flux, Euler or Navier-Stokes, no blending, no eddy viscosity.
+// volume flux, Euler or Navier-Stokes (also with the eddy viscosity), no
+// blending.
 int curved_compatible(dg_ctx* c, const dg_options* o, int cs_field, const char* where) {
+  (void)cs_field;
   if (o->blending) return fail(c, DG_EUNSUPPORTED, "%s: no blending on curved meshes", where);
   if (o->precision != DG_FP64) return fail(c, DG_EUNSUPPORTED, "%s: curved meshes use the FP64 operator", where);
   if (o->vol_flux == DG_VF_CH) return fail(c, DG_EUNSUPPORTED, "%s: curved meshes: KG, PI or STD flux", where);
-  if (o->Cs > 0.0 || cs_field) return fail(c, DG_EUNSUPPORTED, "%s: no Smagorinsky model on curved meshes", where);
   return DG_OK;
 }
 
@@ -419,6 +423,8 @@ int vjp_supported(dg_ctx* c) {
     return fail(c, DG_ESTATE, "general connectivity needs curved elements: call dg_set_geometry first");
   if (c->opt.precision != DG_FP64) return fail(c, DG_EUNSUPPORTED, "vjp: FP64 operator only");
   if (c->opt.vol_flux == DG_VF_CH) return fail(c, DG_EUNSUPPORTED, "vjp: not available for the CH flux");
+  if (c->M && eq_code(c) == 2)
+    return fail(c, DG_EUNSUPPORTED, "vjp: not available with the eddy viscosity on curved meshes");
   return DG_OK;
 }
 
@@ -784,6 +790,8 @@ int dg_set_geometry(dg_ctx* c, const double* X) {
   if (!X) {
     hipFree(c->M);
     c->M = nullptr;
+    hipFree(c->d2e);
+    c->d2e = nullptr;
     return DG_OK;
   }
   if (!is_device_ptr(X)) return fail(c, DG_EINVAL, "dg_set_geometry: X must be a device pointer");
@@ -792,25 +800,30 @@ int dg_set_geometry(dg_ctx* c, const double* X) {
   if (rc) return rc;
   // metric terms into a new array, swapped in only when complete and valid:
   // a failure leaves the context's geometry unchanged
-  double* M = nullptr;
+  double *M = nullptr, *d2 = nullptr;
   hipError_t e = hipMalloc((void**)&M, (size_t)c->nelem * 10 * c->nn * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&d2, (size_t)c->nelem * sizeof(double));
   if (e == hipSuccess && !c->d_bad) e = hipMalloc((void**)&c->d_bad, sizeof(int));
   int bad = 0;
   if (e == hipSuccess) e = hipMemsetAsync(c->d_bad, 0, sizeof(int), c->stream);
-  if (e == hipSuccess) e = c->kt->metrics(X, c->basis, M, c->d_bad, c->nelem, c->chunk, c->stream);
+  if (e == hipSuccess) e = c->kt->metrics(X, c->basis, M, c->d_bad, d2, c->nelem, c->chunk, c->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(&bad, c->d_bad, sizeof(int), hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     hipFree(M);
+    hipFree(d2);
     return fail(c, (e == hipErrorOutOfMemory) ? DG_ENOMEM : DG_EHIP, "dg_set_geometry: %s", hipGetErrorString(e));
   }
   if (bad) {
     hipFree(M);
+    hipFree(d2);
     return fail(c, DG_EINVAL, "dg_set_geometry: %d nodes with a non-positive or non-finite Jacobian", bad);
   }
   hipFree(c->M);
   c->M = M;
+  hipFree(c->d2e);
+  c->d2e = d2;
   return DG_OK;
 }
 
@@ -821,7 +834,6 @@ int dg_set_cs_field(dg_ctx* c, const double* cs) {
     return DG_OK;
   }
   if (!is_device_ptr(cs)) return fail(c, DG_EINVAL, "dg_set_cs_field: cs must be a device pointer");
-  if (c->M) return fail(c, DG_EUNSUPPORTED, "dg_set_cs_field: the Smagorinsky model is not built for curved meshes");
   if (c->opt.vol_flux == DG_VF_CH)
     return fail(c, DG_EUNSUPPORTED, "dg_set_cs_field: the Smagorinsky model is built for the KG, PI and STD fluxes");
   hipError_t e = hipSuccess;

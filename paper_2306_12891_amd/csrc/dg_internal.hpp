@@ -60,6 +60,8 @@ struct StageArgs {
   int wall_dir;
   double wm_h, wm_uinf, wm_b;
   int ne[3];  // elements per direction of the box
+  // curved mesh with the eddy viscosity: squared filter width per element
+  const double* delta2_elem;
 };
 
 struct ReduceArgs {
@@ -134,11 +136,13 @@ struct KernelTable {
   hipError_t (*axpby)(double* y, double a, const double* x, double b, size_t n, hipStream_t);
   // curved mesh: metric terms from node coordinates X[e][3][nn] into M
   // (counts non-positive or non-finite Jacobians into *bad), and the
-  // operator kernels with metric terms (FP64; eq 0 Euler, 1 Navier-Stokes)
-  hipError_t (*metrics)(const double* X, const double* basis, double* M, int* bad, int nelem, int chunk,
-                        hipStream_t);
+  // operator kernels with metric terms (FP64; eq 0 Euler, 1 Navier-Stokes,
+  // 2 with the eddy viscosity; the metric kernel also writes the squared
+  // filter width per element into d2)
+  hipError_t (*metrics)(const double* X, const double* basis, double* M, int* bad, double* d2, int nelem,
+                        int chunk, hipStream_t);
   hipError_t (*stage_curved)(const StageArgs&, int eq, hipStream_t);
-  hipError_t (*lift_curved)(const StageArgs&, hipStream_t);
+  hipError_t (*lift_curved)(const StageArgs&, int eq, hipStream_t);
   // reverse mode on curved elements (FP64; no blending or eddy viscosity there)
   hipError_t (*vjp_curved)(const VjpArgs&, int eq, hipStream_t);
   hipError_t (*vjp_lift_curved)(const VjpArgs&, hipStream_t);

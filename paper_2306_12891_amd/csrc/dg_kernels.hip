@@ -2878,11 +2878,14 @@ __device__ __forceinline__ int node_along(int n, int id, int st, int l) { return
 // Jacobian is not positive and finite.  Coordinates are taken relative to
 // c = (X_first + X_last)/2 of the element (the curl form is translation
 // invariant; small products keep the round-off of its differences small).
+// Also the squared filter width of the eddy viscosity per element, d2[e] =
+// ((element volume)^(1/3) / (N + 1))^2, the volume the quadrature sum of J.
 __global__ __launch_bounds__(NT) void k_metrics(const double* X, const double* basis, double* M, int* bad,
-                                                 int nelem, int chunk) {
+                                                 double* d2, int nelem, int chunk) {
   __shared__ double sD[nf];
   __shared__ double sX[3][nn];
   __shared__ double sG[2][nn];
+  __shared__ double sW[nn];
   const int e = element_of_block(blockIdx.x, chunk);
   if (e >= nelem) return;
   const int t = threadIdx.x;
@@ -2911,6 +2914,15 @@ __global__ __launch_bounds__(NT) void k_metrics(const double* X, const double* b
                      dX[0][2] * (dX[1][0] * dX[2][1] - dX[1][1] * dX[2][0]);
     if (!(J > 0.0) || !isfinite(J)) atomicAdd(bad, 1);
     M[((size_t)e * MS + 9) * nn + t] = 1.0 / J;
+    const double* w = basis + BL.winv();
+    sW[t] = J / (w[ijk[0]] * w[ijk[1]] * w[ijk[2]]);
+  }
+  __syncthreads();
+  if (t == 0) {  // element volume in node order
+    double vol = 0.0;
+    for (int n = 0; n < nn; ++n) vol += sW[n];
+    const double delta = cbrt(vol) / (double)n1;
+    d2[e] = delta * delta;
   }
   for (int i = 0; i < 3; ++i) {
     const int j = (i + 1) % 3, k = (i + 2) % 3;
@@ -3303,7 +3315,13 @@ __global__ __launch_bounds__(NT, DG_N == 5 ? 3 : 1) void k_stage_curved(StageArg
 #pragma unroll
         for (int c = 0; c < 4; ++c)
           g[m][c] = iJ * (mt[m] * s[0][c] + mt[3 + m] * s[1][c] + mt[6 + m] * s[2][c]);
-      const double mu = A.mu, kap = A.kappa;
+      double mu = A.mu, kap = A.kappa;
+      if (EQ == 2) {  // Smagorinsky eddy viscosity with the element's filter width
+        const double cs = A.cs_elem ? A.cs_elem[e] : A.cs;
+        const double mut = eddy_viscosity<double>(g, me[0], cs * cs * A.delta2_elem[e]);
+        mu += mut;
+        kap = fma(A.ktf, mut, kap);
+      }
       viscous_flux<0, double>(g, me[1], me[2], me[3], mu, kap, Fv[0]);
       viscous_flux<1, double>(g, me[1], me[2], me[3], mu, kap, Fv[1]);
       viscous_flux<2, double>(g, me[1], me[2], me[3], mu, kap, Fv[2]);
@@ -3390,10 +3408,11 @@ __global__ __launch_bounds__(NT, DG_N == 5 ? 3 : 1) void k_stage_curved(StageArg
 // One element per workgroup (measured at N = 5: two elements per workgroup,
 // which speeds up the Cartesian lifting kernel, make this one 9 % slower).
 using PLC = Pack<1>;
+template <bool LES>
 __global__ __launch_bounds__(PLC::NTB) void k_lift_curved(StageArgs A) {
   constexpr int EPB = PLC::EPB, TPE = PLC::TPE, FIC = PLC::FI;
   __shared__ double sB[NB_STAGE];
-  __shared__ double sqAll[EPB][4][nn];
+  __shared__ double sqAll[EPB][LES ? 5 : 4][nn];
   __shared__ double sQAll[EPB][6][4][nf];
   const int e0 = EPB * element_of_block(blockIdx.x, A.chunk);
   if (e0 >= A.nelem) return;  // uniform over the workgroup
@@ -3425,6 +3444,7 @@ __global__ __launch_bounds__(PLC::NTB) void k_lift_curved(StageArgs A) {
     sq[1][t] = vy;
     sq[2][t] = vz;
     sq[3][t] = p * ir;
+    if (LES) sq[LES ? 4 : 0][t] = u[0];
   }
 #pragma unroll
   for (int k = 0; k < FIC; ++k)
@@ -3485,9 +3505,16 @@ __global__ __launch_bounds__(PLC::NTB) void k_lift_curved(StageArgs A) {
         for (int c = 0; c < 4; ++c)
           g[m][c] = mt[9] * (mt[m] * s[0][c] + mt[3 + m] * s[1][c] + mt[6 + m] * s[2][c]);
       double F[3][4];
-      viscous_flux<0, double>(g, sq[0][n], sq[1][n], sq[2][n], A.mu, A.kappa, F[0]);
-      viscous_flux<1, double>(g, sq[0][n], sq[1][n], sq[2][n], A.mu, A.kappa, F[1]);
-      viscous_flux<2, double>(g, sq[0][n], sq[1][n], sq[2][n], A.mu, A.kappa, F[2]);
+      double mu = A.mu, kap = A.kappa;
+      if (LES) {  // Smagorinsky eddy viscosity with the element's filter width
+        const double cs = A.cs_elem ? A.cs_elem[e] : A.cs;
+        const double mut = eddy_viscosity<double>(g, sq[LES ? 4 : 0][n], cs * cs * A.delta2_elem[e]);
+        mu += mut;
+        kap = fma(A.ktf, mut, kap);
+      }
+      viscous_flux<0, double>(g, sq[0][n], sq[1][n], sq[2][n], mu, kap, F[0]);
+      viscous_flux<1, double>(g, sq[0][n], sq[1][n], sq[2][n], mu, kap, F[1]);
+      viscous_flux<2, double>(g, sq[0][n], sq[1][n], sq[2][n], mu, kap, F[2]);
       double Nv[3];
       const double so = curved_face_normal(cf[k], Nv);
       const double Jf[3] = {so * Nv[0], so * Nv[1], so * Nv[2]};  // face metric along the own +xi
@@ -4164,7 +4191,8 @@ hipError_t launch_axpby(double* y, double a, const double* x, double b, size_t n
 template <int VF>
 hipError_t launch_stage_curved_vf(const StageArgs& A, int eq, hipStream_t s) {
   const dim3 grid(blocks_for(A)), block(NT);
-  if (eq == 1) hipLaunchKernelGGL((k_stage_curved<VF, 1>), grid, block, 0, s, A);
+  if (eq == 2) hipLaunchKernelGGL((k_stage_curved<VF, 2>), grid, block, 0, s, A);
+  else if (eq == 1) hipLaunchKernelGGL((k_stage_curved<VF, 1>), grid, block, 0, s, A);
   else hipLaunchKernelGGL((k_stage_curved<VF, 0>), grid, block, 0, s, A);
   return hipGetLastError();
 }
@@ -4179,9 +4207,10 @@ hipError_t launch_stage_curved(const StageArgs& A, int eq, hipStream_t s) {
   }
 }
 
-hipError_t launch_lift_curved(const StageArgs& A0, hipStream_t s) {
+hipError_t launch_lift_curved(const StageArgs& A0, int eq, hipStream_t s) {
   const StageArgs A = grouped<PLC>(A0);
-  hipLaunchKernelGGL(k_lift_curved, dim3(blocks_for(A)), dim3(PLC::NTB), 0, s, A);
+  if (eq == 2) hipLaunchKernelGGL((k_lift_curved<true>), dim3(blocks_for(A)), dim3(PLC::NTB), 0, s, A);
+  else hipLaunchKernelGGL((k_lift_curved<false>), dim3(blocks_for(A)), dim3(PLC::NTB), 0, s, A);
   return hipGetLastError();
 }
 
@@ -4207,9 +4236,9 @@ hipError_t launch_vjp_lift_curved(const VjpArgs& A, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_metrics(const double* X, const double* basis, double* M, int* bad, int nelem, int chunk,
-                          hipStream_t s) {
-  hipLaunchKernelGGL(k_metrics, dim3(8 * chunk), dim3(NT), 0, s, X, basis, M, bad, nelem, chunk);
+hipError_t launch_metrics(const double* X, const double* basis, double* M, int* bad, double* d2, int nelem,
+                          int chunk, hipStream_t s) {
+  hipLaunchKernelGGL(k_metrics, dim3(8 * chunk), dim3(NT), 0, s, X, basis, M, bad, d2, nelem, chunk);
   return hipGetLastError();
 }
 
