@@ -129,7 +129,7 @@ int dg_get_options(const dg_ctx* ctx, dg_options* opt);
  * Errors: DG_EINVAL for a host pointer, DG_EUNSUPPORTED with DG_VF_CH,
  * DG_ENOMEM.  dg_vjp and rk_step_vjp differentiate through the model (mu_t
  * through |S|, with derivative 0 where |S| = 0, and through rho), on the
- * Cartesian box.  The
+ * Cartesian box and on curved meshes.  The
  * time-step estimate dg_max_dt uses the molecular viscosity only. */
 int dg_set_cs_field(dg_ctx* ctx, const double* cs);
 
@@ -157,8 +157,8 @@ int dg_set_cs_field(dg_ctx* ctx, const double* cs);
  * pointer or a non-positive / non-finite Jacobian at any node; DG_EUNSUPPORTED with
  * blending, DG_MIXED or DG_VF_CH (and later dg_set_options calls that would
  * enable them return it); DG_ENOMEM.  dg_vjp and rk_step_vjp work on curved
- * meshes (also with general connectivity), except with the Smagorinsky model
- * there (DG_EUNSUPPORTED); dg_node_weights returns DG_EUNSUPPORTED there
+ * meshes (also with general connectivity and the Smagorinsky model);
+ * dg_node_weights returns DG_EUNSUPPORTED there
  * (per-node Jacobians: use dg_integrals). */
 int dg_set_geometry(dg_ctx* ctx, const double* X);
 
@@ -240,8 +240,7 @@ int dg_rk_steps(dg_ctx* ctx, double* U, double dt, int nsteps);
  * Smagorinsky model it includes the eddy viscosity's dependence on the
  * lifted gradient and the density (derivative of |S| taken as 0 where
  * |S| = 0); with wall-modelled boundaries it includes the wall model.  Not
- * available with DG_MIXED, the CH flux, or the Smagorinsky model on curved
- * meshes (DG_EUNSUPPORTED).
+ * available with DG_MIXED or the CH flux (DG_EUNSUPPORTED).
  * Allocates the reverse-mode face buffer (and with blending two more buffers)
  * on first use. */
 int dg_vjp(dg_ctx* ctx, const double* U, const double* Ut_bar, double* U_bar);

@@ -423,8 +423,6 @@ int vjp_supported(dg_ctx* c) {
     return fail(c, DG_ESTATE, "general connectivity needs curved elements: call dg_set_geometry first");
   if (c->opt.precision != DG_FP64) return fail(c, DG_EUNSUPPORTED, "vjp: FP64 operator only");
   if (c->opt.vol_flux == DG_VF_CH) return fail(c, DG_EUNSUPPORTED, "vjp: not available for the CH flux");
-  if (c->M && eq_code(c) == 2)
-    return fail(c, DG_EUNSUPPORTED, "vjp: not available with the eddy viscosity on curved meshes");
   return DG_OK;
 }
 
@@ -483,6 +481,7 @@ int run_vjp(dg_ctx* c, const double* U, const double* lambda, double* U_bar, con
     v.wm_h = a.wm_h;
     v.wm_uinf = a.wm_uinf;
     v.wm_b = a.wm_b;
+    v.delta2_elem = a.delta2_elem;
   }
   hipError_t e;
   if (c->M) {  // curved mesh (FP64, no blending: checked when set)
@@ -490,7 +489,7 @@ int run_vjp(dg_ctx* c, const double* U, const double* lambda, double* U_bar, con
       e = timed(c, DG_K_VJP_LIFT, [&] { return c->kt->vjp_lift_curved(v, c->stream); });
       if (e != hipSuccess) return hip_fail(c, e, "vjp lifting kernel (curved)");
     }
-    e = timed(c, DG_K_VJP, [&] { return c->kt->vjp_curved(v, c->opt.equations, c->stream); });
+    e = timed(c, DG_K_VJP, [&] { return c->kt->vjp_curved(v, eq_code(c), c->stream); });
     if (e != hipSuccess) return hip_fail(c, e, "vjp kernel (curved)");
     return DG_OK;
   }

@@ -92,6 +92,8 @@ struct VjpArgs {
   // wall-modelled boundaries (see StageArgs); wall_dir -1: none
   int wall_dir;
   double wm_h, wm_uinf, wm_b;
+  // curved mesh with the eddy viscosity: squared filter width per element
+  const double* delta2_elem;
   double invJ[3];
   double gamma, mu, kappa;
   int nelem, chunk;
@@ -143,7 +145,8 @@ struct KernelTable {
                         int chunk, hipStream_t);
   hipError_t (*stage_curved)(const StageArgs&, int eq, hipStream_t);
   hipError_t (*lift_curved)(const StageArgs&, int eq, hipStream_t);
-  // reverse mode on curved elements (FP64; no blending or eddy viscosity there)
+  // reverse mode on curved elements (FP64, no blending; eq as for vjp, the
+  // pass-1 variant per VjpArgs.les)
   hipError_t (*vjp_curved)(const VjpArgs&, int eq, hipStream_t);
   hipError_t (*vjp_lift_curved)(const VjpArgs&, hipStream_t);
   // wall-model flux at the wall face nodes into Fvf (FP64, after the lift)

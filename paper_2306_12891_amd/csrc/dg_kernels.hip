@@ -1748,7 +1748,7 @@ __device__ __forceinline__ void les_gradient_cotangent(const double Fvb[3][4], c
 
 __device__ __forceinline__ double vjp_csd2(const VjpArgs& A, int e) {
   const double cs = A.cs_elem ? A.cs_elem[e] : A.cs;
-  return cs * cs * A.delta2;
+  return cs * cs * (A.delta2_elem ? A.delta2_elem[e] : A.delta2);
 }
 
 // Wall faces of element e (bit f), at most the two normal to wall_dir.
@@ -3697,7 +3697,7 @@ __device__ __forceinline__ void vjp_face_item_curved(const VjpArgs& A, int e, in
 // (sJo), the neighbour's lt at its node scaled by -s_own s_nb w_nb (sLn; w the
 // lifting weight of the neighbour's face), and, with Q, q* (forward gradient)
 // and the neighbour's pass-1 output (sGn).
-template <bool Q>
+template <bool Q, bool GN = Q>
 __device__ __forceinline__ void vjp_face_ns_curved(const VjpArgs& A, int e, int q, const double* swinv,
                                                    double (*sJo)[3][nf], double (*sLn)[4][nf], double (*sQ)[4][nf],
                                                    double (*sGn)[4][nf]) {
@@ -3730,9 +3730,11 @@ __device__ __forceinline__ void vjp_face_ns_curved(const VjpArgs& A, int e, int 
     sQ[it.f][1][it.a] = 0.5 * (vL + vR);
     sQ[it.f][2][it.a] = 0.5 * (wL + wR);
     sQ[it.f][3][it.a] = 0.5 * (pL * iL + pR * iR);
-    const double* Gn = A.Gbf + ((size_t)it.nb * 6 + it.fb) * 4 * nf;
+    if (GN) {
+      const double* Gn = A.Gbf + ((size_t)it.nb * 6 + it.fb) * 4 * nf;
 #pragma unroll
-    for (int cc = 0; cc < 4; ++cc) sGn[it.f][cc][it.a] = Gn[cc * nf + it.ab];
+      for (int cc = 0; cc < 4; ++cc) sGn[it.f][cc][it.a] = Gn[cc * nf + it.ab];
+    }
   }
 }
 
@@ -3781,12 +3783,17 @@ __device__ __forceinline__ void viscous_flux_cotangent_curved(const double (*sLt
 
 // Pass 1: at each own face node, the cotangent of the reference derivative of
 // q along the face direction times the face's lifting weight -> Gbf[e][f][c][a].
+// With the Smagorinsky model (LES) the gradient cotangent at a face node
+// depends on the eddy viscosity there: the kernel then also forms the forward
+// chain-rule gradient at its own face nodes (q at all nodes, q* of all faces).
+template <bool LES>
 __global__ __launch_bounds__(NT) void k_vjp_lift_curved(VjpArgs A) {
   __shared__ double sB[NB_STAGE];
   __shared__ double sLt[5][nn];
-  __shared__ double sU[3][nn];
+  __shared__ double sU[LES ? 5 : 3][nn];  // u, v, w (, theta, rho)
   __shared__ double sLn[6][4][nf];
   __shared__ double sJo[6][3][nf];
+  __shared__ double sQ[LES ? 6 : 1][4][nf];
   const int e = element_of_block(blockIdx.x, A.chunk);
   if (e >= A.nelem) return;
   const int t = threadIdx.x;
@@ -3799,12 +3806,22 @@ __global__ __launch_bounds__(NT) void k_vjp_lift_curved(VjpArgs A) {
     const double iJ = A.M[((size_t)e * MS + 9) * nn + t];
 #pragma unroll
     for (int j = 0; j < 3; ++j) sU[j][t] = Ue[(1 + j) * nn + t] * ir;
+    if (LES) {
+      const double p = (A.gamma - 1.0) * (Ue[4 * nn + t] - 0.5 * (Ue[nn + t] * sU[0][t] + Ue[2 * nn + t] * sU[1][t] +
+                                                                 Ue[3 * nn + t] * sU[2][t]));
+      sU[LES ? 3 : 0][t] = p * ir;
+      sU[LES ? 4 : 0][t] = Ue[t];
+    }
 #pragma unroll
     for (int v = 0; v < 5; ++v) sLt[v][t] = Le[v * nn + t] * iJ;
   }
   __syncthreads();  // swinv
-  for (int q = t; q < 6 * nf; q += NT) vjp_face_ns_curved<false>(A, e, q, swinv, sJo, sLn, nullptr, nullptr);
+  for (int q = t; q < 6 * nf; q += NT) {
+    if (LES) vjp_face_ns_curved<true, false>(A, e, q, swinv, sJo, sLn, sQ, nullptr);
+    else vjp_face_ns_curved<false>(A, e, q, swinv, sJo, sLn, nullptr, nullptr);
+  }
   __syncthreads();
+  const double csd2 = LES ? vjp_csd2(A, e) : 0.0;
   for (int q = t; q < 6 * nf; q += NT) {
     const int f = q / nf, a = q - f * nf, d = f >> 1;
     const int p = face_vol_node(f, a);
@@ -3815,7 +3832,41 @@ __global__ __launch_bounds__(NT) void k_vjp_lift_curved(VjpArgs A) {
     double Fvb[3][4], gb[3][4];
     viscous_flux_cotangent_curved(sLt, sLn, sJo, sB + BL.Dw(), swinv, p, ijk, mt, Fvb);
     const double u[3] = {sU[0][p], sU[1][p], sU[2][p]};
-    gradient_cotangent(Fvb, u, A.mu, A.kappa, gb);
+    if (LES) {  // forward chain-rule gradient at p: reference derivatives with lifting
+      const double* sDw = sB + BL.Dw();
+      double sr[3][4];
+#pragma unroll
+      for (int dd = 0; dd < 3; ++dd) {
+        const int st = dd == 0 ? 1 : (dd == 1 ? n1 : nf);
+        const int id = ijk[dd];
+        const int base = p - id * st;
+        const double* crow = sDw + id * n1;
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int l = 0; l < n1; ++l) {
+          const double c = crow[l];
+#pragma unroll
+          for (int cc = 0; cc < 4; ++cc) acc[cc] = fma(c, sU[cc][base + l * st], acc[cc]);
+        }
+        if (id == 0 || id == N) {
+          const int ff = 2 * dd + (id == N);
+          const int aa = dd == 0 ? ijk[1] + n1 * ijk[2] : (dd == 1 ? ijk[0] + n1 * ijk[2] : ijk[0] + n1 * ijk[1]);
+          const double w = id == N ? swinv[N] : -swinv[0];
+#pragma unroll
+          for (int cc = 0; cc < 4; ++cc) acc[cc] = fma(w, sQ[ff][cc][aa], acc[cc]);
+        }
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) sr[dd][cc] = acc[cc];
+      }
+      double g[3][4];
+#pragma unroll
+      for (int m = 0; m < 3; ++m)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) g[m][c] = mt[9] * (mt[m] * sr[0][c] + mt[3 + m] * sr[1][c] + mt[6 + m] * sr[2][c]);
+      double rhob = 0.0;
+      les_gradient_cotangent(Fvb, u, g, sU[LES ? 4 : 0][p], A.mu, A.kappa, csd2, A.ktf, gb, rhob);
+    } else {
+      gradient_cotangent(Fvb, u, A.mu, A.kappa, gb);
+    }
     const double w = (f & 1) ? swinv[N] : -swinv[0];
     double* out = A.Gbf + ((size_t)e * 6 + f) * 4 * nf;
 #pragma unroll
@@ -3827,7 +3878,8 @@ __global__ __launch_bounds__(NT) void k_vjp_lift_curved(VjpArgs A) {
 // Pass 2: U_bar (or U_acc + U_bar) on curved elements.
 template <int VF, int EQ>
 __global__ __launch_bounds__(NT) void k_vjp_curved(VjpArgs A) {
-  constexpr bool NS = (EQ == 1);
+  constexpr bool NS = (EQ >= 1);
+  constexpr bool LES = (EQ == 2);
   __shared__ double sB[NB_STAGE];
   __shared__ double sP[7][nn];
   __shared__ double sM[9][nn];
@@ -3922,20 +3974,23 @@ __global__ __launch_bounds__(NT) void k_vjp_curved(VjpArgs A) {
       for (int m = 0; m < 3; ++m)
 #pragma unroll
         for (int c = 0; c < 4; ++c) g[m][c] = mt[9] * (mt[m] * s[0][c] + mt[3 + m] * s[1][c] + mt[6 + m] * s[2][c]);
+      const double csd2 = LES ? vjp_csd2(A, e) : 0.0;
+      const double mue = LES ? A.mu + eddy_viscosity<double>(g, me[0], csd2) : A.mu;
       const double div = g[0][0] + g[1][1] + g[2][2];
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
         double acc = 0.0;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-          const double tau = A.mu * (g[d][j] + g[j][d]) - (j == d ? (2.0 / 3.0) * A.mu * div : 0.0);
+          const double tau = mue * (g[d][j] + g[j][d]) - (j == d ? (2.0 / 3.0) * mue * div : 0.0);
           acc = fma(tau, Fvb[d][3], acc);
         }
         pb[1 + j] += acc;
       }
       double gb[3][4];
       const double uu[3] = {me[1], me[2], me[3]};
-      gradient_cotangent(Fvb, uu, A.mu, A.kappa, gb);
+      if (LES) les_gradient_cotangent(Fvb, uu, g, me[0], A.mu, A.kappa, csd2, A.ktf, gb, pb[0]);
+      else gradient_cotangent(Fvb, uu, A.mu, A.kappa, gb);
 #pragma unroll
       for (int d = 0; d < 3; ++d)
 #pragma unroll
@@ -4217,7 +4272,8 @@ hipError_t launch_lift_curved(const StageArgs& A0, int eq, hipStream_t s) {
 template <int VF>
 hipError_t launch_vjp_curved_vf(const VjpArgs& A, int eq, hipStream_t s) {
   const dim3 grid(8 * A.chunk), block(NT);
-  if (eq == 1) hipLaunchKernelGGL((k_vjp_curved<VF, 1>), grid, block, 0, s, A);
+  if (eq == 2) hipLaunchKernelGGL((k_vjp_curved<VF, 2>), grid, block, 0, s, A);
+  else if (eq == 1) hipLaunchKernelGGL((k_vjp_curved<VF, 1>), grid, block, 0, s, A);
   else hipLaunchKernelGGL((k_vjp_curved<VF, 0>), grid, block, 0, s, A);
   return hipGetLastError();
 }
@@ -4232,7 +4288,8 @@ hipError_t launch_vjp_curved(const VjpArgs& A, int eq, hipStream_t s) {
 }
 
 hipError_t launch_vjp_lift_curved(const VjpArgs& A, hipStream_t s) {
-  hipLaunchKernelGGL(k_vjp_lift_curved, dim3(8 * A.chunk), dim3(NT), 0, s, A);
+  if (A.les) hipLaunchKernelGGL((k_vjp_lift_curved<true>), dim3(8 * A.chunk), dim3(NT), 0, s, A);
+  else hipLaunchKernelGGL((k_vjp_lift_curved<false>), dim3(8 * A.chunk), dim3(NT), 0, s, A);
   return hipGetLastError();
 }
 

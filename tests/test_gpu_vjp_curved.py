@@ -2,7 +2,8 @@
 and dg_set_connectivity) against the oracle's forward-mode dual numbers of the
 curved operator: <w, J v> (oracle) = <J^T w, v> (GPU) to 1e-12 of the product
 scale on warped periodic meshes and rotated-element meshes, a full Jacobian on
-a one-element warped mesh, and the one-step Runge-Kutta product."""
+a one-element warped mesh, and the one-step Runge-Kutta product; the same
+with the Smagorinsky eddy viscosity (constant and per-element C_s)."""
 import numpy as np
 import pytest
 
@@ -21,18 +22,21 @@ def torch_cuda():
     return torch
 
 
-def make(orc, torch, N, ne, eq, vf, sf, mu=2e-2, rotate_seed=None, amp=0.05):
+def make(orc, torch, N, ne, eq, vf, sf, mu=2e-2, rotate_seed=None, amp=0.05, Cs=0.0, cs_elem=None):
     from paper_2306_12891_amd import dg
     xn = I.warped_coordinates(N, ne, amp=amp)
     conn = perm = None
     if rotate_seed is not None:
         perm, conn = I.rotated_elements(N, ne, seed=rotate_seed)
         xn = I.relabel(xn, perm)
-    s = orc.Setup(N=N, nelem=ne, equations=eq, vol_flux=vf, surf_flux=sf, mu=mu, xnodes=xn, conn=conn)
-    op = dg.DG(ne, N, gamma=G, mu=mu, equations=eq, vol_flux=vf, surf_flux=sf)
+    s = orc.Setup(N=N, nelem=ne, equations=eq, vol_flux=vf, surf_flux=sf, mu=mu, xnodes=xn, conn=conn, Cs=Cs,
+                  cs_elem=cs_elem)
+    op = dg.DG(ne, N, gamma=G, mu=mu, equations=eq, vol_flux=vf, surf_flux=sf, Cs=Cs)
     if conn is not None:
         op.set_connectivity(conn)
     op.set_geometry(torch.from_numpy(xn).cuda())
+    if cs_elem is not None:
+        op.set_cs_field(torch.from_numpy(cs_elem).cuda())
     return s, op, xn
 
 
@@ -97,6 +101,69 @@ def test_rk_step_vjp_dot_product(orc, torch_cuda, rotate_seed):
     U = I.random_smooth(N, ne, seed=41, noise=0.01, xnodes=xn)
     v = I.random_directions(U.shape, 4)
     w = I.random_directions(U.shape, 5)
+    dt = 0.5 * orc.max_dt(s, U, 0.5)
+    _, Jv = orc.rk_jvp(s, U, v, dt, 1)
+    JTw = op.rk_step_vjp(torch.from_numpy(U).cuda(), dt, torch.from_numpy(w).cuda()).cpu().numpy()
+    dot_check(np.sum(w * Jv), np.sum(JTw * v), np.sum(np.abs(w * Jv)))
+
+
+# ---------------------------------------------------------------------------
+# Smagorinsky eddy viscosity (filter width from the element volume)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("vf,sf,field", [(1, 1, False), (0, 0, True), (3, 2, False)])
+@pytest.mark.parametrize("N", [2, 3, 5])
+def test_les_vjp_dot_product(orc, torch_cuda, vf, sf, field, N):
+    ne = (3, 2, 2)
+    cs = np.random.default_rng(700 + N).uniform(0.1, 0.4, 12) if field else None
+    s, op, xn = make(orc, torch_cuda, N, ne, 1, vf, sf, mu=2e-3, Cs=0.0 if field else 0.3, cs_elem=cs)
+    U = I.random_smooth(N, ne, seed=710 + N, noise=0.02, xnodes=xn)
+    v = I.random_directions(U.shape, 6)
+    w = I.random_directions(U.shape, 7)
+    _, Jv = orc.jvp(s, U, v)
+    JTw = op.vjp(torch_cuda.from_numpy(U).cuda(), torch_cuda.from_numpy(w).cuda()).cpu().numpy()
+    dot_check(np.sum(w * Jv), np.sum(JTw * v), np.sum(np.abs(w * Jv)))
+
+
+@pytest.mark.parametrize("N", [2, 4])
+def test_les_vjp_rotated_elements(orc, torch_cuda, N):
+    ne = (3, 2, 2)
+    s, op, xn = make(orc, torch_cuda, N, ne, 1, 1, 1, mu=2e-3, rotate_seed=N + 11, Cs=0.25)
+    U = I.random_smooth(N, ne, seed=720 + N, noise=0.02, xnodes=xn)
+    v = I.random_directions(U.shape, 8)
+    w = I.random_directions(U.shape, 9)
+    _, Jv = orc.jvp(s, U, v)
+    JTw = op.vjp(torch_cuda.from_numpy(U).cuda(), torch_cuda.from_numpy(w).cuda()).cpu().numpy()
+    dot_check(np.sum(w * Jv), np.sum(JTw * v), np.sum(np.abs(w * Jv)))
+
+
+def test_les_full_jacobian_one_element(orc, torch_cuda):
+    import torch
+    N, ne = 2, (1, 1, 1)
+    s, op, xn = make(orc, torch_cuda, N, ne, 1, 1, 1, mu=5e-3, amp=0.04, Cs=0.3)
+    U = I.random_smooth(N, ne, seed=37, noise=0.05, xnodes=xn)
+    n = U.size
+    J = np.zeros((n, n))
+    for k in range(n):
+        e = np.zeros(n)
+        e[k] = 1.0
+        J[:, k] = orc.jvp(s, U, e.reshape(U.shape))[1].ravel()
+    Ud = torch.from_numpy(U).cuda()
+    JT = np.zeros((n, n))
+    for k in range(n):
+        e = torch.zeros(U.shape, dtype=torch.float64, device="cuda")
+        e.view(-1)[k] = 1.0
+        JT[k] = op.vjp(Ud, e).cpu().numpy().ravel()
+    assert np.max(np.abs(JT - J)) <= 1e-12 * np.max(np.abs(J))
+
+
+def test_les_rk_step_vjp_dot_product(orc, torch_cuda):
+    import torch
+    N, ne = 3, (2, 3, 2)
+    cs = np.random.default_rng(730).uniform(0.1, 0.4, 12)
+    s, op, xn = make(orc, torch_cuda, N, ne, 1, 1, 1, mu=2e-3, rotate_seed=5, cs_elem=cs)
+    U = I.random_smooth(N, ne, seed=43, noise=0.01, xnodes=xn)
+    v = I.random_directions(U.shape, 10)
+    w = I.random_directions(U.shape, 11)
     dt = 0.5 * orc.max_dt(s, U, 0.5)
     _, Jv = orc.rk_jvp(s, U, v, dt, 1)
     JTw = op.rk_step_vjp(torch.from_numpy(U).cuda(), dt, torch.from_numpy(w).cuda()).cpu().numpy()
