@@ -13,7 +13,8 @@
  *     (Sec. 2, Sec. 4.1);
  *   - element-wise convex blending with a finite-volume subcell operator,
  *     U_t = a U_t^FV + (1 - a) U_t^DG (Sec. 4.1, blending equation), first
- *     order in the outer subcells (Sec. 4.1);
+ *     order in the outer subcells (Sec. 4.1); with Navier-Stokes only the
+ *     advective operator is blended, the viscous terms enter unweighted;
  *   - blending coefficient from a modal indicator through the sigmoid with
  *     threshold T(N) = 0.5 * 10^(-1.8 (N+1)^0.25) (Sec. 4.1, indicator
  *     equation), spread to face neighbours by 1/2 (Sec. 4.1), and kept in
@@ -85,7 +86,7 @@ typedef struct {
   int32_t equations;    /* DG_EULER | DG_NS                          (EULER)   */
   int32_t vol_flux;     /* two-point volume flux: DG_VF_*            (KG)      */
   int32_t surf_flux;    /* Riemann solver: DG_SF_*                   (LLF)     */
-  int32_t blending;     /* 0 | 1: DG/FV blending (Euler only)        (0)       */
+  int32_t blending;     /* 0 | 1: DG/FV blending of the advective terms (0)    */
   int32_t indicator;    /* DG_IND_HENNEMANN | DG_IND_PERSSON         (HENNEMANN) */
   int32_t fv_recon;     /* DG_FV_FIRST | DG_FV_MINMOD                (MINMOD)  */
   int32_t precision;    /* DG_FP64 | DG_MIXED                        (FP64)    */
@@ -109,7 +110,7 @@ void dg_default_options(dg_options* opt);
 int dg_init(const dg_mesh* mesh, int N, double gamma, double mu, dg_ctx** out);
 
 /* Replaces the options.  Validated here: DG_EUNSUPPORTED for blending with
- * DG_NS, blending with N < 2, DG_MIXED with blending, or the Smagorinsky
+ * N < 2, DG_MIXED with blending, or the Smagorinsky
  * model (Cs > 0) with the DG_VF_CH flux; DG_EINVAL for Cs < 0 or Prt <= 0. */
 int dg_set_options(dg_ctx* ctx, const dg_options* opt);
 int dg_get_options(const dg_ctx* ctx, dg_options* opt);
@@ -230,7 +231,7 @@ int dg_rk_steps(dg_ctx* ctx, double* U, double dt, int nsteps);
 /* Vector-Jacobian product of the operator: U_bar = (dL/dU)^T Ut_bar (the
  * reverse mode of dg_time_derivative, for gradients of functionals of the
  * solution).  Overwrites U_bar, which must not alias U or Ut_bar.  With
- * blending (Euler) the product includes the dependence of the blending
+ * blending the product includes the dependence of the blending
  * coefficient on U (paper Sec. 4.1: indicator sigmoid, clip and neighbour
  * spread) and of the FV subcell reconstruction; at their switches the
  * one-sided rules are: derivative 0 where the coefficient is clipped or cut

@@ -705,8 +705,6 @@ int dg_set_options(dg_ctx* c, const dg_options* o) {
   if (!(o->alpha_min >= 0.0 && o->alpha_min <= o->alpha_max && o->alpha_max <= 1.0) ||
       !(o->alpha_spread >= 0.0 && o->alpha_spread <= 1.0))
     return fail(c, DG_EINVAL, "dg_set_options: need 0 <= alpha_min <= alpha_max <= 1, 0 <= spread <= 1");
-  if (o->blending && o->equations == DG_NS)
-    return fail(c, DG_EUNSUPPORTED, "dg_set_options: blending is implemented for the Euler equations only");
   if (o->blending && c->N < 2) return fail(c, DG_EUNSUPPORTED, "dg_set_options: blending needs N >= 2");
   if (o->precision == DG_MIXED && !c->kt->stage_mixed)
     return fail(c, DG_EUNSUPPORTED, "dg_set_options: mixed precision not built for this degree");

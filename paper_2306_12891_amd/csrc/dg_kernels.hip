@@ -904,6 +904,25 @@ __device__ __forceinline__ void face_item(const StageArgs& A, const FaceData<NS,
 #else
 #define DG_STAGE_BOUNDS __launch_bounds__(PS::NTB)
 #endif
+// Viscous fluxes at a node from its lifted gradient g (with the Smagorinsky
+// eddy viscosity when LES).
+template <bool LES, class R>
+__device__ __forceinline__ void node_viscous_flux(const StageArgs& A, int e, const R g[3][4], const R* me,
+                                                  R Fv[3][4]) {
+  R mu = (R)A.mu, kap = (R)A.kappa;
+  if (LES) {
+    const double cs = A.cs_elem ? A.cs_elem[e] : A.cs;
+    const R mut = eddy_viscosity<R>(g, me[0], (R)(cs * cs * A.delta2));
+    mu += mut;
+    kap = fmaR((R)A.ktf, mut, kap);
+  }
+  viscous_flux<0, R>(g, me[1], me[2], me[3], mu, kap, Fv[0]);
+  viscous_flux<1, R>(g, me[1], me[2], me[3], mu, kap, Fv[1]);
+  viscous_flux<2, R>(g, me[1], me[2], me[3], mu, kap, Fv[2]);
+}
+
+// With BLEND (FP64) only the advective operator is blended: the viscous terms
+// enter unweighted, and MODE_DIFF leaves them out.
 template <int VF, int EQ, bool BLEND, class R, bool WALL = false>
 __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
   constexpr bool NS = (EQ >= 1);
@@ -990,7 +1009,7 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
   R acc[5] = {0, 0, 0, 0, 0};
   R Fv[3][4];
   if (t < nn) {
-    constexpr bool FG = NS && DG_FUSED_GRAD;
+    constexpr bool FG = NS && DG_FUSED_GRAD && !BLEND;
     R gs[3][4];
     volume_dir<VF, 0, R, FG>(sP, sDhat, t, ijk[0], me, invJ[0], (R)gm1, acc, sDw, gs[0]);
     volume_dir<VF, 1, R, FG>(sP, sDhat, t, ijk[1], me, invJ[1], (R)gm1, acc, sDw, gs[1]);
@@ -1007,7 +1026,7 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
         for (int v = 0; v < 5; ++v) acc[v] = fmaR(c, sF[f][v][a], acc[v]);
       }
     }
-    if (NS) {
+    if (NS && !BLEND) {  // blended: after the subcell pass (registers)
       R g[3][4];
       if (!FG) {
         lifted_gradient<R, nnp>(sP, sQ, sDw, swinv, t, ijk, invJ, g);
@@ -1030,16 +1049,7 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
         for (int c = 0; c < 4; ++c) g[d][c] = invJ[d] * s[c];
       }
       }
-      R mu = (R)A.mu, kap = (R)A.kappa;
-      if (LES) {
-        const double cs = A.cs_elem ? A.cs_elem[e] : A.cs;
-        const R mut = eddy_viscosity<R>(g, me[0], (R)(cs * cs * A.delta2));
-        mu += mut;
-        kap = fmaR((R)A.ktf, mut, kap);
-      }
-      viscous_flux<0, R>(g, me[1], me[2], me[3], mu, kap, Fv[0]);
-      viscous_flux<1, R>(g, me[1], me[2], me[3], mu, kap, Fv[1]);
-      viscous_flux<2, R>(g, me[1], me[2], me[3], mu, kap, Fv[2]);
+      node_viscous_flux<LES, R>(A, e, g, me, Fv);
     }
   }
 
@@ -1116,6 +1126,11 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
 #pragma unroll
       for (int v = 0; v < 5; ++v) acc[v] = (R)0;
     }
+    if (NS && t < nn) {  // sP and sQ are intact: the subcell pass writes sX only
+      R g[3][4];
+      lifted_gradient<R, nnp>(sP, sQ, sDw, swinv, t, ijk, invJ, g);
+      node_viscous_flux<LES, R>(A, e, g, me, Fv);
+    }
   }
 
   // Runge-Kutta register (stages 2-5), loaded ahead of the viscous phase so
@@ -1125,7 +1140,7 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
 #pragma unroll
     for (int v = 0; v < 5; ++v) gprev[v] = A.G[(size_t)e * 5 * nn + t + v * nn];
   }
-  if (NS) {
+  if (NS && !(BLEND && A.mode == MODE_DIFF)) {  // uniform over the workgroup
     // viscous divergence: all twelve flux components exchanged through LDS once
     __syncthreads();
     if (t < nn) {
@@ -2163,7 +2178,7 @@ __global__ __launch_bounds__(NT, WALL || N > 6 ? 1 : 3) void k_vjp(VjpArgs A) {
     volume_vjp_dir<VF, 0>(sP, sLam, sDhat, t, ijk[0], me, lam, A.invJ[0], pb);
     volume_vjp_dir<VF, 1>(sP, sLam, sDhat, t, ijk[1], me, lam, A.invJ[1], pb);
     volume_vjp_dir<VF, 2>(sP, sLam, sDhat, t, ijk[2], me, lam, A.invJ[2], pb);
-    if (!NS && A.alpha) {  // blended: the DG volume term enters with weight 1 - alpha
+    if (A.alpha) {  // blended: the DG advective volume term enters with weight 1 - alpha
       const double wv = 1.0 - A.alpha[e];
 #pragma unroll
       for (int i = 0; i < 6; ++i) pb[i] *= wv;
@@ -4108,7 +4123,18 @@ hipError_t launch_stage_vf(const StageArgs& A0, int eq, hipStream_t s) {
       return hipErrorInvalidValue;
     }
   }
-  if (eq == 2) {
+  if (A.blend && eq >= 1) {  // FP64 (checked on the host)
+    if constexpr (sizeof(R) == 8) {
+      if (eq == 2) {
+        if constexpr (VF != VF_CH) hipLaunchKernelGGL((k_stage<VF, 2, true, double>), grid, block, 0, s, A);
+        else return hipErrorInvalidValue;
+      } else {
+        hipLaunchKernelGGL((k_stage<VF, 1, true, double>), grid, block, 0, s, A);
+      }
+    } else {
+      return hipErrorInvalidValue;
+    }
+  } else if (eq == 2) {
     if constexpr (VF != VF_CH) hipLaunchKernelGGL((k_stage<VF, 2, false, R>), grid, block, 0, s, A);
     else return hipErrorInvalidValue;
   } else if (eq == 1) {

@@ -246,7 +246,7 @@ def test_error_paths(orc, torch_cuda):
     assert op.raw_call("rk_step", P(U.data_ptr()), ctypes.c_double(float("nan"))) == dg.DG_EINVAL
     assert op.raw_call("rk_step", P(None), ctypes.c_double(1e-3)) == dg.DG_EINVAL
     with pytest.raises(dg.DGError) as ei:
-        op.set_options(equations=1, blending=1)
+        op.set_options(precision=dg.MIXED, vol_flux=dg.PI, blending=1)
     assert ei.value.code == dg.DG_EUNSUPPORTED
     assert op.check_finite(U)
     V = U.clone()

@@ -334,3 +334,80 @@ def test_jvp_through_blending_matches_central_differences(orc):
         fixed = (orc.time_derivative(s, U + eps * v, alpha=al) - orc.time_derivative(s, U - eps * v, alpha=al)) / (
             2 * eps)
         assert np.max(np.abs(fixed - Jv)) > 1e-2 * scale
+
+
+# ---------------------------------------------------------------------------
+# Navier-Stokes with blending.  Reading: only the advective operator is
+# blended (the FV subcell scheme carries no viscous terms); the BR1 viscous
+# terms enter with weight one in every element.
+# ---------------------------------------------------------------------------
+def _ns(orc, N, nelem, blending, eq=1, mu=2e-2, **kw):
+    return orc.Setup(N=N, nelem=nelem, equations=eq, mu=mu, blending=blending, fv_recon=orc.FV_MINMOD,
+                     vol_flux=orc.KG, surf_flux=orc.LLF, **kw)
+
+
+def test_ns_blending_leaves_viscous_terms_unweighted(orc):
+    """For any fixed alpha field, NS-blended minus Euler-blended equals the
+    unblended NS minus Euler operator: the viscous terms do not depend on
+    alpha."""
+    N, nelem = 3, (3, 2, 2)
+    U = I.random_smooth(N, nelem, seed=21, noise=0.03)
+    visc = orc.time_derivative(_ns(orc, N, nelem, 0), U) - orc.time_derivative(_ns(orc, N, nelem, 0, eq=0), U)
+    assert np.max(np.abs(visc)) > 1e-3 * np.max(np.abs(orc.time_derivative(_ns(orc, N, nelem, 0), U)))
+    rng = np.random.default_rng(3)
+    for alpha in (np.zeros(12), np.ones(12), rng.uniform(0, 1, 12)):
+        d = orc.time_derivative(_ns(orc, N, nelem, 1), U, alpha=alpha) - orc.time_derivative(
+            _ns(orc, N, nelem, 1, eq=0), U, alpha=alpha)
+        assert np.max(np.abs(d - visc)) <= 1e-13 * np.max(np.abs(visc)) * 100
+
+
+def test_ns_alpha_zero_is_unblended_bitwise(orc):
+    N, nelem = 4, (2, 2, 1)
+    U = I.random_smooth(N, nelem, seed=22, noise=0.02)
+    Ut = orc.time_derivative(_ns(orc, N, nelem, 1), U, alpha=np.zeros(4))
+    assert np.array_equal(Ut, orc.time_derivative(_ns(orc, N, nelem, 0), U))
+
+
+@pytest.mark.parametrize("N", [2, 4])
+def test_ns_alpha_one_is_plain_fv_plus_viscous(orc, N):
+    """alpha = 1 with first-order subcells: the independent numpy FV scheme
+    plus the unblended viscous terms."""
+    nelem, lo, hi = (3, 2, 2), (0.0, 0.0, 0.0), (1.0, 0.5, 0.7)
+    U = I.random_smooth(N, nelem, lo, hi, seed=23, noise=0.02)
+    mk = lambda eq, b: orc.Setup(N=N, nelem=nelem, lo=lo, hi=hi, equations=eq, mu=1e-2, vol_flux=3, surf_flux=0,
+                                 blending=b, fv_recon=0)
+    visc = orc.time_derivative(mk(1, 0), U) - orc.time_derivative(mk(0, 0), U)
+    Ut = orc.time_derivative(mk(1, 1), U, alpha=np.ones(12))
+    ref = fv_first_order_numpy(U, N, nelem, lo, hi) + visc
+    assert np.max(np.abs(Ut - ref)) <= 1e-11 * np.max(np.abs(ref))
+
+
+def test_ns_blended_freestream_and_conservation(orc):
+    N, nelem = 4, (3, 2, 2)
+    rng = np.random.default_rng(4)
+    alpha = rng.uniform(0, 1, 12)
+    s = _ns(orc, N, nelem, 1)
+    Uf = I.freestream(N, nelem, u=(0.4, -0.3, 0.2))
+    assert np.max(np.abs(orc.time_derivative(s, Uf, alpha=alpha))) <= 1e-13 * 10 * N * N
+    U = I.random_smooth(N, nelem, seed=24, noise=0.05)
+    Ut = orc.time_derivative(s, U, alpha=alpha)
+    I_ = orc.integrals(s, Ut)
+    scale = orc.integrals(s, np.abs(Ut))
+    assert np.all(np.abs(I_) < 1e-13 * scale)
+
+
+@pytest.mark.parametrize("eq", [1, 2])
+def test_ns_jvp_through_blending_matches_central_differences(orc, eq):
+    """Indicator-driven alpha with Navier-Stokes (eq 2: with the Smagorinsky
+    model): dual numbers against central differences to 1e-7 of max |J v|."""
+    N, nelem = 3, (3, 3, 2)
+    s = _ns(orc, N, nelem, 1, eq=1, mu=5e-3, Cs=0.2 if eq == 2 else 0.0)
+    U = blended_noisy_state(N, nelem)
+    _, _, al = orc.alpha(s, U)
+    assert np.sum((al > 0.02) & (al < 0.69)) >= 6
+    eps = 1e-6
+    for k in range(2):  # directions whose +-eps segment crosses no minmod switch
+        v = I.random_directions(U.shape, k)
+        _, Jv = orc.jvp(s, U, v)
+        fd = (orc.time_derivative(s, U + eps * v) - orc.time_derivative(s, U - eps * v)) / (2 * eps)
+        assert np.max(np.abs(fd - Jv)) <= 1e-7 * np.max(np.abs(Jv))
