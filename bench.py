@@ -42,6 +42,9 @@ WORKLOADS = {
                             "NS freestream Ma0.5, N=7, 64^3 elems, PI+Roe, BR1, LSERK4"),
     "sod_n5_64x8x8": (5, (64, 8, 8), 0, 0, 0, 0.0, 1,
                       "Euler Sod tube, N=5, 64x8x8 elems, KG+LLF, DG/FV blending (minmod), LSERK4"),
+    "sod_ns_n4_256x16x16": (4, (256, 16, 16), 1, 0, 0, 2e-6, 1,
+                            "High-Reynolds viscous Sod tube (Navier-Stokes, mu 2e-6, Pr 0.72), N=4, 256x16x16 elems, "
+                            "KG+LLF, DG/FV blending of the advective terms (minmod), BR1, LSERK4"),
     "tgv_les_n5_32": (5, (32, 32, 32), 1, 1, 1, 1.0 / 1600, 0,
                       "TGV Ma0.1 Re1600 LES (Smagorinsky C_s=0.17, Pr_t=0.9), N=5, 32^3 elems, PI+Roe, BR1, "
                       "LSERK4"),
@@ -107,12 +110,13 @@ def domain(name):
 # calibration (FETCH x 2.000, WRITE x 1.000); see profiles/k_stage_*.md.  Valid
 # only for the kernel source they were taken on (sha256 prefix).
 MEASURED_TRAFFIC = {
-    "kernel_sha": "346d05c94fb92b05",
+    "kernel_sha": "937e3176427bee48",
     "tgv_n5_32": {"bytes_per_launch": 1380.3e6, "fetch": 870.7e6, "write": 509.6e6},
-    "tgv_n7_64": {"bytes_per_launch": 26683.3e6, "fetch": 17019.6e6, "write": 9663.7e6},
-    "freestream_euler_n7_64": {"bytes_per_launch": 22921.5e6, "fetch": 13257.8e6, "write": 9663.7e6},
-    "tgv_curved_n5_32": {"bytes_per_launch": 2029.5e6, "fetch": 1519.9e6, "write": 509.6e6},
+    "tgv_n7_64": {"bytes_per_launch": 26682.9e6, "fetch": 17019.2e6, "write": 9663.7e6},
+    "freestream_euler_n7_64": {"bytes_per_launch": 22926.9e6, "fetch": 13263.2e6, "write": 9663.7e6},
+    "tgv_curved_n5_32": {"bytes_per_launch": 2029.4e6, "fetch": 1519.8e6, "write": 509.6e6},
     "channel_wm_n5_32": {"bytes_per_launch": 1372.5e6, "fetch": 862.9e6, "write": 509.6e6},
+    "sod_ns_n4_256x16x16": {"bytes_per_launch": 2266.7e6, "fetch": 1676.6e6, "write": 590.0e6},
 }
 
 
