@@ -8,6 +8,12 @@ benchmark times.
   subcells, 500 steps: the data stay constant in y and z, so each x-line of
   the 3-D run equals the quasi-1-D tube (64 x 1 x 1 elements of the same cell
   size and time step), which the oracle integrates in seconds.
+* Wall-modelled channel LES and the TGV LES, N = 5, 32^3 elements: sampled
+  elements against the oracle.
+* TGV on the warped 32^3 mesh of N = 5 (curved elements): the whole mesh
+  against the oracle.
+* High-Reynolds viscous Sod tube, N = 4, 256 x 16 x 16 elements, blended
+  Navier-Stokes, 100 steps: each x-line against the quasi-1-D oracle run.
 """
 import math
 
@@ -140,3 +146,90 @@ def test_channel_wm_n5_32_sampled(orc, torch_cuda):
         scale = max(S[v], np.max(np.abs(ref[:, v])))
         err = np.max(np.abs(got[:, v] - ref[:, v]))
         assert err <= 1e-12 * scale, (v, err, scale)
+
+
+def test_tgv_les_n5_32_sampled(orc, torch_cuda):
+    """TGV LES (Smagorinsky C_s = 0.17) at the benchmark's size: one FP64
+    evaluation against the oracle on corner and seeded random elements."""
+    import torch
+
+    from paper_2306_12891_amd import dg
+    N, n = 5, 32
+    mu, Cs = 1.0 / 1600, 0.17
+    U = I.tgv(N, (n, n, n))
+    rng = np.random.default_rng(11)
+    corners = [0, n - 1, n * (n - 1), n * n - 1, n * n * (n - 1), n ** 3 - 1]
+    sel = np.unique(np.concatenate([corners, rng.integers(0, n ** 3, 48)])).astype(np.int32)
+    s = orc.Setup(N=N, nelem=(n, n, n), equations=1, vol_flux=1, surf_flux=1, mu=mu, Cs=Cs)
+    ref = orc.time_derivative_elems(s, U, sel)
+    op = dg.DG((n, n, n), N, gamma=G, mu=mu, equations=dg.NS, vol_flux=dg.PI, surf_flux=dg.ROE, Cs=Cs)
+    Ud = torch.from_numpy(U).cuda()
+    got = op.time_derivative(Ud)[torch.from_numpy(sel).long().cuda()].cpu().numpy()
+    del Ud
+    op.close()
+    S = term_scale(U[sel], N, [2.0 / (TWO_PI / n)] * 3)
+    for v in range(5):
+        scale = max(S[v], np.max(np.abs(ref[:, v])))
+        err = np.max(np.abs(got[:, v] - ref[:, v]))
+        assert err <= 1e-12 * scale, (v, err, scale)
+
+
+def test_tgv_curved_n5_32_whole_mesh(orc, torch_cuda):
+    """The curved benchmark configuration (warped periodic 32^3 mesh of N = 5,
+    displacement amplitude 0.04 of the box, PI + Roe, BR1): one evaluation of
+    the whole mesh against the oracle, to 1e-12 of the term scale."""
+    import torch
+
+    from paper_2306_12891_amd import dg
+    N, n = 5, 32
+    mu = 1.0 / 1600
+    xn = I.warped_coordinates(N, (n, n, n), amp=0.04)
+    U = I.tgv(N, (n, n, n), xnodes=xn)
+    s = orc.Setup(N=N, nelem=(n, n, n), equations=1, vol_flux=1, surf_flux=1, mu=mu, xnodes=xn)
+    ref = orc.time_derivative(s, U)
+    op = dg.DG((n, n, n), N, gamma=G, mu=mu, equations=dg.NS, vol_flux=dg.PI, surf_flux=dg.ROE)
+    op.set_geometry(torch.from_numpy(xn).cuda())
+    got = op.time_derivative(torch.from_numpy(U).cuda()).cpu().numpy()
+    op.close()
+    Ja, J = orc.metrics(s)
+    h = max(np.max(np.sqrt(np.sum(Ja[:, i] ** 2, axis=1)) / J) for i in range(3))
+    S = term_scale(U, N, [h, h, h])
+    for v in range(5):
+        scale = max(S[v], np.max(np.abs(ref[:, v])))
+        err = np.max(np.abs(got[:, v] - ref[:, v]))
+        assert err <= 1e-12 * scale, (v, err, scale)
+
+
+def test_sod_ns_n4_256x16x16_100_steps(orc, torch_cuda):
+    """Blended Navier-Stokes at the benchmark's size (N = 4, 256 x 16 x 16,
+    mu 2e-6, KG + LLF, minmod subcells): 100 steps; the data stay constant in
+    y and z, so each x-line equals the quasi-1-D oracle run of the same cell
+    size and time step; blended elements present at the end."""
+    import torch
+
+    from paper_2306_12891_amd import dg
+    N, steps, mu = 4, 100, 2e-6
+    nelem, lo, hi = (256, 16, 16), (0.0, 0.0, 0.0), (1.0, 0.125, 0.125)
+    op = dg.DG(nelem, N, gamma=G, mu=mu, lo=lo, hi=hi, equations=dg.NS, vol_flux=dg.KG, surf_flux=dg.LLF,
+               blending=1, fv_recon=dg.FV_MINMOD)
+    U0 = I.sod(N, nelem, lo, hi)
+    Ud = torch.from_numpy(U0).cuda()
+    dt = op.max_dt(Ud, 0.5)
+    op.rk_steps(Ud, dt, steps)
+    assert op.check_finite(Ud)
+    assert float((op.alpha(Ud) > 0).double().mean().item()) > 0.01
+    got = Ud.cpu().numpy()
+    op.close()
+    h1 = (1.0, 0.125 / 16, 0.125 / 16)
+    s1 = orc.Setup(N=N, nelem=(256, 1, 1), lo=lo, hi=h1, equations=1, mu=mu, vol_flux=0, surf_flux=0, blending=1,
+                   fv_recon=1)
+    U1 = I.sod(N, (256, 1, 1), lo, h1)
+    assert abs(orc.max_dt(s1, U1, 0.5) - dt) <= 1e-15 * dt
+    ref = orc.rk_steps(s1, U1, dt, steps)
+    g3 = got.reshape(16, 16, 256, 5, N + 1, N + 1, N + 1)
+    for ez in (0, 9, 15):
+        for ey in (0, 6):
+            line = g3[ez, ey]
+            for v in (0, 1, 4):
+                err = np.max(np.abs(line[:, v] - ref[:, v]))
+                assert err <= 1e-8 * np.max(np.abs(ref[:, 0])), (ez, ey, v, err)
