@@ -1274,7 +1274,8 @@ static void spread_alpha(const Ctx& c, const std::vector<T>& a1, std::vector<T>&
   alpha.assign(c.nelem, T(0.0));
   for (int e = 0; e < c.nelem; ++e) {
     T m = T(0.0);
-    for (int f = 0; f < 6; ++f) m = max_(m, a1[c.nbr[6 * e + f]]);
+    for (int f = 0; f < 6; ++f)  // reading: a wall face (no neighbour) spreads nothing
+      if (c.nbr[6 * e + f] >= 0) m = max_(m, a1[c.nbr[6 * e + f]]);
     T a = max_(a1[e], c.s.alpha_spread * m);
     if (value(a) < c.s.alpha_min) a = T(0.0);
     alpha[e] = a;
@@ -1334,8 +1335,10 @@ static void fv_subcell(const Ctx& c, const T* U, const std::vector<T>& fstar, T*
         // interface fluxes Fh[m] = F_{m-1/2}, m = 0..N+1
         std::vector<T> Fh((n1 + 1) * 5);
         const int em = c.nbr[6 * e + 2 * d];
+        T fw[5];
+        if (em < 0) wall_inviscid_flux(c, U, e, d, a, false, fw);  // the same face flux as the DG part
         for (int v = 0; v < 5; ++v) {
-          Fh[0 * 5 + v] = fstar[((size_t(em) * 3 + d) * 5 + v) * c.nf + a];
+          Fh[0 * 5 + v] = em < 0 ? fw[v] : fstar[((size_t(em) * 3 + d) * 5 + v) * c.nf + a];
           Fh[n1 * 5 + v] = fstar[((size_t(e) * 3 + d) * 5 + v) * c.nf + a];
         }
         for (int m = 0; m < N; ++m) {
@@ -1779,8 +1782,9 @@ static bool valid(const Setup* s) {
   // viscosity) without blending
   if (s->xnodes && s->blending) return false;
   if (s->conn && !s->xnodes) return false;
-  // walls: Navier-Stokes on the box, no blending (the spread needs neighbours)
-  if (s->wall_dir >= 0 && (s->wall_dir > 2 || s->equations != EQ_NS || s->blending || s->xnodes)) return false;
+  // walls: Navier-Stokes on the box (also with blending: a wall face spreads
+  // no coefficient, and its FV face flux is the wall flux of the DG part)
+  if (s->wall_dir >= 0 && (s->wall_dir > 2 || s->equations != EQ_NS || s->xnodes)) return false;
   if (s->wall_dir >= 0 && s->wm_mainf > 0.0 && !(s->wm_uinf > 0.0)) return false;
   if (s->conn) {  // every face pair must point back at itself with the inverse orientation
     const int ne = s->nx * s->ny * s->nz, n1 = s->N + 1;
@@ -1888,7 +1892,7 @@ int or_dense_time_derivative(const Setup* s, const double* U, double* Ut) {
 
 // Indicator E, clipped a1 (before spread) and final alpha, per element.
 int or_alpha(const Setup* s, const double* U, double* E, double* a1, double* alpha) {
-  if (!valid(s) || s->N < 2 || s->wall_dir >= 0) return -1;
+  if (!valid(s) || s->N < 2) return -1;
   const Ctx c = make_ctx(*s);
   std::vector<double> Ev, a1v, al;
   indicator_pass(c, U, Ev, a1v);

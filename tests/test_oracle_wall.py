@@ -255,8 +255,6 @@ def test_unsupported_wall_setups_are_rejected(orc):
     with pytest.raises(ValueError):
         orc.time_derivative(wall_setup(orc, N, nelem, equations=orc.EULER), U)
     with pytest.raises(ValueError):
-        orc.time_derivative(wall_setup(orc, N, nelem, blending=1), U)
-    with pytest.raises(ValueError):
         orc.time_derivative(wall_setup(orc, N, nelem, wall_dir=3), U)
     with pytest.raises(ValueError):
         orc.time_derivative(wall_setup(orc, N, nelem, xnodes=I.warped_coordinates(N, nelem)), U)
@@ -283,3 +281,97 @@ def test_channel_state_is_a_wall_flow(orc):
     assert np.max(np.abs(V[:, 0, :, 1:4, :, 0, :])) < 1e-14
     assert np.max(np.abs(V[:, -1, :, 1:4, :, N, :])) < 1e-14
     assert abs(np.max(U[:, 1]) - 1.0) < 0.15
+
+
+# ---------------------------------------------------------------------------
+# Walls with the DG/FV blending.  Readings: a wall face spreads no blending
+# coefficient; the FV subcells of a wall element take the wall's advective
+# flux (mirror state) at that face, the same flux as the DG part, so the
+# surface terms stay unblended there too.
+# ---------------------------------------------------------------------------
+def blended_wall_state(N, nelem):
+    base = I.random_smooth(N, nelem, seed=41, amp=0.1)
+    ne = int(np.prod(nelem))
+    fac = np.random.default_rng(6).uniform(0.2, 1.0, ne)[:, None, None, None, None]
+    return base * (1 + np.random.default_rng(98).standard_normal(base.shape) * 0.05 * fac)
+
+
+def test_blending_with_walls_alpha_zero_is_unblended_bitwise(orc):
+    N, nelem = 3, (2, 3, 2)
+    U = I.random_smooth(N, nelem, seed=43, noise=0.02)
+    a = orc.time_derivative(wall_setup(orc, N, nelem, mu=2e-3, surf_flux=1, blending=1, fv_recon=1), U,
+                            alpha=np.zeros(12))
+    b = orc.time_derivative(wall_setup(orc, N, nelem, mu=2e-3, surf_flux=1), U)
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("sf,vf,Cs", [(0, 0, 0.0), (1, 1, 0.2)])
+def test_blending_with_walls_conservation_and_wall_shear(orc, sf, vf, Cs):
+    """With any alpha field: no mass or energy through the walls, and the
+    tangential momentum changes by the wall shear alone (the FV subcell
+    scheme is conservative and shares the element-face fluxes)."""
+    N, nelem = 3, (2, 3, 2)
+    s = wall_setup(orc, N, nelem, mu=2e-3, surf_flux=sf, vol_flux=vf, Cs=Cs, wm_uinf=0.8, wm_mainf=0.5,
+                   blending=1, fv_recon=1)
+    U = I.random_smooth(N, nelem, seed=17, noise=0.02)
+    Ut = orc.time_derivative(s, U, alpha=np.random.default_rng(8).uniform(0.0, 1.0, 12))
+    tot = integrate(N, nelem, Ut)
+    scale = integrate(N, nelem, np.abs(Ut))
+    assert abs(tot[0]) <= 1e-12 * scale[0]
+    assert abs(tot[4]) <= 1e-12 * scale[4]
+    shear = wall_shear_integral(orc, s, N, nelem, U)
+    for v in (1, 3):
+        assert abs(tot[v] - shear[v]) <= 1e-12 * scale[v], (v, tot[v], shear[v])
+
+
+def test_blending_with_walls_mid_plane_reflection(orc):
+    """Indicator-driven blending with walls keeps the mirror symmetry of the
+    channel (the modal energies of reflected data are equal)."""
+    N, nelem = 3, (2, 3, 2)
+    s = wall_setup(orc, N, nelem, mu=3e-3, surf_flux=1, vol_flux=1, blending=1, fv_recon=1)
+    U = blended_wall_state(N, nelem)
+    _, _, al = orc.alpha(s, U)
+    assert np.sum(al > 0) >= 4
+    a = orc.time_derivative(s, U)
+    b = orc.time_derivative(s, reflect_y(U, N, nelem))
+    assert np.max(np.abs(reflect_y(a, N, nelem) - b)) <= 1e-11 * np.max(np.abs(a))
+
+
+def test_blending_spread_stops_at_walls(orc):
+    """A hot element in the bottom wall row spreads to its five existing
+    neighbours only; the same element with periodic y spreads to six."""
+    from numpy.polynomial import legendre as leg
+    N, n = 3, 3
+    ne = n ** 3
+    x = I.lgl_points(N)
+    X = x[None, None, :] * np.ones((N + 1, N + 1, 1))
+    q = np.ones((ne, N + 1, N + 1, N + 1))
+    hot = 1 + n * (0 + n * 1)  # ex = 1, ey = 0 (wall row), ez = 1
+    q[hot] = leg.legval(X, np.eye(N + 1)[N])
+    one = np.ones_like(q)
+    rho = 1.0 + 0.3 * q
+    U = I.from_primitive(rho, 0 * one, 0 * one, 0 * one, one, G)
+    sw = wall_setup(orc, N, (n, n, n), mu=1e-3, blending=1)
+    sp = wall_setup(orc, N, (n, n, n), wall_dir=-1, mu=1e-3, blending=1)
+    _, a1w, alw = orc.alpha(sw, U)
+    _, a1p, alp = orc.alpha(sp, U)
+    assert np.array_equal(a1w, a1p) and a1w[hot] > 0.01 and np.count_nonzero(a1w) == 1
+    assert np.count_nonzero(alw) == 1 + 5 and np.count_nonzero(alp) == 1 + 6
+    below = hot + n * (n - 1)  # the periodic image across the wall (ey = n - 1)
+    assert alw[below] == 0.0 and alp[below] == 0.5 * a1p[hot]
+
+
+@pytest.mark.parametrize("Cs", [0.0, 0.2])
+def test_blending_with_walls_jvp_matches_central_differences(orc, Cs):
+    N, nelem = 3, (2, 3, 2)
+    s = wall_setup(orc, N, nelem, mu=3e-3, surf_flux=0, vol_flux=0, Cs=Cs, wm_uinf=0.9, wm_mainf=0.6,
+                   blending=1, fv_recon=1)
+    U = blended_wall_state(N, nelem)
+    _, _, al = orc.alpha(s, U)
+    assert np.sum((al > 0.02) & (al < 0.69)) >= 3
+    eps = 1e-6
+    for k in range(2):
+        v = I.random_directions(U.shape, k)
+        _, Jv = orc.jvp(s, U, v)
+        fd = (orc.time_derivative(s, U + eps * v) - orc.time_derivative(s, U - eps * v)) / (2 * eps)
+        assert np.max(np.abs(fd - Jv)) <= 1e-7 * np.max(np.abs(Jv))
