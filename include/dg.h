@@ -198,7 +198,9 @@ int dg_set_connectivity(dg_ctx* ctx, const int32_t* conn);
  * The wall shear stress rho u_tau^2 acts against that velocity in the
  * tangential momentum; mass, normal momentum and energy see no flux through
  * the wall (adiabatic wall at rest).  Needs the FP64 Navier-Stokes operator
- * (also with the Smagorinsky model), mu > 0, no blending, the Cartesian box;
+ * (also with the Smagorinsky model and with blending: a wall face spreads no
+ * blending coefficient, and the FV subcells of a wall element take the wall's
+ * advective flux there), mu > 0, the Cartesian box;
  * while walls are set, dg_set_options, dg_set_geometry and dg_set_connectivity
  * calls that would break this return DG_EUNSUPPORTED.  dg_vjp and rk_step_vjp
  * differentiate through the walls (mirror states, and the wall shear through

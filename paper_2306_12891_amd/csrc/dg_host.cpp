@@ -368,7 +368,7 @@ int run_stage(dg_ctx* c, const double* Xin, double* Xout, double* Ut, int mode, 
   const int eq = eq_code(c);
   if (c->conn && !c->M)
     return fail(c, DG_ESTATE, "general connectivity needs curved elements: call dg_set_geometry first");
-  if (c->wall_dir >= 0 && (eq == 0 || c->opt.blending || c->opt.precision != DG_FP64 || c->M))
+  if (c->wall_dir >= 0 && (eq == 0 || c->opt.precision != DG_FP64 || c->M))
     return fail(c, DG_ESTATE, "wall-modelled boundaries need the FP64 Navier-Stokes operator on the box");
   if (c->M) {  // curved mesh (FP64, no blending: checked when set)
     if (eq >= 1) {
@@ -412,7 +412,6 @@ int curved_compatible(dg_ctx* c, const dg_options* o, int cs_field, const char* 
 // (with or without eddy viscosity), no blending, on the Cartesian box.
 int wall_compatible(dg_ctx* c, const dg_options* o, const char* where) {
   if (o->equations != DG_NS) return fail(c, DG_EUNSUPPORTED, "%s: walls need the Navier-Stokes equations", where);
-  if (o->blending) return fail(c, DG_EUNSUPPORTED, "%s: no blending with walls", where);
   if (o->precision != DG_FP64) return fail(c, DG_EUNSUPPORTED, "%s: walls use the FP64 operator", where);
   if (c->M || c->conn) return fail(c, DG_EUNSUPPORTED, "%s: walls are built for the Cartesian box", where);
   return DG_OK;

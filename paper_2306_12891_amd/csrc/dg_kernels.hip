@@ -929,7 +929,7 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
   constexpr bool LES = (EQ == 2);
   constexpr bool MX = sizeof(R) == 4;
   static_assert(!(BLEND && MX), "the blended operator is FP64 only");
-  static_assert(!WALL || (NS && !BLEND && !MX), "walls: FP64 Navier-Stokes without blending");
+  static_assert(!WALL || (NS && !MX), "walls: FP64 Navier-Stokes");
   // LDS pool: primitives sP[7][nnp], face fluxes sF[6][5][nf], and for
   // Navier-Stokes the interface values sQ[6][4][nf] and the neighbours' normal
   // viscous fluxes sFn[6][4][nf].  The twelve viscous-flux components of all
@@ -1059,7 +1059,10 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
     {
       double m = 0.0;
 #pragma unroll
-      for (int f = 0; f < 6; ++f) m = fmax(m, A.alpha1[A.nbr[6 * e + f]]);
+      for (int f = 0; f < 6; ++f) {
+        const int nb = A.nbr[6 * e + f];
+        if (!WALL || nb >= 0) m = fmax(m, A.alpha1[nb]);  // a wall face spreads nothing
+      }
       al = fmax(A.alpha1[e], A.aspread * m);
       if (al < A.amin) al = 0.0;
       if (t == 0 && A.alpha_out) A.alpha_out[e] = al;
@@ -2357,7 +2360,9 @@ __device__ double spread_weight(const VjpArgs& A, int j, int e) {
   double m = 0.0, w[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int f = 0; f < 6; ++f) {
-    const double x = A.alpha1[A.nbr[6 * j + f]];
+    const int nb = A.nbr[6 * j + f];
+    if (nb < 0) continue;  // wall face: not part of the maximum
+    const double x = A.alpha1[nb];
     if (x > m) {
 #pragma unroll
       for (int g = 0; g < 6; ++g) w[g] = g == f ? 1.0 : 0.0;
@@ -2394,7 +2399,7 @@ __global__ __launch_bounds__(NT) void k_vjp_alpha(VjpArgs A) {
                    A.nbr[6 * e + 5]};
     double r = 0.0;
     for (int i = 0; i < 7; ++i) {
-      bool dup = false;
+      bool dup = cand[i] < 0;  // wall face
       for (int k = 0; k < i; ++k) dup = dup || cand[k] == cand[i];
       if (!dup) r += A.abar[cand[i]] * spread_weight(A, cand[i], e);
     }
@@ -2755,7 +2760,10 @@ __global__ void k_spread(StageArgs A) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= A.nelem) return;
   double m = 0.0;
-  for (int f = 0; f < 6; ++f) m = fmax(m, A.alpha1[A.nbr[6 * e + f]]);
+  for (int f = 0; f < 6; ++f) {
+    const int nb = A.nbr[6 * e + f];
+    if (nb >= 0) m = fmax(m, A.alpha1[nb]);  // a wall face spreads nothing
+  }
   double al = fmax(A.alpha1[e], A.aspread * m);
   if (al < A.amin) al = 0.0;
   A.alpha_out[e] = al;
@@ -4111,10 +4119,15 @@ hipError_t launch_stage_vf(const StageArgs& A0, int eq, hipStream_t s) {
   if (A.wall_dir >= 0) {  // walls: FP64 Navier-Stokes (checked on the host)
     if constexpr (sizeof(R) == 8) {
       if (eq == 2) {
-        if constexpr (VF != VF_CH) hipLaunchKernelGGL((k_stage<VF, 2, false, double, true>), grid, block, 0, s, A);
-        else return hipErrorInvalidValue;
+        if constexpr (VF != VF_CH) {
+          if (A.blend) hipLaunchKernelGGL((k_stage<VF, 2, true, double, true>), grid, block, 0, s, A);
+          else hipLaunchKernelGGL((k_stage<VF, 2, false, double, true>), grid, block, 0, s, A);
+        } else {
+          return hipErrorInvalidValue;
+        }
       } else if (eq == 1) {
-        hipLaunchKernelGGL((k_stage<VF, 1, false, double, true>), grid, block, 0, s, A);
+        if (A.blend) hipLaunchKernelGGL((k_stage<VF, 1, true, double, true>), grid, block, 0, s, A);
+        else hipLaunchKernelGGL((k_stage<VF, 1, false, double, true>), grid, block, 0, s, A);
       } else {
         return hipErrorInvalidValue;
       }

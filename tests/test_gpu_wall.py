@@ -4,7 +4,8 @@ oracle through the C ABI: single evaluations to 1e-12 of the term scale for
 all degrees, wall directions, flux pairs, with the Smagorinsky model and in
 the log region of the law, a Runge-Kutta rollout, removal of the walls, the error
 paths, and the reverse mode through the wall model (dot products against the
-oracle's dual numbers, a full Jacobian, rk_step_vjp)."""
+oracle's dual numbers, a full Jacobian, rk_step_vjp); walls together with the
+DG/FV blending, forward and reverse."""
 import numpy as np
 import pytest
 
@@ -215,3 +216,107 @@ def test_rk_step_vjp_dot_product(orc, torch_cuda):
     JTw = op.rk_step_vjp(torch.from_numpy(U).cuda(), dt, torch.from_numpy(w).cuda()).cpu().numpy()
     a, b = np.sum(w * Jv), np.sum(JTw * v)
     assert abs(a - b) <= 1e-12 * np.sum(np.abs(w * Jv)), (a, b)
+
+
+# ---------------------------------------------------------------------------
+# Walls with the DG/FV blending (a wall face spreads no coefficient; the FV
+# subcells take the wall's advective flux there).
+# ---------------------------------------------------------------------------
+def make_blend(orc, N, nelem, vf=0, sf=0, mu=3e-3, Cs=0.0, uinf=0.9, mainf=0.6, lo=(0, 0, 0), hi=(TWO_PI,) * 3):
+    from paper_2306_12891_amd import dg
+    s = orc.Setup(N=N, nelem=nelem, lo=lo, hi=hi, equations=orc.NS, vol_flux=vf, surf_flux=sf, mu=mu, Cs=Cs,
+                  wall_dir=1, wm_uinf=uinf, wm_mainf=mainf, blending=1, fv_recon=1)
+    op = dg.DG(nelem, N, gamma=G, mu=mu, lo=lo, hi=hi, equations=dg.NS, vol_flux=vf, surf_flux=sf, Cs=Cs,
+               blending=1, fv_recon=dg.FV_MINMOD)
+    op.set_wall_model(1, uinf, mainf)
+    return s, op
+
+
+def blended_wall_state(N, nelem):
+    base = I.random_smooth(N, nelem, seed=41, amp=0.1)
+    ne = int(np.prod(nelem))
+    fac = np.random.default_rng(6).uniform(0.2, 1.0, ne)[:, None, None, None, None]
+    return base * (1 + np.random.default_rng(98).standard_normal(base.shape) * 0.05 * fac)
+
+
+@pytest.mark.parametrize("vf,sf,Cs", [(0, 0, 0.0), (1, 1, 0.0), (1, 1, 0.2), (3, 2, 0.2)])
+@pytest.mark.parametrize("N", [3, 5])
+def test_blended_walls_noisy_state(orc, torch_cuda, vf, sf, Cs, N):
+    """Coefficients inside their bounds, also in both wall rows: alpha to
+    rounding amplified by the sigmoid slope, U_t to 1e-12 of the oracle at the
+    GPU's alpha."""
+    nelem = (2, 3, 2)
+    s, op = make_blend(orc, N, nelem, vf, sf, Cs=Cs)
+    U = blended_wall_state(N, nelem)
+    _, _, al_ref = orc.alpha(s, U)
+    assert np.sum(al_ref > 0) >= 4
+    al = op.alpha(torch_cuda.from_numpy(U).cuda()).cpu().numpy()
+    assert np.allclose(al, al_ref, rtol=1e-9, atol=1e-14)
+    ref = orc.time_derivative(s, U, alpha=al)
+    assert_ut_close(gpu_ut(torch_cuda, op, U), ref, U, N, nelem, (0, 0, 0), (TWO_PI,) * 3)
+
+
+@pytest.mark.parametrize("N", [3, 5])
+def test_blended_walls_sod_in_a_channel(orc, torch_cuda, N):
+    """Sod data along x between walls normal to y, after three oracle steps:
+    coefficients (exactly comparable here) first, then U_t, then a rollout."""
+    import torch
+    nelem, lo, hi = (16, 2, 2), (0, 0, 0), (1.0, 0.125, 0.125)
+    s, op = make_blend(orc, N, nelem, 0, 0, mu=1e-4, uinf=1.0, mainf=0.0, lo=lo, hi=hi)
+    U = I.sod(N, nelem, lo, hi)
+    U = orc.rk_steps(s, U, 0.25 * orc.max_dt(s, U, 0.5), 3)
+    _, _, al_ref = orc.alpha(s, U)
+    assert not np.any(np.abs(al_ref - 0.01) < 1e-9) and np.count_nonzero(al_ref) > 0
+    Ud = torch.from_numpy(U).cuda()
+    assert np.max(np.abs(op.alpha(Ud).cpu().numpy() - al_ref)) < 1e-12
+    assert_ut_close(gpu_ut(torch_cuda, op, U), orc.time_derivative(s, U), U, N, nelem, lo, hi)
+    dt = op.max_dt(Ud, 0.5)
+    op.rk_steps(Ud, dt, 8)
+    assert_state_close(Ud.cpu().numpy(), orc.rk_steps(s, U, dt, 8))
+
+
+def test_blended_walls_spread_stops_at_the_wall(orc, torch_cuda):
+    from numpy.polynomial import legendre as leg
+    N, n = 3, 3
+    x = I.lgl_points(N)
+    X = x[None, None, :] * np.ones((N + 1, N + 1, 1))
+    q = np.ones((n ** 3, N + 1, N + 1, N + 1))
+    hot = 1 + n * (0 + n * 1)
+    q[hot] = leg.legval(X, np.eye(N + 1)[N])
+    one = np.ones_like(q)
+    U = I.from_primitive(1.0 + 0.3 * q, 0 * one, 0 * one, 0 * one, one, G)
+    s, op = make_blend(orc, N, (n, n, n))
+    _, _, al_ref = orc.alpha(s, U)
+    al = op.alpha(torch_cuda.from_numpy(U).cuda()).cpu().numpy()
+    assert np.count_nonzero(al_ref) == 6 and np.array_equal(al, al_ref)
+
+
+@pytest.mark.parametrize("Cs", [0.0, 0.2])
+@pytest.mark.parametrize("N", [2, 3, 5])
+def test_blended_walls_vjp_dot_product(orc, torch_cuda, Cs, N):
+    nelem = (2, 3, 2)
+    s, op = make_blend(orc, N, nelem, 1, 1, Cs=Cs)
+    U = blended_wall_state(N, nelem)
+    _, _, al = orc.alpha(s, U)
+    assert np.sum(al > 0) >= 3
+    Ud = torch_cuda.from_numpy(U).cuda()
+    for k in range(2):
+        v = I.random_directions(U.shape, 80 + k)
+        w = I.random_directions(U.shape, 90 + k)
+        _, Jv = orc.jvp(s, U, v)
+        JTw = op.vjp(Ud, torch_cuda.from_numpy(w).cuda()).cpu().numpy()
+        a, b, scale = np.sum(w * Jv), np.sum(JTw * v), np.sum(np.abs(w * Jv))
+        assert abs(a - b) <= 1e-11 * scale, (a, b, abs(a - b) / scale)
+
+
+def test_blended_walls_rk_step_vjp(orc, torch_cuda):
+    N, nelem = 3, (2, 3, 2)
+    s, op = make_blend(orc, N, nelem, 0, 0, Cs=0.2)
+    U = blended_wall_state(N, nelem)
+    v = I.random_directions(U.shape, 95)
+    w = I.random_directions(U.shape, 96)
+    dt = 0.25 * orc.max_dt(s, U, 0.5)
+    _, Jv = orc.rk_jvp(s, U, v, dt, 1)
+    JTw = op.rk_step_vjp(torch_cuda.from_numpy(U).cuda(), dt, torch_cuda.from_numpy(w).cuda()).cpu().numpy()
+    a, b, scale = np.sum(w * Jv), np.sum(JTw * v), np.sum(np.abs(w * Jv))
+    assert abs(a - b) <= 1e-11 * scale, (a, b, abs(a - b) / scale)
