@@ -110,13 +110,13 @@ def domain(name):
 # calibration (FETCH x 2.000, WRITE x 1.000); see profiles/k_stage_*.md.  Valid
 # only for the kernel source they were taken on (sha256 prefix).
 MEASURED_TRAFFIC = {
-    "kernel_sha": "937e3176427bee48",
+    "kernel_sha": "bbabc12f9d61b605",
     "tgv_n5_32": {"bytes_per_launch": 1380.3e6, "fetch": 870.7e6, "write": 509.6e6},
-    "tgv_n7_64": {"bytes_per_launch": 26682.9e6, "fetch": 17019.2e6, "write": 9663.7e6},
-    "freestream_euler_n7_64": {"bytes_per_launch": 22926.9e6, "fetch": 13263.2e6, "write": 9663.7e6},
+    "tgv_n7_64": {"bytes_per_launch": 26683.8e6, "fetch": 17020.1e6, "write": 9663.7e6},
+    "freestream_euler_n7_64": {"bytes_per_launch": 22941.2e6, "fetch": 13277.5e6, "write": 9663.7e6},
     "tgv_curved_n5_32": {"bytes_per_launch": 2029.4e6, "fetch": 1519.8e6, "write": 509.6e6},
     "channel_wm_n5_32": {"bytes_per_launch": 1372.5e6, "fetch": 862.9e6, "write": 509.6e6},
-    "sod_ns_n4_256x16x16": {"bytes_per_launch": 2266.7e6, "fetch": 1676.6e6, "write": 590.0e6},
+    "sod_ns_n4_256x16x16": {"bytes_per_launch": 2266.7e6, "fetch": 1676.7e6, "write": 590.0e6},
 }
 
 

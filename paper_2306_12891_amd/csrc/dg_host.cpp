@@ -172,6 +172,7 @@ struct dg_ctx {
   double* G = nullptr;
   double* U2 = nullptr;
   double* alpha1 = nullptr;
+  double* alpha1b = nullptr;  // the other of the pair the fused indicator ping-pongs
   double* alpha = nullptr;
   double* Fvf = nullptr;
   double* cs_field = nullptr;  // per-element Smagorinsky coefficients (dg_set_cs_field)
@@ -235,6 +236,7 @@ void release(dg_ctx* c) {
   hipFree(c->G);
   hipFree(c->U2);
   hipFree(c->alpha1);
+  hipFree(c->alpha1b);
   hipFree(c->alpha);
   hipFree(c->Fvf);
   hipFree(c->cs_field);
@@ -348,8 +350,10 @@ hipError_t timed(dg_ctx* c, int kind, F&& launch) {
 }
 
 // One evaluation of the operator on X_in: [indicator], [BR1 lifting], stage.
+// alpha1_next (blending, MODE_RK): the stage kernel writes the coefficients of
+// X_out there, and the indicator of X_in is taken as already in c->alpha1.
 int run_stage(dg_ctx* c, const double* Xin, double* Xout, double* Ut, int mode, double A, double Bdt, int writeG,
-              double* alpha_out) {
+              double* alpha_out, double* alpha1_next = nullptr) {
   StageArgs a = stage_args(c);
   a.U = Xin;
   a.Uout = Xout;
@@ -360,8 +364,9 @@ int run_stage(dg_ctx* c, const double* Xin, double* Xout, double* Ut, int mode, 
   a.Bdt = Bdt;
   a.writeG = writeG;
   a.alpha_out = alpha_out;
+  a.alpha1_next = alpha1_next;
   hipError_t e;
-  if (c->opt.blending) {
+  if (c->opt.blending && !alpha1_next) {
     e = timed(c, DG_K_INDICATOR, [&] { return c->kt->alpha1(a, c->stream); });
     if (e != hipSuccess) return hip_fail(c, e, "indicator kernel");
   }
@@ -673,6 +678,7 @@ int dg_init(const dg_mesh* mesh, int N, double gamma, double mu, dg_ctx** out) {
   alloc((void**)&c->G, c->nstate * sizeof(double));
   alloc((void**)&c->U2, c->nstate * sizeof(double));
   alloc((void**)&c->alpha1, (size_t)c->nelem * sizeof(double));
+  alloc((void**)&c->alpha1b, (size_t)c->nelem * sizeof(double));
   alloc((void**)&c->alpha, (size_t)c->nelem * sizeof(double));
   alloc((void**)&c->Fvf, (size_t)c->nelem * 6 * 4 * c->nf * sizeof(double));
   alloc((void**)&c->partial, kRedBlocks * 5 * sizeof(double));
@@ -870,12 +876,24 @@ int dg_rk_steps(dg_ctx* c, double* U, double dt, int nsteps) {
   if (!finite_pos(dt)) return fail(c, DG_EINVAL, "rk_step: dt must be finite and > 0");
   if (nsteps < 0) return fail(c, DG_EINVAL, "rk_step: nsteps < 0");
   double* cur = U;
+  // blended Euler operator: the indicator of the start state once, then each
+  // stage kernel writes that of its output for the next stage (alpha1 /
+  // alpha1b ping-pong); Navier-Stokes keeps the separate indicator launch
+  const bool fuse = c->opt.blending && c->opt.equations == DG_EULER && c->kt->fused_alpha1 && nsteps > 0;
+  if (fuse) {
+    StageArgs a = stage_args(c);
+    a.U = U;
+    const hipError_t e = timed(c, DG_K_INDICATOR, [&] { return c->kt->alpha1(a, c->stream); });
+    if (e != hipSuccess) return hip_fail(c, e, "indicator kernel");
+  }
   for (int s = 0; s < nsteps; ++s)
     for (int k = 0; k < 5; ++k) {
       double* nxt = (cur == U) ? c->U2 : U;
       const int writeG = (k < 4) ? 1 : 0;  // the last stage's register is never read again
-      const int rc = run_stage(c, cur, nxt, nullptr, MODE_RK, kA[k], kB[k] * dt, writeG, nullptr);
+      const int rc = run_stage(c, cur, nxt, nullptr, MODE_RK, kA[k], kB[k] * dt, writeG, nullptr,
+                               fuse ? c->alpha1b : nullptr);
       if (rc) return rc;
+      if (fuse) std::swap(c->alpha1, c->alpha1b);
       cur = nxt;
     }
   if (cur != U) {

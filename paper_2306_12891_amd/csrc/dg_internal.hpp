@@ -62,6 +62,10 @@ struct StageArgs {
   int ne[3];  // elements per direction of the box
   // curved mesh with the eddy viscosity: squared filter width per element
   const double* delta2_elem;
+  // blended Euler operator, MODE_RK: the stage kernel also writes the
+  // first-stage coefficient of its output state per element here (NULL: not;
+  // only where KernelTable.fused_alpha1 is set)
+  double* alpha1_next;
 };
 
 struct ReduceArgs {
@@ -114,6 +118,7 @@ struct VjpArgs {
 
 struct KernelTable {
   int nt;  // threads per block
+  int fused_alpha1;  // the blended Euler stage kernels honour StageArgs.alpha1_next
   hipError_t (*stage)(const StageArgs&, int eq, hipStream_t);
   hipError_t (*stage_mixed)(const StageArgs&, int eq, hipStream_t);
   hipError_t (*lift)(const StageArgs&, int eq, hipStream_t);

@@ -904,6 +904,90 @@ __device__ __forceinline__ void face_item(const StageArgs& A, const FaceData<NS,
 #else
 #define DG_STAGE_BOUNDS __launch_bounds__(PS::NTB)
 #endif
+// Indicator quantity q = rho p of a conservative node state.
+__device__ __forceinline__ double indicator_q(const double u[5], double gm1) {
+  const double ir = 1.0 / u[0];
+  const double p = gm1 * (u[4] - 0.5 * ir * (u[1] * u[1] + u[2] * u[2] + u[3] * u[3]));
+  return u[0] * p;
+}
+
+// First-stage blending coefficient of one element (Sec. 4.1): modal energies
+// of q (node t holds qt) by the three 1-D V^-1 contractions through LDS (sq,
+// st: nn doubles each, sVi: V^-1 already written), the three energy sums by
+// lane shuffles within each wave and the per-wave partials (sred: 3 NT/64
+// doubles) in a fixed order, then the sigmoid, the clip at alpha_max and the
+// cut-off below alpha_min.  Every thread of the workgroup (NT threads, one
+// element) calls it; the result is valid in thread 0.
+constexpr int NWAVE = NT / 64;
+__device__ __forceinline__ double element_alpha1(const StageArgs& A, const double* sVi, double* sq, double* st,
+                                                 double* sred, int t, const int ijk[3], double qt) {
+  if (t < nn) sq[t] = qt;
+  __syncthreads();
+  if (t < nn) {  // x: st[a,j,k] = sum_i Vinv[a][i] q[i,j,k]
+    const int base = t - ijk[0];
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < n1; ++i) s = fma(sVi[ijk[0] * n1 + i], sq[base + i], s);
+    st[t] = s;
+  }
+  __syncthreads();
+  if (t < nn) {  // y
+    const int base = t - ijk[1] * n1;
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < n1; ++j) s = fma(sVi[ijk[1] * n1 + j], st[base + j * n1], s);
+    sq[t] = s;
+  }
+  __syncthreads();
+  double e2 = 0.0;
+  int mx = 0;
+  if (t < nn) {  // z
+    const int base = t - ijk[2] * nf;
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < n1; ++k) s = fma(sVi[ijk[2] * n1 + k], sq[base + k * nf], s);
+    e2 = s * s;
+    mx = max(ijk[0], max(ijk[1], ijk[2]));
+  }
+  double r0 = e2, r1 = (mx == N) ? e2 : 0.0, r2 = (mx == N - 1) ? e2 : 0.0;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    r0 += __shfl_xor(r0, o);
+    r1 += __shfl_xor(r1, o);
+    r2 += __shfl_xor(r2, o);
+  }
+  if ((t & 63) == 0) {
+    sred[t >> 6] = r0;
+    sred[NWAVE + (t >> 6)] = r1;
+    sred[2 * NWAVE + (t >> 6)] = r2;
+  }
+  __syncthreads();
+  double a1 = 0.0;
+  if (t == 0) {
+    double S = 0.0, SN = 0.0, SN1 = 0.0;
+#pragma unroll
+    for (int w = 0; w < NWAVE; ++w) {
+      S += sred[w];
+      SN += sred[NWAVE + w];
+      SN1 += sred[2 * NWAVE + w];
+    }
+    const double EN = S > 0.0 ? SN / S : 0.0;
+    const double rest = S - SN;
+    const double EN1 = rest > 0.0 ? SN1 / rest : 0.0;
+    const double E = A.indicator == 1 ? EN : fmax(EN, EN1);
+    const double a0 = 1.0 / (1.0 + exp(-(A.sharp / A.thresh) * (E - A.thresh)));
+    a1 = fmin(a0, A.amax);
+    if (a1 < A.amin) a1 = 0.0;
+  }
+  return a1;
+}
+
+// The blended Euler stage kernel's epilogue computes the next stage's first
+// coefficient (StageArgs.alpha1_next) when its LDS pool holds the indicator's
+// scratch and one pass of threads loads the basis with V^-1.
+constexpr bool kFusedAlpha1 = N >= 2 && DG_EPB_STAGE == 1 && 7 * nnp + 30 * nf >= 2 * nn + 3 * NWAVE &&
+                               NB_STAGE + nf <= NT;
+
 // Viscous fluxes at a node from its lifted gradient g (with the Smagorinsky
 // eddy viscosity when LES).
 template <bool LES, class R>
@@ -942,7 +1026,7 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
   __shared__ R sPoolAll[EPB][POOL];
   __shared__ R sB[NB_STAGE];
   __shared__ double sXAll[EPB][BLEND ? 5 : 1][BLEND ? nn : 1];
-  __shared__ double sB64[BLEND ? NB_STAGE : 1];
+  __shared__ double sB64[BLEND ? NB_STAGE + nf : 1];  // with V^-1 (Vinv follows edge in the basis)
 
   const int e0 = EPB * element_of_block(blockIdx.x, A.chunk);
   if (e0 >= A.nelem) return;  // uniform over the workgroup
@@ -976,6 +1060,8 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
   }
   static_assert(NB_STAGE <= PS::NTB, "one basis entry per thread");
   const double bval = tid < NB_STAGE ? A.basis[tid] : 0.0;
+  // V^-1 for the indicator of the stage output (blended Euler runs)
+  const double vval = (BLEND && !NS && kFusedAlpha1 && tid >= NB_STAGE && tid < NB_STAGE + nf) ? A.basis[tid] : 0.0;
   const Ref ref = MX ? reference_state(A.U, gm1) : Ref{0.0, 0.0, 0.0};
   // Round trip 2: the face states (needs the neighbour indices).
 #pragma unroll
@@ -985,6 +1071,8 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
     sB[tid] = (R)bval;
     if (BLEND) sB64[tid] = bval;
   }
+  if constexpr (BLEND && !NS && kFusedAlpha1)
+    if (tid >= NB_STAGE && tid < NB_STAGE + nf) sB64[tid] = vval;
   const R* sDhat = sB + BL.Dhat();
   const R* sDw = sB + BL.Dw();
   const R* swinv = sB + BL.winv();
@@ -1205,8 +1293,26 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
         double gv = ut[v];
         if (A.A != 0.0) gv = A.A * gprev[v] + ut[v];
         if (A.writeG) A.G[o + v * nn] = gv;
-        A.Uout[o + v * nn] = u[v] + A.Bdt * gv;
+        u[v] = u[v] + A.Bdt * gv;  // the stage output, kept for the indicator below
+        A.Uout[o + v * nn] = u[v];
       }
+    }
+  }
+  // Euler only: measured on the blended Navier-Stokes stage (N = 4, its
+  // occupancy limited by LDS) the epilogue's barriers cost more than the
+  // separate indicator launch it saves.
+  if constexpr (BLEND && !NS && kFusedAlpha1) {
+    if (A.alpha1_next && A.mode == MODE_RK) {  // uniform over the workgroup
+      static_assert(POOL >= 2 * nn + 3 * NWAVE && PS::NTB == NT && BL.Vinv() == NB_STAGE,
+                    "indicator scratch in the LDS pool, V^-1 after the stage basis");
+      double* sq = reinterpret_cast<double*>(sPool);
+      double* st = sq + nn;
+      double* sred = st + nn;
+      const double* sVi = sB64 + NB_STAGE;
+      __syncthreads();  // the pool's last readers (subcell and viscous passes) are done
+      const double qt = t < nn ? indicator_q(u, gm1) : 0.0;
+      const double a1 = element_alpha1(A, sVi, sq, st, sred, t, ijk, qt);
+      if (t == 0) A.alpha1_next[e] = a1;
     }
   }
 }
@@ -2685,75 +2791,25 @@ __global__ __launch_bounds__(NT) void k_alpha1(StageArgs A) {
   __shared__ double sV[nf];
   __shared__ double sq[nn];
   __shared__ double st[nn];
-  __shared__ double sred[3][NT];
+  __shared__ double sred[3 * NWAVE];
   const int e = element_of_block(blockIdx.x, A.chunk);
   if (e >= A.nelem) return;
   const int t = threadIdx.x;
   for (int q = t; q < nf; q += NT) sV[q] = A.basis[BL.Vinv() + q];
   const double* Ue = A.U + (size_t)e * 5 * nn;
-  const double gm1 = A.gamma - 1.0;
   int ijk[3] = {0, 0, 0};
+  double qt = 0.0;
   if (t < nn) {
     double u[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) u[v] = Ue[v * nn + t];
-    const double ir = 1.0 / u[0];
-    const double p = gm1 * (u[4] - 0.5 * ir * (u[1] * u[1] + u[2] * u[2] + u[3] * u[3]));
-    sq[t] = u[0] * p;
+    qt = indicator_q(u, A.gamma - 1.0);
     ijk[0] = t % n1;
     ijk[1] = (t / n1) % n1;
     ijk[2] = t / nf;
   }
-  __syncthreads();
-  if (t < nn) {  // x: st[a,j,k] = sum_i Vinv[a][i] q[i,j,k]
-    const int base = t - ijk[0];
-    double s = 0.0;
-#pragma unroll
-    for (int i = 0; i < n1; ++i) s = fma(sV[ijk[0] * n1 + i], sq[base + i], s);
-    st[t] = s;
-  }
-  __syncthreads();
-  if (t < nn) {  // y
-    const int base = t - ijk[1] * n1;
-    double s = 0.0;
-#pragma unroll
-    for (int j = 0; j < n1; ++j) s = fma(sV[ijk[1] * n1 + j], st[base + j * n1], s);
-    sq[t] = s;
-  }
-  __syncthreads();
-  double e2 = 0.0;
-  int mx = 0;
-  if (t < nn) {  // z
-    const int base = t - ijk[2] * nf;
-    double s = 0.0;
-#pragma unroll
-    for (int k = 0; k < n1; ++k) s = fma(sV[ijk[2] * n1 + k], sq[base + k * nf], s);
-    e2 = s * s;
-    mx = max(ijk[0], max(ijk[1], ijk[2]));
-  }
-  sred[0][t] = e2;
-  sred[1][t] = (mx == N) ? e2 : 0.0;
-  sred[2][t] = (mx == N - 1) ? e2 : 0.0;
-  __syncthreads();
-  for (int h = NTP2 / 2; h > 0; h >>= 1) {
-    if (t < h && t + h < NT) {
-      sred[0][t] += sred[0][t + h];
-      sred[1][t] += sred[1][t + h];
-      sred[2][t] += sred[2][t + h];
-    }
-    __syncthreads();
-  }
-  if (t == 0) {
-    const double S = sred[0][0], SN = sred[1][0], SN1 = sred[2][0];
-    const double EN = S > 0.0 ? SN / S : 0.0;
-    const double rest = S - SN;
-    const double EN1 = rest > 0.0 ? SN1 / rest : 0.0;
-    const double E = A.indicator == 1 ? EN : fmax(EN, EN1);
-    const double a0 = 1.0 / (1.0 + exp(-(A.sharp / A.thresh) * (E - A.thresh)));
-    double a1 = fmin(a0, A.amax);
-    if (a1 < A.amin) a1 = 0.0;
-    const_cast<double*>(A.alpha1)[e] = a1;
-  }
+  const double a1 = element_alpha1(A, sV, sq, st, sred, t, ijk, qt);
+  if (t == 0) const_cast<double*>(A.alpha1)[e] = a1;
 }
 
 __global__ void k_spread(StageArgs A) {
@@ -4344,7 +4400,7 @@ hipError_t launch_nonfinite(const ReduceArgs& R, hipStream_t s) {
 }
 
 const KernelTable kTable = {
-    NT, launch_stage, launch_stage_mixed, launch_lift, launch_lift_mixed, launch_alpha1, launch_spread,
+    NT, kFusedAlpha1 ? 1 : 0, launch_stage, launch_stage_mixed, launch_lift, launch_lift_mixed, launch_alpha1, launch_spread,
     launch_max_rate, launch_integrals, launch_nonfinite, launch_vjp, launch_vjp_lift, launch_vjp_alpha_bar,
     launch_vjp_alpha, launch_vjp_fv, launch_axpby, launch_metrics, launch_stage_curved, launch_lift_curved,
     launch_vjp_curved, launch_vjp_lift_curved, launch_wall_flux,
