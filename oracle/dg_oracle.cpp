@@ -35,12 +35,14 @@
 //   * wall-modelled boundaries: Spalding's law of the wall with the van
 //     Driest transformation of the input velocity (Sec. 3, Spalding and van
 //     Driest eqs.); how the model enters the DG boundary (slip-wall
-//     interface states, exchange location, tangential stress) is a reading.
+//     interface states, exchange location, tangential stress) is a reading;
+//   * the blend with Navier-Stokes and with walls: the FV subcell scheme
+//     carries no viscous terms, so only the advective operator is blended,
+//     and a wall face spreads no coefficient (readings).
 // Everything the paper leaves open (BR1 lifting, the Kennedy-Gruber and
 // Pirozzoli two-point fluxes, LLF/Roe, the LSERK4 coefficients, the modal
-// energy definition, the sharpness s, the FV reconstruction) follows the
-// standard literature readings listed in the design notes, and each place is
-// marked "reading:" below.
+// energy definition, the sharpness s, the FV reconstruction) follows standard
+// readings from the literature, and each place is marked "reading:" below.
 //
 // "parity unpinned" items (fixed only by GPU/oracle agreement, no independent
 // pin exists): the Roe dissipation constants beyond the consistency identity,
@@ -1360,7 +1362,9 @@ static void fv_subcell(const Ctx& c, const T* U, const std::vector<T>& fstar, T*
 
 // ---------------------------------------------------------------------------
 // Full time derivative.  alpha_in (optional) overrides the indicator.
-// Ut = (1 - a) Ut_DG_adv + a Ut_FV (+ viscous, never blended).
+// Ut = (1 - a) Ut_DG_adv + a Ut_FV (+ viscous, never blended).  reading: the
+// FV subcell scheme has no viscous fluxes, so with Navier-Stokes only the
+// advective operator is blended.
 // ---------------------------------------------------------------------------
 template <class T>
 static void time_derivative(const Ctx& c, const T* U, T* Ut, const double* alpha_in,
