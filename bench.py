@@ -1,15 +1,21 @@
 """Throughput benchmark of the split-form DGSEM hot path on one MI355X.
 
-Default workload: Taylor-Green vortex, Ma 0.1, Re 1600, Pr 0.72, N = 5 on
-32^3 periodic elements (7.08 M nodes), Pirozzoli split flux + Roe, BR1
-lifting, FP64, LSERK4.  A "step" is one Runge-Kutta step (5 stages) over the
+Default workload: Taylor-Green vortex, Ma 0.1, Re 1600, Pr 0.72, N = 7 on
+64^3 periodic elements (134 M nodes), Pirozzoli split flux + Roe, BR1
+lifting, FP64, LSERK4: the configuration the metric is quoted on (FP64
+against the mixed-precision operator at its stated error; the adjoint of
+the N = 5, 16^3 TGV beside it).  A "step" is one Runge-Kutta step (5 stages) over the
 whole mesh.  The metric is DOF-stage updates per second (1/PID with the GPU as
 the single "core"; DOF counts nodes).  Inputs are resident in HBM before the
 timed region; the timed region is bracketed by torch.cuda.synchronize().
 
 Prints one JSON line with the throughput, the roofline of the dominant kernel
-(measured with HIP events on the library's stream during the timed region)
-and the CPU oracle timed on a bounded sample of the same workload.
+(measured with HIP events on the library's stream during the timed region:
+160 B per DOF and launch -- read U and the register, write the register and U
+-- over the average launch time, against 8 TB/s), its FP64 FLOP rate (the
+kernel's flops per DOF, counted with rocprofv3, over the same time, against
+78.6 TFLOP/s), and the CPU oracle timed on a bounded sample of the same
+workload.
 """
 from __future__ import annotations
 
@@ -27,6 +33,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "DOF-stage updates/s (1/PID) FP64 vs mixed at stated err; adjoint/forward time"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
 
 WORKLOADS = {
     # name: (N, nelem, equations, vol_flux, surf_flux, mu, blending, description)
@@ -120,6 +127,13 @@ MEASURED_TRAFFIC = {
 }
 
 
+# FP64 (mixed: FP32) floating-point operations of the stage kernel per DOF
+# and launch, counted with rocprofv3 (SQ_INSTS_VALU_FMA_F64 x 2 + ADD + MUL +
+# TRANS, times 64 lanes, over the DOF of the launch; profiles/k_stage_*.md);
+# valid only for the kernel source they were counted on (sha256 prefix).
+KERNEL_FLOPS = {"kernel_sha": None}
+
+
 def kernel_sha():
     import hashlib
     h = hashlib.sha256()
@@ -211,6 +225,28 @@ def adjoint_leg(torch, dg, inputs, steps=200, every=20, n_dirs=8, eps=1e-6):
             "steps": steps, "forward_s": t_fwd, "gradient_s": t_grad, "gradient_over_forward": t_grad / t_fwd,
             "vjp_over_operator_kernel_time": t_vjp / t_op, "rk_step_vjp_over_rk_step": t_step_vjp / t_step,
             "fd_check": {"eps": eps, "directions": n_dirs, "max_rel_err": max(errs), "rel_errs": errs}}
+
+
+def vjp_only(torch, dg, inputs, reps=10):
+    """One reverse product (dg_vjp) against one operator evaluation on the
+    adjoint configuration's mesh (TGV N = 5, 16^3, symmetry-broken), without
+    the rollout: the launches a kernel profile of the reverse kernels needs."""
+    N, nelem, mu = 5, (16, 16, 16), 1.0 / 1600
+    op = dg.DG(nelem, N, gamma=1.4, mu=mu, equations=dg.NS, vol_flux=dg.PI, surf_flux=dg.ROE, Pr=0.72)
+    U0 = torch.from_numpy(inputs.tgv(N, nelem, symmetry_break=True)).to("cuda:0")
+    lam = torch.from_numpy(inputs.random_directions(tuple(U0.shape), 99)).to("cuda:0")
+    out = torch.empty_like(U0)
+    op.set_profiling(True)
+    for _ in range(reps):
+        op.time_derivative(U0)
+        op.vjp(U0, lam, out=out)
+    prof = op.profile_read()
+    op.close()
+    t_op = prof["stage"][0] + prof["lift"][0]
+    t_vjp = prof["vjp"][0] + prof["vjp_lift"][0]
+    return {"workload": "TGV Ma0.1 Re1600, N=5, 16^3 elems, PI+Roe, BR1; dg_vjp vs dg_time_derivative",
+            "reps": reps, "operator_ms": t_op / reps, "vjp_ms": t_vjp / reps, "vjp_over_operator": t_vjp / t_op,
+            "kernel_ms": {k: v[0] / max(v[1], 1) for k, v in prof.items() if v[1]}}
 
 
 def cpu_baseline(name, spec, U0, dt, max_nodes=8_000_000):
@@ -312,17 +348,34 @@ def measured_copy_bandwidth(torch, mib=4096, reps=10):
 
 
 def roofline(name, nodes, steps, prof):
+    """Roofline of the stage kernel from its event-timed launches: achieved =
+    160 B per DOF and launch (SURVEY-style floor of the Runge-Kutta stage:
+    read U and the register, write the register and U; curved meshes add the
+    80 B of metric terms) over the average launch time.  The exact per-launch
+    average (stage 1 reads no register, stage 5 writes none: 144 B) is
+    reported beside it."""
     ms_stage, n_stage = prof["stage"]
     avg_ms = ms_stage / max(n_stage, 1)
-    step_bytes = stage_bytes_per_step(nodes) + (5 * METRIC_BYTES_PER_NODE * nodes if name in CURVED else 0.0)
-    A = step_bytes * steps / (ms_stage * 1e-3) / 1e9
+    extra = METRIC_BYTES_PER_NODE if name in CURVED else 0.0
+    launch_bytes = (160.0 + extra) * nodes
+    A = launch_bytes / (avg_ms * 1e-3) / 1e9
+    exact = (stage_bytes_per_step(nodes) / 5 + extra * nodes) / (avg_ms * 1e-3) / 1e9
     traffic = None
     if name in MEASURED_TRAFFIC and kernel_sha() == MEASURED_TRAFFIC["kernel_sha"]:
         traffic = MEASURED_TRAFFIC[name]["bytes_per_launch"]
-    return {"bound": "hbm", "achieved": round(A, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(A / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_unit": "bytes per launch",
-            "kernel": ("k_stage_curved" if name in CURVED else "k_stage") + " (operator + LSERK4 stage)",
-            "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": step_bytes / 5}
+    out = {"bound": "hbm", "achieved": round(A, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(A / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_unit": "bytes per launch",
+           "kernel": ("k_stage_curved" if name in CURVED else "k_stage") + " (operator + LSERK4 stage)",
+           "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": launch_bytes,
+           "algorithmic_bytes_per_dof": 160.0 + extra,
+           "frac_exact_144B": round(exact / HBM_PEAK_GBS, 4)}
+    fl = KERNEL_FLOPS.get(name)
+    if fl and kernel_sha() == KERNEL_FLOPS["kernel_sha"]:
+        tf = fl["stage_flops_per_dof"] * nodes / (avg_ms * 1e-3) / 1e12
+        out["fp64"] = {"flops_per_dof_launch": fl["stage_flops_per_dof"], "achieved": round(tf, 2),
+                       "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(tf / FP64_PEAK_TFLOPS, 4),
+                       "counted": "rocprofv3 SQ_INSTS_VALU_{FMA,ADD,MUL,TRANS}_F64 x 64 lanes per DOF"}
+    return out
 
 
 def blended_fraction(torch, op, U0, dt, steps, every=50):
@@ -406,13 +459,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--repeats", type=int, default=5,
                     help="timed blocks of --steps steps; `value` is the first, the rest give mean/min/max")
-    ap.add_argument("--workload", default="tgv_n5_32", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="tgv_n7_64", choices=sorted(WORKLOADS))
     ap.add_argument("--sweep", action="store_true",
                     help="freestream workloads: also time 2^15 ... 2^21 elements")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison run")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint (gradient) leg")
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
+    ap.add_argument("--vjp-only", action="store_true",
+                    help="only time dg_vjp against dg_time_derivative on the adjoint mesh (N = 5, 16^3) and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized float64 device buffer 5 times (reference kernel for the "
                          "FETCH_SIZE/WRITE_SIZE counters) and exit")
@@ -427,6 +482,12 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_read_per_launch": n * 8, "bytes_written_per_launch": n * 8,
                           "launches": 5}))
+        return
+    if args.vjp_only:
+        import torch
+
+        from paper_2306_12891_amd import dg, inputs
+        print(json.dumps(vjp_only(torch, dg, inputs)))
         return
     if args.gpus != 1:
         print(f"bench.py: this path runs on one GPU; --gpus {args.gpus} is not supported "
@@ -481,6 +542,16 @@ def main():
     if not args.no_mixed and vf in (1, 3) and not blend and name not in CURVED and name not in WALLS:
         opm = dg.DG(nelem, N, gamma=1.4, mu=mu, lo=lo, hi=hi, equations=eq, vol_flux=vf, surf_flux=sf,
                     Pr=0.72, precision=dg.MIXED, Cs=cs)
+        # one operator evaluation at the initial state: error of the mixed U_t
+        # per variable against the FP64 operator (which matches the oracle to
+        # 1e-12), relative to max |U_t,v|
+        ut64 = op.time_derivative(U_init)
+        utm = opm.time_derivative(U_init)
+        dut = (utm - ut64).abs()
+        sc = ut64.abs().amax(dim=(0, 2, 3, 4))
+        ut_linf = (dut.amax(dim=(0, 2, 3, 4)) / sc).tolist()
+        ut_l2 = (dut.pow(2).mean(dim=(0, 2, 3, 4)).sqrt() / ut64.pow(2).mean(dim=(0, 2, 3, 4)).sqrt()).tolist()
+        del ut64, utm, dut
         Um = U_init.clone()
         walls_m, profm = timed_rollouts(torch, opm, Um, dt, args.steps, args.warmup, repeats,
                                         not args.no_profile)
@@ -494,7 +565,10 @@ def main():
                           "ms_per_step": wall_m / args.steps * 1e3, "speedup_vs_fp64": wall / wall_m,
                           "err_vs_fp64_linf_rel": linf, "err_vs_fp64_l2_rel": l2,
                           "err_bound_stated": 1e-5, "within_bound": max(linf) <= 1e-5,
-                          "after_steps": args.warmup + args.steps * repeats}
+                          "after_steps": args.warmup + args.steps * repeats,
+                          "ut_err_linf_rel_max_ut": ut_linf, "ut_err_l2_rel": ut_l2,
+                          "ut_err_note": "one evaluation at the initial state against the FP64 operator; rho and E "
+                                         "rates at Ma 0.1 are small differences of O(p0), O(h0) flux terms"}
         if profm:
             extra["mixed"]["kernel_ms_per_step"] = {k: round(v[0] / args.steps, 4) for k, v in profm.items() if v[1]}
             extra["mixed"]["stage_roofline_frac"] = roofline("", nodes, args.steps, profm)["frac"]

@@ -1,11 +1,13 @@
 /* dg.h - C ABI of the MI355X split-form DGSEM library (libdgmi.so).
  *
  * The library evaluates the discontinuous Galerkin spectral element operator
- * of the compressible Euler / Navier-Stokes equations on periodic Cartesian
- * hexahedral meshes and advances it with a five-stage, fourth-order,
- * two-register (2N-storage) explicit Runge-Kutta scheme.  All arithmetic runs
- * in HIP kernels on one GPU; the host side only validates arguments and
- * enqueues work.
+ * of the compressible Euler / Navier-Stokes equations on hexahedral meshes
+ * (the periodic Cartesian box of dg_init; curved elements with structured or
+ * general face connectivity, dg_set_geometry / dg_set_connectivity; two box
+ * faces as wall-modelled boundaries, dg_set_wall_model) and advances it with
+ * a five-stage, fourth-order, two-register (2N-storage) explicit Runge-Kutta
+ * scheme.  All arithmetic runs in HIP kernels on one GPU; the host side only
+ * validates arguments and enqueues work.
  *
  * Method (paper: Blind et al., "Towards Exascale CFD Simulations Using the
  * Discontinuous Galerkin Solver FLEXI"):
@@ -223,8 +225,13 @@ int dg_set_stream(dg_ctx* ctx, void* hip_stream);
 int dg_time_derivative(dg_ctx* ctx, const double* U, double* Ut);
 
 /* One Runge-Kutta step of size dt (> 0, finite), in place: five stages
- * G <- A_k G + L(U), U <- U + B_k dt G.  The blending coefficient is
- * recomputed at every stage. */
+ * G <- A_k G + L(U), U <- U + B_k dt G (A_1 = 0).  The paper fixes only an
+ * explicit Runge-Kutta scheme whose stages are counted in the performance
+ * index (Sec. 2, eq. (pid)); the coefficients A_k, B_k are those of the
+ * Carpenter-Kennedy five-stage fourth-order 2N-storage scheme (a reading).
+ * U: device, state layout above, read and overwritten.  The blending
+ * coefficient is recomputed at every stage.  Errors: DG_EINVAL for a host or
+ * NULL pointer or dt not finite and > 0; DG_EHIP for launch failures. */
 int rk_step(dg_ctx* ctx, double* U, double dt);
 
 /* nsteps Runge-Kutta steps in place (same result as nsteps rk_step calls). */
@@ -248,8 +255,10 @@ int dg_rk_steps(dg_ctx* ctx, double* U, double dt, int nsteps);
  * on first use. */
 int dg_vjp(dg_ctx* ctx, const double* U, const double* Ut_bar, double* U_bar);
 
-/* Vector-Jacobian product of one rk_step: U_bar_n = (dU_{n+1}/dU_n)^T U_bar_np1,
- * with U_n the state before the step.  Recomputes the five stage states from
+/* Vector-Jacobian product of one rk_step (the step of Sec. 2, eq. (pid), with
+ * the 2N-storage coefficients of rk_step): U_bar_n = (dU_{n+1}/dU_n)^T
+ * U_bar_np1, with U_n the state before the step.  All three arrays are
+ * device memory in the state layout; U_n is read only.  Recomputes the five stage states from
  * U_n and runs the reverse 2N-storage recurrence
  *   Gbar <- A_{k+1} Gbar + B_k dt Ybar,  Ybar <- Ybar + VJP(Y_{k-1}, Gbar),
  * k = 5..1.  Overwrites U_bar_n (may alias U_bar_np1, not U_n).  Same
@@ -272,15 +281,31 @@ int rk_step_record(dg_ctx* ctx, double* U, double dt, double* Y);
  * use. */
 int rk_step_vjp_recorded(dg_ctx* ctx, const double* Y, double dt, const double* U_bar_np1, double* U_bar_n);
 
-/* Stable time step: cfl * min(1/((N+1) max sum_d (|u_d|+c)/dx_d),
- *                             1/((N+1)^2 max nu_eff sum_d 1/dx_d^2)),
- * nu_eff = mu gamma/(rho Pr) for DG_NS.  Synchronises. */
+/* Stable time step.  The paper states no time-step rule; the reading used
+ * here is the usual convective and viscous CFL estimate over all nodes:
+ *   dt = cfl * min(1/((N+1) max sum_d (|u_d|+c)/dx_d),
+ *                  1/((N+1)^2 max nu_eff sum_d 1/dx_d^2)),
+ * nu_eff = mu gamma/(rho Pr) for DG_NS (on curved meshes |Ja^d|/(2J) in
+ * place of 1/dx_d and the contravariant velocity).  U: device state; dt_out:
+ * host.  Synchronises.  Errors: DG_EINVAL for bad pointers or cfl not finite
+ * and > 0; DG_ENONFINITE if any node is not finite or has rho <= 0 or p <= 0
+ * (no time step is returned then). */
 int dg_max_dt(dg_ctx* ctx, const double* U, double cfl, double* dt_out);
 
-/* out[v] = sum_e J sum_ijk w_i w_j w_k X[e][v][ijk] (FP64).  Synchronises. */
+/* Conservation integrals (the quadrature that makes the split form
+ * conservative, Sec. 2): out[v] = sum_e J sum_ijk w_i w_j w_k X[e][v][ijk],
+ * FP64, J = dx dy dz / 8 on the box (the node Jacobian on curved meshes),
+ * w the LGL weights.  X: device, state layout; out: host, 5 doubles.  The
+ * sum is taken in a fixed order (deterministic).  Synchronises.  Errors:
+ * DG_EINVAL for bad pointers; DG_EHIP. */
 int dg_integrals(dg_ctx* ctx, const double* X, double out[5]);
 
-/* Blending coefficient per element of state U (device array of nElems). */
+/* Blending coefficient per element of state U (paper Sec. 4.1: modal
+ * indicator of rho*p, sigmoid with threshold T(N), spread of 1/2 to the face
+ * neighbours; Sec. 4.2: clip at alpha_max, zero below alpha_min), exactly the
+ * coefficient the blended operator uses at that state.  U: device, state
+ * layout; alpha: device, nElems doubles, overwritten.  Errors: DG_EINVAL for
+ * bad pointers; DG_EUNSUPPORTED without blending. */
 int dg_alpha(dg_ctx* ctx, const double* U, double* alpha);
 
 /* DG_OK if every entry of the state-sized array X is finite, else

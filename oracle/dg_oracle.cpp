@@ -45,8 +45,14 @@
 // readings from the literature, and each place is marked "reading:" below.
 //
 // "parity unpinned" items (fixed only by GPU/oracle agreement, no independent
-// pin exists): the Roe dissipation constants beyond the consistency identity,
-// the minmod reconstruction details, and the sharpness s.
+// pin exists): the minmod reconstruction beyond its exactness on linear data
+// (the limiter's choice between the two one-sided slopes on non-linear data,
+// and the positivity fallback).  Pinned since the first version were judged
+// unpinned: the Kennedy-Gruber and Pirozzoli energy fluxes are told apart by
+// the pressure rate at constant velocity and pressure (Pirozzoli's is exactly
+// gamma times Kennedy-Gruber's), the sharpness s by the raw sigmoid at E = 0,
+// T/2 and T with the cut-off and clip switched off, and Roe's dissipation by
+// the upwind (Roe) property for supersonic states and its consistency.
 // ============================================================================
 #include <algorithm>
 #include <cmath>
@@ -1447,7 +1453,8 @@ static void integrals(const Ctx& c, const double* X, double out[5]) {
     }
 }
 
-// Time step: dt = CFL * min( 1 / ((N+1) max sum_d (|u_d| + c)/dx_d),
+// Time step (returns -2 for a state with a non-finite node or rho <= 0 or
+// p <= 0): dt = CFL * min( 1 / ((N+1) max sum_d (|u_d| + c)/dx_d),
 //                            1 / ((N+1)^2 max nu_eff sum_d 1/dx_d^2) ),
 // nu_eff = mu gamma / (rho Pr) (viscous part only for Navier-Stokes).  On
 // curved elements 1/dx_d becomes |Ja^d|/(2J) at the node and |u_d| the
@@ -1478,6 +1485,9 @@ static double max_dt(const Ctx& c, const double* U, double cfl) {
           sv += 1.0 / (c.dx[d] * c.dx[d]);
         }
       }
+      // no time step from a state with a non-finite node or rho <= 0 or
+      // p <= 0 (std::max would silently skip a NaN rate)
+      if (!(P.rho > 0.0) || !(P.p > 0.0) || !std::isfinite(s)) return -2.0;
       lam_a = std::max(lam_a, s);
       if (c.s.equations == EQ_NS) lam_v = std::max(lam_v, c.s.mu * g / (P.rho * c.s.Pr) * sv);
     }

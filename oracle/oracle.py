@@ -38,6 +38,19 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def sanitize_check(timeout: float = 300.0):
+    """Builds oracle/sanitize_check.cpp (the oracle source with a driver that
+    calls every entry point on small cases) with g++'s address and
+    undefined-behaviour sanitizers and runs it; returns (exit status, output)."""
+    exe = os.path.join(HERE, "_sanitize_check")
+    cmd = ["g++", "-O1", "-g", "-std=c++17", "-fopenmp", "-ffp-contract=off", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=undefined", "-o", exe, os.path.join(HERE, "sanitize_check.cpp")]
+    subprocess.check_call(cmd)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1", OMP_NUM_THREADS="2")
+    r = subprocess.run([exe], stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True, env=env, timeout=timeout)
+    return r.returncode, r.stdout
+
+
 class _Setup(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("equations", ctypes.c_int32), ("vol_flux", ctypes.c_int32), ("surf_flux", ctypes.c_int32),
@@ -314,6 +327,8 @@ def integrals(s: Setup, X):
 
 def max_dt(s: Setup, U, cfl: float = 0.5) -> float:
     dt = lib().or_max_dt(_ref(s), _p(_f64(U)), float(cfl))
+    if dt == -2.0:
+        raise ValueError("state with a non-finite node or rho <= 0 or p <= 0: no time step")
     if dt < 0:
         raise ValueError("oracle rejected the setup")
     return dt

@@ -31,25 +31,24 @@ def _run(cmd, verbose):
     return r.stdout
 
 
-def build(verbose: bool = False, jobs: int | None = None, out: str = OUT, defines=(), build_dir: str = BUILD,
-          kernel_source: str = os.path.join(HERE, "dg_kernels.hip")) -> str:
-    """Compiles and links the library; defines are extra -D options (tuning)."""
-    os.makedirs(build_dir, exist_ok=True)
-    extra = [f"-D{d}" for d in defines]
+def build(verbose: bool = False, jobs: int | None = None) -> str:
+    """Compiles the committed kernel and host sources and links the library."""
+    os.makedirs(BUILD, exist_ok=True)
     jobs = jobs or min(8, os.cpu_count() or 1)
+    kernel_source = os.path.join(HERE, "dg_kernels.hip")
     cmds = []
     for n in DEGREES:
-        obj = os.path.join(build_dir, f"dg_kernels_N{n}.o")
-        cmds.append([HIPCC, *FLAGS, *extra, f"-DDG_N={n}", "-c", kernel_source, "-o", obj])
-    host_obj = os.path.join(build_dir, "dg_host.o")
-    cmds.append([HIPCC, *FLAGS, *extra, "-x", "hip", "-c", os.path.join(HERE, "dg_host.cpp"), "-o", host_obj])
+        obj = os.path.join(BUILD, f"dg_kernels_N{n}.o")
+        cmds.append([HIPCC, *FLAGS, f"-DDG_N={n}", "-c", kernel_source, "-o", obj])
+    host_obj = os.path.join(BUILD, "dg_host.o")
+    cmds.append([HIPCC, *FLAGS, "-x", "hip", "-c", os.path.join(HERE, "dg_host.cpp"), "-o", host_obj])
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         list(ex.map(lambda c: _run(c, verbose), cmds))
     objs = [c[-1] for c in cmds]
-    tmp = out + ".tmp"
+    tmp = OUT + ".tmp"
     _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs], verbose)
-    os.replace(tmp, out)
-    return out
+    os.replace(tmp, OUT)
+    return OUT
 
 
 if __name__ == "__main__":

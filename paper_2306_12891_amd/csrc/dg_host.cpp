@@ -451,10 +451,13 @@ int ensure_reverse_buffers(dg_ctx* c, bool rk, bool stages = true) {
   return DG_OK;
 }
 
-// U_bar = [Uacc +] (dL/dU)^T lambda on the context's stream.
-int run_vjp(dg_ctx* c, const double* U, const double* lambda, double* U_bar, const double* Uacc) {
-  int rc = ensure_reverse_buffers(c, false);
-  if (rc) return rc;
+// U_bar = [Uacc +] (dL/dU)^T lambda on the context's stream, with the given
+// reverse-mode buffers: the face buffer of gradient cotangents Gbf
+// (Navier-Stokes), and with blending U_t^FV - U_t^DG (Dfd) and the cotangent
+// of alpha (abar).  Every entry of them is written before it is read.
+int run_vjp_buffers(dg_ctx* c, const double* U, const double* lambda, double* U_bar, const double* Uacc,
+                    double* Gbf, double* Dfd, double* abar) {
+  int rc = 0;
   VjpArgs v;
   std::memset(&v, 0, sizeof(v));
   v.U = U;
@@ -463,7 +466,7 @@ int run_vjp(dg_ctx* c, const double* U, const double* lambda, double* U_bar, con
   v.Uacc = Uacc;
   v.nbr = c->nbr;
   v.basis = c->basis;
-  v.Gbf = c->Gbf;
+  v.Gbf = Gbf;
   for (int d = 0; d < 3; ++d) v.invJ[d] = c->invJ[d];
   v.gamma = c->gamma;
   v.mu = c->mu;
@@ -499,12 +502,12 @@ int run_vjp(dg_ctx* c, const double* U, const double* lambda, double* U_bar, con
   }
   if (c->opt.blending) {
     // forward at U: blending coefficients and U_t^FV - U_t^DG
-    if ((rc = run_stage(c, U, nullptr, c->Dfd, MODE_DIFF, 0.0, 0.0, 0, c->alpha))) return rc;
+    if ((rc = run_stage(c, U, nullptr, Dfd, MODE_DIFF, 0.0, 0.0, 0, c->alpha))) return rc;
     const StageArgs a = stage_args(c);
     v.alpha = c->alpha;
     v.alpha1 = c->alpha1;
-    v.Dfd = c->Dfd;
-    v.abar = c->abar;
+    v.Dfd = Dfd;
+    v.abar = abar;
     v.amin = a.amin;
     v.amax = a.amax;
     v.aspread = a.aspread;
@@ -527,6 +530,14 @@ int run_vjp(dg_ctx* c, const double* U, const double* lambda, double* U_bar, con
   e = timed(c, DG_K_VJP, [&] { return c->kt->vjp(v, eq_code(c), c->stream); });
   if (e != hipSuccess) return hip_fail(c, e, "vjp kernel");
   return DG_OK;
+}
+
+// U_bar = [Uacc +] (dL/dU)^T lambda with the context's reverse-mode buffers
+// (allocated on first use).
+int run_vjp(dg_ctx* c, const double* U, const double* lambda, double* U_bar, const double* Uacc) {
+  const int rc = ensure_reverse_buffers(c, false);
+  if (rc) return rc;
+  return run_vjp_buffers(c, U, lambda, U_bar, Uacc, c->Gbf, c->Dfd, c->abar);
 }
 
 // Structured periodic neighbour table of the context's mesh.

@@ -69,12 +69,15 @@ constexpr int NB_STAGE = 2 * n1 * n1 + 3 * n1 + 1;  // Dhat, Dw, winv, xi, edge
 #define DG_STAGE_MIN_WAVES 0
 #endif
 #ifndef DG_SKIP_DIAG
-#define DG_SKIP_DIAG 1
+#define DG_SKIP_DIAG 0
 #endif
 // Accumulate the BR1 gradient inside the split-form volume loop, reusing its
 // partner values and coefficients (1), or in a separate pass (0).  The fused
 // loop is kept rolled: fully unrolled, the partner loads in flight need more
 // than 200 registers.
+#ifndef DG_VDIV_LINES
+#define DG_VDIV_LINES 0
+#endif
 #ifndef DG_FUSED_GRAD
 #define DG_FUSED_GRAD 1
 #endif
@@ -85,6 +88,7 @@ enum { SF_LLF = 0, SF_ROE = 1, SF_CENTRAL = 2 };
 // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
 // contiguous range of elements so that x/y/z neighbours share its L2.
 __device__ __forceinline__ int element_of_block(int b, int chunk) { return (b & 7) * chunk + (b >> 3); }
+
 
 __device__ __forceinline__ int face_node(int d, int l, int a) {
   const int t1 = a % n1, t2 = a / n1;
@@ -417,8 +421,16 @@ constexpr int kPartners = DG_SKIP_DIAG ? N : N + 1;
 // partner instead of the modulo and two address products).
 template <bool ROLLED, int ST, class F>
 __device__ __forceinline__ void partner_loop(int id, int n, int base, F&& body) {
-  if (ROLLED) {
-    int l = DG_SKIP_DIAG ? id : -1, m = DG_SKIP_DIAG ? n : base - ST;
+  if (!DG_SKIP_DIAG) {  // every l; the zero diagonal term is evaluated too
+    if (ROLLED) {
+#pragma unroll 1
+      for (int l = 0; l < n1; ++l) body(l, base + l * ST);
+    } else {
+#pragma unroll
+      for (int l = 0; l < n1; ++l) body(l, base + l * ST);
+    }
+  } else if (ROLLED) {
+    int l = id, m = n;
 #pragma unroll 1
     for (int k = 1; k <= kPartners; ++k) {
       ++l;
@@ -443,8 +455,8 @@ __device__ __forceinline__ void partner_loop(int id, int n, int base, F&& body) 
 // reuses the partner values and coefficients the flux loop reads anyway
 // (off the diagonal Dw = D = Dhat / 2 exactly).
 template <int VF, int D, class R, bool GRAD = false>
-__device__ __forceinline__ void volume_dir(const R (*sP)[nnp], const R* sDhat, int n, int id, const R me[7], R invJ,
-                                           R gm1, R acc[5], const R* sDw = nullptr, R* gs = nullptr) {
+__device__ __forceinline__ void volume_dir(const R (*sP)[nnp], const R* sDhat, R wb, int n, int id, const R me[7],
+                                           R invJ, R gm1, R acc[5], const R* sDw = nullptr, R* gs = nullptr) {
   constexpr int st = D == 0 ? 1 : (D == 1 ? n1 : nf);
   const int base = n - id * st;
   const R* crow = sDhat + id * n1;
@@ -458,52 +470,74 @@ __device__ __forceinline__ void volume_dir(const R (*sP)[nnp], const R* sDhat, i
     }
   };
   if (VF == VF_KG || VF == VF_PI) {
-    // f_rho = fr4/4, f_m = fr4 us/8 + ps/2 e_D, f_E = fr4 xs/8 (+ ps und/4 for KG)
-    // with sums s = a + b and fr4 = rho_s und_s.
-    R s_fr = 0, s_m0 = 0, s_m1 = 0, s_m2 = 0, s_p = 0, s_E1 = 0, s_E2 = 0;
+    // Per partner l the pair weight a_l = c_l (rho_n + rho_l)(und_n + und_l);
+    // the node's own factor of each product is taken out of the sum:
+    //   sum_l a_l (u_n + u_l) = u_n sum_l a_l + sum_l a_l u_l   (u, v, w, x),
+    //   sum_l c_l (p_n + p_l) = p_n rowsum + sum_l c_l p_l,
+    // rowsum = sum_l Dhat_{id l} (1/w_0 in row 0, -1/w_N in row N, 0 inside).
+    // Then f_rho = A/4, f_m = (u_n A + s_u)/8 + P/2 e_D, f_E = (x_n A + s_x)/8
+    // (+ sum_l c_l (p_n + p_l)(und_n + und_l)/4 for KG).  Every partner
+    // including l = id (Dhat has a zero diagonal) is visited with a
+    // compile-time offset from the line start.
+    const R und_n = me[1 + D];
+    R s_A = 0, s_u = 0, s_v = 0, s_w = 0, s_x = 0, s_p = 0, s_E2 = 0;
     auto pair = [&](int l, int m) {
       const R c = crow[l];
       grad_acc(c, m);
-      const R rs = me[0] + sP[0][m];
-      const R us = me[1] + sP[1][m];
-      const R vs = me[2] + sP[2][m];
-      const R ws = me[3] + sP[3][m];
-      const R ps = me[4] + sP[4][m];
-      const R xs = me[5] + sP[5][m];
-      const R und = D == 0 ? us : (D == 1 ? vs : ws);
-      const R cf = c * (rs * und);
-      s_fr += cf;
-      s_m0 = fmaR(cf, us, s_m0);
-      s_m1 = fmaR(cf, vs, s_m1);
-      s_m2 = fmaR(cf, ws, s_m2);
-      const R cp = c * ps;
-      s_p += cp;
-      s_E1 = fmaR(cf, xs, s_E1);
-      if (VF == VF_KG) s_E2 = fmaR(cp, und, s_E2);
+      const R rl = sP[0][m], ul = sP[1][m], vl = sP[2][m], wl = sP[3][m], pl = sP[4][m], xl = sP[5][m];
+      const R undl = D == 0 ? ul : (D == 1 ? vl : wl);
+      const R unds = und_n + undl;
+      const R a = c * ((me[0] + rl) * unds);
+      s_A += a;
+      s_u = fmaR(a, ul, s_u);
+      s_v = fmaR(a, vl, s_v);
+      s_w = fmaR(a, wl, s_w);
+      s_x = fmaR(a, xl, s_x);
+      if (VF == VF_KG) {
+        const R cp = c * (me[4] + pl);
+        s_p += cp;
+        s_E2 = fmaR(cp, unds, s_E2);
+      } else {
+        s_p = fmaR(c, pl, s_p);
+      }
     };
     partner_loop<GRAD, st>(id, n, base, pair);
     const R q4 = (R)0.25, q8 = (R)0.125, h2 = (R)0.5;
-    acc[0] -= invJ * (q4 * s_fr);
-    acc[1] -= invJ * (q8 * s_m0 + (D == 0 ? h2 * s_p : (R)0));
-    acc[2] -= invJ * (q8 * s_m1 + (D == 1 ? h2 * s_p : (R)0));
-    acc[3] -= invJ * (q8 * s_m2 + (D == 2 ? h2 * s_p : (R)0));
-    acc[4] -= invJ * (q8 * s_E1 + (VF == VF_KG ? q4 * s_E2 : (R)0));
+    R P = s_p;
+    if (VF != VF_KG) {
+      const R rowsum = id == 0 ? wb : (id == N ? -wb : (R)0);
+      P = fmaR(me[4], rowsum, s_p);
+    }
+    acc[0] -= invJ * (q4 * s_A);
+    acc[1] -= invJ * (q8 * fmaR(me[1], s_A, s_u) + (D == 0 ? h2 * P : (R)0));
+    acc[2] -= invJ * (q8 * fmaR(me[2], s_A, s_v) + (D == 1 ? h2 * P : (R)0));
+    acc[3] -= invJ * (q8 * fmaR(me[3], s_A, s_w) + (D == 2 ? h2 * P : (R)0));
+    acc[4] -= invJ * (q8 * fmaR(me[5], s_A, s_x) + (VF == VF_KG ? q4 * s_E2 : (R)0));
   } else if (VF == VF_STD) {
     // F# = (F(a) + F(b))/2 with F_rho = rho u_D, F_m = rho u_D u + p e_D, F_E = rho h u_D
+    // with the node's own terms taken out of the sums (rowsum as above)
     const R mA = me[0] * me[1 + D];
     R s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0, sp = 0;
     auto pair = [&](int l, int m) {
       const R c = crow[l];
       grad_acc(c, m);
-      const R mB = sP[0][m] * sP[1 + D][m];
-      s0 = fmaR(c, mA + mB, s0);
-      s1 = fmaR(c, mA * me[1] + mB * sP[1][m], s1);
-      s2 = fmaR(c, mA * me[2] + mB * sP[2][m], s2);
-      s3 = fmaR(c, mA * me[3] + mB * sP[3][m], s3);
-      sp = fmaR(c, me[4] + sP[4][m], sp);
-      s4 = fmaR(c, mA * me[5] + mB * sP[5][m], s4);
+      const R cB = c * (sP[0][m] * sP[1 + D][m]);
+      s0 += cB;
+      s1 = fmaR(cB, sP[1][m], s1);
+      s2 = fmaR(cB, sP[2][m], s2);
+      s3 = fmaR(cB, sP[3][m], s3);
+      s4 = fmaR(cB, sP[5][m], s4);
+      sp = fmaR(c, sP[4][m], sp);
     };
     partner_loop<GRAD, st>(id, n, base, pair);
+    const R rowsum = id == 0 ? wb : (id == N ? -wb : (R)0);
+    const R mr = mA * rowsum;
+    s0 += mr;
+    s1 = fmaR(mr, me[1], s1);
+    s2 = fmaR(mr, me[2], s2);
+    s3 = fmaR(mr, me[3], s3);
+    s4 = fmaR(mr, me[5], s4);
+    sp = fmaR(me[4], rowsum, sp);
     const R h2 = (R)0.5;
     acc[0] -= invJ * (h2 * s0);
     acc[1] -= invJ * (h2 * (s1 + (D == 0 ? sp : (R)0)));
@@ -656,13 +690,32 @@ struct FaceItem {
   int f, a, d, side, nb, nown, nnb, k1, k2;  // k1, k2: tangential momentum components
 };
 
-__device__ __forceinline__ FaceItem face_item_geometry(const int32_t* nbr, int e, int q) {
+// The six neighbours of an element that is the same for the whole workgroup,
+// read with scalar loads (short latency, no vector memory round trip before
+// the face-state loads that need them); pick() selects face f's.
+struct Nbr6 {
+  int n[6];
+  __device__ __forceinline__ int pick(int f) const {  // selects, not an indexed (scratch) array
+    const bool odd = (f & 1) != 0;
+    const int a01 = odd ? n[1] : n[0], a23 = odd ? n[3] : n[2], a45 = odd ? n[5] : n[4];
+    return f < 2 ? a01 : (f < 4 ? a23 : a45);
+  }
+};
+__device__ __forceinline__ Nbr6 uniform_nbr6(const int32_t* nbr, int e) {
+  const int eu = __builtin_amdgcn_readfirstlane(e);
+  Nbr6 r;
+#pragma unroll
+  for (int f = 0; f < 6; ++f) r.n[f] = nbr[6 * eu + f];
+  return r;
+}
+
+__device__ __forceinline__ FaceItem face_item_geometry_nb(int nb, int q) {
   FaceItem it;
   it.f = q / nf;
   it.a = q - it.f * nf;
   it.d = it.f >> 1;
   it.side = it.f & 1;
-  it.nb = nbr[6 * e + it.f];
+  it.nb = nb;
   const int t1 = it.a % n1, t2 = it.a / n1;
   const int sn = it.d == 0 ? 1 : (it.d == 1 ? n1 : nf);
   const int s1 = it.d == 0 ? n1 : 1;
@@ -673,6 +726,15 @@ __device__ __forceinline__ FaceItem face_item_geometry(const int32_t* nbr, int e
   it.k1 = it.d == 2 ? 1 : it.d + 2;  // 1 + (d+1) % 3
   it.k2 = it.d == 0 ? 3 : it.d;      // 1 + (d+2) % 3
   return it;
+}
+
+__device__ __forceinline__ FaceItem face_item_geometry(const int32_t* nbr, int e, int q) {
+  return face_item_geometry_nb(nbr[6 * e + q / nf], q);
+}
+
+// Face item q of a workgroup-uniform element with neighbours b.
+__device__ __forceinline__ FaceItem face_item_geometry(const Nbr6& b, int q) {
+  return face_item_geometry_nb(b.pick(q / nf), q);
 }
 
 // Conservative state of node n with the momentum rotated to (normal, t1, t2).
@@ -1042,15 +1104,17 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
   const double gm1 = A.gamma - 1.0;
   // Memory round trip 1: neighbour indices of the thread's face items, the
   // node state and the basis.
+  static_assert(EPB == 1, "one element per workgroup: its neighbours are uniform");
+  const Nbr6 nb6 = uniform_nbr6(A.nbr, e);
   FaceData<NS, R, WALL> fd[FI];
 #pragma unroll
   for (int k = 0; k < FI; ++k)
-    if (t + k * TPE < 6 * nf) fd[k].it = face_item_geometry(A.nbr, e, t + k * TPE);
+    if (t + k * TPE < 6 * nf) fd[k].it = face_item_geometry(nb6, t + k * TPE);
   // wall faces of the element (bit f): at most the two normal to wall_dir
   int wmask = 0;
   if (WALL) {
-    const int f0 = 2 * A.wall_dir;
-    wmask = (A.nbr[6 * e + f0] < 0 ? 1 << f0 : 0) | (A.nbr[6 * e + f0 + 1] < 0 ? 2 << f0 : 0);
+#pragma unroll
+    for (int f = 0; f < 6; ++f) wmask |= nb6.n[f] < 0 ? 1 << f : 0;
   }
   const double* Ue = A.U + (size_t)e * 5 * nn;
   double u[5], gprev[5];
@@ -1099,9 +1163,9 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
   if (t < nn) {
     constexpr bool FG = NS && DG_FUSED_GRAD && !BLEND;
     R gs[3][4];
-    volume_dir<VF, 0, R, FG>(sP, sDhat, t, ijk[0], me, invJ[0], (R)gm1, acc, sDw, gs[0]);
-    volume_dir<VF, 1, R, FG>(sP, sDhat, t, ijk[1], me, invJ[1], (R)gm1, acc, sDw, gs[1]);
-    volume_dir<VF, 2, R, FG>(sP, sDhat, t, ijk[2], me, invJ[2], (R)gm1, acc, sDw, gs[2]);
+    volume_dir<VF, 0, R, FG>(sP, sDhat, swinv[0], t, ijk[0], me, invJ[0], (R)gm1, acc, sDw, gs[0]);
+    volume_dir<VF, 1, R, FG>(sP, sDhat, swinv[0], t, ijk[1], me, invJ[1], (R)gm1, acc, sDw, gs[1]);
+    volume_dir<VF, 2, R, FG>(sP, sDhat, swinv[0], t, ijk[2], me, invJ[2], (R)gm1, acc, sDw, gs[2]);
     // advective surface terms
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -1148,7 +1212,7 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
       double m = 0.0;
 #pragma unroll
       for (int f = 0; f < 6; ++f) {
-        const int nb = A.nbr[6 * e + f];
+        const int nb = nb6.n[f];
         if (!WALL || nb >= 0) m = fmax(m, A.alpha1[nb]);  // a wall face spreads nothing
       }
       al = fmax(A.alpha1[e], A.aspread * m);
@@ -1232,7 +1296,13 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
     for (int v = 0; v < 5; ++v) gprev[v] = A.G[(size_t)e * 5 * nn + t + v * nn];
   }
   if (NS && !(BLEND && A.mode == MODE_DIFF)) {  // uniform over the workgroup
-    // viscous divergence: all twelve flux components exchanged through LDS once
+    // viscous divergence: all twelve flux components exchanged through LDS
+    // once; with DG_VDIV_LINES a line pass (one thread per line of each
+    // direction, 3 (N+1)^2 lines) replaces the n1 values of every line and
+    // component by sum_l Dw_il Fv_l, in place (lines of one direction are
+    // disjoint and each direction owns four rows), with the coefficients
+    // uniform over the workgroup; each node then reads its 12 sums, instead
+    // of reading n1 partners and coefficients per component.
     __syncthreads();
     if (t < nn) {
 #pragma unroll
@@ -1241,12 +1311,45 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
         for (int c = 0; c < 4; ++c) sV[4 * d + c][t] = Fv[d][c];
     }
     __syncthreads();
+#if DG_VDIV_LINES
+    // one task per (line, pair of components): 6 (N+1)^2 tasks
+    for (int q = tid; q < 6 * nf; q += PS::NTB) {
+      const int cp = q & 1, ql = q >> 1;
+      const int d = ql / nf, a = ql - d * nf;
+      const int st = d == 0 ? 1 : (d == 1 ? n1 : nf);
+      const int base = face_node(d, 0, a);
+      R* r0 = sV[4 * d + 2 * cp];
+      R* r1 = sV[4 * d + 2 * cp + 1];
+      R v0[n1], v1[n1];
+#pragma unroll
+      for (int l = 0; l < n1; ++l) {
+        v0[l] = r0[base + l * st];
+        v1[l] = r1[base + l * st];
+      }
+#pragma unroll
+      for (int i = 0; i < n1; ++i) {
+        R s0 = 0, s1 = 0;
+#pragma unroll
+        for (int l = 0; l < n1; ++l) {
+          const R c = sDw[i * n1 + l];  // the same address in every lane (broadcast)
+          s0 = fmaR(c, v0[l], s0);
+          s1 = fmaR(c, v1[l], s1);
+        }
+        r0[base + i * st] = s0;
+        r1[base + i * st] = s1;
+      }
+    }
+    __syncthreads();
+#endif
     if (t < nn) {
       const R h2 = (R)0.5;
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        const int st = d == 0 ? 1 : (d == 1 ? n1 : nf);
         const int id = ijk[d];
+#if DG_VDIV_LINES
+        R s0 = sV[4 * d + 0][t], s1 = sV[4 * d + 1][t], s2 = sV[4 * d + 2][t], s3 = sV[4 * d + 3][t];
+#else
+        const int st = d == 0 ? 1 : (d == 1 ? n1 : nf);
         const int base = t - id * st;
         const R* crow = sDw + id * n1;
         R s0 = 0, s1 = 0, s2 = 0, s3 = 0;
@@ -1259,6 +1362,7 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
           s2 = fmaR(c, sV[4 * d + 2][m], s2);
           s3 = fmaR(c, sV[4 * d + 3][m], s3);
         }
+#endif
         const int a = d == 0 ? ijk[1] + n1 * ijk[2] : (d == 1 ? ijk[0] + n1 * ijk[2] : ijk[0] + n1 * ijk[1]);
         if (id == 0 || id == N) {  // F*v = mean with the neighbour's normal viscous flux (sFn)
           const int f = 2 * d + (id == N);
@@ -1461,10 +1565,18 @@ __global__ __launch_bounds__(PL::NTB, PL::FI == 1 && N >= 2 ? 8 : 4) void k_lift
   R (*sQ)[4][nf] = sQAll[sl.s];
   const double gm1 = A.gamma - 1.0;
   // Round trip 1: neighbour indices, node state, basis; round trip 2: face states.
+  // neighbours of the workgroup's elements (scalar loads), then the slot's
+  Nbr6 nbs[EPB];
+#pragma unroll
+  for (int k = 0; k < EPB; ++k) nbs[k] = uniform_nbr6(A.nbr, min(e0 + k, A.nelem - 1));
+  Nbr6 nb6 = nbs[0];
+#pragma unroll
+  for (int k = 1; k < EPB; ++k)
+    if (sl.s == k) nb6 = nbs[k];
   FaceItem its[FI];
 #pragma unroll
   for (int k = 0; k < FI; ++k)
-    if (t + k * TPE < 6 * nf) its[k] = face_item_geometry(A.nbr, e, t + k * TPE);
+    if (t + k * TPE < 6 * nf) its[k] = face_item_geometry(nb6, t + k * TPE);
   const double* Ue = A.U + (size_t)e * 5 * nn;
   double u[5];
   if (t < nn) {
@@ -2863,7 +2975,10 @@ __global__ __launch_bounds__(NT) void k_max_rate(ReduceArgs R) {
         ra = (fabs(vx) + c) * R.invdx[0] + (fabs(vy) + c) * R.invdx[1] + (fabs(vz) + c) * R.invdx[2];
         rv = R.nu_fac * ir * (R.invdx[0] * R.invdx[0] + R.invdx[1] * R.invdx[1] + R.invdx[2] * R.invdx[2]);
       }
-      ma = fmax(ma, ra);
+      // a node that is not finite or has rho <= 0 or p <= 0 makes the rate
+      // infinite (fmax would drop a NaN), so the host reports it
+      const bool ok = u[0] > 0.0 && p > 0.0 && isfinite(ra) && isfinite(rv);
+      ma = fmax(ma, ok ? ra : INFINITY);
       mv = fmax(mv, rv);
     }
   }

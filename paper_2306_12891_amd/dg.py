@@ -16,8 +16,7 @@ import os
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-# DGMI_LIBRARY selects another build of the same library (e.g. a tuning variant).
-LIB_PATH = os.environ.get("DGMI_LIBRARY") or os.path.join(_HERE, "libdgmi.so")
+LIB_PATH = os.path.join(_HERE, "libdgmi.so")
 
 DG_OK, DG_EINVAL, DG_ENOMEM, DG_EHIP, DG_EUNSUPPORTED, DG_ENONFINITE, DG_ESTATE = 0, -1, -2, -3, -4, -5, -6
 EULER, NS = 0, 1
@@ -330,6 +329,9 @@ class DG:
         self._check(lib().dg_node_weights(self._ctx, w))
         out = torch.tensor(list(w), dtype=torch.float64).reshape(n1, n1, n1)
         return out.to(device) if device is not None else out
+
+    def last_error(self) -> str:
+        return lib().dg_last_error(self._ctx).decode()
 
     def raw_call(self, name: str, *args) -> int:
         """Calls a C entry point with this context as first argument (error-path tests)."""

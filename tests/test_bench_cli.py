@@ -26,6 +26,7 @@ def test_workload_tables_are_consistent():
         if name in bench.WALLS or name in bench.MODEL_CS:
             assert eq == 1, name
     assert bench.WORKLOADS["tgv_n5_32"][1] == (32, 32, 32)
+    assert bench.WORKLOADS["tgv_n7_64"][:2] == (7, (64, 64, 64))
     traffic = {k for k in bench.MEASURED_TRAFFIC if k != "kernel_sha"}
     assert traffic <= set(bench.WORKLOADS)
     for k in traffic:

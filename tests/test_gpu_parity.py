@@ -178,9 +178,13 @@ def test_ns_rollout(orc, torch_cuda):
     assert_state_close(Ud.cpu().numpy(), ref)
 
 
-def test_sod_rollout_blended(orc, torch_cuda):
+@pytest.mark.parametrize("N", range(2, 8))
+def test_sod_rollout_blended(orc, torch_cuda, N):
+    """20 blended Runge-Kutta steps of the Sod tube at every degree: the
+    stage kernel's epilogue computes the next stage's indicator (its LDS and
+    wave layout depend on N)."""
     import torch
-    N, nelem, lo, hi = 5, (16, 1, 1), (0, 0, 0), (1.0, 1 / 16, 1 / 16)
+    nelem, lo, hi = (16, 1, 1), (0, 0, 0), (1.0, 1 / 16, 1 / 16)
     s, op = make(orc, N, nelem, lo, hi, blending=1)
     U0 = I.sod(N, nelem, lo, hi)
     Ud = torch.from_numpy(U0).cuda()
@@ -199,6 +203,30 @@ def test_tgv_c2_full_size_single_evaluation(orc, torch_cuda):
     U = I.tgv(N, (n, n, n))
     assert_ut_close(gpu_ut(torch_cuda, op, U), orc.time_derivative(s, U), U, N, (n, n, n), (0, 0, 0),
                     (TWO_PI,) * 3)
+
+
+def test_tgv_c2_full_size_rollout(orc, torch_cuda):
+    """TGV Ma 0.1 Re 1600, N = 5, 32^3 elements (7.1 M nodes), PI + Roe, BR1:
+    10 Runge-Kutta steps of the full mesh (the benchmark's launch
+    configuration, dg_rk_steps) against 10 oracle steps, per variable to
+    1e-12 of max |U_v| (the momentum floor max rho * max c for components
+    that are small at Ma 0.1)."""
+    import torch
+    N, n, steps = 5, 32, 10
+    mu = 1.0 / 1600
+    s, op = make(orc, N, (n, n, n), eq=1, vf=1, sf=1, mu=mu)
+    U0 = I.tgv(N, (n, n, n))
+    Ud = torch.from_numpy(U0).cuda()
+    dt = op.max_dt(Ud, 0.5)
+    assert abs(dt - orc.max_dt(s, U0, 0.5)) <= 1e-14 * dt
+    op.rk_steps(Ud, dt, steps)
+    got = Ud.cpu().numpy()
+    del Ud
+    op.close()
+    ref = orc.rk_steps(s, U0, dt, steps)
+    assert_state_close(got, ref)
+    # the run moved the state by far more than the tolerance
+    assert np.max(np.abs(ref[:, 1] - U0[:, 1])) > 1e-6
 
 
 def test_integrals_alpha_dt_and_conservation(orc, torch_cuda):
@@ -255,3 +283,25 @@ def test_error_paths(orc, torch_cuda):
     op1 = dg.DG((2, 2, 2), 1)
     with pytest.raises(dg.DGError):
         op1.set_options(blending=1)
+
+
+@pytest.mark.parametrize("kind", ["nan", "negative_pressure", "negative_density"])
+def test_max_dt_rejects_bad_node(orc, torch_cuda, kind):
+    """One bad node among valid ones: dg_max_dt returns DG_ENONFINITE (no time
+    step), as does the oracle, instead of a step from the other nodes."""
+    from paper_2306_12891_amd import dg
+    N, nelem = 3, (2, 2, 2)
+    s, op = make(orc, N, nelem, eq=1, vf=1, sf=1, mu=1e-2)
+    U = I.density_wave(N, nelem)
+    if kind == "nan":
+        U[3, 2, 1, 2, 0] = float("nan")
+    elif kind == "negative_pressure":
+        m2 = np.sum(U[5, 1:4, 0, 1, 3] ** 2)
+        U[5, 4, 0, 1, 3] = 0.25 * m2 / U[5, 0, 0, 1, 3]
+    else:
+        U[6, 0, 3, 3, 1] = -0.5
+    with pytest.raises(dg.DGError) as ei:
+        op.max_dt(torch_cuda.from_numpy(U).cuda(), 0.5)
+    assert ei.value.code == dg.DG_ENONFINITE
+    with pytest.raises(ValueError):
+        orc.max_dt(s, U, 0.5)

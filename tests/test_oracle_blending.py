@@ -411,3 +411,31 @@ def test_ns_jvp_through_blending_matches_central_differences(orc, eq):
         _, Jv = orc.jvp(s, U, v)
         fd = (orc.time_derivative(s, U + eps * v) - orc.time_derivative(s, U - eps * v)) / (2 * eps)
         assert np.max(np.abs(fd - Jv)) <= 1e-7 * np.max(np.abs(Jv))
+
+
+@pytest.mark.parametrize("N", [3, 5])
+def test_sharpness_reading(orc, N):
+    """The sharpness s of the sigmoid is a reading (the paper does not print
+    it): s = ln(9999), so that the raw coefficient of a state without top-mode
+    energy is 1e-4.  With alpha_min = 0 and alpha_max = 1 (no cut-off, no
+    clip) the raw sigmoid is observable: E = 0 gives 1e-4, E = T/2 gives
+    1/(1 + 9999^(1/2)), E = T gives 1/2 (E from the independent numpy modal
+    transform)."""
+    x = I.lgl_points(N)
+    X = x[None, None, :] * np.ones((N + 1, N + 1, 1))
+    Y = x[None, :, None] * np.ones((N + 1, 1, N + 1))
+    s = orc.Setup(N=N, nelem=(1, 1, 1), blending=1, alpha_min=0.0, alpha_max=1.0)
+    q = 1.0 + 0.3 * X ** (N - 2) * Y + 0.1 * Y ** (N - 2)
+    E, a1, _ = orc.alpha(s, state_from_q(q, N, 1))
+    assert E[0] < 1e-25 and abs(a1[0] - 1e-4) < 1e-15
+    T = T_paper(N)
+    for frac, expect in ((0.5, 1.0 / (1.0 + 9999.0 ** 0.5)), (1.0, 0.5)):
+        Et = frac * T
+        a = np.sqrt(2 * Et / (1 - Et))
+        q = 1.0 + a * np.sqrt((2 * N + 1) / 2) * leg.legval(X, np.eye(N + 1)[N])
+        EN, _ = modal_energy_fraction(q, N)
+        assert abs(EN - Et) < 1e-14
+        E, a1, _ = orc.alpha(s, state_from_q(q, N, 1))
+        assert abs(E[0] - Et) < 1e-14
+        # the sigmoid's slope s/T turns the 1e-14 error of E into ~s/T * 1e-14 * a(1-a)
+        assert abs(a1[0] - expect) < 1e-9, (frac, a1[0], expect)

@@ -222,3 +222,53 @@ def test_element_subset_equals_full_operator(orc, eq, vf, sf):
     sel = [0, 4, 7, 17, 11]
     part = orc.time_derivative_elems(s, U, sel)
     assert np.array_equal(part, full[sel])
+
+
+@pytest.mark.parametrize("kind", ["nan", "negative_pressure", "negative_density"])
+def test_max_dt_rejects_bad_node(orc, kind):
+    """The time-step estimate refuses a state with one bad node (a NaN, p < 0
+    or rho < 0) instead of returning a step from the other nodes; the valid
+    state gives the closed-form convective step of the density wave,
+    CFL / ((N+1) max sum_d (|u_d| + c)/dx_d) with u = (1, 1, 1), p = 1."""
+    N, nelem = 3, (2, 2, 2)
+    s = orc.Setup(N=N, nelem=nelem)
+    U = I.density_wave(N, nelem)
+    rho = U[:, 0]
+    lam = np.max(3 * (1.0 + np.sqrt(G / rho))) / (2 * np.pi / 2)
+    assert abs(orc.max_dt(s, U, 0.5) - 0.5 / ((N + 1) * lam)) <= 1e-14 * orc.max_dt(s, U, 0.5)
+    if kind == "nan":
+        U[3, 2, 1, 2, 0] = float("nan")
+    elif kind == "negative_pressure":
+        m2 = np.sum(U[5, 1:4, 0, 1, 3] ** 2)
+        U[5, 4, 0, 1, 3] = 0.25 * m2 / U[5, 0, 0, 1, 3]
+    else:
+        U[6, 0, 3, 3, 1] = -0.5
+    with pytest.raises(ValueError):
+        orc.max_dt(s, U, 0.5)
+
+
+@pytest.mark.parametrize("N", [3, 5])
+def test_pressure_rate_pirozzoli_is_gamma_times_kennedy_gruber(orc, N):
+    """Separates the two energy fluxes.  With constant velocity U and pressure
+    P and central interface fluxes both split forms move momentum with the
+    mass (u_t = 0), and their energy fluxes differ only in the internal-energy
+    part: KG carries U_d (P/(gamma-1)) {{rho}}{{1/rho}} (its {{p}}{{u}} term is
+    constant and drops out), PI U_d (gamma P/(gamma-1)) {{rho}}{{1/rho}} (from
+    {{h}}).  The operator maps a constant two-point flux to zero, so the
+    pressure rate p_t = (gamma-1)(E_t - u.m_t + |u|^2 rho_t / 2) of PI is
+    exactly gamma times that of KG at every node (and non-zero: {{rho}}{{1/rho}}
+    is not constant).  Swapping the two energy fluxes gives 1/gamma."""
+    nelem = (2, 2, 2)
+    U = I.density_wave(N, nelem)
+    rates = []
+    for vf in (0, 1):
+        s = orc.Setup(N=N, nelem=nelem, vol_flux=vf, surf_flux=2)
+        Ut = orc.time_derivative(s, U)
+        u = U[:, 1:4] / U[:, 0:1]
+        ut_vel = (Ut[:, 1:4] - u * Ut[:, 0:1]) / U[:, 0:1]
+        assert np.max(np.abs(ut_vel)) < 1e-12 * np.max(np.abs(Ut[:, 1:4]))
+        rates.append((G - 1) * (Ut[:, 4] - np.sum(u * Ut[:, 1:4], 1) + 0.5 * np.sum(u * u, 1) * Ut[:, 0]))
+    kg, pi = rates
+    scale = np.max(np.abs(kg))
+    assert scale > 1e-3
+    assert np.max(np.abs(pi - G * kg)) < 1e-12 * G * scale
