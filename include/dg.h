@@ -255,6 +255,23 @@ int dg_rk_steps(dg_ctx* ctx, double* U, double dt, int nsteps);
  * on first use. */
 int dg_vjp(dg_ctx* ctx, const double* U, const double* Ut_bar, double* U_bar);
 
+/* dg_vjp for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same product with the same kernels, bitwise equal to dg_vjp, but its
+ * reverse-mode buffers (the face buffer of gradient cotangents for DG_NS, and
+ * with blending U_t^FV - U_t^DG and the cotangent of the blending
+ * coefficient) are carved from a fixed 64 MiB device array of the library
+ * (one per GPU, held until the process ends; its address is looked up in
+ * dg_init) instead of being allocated on first use.  The call itself
+ * allocates nothing.  Limit: nElems * (6 * 4 * (N+1)^2 [DG_NS] + 5 (N+1)^3 + 1
+ * [blending]) doubles must fit in 64 MiB (e.g. 2.8 M nodes of DG_NS without
+ * blending); larger meshes return DG_EINVAL with the required size.  Every
+ * entry of the array is written before it is read in a call, so nothing needs
+ * clearing; calls that overlap on one GPU (several contexts or streams at
+ * once) race on the array.  Errors as dg_vjp, DG_EHIP if the array's address
+ * could not be obtained. */
+int dg_vjp_noalloc(dg_ctx* ctx, const double* U, const double* Ut_bar, double* U_bar);
+
 /* Vector-Jacobian product of one rk_step (the step of Sec. 2, eq. (pid), with
  * the 2N-storage coefficients of rk_step): U_bar_n = (dU_{n+1}/dU_n)^T
  * U_bar_np1, with U_n the state before the step.  All three arrays are

@@ -71,6 +71,7 @@ int main() {
   EXPECT(rk_step(nullptr, nullptr, 1e-3) == DG_EINVAL);
   EXPECT(dg_rk_steps(nullptr, nullptr, 1e-3, 1) == DG_EINVAL);
   EXPECT(dg_vjp(nullptr, nullptr, nullptr, nullptr) == DG_EINVAL);
+  EXPECT(dg_vjp_noalloc(nullptr, nullptr, nullptr, nullptr) == DG_EINVAL);
   EXPECT(rk_step_vjp(nullptr, nullptr, 1e-3, nullptr, nullptr) == DG_EINVAL);
   EXPECT(rk_step_record(nullptr, nullptr, 1e-3, nullptr) == DG_EINVAL);
   EXPECT(rk_step_vjp_recorded(nullptr, nullptr, 1e-3, nullptr, nullptr) == DG_EINVAL);

@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -16,6 +17,13 @@
 #include "dg_internal.hpp"
 
 using namespace dgmi;
+
+// Device scratch of dg_vjp_noalloc: a file-scope array instead of allocations,
+// for callers that cannot allocate device memory.  Every GPU the library runs
+// on holds its own copy until the process ends; host code reaches it only
+// through the address hipGetSymbolAddress returns for the current device
+// (kept per device in g_scratch), never through the array's name.
+static __device__ __align__(256) double scratch[(size_t(64) << 20) / sizeof(double)];
 
 namespace {
 
@@ -30,6 +38,12 @@ const double kB[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612
                       2277821191437.0 / 14882151754819.0};
 
 char g_init_error[256] = "";
+
+constexpr size_t kScratchBytes = size_t(64) << 20;  // the scratch array below
+constexpr int kMaxDevices = 64;
+void* g_scratch[kMaxDevices] = {};
+std::mutex g_scratch_mutex;
+static_assert(sizeof(scratch) == kScratchBytes, "scratch size");
 
 const KernelTable* table_for(int N) {
   switch (N) {
@@ -194,6 +208,9 @@ struct dg_ctx {
   // reverse mode through the blending: U_t^FV - U_t^DG and the cotangent of alpha
   double* Dfd = nullptr;
   double* abar = nullptr;
+  // this device's copy of the file-scope scratch (dg_vjp_noalloc), or NULL
+  // when its address could not be obtained
+  char* scratch = nullptr;
   char err[256] = "";
   // kernel timing (dg_set_profiling)
   int profiling = 0;
@@ -705,6 +722,15 @@ int dg_init(const dg_mesh* mesh, int N, double gamma, double mu, dg_ctx** out) {
     delete c;
     return oom ? DG_ENOMEM : DG_EHIP;
   }
+  if (c->device >= 0 && c->device < kMaxDevices) {  // with the device current (dg_init's)
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch[c->device]) {
+      void* p = nullptr;
+      if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess) g_scratch[c->device] = p;
+      else (void)hipGetLastError();
+    }
+    c->scratch = static_cast<char*>(g_scratch[c->device]);
+  }
   *out = c;
   return DG_OK;
 }
@@ -925,6 +951,30 @@ int dg_vjp(dg_ctx* c, const double* U, const double* Ut_bar, double* U_bar) {
   int rc = vjp_supported(c);
   if (rc) return rc;
   return run_vjp(c, U, Ut_bar, U_bar, nullptr);
+}
+
+int dg_vjp_noalloc(dg_ctx* c, const double* U, const double* Ut_bar, double* U_bar) {
+  if (check_ctx(c)) return DG_EINVAL;
+  if (!is_device_ptr(U) || !is_device_ptr(Ut_bar) || !is_device_ptr(U_bar))
+    return fail(c, DG_EINVAL, "dg_vjp_noalloc: device pointers required");
+  if ((const void*)U_bar == (const void*)U || (const void*)U_bar == (const void*)Ut_bar)
+    return fail(c, DG_EINVAL, "dg_vjp_noalloc: U_bar must not alias U or Ut_bar");
+  int rc = vjp_supported(c);
+  if (rc) return rc;
+  if (!c->scratch) return fail(c, DG_EHIP, "dg_vjp_noalloc: no device scratch on this device");
+  // the reverse-mode buffers carved from the scratch, 256-byte aligned
+  auto round = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t b_gbf = c->opt.equations == DG_NS ? round((size_t)c->nelem * 6 * 4 * c->nf * sizeof(double)) : 0;
+  const size_t b_dfd = c->opt.blending ? round(c->nstate * sizeof(double)) : 0;
+  const size_t b_abar = c->opt.blending ? round((size_t)c->nelem * sizeof(double)) : 0;
+  if (b_gbf + b_dfd + b_abar > kScratchBytes)
+    return fail(c, DG_EINVAL, "dg_vjp_noalloc: the mesh needs %zu bytes of scratch, at most %zu are available",
+                b_gbf + b_dfd + b_abar, kScratchBytes);
+  char* p = c->scratch;
+  double* Gbf = b_gbf ? reinterpret_cast<double*>(p) : nullptr;
+  double* Dfd = b_dfd ? reinterpret_cast<double*>(p + b_gbf) : nullptr;
+  double* abar = b_abar ? reinterpret_cast<double*>(p + b_gbf + b_dfd) : nullptr;
+  return run_vjp_buffers(c, U, Ut_bar, U_bar, nullptr, Gbf, Dfd, abar);
 }
 
 }  // extern "C"

@@ -30,7 +30,7 @@ EXPORTS = ["dg_default_options", "dg_init", "dg_set_options", "dg_get_options", 
            "dg_time_derivative", "rk_step", "dg_rk_steps", "dg_vjp", "rk_step_vjp", "dg_max_dt",
            "dg_integrals", "dg_alpha", "dg_check_finite", "dg_set_profiling", "dg_profile_read", "dg_node_weights",
            "dg_sizes", "dg_finalize", "dg_last_error", "dg_set_cs_field", "dg_set_geometry",
-           "dg_set_connectivity", "dg_set_wall_model", "rk_step_record", "rk_step_vjp_recorded"]
+           "dg_set_connectivity", "dg_set_wall_model", "rk_step_record", "rk_step_vjp_recorded", "dg_vjp_noalloc"]
 
 
 class DGError(RuntimeError):
@@ -73,6 +73,7 @@ def lib() -> ctypes.CDLL:
             "rk_step": ([P, P, D], I),
             "dg_rk_steps": ([P, P, D, I], I),
             "dg_vjp": ([P, P, P, P], I),
+            "dg_vjp_noalloc": ([P, P, P, P], I),
             "rk_step_vjp": ([P, P, D, P, P], I),
             "dg_max_dt": ([P, P, D, P], I),
             "dg_integrals": ([P, P, P], I),
@@ -241,6 +242,14 @@ class DG:
         po = self._state(out, "U_bar")
         self._stream()
         self._check(lib().dg_vjp(self._ctx, ctypes.c_void_p(pu), ctypes.c_void_p(pb), ctypes.c_void_p(po)))
+        return out
+
+    def vjp_noalloc(self, U: torch.Tensor, Ut_bar: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
+        """dg_vjp_noalloc: the reverse product into the caller's `out`, with
+        the library's fixed device scratch (no allocation in the call)."""
+        pu, pb, po = self._state(U, "U"), self._state(Ut_bar, "Ut_bar"), self._state(out, "U_bar")
+        self._stream()
+        self._check(lib().dg_vjp_noalloc(self._ctx, ctypes.c_void_p(pu), ctypes.c_void_p(pb), ctypes.c_void_p(po)))
         return out
 
     def rk_step_vjp(self, U_n: torch.Tensor, dt: float, U_bar_np1: torch.Tensor,
