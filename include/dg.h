@@ -74,6 +74,19 @@ enum { DG_SF_LLF = 0, DG_SF_ROE = 1, DG_SF_CENTRAL = 2 };
 enum { DG_IND_HENNEMANN = 0, DG_IND_PERSSON = 1 };
 enum { DG_FV_FIRST = 0, DG_FV_MINMOD = 1 };
 enum { DG_FP64 = 0, DG_MIXED = 1 };
+/* BR1 lifting of the Navier-Stokes operator (the standard choice for the
+ * gradients, which the paper leaves open: the lifted gradient takes the
+ * interface values q* = (q- + q+)/2 of the primitive variables q = (u, v, w,
+ * p/rho) on every face).
+ *   TWO_PASS: every stage first lifts the normal viscous flux at all face
+ *     nodes (one kernel), then evaluates the operator.
+ *   SPLIT: the same operator up to rounding, with the lifting split into each
+ *     element's own half of q*, which the stage kernel of a Runge-Kutta stage
+ *     writes for the next stage, and the rest, which the stage kernel adds
+ *     where it reads the neighbour's face data; a step lifts only before its
+ *     first stage.  Applies to the FP64 operator without the eddy viscosity,
+ *     blending, walls or curved geometry; elsewhere TWO_PASS runs. */
+enum { DG_LIFT_TWO_PASS = 0, DG_LIFT_SPLIT = 1 };
 
 typedef struct dg_ctx dg_ctx; /* opaque, library-owned */
 
@@ -92,7 +105,7 @@ typedef struct {
   int32_t indicator;    /* DG_IND_HENNEMANN | DG_IND_PERSSON         (HENNEMANN) */
   int32_t fv_recon;     /* DG_FV_FIRST | DG_FV_MINMOD                (MINMOD)  */
   int32_t precision;    /* DG_FP64 | DG_MIXED                        (FP64)    */
-  int32_t reserved;
+  int32_t lifting;      /* DG_LIFT_*                                 (SPLIT)   */
   double Pr;            /* Prandtl number                            (0.72)    */
   double alpha_min;     /* below: pure DG (paper Sec. 4.2)           (0.01)    */
   double alpha_max;     /* upper clip (paper Sec. 4.2)               (0.7)     */

@@ -42,6 +42,7 @@ int main() {
   dg_options opt;
   dg_default_options(&opt);
   EXPECT(opt.equations == DG_EULER && opt.alpha_min == 0.01 && opt.alpha_max == 0.7 && opt.alpha_spread == 0.5);
+  EXPECT(opt.lifting == DG_LIFT_SPLIT);
   dg_ctx* c = nullptr;
   dg_mesh m = box(2, 2, 2);
   // dg_init argument checks (no allocation happens for any of them)
@@ -110,6 +111,9 @@ int main() {
     EXPECT(dg_set_connectivity(c, conn.data()) == DG_EINVAL);
     dg_options o = opt;
     o.Cs = -1.0;
+    EXPECT(dg_set_options(c, &o) == DG_EINVAL);
+    o = opt;
+    o.lifting = 2;
     EXPECT(dg_set_options(c, &o) == DG_EINVAL);
     EXPECT(dg_sizes(c, &a, &b) == DG_OK && a == 6 && b == (N + 1) * (N + 1) * (N + 1));
     EXPECT(dg_finalize(c) == DG_OK);

@@ -189,6 +189,7 @@ struct dg_ctx {
   double* alpha1b = nullptr;  // the other of the pair the fused indicator ping-pongs
   double* alpha = nullptr;
   double* Fvf = nullptr;
+  double* Fvf2 = nullptr;  // split BR1: the own part of the next stage state (allocated on first use)
   double* cs_field = nullptr;  // per-element Smagorinsky coefficients (dg_set_cs_field)
   int has_cs_field = 0;
   double* M = nullptr;         // curved mesh metrics [nelem][10][nn] (dg_set_geometry), NULL: box
@@ -256,6 +257,7 @@ void release(dg_ctx* c) {
   hipFree(c->alpha1b);
   hipFree(c->alpha);
   hipFree(c->Fvf);
+  hipFree(c->Fvf2);
   hipFree(c->cs_field);
   hipFree(c->M);
   hipFree(c->d2e);
@@ -366,11 +368,40 @@ hipError_t timed(dg_ctx* c, int kind, F&& launch) {
   return e;
 }
 
+// Split BR1 (see StageArgs.split): used for the FP64 Navier-Stokes operator
+// without the eddy viscosity, blending, walls or curved geometry when the
+// options ask for it.
+bool split_on(const dg_ctx* c) {
+  return c->opt.lifting == DG_LIFT_SPLIT && eq_code(c) == 1 && c->opt.precision == DG_FP64 && !c->opt.blending &&
+         c->wall_dir < 0 && !c->M && !c->conn;
+}
+
+// Chaining of the split lifting through the stages of one Runge-Kutta step:
+// CHAIN_IN: c->Fvf already holds the own part of X_in (the previous stage
+// wrote it), so no lifting launch; CHAIN_OUT: the stage kernel writes the own
+// part of X_out for the next stage.  Ignored unless split_on.
+enum { CHAIN_IN = 1, CHAIN_OUT = 2 };
+
+// Chain flags of stage k of a step whose last stage that chains is klast.
+int chain_flags(int k, int klast) { return (k > 0 ? CHAIN_IN : 0) | (k < klast ? CHAIN_OUT : 0); }
+
+int ensure_split_buffer(dg_ctx* c) {
+  if (!split_on(c) || c->Fvf2) return DG_OK;
+  const hipError_t e = hipMalloc((void**)&c->Fvf2, (size_t)c->nelem * 6 * 4 * c->nf * sizeof(double));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    c->Fvf2 = nullptr;
+    return fail(c, (e == hipErrorOutOfMemory) ? DG_ENOMEM : DG_EHIP, "split lifting buffer: %s", hipGetErrorString(e));
+  }
+  return DG_OK;
+}
+
 // One evaluation of the operator on X_in: [indicator], [BR1 lifting], stage.
 // alpha1_next (blending, MODE_RK): the stage kernel writes the coefficients of
 // X_out there, and the indicator of X_in is taken as already in c->alpha1.
+// chain: CHAIN_* flags (split BR1, MODE_RK; needs ensure_split_buffer).
 int run_stage(dg_ctx* c, const double* Xin, double* Xout, double* Ut, int mode, double A, double Bdt, int writeG,
-              double* alpha_out, double* alpha1_next = nullptr) {
+              double* alpha_out, double* alpha1_next = nullptr, int chain = 0) {
   StageArgs a = stage_args(c);
   a.U = Xin;
   a.Uout = Xout;
@@ -402,7 +433,14 @@ int run_stage(dg_ctx* c, const double* Xin, double* Xout, double* Ut, int mode, 
     return DG_OK;
   }
   const bool mixed = c->opt.precision == DG_MIXED;
-  if (eq >= 1) {
+  const bool split = split_on(c);
+  if (!split || mode != MODE_RK) chain = 0;
+  if (split) {
+    a.split = 1;
+    if ((chain & CHAIN_OUT) && !c->Fvf2) return fail(c, DG_ESTATE, "split lifting buffer missing");
+    a.Fvf_next = (chain & CHAIN_OUT) ? c->Fvf2 : nullptr;
+  }
+  if (eq >= 1 && !(chain & CHAIN_IN)) {
     e = timed(c, DG_K_LIFT,
               [&] { return mixed ? c->kt->lift_mixed(a, eq, c->stream) : c->kt->lift(a, eq, c->stream); });
     if (e != hipSuccess) return hip_fail(c, e, "lifting kernel");
@@ -414,6 +452,7 @@ int run_stage(dg_ctx* c, const double* Xin, double* Xout, double* Ut, int mode, 
   e = timed(c, DG_K_STAGE,
             [&] { return mixed ? c->kt->stage_mixed(a, eq, c->stream) : c->kt->stage(a, eq, c->stream); });
   if (e != hipSuccess) return hip_fail(c, e, "stage kernel");
+  if (a.Fvf_next) std::swap(c->Fvf, c->Fvf2);  // the own part of X_out is now c->Fvf
   return DG_OK;
 }
 
@@ -638,6 +677,7 @@ void dg_default_options(dg_options* o) {
   o->indicator = DG_IND_HENNEMANN;
   o->fv_recon = DG_FV_MINMOD;
   o->precision = DG_FP64;
+  o->lifting = DG_LIFT_SPLIT;
   o->Pr = 0.72;
   o->alpha_min = 0.01;
   o->alpha_max = 0.7;
@@ -743,6 +783,7 @@ int dg_set_options(dg_ctx* c, const dg_options* o) {
   if (o->indicator < 0 || o->indicator > 1) return fail(c, DG_EINVAL, "dg_set_options: indicator");
   if (o->fv_recon < 0 || o->fv_recon > 1) return fail(c, DG_EINVAL, "dg_set_options: fv_recon");
   if (o->precision < 0 || o->precision > 1) return fail(c, DG_EINVAL, "dg_set_options: precision");
+  if (o->lifting < 0 || o->lifting > 1) return fail(c, DG_EINVAL, "dg_set_options: lifting");
   if (!finite_pos(o->Pr)) return fail(c, DG_EINVAL, "dg_set_options: Pr must be > 0");
   if (!(o->alpha_min >= 0.0 && o->alpha_min <= o->alpha_max && o->alpha_max <= 1.0) ||
       !(o->alpha_spread >= 0.0 && o->alpha_spread <= 1.0))
@@ -912,6 +953,7 @@ int dg_rk_steps(dg_ctx* c, double* U, double dt, int nsteps) {
   if (!is_device_ptr(U)) return fail(c, DG_EINVAL, "rk_step: U must be a device pointer");
   if (!finite_pos(dt)) return fail(c, DG_EINVAL, "rk_step: dt must be finite and > 0");
   if (nsteps < 0) return fail(c, DG_EINVAL, "rk_step: nsteps < 0");
+  if (const int rc = ensure_split_buffer(c)) return rc;
   double* cur = U;
   // blended Euler operator: the indicator of the start state once, then each
   // stage kernel writes that of its output for the next stage (alpha1 /
@@ -927,8 +969,10 @@ int dg_rk_steps(dg_ctx* c, double* U, double dt, int nsteps) {
     for (int k = 0; k < 5; ++k) {
       double* nxt = (cur == U) ? c->U2 : U;
       const int writeG = (k < 4) ? 1 : 0;  // the last stage's register is never read again
+      // every step starts from a lifting of its start state, so that n steps
+      // in one call and n calls of one step agree bitwise
       const int rc = run_stage(c, cur, nxt, nullptr, MODE_RK, kA[k], kB[k] * dt, writeG, nullptr,
-                               fuse ? c->alpha1b : nullptr);
+                               fuse ? c->alpha1b : nullptr, chain_flags(k, 4));
       if (rc) return rc;
       if (fuse) std::swap(c->alpha1, c->alpha1b);
       cur = nxt;
@@ -1012,13 +1056,15 @@ int rk_step_record(dg_ctx* c, double* U, double dt, double* Y) {
   if (!finite_pos(dt)) return fail(c, DG_EINVAL, "rk_step_record: dt must be finite and > 0");
   const size_t n = c->nstate;
   if (overlaps(U, n, Y, 5 * n)) return fail(c, DG_EINVAL, "rk_step_record: Y overlaps U");
+  if (const int rc = ensure_split_buffer(c)) return rc;
   hipError_t e = hipMemcpyAsync(Y, U, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "rk_step_record copy");
   for (int k = 0; k < 4; ++k) {
-    const int rc = run_stage(c, Y + k * n, Y + (k + 1) * n, nullptr, MODE_RK, kA[k], kB[k] * dt, 1, nullptr);
+    const int rc = run_stage(c, Y + k * n, Y + (k + 1) * n, nullptr, MODE_RK, kA[k], kB[k] * dt, 1, nullptr, nullptr,
+                             chain_flags(k, 4));
     if (rc) return rc;
   }
-  return run_stage(c, Y + 4 * n, U, nullptr, MODE_RK, kA[4], kB[4] * dt, 0, nullptr);
+  return run_stage(c, Y + 4 * n, U, nullptr, MODE_RK, kA[4], kB[4] * dt, 0, nullptr, nullptr, chain_flags(4, 4));
 }
 
 int rk_step_vjp_recorded(dg_ctx* c, const double* Y, double dt, const double* U_bar_np1, double* U_bar_n) {
@@ -1045,12 +1091,15 @@ int rk_step_vjp(dg_ctx* c, const double* U_n, double dt, const double* U_bar_np1
   int rc = vjp_supported(c);
   if (rc) return rc;
   if ((rc = ensure_reverse_buffers(c, true))) return rc;
+  if ((rc = ensure_split_buffer(c))) return rc;
   const size_t bytes = c->nstate * sizeof(double);
   hipError_t e = hipMemcpyAsync(c->Y[0], U_n, bytes, hipMemcpyDeviceToDevice, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "rk_step_vjp copy");
   // forward: stage states Y_1..Y_4 (Y_5 = U_{n+1} is not needed)
   for (int k = 0; k < 4; ++k)
-    if ((rc = run_stage(c, c->Y[k], c->Y[k + 1], nullptr, MODE_RK, kA[k], kB[k] * dt, 1, nullptr))) return rc;
+    if ((rc = run_stage(c, c->Y[k], c->Y[k + 1], nullptr, MODE_RK, kA[k], kB[k] * dt, 1, nullptr, nullptr,
+                        chain_flags(k, 3))))
+      return rc;
   const double* Ys[5] = {c->Y[0], c->Y[1], c->Y[2], c->Y[3], c->Y[4]};
   return rk_reverse(c, Ys, dt, U_bar_np1, U_bar_n, "rk_step_vjp");
 }

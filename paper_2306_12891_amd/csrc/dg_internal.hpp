@@ -66,6 +66,19 @@ struct StageArgs {
   // first-stage coefficient of its output state per element here (NULL: not;
   // only where KernelTable.fused_alpha1 is set)
   double* alpha1_next;
+  // Split BR1 (FP64 Navier-Stokes without the eddy viscosity, walls or
+  // blending, on the box): split != 0 makes Fvf hold each element's "own
+  // part" of its normal viscous flux at its face nodes -- the flux of the
+  // lifted gradient whose interface values q* = (q- + q+)/2 keep only the
+  // element's own half -- and the stage kernel adds the neighbour-dependent
+  // rest itself (it is linear in the other halves: the own element's face
+  // values and, at the face's edges, those of the diagonal elements).  In
+  // MODE_RK the stage kernel then also writes the own part of its output
+  // state into Fvf_next (NULL: not), so that a Runge-Kutta run needs the
+  // lifting kernel only before its first stage.  The lifting kernel with
+  // split != 0 writes the own part.
+  double* Fvf_next;
+  int split;
 };
 
 struct ReduceArgs {

@@ -893,16 +893,121 @@ __device__ __forceinline__ Slot slot_of_thread(int e0, int nelem) {
 // rotated states and (Navier-Stokes) the neighbour's normal viscous flux.
 // At a wall (WALL variant, neighbour -1) fn is the wall-model flux, read from
 // the element's own slot of the wall face.
-template <bool NS, class R, bool WALL = false>
+// Split BR1 (StageArgs.split): at a face node of the element's face f (normal
+// direction d, side s), the neighbour n's lifted gradient differs from its own
+// part (the one n's Fvf holds) by the other halves of the interface values at
+// that node: across the shared face the element's own q (normal derivative,
+// weight c_d), and across n's lateral faces where the node lies on an edge
+// of the face, the q of the diagonal element (n's neighbour there; weight
+// c_g).  The diagonal elements and their nodes follow from the element's
+// coordinates on the structured periodic box; each edge face item loads the
+// density and momenta of its one or two diagonal nodes with the face states.
+struct Lateral {
+  int dir, side;  // n's lateral face (direction, side) through the node
+};
+template <bool SPLIT>
+struct SplitLoads {
+  int nlat = 0;
+  Lateral lat[2];
+  double dg[2][3];  // rho, m_d, m_dg of the diagonal nodes (d: the face normal)
+};
+template <>
+struct SplitLoads<false> {};
+
+// The (up to two) lateral faces of the neighbour across face item it, and the
+// loads of the diagonal nodes (coordinates ec of the element, box ne).
+__device__ __forceinline__ void split_issue(const StageArgs& A, const FaceItem& it, const int ec[3],
+                                            SplitLoads<true>& sp) {
+  const int da = it.d == 0 ? 1 : 0, db = it.d == 2 ? 1 : 2;  // tangential directions, t1 along da
+  const int t1 = it.a % n1, t2 = it.a / n1;
+  // slots filled with fixed indices (selects, no indexed scratch array)
+  const bool e1 = t1 == 0 || t1 == N, e2 = t2 == 0 || t2 == N;
+  sp.nlat = (e1 ? 1 : 0) + (e2 ? 1 : 0);
+  sp.lat[0] = Lateral{e1 ? da : db, e1 ? (t1 == N ? 1 : 0) : (t2 == N ? 1 : 0)};
+  sp.lat[1] = Lateral{db, t2 == N ? 1 : 0};
+  const int tpos[2] = {e1 ? t2 : t1, t1};
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    if (j >= sp.nlat) break;
+    const int dg = sp.lat[j].dir, sg = sp.lat[j].side;
+    int c[3] = {ec[0], ec[1], ec[2]}, ix[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int nq = A.ne[q];
+      const int step = (q == it.d) ? (it.side ? 1 : -1) : ((q == dg) ? (sg ? 1 : -1) : 0);
+      int v = c[q] + step;
+      v = v < 0 ? v + nq : (v >= nq ? v - nq : v);
+      c[q] = v;
+      ix[q] = (q == it.d) ? (it.side ? 0 : N) : ((q == dg) ? (sg ? 0 : N) : tpos[j]);
+    }
+    const size_t diag = (size_t)c[0] + (size_t)A.ne[0] * ((size_t)c[1] + (size_t)A.ne[1] * c[2]);
+    const int node = ix[0] + n1 * ix[1] + nf * ix[2];
+    const double* Ud = A.U + diag * 5 * nn + node;
+    sp.dg[j][0] = Ud[0];
+    sp.dg[j][1] = Ud[(1 + it.d) * nn];
+    sp.dg[j][2] = Ud[(1 + dg) * nn];
+  }
+}
+
+__device__ __forceinline__ double pick3(const double v[3], int d) { return d == 0 ? v[0] : (d == 1 ? v[1] : v[2]); }
+
+template <class R>
+__device__ __forceinline__ void viscous_flux_rt(int d, const R g[3][4], R vx, R vy, R vz, R mu, R kappa, R F[4]) {
+  if (d == 0) viscous_flux<0, R>(g, vx, vy, vz, mu, kappa, F);
+  else if (d == 1) viscous_flux<1, R>(g, vx, vy, vz, mu, kappa, F);
+  else viscous_flux<2, R>(g, vx, vy, vz, mu, kappa, F);
+}
+
+// The neighbour-dependent rest of the neighbour's normal viscous flux at face
+// item it (split BR1), added to fn: the viscous flux (linear in the gradient
+// for constant viscosity) of the gradient made of the other halves, with the
+// neighbour's velocity at the node, written out for its few non-zero terms in
+// the face frame (n, t1, t2) and turned back with selects.  own / nb: the
+// element's and the neighbour's face states (rotated frame, FP64).
+//   normal half g_d = c_d q_e:   tau_nn = 4/3 mu c_d u_n,e, tau_tn = mu c_d u_t,e;
+//   lateral half g_dg = c_g u_g: tau_dg,n += mu c_g u_n,g, tau_nn -= 2/3 mu c_g u_dg,g;
+//   F_E = u_nb . tau_n + kappa c_d theta_e.
+__device__ __forceinline__ void split_rest(const StageArgs& A, const FaceItem& it, const State64& own,
+                                           const State64& nb, const SplitLoads<true>& sp, double fn[4]) {
+  const double hw = 0.5 * A.basis[BL.winv()];  // (1/w_0) / 2, w_0 = w_N
+  const double mu = A.mu;
+  const double cd = pick3(A.invJ, it.d) * (it.side ? -hw : hw);
+  double tnn = (4.0 / 3.0) * mu * cd * own.un;
+  double t1 = mu * cd * own.u1, t2 = mu * cd * own.u2;
+  double fe = A.kappa * cd * own.p * own.ir;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    if (j >= sp.nlat) break;
+    const int dg = sp.lat[j].dir;
+    const double cg = pick3(A.invJ, dg) * (sp.lat[j].side ? hw : -hw) * rcp64(sp.dg[j][0]);
+    const double sh = mu * cg * sp.dg[j][1];                    // tau_dg,n
+    const double dv = (2.0 / 3.0) * mu * cg * sp.dg[j][2];     // from the divergence
+    tnn -= dv;
+    const bool first = dg == (it.d == 2 ? 0 : it.d + 1);        // dg is the t1 direction
+    if (first) t1 += sh;
+    else t2 += sh;
+  }
+  fe += nb.un * tnn + nb.u1 * t1 + nb.u2 * t2;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) fn[c] += c == it.d ? tnn : (c == it.k1 - 1 ? t1 : t2);
+  fn[3] += fe;
+}
+
+template <bool NS, class R, bool WALL = false, bool SPLIT = false>
 struct FaceData {
   FaceItem it;
   double L[5], R_[5];
   R fn[4];
+  SplitLoads<SPLIT> sp;
 };
 
-template <bool NS, class R, bool WALL = false>
-__device__ __forceinline__ void face_issue(const StageArgs& A, int e, FaceData<NS, R, WALL>& fd) {
+template <bool NS, class R, bool WALL = false, bool SPLIT = false>
+__device__ __forceinline__ void face_issue(const StageArgs& A, int e, FaceData<NS, R, WALL, SPLIT>& fd,
+                                           const int* ec = nullptr) {
   const FaceItem& it = fd.it;
+  if constexpr (SPLIT) {
+    split_issue(A, it, ec, fd.sp);
+  }
   if (WALL && it.nb < 0) {
     wall_face_loads(A.U, e, it, fd.L, fd.R_);
     const R* Fn = reinterpret_cast<const R*>(A.Fvf) + ((size_t)e * 6 + it.f) * 4 * nf + it.a;
@@ -928,15 +1033,22 @@ __device__ __forceinline__ void store_q(const FaceItem& it, const R qs[4], R (*s
 
 // Interface values of a face item into LDS: advective f*, and for
 // Navier-Stokes q* = (q- + q+)/2 and the neighbour's normal viscous flux.
-template <int VF, bool NS, class R, bool MX, bool WALL = false>
-__device__ __forceinline__ void face_item(const StageArgs& A, const FaceData<NS, R, WALL>& fd, const Ref& ref,
+template <int VF, bool NS, class R, bool MX, bool WALL = false, bool SPLIT = false>
+__device__ __forceinline__ void face_item(const StageArgs& A, const FaceData<NS, R, WALL, SPLIT>& fd, const Ref& ref,
                                           R (*sF)[5][nf], R (*sQ)[4][nf], R (*sFn)[4][nf]) {
   const FaceItem& it = fd.it;
-  if (NS) {
-#pragma unroll
-    for (int c = 0; c < 4; ++c) sFn[it.f][c][it.a] = fd.fn[c];
-  }
   const State64 sL = state64<0>(fd.L, A.gamma - 1.0), sR = state64<0>(fd.R_, A.gamma - 1.0);
+  if (NS) {
+    R fn[4] = {fd.fn[0], fd.fn[1], fd.fn[2], fd.fn[3]};
+    if constexpr (SPLIT) {
+      static_assert(sizeof(R) == 8, "split BR1: FP64");
+      __builtin_amdgcn_sched_barrier(0);
+      split_rest(A, it, it.side ? sL : sR, it.side ? sR : sL, fd.sp, fn);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) sFn[it.f][c][it.a] = fn[c];
+  }
   const Jumps<R> J = jumps<R, MX>(sL, sR, A.gamma, ref, A.sf);
   R g[5];
   riemann_rot<VF, R>(A.sf, to_rot<R, MX>(sL, ref), to_rot<R, MX>(sR, ref), J, (R)A.gamma, g);
@@ -1067,9 +1179,125 @@ __device__ __forceinline__ void node_viscous_flux(const StageArgs& A, int e, con
   viscous_flux<2, R>(g, me[1], me[2], me[3], mu, kap, Fv[2]);
 }
 
+__device__ __forceinline__ int axis_stride(int j) { return j == 0 ? 1 : (j == 1 ? n1 : nf); }
+
+// Split BR1: the own part of the normal viscous flux at every face node of
+// the element (into Fout, laid out as StageArgs.Fvf), from sq = (u, v, w,
+// theta) at its nodes (LDS), by lines rather than one face node at a time:
+//   pass 1: each normal line (3 nf of them) gives the derivatives of
+//     (u, v, w, theta) along it at both end nodes, and each line of a face
+//     plane along one of the plane's axes j (6 faces x 2 axes x n1 lines,
+//     two tasks per line that split its nodes, so that the tasks' work is
+//     about even) those of u_d and u_j (d: the face normal) at its nodes,
+//     into the LDS scratch sW (48 nf doubles);
+//   pass 2: each face node forms its flux from these and its velocity.
+// Each line's values are read from LDS once; the differentiation matrix comes
+// with uniform loads from the constant address space.  The interface values
+// are the node's own half, q / 2, as in the lifting kernel's split mode.  The
+// caller synchronises the workgroup before (sq written, sW free); the
+// function synchronises between the passes.
+using cdouble_ptr = const double __attribute__((address_space(4)))*;
+template <int TPE>
+__device__ __forceinline__ void own_part_by_lines(const StageArgs& A, int e, int t, const double (*sq)[nn], double* sW,
+                                                  double* Fout) {
+  const cdouble_ptr cb = (cdouble_ptr)(uintptr_t)A.basis;
+  const cdouble_ptr Dw = cb + BL.Dw();
+  const double h0 = -0.5 * cb[BL.winv()], hN = 0.5 * cb[BL.winv() + N];  // own-half weights at the ends
+  double* sGn = sW;            // [3 d][2 side][4 v][nf]
+  double* sT = sW + 24 * nf;   // [6 f][2 jj][2 c][nf]
+  constexpr int HALF = (n1 + 1) / 2;  // a face-plane line task computes outputs [0, HALF) or [HALF, n1)
+  constexpr int NTASK = 3 * nf + 24 * n1;
+  for (int task = t; task < NTASK; task += TPE) {
+    if (task < 3 * nf) {  // normal line
+      const int d = task / nf, a = task - d * nf;
+      const int sd = axis_stride(d);
+      const int base = (d == 0 ? n1 : 1) * (a % n1) + (d == 2 ? n1 : nf) * (a / n1);
+      double g0[4] = {0, 0, 0, 0}, gN[4] = {0, 0, 0, 0};
+#pragma unroll
+      for (int l = 0; l < n1; ++l) {
+        const double c0 = Dw[l], cN = Dw[N * n1 + l];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const double q = sq[v][base + l * sd];
+          g0[v] = fma(c0, q, g0[v]);
+          gN[v] = fma(cN, q, gN[v]);
+        }
+      }
+      const double J = A.invJ[0] * (d == 0) + A.invJ[1] * (d == 1) + A.invJ[2] * (d == 2);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        g0[v] = J * fma(h0, sq[v][base], g0[v]);
+        gN[v] = J * fma(hN, sq[v][base + N * sd], gN[v]);
+        sGn[((2 * d) * 4 + v) * nf + a] = g0[v];
+        sGn[((2 * d + 1) * 4 + v) * nf + a] = gN[v];
+      }
+    } else {  // line of a face plane
+      const int u = (task - 3 * nf) >> 1, hi = (task - 3 * nf) & 1;
+      const int f = u / (2 * n1), r = u - f * 2 * n1, jj = r / n1, pos = r - jj * n1;
+      const int d = f >> 1, id = (f & 1) ? N : 0;
+      const int ja = d == 0 ? 1 : 0, jb = d == 2 ? 1 : 2;
+      const int j = jj ? jb : ja, o = jj ? ja : jb;
+      const int sj = axis_stride(j);
+      const int base = id * axis_stride(d) + pos * axis_stride(o);
+      double qd[n1], qj[n1];
+#pragma unroll
+      for (int l = 0; l < n1; ++l) {
+        qd[l] = sq[d][base + l * sj];
+        qj[l] = sq[j][base + l * sj];
+      }
+      const double J = A.invJ[0] * (j == 0) + A.invJ[1] * (j == 1) + A.invJ[2] * (j == 2);
+      double* out = sT + (f * 2 + jj) * 2 * nf;
+#pragma unroll
+      for (int i = 0; i < n1; ++i) {
+        if ((i < HALF) == (hi != 0)) continue;
+        double td = 0, tj = 0;
+#pragma unroll
+        for (int l = 0; l < n1; ++l) {
+          const double c = Dw[i * n1 + l];
+          td = fma(c, qd[l], td);
+          tj = fma(c, qj[l], tj);
+        }
+        if (i == 0) {
+          td = fma(h0, qd[0], td);
+          tj = fma(h0, qj[0], tj);
+        } else if (i == N) {
+          td = fma(hN, qd[N], td);
+          tj = fma(hN, qj[N], tj);
+        }
+        const int a = jj ? pos + n1 * i : i + n1 * pos;
+        out[a] = J * td;
+        out[nf + a] = J * tj;
+      }
+    }
+  }
+  __syncthreads();
+  const double mu = A.mu, kap = A.kappa;
+  for (int q = t; q < 6 * nf; q += TPE) {
+    const int f = q / nf, a = q - f * nf, d = f >> 1;
+    const int ja = d == 0 ? 1 : 0, jb = d == 2 ? 1 : 2;
+    const int n = (f & 1 ? N : 0) * axis_stride(d) + (a % n1) * axis_stride(ja) + (a / n1) * axis_stride(jb);
+    const double* gn = sGn + f * 4 * nf + a;  // f = 2 d + side
+    const double dn_ud = gn[d * nf], dn_ua = gn[ja * nf], dn_ub = gn[jb * nf], dn_th = gn[3 * nf];
+    const double* tt = sT + f * 4 * nf + a;
+    const double da_ud = tt[0], da_ua = tt[nf], db_ud = tt[2 * nf], db_ub = tt[3 * nf];
+    const double dv = (2.0 / 3.0) * mu * (dn_ud + da_ua + db_ub);
+    const double Fd = mu * (dn_ud + dn_ud) - dv;
+    const double Fa = mu * (dn_ua + da_ud);
+    const double Fb = mu * (dn_ub + db_ud);
+    const double FE = sq[d][n] * Fd + sq[ja][n] * Fa + sq[jb][n] * Fb + kap * dn_th;
+    double* o = Fout + ((size_t)e * 6 + f) * 4 * nf + a;
+    o[d * nf] = Fd;
+    o[ja * nf] = Fa;
+    o[jb * nf] = Fb;
+    o[3 * nf] = FE;
+  }
+}
+
 // With BLEND (FP64) only the advective operator is blended: the viscous terms
-// enter unweighted, and MODE_DIFF leaves them out.
-template <int VF, int EQ, bool BLEND, class R, bool WALL = false>
+// enter unweighted, and MODE_DIFF leaves them out.  SPLIT: the split BR1
+// variant (StageArgs.split; FP64 Navier-Stokes without the eddy viscosity,
+// walls or blending).
+template <int VF, int EQ, bool BLEND, class R, bool WALL = false, bool SPLIT = false>
 __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
   constexpr bool NS = (EQ >= 1);
   constexpr bool LES = (EQ == 2);
@@ -1106,7 +1334,15 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
   // node state and the basis.
   static_assert(EPB == 1, "one element per workgroup: its neighbours are uniform");
   const Nbr6 nb6 = uniform_nbr6(A.nbr, e);
-  FaceData<NS, R, WALL> fd[FI];
+  static_assert(!SPLIT || (EQ == 1 && !BLEND && !WALL && !MX), "split BR1: FP64 Navier-Stokes on the box");
+  int ec[3] = {0, 0, 0};  // the element's coordinates on the box (uniform)
+  if (SPLIT) {
+    const int eu = __builtin_amdgcn_readfirstlane(e);
+    ec[0] = eu % A.ne[0];
+    ec[1] = (eu / A.ne[0]) % A.ne[1];
+    ec[2] = eu / (A.ne[0] * A.ne[1]);
+  }
+  FaceData<NS, R, WALL, SPLIT> fd[FI];
 #pragma unroll
   for (int k = 0; k < FI; ++k)
     if (t + k * TPE < 6 * nf) fd[k].it = face_item_geometry(nb6, t + k * TPE);
@@ -1130,7 +1366,7 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
   // Round trip 2: the face states (needs the neighbour indices).
 #pragma unroll
   for (int k = 0; k < FI; ++k)
-    if (t + k * TPE < 6 * nf) face_issue<NS, R, WALL>(A, e, fd[k]);
+    if (t + k * TPE < 6 * nf) face_issue<NS, R, WALL, SPLIT>(A, e, fd[k], ec);
   if (tid < NB_STAGE) {
     sB[tid] = (R)bval;
     if (BLEND) sB64[tid] = bval;
@@ -1155,7 +1391,7 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
   }
 #pragma unroll
   for (int k = 0; k < FI; ++k)
-    if (t + k * TPE < 6 * nf) face_item<VF, NS, R, MX, WALL>(A, fd[k], ref, sF, sQ, sFn);
+    if (t + k * TPE < 6 * nf) face_item<VF, NS, R, MX, WALL, SPLIT>(A, fd[k], ref, sF, sQ, sFn);
   __syncthreads();
 
   R acc[5] = {0, 0, 0, 0, 0};
@@ -1402,6 +1638,27 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
       }
     }
   }
+  // Split BR1, Runge-Kutta stage: the own part of the normal viscous flux of
+  // the stage output at the element's face nodes, for the next stage (the
+  // lifting kernel's split mode on the output state, from the values just
+  // written and still in registers).
+  if constexpr (SPLIT) {
+    if (A.Fvf_next && A.mode == MODE_RK) {  // uniform over the workgroup
+      static_assert(4 * nn + 48 * nf <= POOL, "lifted variables and line sums in the LDS pool");
+      double (*sq)[nn] = reinterpret_cast<double (*)[nn]>(sPool);
+      __syncthreads();  // the pool's last readers (the viscous pass) are done
+      if (t < nn) {
+        double P[7];
+        primitives<VF_PI, double, false>(u, gm1, Ref{0.0, 0.0, 0.0}, P);
+        sq[0][t] = P[1];
+        sq[1][t] = P[2];
+        sq[2][t] = P[3];
+        sq[3][t] = P[6];
+      }
+      __syncthreads();
+      own_part_by_lines<TPE>(A, e, t, sq, sPool + 4 * nn, A.Fvf_next);
+    }
+  }
   // Euler only: measured on the blended Navier-Stokes stage (N = 4, its
   // occupancy limited by LDS) the epilogue's barriers cost more than the
   // separate indicator launch it saves.
@@ -1434,7 +1691,7 @@ __device__ __forceinline__ void lift_face_q(const StageArgs& A, const FaceItem& 
   store_q(it, qs, sQ);
 }
 
-__device__ __forceinline__ int axis_stride(int j) { return j == 0 ? 1 : (j == 1 ? n1 : nf); }
+
 
 // Index of volume node n on the face of axis j (lower remaining axis first).
 __device__ __forceinline__ int face_index(int j, int i0, int i1, int i2) {
@@ -1444,7 +1701,8 @@ __device__ __forceinline__ int face_index(int j, int i0, int i1, int i2) {
 // Derivative along tangential axis j of the normal velocity u_d and of u_j at
 // node n (BR1: line sum with Dw plus the lifting term of axis j's faces); with
 // THIRD also that of u_o (o: the other tangential axis).
-template <class R, bool THIRD = false>
+// OWNHALF (split BR1): the interface values are the node's own half, q_n / 2.
+template <class R, bool THIRD = false, bool OWNHALF = false>
 __device__ __forceinline__ void tangential_pair(const R (*sq)[nn], const R (*sQ)[4][nf], const R* sDw,
                                                 const R* swinv, int n, int d, int j, int i0, int i1, int i2,
                                                 R invJj, R& dud, R& duj, int o = 0, R* duo = nullptr) {
@@ -1467,9 +1725,16 @@ __device__ __forceinline__ void tangential_pair(const R (*sq)[nn], const R (*sQ)
     const int f = 2 * j + (id == N);
     const R w = id == N ? swinv[N] : -swinv[0];
     const int a = face_index(j, i0, i1, i2);
-    s0 = fmaR(w, sQ[f][d][a], s0);
-    s1 = fmaR(w, sQ[f][j][a], s1);
-    if (THIRD) s2 = fmaR(w, sQ[f][o][a], s2);
+    if (OWNHALF) {
+      const R hw = (R)0.5 * w;
+      s0 = fmaR(hw, sq[d][n], s0);
+      s1 = fmaR(hw, sq[j][n], s1);
+      if (THIRD) s2 = fmaR(hw, sq[o][n], s2);
+    } else {
+      s0 = fmaR(w, sQ[f][d][a], s0);
+      s1 = fmaR(w, sQ[f][j][a], s1);
+      if (THIRD) s2 = fmaR(w, sQ[f][o][a], s2);
+    }
   }
   dud = invJj * s0;
   duj = invJj * s1;
@@ -1482,9 +1747,11 @@ __device__ __forceinline__ void tangential_pair(const R (*sq)[nn], const R (*sQ)
 // derivatives along d of (u, v, w, theta) and, along each tangential axis j,
 // those of u_d and u_j (with the eddy viscosity also the third velocity
 // component, for the full strain rate).
-template <class R, bool LES>
+template <class R, bool LES, bool OWNHALF = false>
 __device__ __forceinline__ void lift_face_node(const StageArgs& A, int e, const FaceItem& it, const R (*sq)[nn],
-                                               const R (*sQ)[4][nf], const R* sB, const R invJ[3]) {
+                                               const R (*sQ)[4][nf], const R* sB, const R invJ[3],
+                                               R* Fout = nullptr) {
+  static_assert(!(OWNHALF && LES), "the split lifting is linear in the gradient: no eddy viscosity");
   const int n = it.nown, d = it.d;
   const int i0 = n % n1, i1 = (n / n1) % n1, i2 = n / nf;
   const R* sDw = sB + BL.Dw();
@@ -1505,7 +1772,13 @@ __device__ __forceinline__ void lift_face_node(const StageArgs& A, int e, const 
     g2 = fmaR(c, sq[2][m], g2);
     g3 = fmaR(c, sq[3][m], g3);
   }
-  {
+  if (OWNHALF) {
+    const R hw = (R)0.5 * (it.side ? swinv[N] : -swinv[0]);
+    g0 = fmaR(hw, sq[0][n], g0);
+    g1 = fmaR(hw, sq[1][n], g1);
+    g2 = fmaR(hw, sq[2][n], g2);
+    g3 = fmaR(hw, sq[3][n], g3);
+  } else {
     const R w = it.side ? swinv[N] : -swinv[0];
     g0 = fmaR(w, sQ[it.f][0][it.a], g0);
     g1 = fmaR(w, sQ[it.f][1][it.a], g1);
@@ -1518,10 +1791,10 @@ __device__ __forceinline__ void lift_face_node(const StageArgs& A, int e, const 
   g2 *= Jd;
   g3 *= Jd;
   R da_ud, da_ua, db_ud, db_ub, da_ub = 0, db_ua = 0;
-  tangential_pair<R, LES>(sq, sQ, sDw, swinv, n, d, ja, i0, i1, i2, ja == 0 ? invJ[0] : invJ[1], da_ud, da_ua, jb,
-                          &da_ub);
-  tangential_pair<R, LES>(sq, sQ, sDw, swinv, n, d, jb, i0, i1, i2, jb == 1 ? invJ[1] : invJ[2], db_ud, db_ub, ja,
-                          &db_ua);
+  tangential_pair<R, LES, OWNHALF>(sq, sQ, sDw, swinv, n, d, ja, i0, i1, i2, ja == 0 ? invJ[0] : invJ[1], da_ud, da_ua,
+                                   jb, &da_ub);
+  tangential_pair<R, LES, OWNHALF>(sq, sQ, sDw, swinv, n, d, jb, i0, i1, i2, jb == 1 ? invJ[1] : invJ[2], db_ud, db_ub,
+                                   ja, &db_ua);
   const R dn_ud = d == 0 ? g0 : (d == 1 ? g1 : g2);
   const R dn_ua = ja == 0 ? g0 : g1;
   const R dn_ub = jb == 1 ? g1 : g2;
@@ -1540,7 +1813,7 @@ __device__ __forceinline__ void lift_face_node(const StageArgs& A, int e, const 
   const R Fb = mu * (dn_ub + db_ud);
   const R ud = sq[d][n], ua = sq[ja][n], ub = sq[jb][n];
   const R FE = ud * Fd + ua * Fa + ub * Fb + kap * g3;
-  R* out = reinterpret_cast<R*>(A.Fvf) + ((size_t)e * 6 + it.f) * 4 * nf + it.a;
+  R* out = (Fout ? Fout : reinterpret_cast<R*>(A.Fvf)) + ((size_t)e * 6 + it.f) * 4 * nf + it.a;
   out[d * nf] = Fd;
   out[ja * nf] = Fa;
   out[jb * nf] = Fb;
@@ -1550,7 +1823,7 @@ __device__ __forceinline__ void lift_face_node(const StageArgs& A, int e, const 
 // Register budget of the lifting kernel: 8 waves per SIMD (64 VGPRs) with one
 // face item per thread, else 4; the line sums with run-time strides are only
 // partly unrolled so that the partner loads in flight fit in it.
-template <class R, bool LES, bool WALL = false>
+template <class R, bool LES, bool WALL = false, bool SPLIT = false>
 __global__ __launch_bounds__(PL::NTB, PL::FI == 1 && N >= 2 ? 8 : 4) void k_lift(StageArgs A) {
   constexpr bool MX = sizeof(R) == 4;
   constexpr int EPB = PL::EPB, TPE = PL::TPE, FI = PL::FI;
@@ -1586,9 +1859,13 @@ __global__ __launch_bounds__(PL::NTB, PL::FI == 1 && N >= 2 ? 8 : 4) void k_lift
   const double bval = tid < NB_STAGE ? A.basis[tid] : 0.0;
   const Ref ref = MX ? reference_state(A.U, gm1) : Ref{0.0, 0.0, 0.0};
   double FL[FI][5], FR[FI][5];
+  static_assert(!SPLIT || (!MX && !LES && !WALL), "split BR1: FP64 Navier-Stokes on the box");
+  constexpr bool split = SPLIT;
 #pragma unroll
   for (int k = 0; k < FI; ++k)
-    if (t + k * TPE < 6 * nf) face_loads_w<WALL>(A.U, e, its[k], FL[k], FR[k]);
+    if (t + k * TPE < 6 * nf) {
+      if (!split) face_loads_w<WALL>(A.U, e, its[k], FL[k], FR[k]);  // split: no interface values
+    }
   if (tid < NB_STAGE) sB[tid] = (R)bval;
   const R invJ[3] = {(R)A.invJ[0], (R)A.invJ[1], (R)A.invJ[2]};
   if (t < nn) {
@@ -1602,11 +1879,14 @@ __global__ __launch_bounds__(PL::NTB, PL::FI == 1 && N >= 2 ? 8 : 4) void k_lift
   }
 #pragma unroll
   for (int k = 0; k < FI; ++k)
-    if (t + k * TPE < 6 * nf) lift_face_q<R, MX>(A, its[k], FL[k], FR[k], ref, sQ);
+    if (t + k * TPE < 6 * nf && !split) lift_face_q<R, MX>(A, its[k], FL[k], FR[k], ref, sQ);
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < FI; ++k)
-    if (t + k * TPE < 6 * nf && !(WALL && its[k].nb < 0)) lift_face_node<R, LES>(A, e, its[k], sq, sQ, sB, invJ);
+    if (t + k * TPE < 6 * nf && !(WALL && its[k].nb < 0)) {
+      if constexpr (SPLIT) lift_face_node<R, false, true>(A, e, its[k], sq, sQ, sB, invJ);
+      else lift_face_node<R, LES>(A, e, its[k], sq, sQ, sB, invJ);
+    }
 }
 
 // Wall-model flux at every wall face node (FP64): thread -> (side p, element
@@ -4322,6 +4602,12 @@ hipError_t launch_stage_vf(const StageArgs& A0, int eq, hipStream_t s) {
     if constexpr (VF != VF_CH) hipLaunchKernelGGL((k_stage<VF, 2, false, R>), grid, block, 0, s, A);
     else return hipErrorInvalidValue;
   } else if (eq == 1) {
+    if constexpr (sizeof(R) == 8) {
+      if (A.split) {
+        hipLaunchKernelGGL((k_stage<VF, 1, false, double, false, true>), grid, block, 0, s, A);
+        return hipGetLastError();
+      }
+    }
     hipLaunchKernelGGL((k_stage<VF, 1, false, R>), grid, block, 0, s, A);
   } else if (A.blend) {
     if constexpr (sizeof(R) == 8) hipLaunchKernelGGL((k_stage<VF, 0, true, double>), grid, block, 0, s, A);
@@ -4358,6 +4644,7 @@ hipError_t launch_lift(const StageArgs& A0, int eq, hipStream_t s) {
     return hipGetLastError();
   }
   if (eq == 2) hipLaunchKernelGGL((k_lift<double, true>), dim3(blocks_for(A)), dim3(PL::NTB), 0, s, A);
+  else if (A.split) hipLaunchKernelGGL((k_lift<double, false, false, true>), dim3(blocks_for(A)), dim3(PL::NTB), 0, s, A);
   else hipLaunchKernelGGL((k_lift<double, false>), dim3(blocks_for(A)), dim3(PL::NTB), 0, s, A);
   return hipGetLastError();
 }

@@ -25,6 +25,7 @@ LLF, ROE, CENTRAL = 0, 1, 2
 HENNEMANN, PERSSON = 0, 1
 FV_FIRST, FV_MINMOD = 0, 1
 FP64, MIXED = 0, 1
+LIFT_TWO_PASS, LIFT_SPLIT = 0, 1
 
 EXPORTS = ["dg_default_options", "dg_init", "dg_set_options", "dg_get_options", "dg_set_stream",
            "dg_time_derivative", "rk_step", "dg_rk_steps", "dg_vjp", "rk_step_vjp", "dg_max_dt",
@@ -46,7 +47,7 @@ class Mesh(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("equations", ctypes.c_int32), ("vol_flux", ctypes.c_int32), ("surf_flux", ctypes.c_int32),
                 ("blending", ctypes.c_int32), ("indicator", ctypes.c_int32), ("fv_recon", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32), ("Pr", ctypes.c_double),
+                ("precision", ctypes.c_int32), ("lifting", ctypes.c_int32), ("Pr", ctypes.c_double),
                 ("alpha_min", ctypes.c_double), ("alpha_max", ctypes.c_double), ("alpha_spread", ctypes.c_double),
                 ("Cs", ctypes.c_double), ("Prt", ctypes.c_double)]
 

@@ -3,7 +3,9 @@ benchmark times.
 
 * TGV Ma 0.1 Re 1600, N = 7, 64^3 elements (134 M nodes): one FP64 evaluation
   on the GPU against the oracle on sampled elements (corners, edges and
-  seeded random elements), and the same for the mixed operator at its bound.
+  seeded random elements), with either BR1 lifting scheme, and the same for
+  the mixed operator at its bound; two Runge-Kutta steps with the split
+  lifting (the benchmark's path) against the two-pass lifting.
 * Extruded Sod tube, N = 5, 64 x 8 x 8 elements, blending with minmod
   subcells, 500 steps: the data stay constant in y and z, so each x-line of
   the 3-D run equals the quasi-1-D tube (64 x 1 x 1 elements of the same cell
@@ -61,8 +63,8 @@ def tgv_n7_64(torch_cuda):
     return N, n, U, sel
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_tgv_n7_64_sampled(orc, torch_cuda, tgv_n7_64, precision):
+@pytest.mark.parametrize("precision,lifting", [(0, 0), (0, 1), (1, 0)])
+def test_tgv_n7_64_sampled(orc, torch_cuda, tgv_n7_64, precision, lifting):
     import torch
 
     from paper_2306_12891_amd import dg
@@ -71,7 +73,7 @@ def test_tgv_n7_64_sampled(orc, torch_cuda, tgv_n7_64, precision):
     s = orc.Setup(N=N, nelem=(n, n, n), equations=1, vol_flux=1, surf_flux=1, mu=mu)
     ref = orc.time_derivative_elems(s, U, sel)
     op = dg.DG((n, n, n), N, gamma=G, mu=mu, equations=dg.NS, vol_flux=dg.PI, surf_flux=dg.ROE,
-               precision=precision)
+               precision=precision, lifting=lifting)
     Ud = torch.from_numpy(U).cuda()
     got = op.time_derivative(Ud)[torch.from_numpy(sel).long().cuda()].cpu().numpy()
     del Ud
@@ -82,6 +84,41 @@ def test_tgv_n7_64_sampled(orc, torch_cuda, tgv_n7_64, precision):
         scale = max(S[v], np.max(np.abs(ref[:, v])))
         err = np.max(np.abs(got[:, v] - ref[:, v]))
         assert err <= tol * scale, (v, err, scale)
+
+
+def test_tgv_n7_64_split_rollout_matches_two_pass(torch_cuda, tgv_n7_64):
+    """The benchmark's launch configuration (dg_rk_steps with the split BR1
+    lifting, whose stage kernels chain the own parts through the stages of a
+    step) against the two-pass lifting, 2 full-size steps: per variable to
+    1e-12 of max(max |U_v|, max rho * max c).  Both evaluate the same
+    operator; the two-pass path is pinned to the oracle by the sampled
+    evaluation above and the full-size C2 rollout."""
+    import torch
+
+    from paper_2306_12891_amd import dg
+    N, n, U, _ = tgv_n7_64
+    mu = 1.0 / 1600
+    got = {}
+    for lifting in (dg.LIFT_SPLIT, dg.LIFT_TWO_PASS):
+        op = dg.DG((n, n, n), N, gamma=G, mu=mu, equations=dg.NS, vol_flux=dg.PI, surf_flux=dg.ROE,
+                   lifting=lifting)
+        Ud = torch.from_numpy(U).cuda()
+        dt = op.max_dt(Ud, 0.5)
+        op.rk_steps(Ud, dt, 2)
+        got[lifting] = Ud.cpu().numpy()
+        del Ud
+        op.close()
+        torch.cuda.empty_cache()
+    a, b = got[dg.LIFT_SPLIT], got[dg.LIFT_TWO_PASS]
+    rho = b[:, 0]
+    u = b[:, 1:4] / rho[:, None]
+    p = (G - 1) * (b[:, 4] - 0.5 * rho * np.sum(u * u, 1))
+    floor = np.max(np.abs(rho)) * np.max(np.sqrt(G * np.abs(p) / rho))
+    for v in range(5):
+        scale = max(np.max(np.abs(b[:, v])), floor)
+        err = np.max(np.abs(a[:, v] - b[:, v]))
+        assert err <= 1e-12 * scale, (v, err, scale)
+    assert np.max(np.abs(b[:, 1] - U[:, 1])) > 1e-6
 
 
 def sod_run_against_quasi_1d(orc, op, s1, U0, U1, nelem, N, dt, steps, every):
