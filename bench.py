@@ -2,7 +2,8 @@
 
 Default workload: Taylor-Green vortex, Ma 0.1, Re 1600, Pr 0.72, N = 7 on
 64^3 periodic elements (134 M nodes), Pirozzoli split flux + Roe, BR1
-lifting, FP64, LSERK4: the configuration the metric is quoted on (FP64
+lifting (split: one lifting launch per step), FP64, LSERK4: the configuration
+the metric is quoted on (FP64
 against the mixed-precision operator at its stated error; the adjoint of
 the N = 5, 16^3 TGV beside it).  A "step" is one Runge-Kutta step (5 stages) over the
 whole mesh.  The metric is DOF-stage updates per second (1/PID with the GPU as
@@ -347,19 +348,33 @@ def measured_copy_bandwidth(torch, mib=4096, reps=10):
     return gbs
 
 
-def roofline(name, nodes, steps, prof):
+def face_flux_bytes_per_node(N, viscous, split):
+    """Algorithmic bytes per node and stage launch of the normal viscous face
+    flux (FP64, 4 values at each of the 6 (N+1)^2 face nodes of an element):
+    the stage kernel reads the neighbours' (192/(N+1) B per node); with the
+    split lifting it also writes the own part of its output in stages 1-4."""
+    if not viscous:
+        return 0.0
+    f = 192.0 / (N + 1)
+    return f * (1.0 + (0.8 if split else 0.0))
+
+
+def roofline(name, nodes, steps, prof, N=None, viscous=False, split=False):
     """Roofline of the stage kernel from its event-timed launches: achieved =
     160 B per DOF and launch (SURVEY-style floor of the Runge-Kutta stage:
     read U and the register, write the register and U; curved meshes add the
     80 B of metric terms) over the average launch time.  The exact per-launch
-    average (stage 1 reads no register, stage 5 writes none: 144 B) is
-    reported beside it."""
+    average of the kernel (stage 1 reads no register, stage 5 writes none:
+    144 B; plus the viscous face fluxes it reads and, with the split lifting,
+    writes) is reported beside it."""
     ms_stage, n_stage = prof["stage"]
     avg_ms = ms_stage / max(n_stage, 1)
     extra = METRIC_BYTES_PER_NODE if name in CURVED else 0.0
     launch_bytes = (160.0 + extra) * nodes
     A = launch_bytes / (avg_ms * 1e-3) / 1e9
-    exact = (stage_bytes_per_step(nodes) / 5 + extra * nodes) / (avg_ms * 1e-3) / 1e9
+    face = face_flux_bytes_per_node(N, viscous, split) if N is not None else 0.0
+    exact_per_node = stage_bytes_per_step(1) / 5 + extra + face
+    exact = exact_per_node * nodes / (avg_ms * 1e-3) / 1e9
     traffic = None
     if name in MEASURED_TRAFFIC and kernel_sha() == MEASURED_TRAFFIC["kernel_sha"]:
         traffic = MEASURED_TRAFFIC[name]["bytes_per_launch"]
@@ -368,7 +383,8 @@ def roofline(name, nodes, steps, prof):
            "kernel": ("k_stage_curved" if name in CURVED else "k_stage") + " (operator + LSERK4 stage)",
            "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": launch_bytes,
            "algorithmic_bytes_per_dof": 160.0 + extra,
-           "frac_exact_144B": round(exact / HBM_PEAK_GBS, 4)}
+           "exact_bytes_per_dof": round(exact_per_node, 2),
+           "frac_exact": round(exact / HBM_PEAK_GBS, 4)}
     fl = KERNEL_FLOPS.get(name)
     if fl and kernel_sha() == KERNEL_FLOPS["kernel_sha"]:
         tf = fl["stage_flops_per_dof"] * nodes / (avg_ms * 1e-3) / 1e12
@@ -466,6 +482,10 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison run")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint (gradient) leg")
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
+    ap.add_argument("--lifting", choices=("split", "two_pass"), default="split",
+                    help="BR1 lifting scheme of the Navier-Stokes operator (split: the library default)")
+    ap.add_argument("--no-lifting-compare", action="store_true",
+                    help="skip the one-block run with the other lifting scheme")
     ap.add_argument("--vjp-only", action="store_true",
                     help="only time dg_vjp against dg_time_derivative on the adjoint mesh (N = 5, 16^3) and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -506,8 +526,13 @@ def main():
     nodes = int(np.prod(nelem)) * (N + 1) ** 3
     U0 = None if name.startswith("freestream") else initial_state(name, N, nelem)
     cs = MODEL_CS.get(name, 0.0)
+    lifting = dg.LIFT_SPLIT if args.lifting == "split" else dg.LIFT_TWO_PASS
     op = dg.DG(nelem, N, gamma=1.4, mu=mu, lo=lo, hi=hi, equations=eq, vol_flux=vf, surf_flux=sf,
-               blending=blend, Pr=0.72, Cs=cs)
+               blending=blend, Pr=0.72, Cs=cs, lifting=lifting)
+    # whether the split lifting runs here (the library uses it for the FP64
+    # Navier-Stokes operator on the box without eddy viscosity, blending or walls)
+    split = (lifting == dg.LIFT_SPLIT and eq == dg.NS and cs == 0.0 and not blend and name not in CURVED
+             and name not in WALLS)
     if name in CURVED:
         op.set_geometry(torch.from_numpy(curved_nodes(name, N, nelem)).to("cuda:0"))
     if name in WALLS:
@@ -523,7 +548,7 @@ def main():
     roof = None
     extra = {"repeats": repeat_stats(nodes, args.steps, walls)}
     if prof:
-        roof = roofline(name, nodes, args.steps, prof)
+        roof = roofline(name, nodes, args.steps, prof, N, eq == dg.NS, split)
         copy_gbs = measured_copy_bandwidth(torch)
         roof["measured_copy_GBs"] = round(copy_gbs, 1)
         roof["frac_of_measured_copy"] = round(roof["achieved"] / copy_gbs, 4)
@@ -532,6 +557,28 @@ def main():
     extra["path_roofline_frac_160B"] = round(path_bytes / wall / 1e9 / HBM_PEAK_GBS, 4)
     extra["pid_gpu_us"] = 1e6 / value
     extra["finite_after_run"] = finite
+    # the same workload with the other BR1 lifting scheme: one block, same
+    # start state and warm-up; its final state against this run's
+    if (eq == dg.NS and cs == 0.0 and not blend and name not in CURVED and name not in WALLS
+            and not args.no_lifting_compare):
+        other = dg.LIFT_TWO_PASS if lifting == dg.LIFT_SPLIT else dg.LIFT_SPLIT
+        op.set_options(lifting=other)
+        Uo = U_init.clone()
+        walls_o, prof_o = timed_rollouts(torch, op, Uo, dt, args.steps, args.warmup, 1, not args.no_profile)
+        op.set_options(lifting=lifting)
+        Uc = U_init.clone()
+        op.rk_steps(Uc, dt, args.warmup + args.steps)
+        scale = torch.maximum(Uc.abs().amax(dim=(0, 2, 3, 4)), Uc[:, 0].abs().amax())
+        err = ((Uo - Uc).abs().amax(dim=(0, 2, 3, 4)) / scale).tolist()
+        extra["other_lifting"] = {
+            "lifting": "two_pass" if other == dg.LIFT_TWO_PASS else "split",
+            "value": nodes * 5 * args.steps / walls_o[0], "ms_per_step": walls_o[0] / args.steps * 1e3,
+            "err_vs_this_run_linf_rel": err, "after_steps": args.warmup + args.steps}
+        if prof_o:
+            extra["other_lifting"]["kernel_ms_per_step"] = {k: round(v[0] / args.steps, 4)
+                                                            for k, v in prof_o.items() if v[1]}
+            extra["other_lifting"]["stage_avg_launch_ms"] = round(prof_o["stage"][0] / max(prof_o["stage"][1], 1), 4)
+        del Uo, Uc
     if blend:
         extra["blended_fraction"] = blended_fraction(torch, op, U_init, dt, args.warmup + args.steps * repeats)
         if not args.no_adjoint:
@@ -600,7 +647,7 @@ def main():
         "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": desc, "N": N, "elements": list(nelem), "dof": nodes, "dt": dt,
-                   "precision": "fp64"},
+                   "precision": "fp64", "br1_lifting": ("split" if split else "two_pass") if eq == dg.NS else None},
         "roofline": roof, "cpu_baseline": cpu, **extra,
     }
     print(json.dumps(line))

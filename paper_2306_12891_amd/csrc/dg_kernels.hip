@@ -1181,9 +1181,26 @@ __device__ __forceinline__ void node_viscous_flux(const StageArgs& A, int e, con
 
 __device__ __forceinline__ int axis_stride(int j) { return j == 0 ? 1 : (j == 1 ? n1 : nf); }
 
+// Padded node layout of the split lifting's LDS copy of (u, v, w, theta): one
+// double after every x-row, so that the lines read across a wavefront (x-lines
+// of different rows, y-lines of different planes) fall on different LDS banks.
+constexpr int SQP = nn + nn / n1;  // doubles per variable
+__device__ __forceinline__ constexpr int pstride(int j) { return j == 0 ? 1 : (j == 1 ? n1 + 1 : n1 * (n1 + 1)); }
+__device__ __forceinline__ int padded(int m) { return m + m / n1; }  // node m = i0 + n1 i1 + nf i2
+
+// The four lifted variables of node t into the padded layout (P: primitives).
+__device__ __forceinline__ void store_own_q(double* sq, int t, const double P[7]) {
+  const int m = padded(t);
+  sq[m] = P[1];
+  sq[SQP + m] = P[2];
+  sq[2 * SQP + m] = P[3];
+  sq[3 * SQP + m] = P[6];
+}
+
 // Split BR1: the own part of the normal viscous flux at every face node of
 // the element (into Fout, laid out as StageArgs.Fvf), from sq = (u, v, w,
-// theta) at its nodes (LDS), by lines rather than one face node at a time:
+// theta) at its nodes (LDS, padded layout), by lines rather than one face
+// node at a time:
 //   pass 1: each normal line (3 nf of them) gives the derivatives of
 //     (u, v, w, theta) along it at both end nodes, and each line of a face
 //     plane along one of the plane's axes j (6 faces x 2 axes x n1 lines,
@@ -1193,12 +1210,11 @@ __device__ __forceinline__ int axis_stride(int j) { return j == 0 ? 1 : (j == 1 
 //   pass 2: each face node forms its flux from these and its velocity.
 // Each line's values are read from LDS once; the differentiation matrix comes
 // with uniform loads from the constant address space.  The interface values
-// are the node's own half, q / 2, as in the lifting kernel's split mode.  The
-// caller synchronises the workgroup before (sq written, sW free); the
-// function synchronises between the passes.
+// are the node's own half, q / 2.  The caller synchronises the workgroup
+// before (sq written, sW free); the function synchronises between the passes.
 using cdouble_ptr = const double __attribute__((address_space(4)))*;
 template <int TPE>
-__device__ __forceinline__ void own_part_by_lines(const StageArgs& A, int e, int t, const double (*sq)[nn], double* sW,
+__device__ __forceinline__ void own_part_by_lines(const StageArgs& A, int e, int t, const double* sq, double* sW,
                                                   double* Fout) {
   const cdouble_ptr cb = (cdouble_ptr)(uintptr_t)A.basis;
   const cdouble_ptr Dw = cb + BL.Dw();
@@ -1210,15 +1226,16 @@ __device__ __forceinline__ void own_part_by_lines(const StageArgs& A, int e, int
   for (int task = t; task < NTASK; task += TPE) {
     if (task < 3 * nf) {  // normal line
       const int d = task / nf, a = task - d * nf;
-      const int sd = axis_stride(d);
-      const int base = (d == 0 ? n1 : 1) * (a % n1) + (d == 2 ? n1 : nf) * (a / n1);
+      const int ja = d == 0 ? 1 : 0, jb = d == 2 ? 1 : 2;
+      const int sd = pstride(d);
+      const int base = (a % n1) * pstride(ja) + (a / n1) * pstride(jb);
       double g0[4] = {0, 0, 0, 0}, gN[4] = {0, 0, 0, 0};
 #pragma unroll
       for (int l = 0; l < n1; ++l) {
         const double c0 = Dw[l], cN = Dw[N * n1 + l];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const double q = sq[v][base + l * sd];
+          const double q = sq[v * SQP + base + l * sd];
           g0[v] = fma(c0, q, g0[v]);
           gN[v] = fma(cN, q, gN[v]);
         }
@@ -1226,24 +1243,24 @@ __device__ __forceinline__ void own_part_by_lines(const StageArgs& A, int e, int
       const double J = A.invJ[0] * (d == 0) + A.invJ[1] * (d == 1) + A.invJ[2] * (d == 2);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        g0[v] = J * fma(h0, sq[v][base], g0[v]);
-        gN[v] = J * fma(hN, sq[v][base + N * sd], gN[v]);
+        g0[v] = J * fma(h0, sq[v * SQP + base], g0[v]);
+        gN[v] = J * fma(hN, sq[v * SQP + base + N * sd], gN[v]);
         sGn[((2 * d) * 4 + v) * nf + a] = g0[v];
         sGn[((2 * d + 1) * 4 + v) * nf + a] = gN[v];
       }
-    } else {  // line of a face plane
+    } else {  // half of a line of a face plane
       const int u = (task - 3 * nf) >> 1, hi = (task - 3 * nf) & 1;
       const int f = u / (2 * n1), r = u - f * 2 * n1, jj = r / n1, pos = r - jj * n1;
       const int d = f >> 1, id = (f & 1) ? N : 0;
       const int ja = d == 0 ? 1 : 0, jb = d == 2 ? 1 : 2;
       const int j = jj ? jb : ja, o = jj ? ja : jb;
-      const int sj = axis_stride(j);
-      const int base = id * axis_stride(d) + pos * axis_stride(o);
+      const int sj = pstride(j);
+      const int base = id * pstride(d) + pos * pstride(o);
       double qd[n1], qj[n1];
 #pragma unroll
       for (int l = 0; l < n1; ++l) {
-        qd[l] = sq[d][base + l * sj];
-        qj[l] = sq[j][base + l * sj];
+        qd[l] = sq[d * SQP + base + l * sj];
+        qj[l] = sq[j * SQP + base + l * sj];
       }
       const double J = A.invJ[0] * (j == 0) + A.invJ[1] * (j == 1) + A.invJ[2] * (j == 2);
       double* out = sT + (f * 2 + jj) * 2 * nf;
@@ -1275,7 +1292,7 @@ __device__ __forceinline__ void own_part_by_lines(const StageArgs& A, int e, int
   for (int q = t; q < 6 * nf; q += TPE) {
     const int f = q / nf, a = q - f * nf, d = f >> 1;
     const int ja = d == 0 ? 1 : 0, jb = d == 2 ? 1 : 2;
-    const int n = (f & 1 ? N : 0) * axis_stride(d) + (a % n1) * axis_stride(ja) + (a / n1) * axis_stride(jb);
+    const int n = (f & 1 ? N : 0) * pstride(d) + (a % n1) * pstride(ja) + (a / n1) * pstride(jb);
     const double* gn = sGn + f * 4 * nf + a;  // f = 2 d + side
     const double dn_ud = gn[d * nf], dn_ua = gn[ja * nf], dn_ub = gn[jb * nf], dn_th = gn[3 * nf];
     const double* tt = sT + f * 4 * nf + a;
@@ -1284,13 +1301,35 @@ __device__ __forceinline__ void own_part_by_lines(const StageArgs& A, int e, int
     const double Fd = mu * (dn_ud + dn_ud) - dv;
     const double Fa = mu * (dn_ua + da_ud);
     const double Fb = mu * (dn_ub + db_ud);
-    const double FE = sq[d][n] * Fd + sq[ja][n] * Fa + sq[jb][n] * Fb + kap * dn_th;
+    const double FE = sq[d * SQP + n] * Fd + sq[ja * SQP + n] * Fa + sq[jb * SQP + n] * Fb + kap * dn_th;
     double* o = Fout + ((size_t)e * 6 + f) * 4 * nf + a;
     o[d * nf] = Fd;
     o[ja * nf] = Fa;
     o[jb * nf] = Fb;
     o[3 * nf] = FE;
   }
+}
+
+// Split BR1 lifting: the own part of the normal viscous flux at every face
+// node of the element (into StageArgs.Fvf), from the element's own nodes
+// only; one element per workgroup.  The stage kernel's epilogue does the same
+// for its output state.
+__global__ __launch_bounds__(PS::NTB) void k_lift_split(StageArgs A) {
+  static_assert(PS::EPB == 1 && PS::TPE == PS::NTB, "one element per workgroup");
+  __shared__ double sW[4 * SQP + 48 * nf];
+  const int e = element_of_block(blockIdx.x, A.chunk);
+  if (e >= A.nelem) return;  // uniform over the workgroup
+  const int t = threadIdx.x;
+  if (t < nn) {
+    const double* Ue = A.U + (size_t)e * 5 * nn;
+    double u[5], P[7];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) u[v] = Ue[v * nn + t];
+    primitives<VF_PI, double, false>(u, A.gamma - 1.0, Ref{0.0, 0.0, 0.0}, P);
+    store_own_q(sW, t, P);
+  }
+  __syncthreads();
+  own_part_by_lines<PS::TPE>(A, e, t, sW, sW + 4 * SQP, A.Fvf);
 }
 
 // With BLEND (FP64) only the advective operator is blended: the viscous terms
@@ -1639,24 +1678,21 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
     }
   }
   // Split BR1, Runge-Kutta stage: the own part of the normal viscous flux of
-  // the stage output at the element's face nodes, for the next stage (the
-  // lifting kernel's split mode on the output state, from the values just
-  // written and still in registers).
+  // the stage output at the element's face nodes, for the next stage (what
+  // k_lift_split computes, here from the values just written and still in
+  // registers).
   if constexpr (SPLIT) {
     if (A.Fvf_next && A.mode == MODE_RK) {  // uniform over the workgroup
-      static_assert(4 * nn + 48 * nf <= POOL, "lifted variables and line sums in the LDS pool");
-      double (*sq)[nn] = reinterpret_cast<double (*)[nn]>(sPool);
+      static_assert(4 * SQP + 48 * nf <= POOL, "lifted variables and line sums in the LDS pool");
+      double* sq = reinterpret_cast<double*>(sPool);
       __syncthreads();  // the pool's last readers (the viscous pass) are done
       if (t < nn) {
         double P[7];
         primitives<VF_PI, double, false>(u, gm1, Ref{0.0, 0.0, 0.0}, P);
-        sq[0][t] = P[1];
-        sq[1][t] = P[2];
-        sq[2][t] = P[3];
-        sq[3][t] = P[6];
+        store_own_q(sq, t, P);
       }
       __syncthreads();
-      own_part_by_lines<TPE>(A, e, t, sq, sPool + 4 * nn, A.Fvf_next);
+      own_part_by_lines<TPE>(A, e, t, sq, sq + 4 * SQP, A.Fvf_next);
     }
   }
   // Euler only: measured on the blended Navier-Stokes stage (N = 4, its
@@ -1701,8 +1737,7 @@ __device__ __forceinline__ int face_index(int j, int i0, int i1, int i2) {
 // Derivative along tangential axis j of the normal velocity u_d and of u_j at
 // node n (BR1: line sum with Dw plus the lifting term of axis j's faces); with
 // THIRD also that of u_o (o: the other tangential axis).
-// OWNHALF (split BR1): the interface values are the node's own half, q_n / 2.
-template <class R, bool THIRD = false, bool OWNHALF = false>
+template <class R, bool THIRD = false>
 __device__ __forceinline__ void tangential_pair(const R (*sq)[nn], const R (*sQ)[4][nf], const R* sDw,
                                                 const R* swinv, int n, int d, int j, int i0, int i1, int i2,
                                                 R invJj, R& dud, R& duj, int o = 0, R* duo = nullptr) {
@@ -1725,16 +1760,9 @@ __device__ __forceinline__ void tangential_pair(const R (*sq)[nn], const R (*sQ)
     const int f = 2 * j + (id == N);
     const R w = id == N ? swinv[N] : -swinv[0];
     const int a = face_index(j, i0, i1, i2);
-    if (OWNHALF) {
-      const R hw = (R)0.5 * w;
-      s0 = fmaR(hw, sq[d][n], s0);
-      s1 = fmaR(hw, sq[j][n], s1);
-      if (THIRD) s2 = fmaR(hw, sq[o][n], s2);
-    } else {
-      s0 = fmaR(w, sQ[f][d][a], s0);
-      s1 = fmaR(w, sQ[f][j][a], s1);
-      if (THIRD) s2 = fmaR(w, sQ[f][o][a], s2);
-    }
+    s0 = fmaR(w, sQ[f][d][a], s0);
+    s1 = fmaR(w, sQ[f][j][a], s1);
+    if (THIRD) s2 = fmaR(w, sQ[f][o][a], s2);
   }
   dud = invJj * s0;
   duj = invJj * s1;
@@ -1747,11 +1775,9 @@ __device__ __forceinline__ void tangential_pair(const R (*sq)[nn], const R (*sQ)
 // derivatives along d of (u, v, w, theta) and, along each tangential axis j,
 // those of u_d and u_j (with the eddy viscosity also the third velocity
 // component, for the full strain rate).
-template <class R, bool LES, bool OWNHALF = false>
+template <class R, bool LES>
 __device__ __forceinline__ void lift_face_node(const StageArgs& A, int e, const FaceItem& it, const R (*sq)[nn],
-                                               const R (*sQ)[4][nf], const R* sB, const R invJ[3],
-                                               R* Fout = nullptr) {
-  static_assert(!(OWNHALF && LES), "the split lifting is linear in the gradient: no eddy viscosity");
+                                               const R (*sQ)[4][nf], const R* sB, const R invJ[3]) {
   const int n = it.nown, d = it.d;
   const int i0 = n % n1, i1 = (n / n1) % n1, i2 = n / nf;
   const R* sDw = sB + BL.Dw();
@@ -1772,13 +1798,7 @@ __device__ __forceinline__ void lift_face_node(const StageArgs& A, int e, const 
     g2 = fmaR(c, sq[2][m], g2);
     g3 = fmaR(c, sq[3][m], g3);
   }
-  if (OWNHALF) {
-    const R hw = (R)0.5 * (it.side ? swinv[N] : -swinv[0]);
-    g0 = fmaR(hw, sq[0][n], g0);
-    g1 = fmaR(hw, sq[1][n], g1);
-    g2 = fmaR(hw, sq[2][n], g2);
-    g3 = fmaR(hw, sq[3][n], g3);
-  } else {
+  {
     const R w = it.side ? swinv[N] : -swinv[0];
     g0 = fmaR(w, sQ[it.f][0][it.a], g0);
     g1 = fmaR(w, sQ[it.f][1][it.a], g1);
@@ -1791,10 +1811,10 @@ __device__ __forceinline__ void lift_face_node(const StageArgs& A, int e, const 
   g2 *= Jd;
   g3 *= Jd;
   R da_ud, da_ua, db_ud, db_ub, da_ub = 0, db_ua = 0;
-  tangential_pair<R, LES, OWNHALF>(sq, sQ, sDw, swinv, n, d, ja, i0, i1, i2, ja == 0 ? invJ[0] : invJ[1], da_ud, da_ua,
-                                   jb, &da_ub);
-  tangential_pair<R, LES, OWNHALF>(sq, sQ, sDw, swinv, n, d, jb, i0, i1, i2, jb == 1 ? invJ[1] : invJ[2], db_ud, db_ub,
-                                   ja, &db_ua);
+  tangential_pair<R, LES>(sq, sQ, sDw, swinv, n, d, ja, i0, i1, i2, ja == 0 ? invJ[0] : invJ[1], da_ud, da_ua, jb,
+                          &da_ub);
+  tangential_pair<R, LES>(sq, sQ, sDw, swinv, n, d, jb, i0, i1, i2, jb == 1 ? invJ[1] : invJ[2], db_ud, db_ub, ja,
+                          &db_ua);
   const R dn_ud = d == 0 ? g0 : (d == 1 ? g1 : g2);
   const R dn_ua = ja == 0 ? g0 : g1;
   const R dn_ub = jb == 1 ? g1 : g2;
@@ -1813,7 +1833,7 @@ __device__ __forceinline__ void lift_face_node(const StageArgs& A, int e, const 
   const R Fb = mu * (dn_ub + db_ud);
   const R ud = sq[d][n], ua = sq[ja][n], ub = sq[jb][n];
   const R FE = ud * Fd + ua * Fa + ub * Fb + kap * g3;
-  R* out = (Fout ? Fout : reinterpret_cast<R*>(A.Fvf)) + ((size_t)e * 6 + it.f) * 4 * nf + it.a;
+  R* out = reinterpret_cast<R*>(A.Fvf) + ((size_t)e * 6 + it.f) * 4 * nf + it.a;
   out[d * nf] = Fd;
   out[ja * nf] = Fa;
   out[jb * nf] = Fb;
@@ -1823,7 +1843,7 @@ __device__ __forceinline__ void lift_face_node(const StageArgs& A, int e, const 
 // Register budget of the lifting kernel: 8 waves per SIMD (64 VGPRs) with one
 // face item per thread, else 4; the line sums with run-time strides are only
 // partly unrolled so that the partner loads in flight fit in it.
-template <class R, bool LES, bool WALL = false, bool SPLIT = false>
+template <class R, bool LES, bool WALL = false>
 __global__ __launch_bounds__(PL::NTB, PL::FI == 1 && N >= 2 ? 8 : 4) void k_lift(StageArgs A) {
   constexpr bool MX = sizeof(R) == 4;
   constexpr int EPB = PL::EPB, TPE = PL::TPE, FI = PL::FI;
@@ -1859,13 +1879,9 @@ __global__ __launch_bounds__(PL::NTB, PL::FI == 1 && N >= 2 ? 8 : 4) void k_lift
   const double bval = tid < NB_STAGE ? A.basis[tid] : 0.0;
   const Ref ref = MX ? reference_state(A.U, gm1) : Ref{0.0, 0.0, 0.0};
   double FL[FI][5], FR[FI][5];
-  static_assert(!SPLIT || (!MX && !LES && !WALL), "split BR1: FP64 Navier-Stokes on the box");
-  constexpr bool split = SPLIT;
 #pragma unroll
   for (int k = 0; k < FI; ++k)
-    if (t + k * TPE < 6 * nf) {
-      if (!split) face_loads_w<WALL>(A.U, e, its[k], FL[k], FR[k]);  // split: no interface values
-    }
+    if (t + k * TPE < 6 * nf) face_loads_w<WALL>(A.U, e, its[k], FL[k], FR[k]);
   if (tid < NB_STAGE) sB[tid] = (R)bval;
   const R invJ[3] = {(R)A.invJ[0], (R)A.invJ[1], (R)A.invJ[2]};
   if (t < nn) {
@@ -1879,14 +1895,11 @@ __global__ __launch_bounds__(PL::NTB, PL::FI == 1 && N >= 2 ? 8 : 4) void k_lift
   }
 #pragma unroll
   for (int k = 0; k < FI; ++k)
-    if (t + k * TPE < 6 * nf && !split) lift_face_q<R, MX>(A, its[k], FL[k], FR[k], ref, sQ);
+    if (t + k * TPE < 6 * nf) lift_face_q<R, MX>(A, its[k], FL[k], FR[k], ref, sQ);
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < FI; ++k)
-    if (t + k * TPE < 6 * nf && !(WALL && its[k].nb < 0)) {
-      if constexpr (SPLIT) lift_face_node<R, false, true>(A, e, its[k], sq, sQ, sB, invJ);
-      else lift_face_node<R, LES>(A, e, its[k], sq, sQ, sB, invJ);
-    }
+    if (t + k * TPE < 6 * nf && !(WALL && its[k].nb < 0)) lift_face_node<R, LES>(A, e, its[k], sq, sQ, sB, invJ);
 }
 
 // Wall-model flux at every wall face node (FP64): thread -> (side p, element
@@ -4644,8 +4657,12 @@ hipError_t launch_lift(const StageArgs& A0, int eq, hipStream_t s) {
     return hipGetLastError();
   }
   if (eq == 2) hipLaunchKernelGGL((k_lift<double, true>), dim3(blocks_for(A)), dim3(PL::NTB), 0, s, A);
-  else if (A.split) hipLaunchKernelGGL((k_lift<double, false, false, true>), dim3(blocks_for(A)), dim3(PL::NTB), 0, s, A);
-  else hipLaunchKernelGGL((k_lift<double, false>), dim3(blocks_for(A)), dim3(PL::NTB), 0, s, A);
+  else if (A.split) {
+    const StageArgs B = grouped<PS>(A0);
+    hipLaunchKernelGGL(k_lift_split, dim3(blocks_for(B)), dim3(PS::NTB), 0, s, B);
+  } else {
+    hipLaunchKernelGGL((k_lift<double, false>), dim3(blocks_for(A)), dim3(PL::NTB), 0, s, A);
+  }
   return hipGetLastError();
 }
 
