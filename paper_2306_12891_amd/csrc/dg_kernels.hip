@@ -1203,10 +1203,10 @@ __device__ __forceinline__ void store_own_q(double* sq, int t, const double P[7]
 // node at a time:
 //   pass 1: each normal line (3 nf of them) gives the derivatives of
 //     (u, v, w, theta) along it at both end nodes, and each line of a face
-//     plane along one of the plane's axes j (6 faces x 2 axes x n1 lines,
-//     two tasks per line that split its nodes, so that the tasks' work is
-//     about even) those of u_d and u_j (d: the face normal) at its nodes,
-//     into the LDS scratch sW (48 nf doubles);
+//     plane along one of the plane's axes j (6 faces x 2 axes x n1 lines)
+//     those of u_d and of u_j (d: the face normal; one task per variable, so
+//     that the tasks' work is about even and the code is the same for both)
+//     at its nodes, into the LDS scratch sW (48 nf doubles);
 //   pass 2: each face node forms its flux from these and its velocity.
 // Each line's values are read from LDS once; the differentiation matrix comes
 // with uniform loads from the constant address space.  The interface values
@@ -1221,7 +1221,6 @@ __device__ __forceinline__ void own_part_by_lines(const StageArgs& A, int e, int
   const double h0 = -0.5 * cb[BL.winv()], hN = 0.5 * cb[BL.winv() + N];  // own-half weights at the ends
   double* sGn = sW;            // [3 d][2 side][4 v][nf]
   double* sT = sW + 24 * nf;   // [6 f][2 jj][2 c][nf]
-  constexpr int HALF = (n1 + 1) / 2;  // a face-plane line task computes outputs [0, HALF) or [HALF, n1)
   constexpr int NTASK = 3 * nf + 24 * n1;
   for (int task = t; task < NTASK; task += TPE) {
     if (task < 3 * nf) {  // normal line
@@ -1248,42 +1247,28 @@ __device__ __forceinline__ void own_part_by_lines(const StageArgs& A, int e, int
         sGn[((2 * d) * 4 + v) * nf + a] = g0[v];
         sGn[((2 * d + 1) * 4 + v) * nf + a] = gN[v];
       }
-    } else {  // half of a line of a face plane
-      const int u = (task - 3 * nf) >> 1, hi = (task - 3 * nf) & 1;
-      const int f = u / (2 * n1), r = u - f * 2 * n1, jj = r / n1, pos = r - jj * n1;
+    } else {  // one variable (u_d or u_j) along a line of a face plane
+      const int u = task - 3 * nf;
+      const int c = u / (12 * n1), w = u - c * 12 * n1;  // c: the variable; the code does not branch on it
+      const int f = w / (2 * n1), r = w - f * 2 * n1, jj = r / n1, pos = r - jj * n1;
       const int d = f >> 1, id = (f & 1) ? N : 0;
       const int ja = d == 0 ? 1 : 0, jb = d == 2 ? 1 : 2;
       const int j = jj ? jb : ja, o = jj ? ja : jb;
       const int sj = pstride(j);
-      const int base = id * pstride(d) + pos * pstride(o);
-      double qd[n1], qj[n1];
+      const double* src = sq + (c ? j : d) * SQP + id * pstride(d) + pos * pstride(o);
+      double q[n1];
 #pragma unroll
-      for (int l = 0; l < n1; ++l) {
-        qd[l] = sq[d * SQP + base + l * sj];
-        qj[l] = sq[j * SQP + base + l * sj];
-      }
+      for (int l = 0; l < n1; ++l) q[l] = src[l * sj];
       const double J = A.invJ[0] * (j == 0) + A.invJ[1] * (j == 1) + A.invJ[2] * (j == 2);
-      double* out = sT + (f * 2 + jj) * 2 * nf;
+      double* out = sT + ((f * 2 + jj) * 2 + c) * nf;
 #pragma unroll
       for (int i = 0; i < n1; ++i) {
-        if ((i < HALF) == (hi != 0)) continue;
-        double td = 0, tj = 0;
+        double tv = 0;
 #pragma unroll
-        for (int l = 0; l < n1; ++l) {
-          const double c = Dw[i * n1 + l];
-          td = fma(c, qd[l], td);
-          tj = fma(c, qj[l], tj);
-        }
-        if (i == 0) {
-          td = fma(h0, qd[0], td);
-          tj = fma(h0, qj[0], tj);
-        } else if (i == N) {
-          td = fma(hN, qd[N], td);
-          tj = fma(hN, qj[N], tj);
-        }
-        const int a = jj ? pos + n1 * i : i + n1 * pos;
-        out[a] = J * td;
-        out[nf + a] = J * tj;
+        for (int l = 0; l < n1; ++l) tv = fma(Dw[i * n1 + l], q[l], tv);
+        if (i == 0) tv = fma(h0, q[0], tv);
+        if (i == N) tv = fma(hN, q[N], tv);
+        out[jj ? pos + n1 * i : i + n1 * pos] = J * tv;
       }
     }
   }
