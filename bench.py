@@ -116,12 +116,18 @@ def domain(name):
 # HBM bytes per launch of the stage kernel measured with rocprofv3 --pmc
 # FETCH_SIZE and WRITE_SIZE (separate runs), each scaled by the plain-copy
 # calibration (FETCH x 2.000, WRITE x 1.000); averages over the five stage
-# launches of one step with the split lifting; see profiles/k_stage_*.md.
+# launches of one step (the TGV workloads with the split lifting); see
+# profiles/k_stage_*.md.
 # Valid only for the kernel source they were taken on (sha256 prefix).
 MEASURED_TRAFFIC = {
     "kernel_sha": "eede713d2624875d",
     "tgv_n7_64": {"bytes_per_launch": 29713.9e6, "fetch": 17473.3e6, "write": 12240.7e6},
     "tgv_n5_32": {"bytes_per_launch": 1563.8e6, "fetch": 873.0e6, "write": 690.8e6},
+    "freestream_euler_n7_64": {"bytes_per_launch": 22901.9e6, "fetch": 13238.3e6, "write": 9663.7e6},
+    "tgv_curved_n5_32": {"bytes_per_launch": 2029.2e6, "fetch": 1519.6e6, "write": 509.6e6},
+    "channel_wm_n5_32": {"bytes_per_launch": 1373.2e6, "fetch": 863.6e6, "write": 509.6e6},
+    "sod_ns_n4_256x16x16": {"bytes_per_launch": 2268.1e6, "fetch": 1678.1e6, "write": 590.0e6},
+    "tgv_les_n5_32": {"bytes_per_launch": 1381.1e6, "fetch": 871.5e6, "write": 509.6e6},
 }
 
 
@@ -134,6 +140,11 @@ KERNEL_FLOPS = {
     "kernel_sha": "eede713d2624875d",
     "tgv_n7_64": {"stage_flops_per_dof": 1418.5},
     "tgv_n5_32": {"stage_flops_per_dof": 1583.6},
+    "freestream_euler_n7_64": {"stage_flops_per_dof": 717.2},
+    "tgv_curved_n5_32": {"stage_flops_per_dof": 2062.5},
+    "channel_wm_n5_32": {"stage_flops_per_dof": 1416.3},
+    "sod_ns_n4_256x16x16": {"stage_flops_per_dof": 1068.3},
+    "tgv_les_n5_32": {"stage_flops_per_dof": 1403.3},
 }
 
 
