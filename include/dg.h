@@ -37,8 +37,9 @@
  * Ownership: the caller owns every array passed in (U, Ut, ...), which must
  * be device memory on the context's device and is never freed or retained.
  * The context owns all scratch (Runge-Kutta register, ping-pong state, face
- * buffers, blending arrays, reduction partials); dg_init allocates it and
- * dg_finalize releases it.
+ * buffers, blending arrays, reduction partials); dg_init allocates it (the
+ * reverse-mode buffers and the split lifting's second face buffer on first
+ * use, as noted at those calls) and dg_finalize releases it.
  *
  * Errors: every function returns DG_OK (0) or a negative code; it never
  * aborts or prints.  dg_last_error() gives a message.  Errors of asynchronous
@@ -247,7 +248,10 @@ int dg_time_derivative(dg_ctx* ctx, const double* U, double* Ut);
  * NULL pointer or dt not finite and > 0; DG_EHIP for launch failures. */
 int rk_step(dg_ctx* ctx, double* U, double dt);
 
-/* nsteps Runge-Kutta steps in place (same result as nsteps rk_step calls). */
+/* nsteps Runge-Kutta steps in place (same result as nsteps rk_step calls).
+ * With the split lifting (dg_options.lifting) rk_step, dg_rk_steps,
+ * rk_step_record and rk_step_vjp allocate a second face buffer of
+ * nElems * 6 * 4 * (N+1)^2 doubles on first use (DG_ENOMEM if that fails). */
 int dg_rk_steps(dg_ctx* ctx, double* U, double dt, int nsteps);
 
 /* Vector-Jacobian product of the operator: U_bar = (dL/dU)^T Ut_bar (the
