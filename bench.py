@@ -377,7 +377,7 @@ def face_flux_bytes_per_node(N, viscous, split):
 
 def roofline(name, nodes, steps, prof, N=None, viscous=False, split=False):
     """Roofline of the stage kernel from its event-timed launches: achieved =
-    160 B per DOF and launch (SURVEY-style floor of the Runge-Kutta stage:
+    160 B per DOF and launch (the floor of a Runge-Kutta stage:
     read U and the register, write the register and U; curved meshes add the
     80 B of metric terms) over the average launch time.  The exact per-launch
     average of the kernel (stage 1 reads no register, stage 5 writes none:

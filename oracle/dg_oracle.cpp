@@ -47,7 +47,7 @@
 // "parity unpinned" items (fixed only by GPU/oracle agreement, no independent
 // pin exists): the minmod reconstruction beyond its exactness on linear data
 // (the limiter's choice between the two one-sided slopes on non-linear data,
-// and the positivity fallback).  Pinned since the first version were judged
+// and the positivity fallback).  Pinned later, after first being listed as
 // unpinned: the Kennedy-Gruber and Pirozzoli energy fluxes are told apart by
 // the pressure rate at constant velocity and pressure (Pirozzoli's is exactly
 // gamma times Kennedy-Gruber's), the sharpness s by the raw sigmoid at E = 0,
