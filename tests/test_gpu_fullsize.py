@@ -5,7 +5,8 @@ benchmark times.
   on the GPU against the oracle on sampled elements (corners, edges and
   seeded random elements), with either BR1 lifting scheme, and the same for
   the mixed operator at its bound; two Runge-Kutta steps with the split
-  lifting (the benchmark's path) against the two-pass lifting.
+  lifting (the benchmark's path) against the two-pass lifting, and its first
+  two stages against the oracle on sampled elements.
 * Extruded Sod tube, N = 5, 64 x 8 x 8 elements, blending with minmod
   subcells, 500 steps: the data stay constant in y and z, so each x-line of
   the 3-D run equals the quasi-1-D tube (64 x 1 x 1 elements of the same cell
@@ -119,6 +120,63 @@ def test_tgv_n7_64_split_rollout_matches_two_pass(torch_cuda, tgv_n7_64):
         err = np.max(np.abs(a[:, v] - b[:, v]))
         assert err <= 1e-12 * scale, (v, err, scale)
     assert np.max(np.abs(b[:, 1] - U[:, 1])) > 1e-6
+
+
+def stencil(n, e):
+    """Element e of the periodic n^3 box and the elements its operator reads:
+    the six face neighbours and, for the BR1 gradient of those neighbours at
+    the shared faces' edges, the twelve edge-diagonal elements."""
+    ex, ey, ez = e % n, (e // n) % n, e // (n * n)
+    out = set()
+    for dx in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dz in (-1, 0, 1):
+                if abs(dx) + abs(dy) + abs(dz) <= 2:
+                    out.add((ex + dx) % n + n * ((ey + dy) % n + n * ((ez + dz) % n)))
+    return out
+
+
+def test_tgv_n7_64_split_stage_chain_sampled(orc, torch_cuda, tgv_n7_64):
+    """The benchmark's launch configuration at full size, stage by stage: one
+    rk_step_record with the split lifting (the lifting launch before stage 1,
+    then each stage kernel writes the own part of its output for the next)
+    against the oracle on sampled elements.  Y_1 = U_0 + B_1 dt L(U_0) and
+    Y_2 = Y_1 + B_2 dt (A_2 L(U_0) + L(Y_1)); the oracle evaluates L(U_0) on
+    the samples' stencils (face neighbours and edge diagonals), forms Y_1 there
+    and evaluates L(Y_1) on the samples, so Y_2 checks the own parts that the
+    first stage kernel chained to the second.  Per variable to 1e-12 of
+    max(max |U_v|, max rho * max c)."""
+    import torch
+
+    from paper_2306_12891_amd import dg
+    N, n, U, sel = tgv_n7_64
+    mu = 1.0 / 1600
+    s = orc.Setup(N=N, nelem=(n, n, n), equations=1, vol_flux=1, surf_flux=1, mu=mu)
+    op = dg.DG((n, n, n), N, gamma=G, mu=mu, equations=dg.NS, vol_flux=dg.PI, surf_flux=dg.ROE,
+               lifting=dg.LIFT_SPLIT)
+    Ud = torch.from_numpy(U).cuda()
+    dt = op.max_dt(Ud, 0.5)
+    Y = torch.empty((5,) + tuple(Ud.shape), dtype=torch.float64, device="cuda")
+    op.rk_step_record(Ud, dt, Y)
+    idx = torch.from_numpy(sel).long().cuda()
+    got1 = Y[1][idx].cpu().numpy()
+    got2 = Y[2][idx].cpu().numpy()
+    del Y, Ud
+    op.close()
+    torch.cuda.empty_cache()
+    A, B = orc.rk_coefficients()
+    zone = np.array(sorted(set().union(*(stencil(n, int(e)) for e in sel))), dtype=np.int32)
+    L0 = orc.time_derivative_elems(s, U, zone)
+    Y1 = U.copy()
+    Y1[zone] = U[zone] + B[0] * dt * L0
+    pos = {int(e): k for k, e in enumerate(zone)}
+    L0s = L0[[pos[int(e)] for e in sel]]
+    L1 = orc.time_derivative_elems(s, Y1, sel)
+    ref1 = Y1[sel]
+    ref2 = ref1 + B[1] * dt * (A[1] * L0s + L1)
+    assert_state_close(got1, ref1, "Y_1")
+    assert_state_close(got2, ref2, "Y_2")
+    assert np.max(np.abs(ref2[:, 1] - U[sel][:, 1])) > 1e3 * 1e-12 * np.max(np.abs(U[:, 1]))
 
 
 def sod_run_against_quasi_1d(orc, op, s1, U0, U1, nelem, N, dt, steps, every):
