@@ -6,7 +6,8 @@ benchmark times.
   seeded random elements), with either BR1 lifting scheme, and the same for
   the mixed operator at its bound; two Runge-Kutta steps with the split
   lifting (the benchmark's path) against the two-pass lifting, and its first
-  two stages against the oracle on sampled elements.
+  two stages against the oracle on sampled elements; 50 steps of the mixed
+  operator against the FP64 run within the stated 1e-5.
 * Extruded Sod tube, N = 5, 64 x 8 x 8 elements, blending with minmod
   subcells, 500 steps: the data stay constant in y and z, so each x-line of
   the 3-D run equals the quasi-1-D tube (64 x 1 x 1 elements of the same cell
@@ -120,6 +121,37 @@ def test_tgv_n7_64_split_rollout_matches_two_pass(torch_cuda, tgv_n7_64):
         err = np.max(np.abs(a[:, v] - b[:, v]))
         assert err <= 1e-12 * scale, (v, err, scale)
     assert np.max(np.abs(b[:, 1] - U[:, 1])) > 1e-6
+
+
+def test_tgv_n7_64_mixed_rollout_within_target(torch_cuda, tgv_n7_64):
+    """The metric's mixed-precision run at full size: 50 steps of the TGV at
+    N = 7 on 64^3 elements with the mixed operator against the FP64 operator
+    (split lifting, pinned to the oracle by the tests above): per variable
+    within the stated 1e-5 of max(max |U_v|, max rho), Linf and L2."""
+    import torch
+
+    from paper_2306_12891_amd import dg
+    N, n, U, _ = tgv_n7_64
+    mu = 1.0 / 1600
+    out = {}
+    dt = None
+    for prec in (dg.FP64, dg.MIXED):
+        op = dg.DG((n, n, n), N, gamma=G, mu=mu, equations=dg.NS, vol_flux=dg.PI, surf_flux=dg.ROE,
+                   precision=prec)
+        Ud = torch.from_numpy(U).cuda()
+        if dt is None:
+            dt = op.max_dt(Ud, 0.5)
+        op.rk_steps(Ud, dt, 50)
+        out[prec] = Ud
+        op.close()
+    a, b = out[dg.FP64], out[dg.MIXED]
+    scale = torch.maximum(a.abs().amax(dim=(0, 2, 3, 4)), a[:, 0].abs().amax())
+    d = (b - a).abs()
+    linf = (d.amax(dim=(0, 2, 3, 4)) / scale).tolist()
+    l2 = (d.pow(2).mean(dim=(0, 2, 3, 4)).sqrt() / scale).tolist()
+    print("mixed vs FP64 after 50 steps, Linf", linf, "L2", l2)
+    assert max(linf) <= 1e-5 and max(l2) <= 1e-5
+    assert max(linf) > 0.0
 
 
 def stencil(n, e):
