@@ -899,8 +899,11 @@ __device__ __forceinline__ Slot slot_of_thread(int e0, int nelem) {
 // that node: across the shared face the element's own q (normal derivative,
 // weight c_d), and across n's lateral faces where the node lies on an edge
 // of the face, the q of the diagonal element (n's neighbour there; weight
-// c_g).  The diagonal elements and their nodes follow from the element's
-// coordinates on the structured periodic box; each edge face item loads the
+// c_g).  On the structured periodic box the diagonal element across n's
+// lateral face is n shifted as the element is by its own neighbour there
+// (n + nbr(e, lateral) - e; the shift along the lateral direction does not
+// depend on the coordinate along d), and its node is n's face node moved to
+// the other side along the lateral direction; each edge face item loads the
 // density and momenta of its one or two diagonal nodes with the face states.
 struct Lateral {
   int dir, side;  // n's lateral face (direction, side) through the node
@@ -915,8 +918,8 @@ template <>
 struct SplitLoads<false> {};
 
 // The (up to two) lateral faces of the neighbour across face item it, and the
-// loads of the diagonal nodes (coordinates ec of the element, box ne).
-__device__ __forceinline__ void split_issue(const StageArgs& A, const FaceItem& it, const int ec[3],
+// loads of the diagonal nodes (element e with the neighbours nb6).
+__device__ __forceinline__ void split_issue(const StageArgs& A, const FaceItem& it, const Nbr6& nb6, int e,
                                             SplitLoads<true>& sp) {
   const int da = it.d == 0 ? 1 : 0, db = it.d == 2 ? 1 : 2;  // tangential directions, t1 along da
   const int t1 = it.a % n1, t2 = it.a / n1;
@@ -925,24 +928,13 @@ __device__ __forceinline__ void split_issue(const StageArgs& A, const FaceItem& 
   sp.nlat = (e1 ? 1 : 0) + (e2 ? 1 : 0);
   sp.lat[0] = Lateral{e1 ? da : db, e1 ? (t1 == N ? 1 : 0) : (t2 == N ? 1 : 0)};
   sp.lat[1] = Lateral{db, t2 == N ? 1 : 0};
-  const int tpos[2] = {e1 ? t2 : t1, t1};
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
     if (j >= sp.nlat) break;
     const int dg = sp.lat[j].dir, sg = sp.lat[j].side;
-    int c[3] = {ec[0], ec[1], ec[2]}, ix[3];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      const int nq = A.ne[q];
-      const int step = (q == it.d) ? (it.side ? 1 : -1) : ((q == dg) ? (sg ? 1 : -1) : 0);
-      int v = c[q] + step;
-      v = v < 0 ? v + nq : (v >= nq ? v - nq : v);
-      c[q] = v;
-      ix[q] = (q == it.d) ? (it.side ? 0 : N) : ((q == dg) ? (sg ? 0 : N) : tpos[j]);
-    }
-    const size_t diag = (size_t)c[0] + (size_t)A.ne[0] * ((size_t)c[1] + (size_t)A.ne[1] * c[2]);
-    const int node = ix[0] + n1 * ix[1] + nf * ix[2];
-    const double* Ud = A.U + diag * 5 * nn + node;
+    const int diag = it.nb + nb6.pick(2 * dg + sg) - e;
+    const int node = it.nnb + (sg ? -N : N) * (dg == 0 ? 1 : (dg == 1 ? n1 : nf));
+    const double* Ud = A.U + (size_t)diag * 5 * nn + node;
     sp.dg[j][0] = Ud[0];
     sp.dg[j][1] = Ud[(1 + it.d) * nn];
     sp.dg[j][2] = Ud[(1 + dg) * nn];
@@ -950,13 +942,6 @@ __device__ __forceinline__ void split_issue(const StageArgs& A, const FaceItem& 
 }
 
 __device__ __forceinline__ double pick3(const double v[3], int d) { return d == 0 ? v[0] : (d == 1 ? v[1] : v[2]); }
-
-template <class R>
-__device__ __forceinline__ void viscous_flux_rt(int d, const R g[3][4], R vx, R vy, R vz, R mu, R kappa, R F[4]) {
-  if (d == 0) viscous_flux<0, R>(g, vx, vy, vz, mu, kappa, F);
-  else if (d == 1) viscous_flux<1, R>(g, vx, vy, vz, mu, kappa, F);
-  else viscous_flux<2, R>(g, vx, vy, vz, mu, kappa, F);
-}
 
 // The neighbour-dependent rest of the neighbour's normal viscous flux at face
 // item it (split BR1), added to fn: the viscous flux (linear in the gradient
@@ -1003,10 +988,10 @@ struct FaceData {
 
 template <bool NS, class R, bool WALL = false, bool SPLIT = false>
 __device__ __forceinline__ void face_issue(const StageArgs& A, int e, FaceData<NS, R, WALL, SPLIT>& fd,
-                                           const int* ec = nullptr) {
+                                           const Nbr6* nb6 = nullptr) {
   const FaceItem& it = fd.it;
   if constexpr (SPLIT) {
-    split_issue(A, it, ec, fd.sp);
+    split_issue(A, it, *nb6, e, fd.sp);
   }
   if (WALL && it.nb < 0) {
     wall_face_loads(A.U, e, it, fd.L, fd.R_);
@@ -1359,13 +1344,6 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
   static_assert(EPB == 1, "one element per workgroup: its neighbours are uniform");
   const Nbr6 nb6 = uniform_nbr6(A.nbr, e);
   static_assert(!SPLIT || (EQ == 1 && !BLEND && !WALL && !MX), "split BR1: FP64 Navier-Stokes on the box");
-  int ec[3] = {0, 0, 0};  // the element's coordinates on the box (uniform)
-  if (SPLIT) {
-    const int eu = __builtin_amdgcn_readfirstlane(e);
-    ec[0] = eu % A.ne[0];
-    ec[1] = (eu / A.ne[0]) % A.ne[1];
-    ec[2] = eu / (A.ne[0] * A.ne[1]);
-  }
   FaceData<NS, R, WALL, SPLIT> fd[FI];
 #pragma unroll
   for (int k = 0; k < FI; ++k)
@@ -1390,7 +1368,7 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
   // Round trip 2: the face states (needs the neighbour indices).
 #pragma unroll
   for (int k = 0; k < FI; ++k)
-    if (t + k * TPE < 6 * nf) face_issue<NS, R, WALL, SPLIT>(A, e, fd[k], ec);
+    if (t + k * TPE < 6 * nf) face_issue<NS, R, WALL, SPLIT>(A, e, fd[k], &nb6);
   if (tid < NB_STAGE) {
     sB[tid] = (R)bval;
     if (BLEND) sB64[tid] = bval;
