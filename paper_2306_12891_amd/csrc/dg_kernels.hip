@@ -944,17 +944,18 @@ __device__ __forceinline__ void split_issue(const StageArgs& A, const FaceItem& 
 __device__ __forceinline__ double pick3(const double v[3], int d) { return d == 0 ? v[0] : (d == 1 ? v[1] : v[2]); }
 
 // The neighbour-dependent rest of the neighbour's normal viscous flux at face
-// item it (split BR1), added to fn: the viscous flux (linear in the gradient
-// for constant viscosity) of the gradient made of the other halves, with the
-// neighbour's velocity at the node, written out for its few non-zero terms in
-// the face frame (n, t1, t2) and turned back with selects.  own / nb: the
-// element's and the neighbour's face states (rotated frame, FP64).
+// item it (split BR1), added to fn (in the face frame: normal, t1, t2 and
+// energy components): the viscous flux (linear in the gradient for constant
+// viscosity) of the gradient made of the other halves, with the neighbour's
+// velocity at the node, written out for its few non-zero terms.  own / nb:
+// the element's and the neighbour's face states (rotated frame, FP64).
 //   normal half g_d = c_d q_e:   tau_nn = 4/3 mu c_d u_n,e, tau_tn = mu c_d u_t,e;
 //   lateral half g_dg = c_g u_g: tau_dg,n += mu c_g u_n,g, tau_nn -= 2/3 mu c_g u_dg,g;
 //   F_E = u_nb . tau_n + kappa c_d theta_e.
 __device__ __forceinline__ void split_rest(const StageArgs& A, const FaceItem& it, const State64& own,
                                            const State64& nb, const SplitLoads<true>& sp, double fn[4]) {
-  const double hw = 0.5 * A.basis[BL.winv()];  // (1/w_0) / 2, w_0 = w_N
+  // (1/w_0) / 2, w_0 = w_N: a uniform load through the constant address space
+  const double hw = 0.5 * ((const double __attribute__((address_space(4)))*)(uintptr_t)A.basis)[BL.winv()];
   const double mu = A.mu;
   const double cd = pick3(A.invJ, it.d) * (it.side ? -hw : hw);
   double tnn = (4.0 / 3.0) * mu * cd * own.un;
@@ -973,8 +974,9 @@ __device__ __forceinline__ void split_rest(const StageArgs& A, const FaceItem& i
     else t2 += sh;
   }
   fe += nb.un * tnn + nb.u1 * t1 + nb.u2 * t2;
-#pragma unroll
-  for (int c = 0; c < 3; ++c) fn[c] += c == it.d ? tnn : (c == it.k1 - 1 ? t1 : t2);
+  fn[0] += tnn;  // fn in the face frame
+  fn[1] += t1;
+  fn[2] += t2;
   fn[3] += fe;
 }
 
@@ -1003,8 +1005,15 @@ __device__ __forceinline__ void face_issue(const StageArgs& A, int e, FaceData<N
   face_loads(A.U, e, it, fd.L, fd.R_);
   if (NS) {
     const R* Fn = reinterpret_cast<const R*>(A.Fvf) + ((size_t)it.nb * 6 + (it.f ^ 1)) * 4 * nf + it.a;
+    if (SPLIT) {  // in the face frame (normal, t1, t2, energy), as the rest is formed
+      fd.fn[0] = Fn[it.d * nf];
+      fd.fn[1] = Fn[(it.k1 - 1) * nf];
+      fd.fn[2] = Fn[(it.k2 - 1) * nf];
+      fd.fn[3] = Fn[3 * nf];
+    } else {
 #pragma unroll
-    for (int c = 0; c < 4; ++c) fd.fn[c] = Fn[c * nf];
+      for (int c = 0; c < 4; ++c) fd.fn[c] = Fn[c * nf];
+    }
   }
 }
 
@@ -1030,9 +1039,11 @@ __device__ __forceinline__ void face_item(const StageArgs& A, const FaceData<NS,
       __builtin_amdgcn_sched_barrier(0);
       split_rest(A, it, it.side ? sL : sR, it.side ? sR : sL, fd.sp, fn);
       __builtin_amdgcn_sched_barrier(0);
-    }
+      store_q(it, fn, sFn);  // from the face frame
+    } else {
 #pragma unroll
-    for (int c = 0; c < 4; ++c) sFn[it.f][c][it.a] = fn[c];
+      for (int c = 0; c < 4; ++c) sFn[it.f][c][it.a] = fn[c];
+    }
   }
   const Jumps<R> J = jumps<R, MX>(sL, sR, A.gamma, ref, A.sf);
   R g[5];
