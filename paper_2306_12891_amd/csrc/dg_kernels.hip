@@ -1284,10 +1284,11 @@ __device__ __forceinline__ void own_part_by_lines(const StageArgs& A, int e, int
     const double Fb = mu * (dn_ub + db_ud);
     const double FE = sq[d * SQP + n] * Fd + sq[ja * SQP + n] * Fa + sq[jb * SQP + n] * Fb + kap * dn_th;
     double* o = Fout + ((size_t)e * 6 + f) * 4 * nf + a;
-    o[d * nf] = Fd;
-    o[ja * nf] = Fa;
-    o[jb * nf] = Fb;
-    o[3 * nf] = FE;
+    // streaming stores: read once, by the neighbours' next stage kernel
+    __builtin_nontemporal_store(Fd, &o[d * nf]);
+    __builtin_nontemporal_store(Fa, &o[ja * nf]);
+    __builtin_nontemporal_store(Fb, &o[jb * nf]);
+    __builtin_nontemporal_store(FE, &o[3 * nf]);
   }
 }
 
@@ -1542,7 +1543,7 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
   // the volume loop, the kernel's register peak).
   if (t < nn && A.mode != MODE_UT && A.A != 0.0) {
 #pragma unroll
-    for (int v = 0; v < 5; ++v) gprev[v] = A.G[(size_t)e * 5 * nn + t + v * nn];
+    for (int v = 0; v < 5; ++v) gprev[v] = __builtin_nontemporal_load(&A.G[(size_t)e * 5 * nn + t + v * nn]);
   }
   if (NS && !(BLEND && A.mode == MODE_DIFF)) {  // uniform over the workgroup
     // viscous divergence: all twelve flux components exchanged through LDS
@@ -1645,9 +1646,11 @@ __global__ DG_STAGE_BOUNDS void k_stage(StageArgs A) {
       for (int v = 0; v < 5; ++v) {
         double gv = ut[v];
         if (A.A != 0.0) gv = A.A * gprev[v] + ut[v];
-        if (A.writeG) A.G[o + v * nn] = gv;
+        // streaming stores (the register is read once, by this element's next
+        // stage; the state by the next stage kernel)
+        if (A.writeG) __builtin_nontemporal_store(gv, &A.G[o + v * nn]);
         u[v] = u[v] + A.Bdt * gv;  // the stage output, kept for the indicator below
-        A.Uout[o + v * nn] = u[v];
+        __builtin_nontemporal_store(u[v], &A.Uout[o + v * nn]);
       }
     }
   }
