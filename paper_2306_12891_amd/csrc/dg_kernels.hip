@@ -1811,10 +1811,10 @@ __device__ __forceinline__ void lift_face_node(const StageArgs& A, int e, const 
   const R ud = sq[d][n], ua = sq[ja][n], ub = sq[jb][n];
   const R FE = ud * Fd + ua * Fa + ub * Fb + kap * g3;
   R* out = reinterpret_cast<R*>(A.Fvf) + ((size_t)e * 6 + it.f) * 4 * nf + it.a;
-  out[d * nf] = Fd;
-  out[ja * nf] = Fa;
-  out[jb * nf] = Fb;
-  out[3 * nf] = FE;
+  __builtin_nontemporal_store(Fd, &out[d * nf]);  // streaming: read once, by the neighbour
+  __builtin_nontemporal_store(Fa, &out[ja * nf]);
+  __builtin_nontemporal_store(Fb, &out[jb * nf]);
+  __builtin_nontemporal_store(FE, &out[3 * nf]);
 }
 
 // Register budget of the lifting kernel: 8 waves per SIMD (64 VGPRs) with one
