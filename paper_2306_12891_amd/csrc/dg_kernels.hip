@@ -3794,7 +3794,7 @@ __global__ __launch_bounds__(NT, DG_N == 5 ? 3 : 1) void k_stage_curved(StageArg
 
   if (t < nn && A.mode != MODE_UT && A.A != 0.0) {
 #pragma unroll
-    for (int v = 0; v < 5; ++v) gprev[v] = A.G[(size_t)e * 5 * nn + t + v * nn];
+    for (int v = 0; v < 5; ++v) gprev[v] = __builtin_nontemporal_load(&A.G[(size_t)e * 5 * nn + t + v * nn]);
   }
   if (NS) {
     __syncthreads();  // sP, sM and sQ consumed
@@ -3858,8 +3858,8 @@ __global__ __launch_bounds__(NT, DG_N == 5 ? 3 : 1) void k_stage_curved(StageArg
         const double ut = acc[v] * iJ;
         double gv = ut;
         if (A.A != 0.0) gv = A.A * gprev[v] + ut;
-        if (A.writeG) A.G[o + v * nn] = gv;
-        A.Uout[o + v * nn] = u[v] + A.Bdt * gv;
+        if (A.writeG) __builtin_nontemporal_store(gv, &A.G[o + v * nn]);  // streaming, as in k_stage
+        __builtin_nontemporal_store(u[v] + A.Bdt * gv, &A.Uout[o + v * nn]);
       }
     }
   }
@@ -3984,7 +3984,8 @@ __global__ __launch_bounds__(PLC::NTB) void k_lift_curved(StageArgs A) {
       const double Jf[3] = {so * Nv[0], so * Nv[1], so * Nv[2]};  // face metric along the own +xi
       double* out = A.Fvf + ((size_t)e * 6 + it.f) * 4 * nf + it.a;
 #pragma unroll
-      for (int c = 0; c < 4; ++c) out[c * nf] = Jf[0] * F[0][c] + Jf[1] * F[1][c] + Jf[2] * F[2][c];
+      for (int c = 0; c < 4; ++c)  // streaming: read once, by the neighbour
+        __builtin_nontemporal_store(Jf[0] * F[0][c] + Jf[1] * F[1][c] + Jf[2] * F[2][c], &out[c * nf]);
     }
 }
 
