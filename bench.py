@@ -120,14 +120,14 @@ def domain(name):
 # profiles/k_stage_*.md.
 # Valid only for the kernel source they were taken on (sha256 prefix).
 MEASURED_TRAFFIC = {
-    "kernel_sha": "eede713d2624875d",
-    "tgv_n7_64": {"bytes_per_launch": 29713.9e6, "fetch": 17473.3e6, "write": 12240.7e6},
-    "tgv_n5_32": {"bytes_per_launch": 1563.8e6, "fetch": 873.0e6, "write": 690.8e6},
-    "freestream_euler_n7_64": {"bytes_per_launch": 22901.9e6, "fetch": 13238.3e6, "write": 9663.7e6},
-    "tgv_curved_n5_32": {"bytes_per_launch": 2029.2e6, "fetch": 1519.6e6, "write": 509.6e6},
-    "channel_wm_n5_32": {"bytes_per_launch": 1373.2e6, "fetch": 863.6e6, "write": 509.6e6},
-    "sod_ns_n4_256x16x16": {"bytes_per_launch": 2268.1e6, "fetch": 1678.1e6, "write": 590.0e6},
-    "tgv_les_n5_32": {"bytes_per_launch": 1381.1e6, "fetch": 871.5e6, "write": 509.6e6},
+    "kernel_sha": "cc42175a04ddafbd",
+    "tgv_n7_64": {"bytes_per_launch": 26891.8e6, "fetch": 14651.1e6, "write": 12240.7e6},
+    "tgv_n5_32": {"bytes_per_launch": 1599.7e6, "fetch": 874.4e6, "write": 725.3e6},
+    "freestream_euler_n7_64": {"bytes_per_launch": 20721.4e6, "fetch": 11057.7e6, "write": 9663.7e6},
+    "tgv_curved_n5_32": {"bytes_per_launch": 2056.2e6, "fetch": 1521.0e6, "write": 535.2e6},
+    "channel_wm_n5_32": {"bytes_per_launch": 1389.6e6, "fetch": 864.3e6, "write": 525.3e6},
+    "sod_ns_n4_256x16x16": {"bytes_per_launch": 2302.3e6, "fetch": 1675.6e6, "write": 626.7e6},
+    "tgv_les_n5_32": {"bytes_per_launch": 1398.8e6, "fetch": 872.3e6, "write": 526.5e6},
 }
 
 
@@ -137,7 +137,7 @@ MEASURED_TRAFFIC = {
 # stage launches of one step; profiles/k_stage_*.md); valid only for the
 # kernel source they were counted on (sha256 prefix).
 KERNEL_FLOPS = {
-    "kernel_sha": "eede713d2624875d",
+    "kernel_sha": "cc42175a04ddafbd",
     "tgv_n7_64": {"stage_flops_per_dof": 1418.5},
     "tgv_n5_32": {"stage_flops_per_dof": 1583.6},
     "freestream_euler_n7_64": {"stage_flops_per_dof": 717.2},
