@@ -44,15 +44,19 @@
 // energy definition, the sharpness s, the FV reconstruction) follows standard
 // readings from the literature, and each place is marked "reading:" below.
 //
-// "parity unpinned" items (fixed only by GPU/oracle agreement, no independent
-// pin exists): the minmod reconstruction beyond its exactness on linear data
-// (the limiter's choice between the two one-sided slopes on non-linear data,
-// and the positivity fallback).  Pinned later, after first being listed as
-// unpinned: the Kennedy-Gruber and Pirozzoli energy fluxes are told apart by
-// the pressure rate at constant velocity and pressure (Pirozzoli's is exactly
-// gamma times Kennedy-Gruber's), the sharpness s by the raw sigmoid at E = 0,
-// T/2 and T with the cut-off and clip switched off, and Roe's dissipation by
-// the upwind (Roe) property for supersonic states and its consistency.
+// "parity unpinned" items: none left among the functions.  Pinned after
+// first being listed as unpinned: the Kennedy-Gruber and Pirozzoli energy
+// fluxes are told apart by the pressure rate at constant velocity and
+// pressure (Pirozzoli's is exactly gamma times Kennedy-Gruber's), the
+// sharpness s by the raw sigmoid at E = 0, T/2 and T with the cut-off and
+// clip switched off, Roe's dissipation by the upwind (Roe) property for
+// supersonic states and its consistency, and the minmod reconstruction on
+// non-linear data by an independent MUSCL scheme on the subcell grid (which
+// also shows that the larger one-sided slope or the central slope would
+// differ).  The reconstruction's first-order fallback for non-positive face
+// states is never reached from states positive at every node (the subcell
+// edges interlace the nodes, so a minmod face value lies between two node
+// values); it guards invalid states only.
 // ============================================================================
 #include <algorithm>
 #include <cmath>
