@@ -32,3 +32,15 @@ def test_workload_tables_are_consistent():
     for k in traffic:
         t = bench.MEASURED_TRAFFIC[k]
         assert abs(t["fetch"] + t["write"] - t["bytes_per_launch"]) <= 1e-3 * t["bytes_per_launch"], k
+
+
+def test_counters_and_profiles_match_the_kernel_source():
+    """The HBM traffic and FP64 counts bench.py reports were collected on the
+    kernel source in the tree (else it reports traffic null), and the
+    rocprofv3 summaries of the headline workload name the same source."""
+    import bench
+    sha = bench.kernel_sha()
+    assert bench.MEASURED_TRAFFIC["kernel_sha"] == sha, "kernel changed since the counters were taken"
+    for f in ("k_stage_tgv_n7_64.md", "k_stage_tgv_n5_32.md"):
+        with open(os.path.join(ROOT, "profiles", f)) as fh:
+            assert sha in fh.read(), f
